@@ -1,0 +1,167 @@
+/*
+ * snn.h -- C ABI of the MI355X (gfx950) SNN library: exact fixed-radius
+ * near-neighbour search by sorting (Chen & Guettel, "Fast and exact
+ * fixed-radius neighbor search based on sorting").
+ *
+ * Result definition (normative for every entry point below).  For data
+ * rows p_i and a query q, both promoted to double (exact),
+ *
+ *     N(q) = { i : S(p_i, q) <= fl(R*R) },
+ *     S(p, q) = fl(... fl(fl(t_0*t_0) + fl(t_1*t_1)) ... + fl(t_{d-1}*t_{d-1})),
+ *     t_k = fl(p_k - q_k),
+ *
+ * i.e. the direct squared distance of Section 4, eq. (ip1), summed left to
+ * right as in the rounding analysis of Section 4, without fused
+ * multiply-add, and compared inclusively with R^2 (Section 3.2).  The
+ * returned distance is (float)sqrt(S).  Index sets are bit-identical to a
+ * CPU float64 evaluation of this rule.
+ *
+ * Memory.  Every pointer named "device" is HIP device memory of the
+ * device in snn_device.device; "host" pointers are ordinary host memory.
+ * Inputs are borrowed for the duration of the call only.  Device memory
+ * the library needs (the index, its workspace) comes from snn_device.alloc
+ * (hipMalloc when NULL) and is returned through snn_device.free.
+ *
+ * Streams.  All device work of a call is enqueued on snn_device.stream
+ * (NULL: the null stream).  snn_query / snn_query_self synchronise that
+ * stream once, to learn the number of neighbours; they return with the CSR
+ * arrays still being written by work enqueued on the stream.
+ *
+ * Errors.  Every entry point returns an snn_status; on failure
+ * snn_last_error() describes it (thread-local, valid until the next call on
+ * the thread).  No C++ exception crosses this interface.  Calls on one
+ * index from several host threads must be serialised by the caller.
+ */
+#ifndef SNN_H_
+#define SNN_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SNN_OK = 0,
+  SNN_EINVAL = -1,    /* bad argument, or NaN/Inf in the data or queries */
+  SNN_ENOMEM = -2,    /* the allocator returned NULL */
+  SNN_EDEVICE = -3,   /* a HIP call failed, or no usable gfx950 device */
+  SNN_EOVERFLOW = -4, /* CSR capacity too small; csr.nnz holds the size needed */
+  SNN_ENOTSUP = -5    /* valid but unsupported request */
+} snn_status;
+
+typedef enum { SNN_F32 = 0, SNN_F64 = 1 } snn_dtype;
+
+/* How candidate distances are screened (all give the same exact result).
+ * FP64:  every window pair is decided by the normative rule in float64.
+ * MIXED: window pairs are screened on the matrix cores (bf16 operands,
+ *        fp32 accumulation) against a rigorous rounding bound; only pairs
+ *        the screen cannot reject are re-decided by the normative rule in
+ *        float64 (the "precision form").
+ * AUTO:  the library picks. */
+typedef enum { SNN_PREC_FP64 = 0, SNN_PREC_MIXED = 1, SNN_PREC_AUTO = 2 } snn_precision;
+
+typedef struct {
+  /* Device allocator; both NULL selects hipMalloc/hipFree.  alloc returns
+   * 256-byte aligned device memory of at least `bytes`, or NULL. */
+  void* (*alloc)(void* ctx, size_t bytes);
+  void (*free)(void* ctx, void* ptr);
+  void* ctx;
+  void* stream; /* hipStream_t */
+  int device;   /* HIP device ordinal */
+} snn_device;
+
+typedef struct {
+  snn_precision precision;
+  /* bf16 terms per coordinate in MIXED mode: 1 (one bf16 value) or 3
+   * (hi/lo split: hi*hi + hi*lo + lo*hi, ~16 bits); 0 = automatic. */
+  int mixed_terms;
+  /* queries per tile / candidates per work unit; 0 = automatic. */
+  int tile_q;
+  int tile_c;
+} snn_options;
+
+typedef struct {
+  int64_t* row_ptr; /* device, m+1 entries, always written */
+  int32_t* col;     /* device, nnz_cap entries: original data row ids,
+                       ascending within a row */
+  float* dist;      /* device, nnz_cap entries: (float)sqrt(S) */
+  int64_t nnz_cap;  /* in: capacity of col / dist */
+  int64_t nnz;      /* out: number of neighbours (also on SNN_EOVERFLOW) */
+} snn_csr;
+
+typedef struct {
+  int64_t pairs_window;   /* sum over queries of |J_q| (Algorithm 2, step 4) */
+  int64_t pairs_executed; /* (query, candidate) pairs the screen evaluated */
+  int64_t pairs_recheck;  /* pairs re-decided in float64 by the normative rule */
+  int64_t nnz;
+  int32_t precision_used; /* snn_precision actually run */
+  int32_t terms_used;     /* MIXED: bf16 terms per coordinate */
+  double screen_ms;       /* device time of the candidate-screen kernel */
+  double total_ms;        /* device time of the whole call */
+} snn_stats;
+
+typedef struct snn_index_s* snn_index_t;
+
+/* Algorithm 1 (Section 3.1): centre by the mean, first principal direction
+ * (power iteration on the centred Gram matrix; any direction keeps the
+ * result exact by eq. (lower)), sort rows by their score, keep the
+ * sorted scores, squared norms and row copies the queries need.
+ *   X: device, n x d row-major, dtype.  1 <= d <= 1024, 1 <= n < 2^31.
+ * Errors: SNN_EINVAL (NULL/ranges/NaN/Inf in X), SNN_ENOMEM, SNN_EDEVICE. */
+snn_status snn_index(const snn_device* dev, const void* X, int64_t n, int32_t d, snn_dtype dtype,
+                     snn_index_t* out);
+
+/* Algorithm 2 (Section 3.2) for m out-of-sample queries.
+ *   Q: device, m x d row-major, same dtype as the index.  m >= 0.
+ *   R: radius, finite and >= 0.  opts may be NULL (AUTO).
+ *   out: caller-owned device CSR; rows follow the order of Q.
+ *   st:  host, may be NULL.
+ * If the neighbours do not fit, returns SNN_EOVERFLOW with out->nnz set to
+ * the number needed and row_ptr written; col/dist are then unspecified. */
+snn_status snn_query(snn_index_t idx, const void* Q, int64_t m, double R, const snn_options* opts,
+                     snn_csr* out, snn_stats* st);
+
+/* All-points self-query: every data row of the index is a query (rows of
+ * the CSR follow the original data order).  Same contract as snn_query. */
+snn_status snn_query_self(snn_index_t idx, double R, const snn_options* opts, snn_csr* out,
+                          snn_stats* st);
+
+/* Host-readable views of index internals, for checking and diagnostics.
+ * Device pointers stay owned by the index. */
+typedef struct {
+  int64_t n;
+  int32_t d;
+  snn_dtype dtype;
+  const double* mu;       /* device, d: column means */
+  const double* v;        /* device, d: unit sorting direction */
+  const double* key;      /* device, n: sorted scores, float32 values held in double */
+  const int32_t* perm;    /* device, n: sorted position -> original row id */
+  double max_norm;        /* host: max_i ||fl32(p_i - mu)|| */
+  double key_eps;         /* host: bound on |key_i - v.(p_i - mu)| over all i */
+  int32_t power_iters;    /* host: power iterations run */
+} snn_index_view;
+
+snn_status snn_index_get_view(snn_index_t idx, snn_index_view* view);
+
+void snn_index_free(snn_index_t idx);
+
+/* Stable LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit)
+ * of the keys, in place (the building block of Algorithm 1, step 6).
+ *   keys, vals: device, n entries each.  0 <= begin_bit < end_bit <= 32.
+ * Scratch comes from dev->alloc.  Stable: equal keys keep their order. */
+snn_status snn_sort_pairs_u32(const snn_device* dev, uint32_t* keys, uint32_t* vals, int64_t n,
+                              int begin_bit, int end_bit);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* snn_last_error(void);
+
+/* Library version string. */
+const char* snn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNN_H_ */

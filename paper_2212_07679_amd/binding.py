@@ -1,0 +1,307 @@
+"""ctypes binding of libsnn (include/snn.h): argument marshalling only.
+
+Every step of index construction and querying runs in the library's HIP
+kernels.  PyTorch provides device memory (its caching allocator, handed to
+the library as the snn_device allocator) and the stream.  If libsnn.so is
+missing, or the library reports an error, a ``SnnError`` is raised; there is
+no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsnn.so")
+
+SNN_OK, SNN_EINVAL, SNN_ENOMEM, SNN_EDEVICE, SNN_EOVERFLOW, SNN_ENOTSUP = 0, -1, -2, -3, -4, -5
+SNN_F32, SNN_F64 = 0, 1
+PRECISION = {"fp64": 0, "mixed": 1, "auto": 2}
+
+STATUS_NAMES = {
+    SNN_OK: "SNN_OK",
+    SNN_EINVAL: "SNN_EINVAL",
+    SNN_ENOMEM: "SNN_ENOMEM",
+    SNN_EDEVICE: "SNN_EDEVICE",
+    SNN_EOVERFLOW: "SNN_EOVERFLOW",
+    SNN_ENOTSUP: "SNN_ENOTSUP",
+}
+
+
+class SnnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class snn_device(ctypes.Structure):
+    _fields_ = [
+        ("alloc", ALLOC_FN),
+        ("free", FREE_FN),
+        ("ctx", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+        ("device", ctypes.c_int),
+    ]
+
+
+class snn_options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int),
+        ("mixed_terms", ctypes.c_int),
+        ("tile_q", ctypes.c_int),
+        ("tile_c", ctypes.c_int),
+    ]
+
+
+class snn_csr(ctypes.Structure):
+    _fields_ = [
+        ("row_ptr", ctypes.c_void_p),
+        ("col", ctypes.c_void_p),
+        ("dist", ctypes.c_void_p),
+        ("nnz_cap", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+    ]
+
+
+class snn_stats(ctypes.Structure):
+    _fields_ = [
+        ("pairs_window", ctypes.c_int64),
+        ("pairs_executed", ctypes.c_int64),
+        ("pairs_recheck", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("precision_used", ctypes.c_int32),
+        ("terms_used", ctypes.c_int32),
+        ("screen_ms", ctypes.c_double),
+        ("total_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class snn_index_view(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("d", ctypes.c_int32),
+        ("dtype", ctypes.c_int),
+        ("mu", ctypes.c_void_p),
+        ("v", ctypes.c_void_p),
+        ("key", ctypes.c_void_p),
+        ("perm", ctypes.c_void_p),
+        ("max_norm", ctypes.c_double),
+        ("key_eps", ctypes.c_double),
+        ("power_iters", ctypes.c_int32),
+    ]
+
+
+# symbol -> (restype, argtypes): every entry point declared in include/snn.h
+SIGNATURES = {
+    "snn_index": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                 ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    "snn_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                 ctypes.POINTER(snn_options), ctypes.POINTER(snn_csr), ctypes.POINTER(snn_stats)]),
+    "snn_query_self": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(snn_options),
+                                      ctypes.POINTER(snn_csr), ctypes.POINTER(snn_stats)]),
+    "snn_index_get_view": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(snn_index_view)]),
+    "snn_index_free": (None, [ctypes.c_void_p]),
+    "snn_sort_pairs_u32": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
+    "snn_last_error": (ctypes.c_char_p, []),
+    "snn_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsnn.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise SnnError(SNN_EDEVICE, f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != SNN_OK:
+        raise SnnError(status, lib().snn_last_error().decode())
+
+
+class _TorchAllocator:
+    """snn_device backed by torch's caching allocator on one device/stream."""
+
+    def __init__(self, device: int, stream: Optional[torch.cuda.Stream] = None):
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        dev_id, st = device, self.stream
+
+        def _alloc(_ctx, nbytes):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev_id, st)
+            except Exception:  # out of memory -> NULL -> SNN_ENOMEM
+                return None
+
+        def _free(_ctx, ptr):
+            if ptr:
+                torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.dev = snn_device(self._alloc, self._free, None, ctypes.c_void_p(self.stream.cuda_stream), device)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return SNN_F32
+    if t.dtype == torch.float64:
+        return SNN_F64
+    raise SnnError(SNN_EINVAL, f"unsupported dtype {t.dtype}")
+
+
+def _device_tensor_from_ptr(ptr: int, count: int, dtype: torch.dtype, device: int) -> torch.Tensor:
+    """Copy `count` elements at device address `ptr` into a new torch tensor."""
+    out = torch.empty(count, dtype=dtype, device=f"cuda:{device}")
+    if count:
+        nbytes = count * out.element_size()
+        hip = _hip()
+        torch.cuda.synchronize(device)
+        r = hip.hipMemcpy(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes), 3)
+        if r != 0:
+            raise SnnError(SNN_EDEVICE, f"hipMemcpy failed ({r})")
+    return out
+
+
+_hiplib = None
+
+
+def _hip():
+    global _hiplib
+    if _hiplib is None:
+        _hiplib = ctypes.CDLL("libamdhip64.so")
+        _hiplib.hipMemcpy.restype = ctypes.c_int
+        _hiplib.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    return _hiplib
+
+
+class Index:
+    """An SNN index (Algorithm 1) over the rows of a device tensor X (n x d)."""
+
+    def __init__(self, X: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+        if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dim() != 2:
+            raise SnnError(SNN_EINVAL, "X must be a 2-D CUDA tensor")
+        X = X.contiguous()
+        self.device = X.device.index if X.device.index is not None else torch.cuda.current_device()
+        self.dtype = X.dtype
+        self.n, self.d = X.shape
+        self._alloc = _TorchAllocator(self.device, stream)
+        self._h = ctypes.c_void_p()
+        self._nnz_hint = 0
+        _check(lib().snn_index(ctypes.byref(self._alloc.dev), ctypes.c_void_p(X.data_ptr()), self.n, self.d,
+                               _dtype_code(X), ctypes.byref(self._h)))
+
+    @property
+    def stream(self) -> torch.cuda.Stream:
+        return self._alloc.stream
+
+    def close(self):
+        if self._h:
+            lib().snn_index_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _opts(self, precision: str, terms: int, tile_q: int, tile_c: int) -> snn_options:
+        if precision not in PRECISION:
+            raise SnnError(SNN_EINVAL, f"precision must be one of {sorted(PRECISION)}")
+        return snn_options(PRECISION[precision], int(terms), int(tile_q), int(tile_c))
+
+    def _run(self, Q: Optional[torch.Tensor], m: int, R: float, opts: snn_options, nnz_cap: Optional[int],
+             want_stats: bool):
+        dev = f"cuda:{self.device}"
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            row_ptr = torch.empty(m + 1, dtype=torch.int64, device=dev)
+            cap = int(nnz_cap) if nnz_cap is not None else max(self._nnz_hint, 4 * m, 1024)
+            for _ in range(3):
+                col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+                dist = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+                csr = snn_csr(row_ptr.data_ptr(), col.data_ptr(), dist.data_ptr(), cap, 0)
+                st = snn_stats()
+                if Q is None:
+                    status = lib().snn_query_self(self._h, float(R), ctypes.byref(opts), ctypes.byref(csr),
+                                                  ctypes.byref(st))
+                else:
+                    status = lib().snn_query(self._h, ctypes.c_void_p(Q.data_ptr()), m, float(R),
+                                             ctypes.byref(opts), ctypes.byref(csr), ctypes.byref(st))
+                if status == SNN_EOVERFLOW and nnz_cap is None:
+                    cap = int(csr.nnz)
+                    continue
+                _check(status)
+                break
+            nnz = int(csr.nnz)
+            self._nnz_hint = max(self._nnz_hint, nnz + nnz // 4)
+            res = (row_ptr, col[:nnz], dist[:nnz])
+            return (res + (st.as_dict(),)) if want_stats else res
+
+    def query(self, Q: torch.Tensor, R: float, precision: str = "auto", terms: int = 0, tile_q: int = 0,
+              tile_c: int = 0, nnz_cap: Optional[int] = None, stats: bool = False):
+        """Algorithm 2 for the rows of Q (m x d, same dtype and device)."""
+        if not isinstance(Q, torch.Tensor) or not Q.is_cuda or Q.dim() != 2 or Q.shape[1] != self.d:
+            raise SnnError(SNN_EINVAL, "Q must be a CUDA tensor of shape (m, d)")
+        if Q.dtype != self.dtype:
+            raise SnnError(SNN_EINVAL, "Q must have the index dtype")
+        Q = Q.contiguous()
+        return self._run(Q, Q.shape[0], R, self._opts(precision, terms, tile_q, tile_c), nnz_cap, stats)
+
+    def query_self(self, R: float, precision: str = "auto", terms: int = 0, tile_q: int = 0, tile_c: int = 0,
+                   nnz_cap: Optional[int] = None, stats: bool = False):
+        """Every data row as a query (rows in original data order)."""
+        return self._run(None, self.n, R, self._opts(precision, terms, tile_q, tile_c), nnz_cap, stats)
+
+    def view(self) -> dict:
+        """Index internals copied into new tensors (for checks)."""
+        v = snn_index_view()
+        _check(lib().snn_index_get_view(self._h, ctypes.byref(v)))
+        torch.cuda.synchronize(self.device)
+        return {
+            "n": v.n,
+            "d": v.d,
+            "mu": _device_tensor_from_ptr(v.mu, v.d, torch.float64, self.device),
+            "v": _device_tensor_from_ptr(v.v, v.d, torch.float64, self.device),
+            "key": _device_tensor_from_ptr(v.key, v.n, torch.float64, self.device),
+            "perm": _device_tensor_from_ptr(v.perm, v.n, torch.int32, self.device),
+            "max_norm": v.max_norm,
+            "key_eps": v.key_eps,
+            "power_iters": v.power_iters,
+        }
+
+
+def sort_pairs_u32(keys: torch.Tensor, vals: torch.Tensor, begin_bit: int = 0, end_bit: int = 32) -> None:
+    """Stable LSD radix sort of (keys, vals) in place (uint32 data in int32 tensors)."""
+    if keys.shape != vals.shape or keys.dim() != 1 or not keys.is_cuda or not vals.is_cuda:
+        raise SnnError(SNN_EINVAL, "keys and vals must be 1-D CUDA tensors of equal length")
+    if keys.dtype not in (torch.int32, torch.uint32) or vals.dtype not in (torch.int32, torch.uint32):
+        raise SnnError(SNN_EINVAL, "keys and vals must be 32-bit")
+    if not keys.is_contiguous() or not vals.is_contiguous():
+        raise SnnError(SNN_EINVAL, "keys and vals must be contiguous")
+    device = keys.device.index
+    alloc = _TorchAllocator(device)
+    _check(lib().snn_sort_pairs_u32(ctypes.byref(alloc.dev), ctypes.c_void_p(keys.data_ptr()),
+                                    ctypes.c_void_p(vals.data_ptr()), keys.numel(), begin_bit, end_bit))

@@ -1,0 +1,141 @@
+// Device-side helpers shared by the gfx950 kernels: wavefront reductions,
+// order-preserving float keys, bf16 rounding, and an LDS-staged appender for
+// (query, candidate) pairs.  gfx950 wavefronts are 64 lanes wide.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snn {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Order-preserving map float -> uint32: a < b (as floats, -0 < +0) iff
+// key(a) < key(b).  NaN never reaches these kernels (inputs are checked).
+__host__ __device__ __forceinline__ uint32_t float_to_ordered(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ __forceinline__ float ordered_to_float(uint32_t k) {
+  uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  return __builtin_bit_cast(float, u);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    T w = __shfl_xor(v, o, kWave);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    T w = __shfl_xor(v, o, kWave);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+// Round-to-nearest-even float -> bf16 bits (finite inputs).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(r >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) {
+  return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+
+// atomicMax on non-negative doubles via their bit patterns (monotone for x >= 0).
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(addr),
+            (unsigned long long)__builtin_bit_cast(uint64_t, v));
+}
+
+// Survivor pairs are written as (query sorted position, candidate sorted
+// position).  Each workgroup stages its pairs in LDS and reserves global
+// space with one atomic at the end; if the LDS stage is full a pair goes
+// straight to global memory.  The global list has capacity `cap`; the
+// counter keeps counting past it so the host learns the size needed.
+struct PairSink {
+  int2* out;
+  unsigned long long* counter;
+  long long cap;
+};
+
+template <int kStage>
+struct PairStage {
+  int2 buf[kStage];
+  int count;
+  long long base;
+};
+
+template <int kStage>
+__device__ __forceinline__ void stage_init(PairStage<kStage>& st) {
+  if (threadIdx.x == 0) st.count = 0;
+}
+
+template <int kStage>
+__device__ __forceinline__ void stage_push(PairStage<kStage>& st, const PairSink& sink, int q, int j) {
+  int pos = atomicAdd(&st.count, 1);
+  if (pos < kStage) {
+    st.buf[pos] = make_int2(q, j);
+  } else {
+    unsigned long long g = atomicAdd(sink.counter, 1ull);
+    if ((long long)g < sink.cap) sink.out[g] = make_int2(q, j);
+  }
+}
+
+// Wave-aggregated push: every lane with `pred` pushes (q, j).  One LDS
+// atomic per wave.
+template <int kStage>
+__device__ __forceinline__ void stage_push_wave(PairStage<kStage>& st, const PairSink& sink, bool pred, int q,
+                                                int j) {
+  uint64_t mask = __ballot(pred);
+  if (mask == 0) return;
+  int cnt = __popcll(mask);
+  int leader = __ffsll((long long)mask) - 1;
+  int rank = __popcll(mask & ((1ull << lane_id()) - 1ull));
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(&st.count, cnt);
+  base = __shfl(base, leader, kWave);
+  if (pred) {
+    int pos = base + rank;
+    if (pos < kStage) {
+      st.buf[pos] = make_int2(q, j);
+    } else {
+      unsigned long long g = atomicAdd(sink.counter, 1ull);
+      if ((long long)g < sink.cap) sink.out[g] = make_int2(q, j);
+    }
+  }
+}
+
+// Must be called by all threads of the block after the last push.
+template <int kStage>
+__device__ __forceinline__ void stage_flush(PairStage<kStage>& st, const PairSink& sink) {
+  __syncthreads();
+  int cnt = st.count < kStage ? st.count : kStage;
+  if (threadIdx.x == 0) {
+    st.base = cnt ? (long long)atomicAdd(sink.counter, (unsigned long long)cnt) : 0;
+  }
+  __syncthreads();
+  long long base = st.base;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    long long g = base + i;
+    if (g < sink.cap) sink.out[g] = st.buf[i];
+  }
+}
+
+}  // namespace snn

@@ -1,0 +1,328 @@
+// From surviving (query, candidate) pairs to CSR neighbour lists.
+//
+//  k_recheck  every survivor is decided by the normative rule on the
+//             original coordinates in float64 (direct form of eq. (ip1),
+//             left to right, no fused multiply-add; inclusive compare of
+//             Section 3.2).  Neighbours take a slot in their row.
+//  (scan)     row counts -> row_ptr
+//  k_scatter  neighbours into their rows
+//  row sort   ids ascending within each row: rows of <= 16 entries by one
+//             lane, <= 64 by one wavefront (bitonic across lanes), longer by
+//             one workgroup (bitonic in LDS, then merge passes).
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "device_common.h"
+#include "query_plan.h"
+#include "snn_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace snn {
+
+namespace {
+constexpr int kThreads = 256;
+
+__global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, int32_t* __restrict__ row_cnt) {
+  const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count);
+  const int d = q.d;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int2 pr = sv.pairs[i];
+    const double* qp = q.q64 + (int64_t)pr.x * q.dp;
+    const double* pp = q.p64 + (int64_t)pr.y * q.dp;
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const double t = pp[k] - qp[k];
+      s = s + t * t;
+    }
+    if (s <= q.R2) {
+      const int qo = q.qorig[pr.x];
+      sv.res_q[i] = qo;
+      sv.res_id[i] = q.perm[pr.y];
+      sv.res_dist[i] = (float)sqrt(s);
+      sv.res_slot[i] = atomicAdd(&row_cnt[qo], 1);
+    } else {
+      sv.res_q[i] = -1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(Survivors sv, const int64_t* __restrict__ row_ptr,
+                                                     int32_t* __restrict__ col, float* __restrict__ dist) {
+  const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int qo = sv.res_q[i];
+    if (qo < 0) continue;
+    const int64_t pos = row_ptr[qo] + sv.res_slot[i];
+    col[pos] = sv.res_id[i];
+    dist[pos] = sv.res_dist[i];
+  }
+}
+
+// rows of <= 16: insertion sort by one lane; others go to the wave / block lists
+__global__ __launch_bounds__(kThreads) void k_row_sort_small(const int64_t* __restrict__ row_ptr, int64_t m,
+                                                            int32_t* __restrict__ col, float* __restrict__ dist,
+                                                            int32_t* __restrict__ mid_list,
+                                                            int32_t* __restrict__ long_list,
+                                                            unsigned long long* __restrict__ counts) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = row_ptr[r], e = row_ptr[r + 1];
+    const int64_t len = e - b;
+    if (len <= 1) continue;
+    if (len <= 16) {
+      int32_t c[16];
+      float dd[16];
+      for (int i = 0; i < len; ++i) {
+        c[i] = col[b + i];
+        dd[i] = dist[b + i];
+      }
+      for (int i = 1; i < len; ++i) {
+        int32_t ci = c[i];
+        float di = dd[i];
+        int k = i - 1;
+        while (k >= 0 && c[k] > ci) {
+          c[k + 1] = c[k];
+          dd[k + 1] = dd[k];
+          --k;
+        }
+        c[k + 1] = ci;
+        dd[k + 1] = di;
+      }
+      for (int i = 0; i < len; ++i) {
+        col[b + i] = c[i];
+        dist[b + i] = dd[i];
+      }
+    } else if (len <= 64) {
+      mid_list[atomicAdd(&counts[0], 1ull)] = (int32_t)r;
+    } else {
+      long_list[atomicAdd(&counts[1], 1ull)] = (int32_t)r;
+    }
+  }
+}
+
+// one wavefront per row of 17..64 entries: bitonic sort across lanes
+__global__ __launch_bounds__(kThreads) void k_row_sort_wave(const int64_t* __restrict__ row_ptr,
+                                                           int32_t* __restrict__ col, float* __restrict__ dist,
+                                                           const int32_t* __restrict__ mid_list,
+                                                           const unsigned long long* __restrict__ counts) {
+  const long long nrows = (long long)counts[0];
+  const int lane = lane_id();
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) / kWave;
+  for (long long w = wave; w < nrows; w += nwaves) {
+    const int r = mid_list[w];
+    const int64_t b = row_ptr[r], e = row_ptr[r + 1];
+    const int len = (int)(e - b);
+    int32_t c = lane < len ? col[b + lane] : INT_MAX;
+    float dd = lane < len ? dist[b + lane] : 0.f;
+    for (int k = 2; k <= kWave; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int32_t oc = __shfl_xor(c, j, kWave);
+        const float od = __shfl_xor(dd, j, kWave);
+        const bool up = ((lane & k) == 0);
+        const bool lower = ((lane & j) == 0);
+        const bool take_min = (up == lower);
+        const bool swap = take_min ? (oc < c) : (oc > c);
+        if (swap) {
+          c = oc;
+          dd = od;
+        }
+      }
+    }
+    if (lane < len) {
+      col[b + lane] = c;
+      dist[b + lane] = dd;
+    }
+  }
+}
+
+constexpr int kBlockSort = 4096;
+
+__device__ __forceinline__ void bitonic_lds(uint64_t* a, int n) {
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t x = a[i], y = a[ixj];
+          const bool up = ((i & k) == 0);
+          if ((x > y) == up) {
+            a[i] = y;
+            a[ixj] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ uint64_t pack_cd(int32_t c, float d) {
+  return ((uint64_t)(uint32_t)c << 32) | (uint64_t)__builtin_bit_cast(uint32_t, d);
+}
+
+// one workgroup per row of > 64 entries: sort runs of 4096 in LDS, then
+// merge runs pairwise (each element finds its rank in the partner run by
+// binary search; ids are unique within a row).
+__global__ __launch_bounds__(kThreads) void k_row_sort_block(const int64_t* __restrict__ row_ptr,
+                                                            int32_t* __restrict__ col, float* __restrict__ dist,
+                                                            const int32_t* __restrict__ long_list,
+                                                            const unsigned long long* __restrict__ counts,
+                                                            int32_t* __restrict__ tmp_col,
+                                                            float* __restrict__ tmp_dist) {
+  __shared__ uint64_t a[kBlockSort];
+  const long long nrows = (long long)counts[1];
+  for (long long w = blockIdx.x; w < nrows; w += gridDim.x) {
+    const int r = long_list[w];
+    const int64_t b = row_ptr[r], e = row_ptr[r + 1];
+    const int64_t len = e - b;
+    for (int64_t c0 = 0; c0 < len; c0 += kBlockSort) {
+      const int cl = (int)min((int64_t)kBlockSort, len - c0);
+      int np2 = 1;
+      while (np2 < cl) np2 <<= 1;
+      __syncthreads();
+      for (int i = threadIdx.x; i < np2; i += blockDim.x)
+        a[i] = i < cl ? pack_cd(col[b + c0 + i], dist[b + c0 + i]) : ~0ull;
+      __syncthreads();
+      bitonic_lds(a, np2);
+      for (int i = threadIdx.x; i < cl; i += blockDim.x) {
+        col[b + c0 + i] = (int32_t)(a[i] >> 32);
+        dist[b + c0 + i] = __builtin_bit_cast(float, (uint32_t)(a[i] & 0xffffffffu));
+      }
+    }
+    __syncthreads();
+    // merge passes: runs of `width` sorted, ping-pong through tmp (at the
+    // row's own offset, tmp has the caller's capacity)
+    int32_t *sc = col + b, *dc = tmp_col + b;
+    float *sd = dist + b, *dd = tmp_dist + b;
+    bool in_tmp = false;
+    for (int64_t width = kBlockSort; width < len; width <<= 1) {
+      for (int64_t i = threadIdx.x; i < len; i += blockDim.x) {
+        const int64_t run = i / width;
+        const int64_t rs = run * width;
+        const int64_t ps = (run ^ 1) * width;  // partner run start
+        const int64_t pair = min(rs, ps);
+        const int32_t key = sc[i];
+        int64_t rank = 0;
+        if (ps < len) {
+          int64_t lo = ps, hi = min(ps + width, len);
+          while (lo < hi) {
+            const int64_t md = (lo + hi) >> 1;
+            if (sc[md] < key)
+              lo = md + 1;
+            else
+              hi = md;
+          }
+          rank = lo - ps;
+        }
+        const int64_t out = pair + (i - rs) + rank;
+        dc[out] = key;
+        dd[out] = sd[i];
+      }
+      __syncthreads();
+      int32_t* t1 = sc;
+      sc = dc;
+      dc = t1;
+      float* t2 = sd;
+      sd = dd;
+      dd = t2;
+      in_tmp = !in_tmp;
+    }
+    if (in_tmp) {
+      for (int64_t i = threadIdx.x; i < len; i += blockDim.x) {
+        dc[i] = sc[i];
+        dd[i] = sd[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_row_max(const int32_t* __restrict__ cnt, int64_t m,
+                                                      unsigned long long* __restrict__ out) {
+  int v = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    v = max(v, cnt[i]);
+  v = wave_max(v);
+  if (lane_id() == 0 && v > 0) atomicMax(out, (unsigned long long)v);
+}
+
+__global__ void k_self_qnorm(const float* __restrict__ ynorm, int64_t n, double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (double)ynorm[i];
+}
+
+int grid_for(int64_t work, int cap) {
+  int64_t g = (work + kThreads - 1) / kThreads;
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+}  // namespace
+
+void launch_row_max(const int32_t* row_cnt, int64_t m, unsigned long long* out, hipStream_t s) {
+  if (m <= 0) return;
+  k_row_max<<<grid_for(m, 1024), kThreads, 0, s>>>(row_cnt, m, out);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_self_qnorm(const float* ynorm, int64_t n, double* out, hipStream_t s) {
+  k_self_qnorm<<<grid_for(n, 4096), kThreads, 0, s>>>(ynorm, n, out);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_recheck(const QueryDev& q, const Survivors& sv, int32_t* row_cnt, int grid, hipStream_t s) {
+  k_recheck<<<grid, kThreads, 0, s>>>(q, sv, row_cnt);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_scatter(const Survivors& sv, const int64_t* row_ptr, int32_t* col, float* dist, int grid,
+                    hipStream_t s) {
+  k_scatter<<<grid, kThreads, 0, s>>>(sv, row_ptr, col, dist);
+  SNN_LAUNCH_CHECK();
+}
+
+// lists: 2*m int32 (mid rows, long rows) followed by nothing; list_counts: 2
+// counters; the tmp arrays for long-row merges reuse lists' tail when given.
+void launch_row_sort(const int64_t* row_ptr, int64_t m, int32_t* col, float* dist, int32_t* lists,
+                     unsigned long long* list_counts, int grid, hipStream_t s) {
+  (void)grid;
+  k_fill_u64<<<1, 64, 0, s>>>(list_counts, 2, 0ull);
+  SNN_LAUNCH_CHECK();
+  if (m <= 0) return;
+  k_row_sort_small<<<grid_for(m, 8192), kThreads, 0, s>>>(row_ptr, m, col, dist, lists, lists + m, list_counts);
+  SNN_LAUNCH_CHECK();
+  k_row_sort_wave<<<1024, kThreads, 0, s>>>(row_ptr, col, dist, lists, list_counts);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_row_sort_long(const int64_t* row_ptr, int32_t* col, float* dist, const int32_t* long_list,
+                          const unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s) {
+  k_row_sort_block<<<512, kThreads, 0, s>>>(row_ptr, col, dist, long_list, list_counts, tmp_col, tmp_dist);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill_u64<<<grid_for(n, 4096), kThreads, 0, s>>>(p, n, v);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return;
+  k_fill_i32<<<grid_for(n, 4096), kThreads, 0, s>>>(p, n, v);
+  SNN_LAUNCH_CHECK();
+}
+
+}  // namespace snn

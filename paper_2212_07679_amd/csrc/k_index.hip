@@ -1,0 +1,434 @@
+// Index construction (Algorithm 1, Section 3.1) on gfx950.
+//
+//  step 2  column means          k_colsum_partial + k_colsum_final (float64,
+//                                fixed-order reductions: deterministic)
+//  step 4  first principal dir.  centred Gram matrix C = X^T X in float64
+//                                (register-tiled, LDS-staged rows) and a
+//                                power iteration in one workgroup.  The SVD of
+//                                eq. (svd) is replaced: any unit direction
+//                                keeps the query exact (eq. (lower)); only
+//                                the window sizes depend on it.
+//  step 5  scores                key_i = fl32(x_i . v), x_i = p_i - mu in float64
+//  step 6  sort                  LSD radix sort of order-preserving keys
+//  step 7  norms                 h_i = ||y_i||^2 / 2 with y_i = fl32(p_i - mu),
+//                                gathered with the rows into score order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "device_common.h"
+#include "snn_internal.h"
+
+namespace snn {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename T>
+__device__ __forceinline__ double ld(const T* p, int64_t i) {
+  return (double)p[i];
+}
+
+// ---- step 2: column sums ---------------------------------------------------
+// Thread layout: cols_per_pass = min(d, 256) consecutive columns, rows_per_pass
+// rows at once; each thread owns one column of a fixed row subset.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_colsum_partial(const T* __restrict__ X, int64_t n, int d,
+                                                            int64_t rows_per_block, double* __restrict__ part,
+                                                            int* __restrict__ bad) {
+  __shared__ double red[kThreads];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(n, r0 + rows_per_block);
+  int badloc = 0;
+  for (int c0 = 0; c0 < d; c0 += kThreads) {
+    const int cpp = min(d - c0, kThreads);
+    const int rpp = kThreads / cpp;
+    const int roff = t / cpp, c = c0 + t % cpp;
+    double s = 0.0;
+    if (roff < rpp) {
+      for (int64_t r = r0 + roff; r < r1; r += rpp) {
+        double x = ld(X, r * d + c);
+        if (!isfinite(x)) badloc = 1;
+        s += x;
+      }
+    }
+    red[t] = (roff < rpp) ? s : 0.0;
+    __syncthreads();
+    if (t < cpp) {
+      double tot = 0.0;
+      for (int k = 0; k < rpp; ++k) tot += red[k * cpp + t];
+      part[(int64_t)blockIdx.x * d + c0 + t] = tot;
+    }
+    __syncthreads();
+  }
+  if (badloc) atomicOr(bad, 1);
+}
+
+__global__ void k_colsum_final(const double* __restrict__ part, int nblocks, int d, int64_t n,
+                               double* __restrict__ mu) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d; c += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * d + c];
+    mu[c] = s / (double)n;
+  }
+}
+
+// ---- step 4: centred Gram matrix --------------------------------------------
+// Each thread owns a TS x TS tile of C.  Rows are staged in LDS, centred in
+// float64.  blockIdx.y selects the group of 256 thread tiles (large d).
+template <typename T, int TS>
+__global__ __launch_bounds__(kThreads) void k_gram_partial(const T* __restrict__ X, int64_t n, int d,
+                                                          const double* __restrict__ mu, int64_t rows_per_block,
+                                                          int rows_chunk, double* __restrict__ part) {
+  extern __shared__ double stage[];  // rows_chunk x d
+  const int t = threadIdx.x;
+  const int tiles_1d = (d + TS - 1) / TS;
+  const int tile = blockIdx.y * kThreads + t;
+  const bool active = tile < tiles_1d * tiles_1d;
+  const int ta = active ? (tile / tiles_1d) * TS : 0;
+  const int tb = active ? (tile % tiles_1d) * TS : 0;
+  double acc[TS][TS];
+#pragma unroll
+  for (int i = 0; i < TS; ++i)
+#pragma unroll
+    for (int j = 0; j < TS; ++j) acc[i][j] = 0.0;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(n, r0 + rows_per_block);
+  for (int64_t rc = r0; rc < r1; rc += rows_chunk) {
+    const int rows = (int)min((int64_t)rows_chunk, r1 - rc);
+    __syncthreads();
+    for (int e = t; e < rows * d; e += kThreads) {
+      int c = e % d;
+      stage[e] = ld(X, rc * d + e) - mu[c];
+    }
+    __syncthreads();
+    if (active) {
+      for (int r = 0; r < rows; ++r) {
+        const double* row = stage + r * d;
+        double a[TS], b[TS];
+#pragma unroll
+        for (int i = 0; i < TS; ++i) {
+          a[i] = (ta + i < d) ? row[ta + i] : 0.0;
+          b[i] = (tb + i < d) ? row[tb + i] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < TS; ++i)
+#pragma unroll
+          for (int j = 0; j < TS; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+      }
+    }
+  }
+  if (active) {
+    double* out = part + (int64_t)blockIdx.x * d * d;
+#pragma unroll
+    for (int i = 0; i < TS; ++i)
+#pragma unroll
+      for (int j = 0; j < TS; ++j)
+        if (ta + i < d && tb + j < d) out[(int64_t)(ta + i) * d + tb + j] = acc[i][j];
+  }
+}
+
+__global__ void k_gram_final(const double* __restrict__ part, int nblocks, int64_t dd, double* __restrict__ C) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < dd; e += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * dd + e];
+    C[e] = s;
+  }
+}
+
+__device__ double block_sum_1024(double v, double* red) {
+  const int t = threadIdx.x;
+  v = wave_sum(v);
+  __syncthreads();
+  if (t % kWave == 0) red[t / kWave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) s += red[w];
+  return s;
+}
+
+// Power iteration v <- C v / ||C v|| in one workgroup of 1024 threads, with v
+// and C v in LDS and C read from global memory (L2-resident).  Stops when
+// the Rayleigh quotient changes by less than 1e-12 relative (it converges at
+// twice the rate of v) or after max_iter.  The largest-magnitude entry is
+// made positive; C = 0 gives e_1.
+__global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ C, int d, int max_iter,
+                                                     double* __restrict__ v_out, int* __restrict__ iters_out) {
+  extern __shared__ double lds[];
+  __shared__ double red[16];
+  __shared__ int s_stop;
+  const int t = threadIdx.x;
+  double* v = lds;      // d
+  double* w = lds + d;  // d
+  // deterministic start: 1 + small distinct perturbation per coordinate
+  for (int i = t; i < d; i += blockDim.x) v[i] = 1.0 + 0.01 * (double)((i * 2654435761u) % 1000u) / 1000.0;
+  __syncthreads();
+  double loc = 0.0;
+  for (int i = t; i < d; i += blockDim.x) loc += v[i] * v[i];
+  double nv = sqrt(block_sum_1024(loc, red));
+  for (int i = t; i < d; i += blockDim.x) v[i] /= nv;
+  __syncthreads();
+  double lambda_prev = -1.0;
+  int it = 0;
+  bool zero = false;
+  for (it = 1; it <= max_iter; ++it) {
+    double part = 0.0;
+    for (int i = t; i < d; i += blockDim.x) {
+      double s = 0.0;
+      for (int j = 0; j < d; ++j) s += C[(int64_t)i * d + j] * v[j];
+      w[i] = s;
+      part += s * v[i];
+    }
+    double lambda = block_sum_1024(part, red);  // Rayleigh quotient v^T C v
+    loc = 0.0;
+    for (int i = t; i < d; i += blockDim.x) loc += w[i] * w[i];
+    double nw = sqrt(block_sum_1024(loc, red));
+    if (!(nw > 0.0)) {
+      zero = true;
+      break;
+    }
+    for (int i = t; i < d; i += blockDim.x) v[i] = w[i] / nw;
+    if (t == 0) s_stop = (fabs(lambda - lambda_prev) <= 1e-12 * fabs(lambda)) ? 1 : 0;
+    __syncthreads();
+    if (s_stop) break;
+    lambda_prev = lambda;
+  }
+  __syncthreads();
+  if (t == 0) {
+    if (zero) {
+      for (int i = 0; i < d; ++i) v[i] = (i == 0) ? 1.0 : 0.0;
+    }
+    int im = 0;
+    double am = -1.0;
+    for (int i = 0; i < d; ++i)
+      if (fabs(v[i]) > am) {
+        am = fabs(v[i]);
+        im = i;
+      }
+    double sgn = v[im] < 0 ? -1.0 : 1.0;
+    double ss = 0.0;
+    for (int i = 0; i < d; ++i) ss += v[i] * v[i];
+    double inv = 1.0 / sqrt(ss);
+    for (int i = 0; i < d; ++i) v_out[i] = sgn * v[i] * inv;
+    *iters_out = it > max_iter ? max_iter : it;
+  }
+}
+
+// ---- step 5: scores ----------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_project(const T* __restrict__ X, int64_t n, int d,
+                                                     const double* __restrict__ mu, const double* __restrict__ v,
+                                                     uint32_t* __restrict__ ukey, uint32_t* __restrict__ val,
+                                                     double* __restrict__ max_norm) {
+  double nmax = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T* p = X + i * d;
+    double a = 0.0, nn = 0.0;
+    for (int k = 0; k < d; ++k) {
+      double x = (double)p[k] - mu[k];
+      a += x * v[k];
+      double y = (double)(float)x;
+      nn += y * y;
+    }
+    ukey[i] = float_to_ordered((float)a);
+    val[i] = (uint32_t)i;
+    nmax = fmax(nmax, nn);
+  }
+  nmax = wave_max(nmax);
+  if (lane_id() == 0) atomic_max_nonneg(max_norm, nmax);
+}
+
+// ---- gather into score order -------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, int64_t n, int d, int dp,
+                                                    const double* __restrict__ mu,
+                                                    const uint32_t* __restrict__ ukey,
+                                                    const uint32_t* __restrict__ val, double* __restrict__ key,
+                                                    int32_t* __restrict__ perm, T* __restrict__ po,
+                                                    double* __restrict__ p64, float* __restrict__ ys,
+                                                    float* __restrict__ h, float* __restrict__ ynorm) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t i = val[s];
+    perm[s] = (int32_t)i;
+    key[s] = (double)ordered_to_float(ukey[s]);
+    const T* p = X + (int64_t)i * d;
+    double nn = 0.0;
+    for (int k = 0; k < d; ++k) {
+      T x = p[k];
+      po[s * d + k] = x;
+      p64[s * dp + k] = (double)x;
+      float y = (float)((double)x - mu[k]);
+      ys[s * d + k] = y;
+      nn += (double)y * (double)y;
+    }
+    for (int k = d; k < dp; ++k) p64[s * dp + k] = 0.0;
+    h[s] = (float)(0.5 * nn);
+    // round ||y|| up to float so it bounds the true norm
+    float nr = (float)sqrt(nn);
+    if ((double)nr < sqrt(nn)) nr = nextafterf(nr, INFINITY);
+    ynorm[s] = nr;
+  }
+}
+
+// ---- mixed-precision operand rows ---------------------------------------------
+// terms = 1: row = [bf16(y_0..y_{d-1}), 0...]                 (ka = pad16(d))
+// terms = 3: cand = [hi | lo | hi], query = [hi | hi | lo]     (ka = pad16(3d))
+// with hi = bf16(y), lo = bf16(y - hi) (y - hi is exact in float).
+__global__ __launch_bounds__(kThreads) void k_operands(const float* __restrict__ ys, int64_t n, int d, int terms,
+                                                      int ka, uint16_t* __restrict__ cand,
+                                                      uint16_t* __restrict__ qself) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * ka; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / ka;
+    const int k = (int)(e % ka);
+    uint16_t cv = 0, qv = 0;
+    if (terms == 1) {
+      if (k < d) cv = qv = f32_to_bf16_rne(ys[s * d + k]);
+    } else if (k < 3 * d) {
+      const int seg = k / d, c = k % d;
+      const float y = ys[s * d + c];
+      const uint16_t hi = f32_to_bf16_rne(y);
+      const uint16_t lo = f32_to_bf16_rne(y - bf16_to_f32(hi));
+      cv = (seg == 1) ? lo : hi;
+      qv = (seg == 2) ? lo : hi;
+    }
+    cand[e] = cv;
+    if (qself) qself[e] = qv;
+  }
+}
+
+int grid_for(int64_t work, int per_block = kThreads, int cap = 8192) {
+  int64_t g = (work + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+template <typename T>
+void build_index_t(Index& ix, const T* X) {
+  hipStream_t s = ix.arena.stream();
+  const int64_t n = ix.n;
+  const int d = ix.d;
+  const DeviceInfo& di = device_info(ix.arena.dev().device);
+
+  ix.mu.ensure(ix.arena, sizeof(double) * d);
+  ix.v.ensure(ix.arena, sizeof(double) * d);
+  ix.key.ensure(ix.arena, sizeof(double) * n);
+  ix.perm.ensure(ix.arena, sizeof(int32_t) * n);
+  ix.po.ensure(ix.arena, sizeof(T) * n * d);
+  ix.p64.ensure(ix.arena, sizeof(double) * n * ix.dp);
+  ix.ys.ensure(ix.arena, sizeof(float) * n * d);
+  ix.h.ensure(ix.arena, sizeof(float) * n);
+  ix.ynorm.ensure(ix.arena, sizeof(float) * n);
+
+  // scratch: partials, flags, Gram, power-iteration work
+  const int g1 = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 2047) / 2048));
+  const int64_t rpb1 = (n + g1 - 1) / g1;
+  int ts = 1;
+  while (ts < 8 && (d + ts - 1) / ts > 16) ts *= 2;
+  const int tiles_1d = (d + ts - 1) / ts;
+  const int gy = (tiles_1d * tiles_1d + kThreads - 1) / kThreads;
+  int64_t dd = (int64_t)d * d;
+  int g2 = (int)std::min<int64_t>(std::max<int64_t>(1, (n + 4095) / 4096), 2 * (int64_t)di.cus);
+  g2 = (int)std::max<int64_t>(1, std::min<int64_t>(g2, (int64_t)(256ll << 20) / (dd * 8)));
+  const int64_t rpb2 = (n + g2 - 1) / g2;
+  const int rows_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, 4096 / d));
+
+  struct Scratch {
+    int bad;
+    int iters;
+    double max_norm;
+  };
+  const size_t off_part1 = 256;
+  const size_t off_part2 = off_part1 + ((sizeof(double) * g1 * d + 255) & ~size_t(255));
+  const size_t off_C = off_part2 + ((sizeof(double) * g2 * dd + 255) & ~size_t(255));
+  const size_t off_keys = off_C + ((sizeof(double) * dd + 255) & ~size_t(255));
+  const size_t total = off_keys + 2 * sizeof(uint32_t) * n + 256;
+  char* mem = static_cast<char*>(ix.arena.alloc(total));
+  Scratch* sc = reinterpret_cast<Scratch*>(mem);
+  double* part1 = reinterpret_cast<double*>(mem + off_part1);
+  double* part2 = reinterpret_cast<double*>(mem + off_part2);
+  double* C = reinterpret_cast<double*>(mem + off_C);
+  uint32_t* ukey = reinterpret_cast<uint32_t*>(mem + off_keys);
+  uint32_t* val = ukey + n;
+
+  SNN_HIP(hipMemsetAsync(sc, 0, sizeof(Scratch), s));
+  k_colsum_partial<T><<<g1, kThreads, 0, s>>>(X, n, d, rpb1, part1, &sc->bad);
+  SNN_LAUNCH_CHECK();
+  k_colsum_final<<<(d + 255) / 256, 256, 0, s>>>(part1, g1, d, n, ix.mu.as<double>());
+  SNN_LAUNCH_CHECK();
+
+  const size_t lds2 = sizeof(double) * rows_chunk * d;
+  dim3 grid2(g2, gy);
+  switch (ts) {
+    case 1: k_gram_partial<T, 1><<<grid2, kThreads, lds2, s>>>(X, n, d, ix.mu.as<double>(), rpb2, rows_chunk, part2); break;
+    case 2: k_gram_partial<T, 2><<<grid2, kThreads, lds2, s>>>(X, n, d, ix.mu.as<double>(), rpb2, rows_chunk, part2); break;
+    case 4: k_gram_partial<T, 4><<<grid2, kThreads, lds2, s>>>(X, n, d, ix.mu.as<double>(), rpb2, rows_chunk, part2); break;
+    default: k_gram_partial<T, 8><<<grid2, kThreads, lds2, s>>>(X, n, d, ix.mu.as<double>(), rpb2, rows_chunk, part2); break;
+  }
+  SNN_LAUNCH_CHECK();
+  k_gram_final<<<grid_for(dd), kThreads, 0, s>>>(part2, g2, dd, C);
+  SNN_LAUNCH_CHECK();
+  k_power_iter<<<1, 1024, 2 * sizeof(double) * d, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
+  SNN_LAUNCH_CHECK();
+  k_project<T><<<grid_for(n, kThreads, 4 * di.cus * 8), kThreads, 0, s>>>(X, n, d, ix.mu.as<double>(),
+                                                                          ix.v.as<double>(), ukey, val,
+                                                                          &sc->max_norm);
+  SNN_LAUNCH_CHECK();
+  radix_sort_pairs(ix.arena, ukey, val, n, 0, 32, s);
+  T* po = ix.po.as<T>();
+  double* p64 = ix.p64.as<double>();
+  k_gather<T><<<grid_for(n, kThreads, 4 * di.cus * 8), kThreads, 0, s>>>(
+      X, n, d, ix.dp, ix.mu.as<double>(), ukey, val, ix.key.as<double>(), ix.perm.as<int32_t>(), po, p64,
+      ix.ys.as<float>(), ix.h.as<float>(), ix.ynorm.as<float>());
+  SNN_LAUNCH_CHECK();
+
+  Scratch hs;
+  SNN_HIP(hipMemcpyAsync(&hs, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+  SNN_HIP(hipStreamSynchronize(s));
+  ix.arena.release(mem);
+  if (hs.bad) fail(SNN_EINVAL, "snn_index: X contains NaN or Inf");
+  std::vector<double> vh(d);
+  SNN_HIP(hipMemcpy(vh.data(), ix.v.ptr, sizeof(double) * d, hipMemcpyDeviceToHost));
+  double vn = 0.0;
+  for (double x : vh) vn += x * x;
+  const double u64 = std::ldexp(1.0, -53), u32 = std::ldexp(1.0, -24);
+  ix.vnorm = std::sqrt(vn) * (1.0 + 4.0 * (d + 2) * u64);
+  ix.max_norm = std::sqrt(hs.max_norm) * (1.0 + 4.0 * (d + 2) * u64);
+  ix.power_iters = hs.iters;
+  // |fl32(fl64(x . v)) - (p - mu).v| <= (u32 + gamma64_{d+2}) ||p - mu|| ||v||,
+  // and ||p - mu|| <= ||y|| (1 + u32) with y = fl32(p - mu).
+  const double g64 = (d + 2) * u64 / (1.0 - (d + 2) * u64);
+  ix.key_eps = 1.01 * (u32 + g64) * (1.0 + u32) * ix.max_norm * ix.vnorm;
+}
+
+}  // namespace
+
+void build_index(Index& ix, const void* X) {
+  if (ix.dtype == SNN_F32)
+    build_index_t<float>(ix, static_cast<const float*>(X));
+  else
+    build_index_t<double>(ix, static_cast<const double*>(X));
+}
+
+void build_mixed_operands(Index& ix, int terms) {
+  MixedOperands& mo = ix.mixed[terms == 1 ? 0 : 1];
+  if (mo.terms == terms) return;
+  const int d = ix.d;
+  const int ka = terms == 1 ? ((d + 15) / 16) * 16 : ((3 * d + 15) / 16) * 16;
+  mo.cand.ensure(ix.arena, sizeof(uint16_t) * ix.n * ka + 256);
+  uint16_t* qself = nullptr;
+  if (terms == 3) {
+    mo.qself.ensure(ix.arena, sizeof(uint16_t) * ix.n * ka + 256);
+    qself = mo.qself.as<uint16_t>();
+  }
+  const DeviceInfo& di = device_info(ix.arena.dev().device);
+  k_operands<<<grid_for(ix.n * ka, kThreads, 4 * di.cus * 8), kThreads, 0, ix.arena.stream()>>>(
+      ix.ys.as<float>(), ix.n, d, terms, ka, mo.cand.as<uint16_t>(), qself);
+  SNN_LAUNCH_CHECK();
+  mo.terms = terms;
+  mo.ka = ka;
+}
+
+}  // namespace snn

@@ -1,0 +1,209 @@
+// Query preparation and windows (Algorithm 2, steps 2-4, Section 3.2).
+//
+//  k_query_keys    x_q = q - mu, alpha_q = x_q . v (float64), ||fl32(x_q)||,
+//                  order-preserving key of fl32(alpha_q) for the query sort
+//  (radix sort)    queries into score order, so that a tile of consecutive
+//                  queries shares one union window (the gemm over the union
+//                  of candidate sets, Section 4)
+//  k_query_gather  query rows in float64, score order
+//  k_window        J_q = [lo_q, hi_q) by binary search on the sorted keys,
+//                  with the window half-width widened outward by a rigorous
+//                  bound on the score rounding (eq. (lower) is exact only for
+//                  exact scores); per-tile union windows
+//  k_tile_units    work units per tile
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "device_common.h"
+#include "query_plan.h"
+#include "snn_internal.h"
+
+namespace snn {
+
+namespace {
+constexpr int kThreads = 256;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_query_keys(const T* __restrict__ Q, int64_t m, int d,
+                                                        const double* __restrict__ mu,
+                                                        const double* __restrict__ v, uint32_t* __restrict__ ukey,
+                                                        uint32_t* __restrict__ val, double* __restrict__ qalpha,
+                                                        double* __restrict__ qnorm, int* __restrict__ bad) {
+  int badloc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const T* q = Q + i * d;
+    double a = 0.0, nn = 0.0;
+    for (int k = 0; k < d; ++k) {
+      double qk = (double)q[k];
+      if (!isfinite(qk)) badloc = 1;
+      double x = qk - mu[k];
+      a += x * v[k];
+      double y = (double)(float)x;
+      nn += y * y;
+    }
+    ukey[i] = float_to_ordered((float)a);
+    val[i] = (uint32_t)i;
+    qalpha[i] = a;
+    qnorm[i] = sqrt(nn);
+  }
+  if (badloc) atomicOr(bad, 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_query_gather(const T* __restrict__ Q, int64_t m, int d, int dp,
+                                                          const uint32_t* __restrict__ qperm,
+                                                          const double* __restrict__ qalpha_in,
+                                                          const double* __restrict__ qnorm_in,
+                                                          double* __restrict__ q64, int32_t* __restrict__ qorig,
+                                                          double* __restrict__ qalpha, double* __restrict__ qnorm) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m * dp; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / dp;
+    const int k = (int)(e % dp);
+    const uint32_t i = qperm[s];
+    q64[e] = k < d ? (double)Q[(int64_t)i * d + k] : 0.0;
+    if (k == 0) {
+      qorig[s] = (int32_t)i;
+      qalpha[s] = qalpha_in[i];
+      qnorm[s] = qnorm_in[i];
+    }
+  }
+}
+
+// lower_bound: first index with key >= x;  upper_bound: first index with key > x
+__device__ __forceinline__ int lower_bound_d(const double* __restrict__ key, int n, double x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (key[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+__device__ __forceinline__ int upper_bound_d(const double* __restrict__ key, int n, double x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (key[mid] <= x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// W_q = (R ||v|| (1 + 4 gamma_{d+3}) + key_eps + eps_q) (1 + 8u) with
+// eps_q = eps_scale * ||y_q||; the bounds are then rounded outward.
+// Requires T % 64 == 0 so that a wavefront never straddles two tiles.
+__global__ __launch_bounds__(kThreads) void k_window(const double* __restrict__ key, int n,
+                                                    const double* __restrict__ qalpha,
+                                                    const double* __restrict__ qnorm, int64_t m, double w_base,
+                                                    double eps_scale, int T, int32_t* __restrict__ lo_out,
+                                                    int32_t* __restrict__ hi_out, int32_t* __restrict__ tlo,
+                                                    int32_t* __restrict__ thi,
+                                                    unsigned long long* __restrict__ pairs_window) {
+  const double u = 1.1102230246251565e-16;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int lo = INT_MAX, hi = INT_MIN;
+  long long cnt = 0;
+  if (s < m) {
+    const double W = (w_base + eps_scale * qnorm[s]) * (1.0 + 8.0 * u);
+    const double a = qalpha[s];
+    const double lv = nextafter(a - W, -INFINITY);
+    const double hv = nextafter(a + W, INFINITY);
+    lo = lower_bound_d(key, n, lv);
+    hi = upper_bound_d(key, n, hv);
+    if (lo_out) {
+      lo_out[s] = lo;
+      hi_out[s] = hi;
+    }
+    cnt = hi > lo ? hi - lo : 0;
+    if (hi <= lo) {  // empty window: neutral for the tile union
+      lo = INT_MAX;
+      hi = INT_MIN;
+    }
+  }
+  int wlo = wave_min(lo), whi = wave_max(hi);
+  long long wc = wave_sum(cnt);
+  const int64_t s0 = s - lane_id();
+  if (lane_id() == 0 && s0 < m) {
+    const int tile = (int)(s0 / T);
+    if (wlo != INT_MAX) {
+      atomicMin(&tlo[tile], wlo);
+      atomicMax(&thi[tile], whi);
+    }
+    atomicAdd(pairs_window, (unsigned long long)wc);
+  }
+}
+
+__global__ void k_tile_init(int32_t* __restrict__ tlo, int32_t* __restrict__ thi, int ntiles) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
+    tlo[t] = INT_MAX;
+    thi[t] = INT_MIN;
+  }
+}
+
+__global__ void k_tile_units(int32_t* __restrict__ tlo, int32_t* __restrict__ thi, int ntiles, int CH,
+                             int32_t* __restrict__ units) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
+    int a = tlo[t], b = thi[t];
+    if (a == INT_MAX || b <= a) {
+      tlo[t] = 0;
+      thi[t] = 0;
+      units[t] = 0;
+    } else {
+      units[t] = (int32_t)(((int64_t)b - a + CH - 1) / CH);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+namespace {
+int grid_for(int64_t work, int cap) {
+  int64_t g = (work + kThreads - 1) / kThreads;
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+}  // namespace
+
+void launch_query_keys(snn_dtype dt, const void* Q, int64_t m, int d, const double* mu, const double* v,
+                       uint32_t* ukey, uint32_t* val, double* qalpha, double* qnorm, int* bad, hipStream_t s) {
+  const int g = grid_for(m, 8192);
+  if (dt == SNN_F32)
+    k_query_keys<float><<<g, kThreads, 0, s>>>((const float*)Q, m, d, mu, v, ukey, val, qalpha, qnorm, bad);
+  else
+    k_query_keys<double><<<g, kThreads, 0, s>>>((const double*)Q, m, d, mu, v, ukey, val, qalpha, qnorm, bad);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, const uint32_t* qperm,
+                         const double* qalpha_in, const double* qnorm_in, double* q64, int32_t* qorig,
+                         double* qalpha, double* qnorm, hipStream_t s) {
+  const int g = grid_for(m * dp, 16384);
+  if (dt == SNN_F32)
+    k_query_gather<float><<<g, kThreads, 0, s>>>((const float*)Q, m, d, dp, qperm, qalpha_in, qnorm_in, q64, qorig,
+                                                 qalpha, qnorm);
+  else
+    k_query_gather<double><<<g, kThreads, 0, s>>>((const double*)Q, m, d, dp, qperm, qalpha_in, qnorm_in, q64, qorig,
+                                                  qalpha, qnorm);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_windows(const double* key, int n, const double* qalpha, const double* qnorm, int64_t m, double w_base,
+                    double eps_scale, int T, int CH, int ntiles, int32_t* lo, int32_t* hi, int32_t* tlo,
+                    int32_t* thi, int32_t* units, unsigned long long* pairs_window, hipStream_t s) {
+  k_tile_init<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles);
+  SNN_LAUNCH_CHECK();
+  if (m > 0) {
+    k_window<<<(unsigned)((m + kThreads - 1) / kThreads), kThreads, 0, s>>>(key, n, qalpha, qnorm, m, w_base,
+                                                                           eps_scale, T, lo, hi, tlo, thi,
+                                                                           pairs_window);
+    SNN_LAUNCH_CHECK();
+  }
+  k_tile_units<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles, CH, units);
+  SNN_LAUNCH_CHECK();
+}
+
+}  // namespace snn

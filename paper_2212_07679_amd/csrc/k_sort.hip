@@ -1,0 +1,256 @@
+// LSD radix sort of (uint32 key, uint32 value) pairs and exclusive scans.
+//
+// Algorithm 1 step 6 sorts the data by score; here the scores are mapped to
+// order-preserving uint32 keys and sorted least-significant digit first with
+// 8-bit digits.  Each pass: per-block digit histograms (digit-major layout),
+// one exclusive scan over them, and a stable scatter in which every block
+// ranks its keys with wavefront ballots (64-lane match of equal digits) and
+// LDS counters, so equal keys keep their input order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device_common.h"
+#include "snn_internal.h"
+
+namespace snn {
+
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per block
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                            int shift, uint32_t mask, uint32_t* __restrict__ hist,
+                                                            int nblocks) {
+  __shared__ uint32_t h[kSortThreads / kWave][kRadix];
+  const int t = threadIdx.x, w = t / kWave;
+  for (int i = t; i < (kSortThreads / kWave) * kRadix; i += kSortThreads) (&h[0][0])[i] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    int64_t idx = base + (int64_t)i * kSortThreads + t;
+    if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  if (t < kRadix) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int ww = 0; ww < kSortThreads / kWave; ++ww) s += h[ww][t];
+    hist[(int64_t)t * nblocks + blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                               const uint32_t* __restrict__ vin,
+                                                               uint32_t* __restrict__ kout,
+                                                               uint32_t* __restrict__ vout, int64_t n, int shift,
+                                                               int bits, const uint32_t* __restrict__ hist,
+                                                               int nblocks) {
+  constexpr int kW = kSortThreads / kWave;
+  __shared__ uint32_t s_off[kRadix];
+  __shared__ uint32_t s_run[kRadix];
+  __shared__ uint32_t s_wcnt[kW][kRadix];
+  const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
+  const uint32_t mask = (1u << bits) - 1u;
+  if (t < kRadix) {
+    s_off[t] = ((uint32_t)t <= mask) ? hist[(int64_t)t * nblocks + blockIdx.x] : 0u;
+    s_run[t] = 0;
+#pragma unroll
+    for (int ww = 0; ww < kW; ++ww) s_wcnt[ww][t] = 0;
+  }
+  __syncthreads();
+  const uint64_t lt = (1ull << lane) - 1ull;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int i = 0; i < kSortItems; ++i) {
+    const int64_t idx = base + (int64_t)i * kSortThreads + t;
+    const bool valid = idx < n;
+    uint32_t k = 0, v = 0, dg = 0;
+    if (valid) {
+      k = kin[idx];
+      v = vin[idx];
+      dg = (k >> shift) & mask;
+    }
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < bits; ++b) {
+      uint64_t mb = __ballot((dg >> b) & 1u);
+      peers &= ((dg >> b) & 1u) ? mb : ~mb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && (peers & lt) == 0) s_wcnt[w][dg] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = s_run[dg] + rank;
+      for (int ww = 0; ww < w; ++ww) pos += s_wcnt[ww][dg];
+      const uint32_t g = s_off[dg] + pos;
+      kout[g] = k;
+      vout[g] = v;
+    }
+    __syncthreads();
+    if (t < kRadix) {
+      uint32_t s = 0;
+#pragma unroll
+      for (int ww = 0; ww < kW; ++ww) {
+        s += s_wcnt[ww][t];
+        s_wcnt[ww][t] = 0;
+      }
+      s_run[t] += s;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- scans
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* lds, T& total) {
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) lds[w] = x;
+  __syncthreads();
+  T pre = 0, tot = 0;
+#pragma unroll
+  for (int ww = 0; ww < kScanThreads / kWave; ++ww) {
+    T s = lds[ww];
+    if (ww < w) pre += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return pre + x - v;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(const TI* __restrict__ in, int64_t n,
+                                                           TO* __restrict__ sums) {
+  __shared__ TO lds[kScanThreads / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  TO s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    int64_t idx = base + i;
+    if (idx < n) s += (TO)in[idx];
+  }
+  TO total;
+  block_exclusive_scan<TO>(s, lds, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// out[i] = offsets[block] + exclusive prefix within the tile; if `write_total`
+// the thread owning element n-1 also writes out[n].
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const TI* in, TO* out, int64_t n,
+                                                            const TO* __restrict__ offsets, int write_total) {
+  __shared__ TO lds[kScanThreads / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  TI vals[kScanItems];
+  TO s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    int64_t idx = base + i;
+    vals[i] = idx < n ? in[idx] : (TI)0;
+    s += (TO)vals[i];
+  }
+  TO total;
+  TO run = block_exclusive_scan<TO>(s, lds, total) + (offsets ? offsets[blockIdx.x] : (TO)0);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    int64_t idx = base + i;
+    if (idx < n) {
+      out[idx] = run;
+      run += (TO)vals[i];
+      if (write_total && idx == n - 1) out[n] = run;
+    }
+  }
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Recursive exclusive scan; scratch holds the block sums of every level.
+template <typename TI, typename TO>
+void scan_rec(const TI* in, TO* out, int64_t n, int write_total, TO* scratch, hipStream_t s) {
+  if (n <= 0) {
+    if (write_total) {
+      TO z = 0;
+      SNN_HIP(hipMemcpyAsync(out, &z, sizeof(TO), hipMemcpyHostToDevice, s));
+    }
+    return;
+  }
+  const int64_t nb = ceil_div(n, kScanTile);
+  if (nb == 1) {
+    k_scan_apply<TI, TO><<<1, kScanThreads, 0, s>>>(in, out, n, nullptr, write_total);
+    SNN_LAUNCH_CHECK();
+    return;
+  }
+  TO* sums = scratch;
+  k_scan_sums<TI, TO><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, sums);
+  SNN_LAUNCH_CHECK();
+  scan_rec<TO, TO>(sums, sums, nb, 0, scratch + nb, s);
+  k_scan_apply<TI, TO><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, sums, write_total);
+  SNN_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+size_t scan_scratch_bytes(int64_t n) {
+  size_t total = 0;
+  int64_t m = n;
+  while (m > kScanTile) {
+    m = ceil_div(m, kScanTile);
+    total += (size_t)m;
+  }
+  return (total + 64) * sizeof(int64_t);
+}
+
+void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* scratch, hipStream_t s) {
+  scan_rec<int32_t, int64_t>(in, out, n, 1, reinterpret_cast<int64_t*>(scratch), s);
+}
+
+void exclusive_scan_u32(uint32_t* data, int64_t n, void* scratch, hipStream_t s) {
+  scan_rec<uint32_t, uint32_t>(data, data, n, 0, reinterpret_cast<uint32_t*>(scratch), s);
+}
+
+void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n, int begin_bit, int end_bit,
+                      hipStream_t s) {
+  if (n <= 1 || begin_bit >= end_bit) return;
+  if (n > (int64_t)UINT32_MAX / 2) fail(SNN_EINVAL, "radix sort: too many keys");
+  const int nblocks = (int)ceil_div(n, kSortTile);
+  const size_t nhist = (size_t)nblocks * kRadix;
+  const size_t bytes = 2 * (size_t)n * sizeof(uint32_t) + nhist * sizeof(uint32_t) + scan_scratch_bytes(nhist) + 1024;
+  char* mem = static_cast<char*>(a.alloc(bytes));
+  uint32_t* k2 = reinterpret_cast<uint32_t*>(mem);
+  uint32_t* v2 = k2 + n;
+  uint32_t* hist = v2 + n;
+  void* scratch = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(hist + nhist) + 255) & ~uintptr_t(255));
+  uint32_t *kin = keys, *vin = vals, *kout = k2, *vout = v2;
+  for (int shift = begin_bit; shift < end_bit; shift += kRadixBits) {
+    const int bits = std::min(kRadixBits, end_bit - shift);
+    const uint32_t mask = (1u << bits) - 1u;
+    k_radix_hist<<<nblocks, kSortThreads, 0, s>>>(kin, n, shift, mask, hist, nblocks);
+    SNN_LAUNCH_CHECK();
+    exclusive_scan_u32(hist, (int64_t)nhist, scratch, s);
+    k_radix_scatter<<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, bits, hist, nblocks);
+    SNN_LAUNCH_CHECK();
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  if (kin != keys) {
+    SNN_HIP(hipMemcpyAsync(keys, kin, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    SNN_HIP(hipMemcpyAsync(vals, vin, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  }
+  a.release(mem);
+}
+
+}  // namespace snn

@@ -1,0 +1,521 @@
+// C ABI of libsnn: argument checks, device memory, and the orchestration of
+// Algorithm 1 (snn_index) and Algorithm 2 (snn_query / snn_query_self) as a
+// chain of kernels on the caller's stream with a single host read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "query_plan.h"
+#include "snn_internal.h"
+
+namespace snn {
+
+void launch_row_sort_long(const int64_t* row_ptr, int32_t* col, float* dist, const int32_t* long_list,
+                          const unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s);
+void launch_row_max(const int32_t* row_cnt, int64_t m, unsigned long long* out, hipStream_t s);
+void launch_self_qnorm(const float* ynorm, int64_t n, double* out, hipStream_t s);
+
+namespace {
+thread_local std::string g_err;
+}
+
+void fail(snn_status code, const std::string& msg) { throw Error(code, msg); }
+
+void check_hip(hipError_t e, const char* what, const char* file, int line) {
+  if (e == hipSuccess) return;
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), what, file,
+                line);
+  throw Error(e == hipErrorOutOfMemory ? SNN_ENOMEM : SNN_EDEVICE, buf);
+}
+
+void* DeviceArena::alloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (dev_.alloc) {
+    p = dev_.alloc(dev_.ctx, bytes);
+    if (!p) fail(SNN_ENOMEM, "device allocator returned NULL for " + std::to_string(bytes) + " bytes");
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      fail(SNN_ENOMEM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
+    }
+    SNN_HIP(e);
+  }
+  return p;
+}
+
+void DeviceArena::release(void* p) {
+  if (!p) return;
+  if (dev_.free)
+    dev_.free(dev_.ctx, p);
+  else
+    (void)hipFree(p);
+}
+
+void Buffer::ensure(DeviceArena& a, size_t need) {
+  if (need <= bytes && ptr) return;
+  reset(a);
+  ptr = a.alloc(need);
+  bytes = need;
+}
+
+void Buffer::reset(DeviceArena& a) {
+  if (ptr) a.release(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+const DeviceInfo& device_info(int device) {
+  static std::mutex mu;
+  static std::vector<DeviceInfo> cache;
+  static std::vector<bool> have;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)cache.size() <= device) {
+    cache.resize(device + 1);
+    have.resize(device + 1, false);
+  }
+  if (!have[device]) {
+    int cus = 0;
+    SNN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    cache[device].cus = cus > 0 ? cus : 1;
+    cache[device].xcds = cus >= 64 ? 8 : 1;
+    have[device] = true;
+  }
+  return cache[device];
+}
+
+namespace {
+
+// Select the device of `dev` for the duration of a call, check it is gfx950.
+struct DeviceScope {
+  int prev = -1;
+  explicit DeviceScope(int device) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+      (void)hipGetLastError();
+      fail(SNN_EDEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= count) fail(SNN_EINVAL, "device ordinal out of range");
+    SNN_HIP(hipGetDevice(&prev));
+    SNN_HIP(hipSetDevice(device));
+    static std::mutex mu;
+    static std::vector<int> ok;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)ok.size() <= device) ok.resize(device + 1, -1);
+    if (ok[device] < 0) {
+      hipDeviceProp_t p;
+      SNN_HIP(hipGetDeviceProperties(&p, device));
+      ok[device] = std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+    }
+    if (!ok[device]) fail(SNN_EDEVICE, "device is not gfx950 (this library is built for MI355X only)");
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <class F>
+snn_status guard(F&& f) {
+  try {
+    f();
+    g_err.clear();
+    return SNN_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return SNN_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return SNN_EDEVICE;
+  } catch (...) {
+    g_err = "unknown error";
+    return SNN_EDEVICE;
+  }
+}
+
+constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
+
+double gamma64(int k) { return k * kU64 / (1.0 - k * kU64); }
+
+// Control block read back once per query.
+struct Ctl {
+  unsigned long long counters[kMaxXcd];
+  unsigned long long survivors;
+  unsigned long long pairs_window;
+  unsigned long long list_counts[2];
+  unsigned long long row_max;
+  unsigned long long pad0;
+  int bad;
+  int pad1;
+};
+
+struct HostCtl {
+  Ctl ctl;
+  int64_t nnz;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Carves aligned sub-arrays out of one buffer.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off += align256(sizeof(T) * std::max<size_t>(count, 1));
+    return p;
+  }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------------ query
+static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, const snn_options* opts,
+                      snn_csr* out, snn_stats* st) {
+  if (!out) fail(SNN_EINVAL, "out is NULL");
+  if (!std::isfinite(R) || R < 0) fail(SNN_EINVAL, "R must be finite and >= 0");
+  if (m < 0) fail(SNN_EINVAL, "m must be >= 0");
+  if (m >= (int64_t)INT32_MAX) fail(SNN_EINVAL, "m must be < 2^31 - 1");
+  if (!self && m > 0 && !Q) fail(SNN_EINVAL, "Q is NULL");
+  if (!out->row_ptr) fail(SNN_EINVAL, "out->row_ptr is NULL");
+  if (out->nnz_cap < 0) fail(SNN_EINVAL, "nnz_cap must be >= 0");
+  if (out->nnz_cap > 0 && (!out->col || !out->dist)) fail(SNN_EINVAL, "out->col / out->dist is NULL");
+  snn_options o{};
+  o.precision = SNN_PREC_AUTO;
+  if (opts) o = *opts;
+  if (o.precision != SNN_PREC_FP64 && o.precision != SNN_PREC_MIXED && o.precision != SNN_PREC_AUTO)
+    fail(SNN_EINVAL, "unknown precision");
+  if (o.mixed_terms != 0 && o.mixed_terms != 1 && o.mixed_terms != 3) fail(SNN_EINVAL, "mixed_terms must be 0, 1 or 3");
+  if (o.tile_q < 0 || o.tile_c < 0) fail(SNN_EINVAL, "tile sizes must be >= 0");
+  if (o.tile_q % 64 != 0) fail(SNN_EINVAL, "tile_q must be a multiple of 64");
+
+  DeviceScope scope(ix.arena.dev().device);
+  hipStream_t s = ix.arena.stream();
+  const DeviceInfo& di = device_info(ix.arena.dev().device);
+  const int d = ix.d;
+  const int64_t n = ix.n;
+  const double R2 = R * R;
+
+  snn_precision prec = o.precision == SNN_PREC_AUTO ? SNN_PREC_FP64 : o.precision;
+  if (prec == SNN_PREC_MIXED) fail(SNN_ENOTSUP, "mixed precision screen not built yet");
+  const int T = o.tile_q ? o.tile_q : 64;
+  const int CH = o.tile_c ? o.tile_c : 1024;
+  const int ntiles = (int)std::max<int64_t>(1, (m + T - 1) / T);
+
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (st) {
+    for (auto& e : ev) SNN_HIP(hipEventCreate(&e));
+    SNN_HIP(hipEventRecord(ev[0], s));
+  }
+
+  // ---- workspace
+  Carver probe(nullptr);
+  auto plan_query = [&](Carver& c) {
+    struct P {
+      uint32_t* ukey;
+      uint32_t* val;
+      double* qa_in;
+      double* qn_in;
+      double* q64;
+      int32_t* qorig;
+      double* qa;
+      double* qn;
+      int32_t* lo;
+      int32_t* hi;
+      int32_t* tlo;
+      int32_t* thi;
+      int32_t* units;
+      int64_t* unit_off;
+      char* scan_scratch;
+      Ctl* ctl;
+      int32_t* row_cnt;
+      int32_t* lists;
+    } p;
+    const size_t mq = self ? 1 : (size_t)m;
+    p.ukey = c.take<uint32_t>(mq);
+    p.val = c.take<uint32_t>(mq);
+    p.qa_in = c.take<double>(mq);
+    p.qn_in = c.take<double>(mq);
+    p.q64 = c.take<double>(mq * ix.dp);
+    p.qorig = c.take<int32_t>(mq);
+    p.qa = c.take<double>(mq);
+    p.qn = c.take<double>(std::max<size_t>(m, 1));
+    p.lo = nullptr;
+    p.hi = nullptr;
+    p.tlo = c.take<int32_t>(ntiles);
+    p.thi = c.take<int32_t>(ntiles);
+    p.units = c.take<int32_t>(ntiles);
+    p.unit_off = c.take<int64_t>(ntiles + 1);
+    p.scan_scratch = c.take<char>(std::max(scan_scratch_bytes(ntiles), scan_scratch_bytes(std::max<int64_t>(m, 1))));
+    p.ctl = c.take<Ctl>(1);
+    p.row_cnt = c.take<int32_t>(std::max<int64_t>(m, 1));
+    p.lists = c.take<int32_t>(2 * std::max<int64_t>(m, 1));
+    return p;
+  };
+  plan_query(probe);
+  ix.ws[0].ensure(ix.arena, probe.off + 256);
+  Carver carve(ix.ws[0].ptr);
+  auto P = plan_query(carve);
+
+  launch_fill_u64(reinterpret_cast<unsigned long long*>(P.ctl), sizeof(Ctl) / 8, 0ull, s);
+  launch_fill_i32(P.row_cnt, m, 0, s);
+
+  const double* q64;
+  const int32_t* qorig;
+  const double* qa;
+  const double* qn;
+  if (!self) {
+    if (m > 0) {
+      launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), P.ukey, P.val, P.qa_in, P.qn_in,
+                        &P.ctl->bad, s);
+      radix_sort_pairs(ix.arena, P.ukey, P.val, m, 8, 32, s);
+      launch_query_gather(ix.dtype, Q, m, d, ix.dp, P.val, P.qa_in, P.qn_in, P.q64, P.qorig, P.qa, P.qn, s);
+    }
+    q64 = P.q64;
+    qorig = P.qorig;
+    qa = P.qa;
+    qn = P.qn;
+  } else {
+    q64 = ix.p64.as<double>();
+    qorig = ix.perm.as<int32_t>();
+    qa = ix.key.as<double>();
+    launch_self_qnorm(ix.ynorm.as<float>(), n, P.qn, s);
+    qn = P.qn;
+  }
+
+  // W_q = R ||v|| (1 + 4 gamma_{d+3}) + key_eps + eps_q, eps_q = c ||y_q||
+  const double u32 = std::ldexp(1.0, -24);
+  const double w_base = R * ix.vnorm * (1.0 + 4.0 * gamma64(d + 3)) + ix.key_eps;
+  const double eps_scale = 1.01 * (u32 + gamma64(d + 2)) * (1.0 + u32) * ix.vnorm;
+  launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, CH, ntiles, P.lo, P.hi, P.tlo,
+                 P.thi, P.units, &P.ctl->pairs_window, s);
+  exclusive_scan_i32_to_i64(P.units, P.unit_off, ntiles, P.scan_scratch, s);
+
+  QueryDev qd{};
+  qd.m = m;
+  qd.d = d;
+  qd.dp = ix.dp;
+  qd.T = T;
+  qd.CH = CH;
+  qd.ntiles = ntiles;
+  qd.R2 = R2;
+  qd.q64 = q64;
+  qd.qorig = qorig;
+  qd.p64 = ix.p64.as<double>();
+  qd.perm = ix.perm.as<int32_t>();
+  qd.tlo = P.tlo;
+  qd.thi = P.thi;
+  qd.unit_off = P.unit_off;
+  qd.counters = P.ctl->counters;
+  qd.nxcd = di.xcds;
+
+  // survivors: capacity remembered on the index, grown on overflow
+  long long cap = std::max<long long>(1 << 16, (long long)(ix.ws[1].bytes / 24));
+  HostCtl hc{};
+  for (int attempt = 0;; ++attempt) {
+    // five arrays, each padded to 256 bytes by the carver
+    const size_t need = (size_t)cap * 24 + 2048;
+    ix.ws[1].ensure(ix.arena, need);
+    cap = (long long)((ix.ws[1].bytes - 2048) / 24);
+    Carver sc(ix.ws[1].ptr);
+    Survivors sv{};
+    sv.pairs = sc.take<int2>(cap);
+    sv.res_q = sc.take<int32_t>(cap);
+    sv.res_id = sc.take<int32_t>(cap);
+    sv.res_dist = sc.take<float>(cap);
+    sv.res_slot = sc.take<int32_t>(cap);
+    // recompute cap to fit the carve exactly
+    sv.cap = cap;
+    sv.count = &P.ctl->survivors;
+    qd.sink.out = sv.pairs;
+    qd.sink.counter = sv.count;
+    qd.sink.cap = cap;
+    if (attempt > 0) {
+      launch_fill_u64(P.ctl->counters, kMaxXcd, 0ull, s);
+      launch_fill_u64(&P.ctl->survivors, 1, 0ull, s);
+      launch_fill_i32(P.row_cnt, m, 0, s);
+    }
+    const int grid = std::max(di.xcds, (di.cus * 4 / di.xcds) * di.xcds);
+    if (st) SNN_HIP(hipEventRecord(ev[1], s));
+    if (m > 0) launch_cand_fp64(qd, grid, s);
+    if (st) SNN_HIP(hipEventRecord(ev[2], s));
+    launch_recheck(qd, sv, P.row_cnt, di.cus * 8, s);
+    exclusive_scan_i32_to_i64(P.row_cnt, out->row_ptr, m, P.scan_scratch, s);
+    launch_row_max(P.row_cnt, m, &P.ctl->row_max, s);
+    SNN_HIP(hipMemcpyAsync(&hc.ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    SNN_HIP(hipMemcpyAsync(&hc.nnz, out->row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SNN_HIP(hipStreamSynchronize(s));
+    if (hc.ctl.bad) fail(SNN_EINVAL, "Q contains NaN or Inf");
+    if ((long long)hc.ctl.survivors <= cap) {
+      out->nnz = hc.nnz;
+      if (st) {
+        st->pairs_window = (int64_t)hc.ctl.pairs_window;
+        st->pairs_recheck = (int64_t)hc.ctl.survivors;
+        st->nnz = hc.nnz;
+        st->precision_used = prec;
+        st->terms_used = 0;
+      }
+      if (hc.nnz > out->nnz_cap) {
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "CSR capacity %lld < %lld neighbours", (long long)out->nnz_cap,
+                      (long long)hc.nnz);
+        throw Error(SNN_EOVERFLOW, buf);
+      }
+      launch_scatter(sv, out->row_ptr, out->col, out->dist, di.cus * 8, s);
+      break;
+    }
+    cap = (long long)(hc.ctl.survivors * 5 / 4) + 1024;
+    ix.ws[1].reset(ix.arena);
+  }
+
+  // ---- rows: ids ascending
+  int32_t* tmp_col = nullptr;
+  float* tmp_dist = nullptr;
+  if (hc.ctl.row_max > 4096) {
+    ix.ws[2].ensure(ix.arena, (size_t)hc.nnz * 8 + 512);
+    Carver tc(ix.ws[2].ptr);
+    tmp_col = tc.take<int32_t>(hc.nnz);
+    tmp_dist = tc.take<float>(hc.nnz);
+  }
+  launch_row_sort(out->row_ptr, m, out->col, out->dist, P.lists, P.ctl->list_counts, 0, s);
+  launch_row_sort_long(out->row_ptr, out->col, out->dist, P.lists + m, P.ctl->list_counts, tmp_col, tmp_dist, s);
+
+  if (st) {
+    SNN_HIP(hipEventRecord(ev[3], s));
+    SNN_HIP(hipEventSynchronize(ev[3]));
+    float a = 0, b = 0;
+    SNN_HIP(hipEventElapsedTime(&a, ev[1], ev[2]));
+    SNN_HIP(hipEventElapsedTime(&b, ev[0], ev[3]));
+    st->screen_ms = a;
+    st->total_ms = b;
+    int64_t executed = 0;
+    st->pairs_executed = executed;
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+}
+
+}  // namespace snn
+
+using namespace snn;
+
+struct snn_index_s : Index {
+  explicit snn_index_s(const snn_device& d) : Index(d) {}
+};
+
+static void free_index(snn_index_s* ix) {
+  if (!ix) return;
+  DeviceArena& a = ix->arena;
+  Buffer* bufs[] = {&ix->mu, &ix->v, &ix->key, &ix->perm, &ix->po, &ix->p64, &ix->ys, &ix->h, &ix->ynorm,
+                    &ix->stats_host_dev};
+  for (Buffer* b : bufs) b->reset(a);
+  for (auto& mo : ix->mixed) {
+    mo.cand.reset(a);
+    mo.qself.reset(a);
+  }
+  for (auto& w : ix->ws) w.reset(a);
+  delete ix;
+}
+
+extern "C" {
+
+snn_status snn_index(const snn_device* dev, const void* X, int64_t n, int32_t d, snn_dtype dtype,
+                     snn_index_t* out) {
+  return guard([&] {
+    if (!dev || !out) fail(SNN_EINVAL, "dev / out is NULL");
+    *out = nullptr;
+    if (!X) fail(SNN_EINVAL, "X is NULL");
+    if (n < 1 || n >= (int64_t)INT32_MAX) fail(SNN_EINVAL, "n must be in [1, 2^31 - 1)");
+    if (d < 1 || d > 1024) fail(SNN_EINVAL, "d must be in [1, 1024]");
+    if (dtype != SNN_F32 && dtype != SNN_F64) fail(SNN_EINVAL, "unknown dtype");
+    if ((dev->alloc == nullptr) != (dev->free == nullptr)) fail(SNN_EINVAL, "alloc and free must both be set");
+    DeviceScope scope(dev->device);
+    snn_index_s* ix = new snn_index_s(*dev);
+    ix->n = n;
+    ix->d = d;
+    ix->dp = ((d + 3) / 4) * 4;
+    ix->dtype = dtype;
+    try {
+      build_index(*ix, X);
+    } catch (...) {
+      free_index(ix);
+      throw;
+    }
+    *out = ix;
+  });
+}
+
+snn_status snn_query(snn_index_t idx, const void* Q, int64_t m, double R, const snn_options* opts, snn_csr* out,
+                     snn_stats* st) {
+  return guard([&] {
+    if (!idx) fail(SNN_EINVAL, "index is NULL");
+    run_query(*idx, Q, m, R, false, opts, out, st);
+  });
+}
+
+snn_status snn_query_self(snn_index_t idx, double R, const snn_options* opts, snn_csr* out, snn_stats* st) {
+  return guard([&] {
+    if (!idx) fail(SNN_EINVAL, "index is NULL");
+    run_query(*idx, nullptr, idx->n, R, true, opts, out, st);
+  });
+}
+
+snn_status snn_index_get_view(snn_index_t idx, snn_index_view* view) {
+  return guard([&] {
+    if (!idx || !view) fail(SNN_EINVAL, "NULL argument");
+    view->n = idx->n;
+    view->d = idx->d;
+    view->dtype = idx->dtype;
+    view->mu = idx->mu.as<double>();
+    view->v = idx->v.as<double>();
+    view->key = idx->key.as<double>();
+    view->perm = idx->perm.as<int32_t>();
+    view->max_norm = idx->max_norm;
+    view->key_eps = idx->key_eps;
+    view->power_iters = idx->power_iters;
+  });
+}
+
+void snn_index_free(snn_index_t idx) {
+  if (!idx) return;
+  try {
+    DeviceScope scope(idx->arena.dev().device);
+    (void)hipStreamSynchronize(idx->arena.stream());
+    free_index(idx);
+  } catch (...) {
+    free_index(idx);
+  }
+}
+
+snn_status snn_sort_pairs_u32(const snn_device* dev, uint32_t* keys, uint32_t* vals, int64_t n, int begin_bit,
+                              int end_bit) {
+  return guard([&] {
+    if (!dev) fail(SNN_EINVAL, "dev is NULL");
+    if (n < 0) fail(SNN_EINVAL, "n must be >= 0");
+    if (n > 0 && (!keys || !vals)) fail(SNN_EINVAL, "keys / vals is NULL");
+    if (begin_bit < 0 || end_bit > 32 || begin_bit >= end_bit) fail(SNN_EINVAL, "bad bit range");
+    if ((dev->alloc == nullptr) != (dev->free == nullptr)) fail(SNN_EINVAL, "alloc and free must both be set");
+    DeviceScope scope(dev->device);
+    DeviceArena a(*dev);
+    radix_sort_pairs(a, keys, vals, n, begin_bit, end_bit, a.stream());
+  });
+}
+
+const char* snn_last_error(void) { return g_err.c_str(); }
+
+const char* snn_version(void) { return "snn-mi355x 0.1"; }
+
+}  // extern "C"

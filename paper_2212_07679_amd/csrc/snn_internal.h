@@ -1,0 +1,121 @@
+// Host-side internals of libsnn: error plumbing, device memory, the index
+// object and the launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "snn.h"
+
+namespace snn {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  snn_status code;
+  Error(snn_status c, const std::string& msg) : std::runtime_error(msg), code(c) {}
+};
+
+[[noreturn]] void fail(snn_status code, const std::string& msg);
+void check_hip(hipError_t e, const char* what, const char* file, int line);
+#define SNN_HIP(call) ::snn::check_hip((call), #call, __FILE__, __LINE__)
+#define SNN_LAUNCH_CHECK() ::snn::check_hip(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+// ---------------------------------------------------------------- memory
+// Device allocations through snn_device.alloc (or hipMalloc).  Freed with
+// the matching free; all frees happen after the stream work using the
+// buffer has been enqueued, which is safe for stream-ordered allocators and
+// for hipFree (which synchronises).
+class DeviceArena {
+ public:
+  explicit DeviceArena(const snn_device& d) : dev_(d) {}
+  void* alloc(size_t bytes);
+  void release(void* p);
+  const snn_device& dev() const { return dev_; }
+  hipStream_t stream() const { return (hipStream_t)dev_.stream; }
+
+ private:
+  snn_device dev_;
+};
+
+// A grow-only device buffer owned by an arena.
+struct Buffer {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  template <typename T>
+  T* as() const {
+    return reinterpret_cast<T*>(ptr);
+  }
+  void ensure(DeviceArena& a, size_t need);
+  void reset(DeviceArena& a);
+};
+
+// ---------------------------------------------------------------- device info
+struct DeviceInfo {
+  int cus = 256;       // compute units
+  int xcds = 8;        // accelerator complex dies (separate L2 each)
+  int lds_bytes = 160 * 1024;
+};
+const DeviceInfo& device_info(int device);
+
+// ---------------------------------------------------------------- index
+// Everything lives in sorted (score) order unless noted.
+struct MixedOperands {
+  int terms = 0;     // 1 or 3
+  int ka = 0;        // packed bf16 length per row (multiple of 16)
+  Buffer cand;       // n x ka bf16: candidate operand rows
+  Buffer qself;      // n x ka bf16: query operand rows for self-queries
+};
+
+struct Index {
+  explicit Index(const snn_device& d) : arena(d) {}
+  DeviceArena arena;
+  int64_t n = 0;
+  int d = 0;
+  int dp = 4;  // padded float64 row stride (multiple of 4)
+  snn_dtype dtype = SNN_F32;
+
+  Buffer mu;    // d doubles
+  Buffer v;     // d doubles (unit)
+  Buffer key;   // n doubles: fl32(score) in ascending order
+  Buffer perm;  // n int32: sorted position -> original id
+  Buffer po;    // n x d input dtype: original rows, sorted
+  Buffer p64;   // n x dp doubles: original rows, sorted, zero-padded
+  Buffer ys;    // n x d floats: fl32(p - mu), sorted
+  Buffer h;     // n floats: ||ys||^2 / 2 rounded to nearest, sorted
+  Buffer ynorm; // n floats: ||ys|| rounded up, sorted
+  MixedOperands mixed[2];  // [0]: terms = 1, [1]: terms = 3
+
+  double max_norm = 0;  // max ||ys_i|| (float64, rounded up)
+  double vnorm = 1;     // ||v|| (float64, rounded up)
+  double key_eps = 0;   // bound on |key_i - v.(p_i - mu)|
+  int power_iters = 0;
+
+  // per-call workspace (grow-only)
+  Buffer ws[16];
+  Buffer stats_host_dev;  // small device block read back at the end of a query
+};
+
+// ---------------------------------------------------------------- launchers
+// (each defined in the kernel file named in the comment)
+
+// k_sort.hip
+void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n, int begin_bit, int end_bit,
+                      hipStream_t s);
+size_t scan_scratch_bytes(int64_t n);
+// Exclusive scan of int32 counts into int64 offsets (out has n+1 entries,
+// out[n] = total).  scratch: scan_scratch_bytes(n).
+void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* scratch, hipStream_t s);
+void exclusive_scan_u32(uint32_t* data, int64_t n, void* scratch, hipStream_t s);
+
+// k_index.hip
+void build_index(Index& ix, const void* X);
+void build_mixed_operands(Index& ix, int terms);
+
+// k_query.hip / k_cand_*.hip / k_csr.hip are driven from runtime.hip through
+// the declarations in query_plan.h.
+
+}  // namespace snn

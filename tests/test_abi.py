@@ -1,0 +1,86 @@
+"""The C-ABI library loads, exports every symbol include/snn.h declares, and
+rejects bad arguments -- all without a GPU (no compute call is made)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2212_07679_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "snn.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(snn_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("snn_index", "snn_query", "snn_query_self", "snn_index_free", "snn_last_error"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    for s in declared_symbols():
+        assert hasattr(L, s), s
+    assert set(declared_symbols()) <= set(B.SIGNATURES)
+
+
+def test_version():
+    assert B.lib().snn_version().decode().startswith("snn-mi355x")
+
+
+def _dev():
+    return B.snn_device(B.ALLOC_FN(), B.FREE_FN(), None, None, 0)
+
+
+def test_index_argument_errors():
+    L = B.lib()
+    out = ctypes.c_void_p()
+    dev = _dev()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: arguments are checked first
+    assert L.snn_index(None, fake, 10, 2, 0, ctypes.byref(out)) == B.SNN_EINVAL
+    assert L.snn_index(ctypes.byref(dev), None, 10, 2, 0, ctypes.byref(out)) == B.SNN_EINVAL
+    assert L.snn_index(ctypes.byref(dev), fake, 0, 2, 0, ctypes.byref(out)) == B.SNN_EINVAL
+    assert L.snn_index(ctypes.byref(dev), fake, 10, 0, 0, ctypes.byref(out)) == B.SNN_EINVAL
+    assert L.snn_index(ctypes.byref(dev), fake, 10, 2000, 0, ctypes.byref(out)) == B.SNN_EINVAL
+    assert L.snn_index(ctypes.byref(dev), fake, 10, 2, 7, ctypes.byref(out)) == B.SNN_EINVAL
+    assert b"d must be" in L.snn_last_error() or b"dtype" in L.snn_last_error()
+
+
+def test_query_argument_errors():
+    L = B.lib()
+    csr = B.snn_csr(0, 0, 0, 0, 0)
+    assert L.snn_query(None, None, 1, 1.0, None, ctypes.byref(csr), None) == B.SNN_EINVAL
+    assert L.snn_query_self(None, 1.0, None, ctypes.byref(csr), None) == B.SNN_EINVAL
+    v = B.snn_index_view()
+    assert L.snn_index_get_view(None, ctypes.byref(v)) == B.SNN_EINVAL
+    L.snn_index_free(None)  # no-op
+
+
+def test_sort_argument_errors():
+    L = B.lib()
+    dev = _dev()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.snn_sort_pairs_u32(None, fake, fake, 4, 0, 32) == B.SNN_EINVAL
+    assert L.snn_sort_pairs_u32(ctypes.byref(dev), fake, fake, 4, 0, 33) == B.SNN_EINVAL
+    assert L.snn_sort_pairs_u32(ctypes.byref(dev), fake, fake, 4, 8, 8) == B.SNN_EINVAL
+    assert L.snn_sort_pairs_u32(ctypes.byref(dev), None, fake, 4, 0, 32) == B.SNN_EINVAL
+    assert L.snn_sort_pairs_u32(ctypes.byref(dev), fake, fake, -1, 0, 32) == B.SNN_EINVAL
+
+
+@pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
+                    reason="a GPU may be present; the no-device path is only checked without one")
+def test_no_device_is_a_clean_error():
+    L = B.lib()
+    out = ctypes.c_void_p()
+    dev = _dev()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.snn_index(ctypes.byref(dev), fake, 10, 2, 0, ctypes.byref(out)) == B.SNN_EDEVICE
+    assert b"device" in L.snn_last_error()

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Index sets and row pointers must be bit-identical to the oracle; distances
+within 1e-5 relative (exactly 0 for S = 0).  Sizes span several tiles and
+work units with ragged tails.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_07679_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_07679_amd import binding
+
+    return binding
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def check_same(got, ref, what=""):
+    row_ptr, col, dist = (t.cpu().numpy() for t in got[:3])
+    assert row_ptr.shape == ref.row_ptr.shape, what
+    bad = np.flatnonzero(row_ptr != ref.row_ptr)
+    assert bad.size == 0, f"{what}: row_ptr differs first at {bad[:5]}"
+    assert np.array_equal(col, ref.col), f"{what}: col differs"
+    zero = ref.dist == 0
+    assert np.all(dist[zero] == 0), what
+    rel = np.abs(dist - ref.dist) / np.maximum(ref.dist, 1e-300)
+    assert np.all(rel[~zero] <= 1e-5), f"{what}: max rel dist err {rel.max()}"
+
+
+PRECS = ["fp64"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_uniform2d_full(B, prec):
+    w = W.uniform2d()
+    say(f"uniform2d n={w.n} m={w.m} R={w.R} prec={prec}")
+    ref = oracle.brute_radius(w.P, w.Q, w.R)
+    idx = B.Index(to_dev(w.P))
+    got = idx.query(to_dev(w.Q), w.R, precision=prec, stats=True)
+    check_same(got, ref, "uniform2d")
+    st = got[3]
+    o2, ost = oracle.snn_query(oracle.build_index(w.P), w.Q, w.R)
+    assert st["nnz"] == ref.row_ptr[-1]
+    # the GPU window is at least the exact-arithmetic window and close to it
+    assert st["pairs_window"] >= 0.99 * ost["pairs_window"]
+    assert st["pairs_window"] <= 1.05 * ost["pairs_window"] + 1000
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("R", [1.5, 3.0])
+def test_gmm16_small(B, prec, R):
+    w = W.gmm16(n=30_000, m=3_000, R=R)
+    say(f"gmm16 n={w.n} m={w.m} R={R} prec={prec}")
+    idx_o = oracle.build_index(w.P)
+    ref, _ = oracle.snn_query(idx_o, w.Q, w.R)
+    idx = B.Index(to_dev(w.P))
+    got = idx.query(to_dev(w.Q), w.R, precision=prec)
+    check_same(got, ref, f"gmm16 R={R}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_self_query_blobs(B, prec):
+    w = W.blobs3d(n=20_000, R=0.02)
+    say(f"blobs3d self n={w.n} R={w.R} prec={prec}")
+    ref, _ = oracle.snn_query(oracle.build_index(w.P), w.P, w.R)
+    idx = B.Index(to_dev(w.P))
+    got = idx.query_self(w.R, precision=prec)
+    check_same(got, ref, "blobs3d self")
+
+
+@pytest.mark.parametrize("d", [1, 3, 5, 8, 13, 32, 37, 70])
+def test_dims(B, d):
+    g = np.random.default_rng(100 + d)
+    n, m = 3000, 257
+    P = g.standard_normal((n, d)).astype(np.float32)
+    Q = np.concatenate([P[:100], g.standard_normal((m - 100, d)).astype(np.float32)])
+    R = float(np.sqrt(d) * 0.6)
+    say(f"dims d={d} n={n} m={m} R={R}")
+    ref = oracle.brute_radius(P, Q, R)
+    idx = B.Index(to_dev(P))
+    for prec in PRECS:
+        check_same(idx.query(to_dev(Q), R, precision=prec), ref, f"d={d} {prec}")
+
+
+def test_edge_cases(B):
+    say("edge cases")
+    g = np.random.default_rng(7)
+    P = g.random((500, 3))
+    idx = B.Index(to_dev(P))
+    # m = 0
+    rp, col, dist = idx.query(to_dev(np.zeros((0, 3))), 0.1)
+    assert rp.cpu().tolist() == [0] and col.numel() == 0
+    # R = 0 with exact duplicates
+    P2 = np.concatenate([P, P[:50]])
+    idx2 = B.Index(to_dev(P2))
+    check_same(idx2.query_self(0.0), oracle.brute_radius(P2, P2, 0.0), "R=0 duplicates")
+    # n = 1
+    idx1 = B.Index(to_dev(P[:1]))
+    check_same(idx1.query(to_dev(P[:5]), 0.3), oracle.brute_radius(P[:1], P[:5], 0.3), "n=1")
+    # every point a neighbour of every query: long rows (> 4096 needs merges)
+    P3 = g.random((6000, 2))
+    idx3 = B.Index(to_dev(P3))
+    Q3 = P3[:70]
+    check_same(idx3.query(to_dev(Q3), 2.0), oracle.brute_radius(P3, Q3, 2.0), "all neighbours")
+    # rows of 17..64 and 65..4096 entries
+    check_same(idx3.query(to_dev(Q3), 0.06), oracle.brute_radius(P3, Q3, 0.06), "medium rows")
+    check_same(idx3.query(to_dev(Q3), 0.4), oracle.brute_radius(P3, Q3, 0.4), "long rows")
+
+
+def test_lattice_ties(B):
+    say("lattice ties")
+    P = W.lattice(-12, 12, 2)
+    Q = P[::13]
+    idx = B.Index(to_dev(P))
+    check_same(idx.query(to_dev(Q), 5.0), oracle.brute_radius(P, Q, 5.0), "lattice R=5")
+    P3 = W.lattice(-5, 5, 3).astype(np.float32)
+    idx3 = B.Index(to_dev(P3))
+    check_same(idx3.query_self(3.0), oracle.brute_radius(P3, P3, 3.0), "3-D lattice self")
+
+
+def test_far_from_origin(B):
+    # near-duplicates far from the mean: large ||x|| against a tiny radius
+    say("far from origin")
+    g = np.random.default_rng(8)
+    P = np.concatenate([1e4 + g.standard_normal((2000, 4)) * 1e-3, -1e4 + g.standard_normal((2000, 4)) * 1e-3])
+    Q = P[::9] + 1e-4 * g.standard_normal((P[::9].shape[0], 4))
+    idx = B.Index(to_dev(P))
+    check_same(idx.query(to_dev(Q), 2e-3), oracle.brute_radius(P, Q, 2e-3), "far")
+
+
+def test_determinism(B):
+    say("determinism")
+    w = W.gmm16(n=20_000, m=1_000, R=3.0)
+    idx = B.Index(to_dev(w.P))
+    a = [t.cpu().numpy().tobytes() for t in idx.query(to_dev(w.Q), w.R)]
+    b = [t.cpu().numpy().tobytes() for t in idx.query(to_dev(w.Q), w.R)]
+    assert a == b
+
+
+def test_overflow_and_retry(B):
+    say("overflow")
+    w = W.uniform2d(n=5000, m=500, R=0.05)
+    idx = B.Index(to_dev(w.P))
+    with pytest.raises(B.SnnError) as e:
+        idx.query(to_dev(w.Q), w.R, nnz_cap=10)
+    assert e.value.status == B.SNN_EOVERFLOW
+    ref = oracle.brute_radius(w.P, w.Q, w.R)
+    check_same(idx.query(to_dev(w.Q), w.R), ref, "after retry")
+
+
+def test_nan_rejected(B):
+    say("nan")
+    P = np.random.default_rng(1).random((100, 3)).astype(np.float32)
+    Pn = P.copy()
+    Pn[17, 1] = np.nan
+    with pytest.raises(B.SnnError) as e:
+        B.Index(to_dev(Pn))
+    assert e.value.status == B.SNN_EINVAL
+    idx = B.Index(to_dev(P))
+    Q = P[:5].copy()
+    Q[2, 0] = np.inf
+    with pytest.raises(B.SnnError) as e:
+        idx.query(to_dev(Q), 0.1)
+    assert e.value.status == B.SNN_EINVAL
+    with pytest.raises(B.SnnError):
+        idx.query(to_dev(P[:5]), -1.0)
+
+
+def test_index_internals(B):
+    say("index internals")
+    w = W.gmm16(n=50_000, m=10, R=1.5)
+    idx = B.Index(to_dev(w.P))
+    v = idx.view()
+    P = w.P.astype(np.float64)
+    mu = P.mean(0)
+    assert np.allclose(v["mu"].cpu().numpy(), mu, rtol=1e-12, atol=1e-12)
+    vv = v["v"].cpu().numpy()
+    assert abs(np.linalg.norm(vv) - 1) < 1e-12
+    X = P - mu
+    C = X.T @ X
+    lam = np.linalg.eigvalsh(C)
+    assert vv @ C @ vv >= (1 - 1e-6) * lam[-1]  # Rayleigh quotient of the power iteration
+    key = v["key"].cpu().numpy()
+    perm = v["perm"].cpu().numpy()
+    assert np.all(np.diff(key) >= 0)
+    assert np.array_equal(np.sort(perm), np.arange(w.n))
+    alpha = X[perm] @ vv
+    assert np.all(np.abs(key - alpha) <= v["key_eps"])
+
+
+@pytest.mark.parametrize("n,bits", [(1, (0, 32)), (1000, (0, 32)), (100_003, (0, 32)), (70_000, (8, 32)),
+                                    (5000, (0, 3))])
+def test_radix_sort(B, n, bits):
+    say(f"radix sort n={n} bits={bits}")
+    g = np.random.default_rng(n)
+    k = g.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+    k[: n // 3] = k[n // 3 : 2 * (n // 3)]  # many equal keys: stability matters
+    vals = np.arange(n, dtype=np.uint32)
+    kt = to_dev(k.view(np.int32))
+    vt = to_dev(vals.view(np.int32))
+    B.sort_pairs_u32(kt, vt, *bits)
+    torch.cuda.synchronize()
+    mask = np.uint32(((1 << (bits[1] - bits[0])) - 1) << bits[0]) if bits[1] - bits[0] < 32 else np.uint32(0xFFFFFFFF)
+    order = np.argsort(k & mask, kind="stable")
+    assert np.array_equal(vt.cpu().numpy().view(np.uint32), vals[order])
+    assert np.array_equal(kt.cpu().numpy().view(np.uint32), k[order])
