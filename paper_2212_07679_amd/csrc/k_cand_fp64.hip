@@ -131,6 +131,27 @@ __global__ __launch_bounds__(kThreads) void k_cand_fp64_big(QueryDev q, int dp) 
 
 }  // namespace
 
+int fp64_blocks_per_cu(int dp) {
+  int nb = 0;
+  hipError_t e;
+  switch (dp) {
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_fp64_reg<4>, kThreads, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_fp64_reg<8>, kThreads, 0); break;
+    case 12: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_fp64_reg<12>, kThreads, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_fp64_reg<16>, kThreads, 0); break;
+    case 20: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_fp64_reg<20>, kThreads, 0); break;
+    case 24: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_fp64_reg<24>, kThreads, 0); break;
+    case 28: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_fp64_reg<28>, kThreads, 0); break;
+    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_fp64_reg<32>, kThreads, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_fp64_big, kThreads, 0); break;
+  }
+  if (e != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  return nb;
+}
+
 void launch_cand_fp64(const QueryDev& q, int grid, hipStream_t s) {
   switch (q.dp) {
     case 4: k_cand_fp64_reg<4><<<grid, kThreads, 0, s>>>(q); break;

@@ -1,0 +1,285 @@
+// Mixed-precision candidate screen on the gfx950 matrix cores (the
+// "precision form").
+//
+// Section 4 rewrites the radius test ||x_j - x_q||^2 <= R^2 as eq. (ip2),
+//     xbar_j - x_j^T x_q <= (R^2 - x_q^T x_q) / 2,
+// so a block of score-adjacent queries against a block of window candidates
+// is one small matrix product (the gemm over the union window).  Here that
+// product runs as v_mfma_f32_32x32x16_bf16: bf16 operands, fp32 accumulation.
+// The screen never decides a pair by itself: it only REJECTS pairs it can
+// prove to be outside the radius, using a rigorous bound on everything the
+// bf16/fp32 evaluation can get wrong; every other pair goes to the float64
+// recheck (normative rule), so the result is exact.
+//
+// With y = fl32(p - mu) (centred rows), h_j = ||y_j||^2 / 2 and a per-query
+// constant C_q, the screen passes (q, j) iff
+//     D = fl_mfma( sum_k a_qk b_jk + C_q )  >=  fl32(h_j),
+// where the packed operands satisfy sum_k a_qk b_jk ~ y_q . y_j:
+//   terms = 1:  a = bf16(y_q),              b = bf16(y_j)
+//   terms = 3:  a = [hi_q, hi_q, lo_q],     b = [hi_j, lo_j, hi_j]
+//               hi = bf16(y), lo = bf16(y - hi)   (hi*hi + hi*lo + lo*hi)
+// C_q is chosen (k_mixed_qprep) so that every pair with S(p_j, q) <= fl(R*R)
+// passes:
+//   C_q >= R2'/2 - h_q + eta sqrt(R2') + eta^2/2 + e_rep + e_acc + e_h
+//   R2'   = fl(R*R) (1 + 2 gamma64_{d+2})   bounds the exact ||p - q||^2
+//   eta   = 1.01 u32 (Y + ||y_q||)          centring rounding, Y = max_j ||y_j||
+//   e_rep = c_rep Y ||y_q||                 bf16 representation error
+//           c_rep = u_b (2 + u_b) (terms 1), u_b^2 (3 + 3 u_b) (terms 3), u_b = 2^-8
+//   e_acc = 2 gamma32_{K+1} (1.02 Y ||y_q|| + |C_q|)  fp32 accumulation of the
+//           K exact bf16 products and C (factor 2: the accumulation order and
+//           rounding inside the matrix core are not specified)
+//   e_h   = 1.01 u32 Y^2 / 2                rounding of h_j to fp32
+// and rounded up to fp32.
+//
+// Data layout.  Candidates and queries are rows of KA bf16 (KA a multiple
+// of 16) in score order.  A wavefront owns QB blocks of 32 queries (the A
+// operand, loaded once per work unit) and sweeps the unit's candidates 32
+// at a time (the B operand: lane l loads 16 contiguous bytes of candidate
+// l % 32, so a step reads 32 consecutive rows).  The accumulator of the
+// 32x32 block starts at C_q (each lane's 16 accumulators belong to 16
+// queries and one candidate), so the epilogue is a max over the lane's 16
+// values and one compare with h_j; only when some lane passes does the
+// wave walk its accumulators and append (query, candidate) pairs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_common.h"
+#include "query_plan.h"
+#include "snn_internal.h"
+
+namespace snn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+double mixed_c_rep(int terms) {
+  const double ub = std::ldexp(1.0, -8);
+  return 1.01 * (terms == 1 ? ub * (2.0 + ub) : ub * ub * (3.0 + 3.0 * ub));
+}
+
+MixedBound mixed_bound(int terms, int KA, int d, double R2, double Y) {
+  const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+  auto g32 = [&](int k) { return k * u32 / (1.0 - k * u32); };
+  auto g64 = [&](int k) { return k * u64 / (1.0 - k * u64); };
+  MixedBound b;
+  const double r2p = R2 * (1.0 + 2.0 * g64(d + 2));
+  b.r2p_half = 0.5 * r2p;
+  b.sqrt_r2p = std::sqrt(r2p) * (1.0 + 1e-15);
+  b.u32p = 1.01 * u32;
+  b.Y = Y;
+  b.c_rep = mixed_c_rep(terms);
+  b.g_acc = 2.0 * g32(KA + 1);
+  b.e_h = 1.01 * u32 * Y * Y * 0.5;
+  b.g64 = g64(d + 1);
+  return b;
+}
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / kWave;
+constexpr int kStage = 2048;
+
+__device__ __forceinline__ float round_up_f32(double c) {
+  float f = (float)c;
+  if ((double)f < c) f = nextafterf(f, INFINITY);
+  return f;
+}
+
+__device__ __forceinline__ float threshold(const MixedBound& b, double hq, double nq) {
+  const double eta = b.u32p * (b.Y + nq);
+  const double hlo = hq * (1.0 - b.g64);
+  double c0 = b.r2p_half - hlo + eta * b.sqrt_r2p + 0.5 * eta * eta + b.c_rep * b.Y * nq + b.e_h;
+  c0 += 8.0 * 1.1102230246251565e-16 * (b.r2p_half + hq + b.Y * nq) + 1e-30;
+  const double e_acc = b.g_acc * (1.02 * b.Y * nq + fabs(c0)) * 1.01;
+  return round_up_f32(c0 + e_acc);
+}
+
+// Out-of-sample queries: operands and thresholds from the float64 rows.
+__global__ __launch_bounds__(kThreads) void k_mixed_qprep(const double* __restrict__ q64, int64_t m, int d, int dp,
+                                                         const double* __restrict__ mu, int terms, int KA,
+                                                         MixedBound b, uint16_t* __restrict__ qop,
+                                                         float* __restrict__ cthr) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x) {
+    const double* q = q64 + s * dp;
+    uint16_t* o = qop + s * KA;
+    double nn = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const float y = (float)(q[k] - mu[k]);
+      nn += (double)y * (double)y;
+      const uint16_t hi = f32_to_bf16_rne(y);
+      if (terms == 1) {
+        o[k] = hi;
+      } else {
+        const uint16_t lo = f32_to_bf16_rne(y - bf16_to_f32(hi));
+        o[k] = hi;
+        o[d + k] = hi;
+        o[2 * d + k] = lo;
+      }
+    }
+    for (int k = terms * d; k < KA; ++k) o[k] = 0;
+    const double nq = sqrt(nn) * (1.0 + 1e-15);
+    cthr[s] = threshold(b, 0.5 * nn, nq);
+  }
+}
+
+// Self-queries: the query rows are the index rows.
+__global__ __launch_bounds__(kThreads) void k_mixed_qprep_self(const float* __restrict__ ys, int64_t n, int d,
+                                                              MixedBound b, float* __restrict__ cthr) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+    const float* y = ys + s * d;
+    double nn = 0.0;
+    for (int k = 0; k < d; ++k) nn += (double)y[k] * (double)y[k];
+    const double nq = sqrt(nn) * (1.0 + 1e-15);
+    cthr[s] = threshold(b, 0.5 * nn, nq);
+  }
+}
+
+__device__ __forceinline__ float max16(const f32x16& a) {
+  float m0 = fmaxf(fmaxf(a[0], a[1]), a[2]);
+  float m1 = fmaxf(fmaxf(a[3], a[4]), a[5]);
+  float m2 = fmaxf(fmaxf(a[6], a[7]), a[8]);
+  float m3 = fmaxf(fmaxf(a[9], a[10]), a[11]);
+  float m4 = fmaxf(fmaxf(a[12], a[13]), a[14]);
+  m0 = fmaxf(fmaxf(m0, m1), m2);
+  m3 = fmaxf(fmaxf(m3, m4), a[15]);
+  return fmaxf(m0, m3);
+}
+
+template <int NS, int QB>
+__global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) {
+  __shared__ PairStage<kStage> st;
+  __shared__ long long s_unit;
+  stage_init(st);
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int xcd = blockIdx.x % q.nxcd;
+  const int KA = x.KA;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_unit = next_unit(q, xcd);
+    __syncthreads();
+    const int64_t u = uniform_i64(s_unit);
+    if (u < 0) break;
+    const int tile = uniform_i32(unit_tile(q, u));
+    const int64_t c = u - q.unit_off[tile];
+    const int64_t q0 = (int64_t)tile * q.T + (int64_t)wave * 32 * QB;
+    const int64_t j0 = q.tlo[tile] + c * q.CH;
+    const int64_t j1 = min(j0 + q.CH, (int64_t)q.thi[tile]);
+    if (q0 >= q.m) continue;  // this wave has no queries in the (ragged) last tile
+
+    bf16x8 A[QB][NS];
+    f32x16 Cin[QB];
+#pragma unroll
+    for (int b = 0; b < QB; ++b) {
+      const int64_t qr = q0 + b * 32 + l32;
+      const bool vq = qr < q.m;
+      const bf16x8* src = reinterpret_cast<const bf16x8*>(x.qop + (vq ? qr : 0) * KA + 8 * half);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        bf16x8 v = src[2 * s];
+        if (!vq) v = bf16x8{};
+        A[b][s] = v;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t qi = q0 + b * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        Cin[b][r] = qi < q.m ? x.cthr[qi] : -INFINITY;
+      }
+    }
+
+    for (int64_t jb = j0; jb < j1; jb += 32) {
+      const int64_t jc = jb + l32;
+      const bool vj = jc < j1;
+      const int64_t jj = vj ? jc : j1 - 1;
+      const bf16x8* src = reinterpret_cast<const bf16x8*>(x.cop + jj * KA + 8 * half);
+      bf16x8 Bv[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) Bv[s] = src[2 * s];
+      const float hj = vj ? x.h[jj] : INFINITY;
+#pragma unroll
+      for (int b = 0; b < QB; ++b) {
+        f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][0], Bv[0], Cin[b], 0, 0, 0);
+#pragma unroll
+        for (int s = 1; s < NS; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][s], Bv[s], acc, 0, 0, 0);
+        const bool any = max16(acc) >= hj;
+        if (__ballot(any)) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int64_t qi = q0 + b * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+            stage_push_wave(st, q.sink, acc[r] >= hj, (int)qi, (int)jj);
+          }
+        }
+      }
+    }
+  }
+  stage_flush(st, q.sink);
+}
+
+template <int NS, int QB>
+void launch_ns(const QueryDev& q, const MixedDev& x, int grid, hipStream_t s) {
+  k_cand_mfma<NS, QB><<<grid, kThreads, 0, s>>>(q, x);
+}
+
+int grid_for(int64_t work, int cap) {
+  int64_t g = (work + kThreads - 1) / kThreads;
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+}  // namespace
+
+int mixed_max_slices() { return 8; }
+int mixed_queries_per_wave() { return 64; }
+
+int mixed_blocks_per_cu(int KA) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (KA / 16) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<1, 2>, kThreads, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<2, 2>, kThreads, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<3, 2>, kThreads, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<4, 2>, kThreads, 0); break;
+    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<5, 2>, kThreads, 0); break;
+    case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<6, 2>, kThreads, 0); break;
+    case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<7, 2>, kThreads, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<8, 2>, kThreads, 0); break;
+    default: break;
+  }
+  if (e != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  return nb;
+}
+
+void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, int terms, int KA,
+                        const MixedBound& b, uint16_t* qop, float* cthr, hipStream_t s) {
+  if (m <= 0) return;
+  k_mixed_qprep<<<grid_for(m, 8192), kThreads, 0, s>>>(q64, m, d, dp, mu, terms, KA, b, qop, cthr);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* cthr, hipStream_t s) {
+  k_mixed_qprep_self<<<grid_for(n, 8192), kThreads, 0, s>>>(ys, n, d, b, cthr);
+  SNN_LAUNCH_CHECK();
+}
+
+// T must equal 4 waves x 32 x QB (QB = 2).
+void launch_cand_mfma(const QueryDev& q, const MixedDev& x, int grid, hipStream_t s) {
+  const int ns = x.KA / 16;
+  switch (ns) {
+    case 1: launch_ns<1, 2>(q, x, grid, s); break;
+    case 2: launch_ns<2, 2>(q, x, grid, s); break;
+    case 3: launch_ns<3, 2>(q, x, grid, s); break;
+    case 4: launch_ns<4, 2>(q, x, grid, s); break;
+    case 5: launch_ns<5, 2>(q, x, grid, s); break;
+    case 6: launch_ns<6, 2>(q, x, grid, s); break;
+    case 7: launch_ns<7, 2>(q, x, grid, s); break;
+    case 8: launch_ns<8, 2>(q, x, grid, s); break;
+    default: fail(SNN_ENOTSUP, "mixed screen supports packed operand rows of at most 128 bf16");
+  }
+  SNN_LAUNCH_CHECK();
+}
+
+}  // namespace snn

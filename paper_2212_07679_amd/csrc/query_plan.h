@@ -83,6 +83,35 @@ void launch_windows(const double* key, int n, const double* qalpha, const double
 
 // k_cand_fp64.hip: plain float64 screen (every window pair, normative rule)
 void launch_cand_fp64(const QueryDev& q, int grid, hipStream_t s);
+int fp64_blocks_per_cu(int dp);
+
+// k_cand_mfma.hip: mixed-precision screen on the matrix cores
+struct MixedDev {
+  const uint16_t* qop;  // m x KA bf16: query operand rows (score order)
+  const float* cthr;    // m: per-query accumulator start C_q
+  const uint16_t* cop;  // n x KA bf16: candidate operand rows (score order)
+  const float* h;       // n: fl32(||y_j||^2 / 2)
+  int KA;
+};
+struct MixedBound {
+  double r2p_half;  // R2' / 2
+  double sqrt_r2p;  // sqrt(R2'), rounded up
+  double u32p;      // 1.01 u32
+  double Y;         // max_j ||y_j||
+  double c_rep;     // bf16 representation error coefficient
+  double g_acc;     // 2 gamma32_{K+1}
+  double e_h;       // rounding of h_j to fp32
+  double g64;       // gamma64_{d+1}: relative error of h_q in float64
+};
+double mixed_c_rep(int terms);
+MixedBound mixed_bound(int terms, int KA, int d, double R2, double Y);
+int mixed_max_slices();
+int mixed_queries_per_wave();
+int mixed_blocks_per_cu(int KA);
+void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, int terms, int KA,
+                        const MixedBound& b, uint16_t* qop, float* cthr, hipStream_t s);
+void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* cthr, hipStream_t s);
+void launch_cand_mfma(const QueryDev& q, const MixedDev& x, int grid, hipStream_t s);
 
 // k_csr.hip
 struct Survivors {

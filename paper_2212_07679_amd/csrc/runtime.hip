@@ -210,10 +210,25 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const int64_t n = ix.n;
   const double R2 = R * R;
 
-  snn_precision prec = o.precision == SNN_PREC_AUTO ? SNN_PREC_FP64 : o.precision;
-  if (prec == SNN_PREC_MIXED) fail(SNN_ENOTSUP, "mixed precision screen not built yet");
-  const int T = o.tile_q ? o.tile_q : 64;
-  const int CH = o.tile_c ? o.tile_c : 1024;
+  // ---- precision plan
+  // The mixed screen passes every pair whose decomposed distance is within
+  // about 2 * slack of R^2; it pays off when that band is narrow.
+  const double Y = ix.max_norm;
+  auto ka_of = [&](int t) { return ((t * d + 15) / 16) * 16; };
+  auto slack_of = [&](int t) { return 2.0 * mixed_c_rep(t) * Y * Y; };
+  int terms = o.mixed_terms;
+  if (terms == 0) terms = (slack_of(1) <= 0.5 * R2 || ka_of(3) > 16 * mixed_max_slices()) ? 1 : 3;
+  const bool mixed_ok = ka_of(terms) <= 16 * mixed_max_slices();
+  snn_precision prec = o.precision;
+  if (prec == SNN_PREC_AUTO) prec = (mixed_ok && slack_of(terms) <= 4.0 * R2) ? SNN_PREC_MIXED : SNN_PREC_FP64;
+  if (prec == SNN_PREC_MIXED && !mixed_ok)
+    fail(SNN_ENOTSUP, "mixed screen: packed operand rows longer than 128 bf16 (lower d or use terms=1)");
+  if (prec == SNN_PREC_MIXED && o.tile_q && o.tile_q != 4 * mixed_queries_per_wave())
+    fail(SNN_EINVAL, "mixed screen: tile_q must be 256");
+  const int T = prec == SNN_PREC_MIXED ? 4 * mixed_queries_per_wave() : (o.tile_q ? o.tile_q : 64);
+  const int CH = o.tile_c ? o.tile_c : (prec == SNN_PREC_MIXED ? 4096 : 1024);
+  if (prec == SNN_PREC_MIXED && CH % 32 != 0) fail(SNN_EINVAL, "mixed screen: tile_c must be a multiple of 32");
+  if (prec == SNN_PREC_MIXED) build_mixed_operands(ix, terms);
   const int ntiles = (int)std::max<int64_t>(1, (m + T - 1) / T);
 
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -244,6 +259,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       Ctl* ctl;
       int32_t* row_cnt;
       int32_t* lists;
+      uint16_t* qop;
+      float* cthr;
     } p;
     const size_t mq = self ? 1 : (size_t)m;
     p.ukey = c.take<uint32_t>(mq);
@@ -264,6 +281,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     p.ctl = c.take<Ctl>(1);
     p.row_cnt = c.take<int32_t>(std::max<int64_t>(m, 1));
     p.lists = c.take<int32_t>(2 * std::max<int64_t>(m, 1));
+    const bool mix = prec == SNN_PREC_MIXED;
+    p.qop = c.take<uint16_t>(mix && !self ? (size_t)m * ka_of(terms) : 1);
+    p.cthr = c.take<float>(mix ? std::max<int64_t>(m, 1) : 1);
     return p;
   };
   plan_query(probe);
@@ -323,6 +343,23 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   qd.counters = P.ctl->counters;
   qd.nxcd = di.xcds;
 
+  MixedDev mx{};
+  if (prec == SNN_PREC_MIXED) {
+    MixedOperands& mo = ix.mixed[terms == 1 ? 0 : 1];
+    const MixedBound mb = mixed_bound(terms, mo.ka, d, R2, Y);
+    mx.KA = mo.ka;
+    mx.cop = mo.cand.as<uint16_t>();
+    mx.h = ix.h.as<float>();
+    mx.cthr = P.cthr;
+    if (self) {
+      mx.qop = (terms == 1 ? mo.cand : mo.qself).as<uint16_t>();
+      launch_mixed_qprep_self(ix.ys.as<float>(), n, d, mb, P.cthr, s);
+    } else {
+      mx.qop = P.qop;
+      launch_mixed_qprep(q64, m, d, ix.dp, ix.mu.as<double>(), terms, mo.ka, mb, P.qop, P.cthr, s);
+    }
+  }
+
   // survivors: capacity remembered on the index, grown on overflow
   long long cap = std::max<long long>(1 << 16, (long long)(ix.ws[1].bytes / 24));
   HostCtl hc{};
@@ -349,9 +386,15 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       launch_fill_u64(&P.ctl->survivors, 1, 0ull, s);
       launch_fill_i32(P.row_cnt, m, 0, s);
     }
-    const int grid = std::max(di.xcds, (di.cus * 4 / di.xcds) * di.xcds);
+    const int per_cu = prec == SNN_PREC_MIXED ? mixed_blocks_per_cu(mx.KA) : fp64_blocks_per_cu(ix.dp);
+    const int grid = std::max(di.xcds, (di.cus * per_cu / di.xcds) * di.xcds);
     if (st) SNN_HIP(hipEventRecord(ev[1], s));
-    if (m > 0) launch_cand_fp64(qd, grid, s);
+    if (m > 0) {
+      if (prec == SNN_PREC_MIXED)
+        launch_cand_mfma(qd, mx, grid, s);
+      else
+        launch_cand_fp64(qd, grid, s);
+    }
     if (st) SNN_HIP(hipEventRecord(ev[2], s));
     launch_recheck(qd, sv, P.row_cnt, di.cus * 8, s);
     exclusive_scan_i32_to_i64(P.row_cnt, out->row_ptr, m, P.scan_scratch, s);
@@ -367,7 +410,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
         st->pairs_recheck = (int64_t)hc.ctl.survivors;
         st->nnz = hc.nnz;
         st->precision_used = prec;
-        st->terms_used = 0;
+        st->terms_used = prec == SNN_PREC_MIXED ? terms : 0;
       }
       if (hc.nnz > out->nnz_cap) {
         char buf[160];

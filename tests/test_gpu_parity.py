@@ -44,11 +44,44 @@ def check_same(got, ref, what=""):
     assert np.array_equal(col, ref.col), f"{what}: col differs"
     zero = ref.dist == 0
     assert np.all(dist[zero] == 0), what
-    rel = np.abs(dist - ref.dist) / np.maximum(ref.dist, 1e-300)
-    assert np.all(rel[~zero] <= 1e-5), f"{what}: max rel dist err {rel.max()}"
+    nz = ~zero
+    rel = np.abs(dist[nz] - ref.dist[nz]) / ref.dist[nz]
+    assert np.all(rel <= 1e-5), f"{what}: max rel dist err {rel.max()}"
 
 
-PRECS = ["fp64"]
+PRECS = ["fp64", "mixed", "auto"]
+
+
+@pytest.mark.parametrize("terms", [1, 3])
+@pytest.mark.parametrize("R", [1.5, 4.0])
+def test_mixed_terms_gmm16(B, terms, R):
+    w = W.gmm16(n=40_000, m=2_000, R=R)
+    say(f"mixed terms={terms} gmm16 n={w.n} m={w.m} R={R}")
+    ref, _ = oracle.snn_query(oracle.build_index(w.P), w.Q, w.R)
+    idx = B.Index(to_dev(w.P))
+    got = idx.query(to_dev(w.Q), w.R, precision="mixed", terms=terms, stats=True)
+    check_same(got, ref, f"mixed terms={terms} R={R}")
+    st = got[3]
+    assert st["terms_used"] == terms and st["precision_used"] == 1
+    assert st["pairs_recheck"] >= st["nnz"]
+
+
+@pytest.mark.parametrize("terms", [1, 3])
+def test_mixed_self_gmm128(B, terms):
+    w = W.gmm128z(n=12_000, R=4.0)
+    say(f"mixed self terms={terms} gmm128z n={w.n}")
+    ref, _ = oracle.snn_query(oracle.build_index(w.P), w.P, w.R)
+    idx = B.Index(to_dev(w.P))
+    # d = 128: three bf16 terms need 384-wide rows, beyond the packed limit
+    if terms == 3:
+        with pytest.raises(B.SnnError) as e:
+            idx.query_self(w.R, precision="mixed", terms=3)
+        assert e.value.status == B.SNN_ENOTSUP
+        return
+    check_same(idx.query_self(w.R, precision="mixed", terms=1), ref, "gmm128z self")
+    # a radius with many positives
+    ref2, _ = oracle.snn_query(oracle.build_index(w.P), w.P[:3000], 9.0)
+    check_same(idx.query(to_dev(w.P[:3000]), 9.0, precision="mixed", terms=1), ref2, "gmm128z R=9")
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -128,25 +161,27 @@ def test_edge_cases(B):
     check_same(idx3.query(to_dev(Q3), 0.4), oracle.brute_radius(P3, Q3, 0.4), "long rows")
 
 
-def test_lattice_ties(B):
-    say("lattice ties")
+@pytest.mark.parametrize("prec", PRECS)
+def test_lattice_ties(B, prec):
+    say(f"lattice ties {prec}")
     P = W.lattice(-12, 12, 2)
     Q = P[::13]
     idx = B.Index(to_dev(P))
-    check_same(idx.query(to_dev(Q), 5.0), oracle.brute_radius(P, Q, 5.0), "lattice R=5")
+    check_same(idx.query(to_dev(Q), 5.0, precision=prec), oracle.brute_radius(P, Q, 5.0), "lattice R=5")
     P3 = W.lattice(-5, 5, 3).astype(np.float32)
     idx3 = B.Index(to_dev(P3))
-    check_same(idx3.query_self(3.0), oracle.brute_radius(P3, P3, 3.0), "3-D lattice self")
+    check_same(idx3.query_self(3.0, precision=prec), oracle.brute_radius(P3, P3, 3.0), "3-D lattice self")
 
 
-def test_far_from_origin(B):
+@pytest.mark.parametrize("prec", PRECS)
+def test_far_from_origin(B, prec):
     # near-duplicates far from the mean: large ||x|| against a tiny radius
-    say("far from origin")
+    say(f"far from origin {prec}")
     g = np.random.default_rng(8)
     P = np.concatenate([1e4 + g.standard_normal((2000, 4)) * 1e-3, -1e4 + g.standard_normal((2000, 4)) * 1e-3])
     Q = P[::9] + 1e-4 * g.standard_normal((P[::9].shape[0], 4))
     idx = B.Index(to_dev(P))
-    check_same(idx.query(to_dev(Q), 2e-3), oracle.brute_radius(P, Q, 2e-3), "far")
+    check_same(idx.query(to_dev(Q), 2e-3, precision=prec), oracle.brute_radius(P, Q, 2e-3), "far")
 
 
 def test_determinism(B):
