@@ -40,6 +40,8 @@ def common_flags():
         "-ffp-contract=off",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wno-unused-command-line-argument",
+        # matrix-core results in VGPRs, so the screen's epilogue reads them directly
+        "-mllvm", "-amdgpu-mfma-vgpr-form",
         f"-I{INCLUDE}",
         f"-I{CSRC}",
     ]

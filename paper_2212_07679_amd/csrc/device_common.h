@@ -87,14 +87,27 @@ __device__ __forceinline__ void stage_init(PairStage<kStage>& st) {
   if (threadIdx.x == 0) st.count = 0;
 }
 
+// Global-memory accesses through explicitly global pointers: a generic
+// (flat) access would count against both the vector-memory and the LDS wait
+// counters and force full waits on the loads in flight around it.
+typedef __attribute__((address_space(1))) unsigned long long global_u64;
+
+// an int2 (x at the lower address) stored as one little-endian 64-bit word
+__device__ __forceinline__ void sink_store(const PairSink& sink, long long g, int2 v) {
+  if (g < sink.cap)
+    ((global_u64*)sink.out)[g] = ((unsigned long long)(uint32_t)v.y << 32) | (unsigned long long)(uint32_t)v.x;
+}
+__device__ __forceinline__ unsigned long long sink_reserve(const PairSink& sink, unsigned long long cnt) {
+  return __hip_atomic_fetch_add((global_u64*)sink.counter, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int kStage>
 __device__ __forceinline__ void stage_push(PairStage<kStage>& st, const PairSink& sink, int q, int j) {
   int pos = atomicAdd(&st.count, 1);
   if (pos < kStage) {
     st.buf[pos] = make_int2(q, j);
   } else {
-    unsigned long long g = atomicAdd(sink.counter, 1ull);
-    if ((long long)g < sink.cap) sink.out[g] = make_int2(q, j);
+    sink_store(sink, (long long)sink_reserve(sink, 1ull), make_int2(q, j));
   }
 }
 
@@ -116,8 +129,7 @@ __device__ __forceinline__ void stage_push_wave(PairStage<kStage>& st, const Pai
     if (pos < kStage) {
       st.buf[pos] = make_int2(q, j);
     } else {
-      unsigned long long g = atomicAdd(sink.counter, 1ull);
-      if ((long long)g < sink.cap) sink.out[g] = make_int2(q, j);
+      sink_store(sink, (long long)sink_reserve(sink, 1ull), make_int2(q, j));
     }
   }
 }
@@ -128,14 +140,11 @@ __device__ __forceinline__ void stage_flush(PairStage<kStage>& st, const PairSin
   __syncthreads();
   int cnt = st.count < kStage ? st.count : kStage;
   if (threadIdx.x == 0) {
-    st.base = cnt ? (long long)atomicAdd(sink.counter, (unsigned long long)cnt) : 0;
+    st.base = cnt ? (long long)sink_reserve(sink, (unsigned long long)cnt) : 0;
   }
   __syncthreads();
   long long base = st.base;
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    long long g = base + i;
-    if (g < sink.cap) sink.out[g] = st.buf[i];
-  }
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) sink_store(sink, base + i, st.buf[i]);
 }
 
 }  // namespace snn

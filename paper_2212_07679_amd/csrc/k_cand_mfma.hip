@@ -147,7 +147,54 @@ __device__ __forceinline__ float max16(const f32x16& a) {
   return fmaxf(m0, m3);
 }
 
-template <int NS, int QB>
+template <int NL>
+__device__ __forceinline__ void load_step(bf16x8 (&B)[NL], float& h, const bf16x8* p, const float* hp) {
+#pragma unroll
+  for (int s = 0; s < NL; ++s) B[s] = p[2 * s];
+  h = *hp;
+}
+
+// One 32-candidate step for QB blocks of 32 queries: the matrix products,
+// the max/compare epilogue, and (rarely) the append of passing pairs.
+// Operand slice s of the candidate is B[s] for s < NL and B[s - NL] beyond
+// (the split layout repeats hi as the third segment).
+template <int NS, int QB, int NL>
+__device__ __forceinline__ void screen_step(const bf16x8 (&A)[QB][NS], const f32x16 (&Cin)[QB],
+                                            const bf16x8 (&B)[NL], float hv, int jr, int span, int j0,
+                                            int64_t q0, int half, PairStage<kStage>& st, const PairSink& sink) {
+  const float hj = jr < span ? hv : INFINITY;
+  f32x16 acc[QB];
+#pragma unroll
+  for (int b = 0; b < QB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][0], B[0], Cin[b], 0, 0, 0);
+#pragma unroll
+  for (int s = 1; s < NS; ++s)
+#pragma unroll
+    for (int b = 0; b < QB; ++b)
+      acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][s], B[s < NL ? s : s - NL], acc[b], 0, 0, 0);
+  bool any = false;
+#pragma unroll
+  for (int b = 0; b < QB; ++b) any |= (max16(acc[b]) >= hj);
+  if (__ballot(any)) {
+    // rare: collect each lane's passing accumulators as a bit mask, then
+    // append one pair per lane per round until every mask is empty
+    const int jj = j0 + jr;
+#pragma unroll
+    for (int b = 0; b < QB; ++b) {
+      uint32_t bits = 0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) bits |= (acc[b][r] >= hj ? 1u : 0u) << r;
+      while (__ballot(bits != 0)) {
+        const bool p = bits != 0;
+        const int r = p ? __ffs(bits) - 1 : 0;
+        bits &= bits - 1;
+        const int qi = (int)q0 + b * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        stage_push_wave(st, sink, p, qi, jj);
+      }
+    }
+  }
+}
+
+template <int NS, int QB, int NL>
 __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) {
   __shared__ PairStage<kStage> st;
   __shared__ long long s_unit;
@@ -189,37 +236,49 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
       }
     }
 
-    for (int64_t jb = j0; jb < j1; jb += 32) {
-      const int64_t jc = jb + l32;
-      const bool vj = jc < j1;
-      const int64_t jj = vj ? jc : j1 - 1;
-      const bf16x8* src = reinterpret_cast<const bf16x8*>(x.cop + jj * KA + 8 * half);
-      bf16x8 Bv[NS];
-#pragma unroll
-      for (int s = 0; s < NS; ++s) Bv[s] = src[2 * s];
-      const float hj = vj ? x.h[jj] : INFINITY;
-#pragma unroll
-      for (int b = 0; b < QB; ++b) {
-        f32x16 acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][0], Bv[0], Cin[b], 0, 0, 0);
-#pragma unroll
-        for (int s = 1; s < NS; ++s) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][s], Bv[s], acc, 0, 0, 0);
-        const bool any = max16(acc) >= hj;
-        if (__ballot(any)) {
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            const int64_t qi = q0 + b * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-            stage_push_wave(st, q.sink, acc[r] >= hj, (int)qi, (int)jj);
-          }
-        }
-      }
+    // Candidate rows j0 + 32*it + l32, KB bf16 apart (for the split layout a
+    // row is [hi | lo] and the third operand slice reuses hi).  The operand
+    // and h arrays carry 32 padding rows past n, so the ragged last step
+    // reads in bounds; lanes past j1 are masked by h = +inf.  Two register
+    // sets alternate, so the next step's operands load while this step's
+    // matrix products run.
+    const int span = (int)(j1 - j0);
+    const int nsteps = (span + 31) / 32;
+    const bf16x8* pb = reinterpret_cast<const bf16x8*>(x.cop + (j0 + l32) * x.KB + 8 * half);
+    const float* hp = x.h + j0 + l32;
+    const int stride = 32 * x.KB / 8;  // one step in bf16x8 units
+    // The look-ahead loads are unconditional (past the last step they re-read
+    // the current rows), so no branch separates a load from its use and the
+    // waits stay exact.
+    bf16x8 B0[NL], B1[NL];
+    float h0, h1;
+    load_step<NL>(B0, h0, pb, hp);
+    for (int it = 0; it < nsteps; it += 2) {
+      const int a1 = it + 1 < nsteps ? 1 : 0;
+      load_step<NL>(B1, h1, pb + a1 * stride, hp + a1 * 32);
+      screen_step<NS, QB, NL>(A, Cin, B0, h0, it * 32 + l32, span, (int)j0, q0, half, st, q.sink);
+      if (!a1) break;
+      const int a2 = it + 2 < nsteps ? 2 : 1;
+      pb += a2 * stride;
+      hp += a2 * 32;
+      load_step<NL>(B0, h0, pb, hp);
+      screen_step<NS, QB, NL>(A, Cin, B1, h1, (it + 1) * 32 + l32, span, (int)j0, q0, half, st, q.sink);
     }
   }
   stage_flush(st, q.sink);
 }
 
-template <int NS, int QB>
-void launch_ns(const QueryDev& q, const MixedDev& x, int grid, hipStream_t s) {
-  k_cand_mfma<NS, QB><<<grid, kThreads, 0, s>>>(q, x);
+typedef void (*MixedKernel)(QueryDev, MixedDev);
+
+// (slices per product chain, slices loaded per candidate row)
+MixedKernel pick_kernel(int KA, int KB) {
+  const int ns = KA / 16, nl = KB / 16;
+#define SNN_CASE(NS_, NL_) \
+  if (ns == NS_ && nl == NL_) return k_cand_mfma<NS_, 2, NL_>;
+  SNN_CASE(1, 1) SNN_CASE(2, 2) SNN_CASE(3, 3) SNN_CASE(3, 2) SNN_CASE(4, 4) SNN_CASE(5, 5)
+  SNN_CASE(6, 6) SNN_CASE(6, 4) SNN_CASE(7, 7) SNN_CASE(8, 8)
+#undef SNN_CASE
+  return nullptr;
 }
 
 int grid_for(int64_t work, int cap) {
@@ -232,21 +291,10 @@ int grid_for(int64_t work, int cap) {
 int mixed_max_slices() { return 8; }
 int mixed_queries_per_wave() { return 64; }
 
-int mixed_blocks_per_cu(int KA) {
+int mixed_blocks_per_cu(int KA, int KB) {
+  MixedKernel k = pick_kernel(KA, KB);
   int nb = 0;
-  hipError_t e = hipErrorInvalidValue;
-  switch (KA / 16) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<1, 2>, kThreads, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<2, 2>, kThreads, 0); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<3, 2>, kThreads, 0); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<4, 2>, kThreads, 0); break;
-    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<5, 2>, kThreads, 0); break;
-    case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<6, 2>, kThreads, 0); break;
-    case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<7, 2>, kThreads, 0); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cand_mfma<8, 2>, kThreads, 0); break;
-    default: break;
-  }
-  if (e != hipSuccess || nb < 1) {
+  if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kThreads, 0) != hipSuccess || nb < 1) {
     (void)hipGetLastError();
     nb = 1;
   }
@@ -267,18 +315,9 @@ void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound
 
 // T must equal 4 waves x 32 x QB (QB = 2).
 void launch_cand_mfma(const QueryDev& q, const MixedDev& x, int grid, hipStream_t s) {
-  const int ns = x.KA / 16;
-  switch (ns) {
-    case 1: launch_ns<1, 2>(q, x, grid, s); break;
-    case 2: launch_ns<2, 2>(q, x, grid, s); break;
-    case 3: launch_ns<3, 2>(q, x, grid, s); break;
-    case 4: launch_ns<4, 2>(q, x, grid, s); break;
-    case 5: launch_ns<5, 2>(q, x, grid, s); break;
-    case 6: launch_ns<6, 2>(q, x, grid, s); break;
-    case 7: launch_ns<7, 2>(q, x, grid, s); break;
-    case 8: launch_ns<8, 2>(q, x, grid, s); break;
-    default: fail(SNN_ENOTSUP, "mixed screen supports packed operand rows of at most 128 bf16");
-  }
+  MixedKernel k = pick_kernel(x.KA, x.KB);
+  if (!k) fail(SNN_ENOTSUP, "mixed screen supports packed operand rows of at most 128 bf16");
+  k<<<grid, kThreads, 0, s>>>(q, x);
   SNN_LAUNCH_CHECK();
 }
 

@@ -251,6 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, in
                                                     int32_t* __restrict__ perm, T* __restrict__ po,
                                                     double* __restrict__ p64, float* __restrict__ ys,
                                                     float* __restrict__ h, float* __restrict__ ynorm) {
+  if (blockIdx.x == 0 && threadIdx.x < 32) h[n + threadIdx.x] = INFINITY;  // padding rows
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t i = val[s];
     perm[s] = (int32_t)i;
@@ -277,26 +278,32 @@ __global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, in
 // ---- mixed-precision operand rows ---------------------------------------------
 // terms = 1: row = [bf16(y_0..y_{d-1}), 0...]                 (ka = pad16(d))
 // terms = 3: cand = [hi | lo | hi], query = [hi | hi | lo]     (ka = pad16(3d))
-// with hi = bf16(y), lo = bf16(y - hi) (y - hi is exact in float).
+// with hi = bf16(y), lo = bf16(y - hi) (y - hi is exact in float).  When d is
+// a multiple of 16 the candidate rows are stored as [hi | lo] (kb = 2d): the
+// third segment equals the first and the screen reuses its registers.
+// Rows n .. n+31 of the candidate array are zero padding.
 __global__ __launch_bounds__(kThreads) void k_operands(const float* __restrict__ ys, int64_t n, int d, int terms,
-                                                      int ka, uint16_t* __restrict__ cand,
+                                                      int ka, int kb, uint16_t* __restrict__ cand,
                                                       uint16_t* __restrict__ qself) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * ka; e += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t total = (n + 32) * (int64_t)ka;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = e / ka;
     const int k = (int)(e % ka);
     uint16_t cv = 0, qv = 0;
-    if (terms == 1) {
-      if (k < d) cv = qv = f32_to_bf16_rne(ys[s * d + k]);
-    } else if (k < 3 * d) {
-      const int seg = k / d, c = k % d;
-      const float y = ys[s * d + c];
-      const uint16_t hi = f32_to_bf16_rne(y);
-      const uint16_t lo = f32_to_bf16_rne(y - bf16_to_f32(hi));
-      cv = (seg == 1) ? lo : hi;
-      qv = (seg == 2) ? lo : hi;
+    if (s < n) {
+      if (terms == 1) {
+        if (k < d) cv = qv = f32_to_bf16_rne(ys[s * d + k]);
+      } else if (k < 3 * d) {
+        const int seg = k / d, c = k % d;
+        const float y = ys[s * d + c];
+        const uint16_t hi = f32_to_bf16_rne(y);
+        const uint16_t lo = f32_to_bf16_rne(y - bf16_to_f32(hi));
+        cv = (seg == 1) ? lo : hi;
+        qv = (seg == 2) ? lo : hi;
+      }
     }
-    cand[e] = cv;
-    if (qself) qself[e] = qv;
+    if (k < kb) cand[s * kb + k] = cv;
+    if (qself && s < n) qself[e] = qv;
   }
 }
 
@@ -319,7 +326,7 @@ void build_index_t(Index& ix, const T* X) {
   ix.po.ensure(ix.arena, sizeof(T) * n * d);
   ix.p64.ensure(ix.arena, sizeof(double) * n * ix.dp);
   ix.ys.ensure(ix.arena, sizeof(float) * n * d);
-  ix.h.ensure(ix.arena, sizeof(float) * n);
+  ix.h.ensure(ix.arena, sizeof(float) * (n + 32));
   ix.ynorm.ensure(ix.arena, sizeof(float) * n);
 
   // scratch: partials, flags, Gram, power-iteration work
@@ -417,18 +424,20 @@ void build_mixed_operands(Index& ix, int terms) {
   if (mo.terms == terms) return;
   const int d = ix.d;
   const int ka = terms == 1 ? ((d + 15) / 16) * 16 : ((3 * d + 15) / 16) * 16;
-  mo.cand.ensure(ix.arena, sizeof(uint16_t) * ix.n * ka + 256);
+  const int kb = (terms == 3 && d % 16 == 0) ? 2 * d : ka;
+  mo.cand.ensure(ix.arena, sizeof(uint16_t) * (ix.n + 32) * kb + 256);
   uint16_t* qself = nullptr;
   if (terms == 3) {
     mo.qself.ensure(ix.arena, sizeof(uint16_t) * ix.n * ka + 256);
     qself = mo.qself.as<uint16_t>();
   }
   const DeviceInfo& di = device_info(ix.arena.dev().device);
-  k_operands<<<grid_for(ix.n * ka, kThreads, 4 * di.cus * 8), kThreads, 0, ix.arena.stream()>>>(
-      ix.ys.as<float>(), ix.n, d, terms, ka, mo.cand.as<uint16_t>(), qself);
+  k_operands<<<grid_for((ix.n + 32) * ka, kThreads, 4 * di.cus * 8), kThreads, 0, ix.arena.stream()>>>(
+      ix.ys.as<float>(), ix.n, d, terms, ka, kb, mo.cand.as<uint16_t>(), qself);
   SNN_LAUNCH_CHECK();
   mo.terms = terms;
   mo.ka = ka;
+  mo.kb = kb;
 }
 
 }  // namespace snn

@@ -89,9 +89,10 @@ int fp64_blocks_per_cu(int dp);
 struct MixedDev {
   const uint16_t* qop;  // m x KA bf16: query operand rows (score order)
   const float* cthr;    // m: per-query accumulator start C_q
-  const uint16_t* cop;  // n x KA bf16: candidate operand rows (score order)
-  const float* h;       // n: fl32(||y_j||^2 / 2)
-  int KA;
+  const uint16_t* cop;  // (n + 32) x KB bf16: candidate operand rows (score order)
+  const float* h;       // n + 32: fl32(||y_j||^2 / 2), padding +inf
+  int KA;               // query operand row length = product chain length
+  int KB;               // candidate row length: KA, or 2 KA / 3 for the split layout
 };
 struct MixedBound {
   double r2p_half;  // R2' / 2
@@ -107,7 +108,7 @@ double mixed_c_rep(int terms);
 MixedBound mixed_bound(int terms, int KA, int d, double R2, double Y);
 int mixed_max_slices();
 int mixed_queries_per_wave();
-int mixed_blocks_per_cu(int KA);
+int mixed_blocks_per_cu(int KA, int KB);
 void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, int terms, int KA,
                         const MixedBound& b, uint16_t* qop, float* cthr, hipStream_t s);
 void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* cthr, hipStream_t s);

@@ -348,6 +348,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     MixedOperands& mo = ix.mixed[terms == 1 ? 0 : 1];
     const MixedBound mb = mixed_bound(terms, mo.ka, d, R2, Y);
     mx.KA = mo.ka;
+    mx.KB = mo.kb;
     mx.cop = mo.cand.as<uint16_t>();
     mx.h = ix.h.as<float>();
     mx.cthr = P.cthr;
@@ -386,7 +387,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       launch_fill_u64(&P.ctl->survivors, 1, 0ull, s);
       launch_fill_i32(P.row_cnt, m, 0, s);
     }
-    const int per_cu = prec == SNN_PREC_MIXED ? mixed_blocks_per_cu(mx.KA) : fp64_blocks_per_cu(ix.dp);
+    const int per_cu = prec == SNN_PREC_MIXED ? mixed_blocks_per_cu(mx.KA, mx.KB) : fp64_blocks_per_cu(ix.dp);
     const int grid = std::max(di.xcds, (di.cus * per_cu / di.xcds) * di.xcds);
     if (st) SNN_HIP(hipEventRecord(ev[1], s));
     if (m > 0) {

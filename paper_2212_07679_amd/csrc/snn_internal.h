@@ -65,8 +65,9 @@ const DeviceInfo& device_info(int device);
 // Everything lives in sorted (score) order unless noted.
 struct MixedOperands {
   int terms = 0;     // 1 or 3
-  int ka = 0;        // packed bf16 length per row (multiple of 16)
-  Buffer cand;       // n x ka bf16: candidate operand rows
+  int ka = 0;        // query operand row length in bf16 (multiple of 16)
+  int kb = 0;        // candidate row length: ka, or 2 ka / 3 when the rows are [hi | lo]
+  Buffer cand;       // (n + 32) x kb bf16: candidate operand rows, zero padding rows
   Buffer qself;      // n x ka bf16: query operand rows for self-queries
 };
 
@@ -85,7 +86,7 @@ struct Index {
   Buffer po;    // n x d input dtype: original rows, sorted
   Buffer p64;   // n x dp doubles: original rows, sorted, zero-padded
   Buffer ys;    // n x d floats: fl32(p - mu), sorted
-  Buffer h;     // n floats: ||ys||^2 / 2 rounded to nearest, sorted
+  Buffer h;     // n + 32 floats: ||ys||^2 / 2 rounded to nearest, sorted; padding +inf
   Buffer ynorm; // n floats: ||ys|| rounded up, sorted
   MixedOperands mixed[2];  // [0]: terms = 1, [1]: terms = 3
 
