@@ -42,8 +42,9 @@ __global__ __launch_bounds__(kThreads) void k_cand_fp64_reg(QueryDev q) {
     __syncthreads();
     const int64_t u = uniform_i64(s_unit);
     if (u < 0) break;
-    const int tile = uniform_i32(unit_tile(q, u));
-    const int64_t c = u - q.unit_off[tile];
+    int tile;
+    int64_t c;
+    if (!decode_unit(q, u, tile, c)) continue;
     const int64_t q0 = (int64_t)tile * q.T;
     const int qn = (int)min((int64_t)q.T, q.m - q0);
     const int64_t j0 = q.tlo[tile] + c * q.CH;
@@ -86,8 +87,9 @@ __global__ __launch_bounds__(kThreads) void k_cand_fp64_big(QueryDev q, int dp) 
     __syncthreads();
     const int64_t u = uniform_i64(s_unit);
     if (u < 0) break;
-    const int tile = uniform_i32(unit_tile(q, u));
-    const int64_t c = u - q.unit_off[tile];
+    int tile;
+    int64_t c;
+    if (!decode_unit(q, u, tile, c)) continue;
     const int64_t q0 = (int64_t)tile * q.T;
     const int qn = (int)min((int64_t)q.T, q.m - q0);
     const int64_t j0 = q.tlo[tile] + c * q.CH;

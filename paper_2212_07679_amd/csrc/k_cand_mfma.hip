@@ -103,22 +103,34 @@ __global__ __launch_bounds__(kThreads) void k_mixed_qprep(const double* __restri
                                                          float* __restrict__ cthr) {
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x) {
     const double* q = q64 + s * dp;
-    uint16_t* o = qop + s * KA;
+    uint4* o = reinterpret_cast<uint4*>(qop + s * KA);
     double nn = 0.0;
     for (int k = 0; k < d; ++k) {
       const float y = (float)(q[k] - mu[k]);
       nn += (double)y * (double)y;
-      const uint16_t hi = f32_to_bf16_rne(y);
-      if (terms == 1) {
-        o[k] = hi;
-      } else {
-        const uint16_t lo = f32_to_bf16_rne(y - bf16_to_f32(hi));
-        o[k] = hi;
-        o[d + k] = hi;
-        o[2 * d + k] = lo;
-      }
     }
-    for (int k = terms * d; k < KA; ++k) o[k] = 0;
+    // row [bf16(y)] or [hi | hi | lo], written 8 values (16 bytes) at a time
+    for (int c = 0; c < KA / 8; ++c) {
+      uint32_t w[4];
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        uint32_t pr = 0;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int k = 8 * c + e + t;
+          uint16_t v = 0;
+          if (k < terms * d) {
+            const int seg = k / d, cc = k % d;
+            const float y = (float)(q[cc] - mu[cc]);
+            const uint16_t hi = f32_to_bf16_rne(y);
+            v = (seg == 2) ? f32_to_bf16_rne(y - bf16_to_f32(hi)) : hi;
+          }
+          pr |= (uint32_t)v << (16 * t);
+        }
+        w[e / 2] = pr;
+      }
+      o[c] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
     const double nq = sqrt(nn) * (1.0 + 1e-15);
     cthr[s] = threshold(b, 0.5 * nn, nq);
   }
@@ -147,11 +159,21 @@ __device__ __forceinline__ float max16(const f32x16& a) {
   return fmaxf(m0, m3);
 }
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format
+
+// Operands of step `it` through buffer resources whose base is the unit's
+// first 32-row block: the lane offset is fixed and the step offset is a
+// scalar, so no per-step vector address arithmetic exists.  Reads past the
+// unit (the look-ahead of the last step) are outside num_records and return
+// zeros without touching memory.
 template <int NL>
-__device__ __forceinline__ void load_step(bf16x8 (&B)[NL], float& h, const bf16x8* p, const float* hp) {
+__device__ __forceinline__ void load_step(bf16x8 (&B)[NL], float& h, __amdgpu_buffer_rsrc_t rc,
+                                          __amdgpu_buffer_rsrc_t rh, int voff_c, int voff_h, int it) {
 #pragma unroll
-  for (int s = 0; s < NL; ++s) B[s] = p[2 * s];
-  h = *hp;
+  for (int s = 0; s < NL; ++s)  // slices are 1 KB apart in a 32-row block
+    B[s] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rc, voff_c, it * (NL * 1024) + s * 1024, 0));
+  h = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rh, voff_h, it * 128, 0));
 }
 
 // One 32-candidate step for QB blocks of 32 queries: the matrix products,
@@ -209,8 +231,9 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
     __syncthreads();
     const int64_t u = uniform_i64(s_unit);
     if (u < 0) break;
-    const int tile = uniform_i32(unit_tile(q, u));
-    const int64_t c = u - q.unit_off[tile];
+    int tile;
+    int64_t c;
+    if (!decode_unit(q, u, tile, c)) continue;
     const int64_t q0 = (int64_t)tile * q.T + (int64_t)wave * 32 * QB;
     const int64_t j0 = q.tlo[tile] + c * q.CH;
     const int64_t j1 = min(j0 + q.CH, (int64_t)q.thi[tile]);
@@ -236,32 +259,28 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
       }
     }
 
-    // Candidate rows j0 + 32*it + l32, KB bf16 apart (for the split layout a
-    // row is [hi | lo] and the third operand slice reuses hi).  The operand
-    // and h arrays carry 32 padding rows past n, so the ragged last step
-    // reads in bounds; lanes past j1 are masked by h = +inf.  Two register
-    // sets alternate, so the next step's operands load while this step's
-    // matrix products run.
+    // Candidate rows j0 + 32*it + l32 (for the split layout a row is
+    // [hi | lo] and the third operand slice reuses hi).  j0 is a multiple of
+    // 32 (tile windows are aligned), so step `it` is one 32-row block of the
+    // operand array and lane l reads 16 bytes at l * 16 of each 1 KB slice.
+    // Lanes past j1 are masked by h = +inf.  Two register sets alternate, so
+    // the next step's operands load while this step's products run.
     const int span = (int)(j1 - j0);
     const int nsteps = (span + 31) / 32;
-    const bf16x8* pb = reinterpret_cast<const bf16x8*>(x.cop + (j0 + l32) * x.KB + 8 * half);
-    const float* hp = x.h + j0 + l32;
-    const int stride = 32 * x.KB / 8;  // one step in bf16x8 units
-    // The look-ahead loads are unconditional (past the last step they re-read
-    // the current rows), so no branch separates a load from its use and the
-    // waits stay exact.
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(reinterpret_cast<const char*>(x.cop) + (j0 / 32) * (NL * 1024)), (short)0, nsteps * NL * 1024,
+        kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rh =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(x.h + j0), (short)0, nsteps * 128, kRsrcWord3);
+    const int voff_c = lane * 16, voff_h = l32 * 4;
     bf16x8 B0[NL], B1[NL];
     float h0, h1;
-    load_step<NL>(B0, h0, pb, hp);
+    load_step<NL>(B0, h0, rc, rh, voff_c, voff_h, 0);
     for (int it = 0; it < nsteps; it += 2) {
-      const int a1 = it + 1 < nsteps ? 1 : 0;
-      load_step<NL>(B1, h1, pb + a1 * stride, hp + a1 * 32);
+      load_step<NL>(B1, h1, rc, rh, voff_c, voff_h, it + 1);
       screen_step<NS, QB, NL>(A, Cin, B0, h0, it * 32 + l32, span, (int)j0, q0, half, st, q.sink);
-      if (!a1) break;
-      const int a2 = it + 2 < nsteps ? 2 : 1;
-      pb += a2 * stride;
-      hp += a2 * 32;
-      load_step<NL>(B0, h0, pb, hp);
+      if (it + 1 >= nsteps) break;
+      load_step<NL>(B0, h0, rc, rh, voff_c, voff_h, it + 2);
       screen_step<NS, QB, NL>(A, Cin, B1, h1, (it + 1) * 32 + l32, span, (int)j0, q0, half, st, q.sink);
     }
   }
@@ -270,11 +289,17 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
 
 typedef void (*MixedKernel)(QueryDev, MixedDev);
 
+// Query blocks of 32 per wavefront: every candidate load feeds QB product
+// chains, so more blocks mean fewer candidate bytes through the vector
+// memory return path per matrix product.  Short chains (NS <= 4) afford four
+// blocks within the register file, longer ones two.
+constexpr int qb_for(int ns) { return ns <= 4 ? 4 : 2; }
+
 // (slices per product chain, slices loaded per candidate row)
 MixedKernel pick_kernel(int KA, int KB) {
   const int ns = KA / 16, nl = KB / 16;
 #define SNN_CASE(NS_, NL_) \
-  if (ns == NS_ && nl == NL_) return k_cand_mfma<NS_, 2, NL_>;
+  if (ns == NS_ && nl == NL_) return k_cand_mfma<NS_, qb_for(NS_), NL_>;
   SNN_CASE(1, 1) SNN_CASE(2, 2) SNN_CASE(3, 3) SNN_CASE(3, 2) SNN_CASE(4, 4) SNN_CASE(5, 5)
   SNN_CASE(6, 6) SNN_CASE(6, 4) SNN_CASE(7, 7) SNN_CASE(8, 8)
 #undef SNN_CASE
@@ -289,7 +314,7 @@ int grid_for(int64_t work, int cap) {
 }  // namespace
 
 int mixed_max_slices() { return 8; }
-int mixed_queries_per_wave() { return 64; }
+int mixed_queries_per_wave(int KA) { return 32 * qb_for(KA / 16); }
 
 int mixed_blocks_per_cu(int KA, int KB) {
   MixedKernel k = pick_kernel(KA, KB);

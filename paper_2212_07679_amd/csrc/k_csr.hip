@@ -252,11 +252,17 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 
 __global__ __launch_bounds__(kThreads) void k_row_max(const int32_t* __restrict__ cnt, int64_t m,
                                                       unsigned long long* __restrict__ out) {
+  __shared__ int red[kThreads / kWave];
   int v = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
     v = max(v, cnt[i]);
   v = wave_max(v);
-  if (lane_id() == 0 && v > 0) atomicMax(out, (unsigned long long)v);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / kWave; ++w) v = max(v, red[w]);
+    if (v > 0) atomicMax(out, (unsigned long long)v);
+  }
 }
 
 __global__ void k_self_qnorm(const float* __restrict__ ynorm, int64_t n, double* __restrict__ out) {
@@ -273,7 +279,7 @@ int grid_for(int64_t work, int cap) {
 
 void launch_row_max(const int32_t* row_cnt, int64_t m, unsigned long long* out, hipStream_t s) {
   if (m <= 0) return;
-  k_row_max<<<grid_for(m, 1024), kThreads, 0, s>>>(row_cnt, m, out);
+  k_row_max<<<grid_for(m, 256), kThreads, 0, s>>>(row_cnt, m, out);
   SNN_LAUNCH_CHECK();
 }
 

@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, in
                                                     int32_t* __restrict__ perm, T* __restrict__ po,
                                                     double* __restrict__ p64, float* __restrict__ ys,
                                                     float* __restrict__ h, float* __restrict__ ynorm) {
-  if (blockIdx.x == 0 && threadIdx.x < 32) h[n + threadIdx.x] = INFINITY;  // padding rows
+  if (blockIdx.x == 0 && threadIdx.x < 64) h[n + threadIdx.x] = INFINITY;  // padding rows
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t i = val[s];
     perm[s] = (int32_t)i;
@@ -281,11 +281,18 @@ __global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, in
 // with hi = bf16(y), lo = bf16(y - hi) (y - hi is exact in float).  When d is
 // a multiple of 16 the candidate rows are stored as [hi | lo] (kb = 2d): the
 // third segment equals the first and the screen reuses its registers.
-// Rows n .. n+31 of the candidate array are zero padding.
-__global__ __launch_bounds__(kThreads) void k_operands(const float* __restrict__ ys, int64_t n, int d, int terms,
-                                                      int ka, int kb, uint16_t* __restrict__ cand,
+//
+// Candidate rows are stored in the matrix-core operand order: blocks of 32
+// rows, and inside a block [slice s of 16][half h of 8][row r][8 values], so
+// that one wavefront load of 16 bytes per lane (lane = 32 h + r) reads 1 KB
+// of contiguous memory.  npad (a multiple of 32, at least n + 32) rows are
+// stored; rows n .. npad-1 are zero.  Query rows for self-queries stay
+// row-major (ka per row).
+__global__ __launch_bounds__(kThreads) void k_operands(const float* __restrict__ ys, int64_t n, int64_t npad, int d,
+                                                      int terms, int ka, int kb, uint16_t* __restrict__ cand,
                                                       uint16_t* __restrict__ qself) {
-  const int64_t total = (n + 32) * (int64_t)ka;
+  const int64_t total = npad * (int64_t)ka;
+  const int nl = kb / 16;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t s = e / ka;
     const int k = (int)(e % ka);
@@ -302,7 +309,11 @@ __global__ __launch_bounds__(kThreads) void k_operands(const float* __restrict__
         qv = (seg == 2) ? lo : hi;
       }
     }
-    if (k < kb) cand[s * kb + k] = cv;
+    if (k < kb) {
+      const int64_t blk = s / 32;
+      const int r = (int)(s % 32), sl = k / 16, hh = (k % 16) / 8, el = k % 8;
+      cand[((blk * nl + sl) * 2 + hh) * 256 + r * 8 + el] = cv;
+    }
     if (qself && s < n) qself[e] = qv;
   }
 }
@@ -326,7 +337,7 @@ void build_index_t(Index& ix, const T* X) {
   ix.po.ensure(ix.arena, sizeof(T) * n * d);
   ix.p64.ensure(ix.arena, sizeof(double) * n * ix.dp);
   ix.ys.ensure(ix.arena, sizeof(float) * n * d);
-  ix.h.ensure(ix.arena, sizeof(float) * (n + 32));
+  ix.h.ensure(ix.arena, sizeof(float) * (n + 64));
   ix.ynorm.ensure(ix.arena, sizeof(float) * n);
 
   // scratch: partials, flags, Gram, power-iteration work
@@ -425,15 +436,12 @@ void build_mixed_operands(Index& ix, int terms) {
   const int d = ix.d;
   const int ka = terms == 1 ? ((d + 15) / 16) * 16 : ((3 * d + 15) / 16) * 16;
   const int kb = (terms == 3 && d % 16 == 0) ? 2 * d : ka;
-  mo.cand.ensure(ix.arena, sizeof(uint16_t) * (ix.n + 32) * kb + 256);
-  uint16_t* qself = nullptr;
-  if (terms == 3) {
-    mo.qself.ensure(ix.arena, sizeof(uint16_t) * ix.n * ka + 256);
-    qself = mo.qself.as<uint16_t>();
-  }
+  const int64_t npad = ((ix.n + 32 + 31) / 32) * 32;
+  mo.cand.ensure(ix.arena, sizeof(uint16_t) * npad * kb + 256);
+  mo.qself.ensure(ix.arena, sizeof(uint16_t) * ix.n * ka + 256);
   const DeviceInfo& di = device_info(ix.arena.dev().device);
-  k_operands<<<grid_for((ix.n + 32) * ka, kThreads, 4 * di.cus * 8), kThreads, 0, ix.arena.stream()>>>(
-      ix.ys.as<float>(), ix.n, d, terms, ka, kb, mo.cand.as<uint16_t>(), qself);
+  k_operands<<<grid_for(npad * ka, kThreads, 4 * di.cus * 8), kThreads, 0, ix.arena.stream()>>>(
+      ix.ys.as<float>(), ix.n, npad, d, terms, ka, kb, mo.cand.as<uint16_t>(), mo.qself.as<uint16_t>());
   SNN_LAUNCH_CHECK();
   mo.terms = terms;
   mo.ka = ka;

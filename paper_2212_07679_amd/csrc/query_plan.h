@@ -13,9 +13,17 @@ namespace snn {
 
 constexpr int kMaxXcd = 8;
 
-// Work unit u covers tile t = the tile with unit_off[t] <= u < unit_off[t+1]
-// and candidates [tlo[t] + c*CH, min(tlo[t] + (c+1)*CH, thi[t])) with
-// c = u - unit_off[t].  Tile t holds sorted queries [t*T, min((t+1)*T, m)).
+// Tile t holds score-ordered queries [t*T, min((t+1)*T, m)) and the union
+// window [tlo[t], thi[t]); chunk c of the tile is the candidates
+// [tlo + c*CH, min(tlo + (c+1)*CH, thi)), units[t] chunks in all.
+//
+// Work units are ordered chunk-major inside groups of G consecutive tiles:
+// unit u of group g (group_off[g] <= u < group_off[g+1]) is chunk
+// c = l / Gg of tile t = g*G + l % Gg, with l = u - group_off[g] and Gg the
+// tiles in the group.  Score-adjacent tiles have nearly the same window, so
+// the units that run at the same time on one XCD read the same candidate
+// rows from its L2.  A group reserves (max units of its tiles) x Gg units;
+// (t, c) with c >= units[t] is empty.
 struct QueryDev {
   int64_t m;
   int d;
@@ -23,6 +31,8 @@ struct QueryDev {
   int T;   // queries per tile (multiple of 64)
   int CH;  // candidates per work unit
   int ntiles;
+  int G;        // tiles per group
+  int ngroups;
   double R2;  // fl64(R*R)
   const double* q64;     // m x dp: query rows in float64, score order
   const int32_t* qorig;  // m: score-order position -> caller's query row
@@ -30,7 +40,8 @@ struct QueryDev {
   const int32_t* perm;   // n: score-order position -> original data row
   const int32_t* tlo;    // ntiles
   const int32_t* thi;    // ntiles
-  const int64_t* unit_off;       // ntiles + 1
+  const int32_t* units;          // ntiles
+  const int64_t* group_off;      // ngroups + 1
   unsigned long long* counters;  // kMaxXcd work counters (zeroed per call)
   int nxcd;
   PairSink sink;
@@ -47,7 +58,7 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t x) {
 // of units (so blocks sharing an L2 work on neighbouring tiles); when its
 // range is exhausted the block steals from the other ranges.  -1 when done.
 __device__ __forceinline__ int64_t next_unit(const QueryDev& q, int xcd) {
-  const int64_t total = q.unit_off[q.ntiles];
+  const int64_t total = q.group_off[q.ngroups];
   for (int k = 0; k < q.nxcd; ++k) {
     const int x = (xcd + k) % q.nxcd;
     const int64_t beg = total * x / q.nxcd, end = total * (x + 1) / q.nxcd;
@@ -58,28 +69,40 @@ __device__ __forceinline__ int64_t next_unit(const QueryDev& q, int xcd) {
   return -1;
 }
 
-// tile of unit u (binary search over unit_off)
-__device__ __forceinline__ int unit_tile(const QueryDev& q, int64_t u) {
-  int lo = 0, hi = q.ntiles - 1;
+// (tile, chunk) of unit u; false for an empty unit.  Results are
+// wavefront-uniform.
+__device__ __forceinline__ bool decode_unit(const QueryDev& q, int64_t u, int& tile, int64_t& chunk) {
+  int lo = 0, hi = q.ngroups - 1;
   while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (q.unit_off[mid] <= u)
+    const int mid = (lo + hi + 1) >> 1;
+    if (q.group_off[mid] <= u)
       lo = mid;
     else
       hi = mid - 1;
   }
-  return lo;
+  const int gg = min(q.G, q.ntiles - lo * q.G);
+  const int64_t l = u - q.group_off[lo];
+  chunk = uniform_i64(l / gg);
+  tile = uniform_i32(lo * q.G + (int)(l % gg));
+  return chunk < q.units[tile];
 }
 
 // ---------------------------------------------------------------- launchers
+int query_buckets(int64_t m);
 void launch_query_keys(snn_dtype dt, const void* Q, int64_t m, int d, const double* mu, const double* v,
-                       uint32_t* ukey, uint32_t* val, double* qalpha, double* qnorm, int* bad, hipStream_t s);
-void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, const uint32_t* qperm,
-                         const double* qalpha_in, const double* qnorm_in, double* q64, int32_t* qorig,
-                         double* qalpha, double* qnorm, hipStream_t s);
+                       const double* key, int n, int K, uint32_t* bucket, uint32_t* slot, uint32_t* hist,
+                       double* qalpha, double* qnorm, int* bad, hipStream_t s);
+void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, const uint32_t* bucket,
+                         const uint32_t* slot, const uint32_t* boff, const double* qalpha_in, const double* qnorm_in,
+                         double* q64, int32_t* qorig, double* qalpha, double* qnorm, hipStream_t s);
+// align: tile windows are widened outward to multiples of `align` rows (the
+// mixed screen reads 32-row blocks); extra candidates never change results.
 void launch_windows(const double* key, int n, const double* qalpha, const double* qnorm, int64_t m, double w_base,
-                    double eps_scale, int T, int CH, int ntiles, int32_t* lo, int32_t* hi, int32_t* tlo,
+                    double eps_scale, int T, int CH, int align, int ntiles, int32_t* lo, int32_t* hi, int32_t* tlo,
                     int32_t* thi, int32_t* units, unsigned long long* pairs_window, hipStream_t s);
+
+// units reserved per group of G tiles: Gg x max units of its tiles
+void launch_group_units(const int32_t* units, int ntiles, int G, int32_t* gunits, hipStream_t s);
 
 // k_cand_fp64.hip: plain float64 screen (every window pair, normative rule)
 void launch_cand_fp64(const QueryDev& q, int grid, hipStream_t s);
@@ -107,7 +130,7 @@ struct MixedBound {
 double mixed_c_rep(int terms);
 MixedBound mixed_bound(int terms, int KA, int d, double R2, double Y);
 int mixed_max_slices();
-int mixed_queries_per_wave();
+int mixed_queries_per_wave(int KA);  // 32 x query blocks per wavefront
 int mixed_blocks_per_cu(int KA, int KB);
 void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, int terms, int KA,
                         const MixedBound& b, uint16_t* qop, float* cthr, hipStream_t s);

@@ -223,9 +223,10 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   if (prec == SNN_PREC_AUTO) prec = (mixed_ok && slack_of(terms) <= 4.0 * R2) ? SNN_PREC_MIXED : SNN_PREC_FP64;
   if (prec == SNN_PREC_MIXED && !mixed_ok)
     fail(SNN_ENOTSUP, "mixed screen: packed operand rows longer than 128 bf16 (lower d or use terms=1)");
-  if (prec == SNN_PREC_MIXED && o.tile_q && o.tile_q != 4 * mixed_queries_per_wave())
-    fail(SNN_EINVAL, "mixed screen: tile_q must be 256");
-  const int T = prec == SNN_PREC_MIXED ? 4 * mixed_queries_per_wave() : (o.tile_q ? o.tile_q : 64);
+  const int t_mixed = prec == SNN_PREC_MIXED ? 4 * mixed_queries_per_wave(ka_of(terms)) : 0;
+  if (prec == SNN_PREC_MIXED && o.tile_q && o.tile_q != t_mixed)
+    fail(SNN_EINVAL, "mixed screen: tile_q must be " + std::to_string(t_mixed) + " for this dimension");
+  const int T = prec == SNN_PREC_MIXED ? t_mixed : (o.tile_q ? o.tile_q : 64);
   const int CH = o.tile_c ? o.tile_c : (prec == SNN_PREC_MIXED ? 4096 : 1024);
   if (prec == SNN_PREC_MIXED && CH % 32 != 0) fail(SNN_EINVAL, "mixed screen: tile_c must be a multiple of 32");
   if (prec == SNN_PREC_MIXED) build_mixed_operands(ix, terms);
@@ -238,11 +239,13 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   }
 
   // ---- workspace
+  const int nbuckets = query_buckets(m);
   Carver probe(nullptr);
   auto plan_query = [&](Carver& c) {
     struct P {
       uint32_t* ukey;
       uint32_t* val;
+      uint32_t* hist;
       double* qa_in;
       double* qn_in;
       double* q64;
@@ -255,6 +258,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       int32_t* thi;
       int32_t* units;
       int64_t* unit_off;
+      int32_t* gunits;
       char* scan_scratch;
       Ctl* ctl;
       int32_t* row_cnt;
@@ -263,8 +267,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       float* cthr;
     } p;
     const size_t mq = self ? 1 : (size_t)m;
-    p.ukey = c.take<uint32_t>(mq);
-    p.val = c.take<uint32_t>(mq);
+    p.ukey = c.take<uint32_t>(mq);  // bucket of each query
+    p.val = c.take<uint32_t>(mq);   // slot of each query in its bucket
+    p.hist = c.take<uint32_t>(self ? 1 : nbuckets);
     p.qa_in = c.take<double>(mq);
     p.qn_in = c.take<double>(mq);
     p.q64 = c.take<double>(mq * ix.dp);
@@ -277,7 +282,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     p.thi = c.take<int32_t>(ntiles);
     p.units = c.take<int32_t>(ntiles);
     p.unit_off = c.take<int64_t>(ntiles + 1);
-    p.scan_scratch = c.take<char>(std::max(scan_scratch_bytes(ntiles), scan_scratch_bytes(std::max<int64_t>(m, 1))));
+    p.gunits = c.take<int32_t>(ntiles);
+    p.scan_scratch = c.take<char>(std::max({scan_scratch_bytes(ntiles), scan_scratch_bytes(std::max<int64_t>(m, 1)),
+                                            scan_scratch_bytes(nbuckets)}));
     p.ctl = c.take<Ctl>(1);
     p.row_cnt = c.take<int32_t>(std::max<int64_t>(m, 1));
     p.lists = c.take<int32_t>(2 * std::max<int64_t>(m, 1));
@@ -300,10 +307,13 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const double* qn;
   if (!self) {
     if (m > 0) {
-      launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), P.ukey, P.val, P.qa_in, P.qn_in,
-                        &P.ctl->bad, s);
-      radix_sort_pairs(ix.arena, P.ukey, P.val, m, 8, 32, s);
-      launch_query_gather(ix.dtype, Q, m, d, ix.dp, P.val, P.qa_in, P.qn_in, P.q64, P.qorig, P.qa, P.qn, s);
+      // queries into score order by a counting sort on a uniform score grid
+      launch_fill_i32(reinterpret_cast<int32_t*>(P.hist), nbuckets, 0, s);
+      launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), ix.key.as<double>(), (int)n,
+                        nbuckets, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, &P.ctl->bad, s);
+      exclusive_scan_u32(P.hist, nbuckets, P.scan_scratch, s);
+      launch_query_gather(ix.dtype, Q, m, d, ix.dp, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, P.q64, P.qorig, P.qa,
+                          P.qn, s);
     }
     q64 = P.q64;
     qorig = P.qorig;
@@ -321,11 +331,19 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const double u32 = std::ldexp(1.0, -24);
   const double w_base = R * ix.vnorm * (1.0 + 4.0 * gamma64(d + 3)) + ix.key_eps;
   const double eps_scale = 1.01 * (u32 + gamma64(d + 2)) * (1.0 + u32) * ix.vnorm;
-  launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, CH, ntiles, P.lo, P.hi, P.tlo,
+  launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, CH,
+                 prec == SNN_PREC_MIXED ? 32 : 1, ntiles, P.lo, P.hi, P.tlo,
                  P.thi, P.units, &P.ctl->pairs_window, s);
-  exclusive_scan_i32_to_i64(P.units, P.unit_off, ntiles, P.scan_scratch, s);
+  // chunk-major work order inside groups of G score-adjacent tiles (L2 reuse)
+  const int G = prec == SNN_PREC_MIXED ? 8 : 16;
+  const int ngroups = (ntiles + G - 1) / G;
+  launch_group_units(P.units, ntiles, G, P.gunits, s);
+  exclusive_scan_i32_to_i64(P.gunits, P.unit_off, ngroups, P.scan_scratch, s);
 
   QueryDev qd{};
+  qd.G = G;
+  qd.ngroups = ngroups;
+  qd.units = P.units;
   qd.m = m;
   qd.d = d;
   qd.dp = ix.dp;
@@ -339,7 +357,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   qd.perm = ix.perm.as<int32_t>();
   qd.tlo = P.tlo;
   qd.thi = P.thi;
-  qd.unit_off = P.unit_off;
+  qd.group_off = P.unit_off;
   qd.counters = P.ctl->counters;
   qd.nxcd = di.xcds;
 
@@ -353,7 +371,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     mx.h = ix.h.as<float>();
     mx.cthr = P.cthr;
     if (self) {
-      mx.qop = (terms == 1 ? mo.cand : mo.qself).as<uint16_t>();
+      mx.qop = mo.qself.as<uint16_t>();
       launch_mixed_qprep_self(ix.ys.as<float>(), n, d, mb, P.cthr, s);
     } else {
       mx.qop = P.qop;
@@ -397,7 +415,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
         launch_cand_fp64(qd, grid, s);
     }
     if (st) SNN_HIP(hipEventRecord(ev[2], s));
-    launch_recheck(qd, sv, P.row_cnt, di.cus * 8, s);
+    launch_recheck(qd, sv, P.row_cnt, di.cus * 2, s);
     exclusive_scan_i32_to_i64(P.row_cnt, out->row_ptr, m, P.scan_scratch, s);
     launch_row_max(P.row_cnt, m, &P.ctl->row_max, s);
     SNN_HIP(hipMemcpyAsync(&hc.ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
