@@ -59,8 +59,12 @@ typedef enum { SNN_F32 = 0, SNN_F64 = 1 } snn_dtype;
  *        fp32 accumulation) against a rigorous rounding bound; only pairs
  *        the screen cannot reject are re-decided by the normative rule in
  *        float64 (the "precision form").
- * AUTO:  the library picks. */
-typedef enum { SNN_PREC_FP64 = 0, SNN_PREC_MIXED = 1, SNN_PREC_AUTO = 2 } snn_precision;
+ * FP32:  the same screen with fp32 operands on the vector ALUs (d <= 16):
+ *        a much narrower rounding band, for low dimensions with a radius
+ *        that is small against the data's extent.
+ * AUTO:  the library picks from the width of each screen's rounding band
+ *        relative to R^2 and from d. */
+typedef enum { SNN_PREC_FP64 = 0, SNN_PREC_MIXED = 1, SNN_PREC_AUTO = 2, SNN_PREC_FP32 = 3 } snn_precision;
 
 typedef struct {
   /* Device allocator; both NULL selects hipMalloc/hipFree.  alloc returns

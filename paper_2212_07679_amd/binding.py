@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libsnn.so")
 
 SNN_OK, SNN_EINVAL, SNN_ENOMEM, SNN_EDEVICE, SNN_EOVERFLOW, SNN_ENOTSUP = 0, -1, -2, -3, -4, -5
 SNN_F32, SNN_F64 = 0, 1
-PRECISION = {"fp64": 0, "mixed": 1, "auto": 2}
+PRECISION = {"fp64": 0, "mixed": 1, "auto": 2, "fp32": 3}
+PRECISION_NAMES = {v: k for k, v in PRECISION.items()}
 
 STATUS_NAMES = {
     SNN_OK: "SNN_OK",

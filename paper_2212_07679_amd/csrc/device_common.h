@@ -134,6 +134,21 @@ __device__ __forceinline__ void stage_push_wave(PairStage<kStage>& st, const Pai
   }
 }
 
+// Moves the staged pairs to the global list and empties the stage.  All
+// threads of the block call it right after a __syncthreads(), with no push in
+// flight; the caller's next barrier orders the reset before new pushes.
+template <int kStage>
+__device__ __forceinline__ void stage_drain(PairStage<kStage>& st, const PairSink& sink) {
+  const int cnt = st.count < kStage ? st.count : kStage;
+  if (cnt == 0) return;  // block-uniform: every thread read the same value after the barrier
+  if (threadIdx.x == 0) st.base = (long long)sink_reserve(sink, (unsigned long long)cnt);
+  __syncthreads();
+  const long long base = st.base;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) sink_store(sink, base + i, st.buf[i]);
+  __syncthreads();
+  if (threadIdx.x == 0) st.count = 0;
+}
+
 // Must be called by all threads of the block after the last push.
 template <int kStage>
 __device__ __forceinline__ void stage_flush(PairStage<kStage>& st, const PairSink& sink) {

@@ -38,6 +38,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_fp64_reg(QueryDev q) {
   const int xcd = blockIdx.x % q.nxcd;
   for (;;) {
     __syncthreads();
+    stage_drain(st, q.sink);
     if (threadIdx.x == 0) s_unit = next_unit(q, xcd);
     __syncthreads();
     const int64_t u = uniform_i64(s_unit);
@@ -83,6 +84,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_fp64_big(QueryDev q, int dp) 
   const int xcd = blockIdx.x % q.nxcd;
   for (;;) {
     __syncthreads();
+    stage_drain(st, q.sink);
     if (threadIdx.x == 0) s_unit = next_unit(q, xcd);
     __syncthreads();
     const int64_t u = uniform_i64(s_unit);

@@ -55,6 +55,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 double mixed_c_rep(int terms) {
   const double ub = std::ldexp(1.0, -8);
+  if (terms == 0) return 0.0;  // fp32 operands are the centred values themselves
   return 1.01 * (terms == 1 ? ub * (2.0 + ub) : ub * ub * (3.0 + 3.0 * ub));
 }
 
@@ -80,21 +81,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 constexpr int kStage = 2048;
-
-__device__ __forceinline__ float round_up_f32(double c) {
-  float f = (float)c;
-  if ((double)f < c) f = nextafterf(f, INFINITY);
-  return f;
-}
-
-__device__ __forceinline__ float threshold(const MixedBound& b, double hq, double nq) {
-  const double eta = b.u32p * (b.Y + nq);
-  const double hlo = hq * (1.0 - b.g64);
-  double c0 = b.r2p_half - hlo + eta * b.sqrt_r2p + 0.5 * eta * eta + b.c_rep * b.Y * nq + b.e_h;
-  c0 += 8.0 * 1.1102230246251565e-16 * (b.r2p_half + hq + b.Y * nq) + 1e-30;
-  const double e_acc = b.g_acc * (1.02 * b.Y * nq + fabs(c0)) * 1.01;
-  return round_up_f32(c0 + e_acc);
-}
 
 // Out-of-sample queries: operands and thresholds from the float64 rows.
 __global__ __launch_bounds__(kThreads) void k_mixed_qprep(const double* __restrict__ q64, int64_t m, int d, int dp,
@@ -132,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void k_mixed_qprep(const double* __restri
       o[c] = make_uint4(w[0], w[1], w[2], w[3]);
     }
     const double nq = sqrt(nn) * (1.0 + 1e-15);
-    cthr[s] = threshold(b, 0.5 * nn, nq);
+    cthr[s] = screen_threshold(b, 0.5 * nn, nq);
   }
 }
 
@@ -144,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_mixed_qprep_self(const float* __re
     double nn = 0.0;
     for (int k = 0; k < d; ++k) nn += (double)y[k] * (double)y[k];
     const double nq = sqrt(nn) * (1.0 + 1e-15);
-    cthr[s] = threshold(b, 0.5 * nn, nq);
+    cthr[s] = screen_threshold(b, 0.5 * nn, nq);
   }
 }
 
@@ -227,6 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
   const int KA = x.KA;
   for (;;) {
     __syncthreads();
+    stage_drain(st, q.sink);
     if (threadIdx.x == 0) s_unit = next_unit(q, xcd);
     __syncthreads();
     const int64_t u = uniform_i64(s_unit);

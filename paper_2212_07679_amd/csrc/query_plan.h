@@ -127,8 +127,26 @@ struct MixedBound {
   double e_h;       // rounding of h_j to fp32
   double g64;       // gamma64_{d+1}: relative error of h_q in float64
 };
-double mixed_c_rep(int terms);
+double mixed_c_rep(int terms);  // terms = 0: exact fp32 operands (no representation error)
 MixedBound mixed_bound(int terms, int KA, int d, double R2, double Y);
+
+__device__ __forceinline__ float round_up_f32(double c) {
+  float f = (float)c;
+  if ((double)f < c) f = nextafterf(f, INFINITY);
+  return f;
+}
+
+// Accumulator start C_q of a screen (see k_cand_mfma.hip): every pair with
+// S(p_j, q) <= fl(R*R) satisfies (screen value) >= fl32(h_j).  hq = ||y_q||^2/2
+// and nq >= ||y_q|| in float64.
+__device__ __forceinline__ float screen_threshold(const MixedBound& b, double hq, double nq) {
+  const double eta = b.u32p * (b.Y + nq);
+  const double hlo = hq * (1.0 - b.g64);
+  double c0 = b.r2p_half - hlo + eta * b.sqrt_r2p + 0.5 * eta * eta + b.c_rep * b.Y * nq + b.e_h;
+  c0 += 8.0 * 1.1102230246251565e-16 * (b.r2p_half + hq + b.Y * nq) + 1e-30;
+  const double e_acc = b.g_acc * (1.02 * b.Y * nq + fabs(c0)) * 1.01;
+  return round_up_f32(c0 + e_acc);
+}
 int mixed_max_slices();
 int mixed_queries_per_wave(int KA);  // 32 x query blocks per wavefront
 int mixed_blocks_per_cu(int KA, int KB);
@@ -136,6 +154,17 @@ void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const doubl
                         const MixedBound& b, uint16_t* qop, float* cthr, hipStream_t s);
 void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* cthr, hipStream_t s);
 void launch_cand_mfma(const QueryDev& q, const MixedDev& x, int grid, hipStream_t s);
+
+// k_cand_valu.hip: fp32 vector screen for d <= 16
+int valu_max_d();
+int valu_row_floats(int d);
+int valu_queries_per_tile();
+int valu_blocks_per_cu(int d);
+void launch_valu_operands(const float* ys, const float* h, int64_t n, int d, float* vc, hipStream_t s);
+void launch_valu_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, const MixedBound& b, float* vq,
+                       hipStream_t s);
+void launch_valu_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* vq, hipStream_t s);
+void launch_cand_valu(const QueryDev& q, const float* vq, const float* vc, int grid, hipStream_t s);
 
 // k_csr.hip
 struct Survivors {

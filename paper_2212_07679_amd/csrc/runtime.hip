@@ -184,6 +184,13 @@ struct Carver {
 }  // namespace
 
 // ------------------------------------------------------------------------ query
+static void build_valu_operands(Index& ix) {
+  if (ix.vcand_built) return;
+  ix.vcand.ensure(ix.arena, sizeof(float) * (ix.n + 8) * valu_row_floats(ix.d) + 256);
+  launch_valu_operands(ix.ys.as<float>(), ix.h.as<float>(), ix.n, ix.d, ix.vcand.as<float>(), ix.arena.stream());
+  ix.vcand_built = true;
+}
+
 static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, const snn_options* opts,
                       snn_csr* out, snn_stats* st) {
   if (!out) fail(SNN_EINVAL, "out is NULL");
@@ -197,7 +204,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   snn_options o{};
   o.precision = SNN_PREC_AUTO;
   if (opts) o = *opts;
-  if (o.precision != SNN_PREC_FP64 && o.precision != SNN_PREC_MIXED && o.precision != SNN_PREC_AUTO)
+  if (o.precision != SNN_PREC_FP64 && o.precision != SNN_PREC_MIXED && o.precision != SNN_PREC_AUTO &&
+      o.precision != SNN_PREC_FP32)
     fail(SNN_EINVAL, "unknown precision");
   if (o.mixed_terms != 0 && o.mixed_terms != 1 && o.mixed_terms != 3) fail(SNN_EINVAL, "mixed_terms must be 0, 1 or 3");
   if (o.tile_q < 0 || o.tile_c < 0) fail(SNN_EINVAL, "tile sizes must be >= 0");
@@ -211,25 +219,50 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const double R2 = R * R;
 
   // ---- precision plan
-  // The mixed screen passes every pair whose decomposed distance is within
-  // about 2 * slack of R^2; it pays off when that band is narrow.
+  // A screen passes every pair whose decomposed distance is within about
+  // band(t) = 2 c_rep(t) Y^2 of R^2 (Y = max ||y||), so the pairs re-decided in
+  // float64 grow with band(t) / R^2.  bf16 with one term is cheapest on the
+  // matrix cores; three terms cost three times the products but narrow the
+  // band by ~2^8; the fp32 vector screen has an essentially empty band but
+  // costs d + 1 vector operations per pair.
   const double Y = ix.max_norm;
   auto ka_of = [&](int t) { return ((t * d + 15) / 16) * 16; };
-  auto slack_of = [&](int t) { return 2.0 * mixed_c_rep(t) * Y * Y; };
+  auto rel_band = [&](int t) { return R2 > 0 ? 2.0 * mixed_c_rep(t) * Y * Y / R2 : INFINITY; };
+  auto fits = [&](int t) { return ka_of(t) <= 16 * mixed_max_slices(); };
   int terms = o.mixed_terms;
-  if (terms == 0) terms = (slack_of(1) <= 0.5 * R2 || ka_of(3) > 16 * mixed_max_slices()) ? 1 : 3;
-  const bool mixed_ok = ka_of(terms) <= 16 * mixed_max_slices();
+  if (terms == 0) {
+    if (fits(1) && rel_band(1) <= 0.1)
+      terms = 1;
+    else if (fits(3))
+      terms = 3;
+    else
+      terms = 1;
+  }
   snn_precision prec = o.precision;
-  if (prec == SNN_PREC_AUTO) prec = (mixed_ok && slack_of(terms) <= 4.0 * R2) ? SNN_PREC_MIXED : SNN_PREC_FP64;
-  if (prec == SNN_PREC_MIXED && !mixed_ok)
+  if (prec == SNN_PREC_AUTO) {
+    if (fits(terms) && rel_band(terms) <= 0.5)
+      prec = SNN_PREC_MIXED;
+    else if (d <= valu_max_d())
+      prec = SNN_PREC_FP32;
+    else if (fits(1) && rel_band(1) <= 2.0) {
+      prec = SNN_PREC_MIXED;
+      terms = 1;
+    } else
+      prec = SNN_PREC_FP64;
+  }
+  if (prec == SNN_PREC_MIXED && !fits(terms))
     fail(SNN_ENOTSUP, "mixed screen: packed operand rows longer than 128 bf16 (lower d or use terms=1)");
-  const int t_mixed = prec == SNN_PREC_MIXED ? 4 * mixed_queries_per_wave(ka_of(terms)) : 0;
-  if (prec == SNN_PREC_MIXED && o.tile_q && o.tile_q != t_mixed)
-    fail(SNN_EINVAL, "mixed screen: tile_q must be " + std::to_string(t_mixed) + " for this dimension");
-  const int T = prec == SNN_PREC_MIXED ? t_mixed : (o.tile_q ? o.tile_q : 64);
-  const int CH = o.tile_c ? o.tile_c : (prec == SNN_PREC_MIXED ? 4096 : 1024);
+  if (prec == SNN_PREC_FP32 && d > valu_max_d()) fail(SNN_ENOTSUP, "fp32 vector screen supports d <= 16");
+  int T_fixed = 0;
+  if (prec == SNN_PREC_MIXED) T_fixed = 4 * mixed_queries_per_wave(ka_of(terms));
+  if (prec == SNN_PREC_FP32) T_fixed = valu_queries_per_tile();
+  if (T_fixed && o.tile_q && o.tile_q != T_fixed)
+    fail(SNN_EINVAL, "tile_q must be " + std::to_string(T_fixed) + " for this screen and dimension");
+  const int T = T_fixed ? T_fixed : (o.tile_q ? o.tile_q : 64);
+  const int CH = o.tile_c ? o.tile_c : (prec == SNN_PREC_MIXED ? 4096 : prec == SNN_PREC_FP32 ? 2048 : 1024);
   if (prec == SNN_PREC_MIXED && CH % 32 != 0) fail(SNN_EINVAL, "mixed screen: tile_c must be a multiple of 32");
   if (prec == SNN_PREC_MIXED) build_mixed_operands(ix, terms);
+  if (prec == SNN_PREC_FP32) build_valu_operands(ix);
   const int ntiles = (int)std::max<int64_t>(1, (m + T - 1) / T);
 
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -265,6 +298,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       int32_t* lists;
       uint16_t* qop;
       float* cthr;
+      float* vq;
     } p;
     const size_t mq = self ? 1 : (size_t)m;
     p.ukey = c.take<uint32_t>(mq);  // bucket of each query
@@ -291,6 +325,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     const bool mix = prec == SNN_PREC_MIXED;
     p.qop = c.take<uint16_t>(mix && !self ? (size_t)m * ka_of(terms) : 1);
     p.cthr = c.take<float>(mix ? std::max<int64_t>(m, 1) : 1);
+    p.vq = c.take<float>(prec == SNN_PREC_FP32 ? (size_t)std::max<int64_t>(m, 1) * valu_row_floats(d) : 1);
     return p;
   };
   plan_query(probe);
@@ -335,7 +370,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
                  prec == SNN_PREC_MIXED ? 32 : 1, ntiles, P.lo, P.hi, P.tlo,
                  P.thi, P.units, &P.ctl->pairs_window, s);
   // chunk-major work order inside groups of G score-adjacent tiles (L2 reuse)
-  const int G = prec == SNN_PREC_MIXED ? 8 : 16;
+  const int G = prec == SNN_PREC_FP64 ? 16 : 8;
   const int ngroups = (ntiles + G - 1) / G;
   launch_group_units(P.units, ntiles, G, P.gunits, s);
   exclusive_scan_i32_to_i64(P.gunits, P.unit_off, ngroups, P.scan_scratch, s);
@@ -378,6 +413,13 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       launch_mixed_qprep(q64, m, d, ix.dp, ix.mu.as<double>(), terms, mo.ka, mb, P.qop, P.cthr, s);
     }
   }
+  if (prec == SNN_PREC_FP32) {
+    const MixedBound vb = mixed_bound(0, d, d, R2, Y);
+    if (self)
+      launch_valu_qprep_self(ix.ys.as<float>(), n, d, vb, P.vq, s);
+    else
+      launch_valu_qprep(q64, m, d, ix.dp, ix.mu.as<double>(), vb, P.vq, s);
+  }
 
   // survivors: capacity remembered on the index, grown on overflow
   long long cap = std::max<long long>(1 << 16, (long long)(ix.ws[1].bytes / 24));
@@ -405,12 +447,16 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       launch_fill_u64(&P.ctl->survivors, 1, 0ull, s);
       launch_fill_i32(P.row_cnt, m, 0, s);
     }
-    const int per_cu = prec == SNN_PREC_MIXED ? mixed_blocks_per_cu(mx.KA, mx.KB) : fp64_blocks_per_cu(ix.dp);
+    const int per_cu = prec == SNN_PREC_MIXED  ? mixed_blocks_per_cu(mx.KA, mx.KB)
+                       : prec == SNN_PREC_FP32 ? valu_blocks_per_cu(d)
+                                               : fp64_blocks_per_cu(ix.dp);
     const int grid = std::max(di.xcds, (di.cus * per_cu / di.xcds) * di.xcds);
     if (st) SNN_HIP(hipEventRecord(ev[1], s));
     if (m > 0) {
       if (prec == SNN_PREC_MIXED)
         launch_cand_mfma(qd, mx, grid, s);
+      else if (prec == SNN_PREC_FP32)
+        launch_cand_valu(qd, P.vq, ix.vcand.as<float>(), grid, s);
       else
         launch_cand_fp64(qd, grid, s);
     }
@@ -487,6 +533,9 @@ static void free_index(snn_index_s* ix) {
   for (auto& mo : ix->mixed) {
     mo.cand.reset(a);
     mo.qself.reset(a);
+  }
+  {
+    ix->vcand.reset(a);
   }
   for (auto& w : ix->ws) w.reset(a);
   delete ix;

@@ -49,7 +49,7 @@ def check_same(got, ref, what=""):
     assert np.all(rel <= 1e-5), f"{what}: max rel dist err {rel.max()}"
 
 
-PRECS = ["fp64", "mixed", "auto"]
+PRECS = ["fp64", "mixed", "fp32", "auto"]
 
 
 @pytest.mark.parametrize("terms", [1, 3])
@@ -133,6 +133,11 @@ def test_dims(B, d):
     ref = oracle.brute_radius(P, Q, R)
     idx = B.Index(to_dev(P))
     for prec in PRECS:
+        if prec == "fp32" and d > 16:
+            with pytest.raises(B.SnnError) as e:
+                idx.query(to_dev(Q), R, precision=prec)
+            assert e.value.status == B.SNN_ENOTSUP
+            continue
         check_same(idx.query(to_dev(Q), R, precision=prec), ref, f"d={d} {prec}")
 
 
@@ -260,3 +265,31 @@ def test_radix_sort(B, n, bits):
     order = np.argsort(k & mask, kind="stable")
     assert np.array_equal(vt.cpu().numpy().view(np.uint32), vals[order])
     assert np.array_equal(kt.cpu().numpy().view(np.uint32), k[order])
+
+
+def test_auto_policy(B):
+    # the plan follows the width of each screen's rounding band against R^2
+    say("auto policy")
+    w = W.blobs3d(n=30_000, R=0.005)
+    idx = B.Index(to_dev(w.P))
+    st = idx.query_self(w.R, stats=True)[3]
+    assert B.PRECISION_NAMES[st["precision_used"]] == "fp32"  # bf16 band ~ R^2 for d = 3, tiny R
+    w2 = W.gmm16(n=30_000, m=500, R=1.5)
+    idx2 = B.Index(to_dev(w2.P))
+    st2 = idx2.query(to_dev(w2.Q), w2.R, stats=True)[3]
+    assert B.PRECISION_NAMES[st2["precision_used"]] == "mixed" and st2["terms_used"] == 3
+    w3 = W.gmm128z(n=5_000, R=4.0)
+    idx3 = B.Index(to_dev(w3.P))
+    st3 = idx3.query_self(w3.R, stats=True)[3]
+    assert B.PRECISION_NAMES[st3["precision_used"]] == "mixed" and st3["terms_used"] == 1
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed", "fp64"])
+def test_dense_self_output(B, prec):
+    # many neighbours per row: survivor staging drains, wave/block row sorts
+    say(f"dense self {prec}")
+    w = W.blobs3d(n=40_000, R=0.03, seed=9)
+    ref, _ = oracle.snn_query(oracle.build_index(w.P), w.P, w.R)
+    assert ref.row_ptr[-1] > 20 * w.n
+    idx = B.Index(to_dev(w.P))
+    check_same(idx.query_self(w.R, precision=prec), ref, f"dense self {prec}")
