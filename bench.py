@@ -1,18 +1,24 @@
-"""Benchmark: exact radius queries/s on the gmm16 workload (n = 1e6 points,
-d = 16, float32, 20-cluster Gaussian mixture, 1e5 out-of-sample queries,
-R = 1.5) -- the mixed-precision screen (bf16 matrix cores + float64
-recheck) against the plain float64 GPU kernel.
+"""Benchmark: exact radius queries/s.
 
-One step = one snn_query call over all 1e5 queries with the index and the
-queries resident in HBM.  W untimed warm-up steps, then K timed steps
-bracketed by torch.cuda.synchronize(); the value is m * K / elapsed.
+Default (the headline): the gmm16 workload -- n = 1e6 points, d = 16,
+float32, 20-cluster Gaussian mixture, 1e5 out-of-sample queries, R = 1.5 --
+with the mixed-precision screen (bf16 matrix cores + float64 recheck) timed
+against the plain float64 GPU kernel.  ``--workload`` selects another
+configuration (uniform2d, gmm128z, blobs3d); those print the same kind of
+line for that workload.
+
+One step = one snn_query (or snn_query_self) call over all queries with the
+index and the queries resident in HBM.  W untimed warm-up steps, then K timed
+steps bracketed by torch.cuda.synchronize(); value = m * K / elapsed, timed
+with events on the library's stream.
 
 Prints one JSON line.  ``roofline`` describes the dominant kernel (the
-candidate screen): algorithmic work per launch (sum over queries of the
-window size |J_q| times 2d flop, the count of Section 4 for eq. (ip2)) over
-its average duration, timed with HIP events the library records on its own
-stream around that kernel.  ``cpu_baseline`` times the CPU oracle (CPU SNN,
-Algorithms 1-2 with float64 BLAS) on a bounded sample of the same queries.
+candidate screen): algorithmic work per launch (the sum over queries of the
+window size |J_q| times the flop count Section 4 gives per candidate: 2d for
+eq. (ip2), 3d - 1 for eq. (ip1)) over the kernel's average duration, timed with
+HIP events the library records on its own stream around that kernel.
+``cpu_baseline`` times the CPU oracle (CPU SNN, Algorithms 1-2, float64 BLAS)
+on a bounded sample of the same queries.
 """
 
 from __future__ import annotations
@@ -27,8 +33,63 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_BF16_FLOPS = 2.5e15  # MI355X dense bf16 matrix peak
+PEAK_FP32_VALU_FLOPS = 157.3e12  # MI355X fp32 vector peak (fused multiply-add = 2 flop)
 PEAK_FP64_VALU_OPS = 256 * 4 * 16 * 2.4e9  # non-fused float64 lane-ops/s: CUs x SIMDs x lanes x clock
 PEAK_HBM = 8.0e12
+
+HEADLINE_METRIC = "exact radius queries/s at n=1e6,d=16: MFMA+FP64 recheck vs plain FP64 GPU"
+
+WORKLOADS = {
+    "gmm16": dict(desc="gmm16: n=1e6 d=16 float32, 20-cluster Gaussian mixture, 1e5 out-of-sample queries, R=1.5",
+                  precisions="mixed,fp64", cpu_sample=2000),
+    "uniform2d": dict(desc="uniform2d: n=1e4 d=2 float64 uniform in [0,1]^2, 1e3 queries sampled from the data, "
+                           "R=0.05", precisions="auto,fp64", cpu_sample=1000),
+    "gmm128z": dict(desc="gmm128z: n=2e6 d=128 float32, 50-cluster mixture z-scored per feature, all-points "
+                         "self-query, R=4.0", precisions="auto", cpu_sample=200),
+    "blobs3d": dict(desc="blobs3d: n=5e6 d=3 float32, 1000 Gaussian blobs (std 0.01) + 20% uniform background in "
+                         "[0,1]^3, all-points self-query, R=0.005", precisions="auto", cpu_sample=500),
+}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = {
+    "mixed": "paper_2212_07679_amd/csrc/k_cand_mfma.hip",
+    "fp32": "paper_2212_07679_amd/csrc/k_cand_valu.hip",
+    "fp64": "paper_2212_07679_amd/csrc/k_cand_fp64.hip",
+}
+
+
+def source_hash(rel):
+    import hashlib
+
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, used):
+    """HBM bytes per launch of the screen kernel from the committed counter
+    summary, if it was taken on the current kernel source; else None."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE)).get(f"{workload}/{used}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha256_16") != source_hash(KERNEL_SOURCES[used]):
+        return None
+    return rec["traffic_bytes"]
+
+
+def copy_probe(nbytes):
+    """A plain device-to-device copy of known size, for calibrating the
+    FETCH_SIZE / WRITE_SIZE counters (profile this command with --pmc)."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": src.numel() * 4, "launches": 3}))
 
 
 def parse():
@@ -36,18 +97,38 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--m", type=int, default=100_000)
-    ap.add_argument("--R", type=float, default=1.5)
-    ap.add_argument("--precisions", default="mixed,fp64")
-    ap.add_argument("--cpu-sample", type=int, default=2000, help="queries the CPU oracle times (0: skip)")
+    ap.add_argument("--workload", default="gmm16", choices=sorted(WORKLOADS) + ["copyprobe"])
+    ap.add_argument("--n", type=int, default=0, help="override the number of points (0: the workload's)")
+    ap.add_argument("--m", type=int, default=0, help="override the number of queries (gmm16, uniform2d)")
+    ap.add_argument("--precisions", default="", help="comma list; the first is the reported value")
+    ap.add_argument("--cpu-sample", type=int, default=-1, help="queries the CPU oracle times (0: skip)")
     ap.add_argument("--check", type=int, default=200, help="queries checked against the oracle (0: skip)")
     return ap.parse_args()
 
 
-def time_precision(idx, Q, R, prec, steps, warmup, torch):
+def make_workload(name, n, m):
+    from paper_2212_07679_amd import workloads as W
+
+    if name == "gmm16":
+        return W.gmm16(**({"n": n} if n else {}), **({"m": m} if m else {}))
+    if name == "uniform2d":
+        return W.uniform2d(**({"n": n} if n else {}), **({"m": m} if m else {}))
+    if name == "gmm128z":
+        return W.gmm128z(**({"n": n} if n else {}))
+    if name == "blobs3d":
+        return W.blobs3d(**({"n": n} if n else {}))
+    raise ValueError(name)
+
+
+def run_query(idx, w, Qdev, prec):
+    if w.Q is None:
+        return idx.query_self(w.R, precision=prec, stats=True)
+    return idx.query(Qdev, w.R, precision=prec, stats=True)
+
+
+def time_precision(idx, w, Qdev, prec, steps, warmup, torch):
     for _ in range(warmup):
-        out = idx.query(Q, R, precision=prec, stats=True)
+        out = run_query(idx, w, Qdev, prec)
     torch.cuda.synchronize()
     screen = []
     t0 = time.perf_counter()
@@ -55,7 +136,7 @@ def time_precision(idx, Q, R, prec, steps, warmup, torch):
     stop = torch.cuda.Event(enable_timing=True)
     start.record(idx.stream)
     for _ in range(steps):
-        out = idx.query(Q, R, precision=prec, stats=True)
+        out = run_query(idx, w, Qdev, prec)
         screen.append(out[3]["screen_ms"])
     stop.record(idx.stream)
     torch.cuda.synchronize()
@@ -80,7 +161,7 @@ def cpu_baseline(w, sample):
     t0 = time.perf_counter()
     idx = oracle.build_index(w.P)
     t1 = time.perf_counter()
-    nb, st = oracle.snn_query(idx, w.Q[sel], w.R)
+    nb, st = oracle.snn_query(idx, w.queries[sel], w.R)
     t2 = time.perf_counter()
     return {
         "value": len(sel) / (t2 - t1),
@@ -91,21 +172,47 @@ def cpu_baseline(w, sample):
     }, (sel, nb)
 
 
+def roofline(prec_used, terms, st, screen_ms, d):
+    if prec_used == "mixed":
+        achieved = st["pairs_window"] * 2 * d / (screen_ms / 1e3)
+        return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16_FLOPS / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_BF16_FLOPS, "traffic": None}
+    if prec_used == "fp32":
+        achieved = st["pairs_window"] * 2 * d / (screen_ms / 1e3)
+        return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU_FLOPS / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_FLOPS, "traffic": None}
+    achieved = st["pairs_window"] * (3 * d - 1) / (screen_ms / 1e3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU_OPS / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VALU_OPS, "traffic": None}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); queries shard without communication, "
-              "see the design notes for the multi-GPU mapping", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {a.gpus}); queries shard across GPUs without "
+              "communication, see the design notes for the multi-GPU mapping", file=sys.stderr)
         sys.exit(2)
+    if a.workload == "copyprobe":
+        copy_probe(1 << 30)
+        return
     import numpy as np
     import torch
 
-    from paper_2212_07679_amd import binding, workloads
+    from paper_2212_07679_amd import binding
 
-    w = workloads.gmm16(n=a.n, m=a.m, R=a.R)
+    spec = WORKLOADS[a.workload]
+    precisions = [p for p in (a.precisions or spec["precisions"]).split(",") if p]
+    cpu_sample = spec["cpu_sample"] if a.cpu_sample < 0 else a.cpu_sample
+    t_gen = time.perf_counter()
+    w = make_workload(a.workload, a.n, a.m)
+    print(f"[bench] {a.workload}: n={w.n} d={w.d} m={w.m} R={w.R} generated in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     X = torch.from_numpy(w.P).to(dev)
-    Q = torch.from_numpy(w.Q).to(dev)
+    Qdev = torch.from_numpy(w.Q).to(dev) if w.Q is not None else None
+    torch.cuda.synchronize()
+    idx = binding.Index(X)  # first build: allocations
+    idx.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     idx = binding.Index(X)
@@ -113,8 +220,8 @@ def main():
     index_ms = (time.perf_counter() - t0) * 1e3
 
     results = {}
-    for prec in [p for p in a.precisions.split(",") if p]:
-        out, wall, ev_ms, screen_ms = time_precision(idx, Q, w.R, prec, a.steps, a.warmup, torch)
+    for prec in precisions:
+        out, wall, ev_ms, screen_ms = time_precision(idx, w, Qdev, prec, a.steps, a.warmup, torch)
         st = out[3]
         results[prec] = {
             "qps": w.m * a.steps / (ev_ms / 1e3),
@@ -124,38 +231,31 @@ def main():
             "stats": st,
             "out": out,
         }
-        print(f"[bench] {prec}: {results[prec]['ms_per_step']:.3f} ms/step, screen {screen_ms:.3f} ms, "
-              f"nnz {st['nnz']}, window pairs {st['pairs_window']}, rechecked {st['pairs_recheck']}",
-              file=sys.stderr, flush=True)
+        used = binding.PRECISION_NAMES[st["precision_used"]]
+        print(f"[bench] {prec} ({used}, terms {st['terms_used']}): {results[prec]['ms_per_step']:.3f} ms/step, "
+              f"screen {screen_ms:.3f} ms, nnz {st['nnz']}, window pairs {st['pairs_window']}, "
+              f"rechecked {st['pairs_recheck']}", file=sys.stderr, flush=True)
 
     # identical results across precisions
-    precs = list(results)
-    for p in precs[1:]:
-        for x, y in zip(results[precs[0]]["out"][:3], results[p]["out"][:3]):
-            assert torch.equal(x, y), f"{precs[0]} and {p} differ"
+    for p in precisions[1:]:
+        for x, y in zip(results[precisions[0]]["out"][:3], results[p]["out"][:3]):
+            assert torch.equal(x, y), f"{precisions[0]} and {p} differ"
 
     cpu = None
-    if a.cpu_sample > 0:
-        cpu, (sel, nb) = cpu_baseline(w, a.cpu_sample)
-        # the sampled rows agree with the oracle
-        rp, col, _ = (t.cpu().numpy() for t in results[precs[0]]["out"][:3])
+    if cpu_sample > 0:
+        cpu, (sel, nb) = cpu_baseline(w, cpu_sample)
+        rp, col, dist = (t.cpu().numpy() for t in results[precisions[0]]["out"][:3])
         for k, qi in enumerate(sel[: a.check]):
-            assert np.array_equal(col[rp[qi]:rp[qi + 1]], nb.col[nb.row_ptr[k]:nb.row_ptr[k + 1]]), f"query {qi}"
+            got = col[rp[qi]:rp[qi + 1]]
+            assert np.array_equal(got, nb.col[nb.row_ptr[k]:nb.row_ptr[k + 1]]), f"query {qi} differs from the oracle"
 
-    head = "mixed" if "mixed" in results else precs[0]
+    head = precisions[0]
     r = results[head]
     st = r["stats"]
-    d = w.d
-    if head == "mixed":
-        achieved = st["pairs_window"] * 2 * d / (r["screen_ms"] / 1e3)
-        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16_FLOPS / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_BF16_FLOPS, "traffic": None}
-    else:
-        achieved = st["pairs_window"] * (3 * d) / (r["screen_ms"] / 1e3)
-        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU_OPS / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VALU_OPS, "traffic": None}
+    used = binding.PRECISION_NAMES[st["precision_used"]]
+    fp64 = results.get("fp64")
     line = {
-        "metric": "exact radius queries/s at n=1e6,d=16: MFMA+FP64 recheck vs plain FP64 GPU",
+        "metric": HEADLINE_METRIC if a.workload == "gmm16" else "exact radius queries/s",
         "value": r["qps"],
         "unit": "queries/s",
         "n_gpus": 1,
@@ -165,21 +265,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16+f64" if head == "mixed" else "f64",
+        "dtype": {"mixed": "bf16+f64", "fp32": "f32+f64", "fp64": "f64"}[used],
         "data": "synthetic",
-        "config": {"workload": "gmm16: n=1e6 d=16 float32, 20-cluster Gaussian mixture, 1e5 out-of-sample "
-                               "queries, R=1.5", "n": w.n, "d": d, "m": w.m, "R": w.R, "precision": head},
-        "fp64_gpu_qps": results.get("fp64", {}).get("qps"),
-        "speedup_vs_fp64_gpu": (r["qps"] / results["fp64"]["qps"]) if ("fp64" in results and head != "fp64") else None,
+        "config": {"workload": spec["desc"], "n": w.n, "d": w.d, "m": w.m, "R": w.R, "self_query": w.Q is None,
+                   "precision": used, "terms": st["terms_used"]},
+        "fp64_gpu_qps": fp64["qps"] if fp64 else None,
+        "speedup_vs_fp64_gpu": (r["qps"] / fp64["qps"]) if (fp64 and head != "fp64") else None,
         "pairs_window": st["pairs_window"],
         "pairs_recheck": st["pairs_recheck"],
         "recheck_fraction": st["pairs_recheck"] / max(st["pairs_window"], 1),
         "nnz": st["nnz"],
         "screen_ms": r["screen_ms"],
         "index_ms": index_ms,
-        "roofline": roof,
+        "roofline": roofline(used, st["terms_used"], st, r["screen_ms"], w.d),
         "cpu_baseline": cpu,
     }
+    line["roofline"]["traffic"] = measured_traffic(a.workload, used)
     print(json.dumps(line))
 
 
