@@ -151,6 +151,72 @@ snn_status snn_index_get_view(snn_index_t idx, snn_index_view* view);
 
 void snn_index_free(snn_index_t idx);
 
+/* ---- Batching form --------------------------------------------------------
+ * Many independent instances, each a complete Algorithm 1 + Algorithm 2
+ * (own data, queries, radius and dimension), run as one captured HIP graph of
+ * batched kernels in which the candidate screen of every instance is one
+ * persistent matrix-core launch (the MIXED screen with a float64 recheck, so
+ * every result is exact).  A plan fixes the instance sizes and pointers to the
+ * data; the data may change between runs, and the CSR structs are read again
+ * at every run. */
+typedef struct {
+  const void* X;  /* device, n x d row-major, batch dtype; read at every index pass */
+  const void* Q;  /* device, m x d row-major; NULL with m = n: all-points self-query;
+                     NULL with m = 0: no queries */
+  int64_t n;      /* 1 <= n < 2^31 */
+  int64_t m;      /* 0 <= m < 2^31 */
+  int32_t d;      /* 1 <= d <= 128 */
+  double R;       /* finite, >= 0 */
+  snn_csr* out;   /* host struct owned by the caller; it and its device arrays must
+                     stay valid for the plan's lifetime (they may be replaced between
+                     runs).  Rows follow the order of Q (of X for a self-query). */
+} snn_instance;
+
+typedef struct {
+  int32_t mixed_terms;    /* 0: per instance from its rounding band; or 1 / 3 for all */
+  int32_t tile_c;         /* candidates per work unit (multiple of 32); 0: tuned / 4096 */
+  int32_t tile_g;         /* tiles per work group; 0: tuned / 8 */
+  int32_t autotune;       /* 1: time candidate (tile_c, tile_g) on this batch at creation */
+  const char* tune_cache; /* host path of a tuning cache file (read and appended), or NULL */
+} snn_batch_options;
+
+typedef struct {
+  int32_t tile_q;             /* query slots per tile */
+  int32_t tile_c;             /* candidates per work unit */
+  int32_t tile_g;             /* tiles per work group */
+  int32_t operand_k;          /* bf16 operand row length of the screen */
+  int32_t graph_timed_screen; /* 1 if the query graph times its screen kernel */
+  float tuned_query_ms;       /* best query-pass time the autotuner measured (0: not tuned) */
+} snn_batch_info_t;
+
+typedef struct snn_batch_s* snn_batch_t;
+
+enum { SNN_BATCH_INDEX = 1, SNN_BATCH_QUERY = 2 };
+
+/* Validates the instances, allocates everything (dev->alloc), decides the
+ * screen operands, captures the graphs and runs the index and query passes
+ * once (so the outputs already hold a result).  opts may be NULL.
+ * Errors: SNN_EINVAL (arguments, NaN/Inf in X), SNN_ENOTSUP, SNN_ENOMEM,
+ * SNN_EDEVICE. */
+snn_status snn_batch_create(const snn_device* dev, snn_dtype dtype, const snn_instance* instances,
+                            int32_t count, const snn_batch_options* opts, snn_batch_t* out);
+
+/* Runs the index pass, the query pass, or both (one graph launch) on
+ * dev->stream and waits for it.  Every instance's out->nnz is set; if some
+ * instance's neighbours exceed its nnz_cap the call returns SNN_EOVERFLOW
+ * (that instance's col/dist unspecified, all others complete).  The query
+ * pass uses the index of the latest index pass.  st (host, nullable) sums
+ * over instances; screen_ms is -1 when the screen is not timed. */
+snn_status snn_batch_run(snn_batch_t batch, int32_t what, snn_stats* st);
+
+snn_status snn_batch_info(snn_batch_t batch, snn_batch_info_t* info);
+
+void snn_batch_free(snn_batch_t batch);
+
+/* One-shot form: create, run both passes once, free. */
+snn_status snn_query_batch(const snn_device* dev, snn_dtype dtype, const snn_instance* instances,
+                           int32_t count, const snn_batch_options* opts, snn_stats* st);
+
 /* Stable LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit)
  * of the keys, in place (the building block of Algorithm 1, step 6).
  *   keys, vals: device, n entries each.  0 <= begin_bit < end_bit <= 32.

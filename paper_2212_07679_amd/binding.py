@@ -103,8 +103,55 @@ class snn_index_view(ctypes.Structure):
     ]
 
 
+class snn_instance(ctypes.Structure):
+    _fields_ = [
+        ("X", ctypes.c_void_p),
+        ("Q", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("m", ctypes.c_int64),
+        ("d", ctypes.c_int32),
+        ("R", ctypes.c_double),
+        ("out", ctypes.POINTER(snn_csr)),
+    ]
+
+
+class snn_batch_options(ctypes.Structure):
+    _fields_ = [
+        ("mixed_terms", ctypes.c_int32),
+        ("tile_c", ctypes.c_int32),
+        ("tile_g", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
+        ("tune_cache", ctypes.c_char_p),
+    ]
+
+
+class snn_batch_info_t(ctypes.Structure):
+    _fields_ = [
+        ("tile_q", ctypes.c_int32),
+        ("tile_c", ctypes.c_int32),
+        ("tile_g", ctypes.c_int32),
+        ("operand_k", ctypes.c_int32),
+        ("graph_timed_screen", ctypes.c_int32),
+        ("tuned_query_ms", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+SNN_BATCH_INDEX, SNN_BATCH_QUERY = 1, 2
+
 # symbol -> (restype, argtypes): every entry point declared in include/snn.h
 SIGNATURES = {
+    "snn_batch_create": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_int, ctypes.POINTER(snn_instance),
+                                        ctypes.c_int32, ctypes.POINTER(snn_batch_options),
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "snn_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(snn_stats)]),
+    "snn_batch_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(snn_batch_info_t)]),
+    "snn_batch_free": (None, [ctypes.c_void_p]),
+    "snn_query_batch": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_int, ctypes.POINTER(snn_instance),
+                                       ctypes.c_int32, ctypes.POINTER(snn_batch_options),
+                                       ctypes.POINTER(snn_stats)]),
     "snn_index": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                  ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
     "snn_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
@@ -306,3 +353,108 @@ def sort_pairs_u32(keys: torch.Tensor, vals: torch.Tensor, begin_bit: int = 0, e
     alloc = _TorchAllocator(device)
     _check(lib().snn_sort_pairs_u32(ctypes.byref(alloc.dev), ctypes.c_void_p(keys.data_ptr()),
                                     ctypes.c_void_p(vals.data_ptr()), keys.numel(), begin_bit, end_bit))
+
+
+class Batch:
+    """A plan of many independent instances (the batching form).
+
+    ``instances`` is a list of ``(X, Q, R)`` with X (n x d) and Q (m x d, or
+    None for an all-points self-query) CUDA tensors of one dtype.  Creating
+    the plan runs both passes once; ``run()`` launches the captured graph
+    again (after the data in X / Q changed, or to time it) and returns one
+    ``(row_ptr, col, dist)`` per instance.  The tensors must stay alive and
+    keep their shapes while the plan exists.
+    """
+
+    def __init__(self, instances, terms: int = 0, tile_c: int = 0, tile_g: int = 0, autotune: bool = False,
+                 tune_cache: Optional[str] = None, nnz_caps=None, stream: Optional[torch.cuda.Stream] = None):
+        if not instances:
+            raise SnnError(SNN_EINVAL, "no instances")
+        X0 = instances[0][0]
+        if not isinstance(X0, torch.Tensor) or not X0.is_cuda:
+            raise SnnError(SNN_EINVAL, "X must be CUDA tensors")
+        self.dtype = X0.dtype
+        self.device = X0.device.index if X0.device.index is not None else torch.cuda.current_device()
+        self._alloc = _TorchAllocator(self.device, stream)
+        self._keep = []
+        self.count = len(instances)
+        self._csr = (snn_csr * self.count)()
+        self._inst = (snn_instance * self.count)()
+        self._out = []
+        dev = f"cuda:{self.device}"
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            for i, (X, Q, R) in enumerate(instances):
+                if not isinstance(X, torch.Tensor) or X.dim() != 2 or X.dtype != self.dtype or not X.is_cuda:
+                    raise SnnError(SNN_EINVAL, f"instance {i}: X must be a 2-D CUDA tensor of the batch dtype")
+                if not X.is_contiguous():
+                    raise SnnError(SNN_EINVAL, f"instance {i}: X must be contiguous")
+                n, d = X.shape
+                if Q is not None:
+                    if (not isinstance(Q, torch.Tensor) or Q.dim() != 2 or Q.shape[1] != d or Q.dtype != self.dtype
+                            or not Q.is_cuda or not Q.is_contiguous()):
+                        raise SnnError(SNN_EINVAL, f"instance {i}: Q must be a contiguous (m, d) CUDA tensor")
+                    m = Q.shape[0]
+                else:
+                    m = n
+                cap = int(nnz_caps[i]) if nnz_caps is not None else max(32 * m, 1024)
+                row_ptr = torch.empty(m + 1, dtype=torch.int64, device=dev)
+                col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+                dist = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+                self._out.append([row_ptr, col, dist])
+                self._csr[i] = snn_csr(row_ptr.data_ptr(), col.data_ptr(), dist.data_ptr(), cap, 0)
+                # Q NULL means a self-query when m = n and no queries when m = 0
+                qp = Q.data_ptr() if (Q is not None and m > 0) else None
+                self._inst[i] = snn_instance(X.data_ptr(), qp, n, m, d, float(R), ctypes.pointer(self._csr[i]))
+                self._keep.append((X, Q))
+            self._cache = tune_cache.encode() if tune_cache else None
+            opts = snn_batch_options(int(terms), int(tile_c), int(tile_g), 1 if autotune else 0, self._cache)
+            self._h = ctypes.c_void_p()
+            _check(lib().snn_batch_create(ctypes.byref(self._alloc.dev), _dtype_code(X0), self._inst, self.count,
+                                          ctypes.byref(opts), ctypes.byref(self._h)))
+
+    @property
+    def stream(self) -> torch.cuda.Stream:
+        return self._alloc.stream
+
+    def info(self) -> dict:
+        inf = snn_batch_info_t()
+        _check(lib().snn_batch_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def run(self, index: bool = True, query: bool = True, stats: bool = False):
+        what = (SNN_BATCH_INDEX if index else 0) | (SNN_BATCH_QUERY if query else 0)
+        dev = f"cuda:{self.device}"
+        st = snn_stats()
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            for _ in range(3):
+                status = lib().snn_batch_run(self._h, what, ctypes.byref(st))
+                if status != SNN_EOVERFLOW:
+                    _check(status)
+                    break
+                # grow the outputs that overflowed; the index pass is done
+                for i in range(self.count):
+                    c = self._csr[i]
+                    if c.nnz > c.nnz_cap:
+                        cap = int(c.nnz + c.nnz // 4 + 16)
+                        col = torch.empty(cap, dtype=torch.int32, device=dev)
+                        dist = torch.empty(cap, dtype=torch.float32, device=dev)
+                        self._out[i][1:] = [col, dist]
+                        c.col, c.dist, c.nnz_cap = col.data_ptr(), dist.data_ptr(), cap
+                what = SNN_BATCH_QUERY
+            else:
+                _check(status)
+        if not query:
+            return st.as_dict() if stats else None
+        res = [(o[0], o[1][: int(self._csr[i].nnz)], o[2][: int(self._csr[i].nnz)]) for i, o in enumerate(self._out)]
+        return (res, st.as_dict()) if stats else res
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().snn_batch_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

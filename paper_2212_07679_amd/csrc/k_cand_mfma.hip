@@ -53,29 +53,6 @@ namespace snn {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-double mixed_c_rep(int terms) {
-  const double ub = std::ldexp(1.0, -8);
-  if (terms == 0) return 0.0;  // fp32 operands are the centred values themselves
-  return 1.01 * (terms == 1 ? ub * (2.0 + ub) : ub * ub * (3.0 + 3.0 * ub));
-}
-
-MixedBound mixed_bound(int terms, int KA, int d, double R2, double Y) {
-  const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
-  auto g32 = [&](int k) { return k * u32 / (1.0 - k * u32); };
-  auto g64 = [&](int k) { return k * u64 / (1.0 - k * u64); };
-  MixedBound b;
-  const double r2p = R2 * (1.0 + 2.0 * g64(d + 2));
-  b.r2p_half = 0.5 * r2p;
-  b.sqrt_r2p = std::sqrt(r2p) * (1.0 + 1e-15);
-  b.u32p = 1.01 * u32;
-  b.Y = Y;
-  b.c_rep = mixed_c_rep(terms);
-  b.g_acc = 2.0 * g32(KA + 1);
-  b.e_h = 1.01 * u32 * Y * Y * 0.5;
-  b.g64 = g64(d + 1);
-  return b;
-}
-
 namespace {
 
 constexpr int kThreads = 256;
@@ -225,6 +202,9 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
     const int64_t j0 = q.tlo[tile] + c * q.CH;
     const int64_t j1 = min(j0 + q.CH, (int64_t)q.thi[tile]);
     if (q0 >= q.m) continue;  // this wave has no queries in the (ragged) last tile
+    // padding query slots (start value -inf) only occur after the real
+    // queries of a tile: a wave whose first slot is padding has no work
+    if (x.cthr[q0] == -INFINITY) continue;
 
     bf16x8 A[QB][NS];
     f32x16 Cin[QB];

@@ -187,6 +187,16 @@ int grid_for(int64_t work, int cap) {
 }
 }  // namespace
 
+void launch_tile_init(int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s) {
+  k_tile_init<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_tile_units(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int32_t* units, hipStream_t s) {
+  k_tile_units<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles, CH, align, units);
+  SNN_LAUNCH_CHECK();
+}
+
 void launch_group_units(const int32_t* units, int ntiles, int G, int32_t* gunits, hipStream_t s) {
   k_group_units<<<grid_for((ntiles + G - 1) / G, 1024), kThreads, 0, s>>>(units, ntiles, G, gunits);
   SNN_LAUNCH_CHECK();

@@ -253,4 +253,51 @@ void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n,
   a.release(mem);
 }
 
+size_t radix_sort_ws_bytes(int64_t n) {
+  const int64_t nblocks = ceil_div(std::max<int64_t>(n, 1), kSortTile);
+  const size_t nhist = (size_t)nblocks * kRadix;
+  return 2 * (size_t)n * sizeof(uint32_t) + nhist * sizeof(uint32_t) + scan_scratch_bytes((int64_t)nhist) + 1024;
+}
+
+namespace {
+__global__ void k_copy_pairs(const uint32_t* __restrict__ ks, const uint32_t* __restrict__ vs,
+                             uint32_t* __restrict__ kd, uint32_t* __restrict__ vd, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    kd[i] = ks[i];
+    vd[i] = vs[i];
+  }
+}
+}  // namespace
+
+// Same sort with caller-provided workspace (radix_sort_ws_bytes(n) bytes) and
+// kernels only (no allocation, no copy or memset calls): usable under
+// stream capture.
+void radix_sort_pairs_ws(uint32_t* keys, uint32_t* vals, int64_t n, int begin_bit, int end_bit, void* ws,
+                         hipStream_t s) {
+  if (n <= 1 || begin_bit >= end_bit) return;
+  if (n > (int64_t)UINT32_MAX / 2) fail(SNN_EINVAL, "radix sort: too many keys");
+  const int nblocks = (int)ceil_div(n, kSortTile);
+  const size_t nhist = (size_t)nblocks * kRadix;
+  uint32_t* k2 = static_cast<uint32_t*>(ws);
+  uint32_t* v2 = k2 + n;
+  uint32_t* hist = v2 + n;
+  void* scratch = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(hist + nhist) + 255) & ~uintptr_t(255));
+  uint32_t *kin = keys, *vin = vals, *kout = k2, *vout = v2;
+  for (int shift = begin_bit; shift < end_bit; shift += kRadixBits) {
+    const int bits = std::min(kRadixBits, end_bit - shift);
+    const uint32_t mask = (1u << bits) - 1u;
+    k_radix_hist<<<nblocks, kSortThreads, 0, s>>>(kin, n, shift, mask, hist, nblocks);
+    SNN_LAUNCH_CHECK();
+    exclusive_scan_u32(hist, (int64_t)nhist, scratch, s);
+    k_radix_scatter<<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, bits, hist, nblocks);
+    SNN_LAUNCH_CHECK();
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  if (kin != keys) {
+    k_copy_pairs<<<(unsigned)std::min<int64_t>(ceil_div(n, 256), 4096), 256, 0, s>>>(kin, vin, keys, vals, n);
+    SNN_LAUNCH_CHECK();
+  }
+}
+
 }  // namespace snn

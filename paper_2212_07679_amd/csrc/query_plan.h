@@ -101,6 +101,9 @@ void launch_windows(const double* key, int n, const double* qalpha, const double
                     double eps_scale, int T, int CH, int align, int ntiles, int32_t* lo, int32_t* hi, int32_t* tlo,
                     int32_t* thi, int32_t* units, unsigned long long* pairs_window, hipStream_t s);
 
+void launch_tile_init(int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s);
+void launch_tile_units(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int32_t* units, hipStream_t s);
+
 // units reserved per group of G tiles: Gg x max units of its tiles
 void launch_group_units(const int32_t* units, int ntiles, int G, int32_t* gunits, hipStream_t s);
 
@@ -127,8 +130,36 @@ struct MixedBound {
   double e_h;       // rounding of h_j to fp32
   double g64;       // gamma64_{d+1}: relative error of h_q in float64
 };
-double mixed_c_rep(int terms);  // terms = 0: exact fp32 operands (no representation error)
-MixedBound mixed_bound(int terms, int KA, int d, double R2, double Y);
+// Representation error coefficient of the screen operands, u_b = 2^-8:
+// terms = 1: bf16(y) carries |y - bf16(y)| <= u_b |y|, so the product of two
+// rounded operands differs from y_q . y_j by at most u_b (2 + u_b) |y_q||y_j|;
+// terms = 3: hi + lo leaves u_b^2 |y| and the dropped lo*lo product adds
+// u_b^2, giving u_b^2 (3 + 3 u_b); terms = 0: exact fp32 operands.
+__host__ __device__ inline double mixed_c_rep(int terms) {
+  const double ub = 0.00390625;
+  if (terms == 0) return 0.0;
+  return 1.01 * (terms == 1 ? ub * (2.0 + ub) : ub * ub * (3.0 + 3.0 * ub));
+}
+
+// Constants of the screen start value for one index and radius (the terms
+// of C_q derived in k_cand_mfma.hip).
+__host__ __device__ inline MixedBound mixed_bound(int terms, int KA, int d, double R2, double Y) {
+  const double u32 = 5.9604644775390625e-08, u64 = 1.1102230246251565e-16;
+  const double ga = (KA + 1) * u32 / (1.0 - (KA + 1) * u32);
+  const double gr = (d + 2) * u64 / (1.0 - (d + 2) * u64);
+  const double gh = (d + 1) * u64 / (1.0 - (d + 1) * u64);
+  MixedBound b;
+  const double r2p = R2 * (1.0 + 2.0 * gr);
+  b.r2p_half = 0.5 * r2p;
+  b.sqrt_r2p = sqrt(r2p) * (1.0 + 1e-15);
+  b.u32p = 1.01 * u32;
+  b.Y = Y;
+  b.c_rep = mixed_c_rep(terms);
+  b.g_acc = 2.0 * ga;
+  b.e_h = 1.01 * u32 * Y * Y * 0.5;
+  b.g64 = gh;
+  return b;
+}
 
 __device__ __forceinline__ float round_up_f32(double c) {
   float f = (float)c;

@@ -93,57 +93,36 @@ const DeviceInfo& device_info(int device) {
   return cache[device];
 }
 
-namespace {
-
 // Select the device of `dev` for the duration of a call, check it is gfx950.
-struct DeviceScope {
-  int prev = -1;
-  explicit DeviceScope(int device) {
-    int count = 0;
-    hipError_t e = hipGetDeviceCount(&count);
-    if (e != hipSuccess || count <= 0) {
-      (void)hipGetLastError();
-      fail(SNN_EDEVICE, "no HIP device available");
-    }
-    if (device < 0 || device >= count) fail(SNN_EINVAL, "device ordinal out of range");
-    SNN_HIP(hipGetDevice(&prev));
-    SNN_HIP(hipSetDevice(device));
-    static std::mutex mu;
-    static std::vector<int> ok;
-    std::lock_guard<std::mutex> lk(mu);
-    if ((int)ok.size() <= device) ok.resize(device + 1, -1);
-    if (ok[device] < 0) {
-      hipDeviceProp_t p;
-      SNN_HIP(hipGetDeviceProperties(&p, device));
-      ok[device] = std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
-    }
-    if (!ok[device]) fail(SNN_EDEVICE, "device is not gfx950 (this library is built for MI355X only)");
+DeviceScope::DeviceScope(int device) {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    fail(SNN_EDEVICE, "no HIP device available");
   }
-  ~DeviceScope() {
-    if (prev >= 0) (void)hipSetDevice(prev);
+  if (device < 0 || device >= count) fail(SNN_EINVAL, "device ordinal out of range");
+  SNN_HIP(hipGetDevice(&prev));
+  SNN_HIP(hipSetDevice(device));
+  static std::mutex mu;
+  static std::vector<int> ok;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)ok.size() <= device) ok.resize(device + 1, -1);
+  if (ok[device] < 0) {
+    hipDeviceProp_t p;
+    SNN_HIP(hipGetDeviceProperties(&p, device));
+    ok[device] = std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
   }
-};
-
-template <class F>
-snn_status guard(F&& f) {
-  try {
-    f();
-    g_err.clear();
-    return SNN_OK;
-  } catch (const Error& e) {
-    g_err = e.what();
-    return e.code;
-  } catch (const std::bad_alloc&) {
-    g_err = "host allocation failed";
-    return SNN_ENOMEM;
-  } catch (const std::exception& e) {
-    g_err = e.what();
-    return SNN_EDEVICE;
-  } catch (...) {
-    g_err = "unknown error";
-    return SNN_EDEVICE;
-  }
+  if (!ok[device]) fail(SNN_EDEVICE, "device is not gfx950 (this library is built for MI355X only)");
 }
+
+DeviceScope::~DeviceScope() {
+  if (prev >= 0) (void)hipSetDevice(prev);
+}
+
+void set_last_error(const std::string& msg) { g_err = msg; }
+
+namespace {
 
 constexpr double kU64 = 1.1102230246251565e-16;  // 2^-53
 
@@ -166,20 +145,6 @@ struct HostCtl {
   int64_t nnz;
 };
 
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// Carves aligned sub-arrays out of one buffer.
-struct Carver {
-  char* base;
-  size_t off = 0;
-  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
-  template <typename T>
-  T* take(size_t count) {
-    T* p = reinterpret_cast<T*>(base + off);
-    off += align256(sizeof(T) * std::max<size_t>(count, 1));
-    return p;
-  }
-};
 
 }  // namespace
 

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <new>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -23,6 +24,53 @@ struct Error : std::runtime_error {
 void check_hip(hipError_t e, const char* what, const char* file, int line);
 #define SNN_HIP(call) ::snn::check_hip((call), #call, __FILE__, __LINE__)
 #define SNN_LAUNCH_CHECK() ::snn::check_hip(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+// thread-local message returned by snn_last_error()
+void set_last_error(const std::string& msg);
+
+// Runs f, turning every exception into a status code (nothing crosses the C ABI).
+template <class F>
+snn_status guard(F&& f) {
+  try {
+    f();
+    set_last_error("");
+    return SNN_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return SNN_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return SNN_EDEVICE;
+  } catch (...) {
+    set_last_error("unknown error");
+    return SNN_EDEVICE;
+  }
+}
+
+// Selects a device for the duration of a call and checks that it is gfx950.
+struct DeviceScope {
+  int prev = -1;
+  explicit DeviceScope(int device);
+  ~DeviceScope();
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Carves 256-byte aligned sub-arrays out of one buffer (base nullptr: sizing pass).
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    T* p = reinterpret_cast<T*>(base + off);
+    off += align256(sizeof(T) * (count > 0 ? count : 1));
+    return p;
+  }
+};
 
 // ---------------------------------------------------------------- memory
 // Device allocations through snn_device.alloc (or hipMalloc).  Freed with
@@ -108,6 +156,9 @@ struct Index {
 // k_sort.hip
 void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n, int begin_bit, int end_bit,
                       hipStream_t s);
+size_t radix_sort_ws_bytes(int64_t n);
+void radix_sort_pairs_ws(uint32_t* keys, uint32_t* vals, int64_t n, int begin_bit, int end_bit, void* ws,
+                         hipStream_t s);
 size_t scan_scratch_bytes(int64_t n);
 // Exclusive scan of int32 counts into int64 offsets (out has n+1 entries,
 // out[n] = total).  scratch: scan_scratch_bytes(n).

@@ -64,6 +64,41 @@ def test_query_argument_errors():
     L.snn_index_free(None)  # no-op
 
 
+def test_batch_argument_errors():
+    L = B.lib()
+    dev = _dev()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: arguments are checked first
+    csr = B.snn_csr(0, 0, 0, 0, 0)
+
+    def inst(**kw):
+        a = dict(X=fake.value, Q=None, n=100, m=0, d=3, R=0.1, out=ctypes.pointer(csr))
+        a.update(kw)
+        return (B.snn_instance * 1)(B.snn_instance(**a))
+
+    h = ctypes.c_void_p()
+    ok = inst()
+    assert L.snn_batch_create(None, 0, ok, 1, None, ctypes.byref(h)) == B.SNN_EINVAL
+    assert L.snn_batch_create(ctypes.byref(dev), 0, ok, 0, None, ctypes.byref(h)) == B.SNN_EINVAL
+    assert L.snn_batch_create(ctypes.byref(dev), 0, None, 1, None, ctypes.byref(h)) == B.SNN_EINVAL
+    assert L.snn_batch_create(ctypes.byref(dev), 7, ok, 1, None, ctypes.byref(h)) == B.SNN_EINVAL
+    bad = [inst(X=None), inst(n=0), inst(d=0), inst(d=129), inst(R=-1.0), inst(R=float("nan")),
+           inst(m=5), inst(Q=fake.value, m=-1), inst(out=None)]
+    for b in bad:
+        assert L.snn_batch_create(ctypes.byref(dev), 0, b, 1, None, ctypes.byref(h)) == B.SNN_EINVAL
+        assert not h
+    o = B.snn_batch_options(2, 0, 0, 0, None)
+    assert L.snn_batch_create(ctypes.byref(dev), 0, ok, 1, ctypes.byref(o), ctypes.byref(h)) == B.SNN_EINVAL
+    o = B.snn_batch_options(0, 100, 0, 0, None)
+    assert L.snn_batch_create(ctypes.byref(dev), 0, ok, 1, ctypes.byref(o), ctypes.byref(h)) == B.SNN_EINVAL
+    assert b"tile_c" in L.snn_last_error()
+    st = B.snn_stats()
+    assert L.snn_batch_run(None, 3, ctypes.byref(st)) == B.SNN_EINVAL
+    inf = B.snn_batch_info_t()
+    assert L.snn_batch_info(None, ctypes.byref(inf)) == B.SNN_EINVAL
+    assert L.snn_query_batch(None, 0, ok, 1, None, None) == B.SNN_EINVAL
+    L.snn_batch_free(None)  # no-op
+
+
 def test_sort_argument_errors():
     L = B.lib()
     dev = _dev()

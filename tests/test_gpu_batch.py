@@ -1,0 +1,223 @@
+"""GPU parity of the batching form: many instances in one captured graph.
+
+Every instance's CSR must be bit-identical (row pointers and ids) to the
+brute-force oracle on that instance alone, distances within 1e-5 relative.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2212_07679_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2212_07679_amd import binding
+
+    return binding
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def check_same(got, ref, what=""):
+    row_ptr, col, dist = (t.cpu().numpy() for t in got[:3])
+    assert row_ptr.shape == ref.row_ptr.shape, what
+    bad = np.flatnonzero(row_ptr != ref.row_ptr)
+    assert bad.size == 0, f"{what}: row_ptr differs first at {bad[:5]}"
+    assert np.array_equal(col, ref.col), f"{what}: col differs"
+    zero = ref.dist == 0
+    assert np.all(dist[zero] == 0), what
+    nz = ~zero
+    rel = np.abs(dist[nz] - ref.dist[nz]) / ref.dist[nz]
+    assert rel.size == 0 or rel.max() <= 1e-5, f"{what}: max rel dist err {rel.max()}"
+
+
+def mixed_instances(dtype=np.float32, seed=0):
+    """Uneven sizes, dimensions and radii; self-queries, empty query sets,
+    R = 0, a single point, duplicates."""
+    g = np.random.default_rng([2212, 7679, 77, seed])
+    specs = [
+        # (n, m or None for self, d, R)
+        (3000, 300, 3, 0.08),
+        (1000, None, 8, 0.5),
+        (5000, 700, 32, 1.2),
+        (33, 40, 16, 0.4),
+        (1, 5, 3, 0.5),
+        (2000, 0, 8, 0.3),
+        (1500, 200, 1, 0.001),
+        (800, None, 50, 4.0),
+        (4000, 513, 13, 0.35),
+        (600, 100, 3, 0.0),
+        (257, None, 2, 0.05),
+        (3500, 1100, 42, 1.6),
+    ]
+    out = []
+    for n, m, d, R in specs:
+        P = g.random((n, d))
+        if n >= 10:
+            P[n // 2] = P[0]  # a duplicate
+        Q = None if m is None else g.random((m, d))
+        if Q is not None and m > 2 and n > 3:
+            Q[0] = P[3]  # a query on a data point
+        out.append((P.astype(dtype), None if Q is None else Q.astype(dtype), R))
+    return out
+
+
+def oracle_of(P, Q, R):
+    return oracle.brute_radius(P, P if Q is None else Q, R)
+
+
+def make_batch(B, insts, **kw):
+    dev = [(to_dev(P), None if Q is None else to_dev(Q), R) for P, Q, R in insts]
+    return dev, B.Batch(dev, **kw)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_batch_mixed_instances(B, dtype):
+    insts = mixed_instances(dtype)
+    say(f"batch of {len(insts)} mixed instances, dtype {np.dtype(dtype).name}")
+    dev, bt = make_batch(B, insts)
+    res, st = bt.run(stats=True)
+    for i, (P, Q, R) in enumerate(insts):
+        check_same(res[i], oracle_of(P, Q, R), f"instance {i} (n={P.shape[0]}, d={P.shape[1]})")
+    assert st["nnz"] == sum(int(r[0][-1]) for r in res)
+    assert st["pairs_window"] > 0 and st["pairs_executed"] >= st["pairs_window"] // 2
+    say(f"  info {bt.info()}, stats {st}")
+    bt.close()
+
+
+def test_batch_replay_new_data(B):
+    insts = mixed_instances(np.float32, seed=1)[:6]
+    dev, bt = make_batch(B, insts)
+    res = bt.run()
+    for i, (P, Q, R) in enumerate(insts):
+        check_same(res[i], oracle_of(P, Q, R), f"first run {i}")
+    # new data in the same buffers: index + query replay
+    g = np.random.default_rng(5)
+    new = []
+    for (Pd, Qd, R), (P, Q, _) in zip(dev, insts):
+        P2 = (g.random(P.shape) * 1.3).astype(np.float32)
+        Pd.copy_(torch.from_numpy(P2))
+        Q2 = None
+        if Q is not None:
+            Q2 = (g.random(Q.shape) * 1.3).astype(np.float32)
+            Qd.copy_(torch.from_numpy(Q2))
+        new.append((P2, Q2, R))
+    torch.cuda.synchronize()
+    for rep in range(2):
+        res = bt.run()
+        for i, (P, Q, R) in enumerate(new):
+            check_same(res[i], oracle_of(P, Q, R), f"replay {rep} instance {i}")
+    # new queries only: query-pass replay against the existing index
+    new_q = []
+    for (Pd, Qd, R), (P, Q, _) in zip(dev, new):
+        if Q is not None:
+            Q3 = (g.random(Q.shape) * 1.3).astype(np.float32)
+            Qd.copy_(torch.from_numpy(Q3))
+            Q = Q3
+        new_q.append((P, Q, R))
+    torch.cuda.synchronize()
+    res = bt.run(index=False)
+    for i, (P, Q, R) in enumerate(new_q):
+        check_same(res[i], oracle_of(P, Q, R), f"query-only replay {i}")
+    bt.close()
+
+
+def test_batch_overflow_growth(B):
+    # dense output: capacities of 1 force EOVERFLOW and the binding's regrowth
+    insts = [(W.blobs3d(n=3000, R=0.2, seed=3).P, None, 0.2),
+             (np.random.default_rng(2).random((2000, 8)).astype(np.float32), None, 0.6)]
+    dev, bt = make_batch(B, insts, nnz_caps=[1, 1])
+    res = bt.run()
+    for i, (P, Q, R) in enumerate(insts):
+        ref = oracle_of(P, Q, R)
+        assert ref.row_ptr[-1] > 10 * P.shape[0]
+        check_same(res[i], ref, f"overflow instance {i}")
+    bt.close()
+
+
+def test_batch_terms_choice_and_forced(B):
+    insts = mixed_instances(np.float32, seed=2)[:5]
+    for terms in (1, 3):
+        sub = [x for x in insts if terms == 1 or x[0].shape[1] <= 42]
+        dev, bt = make_batch(B, sub, terms=terms)
+        res, st = bt.run(stats=True)
+        assert st["terms_used"] == terms
+        for i, (P, Q, R) in enumerate(sub):
+            check_same(res[i], oracle_of(P, Q, R), f"terms {terms} instance {i}")
+        bt.close()
+
+
+def test_batch_autotune_and_cache(B, tmp_path):
+    insts = mixed_instances(np.float32, seed=3)[:4]
+    cache = str(tmp_path / "tune.txt")
+    dev, bt = make_batch(B, insts, autotune=True, tune_cache=cache)
+    info = bt.info()
+    say(f"  tuned {info}")
+    assert info["tile_c"] in (1024, 2048, 4096, 8192) and info["tile_g"] in (4, 8, 16)
+    assert info["tuned_query_ms"] > 0
+    res = bt.run()
+    for i, (P, Q, R) in enumerate(insts):
+        check_same(res[i], oracle_of(P, Q, R), f"tuned instance {i}")
+    bt.close()
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and lines[0].endswith(f"{info['tile_c']} {info['tile_g']}")
+    dev2, bt2 = make_batch(B, insts, autotune=True, tune_cache=cache)
+    assert bt2.info()["tile_c"] == info["tile_c"] and bt2.info()["tile_g"] == info["tile_g"]
+    bt2.close()
+
+
+def test_batch_nan_rejected(B):
+    P = np.random.default_rng(4).random((500, 3)).astype(np.float32)
+    Pn = P.copy()
+    Pn[7, 1] = np.nan
+    with pytest.raises(B.SnnError) as e:
+        make_batch(B, [(P, None, 0.1), (Pn, None, 0.1)])
+    assert e.value.status == B.SNN_EINVAL
+    Q = P[:20].copy()
+    dev, bt = make_batch(B, [(P, Q, 0.1)])
+    dev[0][1][3, 0] = float("inf")
+    with pytest.raises(B.SnnError) as e:
+        bt.run(index=False)
+    assert e.value.status == B.SNN_EINVAL
+    bt.close()
+
+
+def test_batch256_full(B):
+    """The 256-instance workload at full size: sampled rows of every instance
+    against the oracle, plus whole-output properties."""
+    insts = W.batch256()
+    say(f"batch256: {len(insts)} instances, sum n = {sum(w.n for w in insts)}, sum m = {sum(w.m for w in insts)}")
+    dev = [(to_dev(w.P), to_dev(w.Q), w.R) for w in insts]
+    bt = B.Batch(dev, autotune=False)
+    res, st = bt.run(stats=True)
+    say(f"  stats {st} info {bt.info()}")
+    g = np.random.default_rng([2212, 7679, 98])
+    for i, w in enumerate(insts):
+        row_ptr, col, dist = (t.cpu().numpy() for t in res[i])
+        assert row_ptr[0] == 0 and np.all(np.diff(row_ptr) >= 0) and row_ptr[-1] == col.size
+        rows = np.unique(np.concatenate([g.choice(w.m, size=min(3, w.m), replace=False), [0, w.m - 1]]))
+        ref = oracle.brute_radius(w.P, w.Q[rows], w.R)
+        for k, r in enumerate(rows):
+            a, b = row_ptr[r], row_ptr[r + 1]
+            assert np.array_equal(col[a:b], ref.col[ref.row_ptr[k]:ref.row_ptr[k + 1]]), f"instance {i} row {r}"
+            rd = ref.dist[ref.row_ptr[k]:ref.row_ptr[k + 1]]
+            assert np.all(np.abs(dist[a:b] - rd) <= 1e-5 * np.maximum(rd, 1e-30)), f"instance {i} row {r} dist"
+    bt.close()
