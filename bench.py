@@ -48,6 +48,9 @@ WORKLOADS = {
                          "self-query, R=4.0", precisions="auto", cpu_sample=200),
     "blobs3d": dict(desc="blobs3d: n=5e6 d=3 float32, 1000 Gaussian blobs (std 0.01) + 20% uniform background in "
                          "[0,1]^3, all-points self-query, R=0.005", precisions="auto", cpu_sample=500),
+    "batch256": dict(desc="batch256: 256 instances, n log-uniform in [1e3,1e5], d in {3,8,32}, float32 uniform in "
+                          "the unit cube, 10% of the points as queries, R for ~30 expected neighbours; one captured "
+                          "graph, autotuned tiles", precisions="mixed", cpu_sample=4000),
 }
 
 
@@ -186,6 +189,148 @@ def roofline(prec_used, terms, st, screen_ms, d):
             "frac": achieved / PEAK_FP64_VALU_OPS, "traffic": None}
 
 
+def oracle_cores():
+    try:
+        from threadpoolctl import threadpool_info
+
+        return int(max([p.get("num_threads", 1) for p in threadpool_info()] or [1]))
+    except Exception:
+        return os.cpu_count() or 1
+
+
+def main_batch(a):
+    """The batching form: all 256 instances in one captured graph.  One step
+    is one launch of the query graph over every instance (the indexes are
+    built by the index graph, timed separately); the same step is also timed
+    with the index pass included, and against a loop of per-instance calls
+    of the plain float64 kernel and of the mixed screen."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2212_07679_amd import binding
+    from paper_2212_07679_amd import workloads as W
+
+    spec = WORKLOADS["batch256"]
+    insts = W.batch256()
+    M = sum(w.m for w in insts)
+    print(f"[bench] batch256: {len(insts)} instances, sum n={sum(w.n for w in insts)} sum m={M}", file=sys.stderr,
+          flush=True)
+    dev = [(torch.from_numpy(w.P).cuda(), torch.from_numpy(w.Q).cuda(), w.R) for w in insts]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = binding.Batch(dev, autotune=True)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    info = plan.info()
+    print(f"[bench] plan created (incl. autotune) in {create_s:.2f} s: {info}", file=sys.stderr, flush=True)
+
+    def timed(fn, steps, stream):
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        out = None
+        for _ in range(steps):
+            out = fn()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / steps, out
+
+    for _ in range(a.warmup):
+        plan.run(index=False, stats=True)
+    screens = []
+
+    def q_step():
+        r = plan.run(index=False, stats=True)
+        screens.append(r[1]["screen_ms"])
+        return r
+
+    ms, (res, st) = timed(q_step, a.steps, plan.stream)
+    full_ms, _ = timed(lambda: plan.run(index=True, stats=True), max(1, a.steps // 2), plan.stream)
+    screen_ms = sum(screens) / len(screens)
+    print(f"[bench] batched query graph {ms:.3f} ms/step (screen {screen_ms:.3f} ms), index+query {full_ms:.3f} ms,"
+          f" stats {st}", file=sys.stderr, flush=True)
+
+    # per-instance calls of the single-instance path (indexes built outside the timing)
+    idxs = [binding.Index(X) for X, _, _ in dev]
+    loops = {}
+    for prec in ("fp64", "mixed"):
+        def loop():
+            return [ix.query(Q, R, precision=prec) for ix, (_, Q, R) in zip(idxs, dev)]
+
+        loop()
+        loops[prec], lres = timed(loop, max(1, min(a.steps, 3)), idxs[0].stream)
+        for i in range(len(insts)):
+            for x, y in zip(lres[i], res[i]):
+                assert torch.equal(x, y), f"instance {i}: batched and per-instance {prec} results differ"
+        print(f"[bench] per-instance loop {prec}: {loops[prec]:.3f} ms/step", file=sys.stderr, flush=True)
+    for ix in idxs:
+        ix.close()
+
+    cpu = None
+    if a.cpu_sample != 0:
+        budget = spec["cpu_sample"] if a.cpu_sample < 0 else a.cpu_sample
+        g = np.random.default_rng(1)
+        order = g.permutation(len(insts))
+        done = 0
+        tq = 0.0
+        used = 0
+        for i in order:
+            w = insts[i]
+            take = min(w.m, 64, budget - done)
+            if take <= 0:
+                break
+            ix = oracle.build_index(w.P)
+            t1 = time.perf_counter()
+            nb, _ = oracle.snn_query(ix, w.Q[:take], w.R)
+            tq += time.perf_counter() - t1
+            done += take
+            used += 1
+            rp, col, _ = (t.cpu().numpy() for t in res[i])
+            for k in range(min(take, 8)):
+                assert np.array_equal(col[rp[k]:rp[k + 1]], nb.col[nb.row_ptr[k]:nb.row_ptr[k + 1]]), \
+                    f"instance {i} query {k} differs from the oracle"
+        cpu = {"value": done / tq, "unit": "queries/s", "cores": oracle_cores(), "kind": "oracle",
+               "sample": f"first {done} queries (up to 64 each) of {used} seeded-random instances; "
+                         "index builds not timed"}
+
+    flops = st["flops_window"]
+    roof = None
+    if screen_ms > 0:
+        ach = flops / (screen_ms / 1e3)
+        roof = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_BF16_FLOPS / 1e12, "unit": "TFLOP/s",
+                "frac": ach / PEAK_BF16_FLOPS, "traffic": None}
+    line = {
+        "metric": "exact radius queries/s (batched instances)",
+        "value": M / (ms / 1e3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16+f64",
+        "data": "synthetic",
+        "config": {"workload": spec["desc"], "instances": len(insts), "sum_n": sum(w.n for w in insts), "sum_m": M,
+                   "tiles": info},
+        "index_and_query_ms_per_step": full_ms,
+        "per_instance_fp64_ms_per_step": loops["fp64"],
+        "per_instance_mixed_ms_per_step": loops["mixed"],
+        "speedup_vs_fp64_gpu": loops["fp64"] / ms,
+        "pairs_window": st["pairs_window"],
+        "pairs_executed": st["pairs_executed"],
+        "pairs_recheck": st["pairs_recheck"],
+        "recheck_fraction": st["pairs_recheck"] / max(st["pairs_window"], 1),
+        "nnz": st["nnz"],
+        "screen_ms": screen_ms,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -194,6 +339,9 @@ def main():
         sys.exit(2)
     if a.workload == "copyprobe":
         copy_probe(1 << 30)
+        return
+    if a.workload == "batch256":
+        main_batch(a)
         return
     import numpy as np
     import torch

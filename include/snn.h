@@ -104,6 +104,8 @@ typedef struct {
   int32_t terms_used;     /* MIXED: bf16 terms per coordinate */
   double screen_ms;       /* device time of the candidate-screen kernel */
   double total_ms;        /* device time of the whole call */
+  double flops_window;    /* algorithmic work of the window: sum over queries of
+                             2 d |J_q| (the flop count of eq. (ip2) per candidate) */
 } snn_stats;
 
 typedef struct snn_index_s* snn_index_t;

@@ -82,6 +82,7 @@ class snn_stats(ctypes.Structure):
         ("terms_used", ctypes.c_int32),
         ("screen_ms", ctypes.c_double),
         ("total_ms", ctypes.c_double),
+        ("flops_window", ctypes.c_double),
     ]
 
     def as_dict(self):

@@ -28,9 +28,6 @@
 
 namespace snn {
 
-void launch_row_sort_long(const int64_t* row_ptr, int32_t* col, float* dist, const int32_t* long_list,
-                          const unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s);
-
 namespace {
 
 constexpr int kChunkRows = 4096;  // rows per chunk of the centring / Gram passes
@@ -119,8 +116,8 @@ struct BatchPlan {
 
   // graphs: index pass, query pass, both
   hipGraphExec_t g_index = nullptr, g_query = nullptr, g_all = nullptr;
-  hipEvent_t ev_screen[2] = {nullptr, nullptr};
-  bool screen_timed = false;
+  bool screen_timed = false;  // device clock stamps bracket the screen in the query graph
+  double clock_khz = 0;       // frequency of that clock
   float last_tune_ms = 0;
   RunResult last;  // read-back of the latest query pass
 
@@ -292,7 +289,7 @@ void alloc_query(BatchPlan& p) {
     p.row_ptr_s = c.take<int64_t>(M + 1);
     p.nnz_base = c.take<int64_t>(p.count + 1);
     p.nnz = c.take<int64_t>(p.count);
-    p.lists = c.take<int32_t>(2 * M);
+    p.lists = c.take<int32_t>(4 * M);
   };
   Carver probe(nullptr);
   carve(probe);
@@ -402,16 +399,15 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   mx.h = p.h;
   mx.KA = p.KA;
   mx.KB = p.KA;
-  if (timed) SNN_HIP(hipEventRecord(p.ev_screen[0], s));
+  if (timed) batch_stamp(&p.ctl->stamp[0], s);
   launch_cand_mfma(qd, mx, p.screen_grid, s);
-  if (timed) SNN_HIP(hipEventRecord(p.ev_screen[1], s));
+  if (timed) batch_stamp(&p.ctl->stamp[1], s);
 
   batch_recheck(b, p.sv, p.q64, p.p64, p.qorig, p.perm, p.row_cnt, di.cus * 4, s);
   exclusive_scan_i32_to_i64(p.row_cnt, p.row_ptr, p.M, p.scan_ws, s);
   batch_scatter(p.sv, p.row_ptr, p.M, p.col_s, p.dist_s, p.stage_cap, di.cus * 8, s);
   batch_rowptr_guard(p.row_ptr, p.M, p.stage_cap, p.row_ptr_s, s);
-  launch_row_sort(p.row_ptr_s, p.M, p.col_s, p.dist_s, p.lists, p.ctl->list_counts, 0, s);
-  launch_row_sort_long(p.row_ptr_s, p.col_s, p.dist_s, p.lists + p.M, p.ctl->list_counts, p.tmp_col, p.tmp_dist, s);
+  launch_row_sort(p.row_ptr_s, p.M, p.col_s, p.dist_s, p.lists, p.ctl->list_counts, p.tmp_col, p.tmp_dist, s);
   batch_outputs(b, p.d_outs, p.row_ptr, p.col_s, p.dist_s, p.stage_cap, p.nnz_base, p.nnz, s);
 }
 
@@ -439,14 +435,7 @@ hipGraphExec_t capture(BatchPlan& p, F&& body) {
 void build_graphs(BatchPlan& p) {
   destroy_graphs(p);
   p.g_index = capture(p, [&](hipStream_t s) { enqueue_index(p, s, true); });
-  // the screen is bracketed by event-record nodes when the runtime captures them
-  p.screen_timed = true;
-  try {
-    p.g_query = capture(p, [&](hipStream_t s) { enqueue_query(p, s, true); });
-  } catch (const Error&) {
-    p.screen_timed = false;
-    p.g_query = capture(p, [&](hipStream_t s) { enqueue_query(p, s, false); });
-  }
+  p.g_query = capture(p, [&](hipStream_t s) { enqueue_query(p, s, true); });
   p.g_all = capture(p, [&](hipStream_t s) {
     enqueue_index(p, s, true);
     enqueue_query(p, s, false);
@@ -512,13 +501,8 @@ RunResult run_graphs(BatchPlan& p, bool do_index, bool do_query) {
     const bool st_over = !sv_over && rr.total > p.stage_cap;
     if (!sv_over && !st_over) {
       rr.screen_ms = -1;
-      if (p.screen_timed && !do_index) {
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, p.ev_screen[0], p.ev_screen[1]) == hipSuccess)
-          rr.screen_ms = ms;
-        else
-          (void)hipGetLastError();
-      }
+      if (!do_index && p.M > 0 && p.clock_khz > 0 && rr.ctl.stamp[1] > rr.ctl.stamp[0])
+        rr.screen_ms = (float)((double)(rr.ctl.stamp[1] - rr.ctl.stamp[0]) / p.clock_khz);
       p.last = rr;
       return rr;
     }
@@ -627,8 +611,6 @@ void autotune(BatchPlan& p, const char* cache_path) {
 void free_plan(BatchPlan* p) {
   if (!p) return;
   destroy_graphs(*p);
-  for (hipEvent_t& e : p->ev_screen)
-    if (e) (void)hipEventDestroy(e);
   for (Buffer* b : {&p->tables, &p->index, &p->query, &p->surv, &p->stage}) b->reset(p->arena);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   delete p;
@@ -644,6 +626,7 @@ void fill_stats(const BatchPlan& p, const RunResult& rr, snn_stats* st) {
   st->terms_used = p.max_terms;
   st->screen_ms = rr.screen_ms;
   st->total_ms = rr.graph_ms;
+  st->flops_window = (double)rr.ctl.flops;
 }
 
 void finish_outputs(BatchPlan& p, const RunResult& rr) {
@@ -707,8 +690,13 @@ BatchPlan* create_batch(const snn_device& devc, snn_dtype dtype, const snn_insta
       b.R2 = in[i].R * in[i].R;
     }
     SNN_HIP(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
-    SNN_HIP(hipEventCreate(&p.ev_screen[0]));
-    SNN_HIP(hipEventCreate(&p.ev_screen[1]));
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, devc.device) != hipSuccess) {
+      (void)hipGetLastError();
+      khz = 0;
+    }
+    p.clock_khz = khz;
+    p.screen_timed = khz > 0;
 
     // pre-pass: centring, direction and norms decide the operand terms
     p.T = 512;

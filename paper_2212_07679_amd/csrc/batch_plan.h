@@ -74,8 +74,9 @@ struct BatchCtl {
   unsigned long long pairs_window;
   unsigned long long flops;     // sum over queries of 2 d |J_q|
   unsigned long long executed;  // pairs the screen evaluated
-  unsigned long long list_counts[2];
+  unsigned long long list_counts[4];
   unsigned long long qbad;  // NaN or Inf in some Q
+  unsigned long long stamp[2];  // device clock around the screen kernel
   unsigned long long pad;
 };
 
@@ -131,6 +132,8 @@ void batch_rowptr_guard(const int64_t* row_ptr, int64_t M, int64_t cap, int64_t*
 void batch_outputs(const BatchDev& b, const BatchOut* outs, const int64_t* row_ptr, const int32_t* col,
                    const float* dist, int64_t cap, int64_t* nnz_base, int64_t* nnz, hipStream_t s);
 void batch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+// writes the device's constant-rate clock (hipDeviceAttributeWallClockRate) to *out
+void batch_stamp(unsigned long long* out, hipStream_t s);
 void batch_zero_i64(int64_t* p, int64_t n, hipStream_t s);
 
 }  // namespace snn

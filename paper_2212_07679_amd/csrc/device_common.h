@@ -112,25 +112,32 @@ __device__ __forceinline__ void stage_push(PairStage<kStage>& st, const PairSink
 }
 
 // Wave-aggregated push: every lane with `pred` pushes (q, j).  One LDS
-// atomic per wave.
+// atomic per wave; the pairs that no longer fit in the stage go straight to
+// the global list under one global reservation per wave.
 template <int kStage>
 __device__ __forceinline__ void stage_push_wave(PairStage<kStage>& st, const PairSink& sink, bool pred, int q,
                                                 int j) {
   uint64_t mask = __ballot(pred);
   if (mask == 0) return;
-  int cnt = __popcll(mask);
-  int leader = __ffsll((long long)mask) - 1;
-  int rank = __popcll(mask & ((1ull << lane_id()) - 1ull));
+  const int cnt = __popcll(mask);
+  const int leader = __ffsll((long long)mask) - 1;
+  const int rank = __popcll(mask & ((1ull << lane_id()) - 1ull));
   int base = 0;
   if (lane_id() == leader) base = atomicAdd(&st.count, cnt);
   base = __shfl(base, leader, kWave);
+  const int first_over = base > kStage ? base : kStage;
+  const int over = base + cnt - first_over;  // pairs past the stage's end
+  unsigned long long g = 0;
+  if (over > 0) {
+    if (lane_id() == leader) g = sink_reserve(sink, (unsigned long long)over);
+    g = __shfl(g, leader, kWave);
+  }
   if (pred) {
-    int pos = base + rank;
-    if (pos < kStage) {
+    const int pos = base + rank;
+    if (pos < kStage)
       st.buf[pos] = make_int2(q, j);
-    } else {
-      sink_store(sink, (long long)sink_reserve(sink, 1ull), make_int2(q, j));
-    }
+    else
+      sink_store(sink, (long long)g + (pos - first_over), make_int2(q, j));
   }
 }
 

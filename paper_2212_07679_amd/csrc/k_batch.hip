@@ -487,11 +487,13 @@ __global__ __launch_bounds__(kThreads) void kb_window(BatchDev b, const double* 
                                                      const int32_t* __restrict__ qorig, int32_t* __restrict__ tlo,
                                                      int32_t* __restrict__ thi, BatchCtl* __restrict__ ctl) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t s0 = s - lane_id();
   int lo = INT_MAX, hi = INT_MIN;
   unsigned long long cnt = 0, fl = 0;
+  // the wavefront's slots share one tile, hence one instance
+  const int i = s0 < b.MS ? __builtin_amdgcn_readfirstlane(b.tile_inst[s0 / b.T]) : 0;
   if (s < b.MS && qorig[s] >= 0) {
-    const int i = b.tile_inst[s / b.T];
-    const BatchInst in = b.inst[i];
+    const BatchInst& in = b.inst[i];
     const BatchDyn& dy = b.dyn[i];
     const double W = (dy.w_base + dy.eps_scale * qn[s]) * (1.0 + 8.0 * kU64);
     const double a = qa[s];
@@ -524,7 +526,6 @@ __global__ __launch_bounds__(kThreads) void kb_window(BatchDev b, const double* 
   }
   const int wlo = wave_min(lo), whi = wave_max(hi);
   const unsigned long long wc = wave_sum(cnt), wf = wave_sum(fl);
-  const int64_t s0 = s - lane_id();
   if (lane_id() == 0 && s0 < b.MS) {
     const int tile = (int)(s0 / b.T);
     if (wlo != INT_MAX) {
@@ -660,6 +661,10 @@ __global__ void kb_fill_f32(float* p, int64_t n, float v) {
     p[i] = v;
 }
 
+__global__ void kb_stamp(unsigned long long* out) {
+  if (threadIdx.x == 0) *out = (unsigned long long)wall_clock64();
+}
+
 __global__ void kb_zero_i64(int64_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0;
@@ -793,6 +798,11 @@ void batch_outputs(const BatchDev& b, const BatchOut* outs, const int64_t* row_p
 void batch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   if (n <= 0) return;
   kb_fill_f32<<<grid_for(n, 4096), kThreads, 0, s>>>(p, n, v);
+  SNN_LAUNCH_CHECK();
+}
+
+void batch_stamp(unsigned long long* out, hipStream_t s) {
+  kb_stamp<<<1, 64, 0, s>>>(out);
   SNN_LAUNCH_CHECK();
 }
 

@@ -156,15 +156,20 @@ __device__ __forceinline__ void screen_step(const bf16x8 (&A)[QB][NS], const f32
 #pragma unroll
     for (int b = 0; b < QB; ++b)
       acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][s], B[s < NL ? s : s - NL], acc[b], 0, 0, 0);
-  bool any = false;
+  uint64_t pm[QB];  // wave masks: lanes with a passing accumulator in block b
+  uint64_t any = 0;
 #pragma unroll
-  for (int b = 0; b < QB; ++b) any |= (max16(acc[b]) >= hj);
-  if (__ballot(any)) {
-    // rare: collect each lane's passing accumulators as a bit mask, then
+  for (int b = 0; b < QB; ++b) {
+    pm[b] = __ballot(max16(acc[b]) >= hj);
+    any |= pm[b];
+  }
+  if (any) {
+    // uncommon: collect each lane's passing accumulators as a bit mask, then
     // append one pair per lane per round until every mask is empty
     const int jj = j0 + jr;
 #pragma unroll
     for (int b = 0; b < QB; ++b) {
+      if (!pm[b]) continue;
       uint32_t bits = 0;
 #pragma unroll
       for (int r = 0; r < 16; ++r) bits |= (acc[b][r] >= hj ? 1u : 0u) << r;
@@ -258,9 +263,9 @@ typedef void (*MixedKernel)(QueryDev, MixedDev);
 
 // Query blocks of 32 per wavefront: every candidate load feeds QB product
 // chains, so more blocks mean fewer candidate bytes through the vector
-// memory return path per matrix product.  Short chains (NS <= 4) afford four
-// blocks within the register file, longer ones two.
-constexpr int qb_for(int ns) { return ns <= 4 ? 4 : 2; }
+// memory return path per matrix product.  Short chains (NS <= 3) afford four
+// blocks within a register budget of two waves per SIMD, longer ones two.
+constexpr int qb_for(int ns) { return ns <= 3 ? 4 : 2; }
 
 // (slices per product chain, slices loaded per candidate row)
 MixedKernel pick_kernel(int KA, int KB) {

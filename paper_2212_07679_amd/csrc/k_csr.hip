@@ -62,79 +62,71 @@ __global__ __launch_bounds__(kThreads) void k_scatter(Survivors sv, const int64_
   }
 }
 
-// rows of <= 16: insertion sort by one lane; others go to the wave / block lists
-__global__ __launch_bounds__(kThreads) void k_row_sort_small(const int64_t* __restrict__ row_ptr, int64_t m,
-                                                            int32_t* __restrict__ col, float* __restrict__ dist,
-                                                            int32_t* __restrict__ mid_list,
-                                                            int32_t* __restrict__ long_list,
-                                                            unsigned long long* __restrict__ counts) {
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = row_ptr[r], e = row_ptr[r + 1];
-    const int64_t len = e - b;
-    if (len <= 1) continue;
-    if (len <= 16) {
-      int32_t c[16];
-      float dd[16];
-      for (int i = 0; i < len; ++i) {
-        c[i] = col[b + i];
-        dd[i] = dist[b + i];
-      }
-      for (int i = 1; i < len; ++i) {
-        int32_t ci = c[i];
-        float di = dd[i];
-        int k = i - 1;
-        while (k >= 0 && c[k] > ci) {
-          c[k + 1] = c[k];
-          dd[k + 1] = dd[k];
-          --k;
-        }
-        c[k + 1] = ci;
-        dd[k + 1] = di;
-      }
-      for (int i = 0; i < len; ++i) {
-        col[b + i] = c[i];
-        dist[b + i] = dd[i];
-      }
-    } else if (len <= 64) {
-      mid_list[atomicAdd(&counts[0], 1ull)] = (int32_t)r;
-    } else {
-      long_list[atomicAdd(&counts[1], 1ull)] = (int32_t)r;
+// Rows by length class: 2..16, 17..32, 33..64 and longer, each appended to
+// its own list (one atomic per wavefront and class).
+__global__ __launch_bounds__(kThreads) void k_row_classify(const int64_t* __restrict__ row_ptr, int64_t m,
+                                                          int32_t* __restrict__ lists,
+                                                          unsigned long long* __restrict__ counts) {
+  const int lane = lane_id();
+  for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x / kWave) * kWave; r0 < m;
+       r0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = r0 + lane;
+    int cls = -1;
+    if (r < m) {
+      const int64_t len = row_ptr[r + 1] - row_ptr[r];
+      cls = len <= 1 ? -1 : len <= 16 ? 0 : len <= 32 ? 1 : len <= 64 ? 2 : 3;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const uint64_t mask = __ballot(cls == c);
+      if (!mask) continue;
+      const int leader = __ffsll((unsigned long long)mask) - 1;
+      unsigned long long base = 0;
+      if (lane == leader) base = atomicAdd(&counts[c], (unsigned long long)__popcll(mask));
+      base = __shfl(base, leader, kWave);
+      if (cls == c) lists[(int64_t)c * m + (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)r;
     }
   }
 }
 
-// one wavefront per row of 17..64 entries: bitonic sort across lanes
-__global__ __launch_bounds__(kThreads) void k_row_sort_wave(const int64_t* __restrict__ row_ptr,
-                                                           int32_t* __restrict__ col, float* __restrict__ dist,
-                                                           const int32_t* __restrict__ mid_list,
-                                                           const unsigned long long* __restrict__ counts) {
-  const long long nrows = (long long)counts[0];
-  const int lane = lane_id();
+// Rows of at most SEG entries, 64 / SEG rows per wavefront: each group of SEG
+// lanes holds one row as (id << 32 | dist bits) and runs a bitonic network
+// across its lanes (partners at distance < SEG stay inside the group).  Ids
+// are unique within a row, so the order is by id alone.
+template <int SEG>
+__global__ __launch_bounds__(kThreads) void k_row_sort_seg(const int64_t* __restrict__ row_ptr,
+                                                          int32_t* __restrict__ col, float* __restrict__ dist,
+                                                          const int32_t* __restrict__ list,
+                                                          const unsigned long long* __restrict__ count) {
+  constexpr int kRows = kWave / SEG;
+  const long long nrows = (long long)*count;
+  const int lane = lane_id(), sub = lane % SEG, grp = lane / SEG;
   const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const long long nwaves = ((long long)gridDim.x * blockDim.x) / kWave;
-  for (long long w = wave; w < nrows; w += nwaves) {
-    const int r = mid_list[w];
-    const int64_t b = row_ptr[r], e = row_ptr[r + 1];
-    const int len = (int)(e - b);
-    int32_t c = lane < len ? col[b + lane] : INT_MAX;
-    float dd = lane < len ? dist[b + lane] : 0.f;
-    for (int k = 2; k <= kWave; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        const int32_t oc = __shfl_xor(c, j, kWave);
-        const float od = __shfl_xor(dd, j, kWave);
-        const bool up = ((lane & k) == 0);
-        const bool lower = ((lane & j) == 0);
-        const bool take_min = (up == lower);
-        const bool swap = take_min ? (oc < c) : (oc > c);
-        if (swap) {
-          c = oc;
-          dd = od;
-        }
+  for (long long w = wave; w * kRows < nrows; w += nwaves) {
+    const long long k = w * kRows + grp;
+    int64_t b = 0;
+    int len = 0;
+    if (k < nrows) {
+      const int r = list[k];
+      b = row_ptr[r];
+      len = (int)(row_ptr[r + 1] - b);
+    }
+    uint64_t key = ~0ull;
+    if (sub < len)
+      key = ((uint64_t)(uint32_t)col[b + sub] << 32) | (uint64_t)__builtin_bit_cast(uint32_t, dist[b + sub]);
+#pragma unroll
+    for (int kk = 2; kk <= SEG; kk <<= 1) {
+#pragma unroll
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        const uint64_t o = __shfl_xor(key, j, kWave);
+        const bool take_min = ((sub & kk) == 0) == ((sub & j) == 0);
+        key = take_min ? (o < key ? o : key) : (o > key ? o : key);
       }
     }
-    if (lane < len) {
-      col[b + lane] = c;
-      dist[b + lane] = dd;
+    if (sub < len) {
+      col[b + sub] = (int32_t)(key >> 32);
+      dist[b + sub] = __builtin_bit_cast(float, (uint32_t)(key & 0xffffffffu));
     }
   }
 }
@@ -174,7 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_block(const int64_t* __re
                                                             int32_t* __restrict__ tmp_col,
                                                             float* __restrict__ tmp_dist) {
   __shared__ uint64_t a[kBlockSort];
-  const long long nrows = (long long)counts[1];
+  const long long nrows = (long long)*counts;
   for (long long w = blockIdx.x; w < nrows; w += gridDim.x) {
     const int r = long_list[w];
     const int64_t b = row_ptr[r], e = row_ptr[r + 1];
@@ -299,23 +291,23 @@ void launch_scatter(const Survivors& sv, const int64_t* row_ptr, int32_t* col, f
   SNN_LAUNCH_CHECK();
 }
 
-// lists: 2*m int32 (mid rows, long rows) followed by nothing; list_counts: 2
-// counters; the tmp arrays for long-row merges reuse lists' tail when given.
+// lists: 4 m int32 (one list per length class); list_counts: 4 counters;
+// tmp_col / tmp_dist: nnz entries, needed only when a row exceeds 4096.
+// Fixed grids (the counts stay on the device), so the sequence can be captured.
 void launch_row_sort(const int64_t* row_ptr, int64_t m, int32_t* col, float* dist, int32_t* lists,
-                     unsigned long long* list_counts, int grid, hipStream_t s) {
-  (void)grid;
-  k_fill_u64<<<1, 64, 0, s>>>(list_counts, 2, 0ull);
+                     unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s) {
+  k_fill_u64<<<1, 64, 0, s>>>(list_counts, 4, 0ull);
   SNN_LAUNCH_CHECK();
   if (m <= 0) return;
-  k_row_sort_small<<<grid_for(m, 8192), kThreads, 0, s>>>(row_ptr, m, col, dist, lists, lists + m, list_counts);
+  k_row_classify<<<grid_for(m, 4096), kThreads, 0, s>>>(row_ptr, m, lists, list_counts);
   SNN_LAUNCH_CHECK();
-  k_row_sort_wave<<<1024, kThreads, 0, s>>>(row_ptr, col, dist, lists, list_counts);
+  k_row_sort_seg<16><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists, list_counts);
   SNN_LAUNCH_CHECK();
-}
-
-void launch_row_sort_long(const int64_t* row_ptr, int32_t* col, float* dist, const int32_t* long_list,
-                          const unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s) {
-  k_row_sort_block<<<512, kThreads, 0, s>>>(row_ptr, col, dist, long_list, list_counts, tmp_col, tmp_dist);
+  k_row_sort_seg<32><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists + m, list_counts + 1);
+  SNN_LAUNCH_CHECK();
+  k_row_sort_seg<64><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists + 2 * m, list_counts + 2);
+  SNN_LAUNCH_CHECK();
+  k_row_sort_block<<<512, kThreads, 0, s>>>(row_ptr, col, dist, lists + 3 * m, list_counts + 3, tmp_col, tmp_dist);
   SNN_LAUNCH_CHECK();
 }
 

@@ -17,8 +17,6 @@
 
 namespace snn {
 
-void launch_row_sort_long(const int64_t* row_ptr, int32_t* col, float* dist, const int32_t* long_list,
-                          const unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s);
 void launch_row_max(const int32_t* row_cnt, int64_t m, unsigned long long* out, hipStream_t s);
 void launch_self_qnorm(const float* ynorm, int64_t n, double* out, hipStream_t s);
 
@@ -133,7 +131,7 @@ struct Ctl {
   unsigned long long counters[kMaxXcd];
   unsigned long long survivors;
   unsigned long long pairs_window;
-  unsigned long long list_counts[2];
+  unsigned long long list_counts[4];
   unsigned long long row_max;
   unsigned long long pad0;
   int bad;
@@ -286,7 +284,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
                                             scan_scratch_bytes(nbuckets)}));
     p.ctl = c.take<Ctl>(1);
     p.row_cnt = c.take<int32_t>(std::max<int64_t>(m, 1));
-    p.lists = c.take<int32_t>(2 * std::max<int64_t>(m, 1));
+    p.lists = c.take<int32_t>(4 * std::max<int64_t>(m, 1));
     const bool mix = prec == SNN_PREC_MIXED;
     p.qop = c.take<uint16_t>(mix && !self ? (size_t)m * ka_of(terms) : 1);
     p.cthr = c.take<float>(mix ? std::max<int64_t>(m, 1) : 1);
@@ -437,6 +435,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       out->nnz = hc.nnz;
       if (st) {
         st->pairs_window = (int64_t)hc.ctl.pairs_window;
+        st->flops_window = 2.0 * d * (double)hc.ctl.pairs_window;
         st->pairs_recheck = (int64_t)hc.ctl.survivors;
         st->nnz = hc.nnz;
         st->precision_used = prec;
@@ -464,8 +463,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     tmp_col = tc.take<int32_t>(hc.nnz);
     tmp_dist = tc.take<float>(hc.nnz);
   }
-  launch_row_sort(out->row_ptr, m, out->col, out->dist, P.lists, P.ctl->list_counts, 0, s);
-  launch_row_sort_long(out->row_ptr, out->col, out->dist, P.lists + m, P.ctl->list_counts, tmp_col, tmp_dist, s);
+  launch_row_sort(out->row_ptr, m, out->col, out->dist, P.lists, P.ctl->list_counts, tmp_col, tmp_dist, s);
 
   if (st) {
     SNN_HIP(hipEventRecord(ev[3], s));
