@@ -403,9 +403,9 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   launch_cand_mfma(qd, mx, p.screen_grid, s);
   if (timed) batch_stamp(&p.ctl->stamp[1], s);
 
-  batch_recheck(b, p.sv, p.q64, p.p64, p.qorig, p.perm, p.row_cnt, di.cus * 4, s);
+  batch_recheck(b, p.sv, p.q64, p.p64, p.qorig, p.perm, p.row_cnt, di.cus * 16, s);
   exclusive_scan_i32_to_i64(p.row_cnt, p.row_ptr, p.M, p.scan_ws, s);
-  batch_scatter(p.sv, p.row_ptr, p.M, p.col_s, p.dist_s, p.stage_cap, di.cus * 8, s);
+  batch_scatter(p.sv, p.row_ptr, p.M, p.col_s, p.dist_s, p.stage_cap, di.cus * 16, s);
   batch_rowptr_guard(p.row_ptr, p.M, p.stage_cap, p.row_ptr_s, s);
   launch_row_sort(p.row_ptr_s, p.M, p.col_s, p.dist_s, p.lists, p.ctl->list_counts, p.tmp_col, p.tmp_dist, s);
   batch_outputs(b, p.d_outs, p.row_ptr, p.col_s, p.dist_s, p.stage_cap, p.nnz_base, p.nnz, s);

@@ -141,6 +141,33 @@ __device__ __forceinline__ void stage_push_wave(PairStage<kStage>& st, const Pai
   }
 }
 
+// Per-wavefront staging of pairs in LDS.  The fill count is wave-uniform
+// (the caller keeps it in a scalar register), so a push is one ballot, a lane
+// rank and an LDS store: no atomics and no cross-lane shuffles.  The caller
+// flushes whenever fewer free entries remain than its largest burst of
+// pushes, and once at the end; a flush takes one global reservation.
+__device__ __forceinline__ void wave_push(int2* buf, int& wcnt, bool p, int q, int j) {
+  const uint64_t m = __ballot(p);
+  if (!m) return;
+  if (p) {
+    const int rank =
+        (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    buf[wcnt + rank] = make_int2(q, j);
+  }
+  wcnt += __popcll(m);
+}
+
+__device__ __forceinline__ void wave_flush(int2* buf, int& wcnt, const PairSink& sink) {
+  if (wcnt == 0) return;
+  __builtin_amdgcn_wave_barrier();  // the lanes' LDS stores come before these reads
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = sink_reserve(sink, (unsigned long long)wcnt);
+  base = __shfl(base, 0, kWave);
+  for (int i = lane_id(); i < wcnt; i += kWave) sink_store(sink, (long long)base + i, buf[i]);
+  __builtin_amdgcn_wave_barrier();  // and these reads before the next pushes
+  wcnt = 0;
+}
+
 // Moves the staged pairs to the global list and empties the stage.  All
 // threads of the block call it right after a __syncthreads(), with no push in
 // flight; the caller's next barrier orders the reset before new pushes.

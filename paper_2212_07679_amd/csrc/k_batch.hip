@@ -449,11 +449,13 @@ __global__ __launch_bounds__(kThreads) void kb_query_gather(
     const uint32_t* __restrict__ qidx, const double* __restrict__ qa_in, const double* __restrict__ qn_in,
     double* __restrict__ q64, int32_t* __restrict__ qorig, double* __restrict__ qa, double* __restrict__ qn,
     uint16_t* __restrict__ qop, float* __restrict__ cthr) {
-  const int KA = b.KA;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < b.M; t += (int64_t)gridDim.x * blockDim.x) {
+  // one wavefront per query: lanes cover the coordinates and the operand row
+  const int KA = b.KA, lane = lane_id();
+  for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; t < b.M;
+       t += ((int64_t)gridDim.x * blockDim.x) / kWave) {
     const uint32_t p = qidx[t];
     const int i = (int)qikey[t];
-    const BatchInst in = b.inst[i];
+    const BatchInst& in = b.inst[i];
     const int d = in.d;
     const int64_t g = (int64_t)qval[p];
     const int64_t r = t - in.qin_off;
@@ -462,20 +464,51 @@ __global__ __launch_bounds__(kThreads) void kb_query_gather(
     const double* m = mu + in.vec_off;
     double* qrow = q64 + in.q64_off + r * in.dp;
     double nn = 0.0;
-    for (int k = 0; k < d; ++k) {
-      const double qv = (double)q[k];
+    for (int k = lane; k < in.dp; k += kWave) {
+      const double qv = k < d ? (double)q[k] : 0.0;
       qrow[k] = qv;
-      const float y = (float)(qv - m[k]);
-      nn += (double)y * (double)y;
+      if (k < d) {
+        const float y = (float)(qv - m[k]);
+        nn += (double)y * (double)y;
+      }
     }
-    for (int k = d; k < in.dp; ++k) qrow[k] = 0.0;
-    qorig[s] = (int32_t)g;
-    qa[s] = qa_in[g];
-    qn[s] = qn_in[g];
-    uint4* row = reinterpret_cast<uint4*>(qop + s * KA);
-    write_operand_row<T>(in.terms, d, KA, q, m, true, [&](int c8) { return row + c8; });
-    cthr[s] = screen_threshold(b.dyn[i].mb, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
+    // any summation order of the squares stays within the gamma_{d+1} bound
+    // the start value allows for
+    nn = wave_sum(nn);
+    uint16_t* row = qop + s * KA;
+    for (int k = lane; k < KA; k += kWave) row[k] = operand_value<T>(in.terms, d, k, q, m, true);
+    if (lane == 0) {
+      qorig[s] = (int32_t)g;
+      qa[s] = qa_in[g];
+      qn[s] = qn_in[g];
+      cthr[s] = screen_threshold(b.dyn[i].mb, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
+    }
   }
+}
+
+// lo: first index with key >= lv, hi: first index with key > hv, over the n
+// sorted keys (the two binary searches interleaved: independent loads).
+__device__ __forceinline__ void window_bounds(const double* __restrict__ key, int n, double lv, double hv, int& lo,
+                                              int& hi) {
+  int l0 = 0, l1 = n, h0 = 0, h1 = n;
+  while (l0 < l1 || h0 < h1) {
+    const int lm = (l0 + l1) >> 1, hm = (h0 + h1) >> 1;
+    const double kl = key[min(lm, n - 1)], kh = key[min(hm, n - 1)];
+    if (l0 < l1) {
+      if (kl < lv)
+        l0 = lm + 1;
+      else
+        l1 = lm;
+    }
+    if (h0 < h1) {
+      if (kh <= hv)
+        h0 = hm + 1;
+      else
+        h1 = hm;
+    }
+  }
+  lo = l0;
+  hi = h0;
 }
 
 // Windows J_q of every query slot by binary search inside its instance's
@@ -486,55 +519,52 @@ __global__ __launch_bounds__(kThreads) void kb_window(BatchDev b, const double* 
                                                      const double* __restrict__ qa, const double* __restrict__ qn,
                                                      const int32_t* __restrict__ qorig, int32_t* __restrict__ tlo,
                                                      int32_t* __restrict__ thi, BatchCtl* __restrict__ ctl) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t s0 = s - lane_id();
-  int lo = INT_MAX, hi = INT_MIN;
-  unsigned long long cnt = 0, fl = 0;
-  // the wavefront's slots share one tile, hence one instance
-  const int i = s0 < b.MS ? __builtin_amdgcn_readfirstlane(b.tile_inst[s0 / b.T]) : 0;
-  if (s < b.MS && qorig[s] >= 0) {
-    const BatchInst& in = b.inst[i];
-    const BatchDyn& dy = b.dyn[i];
-    const double W = (dy.w_base + dy.eps_scale * qn[s]) * (1.0 + 8.0 * kU64);
-    const double a = qa[s];
-    const double lv = nextafter(a - W, -INFINITY);
-    const double hv = nextafter(a + W, INFINITY);
-    const int base = (int)in.row_base, n = (int)in.n;
-    int l0 = 0, l1 = n, h0 = 0, h1 = n;
-    while (l0 < l1 || h0 < h1) {
-      const int lm = (l0 + l1) >> 1, hm = (h0 + h1) >> 1;
-      const double kl = key[base + min(lm, n - 1)], kh = key[base + min(hm, n - 1)];
-      if (l0 < l1) {
-        if (kl < lv)
-          l0 = lm + 1;
-        else
-          l1 = lm;
-      }
-      if (h0 < h1) {
-        if (kh <= hv)
-          h0 = hm + 1;
-        else
-          h1 = hm;
+  __shared__ unsigned long long red[2][kThreads / kWave];
+  unsigned long long acc_cnt = 0, acc_fl = 0;  // this lane's totals over the grid-stride loop
+  for (int64_t s0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x / kWave) * kWave; s0 < b.MS;
+       s0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = s0 + lane_id();
+    int lo = INT_MAX, hi = INT_MIN;
+    // the wavefront's slots share one tile, hence one instance
+    const int i = __builtin_amdgcn_readfirstlane(b.tile_inst[s0 / b.T]);
+    if (s < b.MS && qorig[s] >= 0) {
+      const BatchInst& in = b.inst[i];
+      const BatchDyn& dy = b.dyn[i];
+      const double W = (dy.w_base + dy.eps_scale * qn[s]) * (1.0 + 8.0 * kU64);
+      const double a = qa[s];
+      const int base = (int)in.row_base, n = (int)in.n;
+      int l0, h0;
+      window_bounds(key + base, n, nextafter(a - W, -INFINITY), nextafter(a + W, INFINITY), l0, h0);
+      if (h0 > l0) {
+        lo = base + l0;
+        hi = base + h0;
+        acc_cnt += (unsigned long long)(h0 - l0);
+        acc_fl += (unsigned long long)(h0 - l0) * 2ull * (unsigned long long)in.d;
       }
     }
-    if (h0 > l0) {
-      lo = base + l0;
-      hi = base + h0;
-      cnt = (unsigned long long)(h0 - l0);
-      fl = cnt * 2ull * (unsigned long long)in.d;
-    }
-  }
-  const int wlo = wave_min(lo), whi = wave_max(hi);
-  const unsigned long long wc = wave_sum(cnt), wf = wave_sum(fl);
-  if (lane_id() == 0 && s0 < b.MS) {
-    const int tile = (int)(s0 / b.T);
-    if (wlo != INT_MAX) {
+    const int wlo = wave_min(lo), whi = wave_max(hi);
+    if (lane_id() == 0 && wlo != INT_MAX) {
+      const int tile = (int)(s0 / b.T);
       atomicMin(&tlo[tile], wlo);
       atomicMax(&thi[tile], whi);
     }
-    if (wc) {
-      atomicAdd(&ctl->pairs_window, wc);
-      atomicAdd(&ctl->flops, wf);
+  }
+  // one pair of counter atomics per block (same-address atomics serialise)
+  const unsigned long long wc = wave_sum(acc_cnt), wf = wave_sum(acc_fl);
+  if (lane_id() == 0) {
+    red[0][threadIdx.x / kWave] = wc;
+    red[1][threadIdx.x / kWave] = wf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long c = 0, f = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) {
+      c += red[0][w];
+      f += red[1][w];
+    }
+    if (c) {
+      atomicAdd(&ctl->pairs_window, c);
+      atomicAdd(&ctl->flops, f);
     }
   }
 }
@@ -751,13 +781,13 @@ void batch_query_gather(snn_dtype dt, const BatchDev& b, const double* mu, const
                         const uint32_t* qikey, const uint32_t* qidx, const double* qa_in, const double* qn_in,
                         double* q64, int32_t* qorig, double* qa, double* qn, uint16_t* qop, float* cthr,
                         hipStream_t s) {
-  SNN_DT_LAUNCH(kb_query_gather, grid_for(b.M, 16384), kThreads, b, mu, qval, qikey, qidx, qa_in, qn_in, q64, qorig,
-                qa, qn, qop, cthr);
+  SNN_DT_LAUNCH(kb_query_gather, grid_for(b.M * (int64_t)kWave, 16384), kThreads, b, mu, qval, qikey, qidx, qa_in,
+                qn_in, q64, qorig, qa, qn, qop, cthr);
 }
 
 void batch_windows(const BatchDev& b, const double* key, const double* qa, const double* qn, const int32_t* qorig,
                    int32_t* tlo, int32_t* thi, BatchCtl* ctl, hipStream_t s) {
-  kb_window<<<(unsigned)((b.MS + kThreads - 1) / kThreads), kThreads, 0, s>>>(b, key, qa, qn, qorig, tlo, thi, ctl);
+  kb_window<<<grid_for(b.MS, 1024), kThreads, 0, s>>>(b, key, qa, qn, qorig, tlo, thi, ctl);
   SNN_LAUNCH_CHECK();
 }
 

@@ -57,7 +57,9 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
-constexpr int kStage = 2048;
+// per-wavefront pair stage: flushed when fewer than one query block's worth
+// of pushes (16 x 64) would fit
+constexpr int kWaveStage = 1536;
 
 // Out-of-sample queries: operands and thresholds from the float64 rows.
 __global__ __launch_bounds__(kThreads) void k_mixed_qprep(const double* __restrict__ q64, int64_t m, int d, int dp,
@@ -146,7 +148,7 @@ __device__ __forceinline__ void load_step(bf16x8 (&B)[NL], float& h, __amdgpu_bu
 template <int NS, int QB, int NL>
 __device__ __forceinline__ void screen_step(const bf16x8 (&A)[QB][NS], const f32x16 (&Cin)[QB],
                                             const bf16x8 (&B)[NL], float hv, int jr, int span, int j0,
-                                            int64_t q0, int half, PairStage<kStage>& st, const PairSink& sink) {
+                                            int64_t q0, int half, int2* wbuf, int& wcnt, const PairSink& sink) {
   const float hj = jr < span ? hv : INFINITY;
   f32x16 acc[QB];
 #pragma unroll
@@ -164,8 +166,9 @@ __device__ __forceinline__ void screen_step(const bf16x8 (&A)[QB][NS], const f32
     any |= pm[b];
   }
   if (any) {
-    // uncommon: collect each lane's passing accumulators as a bit mask, then
-    // append one pair per lane per round until every mask is empty
+    // uncommon: in each query block with a passing lane, collect each lane's
+    // passing accumulators as a bit mask, then push one pair per lane per
+    // round into the wavefront's LDS stage (at most 16 x 64 per block)
     const int jj = j0 + jr;
 #pragma unroll
     for (int b = 0; b < QB; ++b) {
@@ -177,25 +180,25 @@ __device__ __forceinline__ void screen_step(const bf16x8 (&A)[QB][NS], const f32
         const bool p = bits != 0;
         const int r = p ? __ffs(bits) - 1 : 0;
         bits &= bits - 1;
-        const int qi = (int)q0 + b * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-        stage_push_wave(st, sink, p, qi, jj);
+        wave_push(wbuf, wcnt, p, (int)q0 + b * 32 + 8 * (r >> 2) + 4 * half + (r & 3), jj);
       }
+      if (wcnt > kWaveStage - 16 * kWave) wave_flush(wbuf, wcnt, sink);
     }
   }
 }
 
 template <int NS, int QB, int NL>
 __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) {
-  __shared__ PairStage<kStage> st;
+  __shared__ int2 wstage[kWaves][kWaveStage];
   __shared__ long long s_unit;
-  stage_init(st);
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int l32 = lane & 31, half = lane >> 5;
   const int xcd = blockIdx.x % q.nxcd;
   const int KA = x.KA;
+  int2* wbuf = wstage[wave];
+  int wcnt = 0;  // wave-uniform fill of wbuf
   for (;;) {
     __syncthreads();
-    stage_drain(st, q.sink);
     if (threadIdx.x == 0) s_unit = next_unit(q, xcd);
     __syncthreads();
     const int64_t u = uniform_i64(s_unit);
@@ -250,13 +253,13 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
     load_step<NL>(B0, h0, rc, rh, voff_c, voff_h, 0);
     for (int it = 0; it < nsteps; it += 2) {
       load_step<NL>(B1, h1, rc, rh, voff_c, voff_h, it + 1);
-      screen_step<NS, QB, NL>(A, Cin, B0, h0, it * 32 + l32, span, (int)j0, q0, half, st, q.sink);
+      screen_step<NS, QB, NL>(A, Cin, B0, h0, it * 32 + l32, span, (int)j0, q0, half, wbuf, wcnt, q.sink);
       if (it + 1 >= nsteps) break;
       load_step<NL>(B0, h0, rc, rh, voff_c, voff_h, it + 2);
-      screen_step<NS, QB, NL>(A, Cin, B1, h1, (it + 1) * 32 + l32, span, (int)j0, q0, half, st, q.sink);
+      screen_step<NS, QB, NL>(A, Cin, B1, h1, (it + 1) * 32 + l32, span, (int)j0, q0, half, wbuf, wcnt, q.sink);
     }
   }
-  stage_flush(st, q.sink);
+  wave_flush(wbuf, wcnt, q.sink);
 }
 
 typedef void (*MixedKernel)(QueryDev, MixedDev);

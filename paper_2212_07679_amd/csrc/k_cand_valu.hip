@@ -28,7 +28,8 @@ namespace snn {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kStage = 2048;
+// per-wavefront pair stage, flushed when fewer than one batch of pushes would fit
+constexpr int kWaveStage = 1024;
 constexpr int kBatch = 8;
 
 typedef const __attribute__((address_space(4))) float cfloat;
@@ -84,14 +85,14 @@ template <int D>
 __global__ __launch_bounds__(kThreads) void k_cand_valu(QueryDev q, const float* __restrict__ vq,
                                                        const float* __restrict__ vc) {
   constexpr int DV = ((D + 1 + 3) / 4) * 4;
-  __shared__ PairStage<kStage> st;
+  __shared__ int2 wstage[kThreads / kWave][kWaveStage];
   __shared__ long long s_unit;
-  stage_init(st);
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int xcd = blockIdx.x % q.nxcd;
+  int2* wbuf = wstage[wave];
+  int wcnt = 0;  // wave-uniform fill of wbuf
   for (;;) {
     __syncthreads();
-    stage_drain(st, q.sink);
     if (threadIdx.x == 0) s_unit = next_unit(q, xcd);
     __syncthreads();
     const int64_t u = uniform_i64(s_unit);
@@ -132,8 +133,8 @@ __global__ __launch_bounds__(kThreads) void k_cand_valu(QueryDev q, const float*
       }
       if (any) {
 #pragma unroll
-        for (int cc = 0; cc < NB; ++cc)
-          if (mk[cc]) stage_push_wave(st, q.sink, (mk[cc] >> lane) & 1ull, (int)qi, (int)(jb + cc));
+        for (int cc = 0; cc < NB; ++cc) wave_push(wbuf, wcnt, (mk[cc] >> lane) & 1ull, (int)qi, (int)(jb + cc));
+        if (wcnt > kWaveStage - NB * kWave) wave_flush(wbuf, wcnt, q.sink);
       }
     }
     for (; jb < j1; ++jb) {
@@ -141,11 +142,11 @@ __global__ __launch_bounds__(kThreads) void k_cand_valu(QueryDev q, const float*
       float acc = cq;
 #pragma unroll
       for (int k = 0; k < D; ++k) acc = fmaf(y[k], cr[k], acc);
-      stage_push_wave(st, q.sink, acc >= cr[D], (int)qi, (int)jb);
+      wave_push(wbuf, wcnt, acc >= cr[D], (int)qi, (int)jb);
+      if (wcnt > kWaveStage - kWave) wave_flush(wbuf, wcnt, q.sink);
     }
   }
-  __syncthreads();
-  stage_drain(st, q.sink);
+  wave_flush(wbuf, wcnt, q.sink);
 }
 
 typedef void (*ValuKernel)(QueryDev, const float*, const float*);

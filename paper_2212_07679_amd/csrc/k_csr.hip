@@ -6,9 +6,10 @@
 //             Section 3.2).  Neighbours take a slot in their row.
 //  (scan)     row counts -> row_ptr
 //  k_scatter  neighbours into their rows
-//  row sort   ids ascending within each row: rows of <= 16 entries by one
-//             lane, <= 64 by one wavefront (bitonic across lanes), longer by
-//             one workgroup (bitonic in LDS, then merge passes).
+//  row sort   ids ascending within each row: rows of <= 16 / 32 / 64 entries
+//             by lane groups of that size (bitonic across lanes, 4 / 2 / 1 rows
+//             per wavefront), longer rows by one workgroup (bitonic in LDS,
+//             then merge passes).
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -62,30 +63,38 @@ __global__ __launch_bounds__(kThreads) void k_scatter(Survivors sv, const int64_
   }
 }
 
+__device__ __forceinline__ int row_class(const int64_t* __restrict__ row_ptr, int64_t r) {
+  const int64_t len = row_ptr[r + 1] - row_ptr[r];
+  return len <= 1 ? -1 : len <= 16 ? 0 : len <= 32 ? 1 : len <= 64 ? 2 : 3;
+}
+
 // Rows by length class: 2..16, 17..32, 33..64 and longer, each appended to
-// its own list (one atomic per wavefront and class).
+// its own list.  A block owns a contiguous range of rows: it counts its rows
+// per class in LDS, reserves each class's space with one global atomic, then
+// writes (so the global counters see one atomic per block and class).
 __global__ __launch_bounds__(kThreads) void k_row_classify(const int64_t* __restrict__ row_ptr, int64_t m,
                                                           int32_t* __restrict__ lists,
                                                           unsigned long long* __restrict__ counts) {
-  const int lane = lane_id();
-  for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x / kWave) * kWave; r0 < m;
-       r0 += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = r0 + lane;
-    int cls = -1;
-    if (r < m) {
-      const int64_t len = row_ptr[r + 1] - row_ptr[r];
-      cls = len <= 1 ? -1 : len <= 16 ? 0 : len <= 32 ? 1 : len <= 64 ? 2 : 3;
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const uint64_t mask = __ballot(cls == c);
-      if (!mask) continue;
-      const int leader = __ffsll((unsigned long long)mask) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(&counts[c], (unsigned long long)__popcll(mask));
-      base = __shfl(base, leader, kWave);
-      if (cls == c) lists[(int64_t)c * m + (int64_t)base + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)r;
-    }
+  __shared__ int cnt[4];
+  __shared__ unsigned long long base[4];
+  const int t = threadIdx.x;
+  const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(m, r0 + per);
+  if (t < 4) cnt[t] = 0;
+  __syncthreads();
+  for (int64_t r = r0 + t; r < r1; r += kThreads) {
+    const int c = row_class(row_ptr, r);
+    if (c >= 0) atomicAdd(&cnt[c], 1);
+  }
+  __syncthreads();
+  if (t < 4) {
+    base[t] = cnt[t] ? atomicAdd(&counts[t], (unsigned long long)cnt[t]) : 0ull;
+    cnt[t] = 0;
+  }
+  __syncthreads();
+  for (int64_t r = r0 + t; r < r1; r += kThreads) {
+    const int c = row_class(row_ptr, r);
+    if (c >= 0) lists[(int64_t)c * m + (int64_t)base[c] + atomicAdd(&cnt[c], 1)] = (int32_t)r;
   }
 }
 
@@ -299,7 +308,7 @@ void launch_row_sort(const int64_t* row_ptr, int64_t m, int32_t* col, float* dis
   k_fill_u64<<<1, 64, 0, s>>>(list_counts, 4, 0ull);
   SNN_LAUNCH_CHECK();
   if (m <= 0) return;
-  k_row_classify<<<grid_for(m, 4096), kThreads, 0, s>>>(row_ptr, m, lists, list_counts);
+  k_row_classify<<<grid_for(m, 1024), kThreads, 0, s>>>(row_ptr, m, lists, list_counts);
   SNN_LAUNCH_CHECK();
   k_row_sort_seg<16><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists, list_counts);
   SNN_LAUNCH_CHECK();

@@ -93,54 +93,63 @@ __global__ __launch_bounds__(kThreads) void k_window(const double* __restrict__ 
                                                     int32_t* __restrict__ thi,
                                                     unsigned long long* __restrict__ pairs_window) {
   const double u = 1.1102230246251565e-16;
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int lo = INT_MAX, hi = INT_MIN;
-  long long cnt = 0;
-  if (s < m) {
-    const double W = (w_base + eps_scale * qnorm[s]) * (1.0 + 8.0 * u);
-    const double a = qalpha[s];
-    const double lv = nextafter(a - W, -INFINITY);
-    const double hv = nextafter(a + W, INFINITY);
-    // lo: first index with key >= lv;  hi: first index with key > hv
-    int l0 = 0, l1 = n, h0 = 0, h1 = n;
-    while (l0 < l1 || h0 < h1) {
-      const int lm = (l0 + l1) >> 1, hm = (h0 + h1) >> 1;
-      const double kl = key[min(lm, n - 1)], kh = key[min(hm, n - 1)];
-      if (l0 < l1) {
-        if (kl < lv)
-          l0 = lm + 1;
-        else
-          l1 = lm;
+  __shared__ unsigned long long red[kThreads / kWave];
+  unsigned long long acc = 0;  // this lane's window sizes over the grid-stride loop
+  for (int64_t s0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x / kWave) * kWave; s0 < m;
+       s0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = s0 + lane_id();
+    int lo = INT_MAX, hi = INT_MIN;
+    if (s < m) {
+      const double W = (w_base + eps_scale * qnorm[s]) * (1.0 + 8.0 * u);
+      const double a = qalpha[s];
+      const double lv = nextafter(a - W, -INFINITY);
+      const double hv = nextafter(a + W, INFINITY);
+      // lo: first index with key >= lv;  hi: first index with key > hv
+      int l0 = 0, l1 = n, h0 = 0, h1 = n;
+      while (l0 < l1 || h0 < h1) {
+        const int lm = (l0 + l1) >> 1, hm = (h0 + h1) >> 1;
+        const double kl = key[min(lm, n - 1)], kh = key[min(hm, n - 1)];
+        if (l0 < l1) {
+          if (kl < lv)
+            l0 = lm + 1;
+          else
+            l1 = lm;
+        }
+        if (h0 < h1) {
+          if (kh <= hv)
+            h0 = hm + 1;
+          else
+            h1 = hm;
+        }
       }
-      if (h0 < h1) {
-        if (kh <= hv)
-          h0 = hm + 1;
-        else
-          h1 = hm;
+      lo = l0;
+      hi = h0;
+      if (lo_out) {
+        lo_out[s] = lo;
+        hi_out[s] = hi;
+      }
+      if (hi > lo) {
+        acc += (unsigned long long)(hi - lo);
+      } else {  // empty window: neutral for the tile union
+        lo = INT_MAX;
+        hi = INT_MIN;
       }
     }
-    lo = l0;
-    hi = h0;
-    if (lo_out) {
-      lo_out[s] = lo;
-      hi_out[s] = hi;
-    }
-    cnt = hi > lo ? hi - lo : 0;
-    if (hi <= lo) {  // empty window: neutral for the tile union
-      lo = INT_MAX;
-      hi = INT_MIN;
-    }
-  }
-  int wlo = wave_min(lo), whi = wave_max(hi);
-  long long wc = wave_sum(cnt);
-  const int64_t s0 = s - lane_id();
-  if (lane_id() == 0 && s0 < m) {
-    const int tile = (int)(s0 / T);
-    if (wlo != INT_MAX) {
+    const int wlo = wave_min(lo), whi = wave_max(hi);
+    if (lane_id() == 0 && wlo != INT_MAX) {
+      const int tile = (int)(s0 / T);
       atomicMin(&tlo[tile], wlo);
       atomicMax(&thi[tile], whi);
     }
-    atomicAdd(pairs_window, (unsigned long long)wc);
+  }
+  // one counter atomic per block (same-address atomics serialise)
+  const unsigned long long wc = wave_sum(acc);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = wc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long c = 0;
+    for (int w = 0; w < kThreads / kWave; ++w) c += red[w];
+    if (c) atomicAdd(pairs_window, c);
   }
 }
 
@@ -240,9 +249,8 @@ void launch_windows(const double* key, int n, const double* qalpha, const double
   k_tile_init<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles);
   SNN_LAUNCH_CHECK();
   if (m > 0) {
-    k_window<<<(unsigned)((m + kThreads - 1) / kThreads), kThreads, 0, s>>>(key, n, qalpha, qnorm, m, w_base,
-                                                                           eps_scale, T, lo, hi, tlo, thi,
-                                                                           pairs_window);
+    k_window<<<grid_for(m, 2048), kThreads, 0, s>>>(key, n, qalpha, qnorm, m, w_base, eps_scale, T, lo, hi, tlo,
+                                                    thi, pairs_window);
     SNN_LAUNCH_CHECK();
   }
   k_tile_units<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles, CH, align, units);

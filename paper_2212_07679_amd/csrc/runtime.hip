@@ -424,7 +424,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
         launch_cand_fp64(qd, grid, s);
     }
     if (st) SNN_HIP(hipEventRecord(ev[2], s));
-    launch_recheck(qd, sv, P.row_cnt, di.cus * 2, s);
+    launch_recheck(qd, sv, P.row_cnt, di.cus * 16, s);
     exclusive_scan_i32_to_i64(P.row_cnt, out->row_ptr, m, P.scan_scratch, s);
     launch_row_max(P.row_cnt, m, &P.ctl->row_max, s);
     SNN_HIP(hipMemcpyAsync(&hc.ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -447,7 +447,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
                       (long long)hc.nnz);
         throw Error(SNN_EOVERFLOW, buf);
       }
-      launch_scatter(sv, out->row_ptr, out->col, out->dist, di.cus * 8, s);
+      launch_scatter(sv, out->row_ptr, out->col, out->dist, di.cus * 16, s);
       break;
     }
     cap = (long long)(hc.ctl.survivors * 5 / 4) + 1024;
