@@ -84,6 +84,11 @@ typedef struct {
   /* queries per tile / candidates per work unit; 0 = automatic. */
   int tile_q;
   int tile_c;
+  /* snn_query_self only: 0 (default) scans each unordered pair once, from
+   * the query that comes first in score order, and reports it in both rows
+   * (the squared distance is exactly symmetric); 1 scans every (query,
+   * candidate) pair.  Both give the same result. */
+  int full_self_scan;
 } snn_options;
 
 typedef struct {

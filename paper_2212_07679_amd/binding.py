@@ -59,6 +59,7 @@ class snn_options(ctypes.Structure):
         ("mixed_terms", ctypes.c_int),
         ("tile_q", ctypes.c_int),
         ("tile_c", ctypes.c_int),
+        ("full_self_scan", ctypes.c_int),
     ]
 
 
@@ -277,10 +278,10 @@ class Index:
         except Exception:
             pass
 
-    def _opts(self, precision: str, terms: int, tile_q: int, tile_c: int) -> snn_options:
+    def _opts(self, precision: str, terms: int, tile_q: int, tile_c: int, full_self_scan: bool = False) -> snn_options:
         if precision not in PRECISION:
             raise SnnError(SNN_EINVAL, f"precision must be one of {sorted(PRECISION)}")
-        return snn_options(PRECISION[precision], int(terms), int(tile_q), int(tile_c))
+        return snn_options(PRECISION[precision], int(terms), int(tile_q), int(tile_c), 1 if full_self_scan else 0)
 
     def _run(self, Q: Optional[torch.Tensor], m: int, R: float, opts: snn_options, nnz_cap: Optional[int],
              want_stats: bool):
@@ -320,9 +321,11 @@ class Index:
         return self._run(Q, Q.shape[0], R, self._opts(precision, terms, tile_q, tile_c), nnz_cap, stats)
 
     def query_self(self, R: float, precision: str = "auto", terms: int = 0, tile_q: int = 0, tile_c: int = 0,
-                   nnz_cap: Optional[int] = None, stats: bool = False):
-        """Every data row as a query (rows in original data order)."""
-        return self._run(None, self.n, R, self._opts(precision, terms, tile_q, tile_c), nnz_cap, stats)
+                   nnz_cap: Optional[int] = None, stats: bool = False, full_self_scan: bool = False):
+        """Every data row as a query (rows in original data order).  Each
+        unordered pair is scanned once unless ``full_self_scan``."""
+        return self._run(None, self.n, R, self._opts(precision, terms, tile_q, tile_c, full_self_scan), nnz_cap,
+                         stats)
 
     def view(self) -> dict:
         """Index internals copied into new tensors (for checks)."""

@@ -313,6 +313,7 @@ void alloc_survivors(BatchPlan& p, int64_t cap) {
   Carver c(p.surv.ptr);
   carve(c);
   p.sv.cap = cap;
+  p.sv.per = 1;
   p.sv.count = &p.ctl->survivors;
   p.sv_cap = cap;
 }

@@ -31,28 +31,48 @@ __global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, 
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (long long)gridDim.x * blockDim.x) {
     const int2 pr = sv.pairs[i];
-    const double* qp = q.q64 + (int64_t)pr.x * q.dp;
-    const double* pp = q.p64 + (int64_t)pr.y * q.dp;
+    const int64_t r0 = (int64_t)sv.per * i;
+    // symmetric self-query: a pair below the diagonal is the mirror of one
+    // the other query of the tile decides
+    bool keep = !q.sym || pr.y >= pr.x;
     double s = 0.0;
-    for (int k = 0; k < d; ++k) {
-      const double t = pp[k] - qp[k];
-      s = s + t * t;
+    if (keep) {
+      const double* qp = q.q64 + (int64_t)pr.x * q.dp;
+      const double* pp = q.p64 + (int64_t)pr.y * q.dp;
+      for (int k = 0; k < d; ++k) {
+        const double t = pp[k] - qp[k];
+        s = s + t * t;
+      }
+      keep = s <= q.R2;
     }
-    if (s <= q.R2) {
+    if (keep) {
       const int qo = q.qorig[pr.x];
-      sv.res_q[i] = qo;
-      sv.res_id[i] = q.perm[pr.y];
-      sv.res_dist[i] = (float)sqrt(s);
-      sv.res_slot[i] = atomicAdd(&row_cnt[qo], 1);
+      const int id = q.perm[pr.y];
+      const float dist = (float)sqrt(s);
+      sv.res_q[r0] = qo;
+      sv.res_id[r0] = id;
+      sv.res_dist[r0] = dist;
+      sv.res_slot[r0] = atomicAdd(&row_cnt[qo], 1);
+      if (sv.per == 2) {
+        if (pr.y != pr.x) {  // the mirrored pair, in the candidate's row
+          sv.res_q[r0 + 1] = id;
+          sv.res_id[r0 + 1] = qo;
+          sv.res_dist[r0 + 1] = dist;
+          sv.res_slot[r0 + 1] = atomicAdd(&row_cnt[id], 1);
+        } else {
+          sv.res_q[r0 + 1] = -1;
+        }
+      }
     } else {
-      sv.res_q[i] = -1;
+      sv.res_q[r0] = -1;
+      if (sv.per == 2) sv.res_q[r0 + 1] = -1;
     }
   }
 }
 
 __global__ __launch_bounds__(kThreads) void k_scatter(Survivors sv, const int64_t* __restrict__ row_ptr,
                                                      int32_t* __restrict__ col, float* __restrict__ dist) {
-  const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count);
+  const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count) * sv.per;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (long long)gridDim.x * blockDim.x) {
     const int qo = sv.res_q[i];

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kThreads) void k_query_gather(const T* __restrict__
 __global__ __launch_bounds__(kThreads) void k_window(const double* __restrict__ key, int n,
                                                     const double* __restrict__ qalpha,
                                                     const double* __restrict__ qnorm, int64_t m, double w_base,
-                                                    double eps_scale, int T, int32_t* __restrict__ lo_out,
+                                                    double eps_scale, int T, int sym, int32_t* __restrict__ lo_out,
                                                     int32_t* __restrict__ hi_out, int32_t* __restrict__ tlo,
                                                     int32_t* __restrict__ thi,
                                                     unsigned long long* __restrict__ pairs_window) {
@@ -129,7 +129,9 @@ __global__ __launch_bounds__(kThreads) void k_window(const double* __restrict__ 
         hi_out[s] = hi;
       }
       if (hi > lo) {
-        acc += (unsigned long long)(hi - lo);
+        // symmetric self-query: only the candidates at or after s are scanned
+        const int from = sym ? max(lo, (int)s) : lo;
+        if (hi > from) acc += (unsigned long long)(hi - from);
       } else {  // empty window: neutral for the tile union
         lo = INT_MAX;
         hi = INT_MIN;
@@ -161,9 +163,10 @@ __global__ void k_tile_init(int32_t* __restrict__ tlo, int32_t* __restrict__ thi
 }
 
 __global__ void k_tile_units(int32_t* __restrict__ tlo, int32_t* __restrict__ thi, int ntiles, int CH, int align,
-                             int32_t* __restrict__ units) {
+                             int sym_T, int32_t* __restrict__ units) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
     int a = tlo[t], b = thi[t];
+    if (sym_T > 0 && a != INT_MAX) a = max(a, t * sym_T);  // symmetric self-query: from the tile's first row
     if (a == INT_MAX || b <= a) {
       tlo[t] = 0;
       thi[t] = 0;
@@ -202,7 +205,7 @@ void launch_tile_init(int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s) {
 }
 
 void launch_tile_units(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int32_t* units, hipStream_t s) {
-  k_tile_units<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles, CH, align, units);
+  k_tile_units<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles, CH, align, 0, units);
   SNN_LAUNCH_CHECK();
 }
 
@@ -244,16 +247,16 @@ void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, 
 }
 
 void launch_windows(const double* key, int n, const double* qalpha, const double* qnorm, int64_t m, double w_base,
-                    double eps_scale, int T, int CH, int align, int ntiles, int32_t* lo, int32_t* hi, int32_t* tlo,
-                    int32_t* thi, int32_t* units, unsigned long long* pairs_window, hipStream_t s) {
+                    double eps_scale, int T, int CH, int align, int ntiles, int sym, int32_t* lo, int32_t* hi,
+                    int32_t* tlo, int32_t* thi, int32_t* units, unsigned long long* pairs_window, hipStream_t s) {
   k_tile_init<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles);
   SNN_LAUNCH_CHECK();
   if (m > 0) {
-    k_window<<<grid_for(m, 2048), kThreads, 0, s>>>(key, n, qalpha, qnorm, m, w_base, eps_scale, T, lo, hi, tlo,
-                                                    thi, pairs_window);
+    k_window<<<grid_for(m, 2048), kThreads, 0, s>>>(key, n, qalpha, qnorm, m, w_base, eps_scale, T, sym, lo, hi,
+                                                    tlo, thi, pairs_window);
     SNN_LAUNCH_CHECK();
   }
-  k_tile_units<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles, CH, align, units);
+  k_tile_units<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles, CH, align, sym ? T : 0, units);
   SNN_LAUNCH_CHECK();
 }
 

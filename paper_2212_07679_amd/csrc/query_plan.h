@@ -44,6 +44,10 @@ struct QueryDev {
   const int64_t* group_off;      // ngroups + 1
   unsigned long long* counters;  // kMaxXcd work counters (zeroed per call)
   int nxcd;
+  // Symmetric self-query: query position s is data position s, tiles scan
+  // candidates from their own first row on, and a pair (s, j) with j >= s is
+  // decided once and reported in both rows (S is exactly symmetric).
+  int sym;
   PairSink sink;
 };
 
@@ -97,9 +101,11 @@ void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, 
                          double* q64, int32_t* qorig, double* qalpha, double* qnorm, hipStream_t s);
 // align: tile windows are widened outward to multiples of `align` rows (the
 // mixed screen reads 32-row blocks); extra candidates never change results.
+// sym: symmetric self-query (counts only candidates j >= s, tiles start at
+// their first row; see QueryDev::sym)
 void launch_windows(const double* key, int n, const double* qalpha, const double* qnorm, int64_t m, double w_base,
-                    double eps_scale, int T, int CH, int align, int ntiles, int32_t* lo, int32_t* hi, int32_t* tlo,
-                    int32_t* thi, int32_t* units, unsigned long long* pairs_window, hipStream_t s);
+                    double eps_scale, int T, int CH, int align, int ntiles, int sym, int32_t* lo, int32_t* hi,
+                    int32_t* tlo, int32_t* thi, int32_t* units, unsigned long long* pairs_window, hipStream_t s);
 
 void launch_tile_init(int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s);
 void launch_tile_units(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int32_t* units, hipStream_t s);
@@ -202,7 +208,8 @@ struct Survivors {
   int2* pairs;                 // (query score position, data score position)
   unsigned long long* count;   // may exceed cap (then pairs were dropped)
   long long cap;
-  int32_t* res_q;              // caller query row or -1
+  int per;                     // results per pair: 1, or 2 for a symmetric self-query
+  int32_t* res_q;              // per * cap: caller query row or -1
   int32_t* res_id;
   float* res_dist;
   int32_t* res_slot;

@@ -173,6 +173,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   if (o.mixed_terms != 0 && o.mixed_terms != 1 && o.mixed_terms != 3) fail(SNN_EINVAL, "mixed_terms must be 0, 1 or 3");
   if (o.tile_q < 0 || o.tile_c < 0) fail(SNN_EINVAL, "tile sizes must be >= 0");
   if (o.tile_q % 64 != 0) fail(SNN_EINVAL, "tile_q must be a multiple of 64");
+  if (o.full_self_scan != 0 && o.full_self_scan != 1) fail(SNN_EINVAL, "full_self_scan must be 0 or 1");
 
   DeviceScope scope(ix.arena.dev().device);
   hipStream_t s = ix.arena.stream();
@@ -329,9 +330,10 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const double u32 = std::ldexp(1.0, -24);
   const double w_base = R * ix.vnorm * (1.0 + 4.0 * gamma64(d + 3)) + ix.key_eps;
   const double eps_scale = 1.01 * (u32 + gamma64(d + 2)) * (1.0 + u32) * ix.vnorm;
-  launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, CH,
-                 prec == SNN_PREC_MIXED ? 32 : 1, ntiles, P.lo, P.hi, P.tlo,
-                 P.thi, P.units, &P.ctl->pairs_window, s);
+  // self-queries scan each unordered pair once (S is exactly symmetric)
+  const int sym = (self && !o.full_self_scan) ? 1 : 0;
+  launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, CH, prec == SNN_PREC_MIXED ? 32 : 1,
+                 ntiles, sym, P.lo, P.hi, P.tlo, P.thi, P.units, &P.ctl->pairs_window, s);
   // chunk-major work order inside groups of G score-adjacent tiles (L2 reuse)
   const int G = prec == SNN_PREC_FP64 ? 16 : 8;
   const int ngroups = (ntiles + G - 1) / G;
@@ -358,6 +360,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   qd.group_off = P.unit_off;
   qd.counters = P.ctl->counters;
   qd.nxcd = di.xcds;
+  qd.sym = sym;
 
   MixedDev mx{};
   if (prec == SNN_PREC_MIXED) {
@@ -385,20 +388,24 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   }
 
   // survivors: capacity remembered on the index, grown on overflow
-  long long cap = std::max<long long>(1 << 16, (long long)(ix.ws[1].bytes / 24));
+  // bytes per survivor: the pair, and per result row, column, distance, slot
+  const int per = sym ? 2 : 1;
+  const size_t per_bytes = 8 + 16 * (size_t)per;
+  long long cap = std::max<long long>(1 << 16, (long long)(ix.ws[1].bytes / per_bytes));
   HostCtl hc{};
   for (int attempt = 0;; ++attempt) {
     // five arrays, each padded to 256 bytes by the carver
-    const size_t need = (size_t)cap * 24 + 2048;
+    const size_t need = (size_t)cap * per_bytes + 2048;
     ix.ws[1].ensure(ix.arena, need);
-    cap = (long long)((ix.ws[1].bytes - 2048) / 24);
+    cap = (long long)((ix.ws[1].bytes - 2048) / per_bytes);
     Carver sc(ix.ws[1].ptr);
     Survivors sv{};
+    sv.per = per;
     sv.pairs = sc.take<int2>(cap);
-    sv.res_q = sc.take<int32_t>(cap);
-    sv.res_id = sc.take<int32_t>(cap);
-    sv.res_dist = sc.take<float>(cap);
-    sv.res_slot = sc.take<int32_t>(cap);
+    sv.res_q = sc.take<int32_t>(cap * per);
+    sv.res_id = sc.take<int32_t>(cap * per);
+    sv.res_dist = sc.take<float>(cap * per);
+    sv.res_slot = sc.take<int32_t>(cap * per);
     // recompute cap to fit the carve exactly
     sv.cap = cap;
     sv.count = &P.ctl->survivors;

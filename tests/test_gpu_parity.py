@@ -285,6 +285,22 @@ def test_auto_policy(B):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "mixed", "fp64"])
+def test_symmetric_self_scan(B, prec):
+    # each unordered pair scanned once and reported in both rows: identical
+    # output to the full scan, with about half the window pairs
+    say(f"symmetric self scan {prec}")
+    w = W.blobs3d(n=30_000, R=0.03, seed=11)
+    ref, _ = oracle.snn_query(oracle.build_index(w.P), w.P, w.R)
+    idx = B.Index(to_dev(w.P))
+    half = idx.query_self(w.R, precision=prec, stats=True)
+    full = idx.query_self(w.R, precision=prec, stats=True, full_self_scan=True)
+    check_same(half, ref, f"symmetric {prec}")
+    check_same(full, ref, f"full {prec}")
+    hw, fw = half[3]["pairs_window"], full[3]["pairs_window"]
+    assert 0.45 * fw < hw < 0.6 * fw, (hw, fw)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed", "fp64"])
 def test_dense_self_output(B, prec):
     # many neighbours per row: survivor staging drains, wave/block row sorts
     say(f"dense self {prec}")
