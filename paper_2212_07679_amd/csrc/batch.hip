@@ -289,7 +289,7 @@ void alloc_query(BatchPlan& p) {
     p.row_ptr_s = c.take<int64_t>(M + 1);
     p.nnz_base = c.take<int64_t>(p.count + 1);
     p.nnz = c.take<int64_t>(p.count);
-    p.lists = c.take<int32_t>(4 * M);
+    p.lists = c.take<int32_t>((size_t)row_sort_lists() * M);
   };
   Carver probe(nullptr);
   carve(probe);

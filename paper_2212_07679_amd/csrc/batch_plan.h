@@ -74,7 +74,7 @@ struct BatchCtl {
   unsigned long long pairs_window;
   unsigned long long flops;     // sum over queries of 2 d |J_q|
   unsigned long long executed;  // pairs the screen evaluated
-  unsigned long long list_counts[4];
+  unsigned long long list_counts[8];
   unsigned long long qbad;  // NaN or Inf in some Q
   unsigned long long stamp[2];  // device clock around the screen kernel
   unsigned long long pad;

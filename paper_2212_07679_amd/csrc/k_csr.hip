@@ -83,31 +83,42 @@ __global__ __launch_bounds__(kThreads) void k_scatter(Survivors sv, const int64_
   }
 }
 
+// Row length classes: 2..16, 17..32, 33..64, 65..128, 129..256, 257..512 and
+// longer (kRowClasses lists).
+constexpr int kRowClasses = 7;
+
 __device__ __forceinline__ int row_class(const int64_t* __restrict__ row_ptr, int64_t r) {
   const int64_t len = row_ptr[r + 1] - row_ptr[r];
-  return len <= 1 ? -1 : len <= 16 ? 0 : len <= 32 ? 1 : len <= 64 ? 2 : 3;
+  if (len <= 1) return -1;
+  if (len <= 16) return 0;
+  if (len <= 32) return 1;
+  if (len <= 64) return 2;
+  if (len <= 128) return 3;
+  if (len <= 256) return 4;
+  if (len <= 512) return 5;
+  return 6;
 }
 
-// Rows by length class: 2..16, 17..32, 33..64 and longer, each appended to
-// its own list.  A block owns a contiguous range of rows: it counts its rows
-// per class in LDS, reserves each class's space with one global atomic, then
-// writes (so the global counters see one atomic per block and class).
+// Rows by length class, each class appended to its own list.  A block owns a
+// contiguous range of rows: it counts its rows per class in LDS, reserves
+// each class's space with one global atomic, then writes (so the global
+// counters see one atomic per block and class).
 __global__ __launch_bounds__(kThreads) void k_row_classify(const int64_t* __restrict__ row_ptr, int64_t m,
                                                           int32_t* __restrict__ lists,
                                                           unsigned long long* __restrict__ counts) {
-  __shared__ int cnt[4];
-  __shared__ unsigned long long base[4];
+  __shared__ int cnt[kRowClasses];
+  __shared__ unsigned long long base[kRowClasses];
   const int t = threadIdx.x;
   const int64_t per = (m + gridDim.x - 1) / gridDim.x;
   const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(m, r0 + per);
-  if (t < 4) cnt[t] = 0;
+  if (t < kRowClasses) cnt[t] = 0;
   __syncthreads();
   for (int64_t r = r0 + t; r < r1; r += kThreads) {
     const int c = row_class(row_ptr, r);
     if (c >= 0) atomicAdd(&cnt[c], 1);
   }
   __syncthreads();
-  if (t < 4) {
+  if (t < kRowClasses) {
     base[t] = cnt[t] ? atomicAdd(&counts[t], (unsigned long long)cnt[t]) : 0ull;
     cnt[t] = 0;
   }
@@ -156,6 +167,70 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_seg(const int64_t* __rest
     if (sub < len) {
       col[b + sub] = (int32_t)(key >> 32);
       dist[b + sub] = __builtin_bit_cast(float, (uint32_t)(key & 0xffffffffu));
+    }
+  }
+}
+
+// Rows of 65 .. 64 E entries, one wavefront per row, E entries per lane:
+// entry i sits in lane i % 64, slot i / 64.  In the bitonic network a partner
+// at distance j >= 64 is another slot of the same lane (a register
+// compare-exchange), a partner at j < 64 the same slot of lane ^ j (one
+// shuffle).
+template <int E>
+__global__ __launch_bounds__(kThreads) void k_row_sort_reg(const int64_t* __restrict__ row_ptr,
+                                                          int32_t* __restrict__ col, float* __restrict__ dist,
+                                                          const int32_t* __restrict__ list,
+                                                          const unsigned long long* __restrict__ count) {
+  constexpr int N = kWave * E;
+  const long long nrows = (long long)*count;
+  const int lane = lane_id();
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const long long nwaves = ((long long)gridDim.x * blockDim.x) / kWave;
+  for (long long w = wave; w < nrows; w += nwaves) {
+    const int r = list[w];
+    const int64_t b = row_ptr[r];
+    const int len = (int)(row_ptr[r + 1] - b);
+    uint64_t key[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = e * kWave + lane;
+      key[e] = i < len ? ((uint64_t)(uint32_t)col[b + i] << 32) | (uint64_t)__builtin_bit_cast(uint32_t, dist[b + i])
+                       : ~0ull;
+    }
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        if (j >= kWave) {
+          const int js = j / kWave;
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            if (e & js) continue;
+            const int i = e * kWave + lane;
+            const bool asc = (i & k) == 0;
+            const uint64_t x = key[e], y = key[e | js];
+            const uint64_t lo = x < y ? x : y, hi = x < y ? y : x;
+            key[e] = asc ? lo : hi;
+            key[e | js] = asc ? hi : lo;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int i = e * kWave + lane;
+            const uint64_t o = __shfl_xor(key[e], j, kWave);
+            const bool take_min = ((i & k) == 0) == ((lane & j) == 0);
+            key[e] = take_min ? (o < key[e] ? o : key[e]) : (o > key[e] ? o : key[e]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = e * kWave + lane;
+      if (i < len) {
+        col[b + i] = (int32_t)(key[e] >> 32);
+        dist[b + i] = __builtin_bit_cast(float, (uint32_t)(key[e] & 0xffffffffu));
+      }
     }
   }
 }
@@ -320,12 +395,13 @@ void launch_scatter(const Survivors& sv, const int64_t* row_ptr, int32_t* col, f
   SNN_LAUNCH_CHECK();
 }
 
-// lists: 4 m int32 (one list per length class); list_counts: 4 counters;
-// tmp_col / tmp_dist: nnz entries, needed only when a row exceeds 4096.
-// Fixed grids (the counts stay on the device), so the sequence can be captured.
+// lists: row_sort_lists() x m int32 (one list per length class);
+// list_counts: 8 counters; tmp_col / tmp_dist: nnz entries, needed only when
+// a row exceeds 4096.  Fixed grids (the counts stay on the device), so the
+// sequence can be captured.
 void launch_row_sort(const int64_t* row_ptr, int64_t m, int32_t* col, float* dist, int32_t* lists,
                      unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s) {
-  k_fill_u64<<<1, 64, 0, s>>>(list_counts, 4, 0ull);
+  k_fill_u64<<<1, 64, 0, s>>>(list_counts, 8, 0ull);
   SNN_LAUNCH_CHECK();
   if (m <= 0) return;
   k_row_classify<<<grid_for(m, 1024), kThreads, 0, s>>>(row_ptr, m, lists, list_counts);
@@ -336,9 +412,17 @@ void launch_row_sort(const int64_t* row_ptr, int64_t m, int32_t* col, float* dis
   SNN_LAUNCH_CHECK();
   k_row_sort_seg<64><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists + 2 * m, list_counts + 2);
   SNN_LAUNCH_CHECK();
-  k_row_sort_block<<<512, kThreads, 0, s>>>(row_ptr, col, dist, lists + 3 * m, list_counts + 3, tmp_col, tmp_dist);
+  k_row_sort_reg<2><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists + 3 * m, list_counts + 3);
+  SNN_LAUNCH_CHECK();
+  k_row_sort_reg<4><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists + 4 * m, list_counts + 4);
+  SNN_LAUNCH_CHECK();
+  k_row_sort_reg<8><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists + 5 * m, list_counts + 5);
+  SNN_LAUNCH_CHECK();
+  k_row_sort_block<<<512, kThreads, 0, s>>>(row_ptr, col, dist, lists + 6 * m, list_counts + 6, tmp_col, tmp_dist);
   SNN_LAUNCH_CHECK();
 }
+
+int row_sort_lists() { return kRowClasses; }
 
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s) {
   if (n <= 0) return;

@@ -217,8 +217,10 @@ struct Survivors {
 void launch_recheck(const QueryDev& q, const Survivors& sv, int32_t* row_cnt, int grid, hipStream_t s);
 void launch_scatter(const Survivors& sv, const int64_t* row_ptr, int32_t* col, float* dist, int grid,
                     hipStream_t s);
-// ids ascending within every row; lists: 4 m int32, list_counts: 4 counters,
-// tmp_col / tmp_dist: nnz entries (may be NULL when no row exceeds 4096)
+// ids ascending within every row; lists: row_sort_lists() x m int32,
+// list_counts: 8 counters, tmp_col / tmp_dist: nnz entries (may be NULL when
+// no row exceeds 4096)
+int row_sort_lists();
 void launch_row_sort(const int64_t* row_ptr, int64_t m, int32_t* col, float* dist, int32_t* lists,
                      unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);

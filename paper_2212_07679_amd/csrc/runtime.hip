@@ -131,7 +131,7 @@ struct Ctl {
   unsigned long long counters[kMaxXcd];
   unsigned long long survivors;
   unsigned long long pairs_window;
-  unsigned long long list_counts[4];
+  unsigned long long list_counts[8];
   unsigned long long row_max;
   unsigned long long pad0;
   int bad;
@@ -285,7 +285,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
                                             scan_scratch_bytes(nbuckets)}));
     p.ctl = c.take<Ctl>(1);
     p.row_cnt = c.take<int32_t>(std::max<int64_t>(m, 1));
-    p.lists = c.take<int32_t>(4 * std::max<int64_t>(m, 1));
+    p.lists = c.take<int32_t>((size_t)row_sort_lists() * std::max<int64_t>(m, 1));
     const bool mix = prec == SNN_PREC_MIXED;
     p.qop = c.take<uint16_t>(mix && !self ? (size_t)m * ka_of(terms) : 1);
     p.cthr = c.take<float>(mix ? std::max<int64_t>(m, 1) : 1);
