@@ -107,12 +107,16 @@ struct BatchPlan {
   int64_t* group_off = nullptr;
   void* scan_ws = nullptr;
   BatchCtl* ctl = nullptr;
-  int32_t* row_cnt = nullptr;
-  int64_t *row_ptr = nullptr, *row_ptr_s = nullptr, *nnz_base = nullptr, *nnz = nullptr;
+  int32_t* row_cnt = nullptr;  // per query slot
+  int32_t* cnt_o = nullptr;    // per output row
+  int64_t* rp_s = nullptr;     // slot-order row offsets
+  int64_t* rp_sg = nullptr;    // the same, zero when the staging arrays overflowed
+  int64_t *row_ptr = nullptr, *nnz_base = nullptr, *nnz = nullptr;  // output order
   int32_t* lists = nullptr;
   Survivors sv{};
-  int32_t *col_s = nullptr, *tmp_col = nullptr;
-  float *dist_s = nullptr, *tmp_dist = nullptr;
+  uint64_t* key_s = nullptr;                     // neighbour keys in slot-order rows
+  int32_t *col_o = nullptr, *tmp_col = nullptr;  // output order, merges
+  float *dist_o = nullptr, *tmp_dist = nullptr;
 
   // graphs: index pass, query pass, both
   hipGraphExec_t g_index = nullptr, g_query = nullptr, g_all = nullptr;
@@ -282,14 +286,16 @@ void alloc_query(BatchPlan& p) {
     p.units = c.take<int32_t>(nt);
     p.gunits = c.take<int32_t>(nt);
     p.group_off = c.take<int64_t>(nt + 1);
-    p.scan_ws = c.take<char>(std::max(scan_scratch_bytes(nt + 1), scan_scratch_bytes(M + 1)));
+    p.scan_ws = c.take<char>(std::max(scan_scratch_bytes(nt + 1), scan_scratch_bytes(MS + 1)));
     p.ctl = c.take<BatchCtl>(1);
-    p.row_cnt = c.take<int32_t>(M);
+    p.row_cnt = c.take<int32_t>(MS);
+    p.rp_s = c.take<int64_t>(MS + 1);
+    p.rp_sg = c.take<int64_t>(MS + 1);
+    p.cnt_o = c.take<int32_t>(M);
     p.row_ptr = c.take<int64_t>(M + 1);
-    p.row_ptr_s = c.take<int64_t>(M + 1);
     p.nnz_base = c.take<int64_t>(p.count + 1);
     p.nnz = c.take<int64_t>(p.count);
-    p.lists = c.take<int32_t>((size_t)row_sort_lists() * M);
+    p.lists = c.take<int32_t>((size_t)row_sort_lists() * MS);
   };
   Carver probe(nullptr);
   carve(probe);
@@ -303,8 +309,7 @@ void alloc_survivors(BatchPlan& p, int64_t cap) {
   auto carve = [&](Carver& c) {
     p.sv.pairs = c.take<int2>(cap);
     p.sv.res_q = c.take<int32_t>(cap);
-    p.sv.res_id = c.take<int32_t>(cap);
-    p.sv.res_dist = c.take<float>(cap);
+    p.sv.res_key = c.take<uint64_t>(cap);
     p.sv.res_slot = c.take<int32_t>(cap);
   };
   Carver probe(nullptr);
@@ -322,8 +327,9 @@ void alloc_stage(BatchPlan& p, int64_t cap) {
   p.stage.reset(p.arena);
   cap = std::max<int64_t>(cap, 1);
   auto carve = [&](Carver& c) {
-    p.col_s = c.take<int32_t>(cap);
-    p.dist_s = c.take<float>(cap);
+    p.key_s = c.take<uint64_t>(cap);
+    p.col_o = c.take<int32_t>(cap);
+    p.dist_o = c.take<float>(cap);
     p.tmp_col = c.take<int32_t>(cap);
     p.tmp_dist = c.take<float>(cap);
   };
@@ -358,10 +364,10 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   launch_fill_u64(reinterpret_cast<unsigned long long*>(p.ctl), sizeof(BatchCtl) / 8, 0ull, s);
   if (p.M == 0) {
     batch_zero_i64(p.row_ptr, 1, s);
-    batch_outputs(b, p.d_outs, p.row_ptr, p.col_s, p.dist_s, p.stage_cap, p.nnz_base, p.nnz, s);
+    batch_outputs(b, p.d_outs, p.row_ptr, p.col_o, p.dist_o, p.stage_cap, p.nnz_base, p.nnz, s);
     return;
   }
-  launch_fill_i32(p.row_cnt, p.M, 0, s);
+  launch_fill_i32(p.row_cnt, p.MS, 0, s);
   launch_tile_init(p.tlo, p.thi, p.ntiles, s);
   batch_query_keys(p.dtype, b, p.mu, p.v, p.qkey, p.qval, p.qa_in, p.qn_in, p.ctl, s);
   radix_sort_pairs_ws(p.qkey, p.qval, p.M, 0, 32, p.sort_ws, s);
@@ -404,12 +410,17 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   launch_cand_mfma(qd, mx, p.screen_grid, s);
   if (timed) batch_stamp(&p.ctl->stamp[1], s);
 
-  batch_recheck(b, p.sv, p.q64, p.p64, p.qorig, p.perm, p.row_cnt, di.cus * 16, s);
-  exclusive_scan_i32_to_i64(p.row_cnt, p.row_ptr, p.M, p.scan_ws, s);
-  batch_scatter(p.sv, p.row_ptr, p.M, p.col_s, p.dist_s, p.stage_cap, di.cus * 16, s);
-  batch_rowptr_guard(p.row_ptr, p.M, p.stage_cap, p.row_ptr_s, s);
-  launch_row_sort(p.row_ptr_s, p.M, p.col_s, p.dist_s, p.lists, p.ctl->list_counts, p.tmp_col, p.tmp_dist, s);
-  batch_outputs(b, p.d_outs, p.row_ptr, p.col_s, p.dist_s, p.stage_cap, p.nnz_base, p.nnz, s);
+  // neighbours are assembled in slot order (a tile's rows are contiguous),
+  // then each row is sorted on its way to its output row
+  batch_recheck(b, p.sv, p.q64, p.p64, p.perm, p.row_cnt, di.cus * 16, s);
+  exclusive_scan_i32_to_i64(p.row_cnt, p.rp_s, p.MS, p.scan_ws, s);
+  launch_perm_counts(p.rp_s, p.MS, p.qorig, p.cnt_o, s);
+  exclusive_scan_i32_to_i64(p.cnt_o, p.row_ptr, p.M, p.scan_ws, s);
+  batch_scatter(p.sv, p.rp_s, p.MS, p.key_s, p.stage_cap, di.cus * 16, s);
+  batch_rowptr_guard(p.rp_s, p.MS, p.stage_cap, p.rp_sg, s);
+  const RowMove mv{p.rp_sg, p.key_s, p.qorig, p.row_ptr, p.col_o, p.dist_o};
+  launch_row_sort_move(mv, p.MS, p.lists, p.ctl->list_counts, p.tmp_col, p.tmp_dist, s);
+  batch_outputs(b, p.d_outs, p.row_ptr, p.col_o, p.dist_o, p.stage_cap, p.nnz_base, p.nnz, s);
 }
 
 template <class F>

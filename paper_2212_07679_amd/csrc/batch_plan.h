@@ -124,10 +124,12 @@ void batch_windows(const BatchDev& b, const double* key, const double* qa, const
                    int32_t* tlo, int32_t* thi, BatchCtl* ctl, hipStream_t s);
 void batch_executed(const BatchDev& b, const int32_t* tlo, const int32_t* thi, int queries_per_wave, BatchCtl* ctl,
                     hipStream_t s);
+// row_cnt per query slot (rows are assembled in slot order)
 void batch_recheck(const BatchDev& b, const Survivors& sv, const double* q64, const double* p64,
-                   const int32_t* qorig, const int32_t* perm, int32_t* row_cnt, int grid, hipStream_t s);
-void batch_scatter(const Survivors& sv, const int64_t* row_ptr, int64_t M, int32_t* col, float* dist, int64_t cap,
-                   int grid, hipStream_t s);
+                   const int32_t* perm, int32_t* row_cnt, int grid, hipStream_t s);
+// neighbour keys into slot-order rows (nothing when row_ptr[M] > cap)
+void batch_scatter(const Survivors& sv, const int64_t* row_ptr, int64_t M, uint64_t* keys, int64_t cap, int grid,
+                   hipStream_t s);
 void batch_rowptr_guard(const int64_t* row_ptr, int64_t M, int64_t cap, int64_t* row_ptr_s, hipStream_t s);
 void batch_outputs(const BatchDev& b, const BatchOut* outs, const int64_t* row_ptr, const int32_t* col,
                    const float* dist, int64_t cap, int64_t* nnz_base, int64_t* nnz, hipStream_t s);

@@ -589,7 +589,6 @@ __global__ __launch_bounds__(kThreads) void kb_executed(BatchDev b, const int32_
 // ---- survivors -> CSR ------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void kb_recheck(BatchDev b, Survivors sv, const double* __restrict__ q64,
                                                       const double* __restrict__ p64,
-                                                      const int32_t* __restrict__ qorig,
                                                       const int32_t* __restrict__ perm,
                                                       int32_t* __restrict__ row_cnt) {
   const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count);
@@ -606,11 +605,10 @@ __global__ __launch_bounds__(kThreads) void kb_recheck(BatchDev b, Survivors sv,
       s = s + t * t;
     }
     if (s <= in.R2) {
-      const int o = qorig[pr.x];
-      sv.res_q[k] = o;
-      sv.res_id[k] = perm[pr.y];
-      sv.res_dist[k] = (float)sqrt(s);
-      sv.res_slot[k] = atomicAdd(&row_cnt[o], 1);
+      // rows are query slots: a tile's rows are neighbours in memory
+      sv.res_q[k] = pr.x;
+      sv.res_key[k] = neighbour_key(perm[pr.y], (float)sqrt(s));
+      sv.res_slot[k] = atomicAdd(&row_cnt[pr.x], 1);
     } else {
       sv.res_q[k] = -1;
     }
@@ -618,17 +616,14 @@ __global__ __launch_bounds__(kThreads) void kb_recheck(BatchDev b, Survivors sv,
 }
 
 __global__ __launch_bounds__(kThreads) void kb_scatter(Survivors sv, const int64_t* __restrict__ row_ptr, int64_t M,
-                                                      int32_t* __restrict__ col, float* __restrict__ dist,
-                                                      int64_t cap) {
+                                                      uint64_t* __restrict__ keys, int64_t cap) {
   if (row_ptr[M] > cap) return;  // staging too small: the host grows it and runs again
   const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count);
   for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < cnt;
        k += (long long)gridDim.x * blockDim.x) {
     const int o = sv.res_q[k];
     if (o < 0) continue;
-    const int64_t pos = row_ptr[o] + sv.res_slot[k];
-    col[pos] = sv.res_id[k];
-    dist[pos] = sv.res_dist[k];
+    keys[row_ptr[o] + sv.res_slot[k]] = sv.res_key[k];
   }
 }
 
@@ -799,14 +794,14 @@ void batch_executed(const BatchDev& b, const int32_t* tlo, const int32_t* thi, i
 }
 
 void batch_recheck(const BatchDev& b, const Survivors& sv, const double* q64, const double* p64,
-                   const int32_t* qorig, const int32_t* perm, int32_t* row_cnt, int grid, hipStream_t s) {
-  kb_recheck<<<grid, kThreads, 0, s>>>(b, sv, q64, p64, qorig, perm, row_cnt);
+                   const int32_t* perm, int32_t* row_cnt, int grid, hipStream_t s) {
+  kb_recheck<<<grid, kThreads, 0, s>>>(b, sv, q64, p64, perm, row_cnt);
   SNN_LAUNCH_CHECK();
 }
 
-void batch_scatter(const Survivors& sv, const int64_t* row_ptr, int64_t M, int32_t* col, float* dist, int64_t cap,
-                   int grid, hipStream_t s) {
-  kb_scatter<<<grid, kThreads, 0, s>>>(sv, row_ptr, M, col, dist, cap);
+void batch_scatter(const Survivors& sv, const int64_t* row_ptr, int64_t M, uint64_t* keys, int64_t cap, int grid,
+                   hipStream_t s) {
+  kb_scatter<<<grid, kThreads, 0, s>>>(sv, row_ptr, M, keys, cap);
   SNN_LAUNCH_CHECK();
 }
 

@@ -3,12 +3,14 @@
 //  k_recheck  every survivor is decided by the normative rule on the
 //             original coordinates in float64 (direct form of eq. (ip1),
 //             left to right, no fused multiply-add; inclusive compare of
-//             Section 3.2).  Neighbours take a slot in their row.
-//  (scan)     row counts -> row_ptr
-//  k_scatter  neighbours into their rows
-//  row sort   ids ascending within each row: rows of <= 16 / 32 / 64 entries
-//             by lane groups of that size (bitonic across lanes, 4 / 2 / 1 rows
-//             per wavefront), longer rows by one workgroup (bitonic in LDS,
+//             Section 3.2).  Neighbours take a slot in their row; rows are
+//             query slots (score order).
+//  (scan)     row counts -> slot-order row offsets
+//  k_scatter  neighbours into their slot-order rows
+//  row sort   each row sorted by id on its way to the caller's row order:
+//             rows of <= 16 / 32 / 64 entries by lane groups of that size
+//             (bitonic across lanes), up to 512 by one wavefront with 2 / 4 / 8
+//             entries per lane, longer rows by one workgroup (bitonic in LDS,
 //             then merge passes).
 #include <hip/hip_runtime.h>
 
@@ -46,19 +48,17 @@ __global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, 
       keep = s <= q.R2;
     }
     if (keep) {
-      const int qo = q.qorig[pr.x];
-      const int id = q.perm[pr.y];
+      // rows are query slots (score order): a tile's rows are neighbours in
+      // memory, so the counters and the later writes stay cache-local
       const float dist = (float)sqrt(s);
-      sv.res_q[r0] = qo;
-      sv.res_id[r0] = id;
-      sv.res_dist[r0] = dist;
-      sv.res_slot[r0] = atomicAdd(&row_cnt[qo], 1);
+      sv.res_q[r0] = pr.x;
+      sv.res_key[r0] = neighbour_key(q.perm[pr.y], dist);
+      sv.res_slot[r0] = atomicAdd(&row_cnt[pr.x], 1);
       if (sv.per == 2) {
-        if (pr.y != pr.x) {  // the mirrored pair, in the candidate's row
-          sv.res_q[r0 + 1] = id;
-          sv.res_id[r0 + 1] = qo;
-          sv.res_dist[r0 + 1] = dist;
-          sv.res_slot[r0 + 1] = atomicAdd(&row_cnt[id], 1);
+        if (pr.y != pr.x) {  // the mirrored pair, in the candidate's row (its slot is its position)
+          sv.res_q[r0 + 1] = pr.y;
+          sv.res_key[r0 + 1] = neighbour_key(q.qorig[pr.x], dist);
+          sv.res_slot[r0 + 1] = atomicAdd(&row_cnt[pr.y], 1);
         } else {
           sv.res_q[r0 + 1] = -1;
         }
@@ -71,15 +71,13 @@ __global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, 
 }
 
 __global__ __launch_bounds__(kThreads) void k_scatter(Survivors sv, const int64_t* __restrict__ row_ptr,
-                                                     int32_t* __restrict__ col, float* __restrict__ dist) {
+                                                     uint64_t* __restrict__ keys) {
   const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count) * sv.per;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (long long)gridDim.x * blockDim.x) {
     const int qo = sv.res_q[i];
     if (qo < 0) continue;
-    const int64_t pos = row_ptr[qo] + sv.res_slot[i];
-    col[pos] = sv.res_id[i];
-    dist[pos] = sv.res_dist[i];
+    keys[row_ptr[qo] + sv.res_slot[i]] = sv.res_key[i];
   }
 }
 
@@ -89,7 +87,7 @@ constexpr int kRowClasses = 7;
 
 __device__ __forceinline__ int row_class(const int64_t* __restrict__ row_ptr, int64_t r) {
   const int64_t len = row_ptr[r + 1] - row_ptr[r];
-  if (len <= 1) return -1;
+  if (len <= 0) return -1;
   if (len <= 16) return 0;
   if (len <= 32) return 1;
   if (len <= 64) return 2;
@@ -132,11 +130,10 @@ __global__ __launch_bounds__(kThreads) void k_row_classify(const int64_t* __rest
 // Rows of at most SEG entries, 64 / SEG rows per wavefront: each group of SEG
 // lanes holds one row as (id << 32 | dist bits) and runs a bitonic network
 // across its lanes (partners at distance < SEG stay inside the group).  Ids
-// are unique within a row, so the order is by id alone.
+// are unique within a row, so the order is by id alone.  The sorted row is
+// written to its destination row.
 template <int SEG>
-__global__ __launch_bounds__(kThreads) void k_row_sort_seg(const int64_t* __restrict__ row_ptr,
-                                                          int32_t* __restrict__ col, float* __restrict__ dist,
-                                                          const int32_t* __restrict__ list,
+__global__ __launch_bounds__(kThreads) void k_row_sort_seg(RowMove mv, const int32_t* __restrict__ list,
                                                           const unsigned long long* __restrict__ count) {
   constexpr int kRows = kWave / SEG;
   const long long nrows = (long long)*count;
@@ -145,28 +142,27 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_seg(const int64_t* __rest
   const long long nwaves = ((long long)gridDim.x * blockDim.x) / kWave;
   for (long long w = wave; w * kRows < nrows; w += nwaves) {
     const long long k = w * kRows + grp;
-    int64_t b = 0;
+    int64_t b = 0, o = 0;
     int len = 0;
     if (k < nrows) {
       const int r = list[k];
-      b = row_ptr[r];
-      len = (int)(row_ptr[r + 1] - b);
+      b = mv.src_rp[r];
+      len = (int)(mv.src_rp[r + 1] - b);
+      o = mv.dst_rp[mv.map[r]];
     }
-    uint64_t key = ~0ull;
-    if (sub < len)
-      key = ((uint64_t)(uint32_t)col[b + sub] << 32) | (uint64_t)__builtin_bit_cast(uint32_t, dist[b + sub]);
+    uint64_t key = sub < len ? mv.src_key[b + sub] : ~0ull;
 #pragma unroll
     for (int kk = 2; kk <= SEG; kk <<= 1) {
 #pragma unroll
       for (int j = kk >> 1; j > 0; j >>= 1) {
-        const uint64_t o = __shfl_xor(key, j, kWave);
+        const uint64_t x = __shfl_xor(key, j, kWave);
         const bool take_min = ((sub & kk) == 0) == ((sub & j) == 0);
-        key = take_min ? (o < key ? o : key) : (o > key ? o : key);
+        key = take_min ? (x < key ? x : key) : (x > key ? x : key);
       }
     }
     if (sub < len) {
-      col[b + sub] = (int32_t)(key >> 32);
-      dist[b + sub] = __builtin_bit_cast(float, (uint32_t)(key & 0xffffffffu));
+      mv.dst_col[o + sub] = (int32_t)(key >> 32);
+      mv.dst_dist[o + sub] = __builtin_bit_cast(float, (uint32_t)(key & 0xffffffffu));
     }
   }
 }
@@ -177,9 +173,7 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_seg(const int64_t* __rest
 // compare-exchange), a partner at j < 64 the same slot of lane ^ j (one
 // shuffle).
 template <int E>
-__global__ __launch_bounds__(kThreads) void k_row_sort_reg(const int64_t* __restrict__ row_ptr,
-                                                          int32_t* __restrict__ col, float* __restrict__ dist,
-                                                          const int32_t* __restrict__ list,
+__global__ __launch_bounds__(kThreads) void k_row_sort_reg(RowMove mv, const int32_t* __restrict__ list,
                                                           const unsigned long long* __restrict__ count) {
   constexpr int N = kWave * E;
   const long long nrows = (long long)*count;
@@ -188,14 +182,14 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_reg(const int64_t* __rest
   const long long nwaves = ((long long)gridDim.x * blockDim.x) / kWave;
   for (long long w = wave; w < nrows; w += nwaves) {
     const int r = list[w];
-    const int64_t b = row_ptr[r];
-    const int len = (int)(row_ptr[r + 1] - b);
+    const int64_t b = mv.src_rp[r];
+    const int len = (int)(mv.src_rp[r + 1] - b);
+    const int64_t o = mv.dst_rp[mv.map[r]];
     uint64_t key[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int i = e * kWave + lane;
-      key[e] = i < len ? ((uint64_t)(uint32_t)col[b + i] << 32) | (uint64_t)__builtin_bit_cast(uint32_t, dist[b + i])
-                       : ~0ull;
+      key[e] = i < len ? mv.src_key[b + i] : ~0ull;
     }
 #pragma unroll
     for (int k = 2; k <= N; k <<= 1) {
@@ -217,9 +211,9 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_reg(const int64_t* __rest
 #pragma unroll
           for (int e = 0; e < E; ++e) {
             const int i = e * kWave + lane;
-            const uint64_t o = __shfl_xor(key[e], j, kWave);
+            const uint64_t x = __shfl_xor(key[e], j, kWave);
             const bool take_min = ((i & k) == 0) == ((lane & j) == 0);
-            key[e] = take_min ? (o < key[e] ? o : key[e]) : (o > key[e] ? o : key[e]);
+            key[e] = take_min ? (x < key[e] ? x : key[e]) : (x > key[e] ? x : key[e]);
           }
         }
       }
@@ -228,8 +222,8 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_reg(const int64_t* __rest
     for (int e = 0; e < E; ++e) {
       const int i = e * kWave + lane;
       if (i < len) {
-        col[b + i] = (int32_t)(key[e] >> 32);
-        dist[b + i] = __builtin_bit_cast(float, (uint32_t)(key[e] & 0xffffffffu));
+        mv.dst_col[o + i] = (int32_t)(key[e] >> 32);
+        mv.dst_dist[o + i] = __builtin_bit_cast(float, (uint32_t)(key[e] & 0xffffffffu));
       }
     }
   }
@@ -256,44 +250,39 @@ __device__ __forceinline__ void bitonic_lds(uint64_t* a, int n) {
   }
 }
 
-__device__ __forceinline__ uint64_t pack_cd(int32_t c, float d) {
-  return ((uint64_t)(uint32_t)c << 32) | (uint64_t)__builtin_bit_cast(uint32_t, d);
-}
-
-// one workgroup per row of > 64 entries: sort runs of 4096 in LDS, then
-// merge runs pairwise (each element finds its rank in the partner run by
-// binary search; ids are unique within a row).
-__global__ __launch_bounds__(kThreads) void k_row_sort_block(const int64_t* __restrict__ row_ptr,
-                                                            int32_t* __restrict__ col, float* __restrict__ dist,
-                                                            const int32_t* __restrict__ long_list,
-                                                            const unsigned long long* __restrict__ counts,
+// One workgroup per row of more than 512 entries: runs of 4096 are sorted
+// in LDS on their way from the source row to the destination row, then runs
+// are merged pairwise in the destination (each element finds its rank in the
+// partner run by binary search; ids are unique within a row), ping-ponging
+// through tmp at the destination offsets (tmp holds the destination nnz).
+__global__ __launch_bounds__(kThreads) void k_row_sort_block(RowMove mv, const int32_t* __restrict__ list,
+                                                            const unsigned long long* __restrict__ count,
                                                             int32_t* __restrict__ tmp_col,
                                                             float* __restrict__ tmp_dist) {
   __shared__ uint64_t a[kBlockSort];
-  const long long nrows = (long long)*counts;
+  const long long nrows = (long long)*count;
   for (long long w = blockIdx.x; w < nrows; w += gridDim.x) {
-    const int r = long_list[w];
-    const int64_t b = row_ptr[r], e = row_ptr[r + 1];
-    const int64_t len = e - b;
+    const int r = list[w];
+    const int64_t b = mv.src_rp[r];
+    const int64_t len = mv.src_rp[r + 1] - b;
+    const int64_t o = mv.dst_rp[mv.map[r]];
     for (int64_t c0 = 0; c0 < len; c0 += kBlockSort) {
       const int cl = (int)min((int64_t)kBlockSort, len - c0);
       int np2 = 1;
       while (np2 < cl) np2 <<= 1;
       __syncthreads();
       for (int i = threadIdx.x; i < np2; i += blockDim.x)
-        a[i] = i < cl ? pack_cd(col[b + c0 + i], dist[b + c0 + i]) : ~0ull;
+        a[i] = i < cl ? mv.src_key[b + c0 + i] : ~0ull;
       __syncthreads();
       bitonic_lds(a, np2);
       for (int i = threadIdx.x; i < cl; i += blockDim.x) {
-        col[b + c0 + i] = (int32_t)(a[i] >> 32);
-        dist[b + c0 + i] = __builtin_bit_cast(float, (uint32_t)(a[i] & 0xffffffffu));
+        mv.dst_col[o + c0 + i] = (int32_t)(a[i] >> 32);
+        mv.dst_dist[o + c0 + i] = __builtin_bit_cast(float, (uint32_t)(a[i] & 0xffffffffu));
       }
     }
     __syncthreads();
-    // merge passes: runs of `width` sorted, ping-pong through tmp (at the
-    // row's own offset, tmp has the caller's capacity)
-    int32_t *sc = col + b, *dc = tmp_col + b;
-    float *sd = dist + b, *dd = tmp_dist + b;
+    int32_t *sc = mv.dst_col + o, *dc = tmp_col + o;
+    float *sd = mv.dst_dist + o, *dd = tmp_dist + o;
     bool in_tmp = false;
     for (int64_t width = kBlockSort; width < len; width <<= 1) {
       for (int64_t i = threadIdx.x; i < len; i += blockDim.x) {
@@ -334,6 +323,17 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_block(const int64_t* __re
       }
     }
     __syncthreads();
+  }
+}
+
+// counts of the destination rows: cnt_dst[map[r]] = length of source row r
+// (rows with map < 0 are padding and empty)
+__global__ __launch_bounds__(kThreads) void k_perm_counts(const int64_t* __restrict__ src_rp, int64_t m,
+                                                         const int32_t* __restrict__ map,
+                                                         int32_t* __restrict__ cnt_dst) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    const int d = map[r];
+    if (d >= 0) cnt_dst[d] = (int32_t)(src_rp[r + 1] - src_rp[r]);
   }
 }
 
@@ -389,36 +389,41 @@ void launch_recheck(const QueryDev& q, const Survivors& sv, int32_t* row_cnt, in
   SNN_LAUNCH_CHECK();
 }
 
-void launch_scatter(const Survivors& sv, const int64_t* row_ptr, int32_t* col, float* dist, int grid,
-                    hipStream_t s) {
-  k_scatter<<<grid, kThreads, 0, s>>>(sv, row_ptr, col, dist);
+void launch_scatter(const Survivors& sv, const int64_t* row_ptr, uint64_t* keys, int grid, hipStream_t s) {
+  k_scatter<<<grid, kThreads, 0, s>>>(sv, row_ptr, keys);
   SNN_LAUNCH_CHECK();
 }
 
-// lists: row_sort_lists() x m int32 (one list per length class);
-// list_counts: 8 counters; tmp_col / tmp_dist: nnz entries, needed only when
-// a row exceeds 4096.  Fixed grids (the counts stay on the device), so the
-// sequence can be captured.
-void launch_row_sort(const int64_t* row_ptr, int64_t m, int32_t* col, float* dist, int32_t* lists,
-                     unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s) {
+// m source rows; lists: row_sort_lists() x m int32 (one list per length
+// class); list_counts: 8 counters; tmp_col / tmp_dist: destination nnz
+// entries, needed only when a row exceeds 4096.  Fixed grids (the counts stay
+// on the device), so the sequence can be captured.
+void launch_row_sort_move(const RowMove& mv, int64_t m, int32_t* lists, unsigned long long* list_counts,
+                          int32_t* tmp_col, float* tmp_dist, hipStream_t s) {
   k_fill_u64<<<1, 64, 0, s>>>(list_counts, 8, 0ull);
   SNN_LAUNCH_CHECK();
   if (m <= 0) return;
-  k_row_classify<<<grid_for(m, 1024), kThreads, 0, s>>>(row_ptr, m, lists, list_counts);
+  k_row_classify<<<grid_for(m, 1024), kThreads, 0, s>>>(mv.src_rp, m, lists, list_counts);
   SNN_LAUNCH_CHECK();
-  k_row_sort_seg<16><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists, list_counts);
+  k_row_sort_seg<16><<<2048, kThreads, 0, s>>>(mv, lists, list_counts);
   SNN_LAUNCH_CHECK();
-  k_row_sort_seg<32><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists + m, list_counts + 1);
+  k_row_sort_seg<32><<<2048, kThreads, 0, s>>>(mv, lists + m, list_counts + 1);
   SNN_LAUNCH_CHECK();
-  k_row_sort_seg<64><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists + 2 * m, list_counts + 2);
+  k_row_sort_seg<64><<<2048, kThreads, 0, s>>>(mv, lists + 2 * m, list_counts + 2);
   SNN_LAUNCH_CHECK();
-  k_row_sort_reg<2><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists + 3 * m, list_counts + 3);
+  k_row_sort_reg<2><<<2048, kThreads, 0, s>>>(mv, lists + 3 * m, list_counts + 3);
   SNN_LAUNCH_CHECK();
-  k_row_sort_reg<4><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists + 4 * m, list_counts + 4);
+  k_row_sort_reg<4><<<2048, kThreads, 0, s>>>(mv, lists + 4 * m, list_counts + 4);
   SNN_LAUNCH_CHECK();
-  k_row_sort_reg<8><<<2048, kThreads, 0, s>>>(row_ptr, col, dist, lists + 5 * m, list_counts + 5);
+  k_row_sort_reg<8><<<2048, kThreads, 0, s>>>(mv, lists + 5 * m, list_counts + 5);
   SNN_LAUNCH_CHECK();
-  k_row_sort_block<<<512, kThreads, 0, s>>>(row_ptr, col, dist, lists + 6 * m, list_counts + 6, tmp_col, tmp_dist);
+  k_row_sort_block<<<512, kThreads, 0, s>>>(mv, lists + 6 * m, list_counts + 6, tmp_col, tmp_dist);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_perm_counts(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst, hipStream_t s) {
+  if (m <= 0) return;
+  k_perm_counts<<<grid_for(m, 4096), kThreads, 0, s>>>(src_rp, m, map, cnt_dst);
   SNN_LAUNCH_CHECK();
 }
 

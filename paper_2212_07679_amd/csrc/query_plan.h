@@ -209,20 +209,34 @@ struct Survivors {
   unsigned long long* count;   // may exceed cap (then pairs were dropped)
   long long cap;
   int per;                     // results per pair: 1, or 2 for a symmetric self-query
-  int32_t* res_q;              // per * cap: caller query row or -1
-  int32_t* res_id;
-  float* res_dist;
-  int32_t* res_slot;
+  int32_t* res_q;              // per * cap: row (query slot) or -1
+  uint64_t* res_key;           // per * cap: neighbour key (id << 32 | distance bits)
+  int32_t* res_slot;           // per * cap: position within the row
 };
+// neighbour key: ordering keys orders by id (ids are unique within a row)
+__host__ __device__ __forceinline__ uint64_t neighbour_key(int32_t id, float dist) {
+  return ((uint64_t)(uint32_t)id << 32) | (uint64_t)__builtin_bit_cast(uint32_t, dist);
+}
 void launch_recheck(const QueryDev& q, const Survivors& sv, int32_t* row_cnt, int grid, hipStream_t s);
-void launch_scatter(const Survivors& sv, const int64_t* row_ptr, int32_t* col, float* dist, int grid,
-                    hipStream_t s);
-// ids ascending within every row; lists: row_sort_lists() x m int32,
-// list_counts: 8 counters, tmp_col / tmp_dist: nnz entries (may be NULL when
-// no row exceeds 4096)
+// keys into slot-order rows at row_ptr[row] + slot
+void launch_scatter(const Survivors& sv, const int64_t* row_ptr, uint64_t* keys, int grid, hipStream_t s);
+// Source row r of a CSR in slot order (neighbour keys) goes, sorted by id,
+// to destination row map[r] of the caller's CSR.
+struct RowMove {
+  const int64_t* src_rp;
+  const uint64_t* src_key;
+  const int32_t* map;  // source row -> destination row (< 0: empty padding row)
+  const int64_t* dst_rp;
+  int32_t* dst_col;
+  float* dst_dist;
+};
+// lists: row_sort_lists() x m int32, list_counts: 8 counters, tmp_col /
+// tmp_dist: destination nnz entries (may be NULL when no row exceeds 4096)
 int row_sort_lists();
-void launch_row_sort(const int64_t* row_ptr, int64_t m, int32_t* col, float* dist, int32_t* lists,
-                     unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s);
+void launch_row_sort_move(const RowMove& mv, int64_t m, int32_t* lists, unsigned long long* list_counts,
+                          int32_t* tmp_col, float* tmp_dist, hipStream_t s);
+// cnt_dst[map[r]] = length of source row r
+void launch_perm_counts(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 

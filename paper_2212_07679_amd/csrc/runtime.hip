@@ -258,7 +258,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       int32_t* gunits;
       char* scan_scratch;
       Ctl* ctl;
-      int32_t* row_cnt;
+      int32_t* row_cnt;  // per query slot
+      int64_t* rp_s;     // slot-order row offsets
+      int32_t* cnt_o;    // per caller row
       int32_t* lists;
       uint16_t* qop;
       float* cthr;
@@ -285,7 +287,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
                                             scan_scratch_bytes(nbuckets)}));
     p.ctl = c.take<Ctl>(1);
     p.row_cnt = c.take<int32_t>(std::max<int64_t>(m, 1));
-    p.lists = c.take<int32_t>((size_t)row_sort_lists() * std::max<int64_t>(m, 1));
+    p.rp_s = c.take<int64_t>(m + 1);
+    p.cnt_o = c.take<int32_t>(std::max<int64_t>(m, 1));
+    p.lists =c.take<int32_t>((size_t)row_sort_lists() * std::max<int64_t>(m, 1));
     const bool mix = prec == SNN_PREC_MIXED;
     p.qop = c.take<uint16_t>(mix && !self ? (size_t)m * ka_of(terms) : 1);
     p.cthr = c.take<float>(mix ? std::max<int64_t>(m, 1) : 1);
@@ -393,6 +397,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const size_t per_bytes = 8 + 16 * (size_t)per;
   long long cap = std::max<long long>(1 << 16, (long long)(ix.ws[1].bytes / per_bytes));
   HostCtl hc{};
+  uint64_t* stage_key = nullptr;  // neighbour keys in slot-order rows
   for (int attempt = 0;; ++attempt) {
     // five arrays, each padded to 256 bytes by the carver
     const size_t need = (size_t)cap * per_bytes + 2048;
@@ -403,8 +408,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     sv.per = per;
     sv.pairs = sc.take<int2>(cap);
     sv.res_q = sc.take<int32_t>(cap * per);
-    sv.res_id = sc.take<int32_t>(cap * per);
-    sv.res_dist = sc.take<float>(cap * per);
+    sv.res_key = sc.take<uint64_t>(cap * per);
     sv.res_slot = sc.take<int32_t>(cap * per);
     // recompute cap to fit the carve exactly
     sv.cap = cap;
@@ -432,7 +436,11 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     }
     if (st) SNN_HIP(hipEventRecord(ev[2], s));
     launch_recheck(qd, sv, P.row_cnt, di.cus * 16, s);
-    exclusive_scan_i32_to_i64(P.row_cnt, out->row_ptr, m, P.scan_scratch, s);
+    // row offsets in slot order (where the neighbours are assembled) and in
+    // the caller's order (where each row ends up)
+    exclusive_scan_i32_to_i64(P.row_cnt, P.rp_s, m, P.scan_scratch, s);
+    launch_perm_counts(P.rp_s, m, qorig, P.cnt_o, s);
+    exclusive_scan_i32_to_i64(P.cnt_o, out->row_ptr, m, P.scan_scratch, s);
     launch_row_max(P.row_cnt, m, &P.ctl->row_max, s);
     SNN_HIP(hipMemcpyAsync(&hc.ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     SNN_HIP(hipMemcpyAsync(&hc.nnz, out->row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -454,14 +462,18 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
                       (long long)hc.nnz);
         throw Error(SNN_EOVERFLOW, buf);
       }
-      launch_scatter(sv, out->row_ptr, out->col, out->dist, di.cus * 16, s);
+      // neighbours into slot-order staging rows
+      ix.ws[3].ensure(ix.arena, (size_t)hc.nnz * 8 + 512);
+      Carver gc(ix.ws[3].ptr);
+      stage_key = gc.take<uint64_t>(hc.nnz);
+      launch_scatter(sv, P.rp_s, stage_key, di.cus * 16, s);
       break;
     }
     cap = (long long)(hc.ctl.survivors * 5 / 4) + 1024;
     ix.ws[1].reset(ix.arena);
   }
 
-  // ---- rows: ids ascending
+  // ---- rows: ids ascending, moved to the caller's row order
   int32_t* tmp_col = nullptr;
   float* tmp_dist = nullptr;
   if (hc.ctl.row_max > 4096) {
@@ -470,7 +482,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     tmp_col = tc.take<int32_t>(hc.nnz);
     tmp_dist = tc.take<float>(hc.nnz);
   }
-  launch_row_sort(out->row_ptr, m, out->col, out->dist, P.lists, P.ctl->list_counts, tmp_col, tmp_dist, s);
+  const RowMove mv{P.rp_s, stage_key, qorig, out->row_ptr, out->col, out->dist};
+  launch_row_sort_move(mv, m, P.lists, P.ctl->list_counts, tmp_col, tmp_dist, s);
 
   if (st) {
     SNN_HIP(hipEventRecord(ev[3], s));
