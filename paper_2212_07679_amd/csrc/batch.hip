@@ -419,7 +419,7 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   batch_scatter(p.sv, p.rp_s, p.MS, p.key_s, p.stage_cap, di.cus * 16, s);
   batch_rowptr_guard(p.rp_s, p.MS, p.stage_cap, p.rp_sg, s);
   const RowMove mv{p.rp_sg, p.key_s, p.qorig, p.row_ptr, p.col_o, p.dist_o};
-  launch_row_sort_move(mv, p.MS, p.lists, p.ctl->list_counts, p.tmp_col, p.tmp_dist, s);
+  launch_row_sort_move(mv, p.MS, INT64_MAX, p.lists, p.ctl->list_counts, p.tmp_col, p.tmp_dist, s);
   batch_outputs(b, p.d_outs, p.row_ptr, p.col_o, p.dist_o, p.stage_cap, p.nnz_base, p.nnz, s);
 }
 

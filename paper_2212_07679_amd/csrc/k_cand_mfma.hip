@@ -66,38 +66,33 @@ __global__ __launch_bounds__(kThreads) void k_mixed_qprep(const double* __restri
                                                          const double* __restrict__ mu, int terms, int KA,
                                                          MixedBound b, uint16_t* __restrict__ qop,
                                                          float* __restrict__ cthr) {
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x) {
+  // kQLanes lanes per query: they share the coordinates and the operand row
+  constexpr int kQLanes = 16;
+  const int sub = threadIdx.x % kQLanes;
+  for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kQLanes; s < m;
+       s += ((int64_t)gridDim.x * blockDim.x) / kQLanes) {
     const double* q = q64 + s * dp;
-    uint4* o = reinterpret_cast<uint4*>(qop + s * KA);
     double nn = 0.0;
-    for (int k = 0; k < d; ++k) {
+    for (int k = sub; k < d; k += kQLanes) {
       const float y = (float)(q[k] - mu[k]);
       nn += (double)y * (double)y;
     }
-    // row [bf16(y)] or [hi | hi | lo], written 8 values (16 bytes) at a time
-    for (int c = 0; c < KA / 8; ++c) {
-      uint32_t w[4];
+    // any summation order stays within the gamma_{d+1} bound the start value allows for
 #pragma unroll
-      for (int e = 0; e < 8; e += 2) {
-        uint32_t pr = 0;
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          const int k = 8 * c + e + t;
-          uint16_t v = 0;
-          if (k < terms * d) {
-            const int seg = k / d, cc = k % d;
-            const float y = (float)(q[cc] - mu[cc]);
-            const uint16_t hi = f32_to_bf16_rne(y);
-            v = (seg == 2) ? f32_to_bf16_rne(y - bf16_to_f32(hi)) : hi;
-          }
-          pr |= (uint32_t)v << (16 * t);
-        }
-        w[e / 2] = pr;
+    for (int off = kQLanes / 2; off > 0; off >>= 1) nn += __shfl_xor(nn, off, kQLanes);
+    // row [bf16(y)] or [hi | hi | lo]
+    uint16_t* o = qop + s * KA;
+    for (int k = sub; k < KA; k += kQLanes) {
+      uint16_t v = 0;
+      if (k < terms * d) {
+        const int seg = k / d, cc = k % d;
+        const float y = (float)(q[cc] - mu[cc]);
+        const uint16_t hi = f32_to_bf16_rne(y);
+        v = (seg == 2) ? f32_to_bf16_rne(y - bf16_to_f32(hi)) : hi;
       }
-      o[c] = make_uint4(w[0], w[1], w[2], w[3]);
+      o[k] = v;
     }
-    const double nq = sqrt(nn) * (1.0 + 1e-15);
-    cthr[s] = screen_threshold(b, 0.5 * nn, nq);
+    if (sub == 0) cthr[s] = screen_threshold(b, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
   }
 }
 
@@ -304,7 +299,7 @@ int mixed_blocks_per_cu(int KA, int KB) {
 void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, int terms, int KA,
                         const MixedBound& b, uint16_t* qop, float* cthr, hipStream_t s) {
   if (m <= 0) return;
-  k_mixed_qprep<<<grid_for(m, 8192), kThreads, 0, s>>>(q64, m, d, dp, mu, terms, KA, b, qop, cthr);
+  k_mixed_qprep<<<grid_for(m * 16, 8192), kThreads, 0, s>>>(q64, m, d, dp, mu, terms, KA, b, qop, cthr);
   SNN_LAUNCH_CHECK();
 }
 

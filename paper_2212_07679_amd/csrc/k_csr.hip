@@ -27,7 +27,12 @@ namespace snn {
 namespace {
 constexpr int kThreads = 256;
 
-__global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, int32_t* __restrict__ row_cnt) {
+// Data rows are read in the input dtype (their promotion to float64 is
+// exact), the query rows of a self-query likewise; out-of-sample query rows
+// are the float64 copies.
+template <typename T, bool SELF>
+__global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, const T* __restrict__ po,
+                                                     int32_t* __restrict__ row_cnt) {
   const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count);
   const int d = q.d;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
@@ -39,11 +44,19 @@ __global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, 
     bool keep = !q.sym || pr.y >= pr.x;
     double s = 0.0;
     if (keep) {
-      const double* qp = q.q64 + (int64_t)pr.x * q.dp;
-      const double* pp = q.p64 + (int64_t)pr.y * q.dp;
-      for (int k = 0; k < d; ++k) {
-        const double t = pp[k] - qp[k];
-        s = s + t * t;
+      const T* pp = po + (int64_t)pr.y * d;
+      if (SELF) {
+        const T* qp = po + (int64_t)pr.x * d;
+        for (int k = 0; k < d; ++k) {
+          const double t = (double)pp[k] - (double)qp[k];
+          s = s + t * t;
+        }
+      } else {
+        const double* qp = q.q64 + (int64_t)pr.x * q.dp;
+        for (int k = 0; k < d; ++k) {
+          const double t = (double)pp[k] - qp[k];
+          s = s + t * t;
+        }
       }
       keep = s <= q.R2;
     }
@@ -384,8 +397,19 @@ void launch_self_qnorm(const float* ynorm, int64_t n, double* out, hipStream_t s
   SNN_LAUNCH_CHECK();
 }
 
-void launch_recheck(const QueryDev& q, const Survivors& sv, int32_t* row_cnt, int grid, hipStream_t s) {
-  k_recheck<<<grid, kThreads, 0, s>>>(q, sv, row_cnt);
+void launch_recheck(const QueryDev& q, const Survivors& sv, snn_dtype dt, const void* po, bool self,
+                    int32_t* row_cnt, int grid, hipStream_t s) {
+  if (dt == SNN_F32) {
+    if (self)
+      k_recheck<float, true><<<grid, kThreads, 0, s>>>(q, sv, static_cast<const float*>(po), row_cnt);
+    else
+      k_recheck<float, false><<<grid, kThreads, 0, s>>>(q, sv, static_cast<const float*>(po), row_cnt);
+  } else {
+    if (self)
+      k_recheck<double, true><<<grid, kThreads, 0, s>>>(q, sv, static_cast<const double*>(po), row_cnt);
+    else
+      k_recheck<double, false><<<grid, kThreads, 0, s>>>(q, sv, static_cast<const double*>(po), row_cnt);
+  }
   SNN_LAUNCH_CHECK();
 }
 
@@ -398,27 +422,40 @@ void launch_scatter(const Survivors& sv, const int64_t* row_ptr, uint64_t* keys,
 // class); list_counts: 8 counters; tmp_col / tmp_dist: destination nnz
 // entries, needed only when a row exceeds 4096.  Fixed grids (the counts stay
 // on the device), so the sequence can be captured.
-void launch_row_sort_move(const RowMove& mv, int64_t m, int32_t* lists, unsigned long long* list_counts,
-                          int32_t* tmp_col, float* tmp_dist, hipStream_t s) {
+void launch_row_sort_move(const RowMove& mv, int64_t m, int64_t max_len, int32_t* lists,
+                          unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s) {
   k_fill_u64<<<1, 64, 0, s>>>(list_counts, 8, 0ull);
   SNN_LAUNCH_CHECK();
-  if (m <= 0) return;
+  if (m <= 0 || max_len <= 0) return;
   k_row_classify<<<grid_for(m, 1024), kThreads, 0, s>>>(mv.src_rp, m, lists, list_counts);
   SNN_LAUNCH_CHECK();
+  // classes whose shortest row exceeds max_len are empty
   k_row_sort_seg<16><<<2048, kThreads, 0, s>>>(mv, lists, list_counts);
   SNN_LAUNCH_CHECK();
-  k_row_sort_seg<32><<<2048, kThreads, 0, s>>>(mv, lists + m, list_counts + 1);
-  SNN_LAUNCH_CHECK();
-  k_row_sort_seg<64><<<2048, kThreads, 0, s>>>(mv, lists + 2 * m, list_counts + 2);
-  SNN_LAUNCH_CHECK();
-  k_row_sort_reg<2><<<2048, kThreads, 0, s>>>(mv, lists + 3 * m, list_counts + 3);
-  SNN_LAUNCH_CHECK();
-  k_row_sort_reg<4><<<2048, kThreads, 0, s>>>(mv, lists + 4 * m, list_counts + 4);
-  SNN_LAUNCH_CHECK();
-  k_row_sort_reg<8><<<2048, kThreads, 0, s>>>(mv, lists + 5 * m, list_counts + 5);
-  SNN_LAUNCH_CHECK();
-  k_row_sort_block<<<512, kThreads, 0, s>>>(mv, lists + 6 * m, list_counts + 6, tmp_col, tmp_dist);
-  SNN_LAUNCH_CHECK();
+  if (max_len > 16) {
+    k_row_sort_seg<32><<<2048, kThreads, 0, s>>>(mv, lists + m, list_counts + 1);
+    SNN_LAUNCH_CHECK();
+  }
+  if (max_len > 32) {
+    k_row_sort_seg<64><<<2048, kThreads, 0, s>>>(mv, lists + 2 * m, list_counts + 2);
+    SNN_LAUNCH_CHECK();
+  }
+  if (max_len > 64) {
+    k_row_sort_reg<2><<<2048, kThreads, 0, s>>>(mv, lists + 3 * m, list_counts + 3);
+    SNN_LAUNCH_CHECK();
+  }
+  if (max_len > 128) {
+    k_row_sort_reg<4><<<2048, kThreads, 0, s>>>(mv, lists + 4 * m, list_counts + 4);
+    SNN_LAUNCH_CHECK();
+  }
+  if (max_len > 256) {
+    k_row_sort_reg<8><<<2048, kThreads, 0, s>>>(mv, lists + 5 * m, list_counts + 5);
+    SNN_LAUNCH_CHECK();
+  }
+  if (max_len > 512) {
+    k_row_sort_block<<<512, kThreads, 0, s>>>(mv, lists + 6 * m, list_counts + 6, tmp_col, tmp_dist);
+    SNN_LAUNCH_CHECK();
+  }
 }
 
 void launch_perm_counts(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst, hipStream_t s) {

@@ -217,7 +217,9 @@ struct Survivors {
 __host__ __device__ __forceinline__ uint64_t neighbour_key(int32_t id, float dist) {
   return ((uint64_t)(uint32_t)id << 32) | (uint64_t)__builtin_bit_cast(uint32_t, dist);
 }
-void launch_recheck(const QueryDev& q, const Survivors& sv, int32_t* row_cnt, int grid, hipStream_t s);
+// po: the index's data rows in the input dtype, score order (n x d)
+void launch_recheck(const QueryDev& q, const Survivors& sv, snn_dtype dt, const void* po, bool self,
+                    int32_t* row_cnt, int grid, hipStream_t s);
 // keys into slot-order rows at row_ptr[row] + slot
 void launch_scatter(const Survivors& sv, const int64_t* row_ptr, uint64_t* keys, int grid, hipStream_t s);
 // Source row r of a CSR in slot order (neighbour keys) goes, sorted by id,
@@ -233,8 +235,10 @@ struct RowMove {
 // lists: row_sort_lists() x m int32, list_counts: 8 counters, tmp_col /
 // tmp_dist: destination nnz entries (may be NULL when no row exceeds 4096)
 int row_sort_lists();
-void launch_row_sort_move(const RowMove& mv, int64_t m, int32_t* lists, unsigned long long* list_counts,
-                          int32_t* tmp_col, float* tmp_dist, hipStream_t s);
+// max_len: an upper bound on the row lengths when the host knows one (the
+// kernels of longer length classes are not launched), else INT64_MAX
+void launch_row_sort_move(const RowMove& mv, int64_t m, int64_t max_len, int32_t* lists,
+                          unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s);
 // cnt_dst[map[r]] = length of source row r
 void launch_perm_counts(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);

@@ -435,7 +435,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
         launch_cand_fp64(qd, grid, s);
     }
     if (st) SNN_HIP(hipEventRecord(ev[2], s));
-    launch_recheck(qd, sv, P.row_cnt, di.cus * 16, s);
+    launch_recheck(qd, sv, ix.dtype, ix.po.ptr, self, P.row_cnt, di.cus * 16, s);
     // row offsets in slot order (where the neighbours are assembled) and in
     // the caller's order (where each row ends up)
     exclusive_scan_i32_to_i64(P.row_cnt, P.rp_s, m, P.scan_scratch, s);
@@ -483,7 +483,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     tmp_dist = tc.take<float>(hc.nnz);
   }
   const RowMove mv{P.rp_s, stage_key, qorig, out->row_ptr, out->col, out->dist};
-  launch_row_sort_move(mv, m, P.lists, P.ctl->list_counts, tmp_col, tmp_dist, s);
+  launch_row_sort_move(mv, m, (int64_t)hc.ctl.row_max, P.lists, P.ctl->list_counts, tmp_col, tmp_dist, s);
 
   if (st) {
     SNN_HIP(hipEventRecord(ev[3], s));
