@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_BF16_FLOPS = 2.5e15  # MI355X dense bf16 matrix peak
-PEAK_FP32_VALU_FLOPS = 157.3e12  # MI355X fp32 vector peak (fused multiply-add = 2 flop)
+PEAK_FP32_FLOPS = 157.3e12  # MI355X fp32 matrix (and vector) peak
 PEAK_FP64_VALU_OPS = 256 * 4 * 16 * 2.4e9  # non-fused float64 lane-ops/s: CUs x SIMDs x lanes x clock
 PEAK_HBM = 8.0e12
 
@@ -57,7 +57,7 @@ WORKLOADS = {
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {
     "mixed": "paper_2212_07679_amd/csrc/k_cand_mfma.hip",
-    "fp32": "paper_2212_07679_amd/csrc/k_cand_valu.hip",
+    "fp32": "paper_2212_07679_amd/csrc/k_cand_mfma.hip",
     "fp64": "paper_2212_07679_amd/csrc/k_cand_fp64.hip",
 }
 
@@ -182,8 +182,8 @@ def roofline(prec_used, terms, st, screen_ms, d):
                 "frac": achieved / PEAK_BF16_FLOPS, "traffic": None}
     if prec_used == "fp32":
         achieved = st["pairs_window"] * 2 * d / (screen_ms / 1e3)
-        return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU_FLOPS / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU_FLOPS, "traffic": None}
+        return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP32_FLOPS / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_FLOPS, "traffic": None}
     achieved = st["pairs_window"] * (3 * d - 1) / (screen_ms / 1e3)
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64_VALU_OPS / 1e12, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VALU_OPS, "traffic": None}

@@ -136,8 +136,56 @@ __device__ __forceinline__ void load_step(bf16x8 (&B)[NL], float& h, __amdgpu_bu
   h = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rh, voff_h, it * 128, 0));
 }
 
-// One 32-candidate step for QB blocks of 32 queries: the matrix products,
-// the max/compare epilogue, and (rarely) the append of passing pairs.
+// The max/compare epilogue of one step: acc[b] is the 32x32 block of query
+// block b against the step's 32 candidates (lane l: candidate l % 32;
+// accumulator r: query 8 (r / 4) + 4 (l / 32) + r % 4 of the block).
+// Two ways of collecting the passing pairs of a block with a passing lane:
+// ROWS: one wave-wide compare per accumulator row r (16 scalar masks), and a
+//       push for each row with passing lanes (cheaper when a block holds
+//       few passes, as with the short fp32 chains);
+// else: each lane packs its passing accumulators into a bit mask and the
+//       wave pushes one pair per lane per round (cheaper when passes are
+//       many, as in dense bf16 outputs: measured on one box, 1.25 vs 1.51 ms
+//       for the 256-instance batch, 21 vs 17 ms for the d = 3 particles).
+template <int QB, bool ROWS>
+__device__ __forceinline__ void screen_epilogue(const f32x16 (&acc)[QB], float hj, int jj, int64_t q0, int half,
+                                                int2* wbuf, int& wcnt, const PairSink& sink) {
+  uint64_t pm[QB];  // wave masks: lanes with a passing accumulator in block b
+  uint64_t any = 0;
+#pragma unroll
+  for (int b = 0; b < QB; ++b) {
+    pm[b] = __ballot(max16(acc[b]) >= hj);
+    any |= pm[b];
+  }
+  if (!any) return;
+  // uncommon: push the passing pairs of each block with a passing lane into
+  // the wavefront's LDS stage (at most 16 x 64 per block).  The row base is
+  // made opaque per step so that the 16 QB row offsets are not hoisted out of
+  // the step loop into registers.
+  int qb = (int)q0 + 4 * half;
+  asm volatile("" : "+v"(qb));
+#pragma unroll
+  for (int b = 0; b < QB; ++b) {
+    if (!pm[b]) continue;
+    if (ROWS) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) wave_push(wbuf, wcnt, acc[b][r] >= hj, qb + b * 32 + 8 * (r >> 2) + (r & 3), jj);
+    } else {
+      uint32_t bits = 0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) bits |= (acc[b][r] >= hj ? 1u : 0u) << r;
+      while (__ballot(bits != 0)) {
+        const bool p = bits != 0;
+        const int r = p ? __ffs(bits) - 1 : 0;
+        bits &= bits - 1;
+        wave_push(wbuf, wcnt, p, qb + b * 32 + 8 * (r >> 2) + (r & 3), jj);
+      }
+    }
+    if (wcnt > kWaveStage - 16 * kWave) wave_flush(wbuf, wcnt, sink);
+  }
+}
+
+// One 32-candidate step of the bf16 screen for QB blocks of 32 queries.
 // Operand slice s of the candidate is B[s] for s < NL and B[s - NL] beyond
 // (the split layout repeats hi as the third segment).
 template <int NS, int QB, int NL>
@@ -153,33 +201,7 @@ __device__ __forceinline__ void screen_step(const bf16x8 (&A)[QB][NS], const f32
 #pragma unroll
     for (int b = 0; b < QB; ++b)
       acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][s], B[s < NL ? s : s - NL], acc[b], 0, 0, 0);
-  uint64_t pm[QB];  // wave masks: lanes with a passing accumulator in block b
-  uint64_t any = 0;
-#pragma unroll
-  for (int b = 0; b < QB; ++b) {
-    pm[b] = __ballot(max16(acc[b]) >= hj);
-    any |= pm[b];
-  }
-  if (any) {
-    // uncommon: in each query block with a passing lane, collect each lane's
-    // passing accumulators as a bit mask, then push one pair per lane per
-    // round into the wavefront's LDS stage (at most 16 x 64 per block)
-    const int jj = j0 + jr;
-#pragma unroll
-    for (int b = 0; b < QB; ++b) {
-      if (!pm[b]) continue;
-      uint32_t bits = 0;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) bits |= (acc[b][r] >= hj ? 1u : 0u) << r;
-      while (__ballot(bits != 0)) {
-        const bool p = bits != 0;
-        const int r = p ? __ffs(bits) - 1 : 0;
-        bits &= bits - 1;
-        wave_push(wbuf, wcnt, p, (int)q0 + b * 32 + 8 * (r >> 2) + 4 * half + (r & 3), jj);
-      }
-      if (wcnt > kWaveStage - 16 * kWave) wave_flush(wbuf, wcnt, sink);
-    }
-  }
+  screen_epilogue<QB, false>(acc, hj, j0 + jr, q0, half, wbuf, wcnt, sink);
 }
 
 template <int NS, int QB, int NL>
@@ -257,6 +279,162 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
   wave_flush(wbuf, wcnt, q.sink);
 }
 
+// ---- fp32 operands ------------------------------------------------------------
+// The same screen with v_mfma_f32_32x32x2_f32: the operands are the fp32
+// centred rows themselves (no representation error, c_rep = 0), so the only
+// screen error is the fp32 rounding of the product chain and the band that
+// goes to the float64 recheck is a few ulps wide (a bf16 band would be several
+// times R^2 wide for low-dimensional particle data), while the compare
+// epilogue is amortised over 32 x 32 blocks.  K = 2 NK coordinates (zero padded).
+// Candidate operands: blocks of 32 rows, NK slices of two coordinates, a
+// slice being 64 floats [k][row], so lane l = 32 k + row reads float l.  The
+// query rows are [y, C_q, 0 ...] of stride DV (k_mfma32_qprep).
+template <int NK, int QB>
+__global__ __launch_bounds__(kThreads) void k_cand_mfma32(QueryDev q, Mfma32Dev x) {
+  __shared__ int2 wstage[kWaves][kWaveStage];
+  __shared__ long long s_unit;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int xcd = blockIdx.x % q.nxcd;
+  int2* wbuf = wstage[wave];
+  int wcnt = 0;  // wave-uniform fill of wbuf
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_unit = next_unit(q, xcd);
+    __syncthreads();
+    const int64_t u = uniform_i64(s_unit);
+    if (u < 0) break;
+    int tile;
+    int64_t c;
+    if (!decode_unit(q, u, tile, c)) continue;
+    const int64_t q0 = (int64_t)tile * q.T + (int64_t)wave * 32 * QB;
+    const int64_t j0 = q.tlo[tile] + c * q.CH;
+    const int64_t j1 = min(j0 + q.CH, (int64_t)q.thi[tile]);
+    if (q0 >= q.m) continue;  // this wave has no queries in the (ragged) last tile
+
+    float A[QB][NK];
+    f32x16 Cin[QB];
+#pragma unroll
+    for (int b = 0; b < QB; ++b) {
+      const int64_t qr = q0 + b * 32 + l32;
+      const bool vq = qr < q.m;
+      const float* row = x.vq + (vq ? qr : 0) * x.DV;
+#pragma unroll
+      for (int s = 0; s < NK; ++s) {
+        const int k = 2 * s + half;
+        A[b][s] = (vq && k < x.d) ? row[k] : 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t qi = q0 + b * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        Cin[b][r] = qi < q.m ? x.vq[qi * x.DV + x.d] : -INFINITY;
+      }
+    }
+
+    // Step `it` covers candidates j0 + 32 it + l32 (j0 is a multiple of 32):
+    // NK slices of 256 bytes through a buffer resource whose reads past the
+    // unit return zeros; lanes past j1 are masked by h = +inf.  Two register
+    // sets alternate so the next step's operands load during this step.
+    const int span = (int)(j1 - j0);
+    const int nsteps = (span + 31) / 32;
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(x.cop + (j0 / 32) * (NK * 64)), (short)0, nsteps * NK * 256, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rh =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(x.h + j0), (short)0, nsteps * 128, kRsrcWord3);
+    const int voff_c = lane * 4, voff_h = l32 * 4;
+    float B0[NK], B1[NK];
+    float h0, h1;
+    auto load = [&](float (&B)[NK], float& h, int it) {
+#pragma unroll
+      for (int s = 0; s < NK; ++s)
+        B[s] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rc, voff_c, it * (NK * 256) + s * 256, 0));
+      h = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rh, voff_h, it * 128, 0));
+    };
+    auto step = [&](const float (&B)[NK], float hv, int it) {
+      const int jr = it * 32 + l32;
+      const float hj = jr < span ? hv : INFINITY;
+      f32x16 acc[QB];
+#pragma unroll
+      for (int b = 0; b < QB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b][0], B[0], Cin[b], 0, 0, 0);
+#pragma unroll
+      for (int s = 1; s < NK; ++s)
+#pragma unroll
+        for (int b = 0; b < QB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b][s], B[s], acc[b], 0, 0, 0);
+      screen_epilogue<QB, true>(acc, hj, (int)j0 + jr, q0, half, wbuf, wcnt, q.sink);
+    };
+    load(B0, h0, 0);
+    for (int it = 0; it < nsteps; it += 2) {
+      load(B1, h1, it + 1);
+      step(B0, h0, it);
+      if (it + 1 >= nsteps) break;
+      load(B0, h0, it + 2);
+      step(B1, h1, it + 1);
+    }
+  }
+  wave_flush(wbuf, wcnt, q.sink);
+}
+
+__global__ __launch_bounds__(kThreads) void k_mfma32_operands(const float* __restrict__ ys, int64_t n, int64_t npad,
+                                                             int d, int NK, float* __restrict__ cop) {
+  const int64_t total = npad * NK * 2;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = e / (NK * 64);
+    const int s = (int)((e / 64) % NK), w = (int)(e % 64);
+    const int64_t row = blk * 32 + (w % 32);
+    const int k = 2 * s + w / 32;
+    cop[e] = (row < n && k < d) ? ys[row * d + k] : 0.f;
+  }
+}
+
+// Query rows of the fp32 screen: [y_0 .. y_{d-1}, C_q, 0 ...] with stride
+// pad4(d + 1); C_q is the rigorous start value for the fp32 product chain.
+__global__ __launch_bounds__(kThreads) void k_mfma32_qprep(const double* __restrict__ q64, int64_t m, int d, int dp,
+                                                          const double* __restrict__ mu, int DV, MixedBound b,
+                                                          float* __restrict__ vq) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x) {
+    float* o = vq + s * DV;
+    double nn = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const float y = (float)(q64[s * dp + k] - mu[k]);
+      nn += (double)y * (double)y;
+      o[k] = y;
+    }
+    for (int k = d + 1; k < DV; ++k) o[k] = 0.f;
+    o[d] = screen_threshold(b, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_mfma32_qprep_self(const float* __restrict__ ys, int64_t n, int d, int DV,
+                                                               MixedBound b, float* __restrict__ vq) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+    float* o = vq + s * DV;
+    double nn = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const float y = ys[s * d + k];
+      nn += (double)y * (double)y;
+      o[k] = y;
+    }
+    for (int k = d + 1; k < DV; ++k) o[k] = 0.f;
+    o[d] = screen_threshold(b, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
+  }
+}
+
+typedef void (*Mfma32Kernel)(QueryDev, Mfma32Dev);
+
+Mfma32Kernel pick_kernel32(int d) {
+  switch ((d + 1) / 2) {
+    case 1: return k_cand_mfma32<1, 4>;
+    case 2: return k_cand_mfma32<2, 4>;
+    case 3: return k_cand_mfma32<3, 4>;
+    case 4: return k_cand_mfma32<4, 4>;
+    case 5: return k_cand_mfma32<5, 4>;
+    case 6: return k_cand_mfma32<6, 4>;
+    case 7: return k_cand_mfma32<7, 4>;
+    case 8: return k_cand_mfma32<8, 4>;
+    default: return nullptr;
+  }
+}
+
 typedef void (*MixedKernel)(QueryDev, MixedDev);
 
 // Query blocks of 32 per wavefront: every candidate load feeds QB product
@@ -305,6 +483,48 @@ void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const doubl
 
 void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* cthr, hipStream_t s) {
   k_mixed_qprep_self<<<grid_for(n, 8192), kThreads, 0, s>>>(ys, n, d, b, cthr);
+  SNN_LAUNCH_CHECK();
+}
+
+int mfma32_max_d() { return 16; }
+int mfma32_query_floats(int d) { return ((d + 1 + 3) / 4) * 4; }
+int mfma32_queries_per_tile() { return 4 * 32 * 4; }
+int64_t mfma32_operand_floats(int64_t n, int d) { return ((n + 32 + 31) / 32) * 32 * 2 * ((d + 1) / 2); }
+
+int mfma32_blocks_per_cu(int d) {
+  Mfma32Kernel k = pick_kernel32(d);
+  int nb = 0;
+  if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kThreads, 0) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  return nb;
+}
+
+void launch_mfma32_operands(const float* ys, int64_t n, int d, float* cop, hipStream_t s) {
+  const int64_t npad = ((n + 32 + 31) / 32) * 32;
+  k_mfma32_operands<<<grid_for(npad * 2 * ((d + 1) / 2), 16384), kThreads, 0, s>>>(ys, n, npad, d, (d + 1) / 2, cop);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_mfma32_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, const MixedBound& b, float* vq,
+                         hipStream_t s) {
+  if (m <= 0) return;
+  k_mfma32_qprep<<<grid_for(m, 8192), kThreads, 0, s>>>(q64, m, d, dp, mu, mfma32_query_floats(d), b, vq);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_mfma32_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* vq, hipStream_t s) {
+  if (n <= 0) return;
+  k_mfma32_qprep_self<<<grid_for(n, 8192), kThreads, 0, s>>>(ys, n, d, mfma32_query_floats(d), b, vq);
+  SNN_LAUNCH_CHECK();
+}
+
+// T must equal mfma32_queries_per_tile(); tile windows aligned to 32 rows.
+void launch_cand_mfma32(const QueryDev& q, const Mfma32Dev& x, int grid, hipStream_t s) {
+  Mfma32Kernel k = pick_kernel32(x.d);
+  if (!k) fail(SNN_ENOTSUP, "fp32 matrix-core screen supports d <= 16");
+  k<<<grid, kThreads, 0, s>>>(q, x);
   SNN_LAUNCH_CHECK();
 }
 

@@ -192,16 +192,24 @@ void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const doubl
 void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* cthr, hipStream_t s);
 void launch_cand_mfma(const QueryDev& q, const MixedDev& x, int grid, hipStream_t s);
 
-// k_cand_valu.hip: fp32 vector screen for d <= 16
-int valu_max_d();
-int valu_row_floats(int d);
-int valu_queries_per_tile();
-int valu_blocks_per_cu(int d);
-void launch_valu_operands(const float* ys, const float* h, int64_t n, int d, float* vc, hipStream_t s);
-void launch_valu_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, const MixedBound& b, float* vq,
-                       hipStream_t s);
-void launch_valu_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* vq, hipStream_t s);
-void launch_cand_valu(const QueryDev& q, const float* vq, const float* vc, int grid, hipStream_t s);
+// k_cand_mfma.hip: fp32 matrix-core screen for d <= 16
+struct Mfma32Dev {
+  const float* vq;   // m x DV: query rows [y, C_q, 0 ...] (score order)
+  int DV;
+  int d;
+  const float* cop;  // candidate operand blocks (see k_cand_mfma32)
+  const float* h;    // n + 64: fl32(||y_j||^2 / 2), padding +inf
+};
+int mfma32_max_d();
+int mfma32_query_floats(int d);  // stride of a query row [y, C_q, 0 ...]
+int mfma32_queries_per_tile();
+int64_t mfma32_operand_floats(int64_t n, int d);
+int mfma32_blocks_per_cu(int d);
+void launch_mfma32_operands(const float* ys, int64_t n, int d, float* cop, hipStream_t s);
+void launch_mfma32_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, const MixedBound& b, float* vq,
+                         hipStream_t s);
+void launch_mfma32_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* vq, hipStream_t s);
+void launch_cand_mfma32(const QueryDev& q, const Mfma32Dev& x, int grid, hipStream_t s);
 
 // k_csr.hip
 struct Survivors {

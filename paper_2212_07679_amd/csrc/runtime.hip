@@ -147,10 +147,10 @@ struct HostCtl {
 }  // namespace
 
 // ------------------------------------------------------------------------ query
-static void build_valu_operands(Index& ix) {
+static void build_fp32_operands(Index& ix) {
   if (ix.vcand_built) return;
-  ix.vcand.ensure(ix.arena, sizeof(float) * (ix.n + 8) * valu_row_floats(ix.d) + 256);
-  launch_valu_operands(ix.ys.as<float>(), ix.h.as<float>(), ix.n, ix.d, ix.vcand.as<float>(), ix.arena.stream());
+  ix.vcand.ensure(ix.arena, sizeof(float) * mfma32_operand_floats(ix.n, ix.d) + 256);
+  launch_mfma32_operands(ix.ys.as<float>(), ix.n, ix.d, ix.vcand.as<float>(), ix.arena.stream());
   ix.vcand_built = true;
 }
 
@@ -206,7 +206,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   if (prec == SNN_PREC_AUTO) {
     if (fits(terms) && rel_band(terms) <= 0.5)
       prec = SNN_PREC_MIXED;
-    else if (d <= valu_max_d())
+    else if (d <= mfma32_max_d())
       prec = SNN_PREC_FP32;
     else if (fits(1) && rel_band(1) <= 2.0) {
       prec = SNN_PREC_MIXED;
@@ -216,17 +216,17 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   }
   if (prec == SNN_PREC_MIXED && !fits(terms))
     fail(SNN_ENOTSUP, "mixed screen: packed operand rows longer than 128 bf16 (lower d or use terms=1)");
-  if (prec == SNN_PREC_FP32 && d > valu_max_d()) fail(SNN_ENOTSUP, "fp32 vector screen supports d <= 16");
+  if (prec == SNN_PREC_FP32 && d > mfma32_max_d()) fail(SNN_ENOTSUP, "fp32 screen supports d <= 16");
   int T_fixed = 0;
   if (prec == SNN_PREC_MIXED) T_fixed = 4 * mixed_queries_per_wave(ka_of(terms));
-  if (prec == SNN_PREC_FP32) T_fixed = valu_queries_per_tile();
+  if (prec == SNN_PREC_FP32) T_fixed = mfma32_queries_per_tile();
   if (T_fixed && o.tile_q && o.tile_q != T_fixed)
     fail(SNN_EINVAL, "tile_q must be " + std::to_string(T_fixed) + " for this screen and dimension");
   const int T = T_fixed ? T_fixed : (o.tile_q ? o.tile_q : 64);
-  const int CH = o.tile_c ? o.tile_c : (prec == SNN_PREC_MIXED ? 4096 : prec == SNN_PREC_FP32 ? 2048 : 1024);
-  if (prec == SNN_PREC_MIXED && CH % 32 != 0) fail(SNN_EINVAL, "mixed screen: tile_c must be a multiple of 32");
+  const int CH = o.tile_c ? o.tile_c : (prec == SNN_PREC_FP64 ? 1024 : 4096);
+  if (prec != SNN_PREC_FP64 && CH % 32 != 0) fail(SNN_EINVAL, "matrix-core screens: tile_c must be a multiple of 32");
   if (prec == SNN_PREC_MIXED) build_mixed_operands(ix, terms);
-  if (prec == SNN_PREC_FP32) build_valu_operands(ix);
+  if (prec == SNN_PREC_FP32) build_fp32_operands(ix);
   const int ntiles = (int)std::max<int64_t>(1, (m + T - 1) / T);
 
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -293,7 +293,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     const bool mix = prec == SNN_PREC_MIXED;
     p.qop = c.take<uint16_t>(mix && !self ? (size_t)m * ka_of(terms) : 1);
     p.cthr = c.take<float>(mix ? std::max<int64_t>(m, 1) : 1);
-    p.vq = c.take<float>(prec == SNN_PREC_FP32 ? (size_t)std::max<int64_t>(m, 1) * valu_row_floats(d) : 1);
+    p.vq = c.take<float>(prec == SNN_PREC_FP32 ? (size_t)std::max<int64_t>(m, 1) * mfma32_query_floats(d) : 1);
     return p;
   };
   plan_query(probe);
@@ -336,7 +336,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const double eps_scale = 1.01 * (u32 + gamma64(d + 2)) * (1.0 + u32) * ix.vnorm;
   // self-queries scan each unordered pair once (S is exactly symmetric)
   const int sym = (self && !o.full_self_scan) ? 1 : 0;
-  launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, CH, prec == SNN_PREC_MIXED ? 32 : 1,
+  launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, CH, prec == SNN_PREC_FP64 ? 1 : 32,
                  ntiles, sym, P.lo, P.hi, P.tlo, P.thi, P.units, &P.ctl->pairs_window, s);
   // chunk-major work order inside groups of G score-adjacent tiles (L2 reuse)
   const int G = prec == SNN_PREC_FP64 ? 16 : 8;
@@ -384,11 +384,12 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     }
   }
   if (prec == SNN_PREC_FP32) {
-    const MixedBound vb = mixed_bound(0, d, d, R2, Y);
+    // K = d rounded up to the two coordinates of one fp32 matrix instruction
+    const MixedBound vb = mixed_bound(0, 2 * ((d + 1) / 2), d, R2, Y);
     if (self)
-      launch_valu_qprep_self(ix.ys.as<float>(), n, d, vb, P.vq, s);
+      launch_mfma32_qprep_self(ix.ys.as<float>(), n, d, vb, P.vq, s);
     else
-      launch_valu_qprep(q64, m, d, ix.dp, ix.mu.as<double>(), vb, P.vq, s);
+      launch_mfma32_qprep(q64, m, d, ix.dp, ix.mu.as<double>(), vb, P.vq, s);
   }
 
   // survivors: capacity remembered on the index, grown on overflow
@@ -422,7 +423,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       launch_fill_i32(P.row_cnt, m, 0, s);
     }
     const int per_cu = prec == SNN_PREC_MIXED  ? mixed_blocks_per_cu(mx.KA, mx.KB)
-                       : prec == SNN_PREC_FP32 ? valu_blocks_per_cu(d)
+                       : prec == SNN_PREC_FP32 ? mfma32_blocks_per_cu(d)
                                                : fp64_blocks_per_cu(ix.dp);
     const int grid = std::max(di.xcds, (di.cus * per_cu / di.xcds) * di.xcds);
     if (st) SNN_HIP(hipEventRecord(ev[1], s));
@@ -430,7 +431,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       if (prec == SNN_PREC_MIXED)
         launch_cand_mfma(qd, mx, grid, s);
       else if (prec == SNN_PREC_FP32)
-        launch_cand_valu(qd, P.vq, ix.vcand.as<float>(), grid, s);
+        launch_cand_mfma32(qd, Mfma32Dev{P.vq, mfma32_query_floats(d), d, ix.vcand.as<float>(), ix.h.as<float>()}, grid,
+                           s);
       else
         launch_cand_fp64(qd, grid, s);
     }

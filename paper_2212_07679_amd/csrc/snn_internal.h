@@ -137,7 +137,7 @@ struct Index {
   Buffer h;     // n + 32 floats: ||ys||^2 / 2 rounded to nearest, sorted; padding +inf
   Buffer ynorm; // n floats: ||ys|| rounded up, sorted
   MixedOperands mixed[2];  // [0]: terms = 1, [1]: terms = 3
-  Buffer vcand;            // (n + 8) x pad4(d + 1) floats: [y, h] rows for the fp32 vector screen
+  Buffer vcand;            // fp32 screen candidate operand blocks (k_cand_mfma32)
   bool vcand_built = false;
 
   double max_norm = 0;  // max ||ys_i|| (float64, rounded up)
