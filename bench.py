@@ -420,6 +420,9 @@ def main():
         "fp64_gpu_qps": fp64["qps"] if fp64 else None,
         "speedup_vs_fp64_gpu": (r["qps"] / fp64["qps"]) if (fp64 and head != "fp64") else None,
         "pairs_window": st["pairs_window"],
+        "pairs_executed": st["pairs_executed"],
+        "pairs_window_per_s": st["pairs_window"] / (r["screen_ms"] / 1e3),
+        "pairs_executed_per_s": st["pairs_executed"] / (r["screen_ms"] / 1e3),
         "pairs_recheck": st["pairs_recheck"],
         "recheck_fraction": st["pairs_recheck"] / max(st["pairs_window"], 1),
         "nnz": st["nnz"],

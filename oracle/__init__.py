@@ -28,6 +28,8 @@ snn     O2: Algorithms 1 and 2 of Section 3 on the CPU -- centring, first
         decomposition of eq. (ip2) -- plus a rigorous floating-point band in
         which decisions are re-taken with the normative S.
 exact   O3: exact rational arithmetic on tiny inputs (fractions.Fraction).
+dbscan  DBSCAN (the application of Section 6.4) on self-query neighbour
+        lists: core points, clusters grown in index order, border points.
 
 Pins: see tests/test_oracle_*.py.  Every function here is pinned by at least
 one test that does not re-use its own formula (exact rationals, lattice
@@ -38,6 +40,7 @@ Cauchy-Schwarz invariant of eq. (lower), the sigma_2 = 0 special case).
 from .brute import Neighbors, normative_sqdist, brute_radius
 from .snn import SnnIndex, build_index, query as snn_query, first_principal_component
 from .exact import exact_sqdist, exact_radius
+from .dbscan import Clustering, dbscan, dbscan_from_neighbors
 
 __all__ = [
     "Neighbors",
@@ -49,4 +52,7 @@ __all__ = [
     "first_principal_component",
     "exact_sqdist",
     "exact_radius",
+    "Clustering",
+    "dbscan",
+    "dbscan_from_neighbors",
 ]

@@ -191,6 +191,20 @@ __global__ void k_group_units(const int32_t* __restrict__ units, int ntiles, int
   }
 }
 
+// Pairs the screen evaluates: wavefronts (of qpw query slots) with at least
+// one real query, times their slots, times the tile's scanned window.
+__global__ void k_executed(const int32_t* __restrict__ tlo, const int32_t* __restrict__ thi, int ntiles, int T,
+                           int64_t m, int qpw, unsigned long long* __restrict__ out) {
+  unsigned long long e = 0;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
+    const int64_t valid = min((int64_t)T, max((int64_t)0, m - (int64_t)t * T));
+    const int64_t waves = (valid + qpw - 1) / qpw;
+    e += (unsigned long long)(waves * qpw) * (unsigned long long)max(0, thi[t] - tlo[t]);
+  }
+  e = wave_sum(e);
+  if (lane_id() == 0 && e) atomicAdd(out, e);
+}
+
 // ---------------------------------------------------------------- launchers
 namespace {
 int grid_for(int64_t work, int cap) {
@@ -206,6 +220,12 @@ void launch_tile_init(int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s) {
 
 void launch_tile_units(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int32_t* units, hipStream_t s) {
   k_tile_units<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles, CH, align, 0, units);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_executed(const int32_t* tlo, const int32_t* thi, int ntiles, int T, int64_t m, int qpw,
+                     unsigned long long* out, hipStream_t s) {
+  k_executed<<<grid_for(ntiles, 64), kThreads, 0, s>>>(tlo, thi, ntiles, T, m, qpw, out);
   SNN_LAUNCH_CHECK();
 }
 

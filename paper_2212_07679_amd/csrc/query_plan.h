@@ -109,6 +109,10 @@ void launch_windows(const double* key, int n, const double* qalpha, const double
 
 void launch_tile_init(int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s);
 void launch_tile_units(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int32_t* units, hipStream_t s);
+// stats only: adds to *out the (query slot, candidate) pairs the screen
+// evaluates, counting qpw slots per wavefront that holds a real query
+void launch_executed(const int32_t* tlo, const int32_t* thi, int ntiles, int T, int64_t m, int qpw,
+                     unsigned long long* out, hipStream_t s);
 
 // units reserved per group of G tiles: Gg x max units of its tiles
 void launch_group_units(const int32_t* units, int ntiles, int G, int32_t* gunits, hipStream_t s);

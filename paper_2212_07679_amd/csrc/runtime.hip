@@ -133,7 +133,7 @@ struct Ctl {
   unsigned long long pairs_window;
   unsigned long long list_counts[8];
   unsigned long long row_max;
-  unsigned long long pad0;
+  unsigned long long executed;
   int bad;
   int pad1;
 };
@@ -338,6 +338,14 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const int sym = (self && !o.full_self_scan) ? 1 : 0;
   launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, CH, prec == SNN_PREC_FP64 ? 1 : 32,
                  ntiles, sym, P.lo, P.hi, P.tlo, P.thi, P.units, &P.ctl->pairs_window, s);
+  if (st) {
+    // query slots per wavefront: the matrix-core screens evaluate whole
+    // 32-query blocks, the float64 screen one query at a time
+    const int qpw = prec == SNN_PREC_MIXED  ? mixed_queries_per_wave(ka_of(terms))
+                    : prec == SNN_PREC_FP32 ? mfma32_queries_per_tile() / 4
+                                            : 1;
+    launch_executed(P.tlo, P.thi, ntiles, T, m, qpw, &P.ctl->executed, s);
+  }
   // chunk-major work order inside groups of G score-adjacent tiles (L2 reuse)
   const int G = prec == SNN_PREC_FP64 ? 16 : 8;
   const int ngroups = (ntiles + G - 1) / G;
@@ -495,8 +503,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     SNN_HIP(hipEventElapsedTime(&b, ev[0], ev[3]));
     st->screen_ms = a;
     st->total_ms = b;
-    int64_t executed = 0;
-    st->pairs_executed = executed;
+    unsigned long long executed = 0;
+    SNN_HIP(hipMemcpy(&executed, &P.ctl->executed, sizeof(executed), hipMemcpyDeviceToHost));
+    st->pairs_executed = (int64_t)executed;
     for (auto& e : ev) (void)hipEventDestroy(e);
   }
 }

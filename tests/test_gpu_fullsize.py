@@ -91,6 +91,7 @@ def run(B, w, prec, rows_count, seed, dense_rows=0):
     say(f"  nnz={row_ptr[-1]} precision_used={B.PRECISION_NAMES[st['precision_used']]} terms={st['terms_used']} "
         f"window pairs={st['pairs_window']} rechecked={st['pairs_recheck']}")
     assert st["nnz"] == row_ptr[-1]
+    assert st["pairs_executed"] >= st["pairs_window"]
     check_whole(row_ptr, col, dist, w.n, w.R, w.Q is None)
     extra = ()
     if dense_rows:

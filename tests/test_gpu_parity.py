@@ -98,6 +98,9 @@ def test_uniform2d_full(B, prec):
     # the GPU window is at least the exact-arithmetic window and close to it
     assert st["pairs_window"] >= 0.99 * ost["pairs_window"]
     assert st["pairs_window"] <= 1.05 * ost["pairs_window"] + 1000
+    # the screen scans tile windows (a superset of every query's window) for
+    # whole query blocks
+    assert st["pairs_executed"] >= st["pairs_window"]
 
 
 @pytest.mark.parametrize("prec", PRECS)
