@@ -48,6 +48,9 @@ WORKLOADS = {
                          "self-query, R=4.0", precisions="auto", cpu_sample=200),
     "blobs3d": dict(desc="blobs3d: n=5e6 d=3 float32, 1000 Gaussian blobs (std 0.01) + 20% uniform background in "
                          "[0,1]^3, all-points self-query, R=0.005", precisions="auto", cpu_sample=500),
+    "dbscan_blobs3d": dict(desc="dbscan_blobs3d: DBSCAN (Section 6.4) of blobs3d, n=5e6 d=3 float32, eps=R=0.005, "
+                                "min_samples=5; one step = all-points self-query + clustering on a built index",
+                           precisions="auto", cpu_sample=50000),
     "batch256": dict(desc="batch256: 256 instances, n log-uniform in [1e3,1e5], d in {3,8,32}, float32 uniform in "
                           "the unit cube, 10% of the points as queries, R for ~30 expected neighbours; one captured "
                           "graph, autotuned tiles", precisions="mixed", cpu_sample=4000),
@@ -331,6 +334,103 @@ def main_batch(a):
     print(json.dumps(line))
 
 
+def main_dbscan(a):
+    """DBSCAN of the particle workload (Section 6.4's application).  One step
+    is the clustering of the indexed points: the all-points self-query with
+    radius eps feeding the union-find labelling on the device.  The index
+    build is timed separately (as for the query workloads), and the route
+    through explicit neighbour lists (snn_query_self + snn_dbscan) is timed
+    beside it."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2212_07679_amd import binding
+    from paper_2212_07679_amd import workloads as W
+
+    spec = WORKLOADS["dbscan_blobs3d"]
+    min_samples = 5
+    w = W.blobs3d(**({"n": a.n} if a.n else {}))
+    eps = w.R
+    X = torch.from_numpy(w.P).to("cuda:0")
+    torch.cuda.synchronize()
+    binding.Index(X).close()  # first build: allocations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx = binding.Index(X)
+    torch.cuda.synchronize()
+    index_ms = (time.perf_counter() - t0) * 1e3
+    stream = idx.stream
+
+    def timed(fn, steps):
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        out = None
+        for _ in range(steps):
+            out = fn()
+        stop.record(stream)
+        torch.cuda.synchronize()
+        return start.elapsed_time(stop) / steps, out
+
+    fused = lambda: idx.dbscan(eps, min_samples, stats=True)  # noqa: E731
+
+    def lists():
+        rp, col, _ = idx.query_self(eps)
+        return binding.dbscan_csr(rp, col, min_samples, stream=stream)
+
+    for _ in range(a.warmup):
+        fused()
+    ms, (labels, core, k, st) = timed(fused, a.steps)
+    lists()
+    lists_ms, (labels2, core2, k2) = timed(lists, max(1, min(a.steps, 3)))
+    assert torch.equal(labels, labels2) and torch.equal(core, core2) and k == k2, "the two routes differ"
+    lab = labels.cpu().numpy()
+    assert k == int(lab.max()) + 1 and lab.min() >= -1
+    print(f"[bench] dbscan: {ms:.3f} ms/step (screen {st['screen_ms']:.3f}), via neighbour lists {lists_ms:.3f} ms, "
+          f"index {index_ms:.1f} ms, clusters {k}, noise {int((lab == -1).sum())}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if a.cpu_sample != 0:
+        ns = spec["cpu_sample"] if a.cpu_sample < 0 else a.cpu_sample
+        # the same recipe at a size the oracle finishes in seconds: blob count
+        # scaled with n, so the points per blob (and the density) stay the same
+        kb = max(1, round(1000 * ns / w.n))
+        ws = W.blobs3d(n=ns, k=kb)
+        t0 = time.perf_counter()
+        oracle.dbscan(ws.P, eps, min_samples)
+        tc = time.perf_counter() - t0
+        cpu = {"value": ns / tc, "unit": "points/s", "cores": oracle_cores(), "kind": "oracle",
+               "sample": f"the blobs3d recipe at n={ns} with {kb} blobs (same points per blob), eps={eps}, "
+                         f"min_samples={min_samples}; brute-force lists + DBSCAN, {tc:.1f} s"}
+    line = {
+        "metric": "DBSCAN points/s (self-query + clustering on a built index)",
+        "value": w.n / (ms / 1e3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": spec["desc"], "n": w.n, "d": w.d, "eps": eps, "min_samples": min_samples},
+        "index_ms": index_ms,
+        "via_lists_ms_per_step": lists_ms,
+        "clusters": k,
+        "noise": int((lab == -1).sum()),
+        "nnz": st["nnz"],
+        "pairs_window": st["pairs_window"],
+        "pairs_recheck": st["pairs_recheck"],
+        "screen_ms": st["screen_ms"],
+        "roofline": roofline(binding.PRECISION_NAMES[st["precision_used"]], st["terms_used"], st, st["screen_ms"],
+                             w.d),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -342,6 +442,9 @@ def main():
         return
     if a.workload == "batch256":
         main_batch(a)
+        return
+    if a.workload == "dbscan_blobs3d":
+        main_dbscan(a)
         return
     import numpy as np
     import torch

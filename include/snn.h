@@ -224,6 +224,46 @@ void snn_batch_free(snn_batch_t batch);
 snn_status snn_query_batch(const snn_device* dev, snn_dtype dtype, const snn_instance* instances,
                            int32_t count, const snn_batch_options* opts, snn_stats* st);
 
+/* ---- DBSCAN on self-query neighbour lists (Section 6.4) --------------------
+ * Section 6.4 runs DBSCAN with SNN as its radius search (eps = R; its
+ * experiments fix min_samples = 5).  Input: the CSR of an all-points
+ * self-query, row i = { j : S(p_j, p_i) <= fl(eps*eps) } with i itself in
+ * it and membership symmetric (j in row i iff i in row j), as
+ * snn_query_self returns; only row_ptr and col are read.  Output:
+ *   core[i]    = 1 iff row i has at least min_samples entries;
+ *   labels[i]  = the cluster of a core point, where clusters are the
+ *                connected components of the core points under "j in row
+ *                i", numbered 0, 1, ... in order of their smallest core id;
+ *                for a non-core point the smallest cluster number among the
+ *                core points of its row; -1 (noise) if there is none.
+ * These are the labels of the classic DBSCAN that visits the points in
+ * index order (scikit-learn's).
+ *   row_ptr:   device, n + 1 int64 (row_ptr[0] = 0, non-decreasing)
+ *   col:       device, row_ptr[n] int32 ids in [0, n)
+ *   labels:    device, n int32 (out)
+ *   core:      device, n uint8 (out; NULL: not returned)
+ *   nclusters: host (out; NULL: not returned)
+ * Scratch comes from dev->alloc; the work runs on dev->stream and the call
+ * returns when the labels are written.  Errors: SNN_EINVAL (NULL pointers,
+ * n < 0, min_samples < 1, row_ptr not starting at 0 or decreasing, an id
+ * outside [0, n) -- checked on the device before any other pass),
+ * SNN_ENOMEM, SNN_EDEVICE. */
+snn_status snn_dbscan(const snn_device* dev, int64_t n, const int64_t* row_ptr, const int32_t* col,
+                      int32_t min_samples, int32_t* labels, uint8_t* core, int64_t* nclusters);
+
+/* DBSCAN of the indexed points themselves: the all-points self-query with
+ * radius eps (as snn_query_self) feeds the clustering directly, without
+ * assembling neighbour lists or distances.  The labels, core flags and
+ * cluster count are those snn_dbscan gives on snn_query_self's lists for
+ * R = eps.  labels: device, n int32 (original point order); core: device, n
+ * uint8 (nullable); nclusters: host (nullable); opts and st as for
+ * snn_query_self (st->nnz = neighbour entries, self included).  Work runs on
+ * the index's stream; the call returns when the labels are written.
+ * Errors: SNN_EINVAL (NULL index or labels, min_samples < 1, eps < 0 or not
+ * finite), SNN_ENOTSUP, SNN_ENOMEM, SNN_EDEVICE. */
+snn_status snn_dbscan_index(snn_index_t index, double eps, int32_t min_samples, const snn_options* opts,
+                            int32_t* labels, uint8_t* core, int64_t* nclusters, snn_stats* st);
+
 /* Stable LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit)
  * of the keys, in place (the building block of Algorithm 1, step 6).
  *   keys, vals: device, n entries each.  0 <= begin_bit < end_bit <= 32.

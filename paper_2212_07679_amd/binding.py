@@ -164,6 +164,12 @@ SIGNATURES = {
     "snn_index_free": (None, [ctypes.c_void_p]),
     "snn_sort_pairs_u32": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
+    "snn_dbscan": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_int64)]),
+    "snn_dbscan_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(snn_options),
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(snn_stats)]),
     "snn_last_error": (ctypes.c_char_p, []),
     "snn_version": (ctypes.c_char_p, []),
 }
@@ -327,6 +333,27 @@ class Index:
         return self._run(None, self.n, R, self._opts(precision, terms, tile_q, tile_c, full_self_scan), nnz_cap,
                          stats)
 
+    def dbscan(self, eps: float, min_samples: int = 5, precision: str = "auto", stats: bool = False,
+               full_self_scan: bool = False):
+        """DBSCAN (Section 6.4) of the indexed points with eps-neighbourhoods
+        of this index's self-query, clustered on the device without
+        assembling the neighbour lists.  Returns ``(labels, core, nclusters)``
+        (plus the stats dict): int32 labels in the original point order (-1
+        noise, clusters numbered by smallest core id), a bool core mask."""
+        opts = self._opts(precision, 0, 0, 0, full_self_scan)
+        dev = f"cuda:{self.device}"
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            labels = torch.empty(max(self.n, 1), dtype=torch.int32, device=dev)
+            core = torch.empty(max(self.n, 1), dtype=torch.uint8, device=dev)
+            k = ctypes.c_int64(0)
+            st = snn_stats()
+            _check(lib().snn_dbscan_index(self._h, float(eps), int(min_samples), ctypes.byref(opts),
+                                          ctypes.c_void_p(labels.data_ptr()), ctypes.c_void_p(core.data_ptr()),
+                                          ctypes.byref(k), ctypes.byref(st)))
+            core = core[:self.n].bool()
+        res = (labels[:self.n], core, int(k.value))
+        return (res + (st.as_dict(),)) if stats else res
+
     def view(self) -> dict:
         """Index internals copied into new tensors (for checks)."""
         v = snn_index_view()
@@ -357,6 +384,47 @@ def sort_pairs_u32(keys: torch.Tensor, vals: torch.Tensor, begin_bit: int = 0, e
     alloc = _TorchAllocator(device)
     _check(lib().snn_sort_pairs_u32(ctypes.byref(alloc.dev), ctypes.c_void_p(keys.data_ptr()),
                                     ctypes.c_void_p(vals.data_ptr()), keys.numel(), begin_bit, end_bit))
+
+
+def dbscan_csr(row_ptr: torch.Tensor, col: torch.Tensor, min_samples: int = 5,
+               stream: Optional[torch.cuda.Stream] = None):
+    """DBSCAN labels from all-points self-query lists (Section 6.4).
+
+    row_ptr (n+1, int64) and col (int32) are CUDA tensors as returned by
+    ``Index.query_self``; the work runs on ``stream`` (default: the current
+    stream), which must be ordered after the producer of the lists.  Returns ``(labels, core, nclusters)``: int32 labels
+    (-1 noise, clusters numbered by smallest core id), a bool core mask and
+    the cluster count."""
+    for t, dt, name in ((row_ptr, torch.int64, "row_ptr"), (col, torch.int32, "col")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dim() != 1 or t.dtype != dt:
+            raise SnnError(SNN_EINVAL, f"{name} must be a 1-D CUDA {dt} tensor")
+    if row_ptr.numel() < 1:
+        raise SnnError(SNN_EINVAL, "row_ptr must hold n + 1 entries")
+    row_ptr = row_ptr.contiguous()
+    col = col.contiguous()
+    n = row_ptr.numel() - 1
+    device = row_ptr.device.index if row_ptr.device.index is not None else torch.cuda.current_device()
+    alloc = _TorchAllocator(device, stream)
+    with torch.cuda.device(device), torch.cuda.stream(alloc.stream):
+        labels = torch.empty(max(n, 1), dtype=torch.int32, device=f"cuda:{device}")
+        core = torch.empty(max(n, 1), dtype=torch.uint8, device=f"cuda:{device}")
+        k = ctypes.c_int64(0)
+        _check(lib().snn_dbscan(ctypes.byref(alloc.dev), n, ctypes.c_void_p(row_ptr.data_ptr()),
+                                ctypes.c_void_p(col.data_ptr()), int(min_samples), ctypes.c_void_p(labels.data_ptr()),
+                                ctypes.c_void_p(core.data_ptr()), ctypes.byref(k)))
+        core = core[:n].bool()
+    return labels[:n], core, int(k.value)
+
+
+def dbscan(X: torch.Tensor, eps: float, min_samples: int = 5, precision: str = "auto"):
+    """DBSCAN of the rows of X: SNN index, then ``Index.dbscan`` (the
+    self-query's accepted pairs clustered on the device).  Returns
+    ``(labels, core, nclusters)``."""
+    idx = Index(X)
+    try:
+        return idx.dbscan(eps, min_samples, precision=precision)
+    finally:
+        idx.close()
 
 
 class Batch:

@@ -83,6 +83,46 @@ __global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, 
   }
 }
 
+// Self-query survivors for clustering: the same normative decision, but a
+// survivor only counts in the rows of both its points (a pair below the
+// diagonal of a symmetric scan is the mirror of one decided elsewhere) and
+// keeps its query slot in res_q as the "accepted" mark (-1 otherwise); no
+// distances, no row slots.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_recheck_edges(QueryDev q, Survivors sv, const T* __restrict__ po,
+                                                           int32_t* __restrict__ row_cnt,
+                                                           unsigned long long* __restrict__ accepted) {
+  const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count);
+  const int d = q.d;
+  unsigned long long acc = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int2 pr = sv.pairs[i];
+    bool keep = !q.sym || pr.y >= pr.x;
+    if (keep) {
+      const T* pp = po + (int64_t)pr.y * d;
+      const T* qp = po + (int64_t)pr.x * d;
+      double s = 0.0;
+      for (int k = 0; k < d; ++k) {
+        const double t = (double)pp[k] - (double)qp[k];
+        s = s + t * t;
+      }
+      keep = s <= q.R2;
+    }
+    if (keep) {
+      atomicAdd(&row_cnt[pr.x], 1);
+      ++acc;
+      if (q.sym && pr.y != pr.x) {
+        atomicAdd(&row_cnt[pr.y], 1);
+        ++acc;
+      }
+    }
+    sv.res_q[i] = keep ? pr.x : -1;
+  }
+  acc = wave_sum(acc);
+  if (lane_id() == 0 && acc) atomicAdd(accepted, acc);
+}
+
 __global__ __launch_bounds__(kThreads) void k_scatter(Survivors sv, const int64_t* __restrict__ row_ptr,
                                                      uint64_t* __restrict__ keys) {
   const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count) * sv.per;
@@ -410,6 +450,15 @@ void launch_recheck(const QueryDev& q, const Survivors& sv, snn_dtype dt, const 
     else
       k_recheck<double, false><<<grid, kThreads, 0, s>>>(q, sv, static_cast<const double*>(po), row_cnt);
   }
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_recheck_edges(const QueryDev& q, const Survivors& sv, snn_dtype dt, const void* po, int32_t* row_cnt,
+                          unsigned long long* accepted, int grid, hipStream_t s) {
+  if (dt == SNN_F32)
+    k_recheck_edges<float><<<grid, kThreads, 0, s>>>(q, sv, static_cast<const float*>(po), row_cnt, accepted);
+  else
+    k_recheck_edges<double><<<grid, kThreads, 0, s>>>(q, sv, static_cast<const double*>(po), row_cnt, accepted);
   SNN_LAUNCH_CHECK();
 }
 

@@ -234,6 +234,19 @@ void launch_recheck(const QueryDev& q, const Survivors& sv, snn_dtype dt, const 
                     int32_t* row_cnt, int grid, hipStream_t s);
 // keys into slot-order rows at row_ptr[row] + slot
 void launch_scatter(const Survivors& sv, const int64_t* row_ptr, uint64_t* keys, int grid, hipStream_t s);
+// self-queries for clustering: row counts of both points of every accepted
+// pair, res_q[i] = query slot of survivor i if accepted else -1 (one entry
+// per survivor), *accepted += neighbour entries
+void launch_recheck_edges(const QueryDev& q, const Survivors& sv, snn_dtype dt, const void* po, int32_t* row_cnt,
+                          unsigned long long* accepted, int grid, hipStream_t s);
+
+// dbscan.hip: clustering of a self-query's accepted pairs (slot space =
+// score order; perm maps a slot to its original id).  work: dbscan_work_bytes(n).
+size_t dbscan_work_bytes(int64_t n);
+// labels / core: original order (core nullable); returns the cluster count
+// (synchronises the stream)
+int64_t dbscan_from_survivors(const Survivors& sv, int64_t n, const int32_t* row_cnt, const int32_t* perm,
+                              int min_samples, void* work, int32_t* labels, uint8_t* core, int grid, hipStream_t s);
 // Source row r of a CSR in slot order (neighbour keys) goes, sorted by id,
 // to destination row map[r] of the caller's CSR.
 struct RowMove {

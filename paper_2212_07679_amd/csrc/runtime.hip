@@ -134,6 +134,7 @@ struct Ctl {
   unsigned long long list_counts[8];
   unsigned long long row_max;
   unsigned long long executed;
+  unsigned long long accepted;  // neighbour entries (clustering mode)
   int bad;
   int pad1;
 };
@@ -154,16 +155,28 @@ static void build_fp32_operands(Index& ix) {
   ix.vcand_built = true;
 }
 
+// Clustering request: the self-query's accepted pairs go to DBSCAN instead
+// of being assembled into neighbour lists.
+struct DbscanReq {
+  int32_t min_samples;
+  int32_t* labels;     // device, n (original order)
+  uint8_t* core;       // device, n or nullptr
+  int64_t nclusters;   // out
+};
+
 static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, const snn_options* opts,
-                      snn_csr* out, snn_stats* st) {
-  if (!out) fail(SNN_EINVAL, "out is NULL");
+                      snn_csr* out, snn_stats* st, DbscanReq* db = nullptr) {
+  if (db && !self) fail(SNN_EINVAL, "clustering needs an all-points self-query");
   if (!std::isfinite(R) || R < 0) fail(SNN_EINVAL, "R must be finite and >= 0");
   if (m < 0) fail(SNN_EINVAL, "m must be >= 0");
   if (m >= (int64_t)INT32_MAX) fail(SNN_EINVAL, "m must be < 2^31 - 1");
   if (!self && m > 0 && !Q) fail(SNN_EINVAL, "Q is NULL");
-  if (!out->row_ptr) fail(SNN_EINVAL, "out->row_ptr is NULL");
-  if (out->nnz_cap < 0) fail(SNN_EINVAL, "nnz_cap must be >= 0");
-  if (out->nnz_cap > 0 && (!out->col || !out->dist)) fail(SNN_EINVAL, "out->col / out->dist is NULL");
+  if (!db) {
+    if (!out) fail(SNN_EINVAL, "out is NULL");
+    if (!out->row_ptr) fail(SNN_EINVAL, "out->row_ptr is NULL");
+    if (out->nnz_cap < 0) fail(SNN_EINVAL, "nnz_cap must be >= 0");
+    if (out->nnz_cap > 0 && (!out->col || !out->dist)) fail(SNN_EINVAL, "out->col / out->dist is NULL");
+  }
   snn_options o{};
   o.precision = SNN_PREC_AUTO;
   if (opts) o = *opts;
@@ -402,8 +415,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
 
   // survivors: capacity remembered on the index, grown on overflow
   // bytes per survivor: the pair, and per result row, column, distance, slot
-  const int per = sym ? 2 : 1;
-  const size_t per_bytes = 8 + 16 * (size_t)per;
+  // (clustering: the pair and one accepted mark)
+  const int per = db ? 1 : (sym ? 2 : 1);
+  const size_t per_bytes = db ? 12 : 8 + 16 * (size_t)per;
   long long cap = std::max<long long>(1 << 16, (long long)(ix.ws[1].bytes / per_bytes));
   HostCtl hc{};
   uint64_t* stage_key = nullptr;  // neighbour keys in slot-order rows
@@ -417,8 +431,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     sv.per = per;
     sv.pairs = sc.take<int2>(cap);
     sv.res_q = sc.take<int32_t>(cap * per);
-    sv.res_key = sc.take<uint64_t>(cap * per);
-    sv.res_slot = sc.take<int32_t>(cap * per);
+    sv.res_key = db ? nullptr : sc.take<uint64_t>(cap * per);
+    sv.res_slot = db ? nullptr : sc.take<int32_t>(cap * per);
     // recompute cap to fit the carve exactly
     sv.cap = cap;
     sv.count = &P.ctl->survivors;
@@ -428,6 +442,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     if (attempt > 0) {
       launch_fill_u64(P.ctl->counters, kMaxXcd, 0ull, s);
       launch_fill_u64(&P.ctl->survivors, 1, 0ull, s);
+      launch_fill_u64(&P.ctl->accepted, 1, 0ull, s);
       launch_fill_i32(P.row_cnt, m, 0, s);
     }
     const int per_cu = prec == SNN_PREC_MIXED  ? mixed_blocks_per_cu(mx.KA, mx.KB)
@@ -445,6 +460,28 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
         launch_cand_fp64(qd, grid, s);
     }
     if (st) SNN_HIP(hipEventRecord(ev[2], s));
+    if (db) {
+      launch_recheck_edges(qd, sv, ix.dtype, ix.po.ptr, P.row_cnt, &P.ctl->accepted, di.cus * 16, s);
+      SNN_HIP(hipMemcpyAsync(&hc.ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+      SNN_HIP(hipStreamSynchronize(s));
+      if ((long long)hc.ctl.survivors <= cap) {
+        ix.ws[3].ensure(ix.arena, dbscan_work_bytes(n));
+        db->nclusters = dbscan_from_survivors(sv, n, P.row_cnt, ix.perm.as<int32_t>(), db->min_samples,
+                                              ix.ws[3].ptr, db->labels, db->core, di.cus * 16, s);
+        if (st) {
+          st->pairs_window = (int64_t)hc.ctl.pairs_window;
+          st->flops_window = 2.0 * d * (double)hc.ctl.pairs_window;
+          st->pairs_recheck = (int64_t)hc.ctl.survivors;
+          st->nnz = (int64_t)hc.ctl.accepted;
+          st->precision_used = prec;
+          st->terms_used = prec == SNN_PREC_MIXED ? terms : 0;
+        }
+        break;
+      }
+      cap = (long long)(hc.ctl.survivors * 5 / 4) + 1024;
+      ix.ws[1].reset(ix.arena);
+      continue;
+    }
     launch_recheck(qd, sv, ix.dtype, ix.po.ptr, self, P.row_cnt, di.cus * 16, s);
     // row offsets in slot order (where the neighbours are assembled) and in
     // the caller's order (where each row ends up)
@@ -481,6 +518,23 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     }
     cap = (long long)(hc.ctl.survivors * 5 / 4) + 1024;
     ix.ws[1].reset(ix.arena);
+  }
+
+  if (db) {
+    if (st) {
+      SNN_HIP(hipEventRecord(ev[3], s));
+      SNN_HIP(hipEventSynchronize(ev[3]));
+      float a = 0, b = 0;
+      SNN_HIP(hipEventElapsedTime(&a, ev[1], ev[2]));
+      SNN_HIP(hipEventElapsedTime(&b, ev[0], ev[3]));
+      st->screen_ms = a;
+      st->total_ms = b;
+      unsigned long long executed = 0;
+      SNN_HIP(hipMemcpy(&executed, &P.ctl->executed, sizeof(executed), hipMemcpyDeviceToHost));
+      st->pairs_executed = (int64_t)executed;
+      for (auto& e : ev) (void)hipEventDestroy(e);
+    }
+    return;
   }
 
   // ---- rows: ids ascending, moved to the caller's row order
@@ -575,6 +629,18 @@ snn_status snn_query_self(snn_index_t idx, double R, const snn_options* opts, sn
   return guard([&] {
     if (!idx) fail(SNN_EINVAL, "index is NULL");
     run_query(*idx, nullptr, idx->n, R, true, opts, out, st);
+  });
+}
+
+snn_status snn_dbscan_index(snn_index_t idx, double eps, int32_t min_samples, const snn_options* opts,
+                            int32_t* labels, uint8_t* core, int64_t* nclusters, snn_stats* st) {
+  return guard([&] {
+    if (!idx) fail(SNN_EINVAL, "index is NULL");
+    if (min_samples < 1) fail(SNN_EINVAL, "min_samples must be >= 1");
+    if (idx->n > 0 && !labels) fail(SNN_EINVAL, "labels is NULL");
+    DbscanReq db{min_samples, labels, core, 0};
+    run_query(*idx, nullptr, idx->n, eps, true, opts, nullptr, st, &db);
+    if (nclusters) *nclusters = db.nclusters;
   });
 }
 

@@ -110,6 +110,27 @@ def test_sort_argument_errors():
     assert L.snn_sort_pairs_u32(ctypes.byref(dev), fake, fake, -1, 0, 32) == B.SNN_EINVAL
 
 
+def test_dbscan_argument_errors():
+    L = B.lib()
+    dev = _dev()
+    fake = ctypes.c_void_p(0x1000)
+    k = ctypes.c_int64(0)
+    assert L.snn_dbscan(None, 4, fake, fake, 5, fake, None, ctypes.byref(k)) == B.SNN_EINVAL
+    assert L.snn_dbscan(ctypes.byref(dev), -1, fake, fake, 5, fake, None, ctypes.byref(k)) == B.SNN_EINVAL
+    assert L.snn_dbscan(ctypes.byref(dev), 4, fake, fake, 0, fake, None, ctypes.byref(k)) == B.SNN_EINVAL
+    assert L.snn_dbscan(ctypes.byref(dev), 4, None, fake, 5, fake, None, ctypes.byref(k)) == B.SNN_EINVAL
+    assert L.snn_dbscan(ctypes.byref(dev), 4, fake, fake, 5, None, None, ctypes.byref(k)) == B.SNN_EINVAL
+    assert L.snn_dbscan(ctypes.byref(dev), 2**31, fake, fake, 5, fake, None, ctypes.byref(k)) == B.SNN_EINVAL
+
+
+def test_dbscan_index_argument_errors():
+    L = B.lib()
+    fake = ctypes.c_void_p(0x1000)
+    k = ctypes.c_int64(0)
+    assert L.snn_dbscan_index(None, 0.1, 5, None, fake, None, ctypes.byref(k), None) == B.SNN_EINVAL
+    assert L.snn_dbscan_index(fake, 0.1, 0, None, fake, None, ctypes.byref(k), None) == B.SNN_EINVAL
+
+
 @pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
                     reason="a GPU may be present; the no-device path is only checked without one")
 def test_no_device_is_a_clean_error():
