@@ -184,11 +184,19 @@ __global__ __launch_bounds__(kThreads) void k_dbe_init(int64_t n, const int32_t*
   }
 }
 
+// The survivors come in score order, so neighbouring entries belong to the
+// same few growing components: each wavefront takes its own contiguous
+// slice of the list, so that the pairs in flight at any moment are spread
+// over the whole point set (and over many roots) while every wavefront still
+// reads its slice coalesced.
 __global__ __launch_bounds__(kThreads) void k_dbe_hook(Survivors sv, const uint8_t* __restrict__ core_s,
                                                        int32_t* parent, const int32_t* __restrict__ perm) {
   const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count);
-  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < cnt;
-       k += (long long)gridDim.x * blockDim.x) {
+  const long long nw = (long long)gridDim.x * (blockDim.x / kWave);
+  const long long w = (long long)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const long long per = (cnt + nw - 1) / nw;
+  const long long k1 = min(cnt, (w + 1) * per);
+  for (long long k = w * per + lane_id(); k < k1; k += kWave) {
     if (sv.res_q[k] < 0) continue;
     const int2 pr = sv.pairs[k];
     if (pr.x != pr.y && core_s[pr.x] && core_s[pr.y]) uf_union_ord(parent, perm, pr.x, pr.y);
