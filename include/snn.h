@@ -59,12 +59,25 @@ typedef enum { SNN_F32 = 0, SNN_F64 = 1 } snn_dtype;
  *        fp32 accumulation) against a rigorous rounding bound; only pairs
  *        the screen cannot reject are re-decided by the normative rule in
  *        float64 (the "precision form").
- * FP32:  the same screen with fp32 operands on the vector ALUs (d <= 16):
+ * FP32:  the same screen with fp32 operands on the matrix cores (d <= 16):
  *        a much narrower rounding band, for low dimensions with a radius
  *        that is small against the data's extent.
  * AUTO:  the library picks from the width of each screen's rounding band
  *        relative to R^2 and from d. */
 typedef enum { SNN_PREC_FP64 = 0, SNN_PREC_MIXED = 1, SNN_PREC_AUTO = 2, SNN_PREC_FP32 = 3 } snn_precision;
+
+/* Distance of a query (Section 2).
+ * L2: the Euclidean rule above.
+ * L1: Manhattan, N(q) = { i : M(p_i, q) <= R } with M the float64 sum, left
+ *     to right, of |fl(p_k - q_k)|; dist = fl32(M).  Every such point lies in
+ *     the Euclidean ball of radius R (the 2-norm never exceeds the 1-norm),
+ *     so the Euclidean window and screen, run with R widened by the rounding
+ *     of M, find a superset that the float64 recheck decides by M.
+ * Angular and cosine neighbours are Euclidean neighbours of normalised rows
+ * (snn_normalize_rows): angle <= a iff ||u - v||^2 <= 2 - 2 cos(a), cosine
+ * distance <= c iff ||u - v||^2 <= 2c, so they are L2 queries with
+ * R = sqrt(2 - 2 cos a) or sqrt(2c). */
+typedef enum { SNN_METRIC_L2 = 0, SNN_METRIC_L1 = 1 } snn_metric;
 
 typedef struct {
   /* Device allocator; both NULL selects hipMalloc/hipFree.  alloc returns
@@ -89,6 +102,8 @@ typedef struct {
    * (the squared distance is exactly symmetric); 1 scans every (query,
    * candidate) pair.  Both give the same result. */
   int full_self_scan;
+  /* snn_metric; 0 = L2 */
+  int metric;
 } snn_options;
 
 typedef struct {
@@ -223,6 +238,15 @@ void snn_batch_free(snn_batch_t batch);
 /* One-shot form: create, run both passes once, free. */
 snn_status snn_query_batch(const snn_device* dev, snn_dtype dtype, const snn_instance* instances,
                            int32_t count, const snn_batch_options* opts, snn_stats* st);
+
+/* Rows scaled to unit Euclidean norm, for angular and cosine neighbours
+ * (Section 2): y_i = x_i / ||x_i|| with ||x_i|| = sqrt of the float64 sum,
+ * left to right, of the squared coordinates, the quotient rounded once to
+ * the dtype (inputs promoted to float64 exactly).
+ *   X, Y: device, n x d row-major, same dtype; Y may equal X.
+ * Errors: SNN_EINVAL (NULL pointers, n < 0, d < 1, a row that is zero or
+ * holds NaN/Inf -- Y is then unspecified), SNN_EDEVICE. */
+snn_status snn_normalize_rows(const snn_device* dev, const void* X, int64_t n, int32_t d, snn_dtype dtype, void* Y);
 
 /* ---- DBSCAN on self-query neighbour lists (Section 6.4) --------------------
  * Section 6.4 runs DBSCAN with SNN as its radius search (eps = R; its

@@ -10,6 +10,7 @@ no fallback path.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from typing import Optional, Tuple
 
@@ -22,6 +23,7 @@ SNN_OK, SNN_EINVAL, SNN_ENOMEM, SNN_EDEVICE, SNN_EOVERFLOW, SNN_ENOTSUP = 0, -1,
 SNN_F32, SNN_F64 = 0, 1
 PRECISION = {"fp64": 0, "mixed": 1, "auto": 2, "fp32": 3}
 PRECISION_NAMES = {v: k for k, v in PRECISION.items()}
+METRIC = {"l2": 0, "l1": 1}
 
 STATUS_NAMES = {
     SNN_OK: "SNN_OK",
@@ -60,6 +62,7 @@ class snn_options(ctypes.Structure):
         ("tile_q", ctypes.c_int),
         ("tile_c", ctypes.c_int),
         ("full_self_scan", ctypes.c_int),
+        ("metric", ctypes.c_int),
     ]
 
 
@@ -170,6 +173,8 @@ SIGNATURES = {
     "snn_dbscan_index": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(snn_options),
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(snn_stats)]),
+    "snn_normalize_rows": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_int, ctypes.c_void_p]),
     "snn_last_error": (ctypes.c_char_p, []),
     "snn_version": (ctypes.c_char_p, []),
 }
@@ -284,10 +289,14 @@ class Index:
         except Exception:
             pass
 
-    def _opts(self, precision: str, terms: int, tile_q: int, tile_c: int, full_self_scan: bool = False) -> snn_options:
+    def _opts(self, precision: str, terms: int, tile_q: int, tile_c: int, full_self_scan: bool = False,
+              metric: str = "l2") -> snn_options:
         if precision not in PRECISION:
             raise SnnError(SNN_EINVAL, f"precision must be one of {sorted(PRECISION)}")
-        return snn_options(PRECISION[precision], int(terms), int(tile_q), int(tile_c), 1 if full_self_scan else 0)
+        if metric not in METRIC:
+            raise SnnError(SNN_EINVAL, f"metric must be one of {sorted(METRIC)}")
+        return snn_options(PRECISION[precision], int(terms), int(tile_q), int(tile_c), 1 if full_self_scan else 0,
+                           METRIC[metric])
 
     def _run(self, Q: Optional[torch.Tensor], m: int, R: float, opts: snn_options, nnz_cap: Optional[int],
              want_stats: bool):
@@ -317,30 +326,32 @@ class Index:
             return (res + (st.as_dict(),)) if want_stats else res
 
     def query(self, Q: torch.Tensor, R: float, precision: str = "auto", terms: int = 0, tile_q: int = 0,
-              tile_c: int = 0, nnz_cap: Optional[int] = None, stats: bool = False):
-        """Algorithm 2 for the rows of Q (m x d, same dtype and device)."""
+              tile_c: int = 0, nnz_cap: Optional[int] = None, stats: bool = False, metric: str = "l2"):
+        """Algorithm 2 for the rows of Q (m x d, same dtype and device);
+        ``metric="l1"`` for Manhattan neighbours."""
         if not isinstance(Q, torch.Tensor) or not Q.is_cuda or Q.dim() != 2 or Q.shape[1] != self.d:
             raise SnnError(SNN_EINVAL, "Q must be a CUDA tensor of shape (m, d)")
         if Q.dtype != self.dtype:
             raise SnnError(SNN_EINVAL, "Q must have the index dtype")
         Q = Q.contiguous()
-        return self._run(Q, Q.shape[0], R, self._opts(precision, terms, tile_q, tile_c), nnz_cap, stats)
+        return self._run(Q, Q.shape[0], R, self._opts(precision, terms, tile_q, tile_c, metric=metric), nnz_cap, stats)
 
     def query_self(self, R: float, precision: str = "auto", terms: int = 0, tile_q: int = 0, tile_c: int = 0,
-                   nnz_cap: Optional[int] = None, stats: bool = False, full_self_scan: bool = False):
+                   nnz_cap: Optional[int] = None, stats: bool = False, full_self_scan: bool = False,
+                   metric: str = "l2"):
         """Every data row as a query (rows in original data order).  Each
         unordered pair is scanned once unless ``full_self_scan``."""
-        return self._run(None, self.n, R, self._opts(precision, terms, tile_q, tile_c, full_self_scan), nnz_cap,
-                         stats)
+        return self._run(None, self.n, R, self._opts(precision, terms, tile_q, tile_c, full_self_scan, metric),
+                         nnz_cap, stats)
 
     def dbscan(self, eps: float, min_samples: int = 5, precision: str = "auto", stats: bool = False,
-               full_self_scan: bool = False):
+               full_self_scan: bool = False, metric: str = "l2"):
         """DBSCAN (Section 6.4) of the indexed points with eps-neighbourhoods
         of this index's self-query, clustered on the device without
         assembling the neighbour lists.  Returns ``(labels, core, nclusters)``
         (plus the stats dict): int32 labels in the original point order (-1
         noise, clusters numbered by smallest core id), a bool core mask."""
-        opts = self._opts(precision, 0, 0, 0, full_self_scan)
+        opts = self._opts(precision, 0, 0, 0, full_self_scan, metric)
         dev = f"cuda:{self.device}"
         with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
             labels = torch.empty(max(self.n, 1), dtype=torch.int32, device=dev)
@@ -384,6 +395,34 @@ def sort_pairs_u32(keys: torch.Tensor, vals: torch.Tensor, begin_bit: int = 0, e
     alloc = _TorchAllocator(device)
     _check(lib().snn_sort_pairs_u32(ctypes.byref(alloc.dev), ctypes.c_void_p(keys.data_ptr()),
                                     ctypes.c_void_p(vals.data_ptr()), keys.numel(), begin_bit, end_bit))
+
+
+def normalize_rows(X: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Rows scaled to unit Euclidean norm (float64 rule, one rounding to the
+    dtype), for angular and cosine neighbours; ``out`` may be ``X``."""
+    if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dim() != 2:
+        raise SnnError(SNN_EINVAL, "X must be a 2-D CUDA tensor")
+    X = X.contiguous()
+    if out is None:
+        out = torch.empty_like(X)
+    if out.shape != X.shape or out.dtype != X.dtype or not out.is_contiguous() or out.device != X.device:
+        raise SnnError(SNN_EINVAL, "out must be a contiguous tensor like X")
+    device = X.device.index if X.device.index is not None else torch.cuda.current_device()
+    alloc = _TorchAllocator(device)
+    _check(lib().snn_normalize_rows(ctypes.byref(alloc.dev), ctypes.c_void_p(X.data_ptr()), X.shape[0], X.shape[1],
+                                    _dtype_code(X), ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def angular_radius(alpha: float) -> float:
+    """Euclidean radius on unit vectors for angles at most ``alpha`` (radians):
+    sqrt(2 - 2 cos(alpha))."""
+    return math.sqrt(max(0.0, 2.0 - 2.0 * math.cos(alpha)))
+
+
+def cosine_radius(c: float) -> float:
+    """Euclidean radius on unit vectors for cosine distance at most ``c``: sqrt(2c)."""
+    return math.sqrt(2.0 * c)
 
 
 def dbscan_csr(row_ptr: torch.Tensor, col: torch.Tensor, min_samples: int = 5,

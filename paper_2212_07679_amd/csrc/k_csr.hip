@@ -27,6 +27,24 @@ namespace snn {
 namespace {
 constexpr int kThreads = 256;
 
+// The normative measure of a pair in float64, left to right over the
+// coordinates, no fused multiply-add: S = sum fl(t_k * t_k) (L2, compared
+// with fl(R*R)) or M = sum |t_k| (L1, compared with R), t_k = fl(p_k - q_k).
+template <typename A, typename B>
+__device__ __forceinline__ double pair_measure(int metric, const A* __restrict__ p, const B* __restrict__ qv,
+                                               int d) {
+  double s = 0.0;
+  if (metric == SNN_METRIC_L1) {
+    for (int k = 0; k < d; ++k) s = s + fabs((double)p[k] - (double)qv[k]);
+  } else {
+    for (int k = 0; k < d; ++k) {
+      const double t = (double)p[k] - (double)qv[k];
+      s = s + t * t;
+    }
+  }
+  return s;
+}
+
 // Data rows are read in the input dtype (their promotion to float64 is
 // exact), the query rows of a self-query likewise; out-of-sample query rows
 // are the float64 copies.
@@ -45,25 +63,16 @@ __global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, 
     double s = 0.0;
     if (keep) {
       const T* pp = po + (int64_t)pr.y * d;
-      if (SELF) {
-        const T* qp = po + (int64_t)pr.x * d;
-        for (int k = 0; k < d; ++k) {
-          const double t = (double)pp[k] - (double)qp[k];
-          s = s + t * t;
-        }
-      } else {
-        const double* qp = q.q64 + (int64_t)pr.x * q.dp;
-        for (int k = 0; k < d; ++k) {
-          const double t = (double)pp[k] - qp[k];
-          s = s + t * t;
-        }
-      }
-      keep = s <= q.R2;
+      if (SELF)
+        s = pair_measure(q.metric, pp, po + (int64_t)pr.x * d, d);
+      else
+        s = pair_measure(q.metric, pp, q.q64 + (int64_t)pr.x * q.dp, d);
+      keep = q.metric == SNN_METRIC_L1 ? s <= q.R1 : s <= q.R2;
     }
     if (keep) {
       // rows are query slots (score order): a tile's rows are neighbours in
       // memory, so the counters and the later writes stay cache-local
-      const float dist = (float)sqrt(s);
+      const float dist = (float)(q.metric == SNN_METRIC_L1 ? s : sqrt(s));
       sv.res_q[r0] = pr.x;
       sv.res_key[r0] = neighbour_key(q.perm[pr.y], dist);
       sv.res_slot[r0] = atomicAdd(&row_cnt[pr.x], 1);
@@ -100,14 +109,8 @@ __global__ __launch_bounds__(kThreads) void k_recheck_edges(QueryDev q, Survivor
     const int2 pr = sv.pairs[i];
     bool keep = !q.sym || pr.y >= pr.x;
     if (keep) {
-      const T* pp = po + (int64_t)pr.y * d;
-      const T* qp = po + (int64_t)pr.x * d;
-      double s = 0.0;
-      for (int k = 0; k < d; ++k) {
-        const double t = (double)pp[k] - (double)qp[k];
-        s = s + t * t;
-      }
-      keep = s <= q.R2;
+      const double s = pair_measure(q.metric, po + (int64_t)pr.y * d, po + (int64_t)pr.x * d, d);
+      keep = q.metric == SNN_METRIC_L1 ? s <= q.R1 : s <= q.R2;
     }
     if (keep) {
       atomicAdd(&row_cnt[pr.x], 1);

@@ -33,7 +33,9 @@ struct QueryDev {
   int ntiles;
   int G;        // tiles per group
   int ngroups;
-  double R2;  // fl64(R*R)
+  double R2;  // fl64(R*R) of the screen radius
+  int metric; // snn_metric of the recheck
+  double R1;  // the L1 radius (metric L1; R2 then belongs to the widened L2 radius)
   const double* q64;     // m x dp: query rows in float64, score order
   const int32_t* qorig;  // m: score-order position -> caller's query row
   const double* p64;     // n x dp: data rows in float64, score order

@@ -187,13 +187,20 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   if (o.tile_q < 0 || o.tile_c < 0) fail(SNN_EINVAL, "tile sizes must be >= 0");
   if (o.tile_q % 64 != 0) fail(SNN_EINVAL, "tile_q must be a multiple of 64");
   if (o.full_self_scan != 0 && o.full_self_scan != 1) fail(SNN_EINVAL, "full_self_scan must be 0 or 1");
+  if (o.metric != SNN_METRIC_L2 && o.metric != SNN_METRIC_L1) fail(SNN_EINVAL, "unknown metric");
 
   DeviceScope scope(ix.arena.dev().device);
   hipStream_t s = ix.arena.stream();
   const DeviceInfo& di = device_info(ix.arena.dev().device);
   const int d = ix.d;
   const int64_t n = ix.n;
-  const double R2 = R * R;
+  // L1: every point with M(p, q) <= R has S(p, q) <= fl(Rs*Rs) for the
+  // widened radius Rs = R (1 + 8 gamma_{d+2}): the exact 1-norm is at most
+  // M (1 + 2 gamma_{d+1}), the 2-norm at most the 1-norm, and S at most the
+  // exact squared 2-norm times (1 + gamma_{d+2}).  The window and the screen
+  // use Rs, the recheck decides by M <= R.
+  const double Rs = o.metric == SNN_METRIC_L1 ? R * (1.0 + 8.0 * gamma64(d + 2)) : R;
+  const double R2 = Rs * Rs;
 
   // ---- precision plan
   // A screen passes every pair whose decomposed distance is within about
@@ -345,7 +352,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
 
   // W_q = R ||v|| (1 + 4 gamma_{d+3}) + key_eps + eps_q, eps_q = c ||y_q||
   const double u32 = std::ldexp(1.0, -24);
-  const double w_base = R * ix.vnorm * (1.0 + 4.0 * gamma64(d + 3)) + ix.key_eps;
+  const double w_base = Rs * ix.vnorm * (1.0 + 4.0 * gamma64(d + 3)) + ix.key_eps;
   const double eps_scale = 1.01 * (u32 + gamma64(d + 2)) * (1.0 + u32) * ix.vnorm;
   // self-queries scan each unordered pair once (S is exactly symmetric)
   const int sym = (self && !o.full_self_scan) ? 1 : 0;
@@ -376,6 +383,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   qd.CH = CH;
   qd.ntiles = ntiles;
   qd.R2 = R2;
+  qd.metric = o.metric;
+  qd.R1 = R;
   qd.q64 = q64;
   qd.qorig = qorig;
   qd.p64 = ix.p64.as<double>();

@@ -25,6 +25,13 @@ batch256   256 independent instances, n log-uniform in [1e3, 1e5],
 blobs3d    5e6 points, d = 3, float32: 80% from 1,000 Gaussian blobs
            (std 0.01) with centres uniform in [0,1]^3, 20% uniform
            background; self-query with R = 0.005.
+angular100 1,183,514 points, d = 100, float32 (the shape of the GloVe-100
+           angular set of Section 6): directions clustered around 100 random
+           unit centres (offset N(0, 0.7^2 I / d)), each row scaled by a
+           log-normal length (raw embeddings are not unit vectors); 1e4
+           out-of-sample queries from the same mixture; neighbours within an
+           angle of 39 degrees (alpha; R is unset: the Euclidean radius on
+           normalised rows follows from alpha).
 """
 
 from __future__ import annotations
@@ -48,6 +55,7 @@ class Workload:
     P: np.ndarray  # (n, d) data, C-contiguous, float32 or float64
     Q: Optional[np.ndarray]  # (m, d) queries; None = self-query (Q is P)
     R: float
+    alpha: Optional[float] = None  # angular workloads: the angle (radians)
 
     @property
     def n(self) -> int:
@@ -139,3 +147,19 @@ def lattice(lo: int, hi: int, d: int = 2) -> np.ndarray:
     axes = [np.arange(lo, hi + 1, dtype=np.float64)] * d
     grids = np.meshgrid(*axes, indexing="ij")
     return np.stack([gr.reshape(-1) for gr in grids], axis=1)
+
+
+def angular100(n: int = 1_183_514, m: int = 10_000, d: int = 100, k: int = 100, spread: float = 0.7,
+               alpha_deg: float = 39.0, seed: int = 7) -> Workload:
+    g = rng_for(7, seed)
+    C = g.standard_normal((k, d))
+    C /= np.linalg.norm(C, axis=1, keepdims=True)
+
+    def draw(count):
+        lab = g.integers(0, k, size=count)
+        X = C[lab] + spread * g.standard_normal((count, d)) / math.sqrt(d)
+        return X * np.exp(0.3 * g.standard_normal((count, 1)))
+
+    P = draw(n)
+    Q = draw(m)
+    return Workload("angular100", P.astype(np.float32), Q.astype(np.float32), float("nan"), math.radians(alpha_deg))
