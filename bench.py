@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -48,6 +49,10 @@ WORKLOADS = {
                          "self-query, R=4.0", precisions="auto", cpu_sample=200),
     "blobs3d": dict(desc="blobs3d: n=5e6 d=3 float32, 1000 Gaussian blobs (std 0.01) + 20% uniform background in "
                          "[0,1]^3, all-points self-query, R=0.005", precisions="auto", cpu_sample=500),
+    "angular100": dict(desc="angular100: n=1183514 d=100 float32 clustered directions (GloVe-100 shape), rows "
+                            "normalised on the device, 1e4 out-of-sample queries, angle <= 39 degrees "
+                            "(Euclidean R = sqrt(2 - 2 cos 39deg) on unit rows)", precisions="auto,fp64",
+                       cpu_sample=300),
     "dbscan_blobs3d": dict(desc="dbscan_blobs3d: DBSCAN (Section 6.4) of blobs3d, n=5e6 d=3 float32, eps=R=0.005, "
                                 "min_samples=5; one step = all-points self-query + clustering on a built index",
                            precisions="auto", cpu_sample=50000),
@@ -123,6 +128,8 @@ def make_workload(name, n, m):
         return W.gmm128z(**({"n": n} if n else {}))
     if name == "blobs3d":
         return W.blobs3d(**({"n": n} if n else {}))
+    if name == "angular100":
+        return W.angular100(**({"n": n} if n else {}), **({"m": m} if m else {}))
     raise ValueError(name)
 
 
@@ -461,6 +468,19 @@ def main():
     dev = torch.device("cuda:0")
     X = torch.from_numpy(w.P).to(dev)
     Qdev = torch.from_numpy(w.Q).to(dev) if w.Q is not None else None
+    normalize_ms = None
+    if w.alpha is not None:
+        # angular neighbours: a Euclidean search of the rows normalised on the
+        # device, with R = sqrt(2 - 2 cos alpha)
+        import dataclasses
+
+        w = dataclasses.replace(w, R=binding.angular_radius(w.alpha))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        binding.normalize_rows(X, out=X)
+        binding.normalize_rows(Qdev, out=Qdev)
+        torch.cuda.synchronize()
+        normalize_ms = (time.perf_counter() - t0) * 1e3
     torch.cuda.synchronize()
     idx = binding.Index(X)  # first build: allocations
     idx.close()
@@ -494,7 +514,14 @@ def main():
 
     cpu = None
     if cpu_sample > 0:
-        cpu, (sel, nb) = cpu_baseline(w, cpu_sample)
+        wc = w
+        if w.alpha is not None:
+            import dataclasses
+
+            from oracle.metrics import normalize_rows
+
+            wc = dataclasses.replace(w, P=normalize_rows(w.P), Q=normalize_rows(w.Q))
+        cpu, (sel, nb) = cpu_baseline(wc, cpu_sample)
         rp, col, dist = (t.cpu().numpy() for t in results[precisions[0]]["out"][:3])
         for k, qi in enumerate(sel[: a.check]):
             got = col[rp[qi]:rp[qi + 1]]
@@ -506,7 +533,8 @@ def main():
     used = binding.PRECISION_NAMES[st["precision_used"]]
     fp64 = results.get("fp64")
     line = {
-        "metric": HEADLINE_METRIC if a.workload == "gmm16" else "exact radius queries/s",
+        "metric": HEADLINE_METRIC if a.workload == "gmm16" else (
+            "exact angular radius queries/s" if w.alpha is not None else "exact radius queries/s"),
         "value": r["qps"],
         "unit": "queries/s",
         "n_gpus": 1,
@@ -519,7 +547,9 @@ def main():
         "dtype": {"mixed": "bf16+f64", "fp32": "f32+f64", "fp64": "f64"}[used],
         "data": "synthetic",
         "config": {"workload": spec["desc"], "n": w.n, "d": w.d, "m": w.m, "R": w.R, "self_query": w.Q is None,
-                   "precision": used, "terms": st["terms_used"]},
+                   "precision": used, "terms": st["terms_used"],
+                   **({"alpha_deg": math.degrees(w.alpha), "normalize_ms": normalize_ms} if w.alpha is not None
+                      else {})},
         "fp64_gpu_qps": fp64["qps"] if fp64 else None,
         "speedup_vs_fp64_gpu": (r["qps"] / fp64["qps"]) if (fp64 and head != "fp64") else None,
         "pairs_window": st["pairs_window"],
