@@ -169,6 +169,20 @@ typedef struct {
   int32_t power_iters;    /* host: power iterations run */
 } snn_index_view;
 
+/* Streaming inserts (the online setting of Section 1): appends k rows of the
+ * index's dtype and dimension, which get ids n .. n+k-1.  The centre mu and
+ * the direction v stay those of the original build (eq. (lower) holds for
+ * any fixed unit v and any common centre, so every later query stays exact;
+ * only the window sizes depend on how well v fits the grown set).  The new
+ * rows are centred, projected and sorted, then merged into the key order
+ * (existing rows first among equal keys); the bounds over all rows are
+ * updated and the screen operands rebuilt on the next query.
+ *   X: device, k x d row-major.  Runs on the index's stream and returns when
+ *   the index is updated.
+ * Errors: SNN_EINVAL (NULL index or X, k < 0, n + k >= 2^31 - 1, NaN/Inf in
+ * X -- the index is then unchanged), SNN_ENOMEM, SNN_EDEVICE. */
+snn_status snn_index_insert(snn_index_t idx, const void* X, int64_t k);
+
 snn_status snn_index_get_view(snn_index_t idx, snn_index_view* view);
 
 void snn_index_free(snn_index_t idx);

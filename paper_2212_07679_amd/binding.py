@@ -165,6 +165,7 @@ SIGNATURES = {
                                       ctypes.POINTER(snn_csr), ctypes.POINTER(snn_stats)]),
     "snn_index_get_view": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(snn_index_view)]),
     "snn_index_free": (None, [ctypes.c_void_p]),
+    "snn_index_insert": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "snn_sort_pairs_u32": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
     "snn_dbscan": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
@@ -343,6 +344,19 @@ class Index:
         unordered pair is scanned once unless ``full_self_scan``."""
         return self._run(None, self.n, R, self._opts(precision, terms, tile_q, tile_c, full_self_scan, metric),
                          nnz_cap, stats)
+
+    def insert(self, X: torch.Tensor) -> None:
+        """Append the rows of X (k x d, the index dtype) as points n .. n+k-1
+        (streaming inserts: the index's centre and direction are kept)."""
+        if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dim() != 2 or X.shape[1] != self.d:
+            raise SnnError(SNN_EINVAL, "X must be a CUDA tensor of shape (k, d)")
+        if X.dtype != self.dtype:
+            raise SnnError(SNN_EINVAL, "X must have the index dtype")
+        X = X.contiguous()
+        with torch.cuda.device(self.device):
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            _check(lib().snn_index_insert(self._h, ctypes.c_void_p(X.data_ptr()), X.shape[0]))
+        self.n += X.shape[0]
 
     def dbscan(self, eps: float, min_samples: int = 5, precision: str = "auto", stats: bool = False,
                full_self_scan: bool = False, metric: str = "l2"):

@@ -250,11 +250,12 @@ __global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, in
                                                     const uint32_t* __restrict__ val, double* __restrict__ key,
                                                     int32_t* __restrict__ perm, T* __restrict__ po,
                                                     double* __restrict__ p64, float* __restrict__ ys,
-                                                    float* __restrict__ h, float* __restrict__ ynorm) {
+                                                    float* __restrict__ h, float* __restrict__ ynorm,
+                                                    int64_t id_base) {
   if (blockIdx.x == 0 && threadIdx.x < 64) h[n + threadIdx.x] = INFINITY;  // padding rows
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t i = val[s];
-    perm[s] = (int32_t)i;
+    perm[s] = (int32_t)(id_base + i);
     key[s] = (double)ordered_to_float(ukey[s]);
     const T* p = X + (int64_t)i * d;
     double nn = 0.0;
@@ -399,7 +400,7 @@ void build_index_t(Index& ix, const T* X) {
   double* p64 = ix.p64.as<double>();
   k_gather<T><<<grid_for(n, kThreads, 4 * di.cus * 8), kThreads, 0, s>>>(
       X, n, d, ix.dp, ix.mu.as<double>(), ukey, val, ix.key.as<double>(), ix.perm.as<int32_t>(), po, p64,
-      ix.ys.as<float>(), ix.h.as<float>(), ix.ynorm.as<float>());
+      ix.ys.as<float>(), ix.h.as<float>(), ix.ynorm.as<float>(), 0);
   SNN_LAUNCH_CHECK();
 
   Scratch hs;
@@ -428,6 +429,175 @@ void build_index(Index& ix, const void* X) {
     build_index_t<float>(ix, static_cast<const float*>(X));
   else
     build_index_t<double>(ix, static_cast<const double*>(X));
+}
+
+// ---- streaming inserts ---------------------------------------------------------
+// Merge path: output row t of the merge of A (old rows, na) and B (new
+// rows, nb), both sorted by key, comes from A[i] or B[t - i] where i is the
+// number of A rows among the first t outputs; equal keys keep A first.
+// src[t] = i (from A) or -(t - i) - 1 (from B).
+__global__ __launch_bounds__(kThreads) void k_merge_path(const double* __restrict__ ka, int64_t na,
+                                                         const double* __restrict__ kb, int64_t nb,
+                                                         int64_t* __restrict__ src) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < na + nb;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    // smallest i in [max(0, t - nb), min(t, na)] with "A[i] comes after B[t - i - 1]"
+    int64_t lo = t - nb > 0 ? t - nb : 0, hi = t < na ? t : na;
+    while (lo < hi) {
+      const int64_t i = (lo + hi) / 2;  // A[i] vs B[t - i - 1]: if A[i] <= B[t-i-1], A[i] is among the first t
+      if (ka[i] <= kb[t - i - 1])
+        lo = i + 1;
+      else
+        hi = i;
+    }
+    // output t is the smaller of A[lo] and B[t - lo] (A first on ties)
+    const bool fromA = lo < na && (t - lo >= nb || ka[lo] <= kb[t - lo]);
+    src[t] = fromA ? lo : -(t - lo) - 1;
+  }
+}
+
+// Copies w values per row from A or B into the merged array.
+template <typename V>
+__global__ __launch_bounds__(kThreads) void k_merge_rows(const V* __restrict__ a, const V* __restrict__ b,
+                                                         const int64_t* __restrict__ src, int64_t rows, int w,
+                                                         V* __restrict__ out) {
+  const int64_t total = rows * w;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = e / w;
+    const int c = (int)(e % w);
+    const int64_t sidx = src[t];
+    out[e] = sidx >= 0 ? a[sidx * w + c] : b[(-sidx - 1) * w + c];
+  }
+}
+
+template <typename V>
+static void merge_rows(const V* a, const V* b, const int64_t* src, int64_t rows, int w, V* out, int cap,
+                       hipStream_t s) {
+  k_merge_rows<V><<<grid_for(rows * w, kThreads, cap), kThreads, 0, s>>>(a, b, src, rows, w, out);
+  SNN_LAUNCH_CHECK();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_check_finite(const T* __restrict__ X, int64_t total,
+                                                           int* __restrict__ bad) {
+  int b = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite((double)X[e])) b = 1;
+  if (b) atomicOr(bad, 1);
+}
+
+__global__ void k_fill_inf(float* __restrict__ p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = INFINITY;
+}
+
+template <typename T>
+static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
+  hipStream_t s = ix.arena.stream();
+  const DeviceInfo& di = device_info(ix.arena.dev().device);
+  const int d = ix.d, dp = ix.dp;
+  const int64_t na = ix.n, nt = na + k;
+
+  // the new rows in key order, with the index's mu and v (scratch)
+  struct Scratch {
+    int bad;
+    int pad;
+    double max_norm;
+  };
+  Carver sz(nullptr);
+  sz.take<Scratch>(1);
+  sz.take<uint32_t>(k);
+  sz.take<uint32_t>(k);
+  sz.take<double>(k);                 // key
+  sz.take<int32_t>(k);                // perm
+  sz.take<T>((size_t)k * d);          // po
+  sz.take<double>((size_t)k * dp);    // p64
+  sz.take<float>((size_t)k * d);      // ys
+  sz.take<float>(k + 64);             // h
+  sz.take<float>(k);                  // ynorm
+  sz.take<int64_t>(nt);               // merge sources
+  void* mem = ix.arena.alloc(sz.off);
+  struct Release {
+    DeviceArena& a;
+    void* p;
+    ~Release() { a.release(p); }
+  } rel{ix.arena, mem};
+  Carver c(mem);
+  Scratch* sc = c.take<Scratch>(1);
+  uint32_t* ukey = c.take<uint32_t>(k);
+  uint32_t* val = c.take<uint32_t>(k);
+  double* keyb = c.take<double>(k);
+  int32_t* permb = c.take<int32_t>(k);
+  T* pob = c.take<T>((size_t)k * d);
+  double* p64b = c.take<double>((size_t)k * dp);
+  float* ysb = c.take<float>((size_t)k * d);
+  float* hb = c.take<float>(k + 64);
+  float* ynb = c.take<float>(k);
+  int64_t* src = c.take<int64_t>(nt);
+
+  SNN_HIP(hipMemsetAsync(sc, 0, sizeof(Scratch), s));
+  const int cap = 4 * di.cus * 8;
+  k_check_finite<T><<<grid_for(k * d, kThreads, cap), kThreads, 0, s>>>(Xn, k * d, &sc->bad);
+  SNN_LAUNCH_CHECK();
+  k_project<T><<<grid_for(k, kThreads, 4 * di.cus * 8), kThreads, 0, s>>>(Xn, k, d, ix.mu.as<double>(),
+                                                                          ix.v.as<double>(), ukey, val,
+                                                                          &sc->max_norm);
+  SNN_LAUNCH_CHECK();
+  radix_sort_pairs(ix.arena, ukey, val, k, 0, 32, s);
+  k_gather<T><<<grid_for(k, kThreads, 4 * di.cus * 8), kThreads, 0, s>>>(
+      Xn, k, d, dp, ix.mu.as<double>(), ukey, val, keyb, permb, pob, p64b, ysb, hb, ynb, na);
+  SNN_LAUNCH_CHECK();
+  Scratch hs;
+  SNN_HIP(hipMemcpyAsync(&hs, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+  SNN_HIP(hipStreamSynchronize(s));
+  if (hs.bad) fail(SNN_EINVAL, "snn_index_insert: X contains NaN or Inf");
+
+  // merged arrays
+  k_merge_path<<<grid_for(nt, kThreads, 4 * di.cus * 8), kThreads, 0, s>>>(ix.key.as<double>(), na, keyb, k, src);
+  SNN_LAUNCH_CHECK();
+  Buffer key, perm, po, p64, ys, h, ynorm;
+  key.ensure(ix.arena, sizeof(double) * nt);
+  perm.ensure(ix.arena, sizeof(int32_t) * nt);
+  po.ensure(ix.arena, sizeof(T) * nt * d);
+  p64.ensure(ix.arena, sizeof(double) * nt * dp);
+  ys.ensure(ix.arena, sizeof(float) * nt * d);
+  h.ensure(ix.arena, sizeof(float) * (nt + 64));
+  ynorm.ensure(ix.arena, sizeof(float) * nt);
+  merge_rows<double>(ix.key.as<double>(), keyb, src, nt, 1, key.as<double>(), cap, s);
+  merge_rows<int32_t>(ix.perm.as<int32_t>(), permb, src, nt, 1, perm.as<int32_t>(), cap, s);
+  merge_rows<T>(ix.po.as<T>(), pob, src, nt, d, po.as<T>(), cap, s);
+  merge_rows<double>(ix.p64.as<double>(), p64b, src, nt, dp, p64.as<double>(), cap, s);
+  merge_rows<float>(ix.ys.as<float>(), ysb, src, nt, d, ys.as<float>(), cap, s);
+  merge_rows<float>(ix.h.as<float>(), hb, src, nt, 1, h.as<float>(), cap, s);
+  merge_rows<float>(ix.ynorm.as<float>(), ynb, src, nt, 1, ynorm.as<float>(), cap, s);
+  k_fill_inf<<<1, 64, 0, s>>>(h.as<float>() + nt, 64);  // padding rows
+  SNN_LAUNCH_CHECK();
+  SNN_HIP(hipStreamSynchronize(s));
+  std::swap(ix.key, key);
+  std::swap(ix.perm, perm);
+  std::swap(ix.po, po);
+  std::swap(ix.p64, p64);
+  std::swap(ix.ys, ys);
+  std::swap(ix.h, h);
+  std::swap(ix.ynorm, ynorm);
+  for (Buffer* b : {&key, &perm, &po, &p64, &ys, &h, &ynorm}) b->reset(ix.arena);
+
+  // bounds over all points; screen operands are rebuilt on the next query
+  const double u64 = std::ldexp(1.0, -53), u32 = std::ldexp(1.0, -24);
+  ix.n = nt;
+  ix.max_norm = std::max(ix.max_norm, std::sqrt(hs.max_norm) * (1.0 + 4.0 * (d + 2) * u64));
+  const double g64 = (d + 2) * u64 / (1.0 - (d + 2) * u64);
+  ix.key_eps = 1.01 * (u32 + g64) * (1.0 + u32) * ix.max_norm * ix.vnorm;
+  ix.mixed[0].terms = 0;
+  ix.mixed[1].terms = 0;
+  ix.vcand_built = false;
+}
+
+void insert_points(Index& ix, const void* X, int64_t k) {
+  if (k == 0) return;
+  if (ix.dtype == SNN_F32)
+    insert_points_t<float>(ix, static_cast<const float*>(X), k);
+  else
+    insert_points_t<double>(ix, static_cast<const double*>(X), k);
 }
 
 void build_mixed_operands(Index& ix, int terms) {

@@ -653,6 +653,17 @@ snn_status snn_dbscan_index(snn_index_t idx, double eps, int32_t min_samples, co
   });
 }
 
+snn_status snn_index_insert(snn_index_t idx, const void* X, int64_t k) {
+  return guard([&] {
+    if (!idx) fail(SNN_EINVAL, "index is NULL");
+    if (k < 0) fail(SNN_EINVAL, "k must be >= 0");
+    if (k > 0 && !X) fail(SNN_EINVAL, "X is NULL");
+    if (idx->n + k >= (int64_t)INT32_MAX) fail(SNN_EINVAL, "n + k must be < 2^31 - 1");
+    DeviceScope scope(idx->arena.dev().device);
+    insert_points(*idx, X, k);
+  });
+}
+
 snn_status snn_index_get_view(snn_index_t idx, snn_index_view* view) {
   return guard([&] {
     if (!idx || !view) fail(SNN_EINVAL, "NULL argument");

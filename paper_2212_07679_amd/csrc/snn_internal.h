@@ -168,6 +168,9 @@ void exclusive_scan_u32(uint32_t* data, int64_t n, void* scratch, hipStream_t s)
 // k_index.hip
 void build_index(Index& ix, const void* X);
 void build_mixed_operands(Index& ix, int terms);
+// appends k rows (ids n .. n+k-1) with the index's mu and v: merged into the
+// key order, bounds updated, screen operands marked for rebuilding
+void insert_points(Index& ix, const void* X, int64_t k);
 
 // k_query.hip / k_cand_*.hip / k_csr.hip are driven from runtime.hip through
 // the declarations in query_plan.h.

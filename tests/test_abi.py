@@ -123,6 +123,14 @@ def test_dbscan_argument_errors():
     assert L.snn_dbscan(ctypes.byref(dev), 2**31, fake, fake, 5, fake, None, ctypes.byref(k)) == B.SNN_EINVAL
 
 
+def test_index_insert_argument_errors():
+    L = B.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.snn_index_insert(None, fake, 4) == B.SNN_EINVAL
+    assert L.snn_index_insert(fake, fake, -1) == B.SNN_EINVAL
+    assert L.snn_index_insert(fake, None, 4) == B.SNN_EINVAL
+
+
 def test_dbscan_index_argument_errors():
     L = B.lib()
     fake = ctypes.c_void_p(0x1000)
