@@ -53,6 +53,9 @@ WORKLOADS = {
                             "normalised on the device, 1e4 out-of-sample queries, angle <= 39 degrees "
                             "(Euclidean R = sqrt(2 - 2 cos 39deg) on unit rows)", precisions="auto,fp64",
                        cpu_sample=300),
+    "stream_gmm16": dict(desc="stream_gmm16: gmm16 mixture, index built on 1e6 points, then --steps inserts of 1e5 "
+                              "points each (streaming); queries of the grown index against a rebuilt one",
+                         precisions="auto", cpu_sample=200000),
     "dbscan_blobs3d": dict(desc="dbscan_blobs3d: DBSCAN (Section 6.4) of blobs3d, n=5e6 d=3 float32, eps=R=0.005, "
                                 "min_samples=5; one step = all-points self-query + clustering on a built index",
                            precisions="auto", cpu_sample=50000),
@@ -438,6 +441,93 @@ def main_dbscan(a):
     print(json.dumps(line))
 
 
+def main_stream(a):
+    """Streaming inserts: one step is one insert of 1e5 points into a grown
+    index (centre and direction kept from the first build).  Reported beside
+    it: the build of the first 1e6 points, a rebuild of the grown set, and
+    queries of the grown index against the rebuilt one (same results)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2212_07679_amd import binding
+    from paper_2212_07679_amd import workloads as W
+
+    spec = WORKLOADS["stream_gmm16"]
+    n0, batch = 1_000_000, 100_000
+    total = n0 + batch * (a.steps + 1)
+    w = W.gmm16(n=total, m=100_000)
+    X = torch.from_numpy(w.P).to("cuda:0")
+    Q = torch.from_numpy(w.Q).to("cuda:0")
+    torch.cuda.synchronize()
+
+    def wall(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, out
+
+    binding.Index(X[:n0]).close()  # allocations
+    build_ms, idx = wall(lambda: binding.Index(X[:n0]))
+    idx.insert(X[n0:n0 + batch])  # warm-up insert
+    times = []
+    for k in range(a.steps):
+        lo = n0 + batch * (k + 1)
+        ms, _ = wall(lambda: idx.insert(X[lo:lo + batch]))
+        times.append(ms)
+    ins_ms = float(np.mean(times))
+    rebuild_ms, full = wall(lambda: binding.Index(X))
+    for i in (idx, full):
+        i.query(Q, w.R)
+    q_grown, r1 = wall(lambda: idx.query(Q, w.R, stats=True))
+    q_full, r2 = wall(lambda: full.query(Q, w.R, stats=True))
+    for x, y in zip(r1[:3], r2[:3]):
+        assert torch.equal(x, y), "grown and rebuilt indexes differ"
+    # bytes the merge moves per insert: every row of the grown arrays read
+    # once (old or new part) and written once
+    d, dp = w.d, ((w.d + 3) // 4) * 4
+    row_bytes = 8 + 4 + 4 * d + 8 * dp + 4 * d + 4 + 4
+    n_mid = n0 + batch * (a.steps / 2 + 1)
+    achieved = 2.0 * row_bytes * n_mid / (ins_ms / 1e3)
+    print(f"[bench] stream: build {build_ms:.1f} ms, insert {ins_ms:.2f} ms per 1e5, rebuild of {total} "
+          f"{rebuild_ms:.1f} ms, query grown {q_grown:.2f} ms vs rebuilt {q_full:.2f} ms", file=sys.stderr, flush=True)
+
+    cpu = None
+    if a.cpu_sample != 0:
+        ns = spec["cpu_sample"] if a.cpu_sample < 0 else a.cpu_sample
+        t0 = time.perf_counter()
+        oracle.build_index(w.P[:ns])
+        tc = time.perf_counter() - t0
+        cpu = {"value": ns / tc, "unit": "points/s", "cores": oracle_cores(), "kind": "oracle",
+               "sample": f"the oracle's index build (Algorithm 1) of {ns} rows of the same mixture, {tc:.2f} s"}
+    line = {
+        "metric": "streaming insert points/s into an exact SNN index",
+        "value": batch / (ins_ms / 1e3),
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": 1,
+        "ms_per_step": ins_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": spec["desc"], "n0": n0, "batch": batch, "n_final": total, "d": d},
+        "build_ms": build_ms,
+        "rebuild_ms": rebuild_ms,
+        "query_ms_grown": q_grown,
+        "query_ms_rebuilt": q_full,
+        "pairs_window_grown": r1[3]["pairs_window"],
+        "pairs_window_rebuilt": r2[3]["pairs_window"],
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -452,6 +542,9 @@ def main():
         return
     if a.workload == "dbscan_blobs3d":
         main_dbscan(a)
+        return
+    if a.workload == "stream_gmm16":
+        main_stream(a)
         return
     import numpy as np
     import torch
