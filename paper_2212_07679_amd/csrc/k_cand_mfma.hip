@@ -185,15 +185,12 @@ __device__ __forceinline__ void screen_epilogue(const f32x16 (&acc)[QB], float h
   }
 }
 
-// One 32-candidate step of the bf16 screen for QB blocks of 32 queries.
+// The products of one 32-candidate step for QB blocks of 32 queries.
 // Operand slice s of the candidate is B[s] for s < NL and B[s - NL] beyond
 // (the split layout repeats hi as the third segment).
 template <int NS, int QB, int NL>
-__device__ __forceinline__ void screen_step(const bf16x8 (&A)[QB][NS], const f32x16 (&Cin)[QB],
-                                            const bf16x8 (&B)[NL], float hv, int jr, int span, int j0,
-                                            int64_t q0, int half, int2* wbuf, int& wcnt, const PairSink& sink) {
-  const float hj = jr < span ? hv : INFINITY;
-  f32x16 acc[QB];
+__device__ __forceinline__ void step_products(const bf16x8 (&A)[QB][NS], const f32x16 (&Cin)[QB],
+                                              const bf16x8 (&B)[NL], f32x16 (&acc)[QB]) {
 #pragma unroll
   for (int b = 0; b < QB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][0], B[0], Cin[b], 0, 0, 0);
 #pragma unroll
@@ -201,6 +198,16 @@ __device__ __forceinline__ void screen_step(const bf16x8 (&A)[QB][NS], const f32
 #pragma unroll
     for (int b = 0; b < QB; ++b)
       acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][s], B[s < NL ? s : s - NL], acc[b], 0, 0, 0);
+}
+
+// One 32-candidate step of the bf16 screen: products, then compares.
+template <int NS, int QB, int NL>
+__device__ __forceinline__ void screen_step(const bf16x8 (&A)[QB][NS], const f32x16 (&Cin)[QB],
+                                            const bf16x8 (&B)[NL], float hv, int jr, int span, int j0,
+                                            int64_t q0, int half, int2* wbuf, int& wcnt, const PairSink& sink) {
+  const float hj = jr < span ? hv : INFINITY;
+  f32x16 acc[QB];
+  step_products<NS, QB, NL>(A, Cin, B, acc);
   screen_epilogue<QB, false>(acc, hj, j0 + jr, q0, half, wbuf, wcnt, sink);
 }
 
@@ -437,11 +444,15 @@ Mfma32Kernel pick_kernel32(int d) {
 
 typedef void (*MixedKernel)(QueryDev, MixedDev);
 
-// Query blocks of 32 per wavefront: every candidate load feeds QB product
-// chains, so more blocks mean fewer candidate bytes through the vector
-// memory return path per matrix product.  Short chains (NS <= 3) afford four
-// blocks within a register budget of two waves per SIMD, longer ones two.
-constexpr int qb_for(int ns) { return ns <= 3 ? 4 : 2; }
+// Query blocks of 32 per wavefront.  More blocks share each candidate load
+// among more product chains, but also make the tiles (4 wavefronts x QB x
+// 32 queries) longer, and with them the union windows of small instances.
+// Measured on one box: two blocks against four, 1.03-1.05 vs 1.25-1.31 ms
+// for the 256-instance batch screen and equal within noise for the n = 1e6,
+// d = 16 set; issuing the next step's products before the previous step's
+// compare epilogue (two accumulator sets) gained nothing at two blocks and
+// lost a wave per SIMD at four.
+constexpr int qb_for(int) { return 2; }
 
 // (slices per product chain, slices loaded per candidate row)
 MixedKernel pick_kernel(int KA, int KB) {
