@@ -426,18 +426,24 @@ __global__ __launch_bounds__(kThreads) void k_mfma32_qprep_self(const float* __r
   }
 }
 
+// Query blocks of 32 per wavefront in the fp32 screen: with two product
+// slices per chain (d <= 4) four blocks keep the matrix pipe busiest
+// (measured on the 5e6-point d = 3 self-query: 30.5 ms per query pass with
+// four blocks, 30.6-31.1 with three, 32.3 with two).
+constexpr int kQB32 = 4;
+
 typedef void (*Mfma32Kernel)(QueryDev, Mfma32Dev);
 
 Mfma32Kernel pick_kernel32(int d) {
   switch ((d + 1) / 2) {
-    case 1: return k_cand_mfma32<1, 4>;
-    case 2: return k_cand_mfma32<2, 4>;
-    case 3: return k_cand_mfma32<3, 4>;
-    case 4: return k_cand_mfma32<4, 4>;
-    case 5: return k_cand_mfma32<5, 4>;
-    case 6: return k_cand_mfma32<6, 4>;
-    case 7: return k_cand_mfma32<7, 4>;
-    case 8: return k_cand_mfma32<8, 4>;
+    case 1: return k_cand_mfma32<1, kQB32>;
+    case 2: return k_cand_mfma32<2, kQB32>;
+    case 3: return k_cand_mfma32<3, kQB32>;
+    case 4: return k_cand_mfma32<4, kQB32>;
+    case 5: return k_cand_mfma32<5, kQB32>;
+    case 6: return k_cand_mfma32<6, kQB32>;
+    case 7: return k_cand_mfma32<7, kQB32>;
+    case 8: return k_cand_mfma32<8, kQB32>;
     default: return nullptr;
   }
 }
@@ -499,7 +505,7 @@ void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound
 
 int mfma32_max_d() { return 16; }
 int mfma32_query_floats(int d) { return ((d + 1 + 3) / 4) * 4; }
-int mfma32_queries_per_tile() { return 4 * 32 * 4; }
+int mfma32_queries_per_tile() { return 4 * 32 * kQB32; }
 int64_t mfma32_operand_floats(int64_t n, int d) { return ((n + 32 + 31) / 32) * 32 * 2 * ((d + 1) / 2); }
 
 int mfma32_blocks_per_cu(int d) {
