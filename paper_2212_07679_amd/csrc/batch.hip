@@ -103,7 +103,7 @@ struct BatchPlan {
   int32_t* qorig = nullptr;
   uint16_t* qop = nullptr;
   float* cthr = nullptr;
-  int32_t *tlo = nullptr, *thi = nullptr, *units = nullptr, *gunits = nullptr;
+  int32_t *tlo = nullptr, *thi = nullptr, *units = nullptr;
   int64_t* group_off = nullptr;
   void* scan_ws = nullptr;
   BatchCtl* ctl = nullptr;
@@ -284,7 +284,6 @@ void alloc_query(BatchPlan& p) {
     p.tlo = c.take<int32_t>(nt);
     p.thi = c.take<int32_t>(nt);
     p.units = c.take<int32_t>(nt);
-    p.gunits = c.take<int32_t>(nt);
     p.group_off = c.take<int64_t>(nt + 1);
     p.scan_ws = c.take<char>(std::max(scan_scratch_bytes(nt + 1), scan_scratch_bytes(MS + 1)));
     p.ctl = c.take<BatchCtl>(1);
@@ -361,14 +360,13 @@ void enqueue_index(BatchPlan& p, hipStream_t s, bool full) {
 void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   const BatchDev b = p.dev();
   const DeviceInfo& di = device_info(p.arena.dev().device);
-  launch_fill_u64(reinterpret_cast<unsigned long long*>(p.ctl), sizeof(BatchCtl) / 8, 0ull, s);
+  launch_query_init(reinterpret_cast<unsigned long long*>(p.ctl), (int)(sizeof(BatchCtl) / 8), p.row_cnt,
+                    p.M ? p.MS : 0, nullptr, 0, p.tlo, p.thi, p.M ? p.ntiles : 0, s);
   if (p.M == 0) {
     batch_zero_i64(p.row_ptr, 1, s);
     batch_outputs(b, p.d_outs, p.row_ptr, p.col_o, p.dist_o, p.stage_cap, p.nnz_base, p.nnz, s);
     return;
   }
-  launch_fill_i32(p.row_cnt, p.MS, 0, s);
-  launch_tile_init(p.tlo, p.thi, p.ntiles, s);
   batch_query_keys(p.dtype, b, p.mu, p.v, p.qkey, p.qval, p.qa_in, p.qn_in, p.ctl, s);
   radix_sort_pairs_ws(p.qkey, p.qval, p.M, 0, 32, p.sort_ws, s);
   batch_inst_keys(p.d_qin_off, p.count, p.qval, p.M, p.qikey, p.qidx, s);
@@ -377,11 +375,9 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   batch_query_gather(p.dtype, b, p.mu, p.qval, p.qikey, p.qidx, p.qa_in, p.qn_in, p.q64, p.qorig, p.qa, p.qn, p.qop,
                      p.cthr, s);
   batch_windows(b, p.key, p.qa, p.qn, p.qorig, p.tlo, p.thi, p.ctl, s);
-  launch_tile_units(p.tlo, p.thi, p.ntiles, p.CH, 32, p.units, s);
-  batch_executed(b, p.tlo, p.thi, p.T / 4, p.ctl, s);
   const int ngroups = (p.ntiles + p.G - 1) / p.G;
-  launch_group_units(p.units, p.ntiles, p.G, p.gunits, s);
-  exclusive_scan_i32_to_i64(p.gunits, p.group_off, ngroups, p.scan_ws, s);
+  launch_tile_plan(p.tlo, p.thi, p.ntiles, p.CH, 32, 0, p.units, p.G, p.group_off, p.T, p.MS, 1, nullptr, s);
+  batch_executed(b, p.tlo, p.thi, p.T / 4, p.ctl, s);
 
   QueryDev qd{};
   qd.m = p.MS;

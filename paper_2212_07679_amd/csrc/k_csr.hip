@@ -393,6 +393,30 @@ __global__ __launch_bounds__(kThreads) void k_perm_counts(const int64_t* __restr
   }
 }
 
+// k_perm_counts plus the longest row and (block 0, thread 0) the total.
+__global__ __launch_bounds__(kThreads) void k_perm_counts_stats(const int64_t* __restrict__ src_rp, int64_t m,
+                                                               const int32_t* __restrict__ map,
+                                                               int32_t* __restrict__ cnt_dst,
+                                                               unsigned long long* __restrict__ row_max,
+                                                               unsigned long long* __restrict__ total) {
+  __shared__ int red[kThreads / kWave];
+  int v = 0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < m; r += (int64_t)gridDim.x * blockDim.x) {
+    const int len = (int)(src_rp[r + 1] - src_rp[r]);
+    const int d = map[r];
+    if (d >= 0) cnt_dst[d] = len;
+    v = max(v, len);
+  }
+  v = wave_max(v);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / kWave; ++w) v = max(v, red[w]);
+    if (v > 0) atomicMax(row_max, (unsigned long long)v);
+    if (blockIdx.x == 0) *total = (unsigned long long)src_rp[m];
+  }
+}
+
 __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -400,21 +424,6 @@ __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = v;
-}
-
-__global__ __launch_bounds__(kThreads) void k_row_max(const int32_t* __restrict__ cnt, int64_t m,
-                                                      unsigned long long* __restrict__ out) {
-  __shared__ int red[kThreads / kWave];
-  int v = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-    v = max(v, cnt[i]);
-  v = wave_max(v);
-  if (lane_id() == 0) red[threadIdx.x / kWave] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < kThreads / kWave; ++w) v = max(v, red[w]);
-    if (v > 0) atomicMax(out, (unsigned long long)v);
-  }
 }
 
 __global__ void k_self_qnorm(const float* __restrict__ ynorm, int64_t n, double* __restrict__ out) {
@@ -428,12 +437,6 @@ int grid_for(int64_t work, int cap) {
 }
 
 }  // namespace
-
-void launch_row_max(const int32_t* row_cnt, int64_t m, unsigned long long* out, hipStream_t s) {
-  if (m <= 0) return;
-  k_row_max<<<grid_for(m, 256), kThreads, 0, s>>>(row_cnt, m, out);
-  SNN_LAUNCH_CHECK();
-}
 
 void launch_self_qnorm(const float* ynorm, int64_t n, double* out, hipStream_t s) {
   k_self_qnorm<<<grid_for(n, 4096), kThreads, 0, s>>>(ynorm, n, out);
@@ -513,6 +516,12 @@ void launch_row_sort_move(const RowMove& mv, int64_t m, int64_t max_len, int32_t
 void launch_perm_counts(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst, hipStream_t s) {
   if (m <= 0) return;
   k_perm_counts<<<grid_for(m, 4096), kThreads, 0, s>>>(src_rp, m, map, cnt_dst);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_perm_counts_stats(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst,
+                              unsigned long long* row_max, unsigned long long* total, hipStream_t s) {
+  k_perm_counts_stats<<<grid_for(m, 4096), kThreads, 0, s>>>(src_rp, m, map, cnt_dst, row_max, total);
   SNN_LAUNCH_CHECK();
 }
 

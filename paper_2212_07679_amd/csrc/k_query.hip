@@ -13,9 +13,10 @@
 //                  with the half-width widened outward by a rigorous bound on
 //                  the score rounding (eq. (lower) is exact only for exact
 //                  scores); per-tile union windows
-//  k_tile_units    work units per tile
+//  k_tile_plan     work units per tile and their offsets (one workgroup)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "device_common.h"
@@ -155,54 +156,95 @@ __global__ __launch_bounds__(kThreads) void k_window(const double* __restrict__ 
   }
 }
 
-__global__ void k_tile_init(int32_t* __restrict__ tlo, int32_t* __restrict__ thi, int ntiles) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
-    tlo[t] = INT_MAX;
-    thi[t] = INT_MIN;
-  }
-}
-
-__global__ void k_tile_units(int32_t* __restrict__ tlo, int32_t* __restrict__ thi, int ntiles, int CH, int align,
-                             int sym_T, int32_t* __restrict__ units) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
-    int a = tlo[t], b = thi[t];
-    if (sym_T > 0 && a != INT_MAX) a = max(a, t * sym_T);  // symmetric self-query: from the tile's first row
-    if (a == INT_MAX || b <= a) {
-      tlo[t] = 0;
-      thi[t] = 0;
-      units[t] = 0;
-    } else {
-      a -= a % align;
-      b = (int)((((int64_t)b + align - 1) / align) * align);
-      tlo[t] = a;
-      thi[t] = b;
-      units[t] = (int32_t)(((int64_t)b - a + CH - 1) / CH);
+// Per-call initialisation in one launch: the control words, the per-slot
+// row counters, the bucket histogram of the query sort and the tile windows
+// (empty: tlo = INT_MAX, thi = INT_MIN, lowered / raised by k_window).
+__global__ __launch_bounds__(kThreads) void k_query_init(unsigned long long* __restrict__ ctl, int ctl_words,
+                                                        int32_t* __restrict__ row_cnt, int64_t m,
+                                                        uint32_t* __restrict__ hist, int nb,
+                                                        int32_t* __restrict__ tlo, int32_t* __restrict__ thi,
+                                                        int ntiles) {
+  const int64_t top = max(max((int64_t)ctl_words, m), (int64_t)max(nb, ntiles));
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < ctl_words) ctl[i] = 0ull;
+    if (i < m) row_cnt[i] = 0;
+    if (hist && i < nb) hist[i] = 0u;
+    if (i < ntiles) {
+      tlo[i] = INT_MAX;
+      thi[i] = INT_MIN;
     }
   }
 }
 
-__global__ void k_group_units(const int32_t* __restrict__ units, int ntiles, int G, int32_t* __restrict__ gunits) {
-  const int ngroups = (ntiles + G - 1) / G;
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += gridDim.x * blockDim.x) {
-    const int t0 = g * G, t1 = min(ntiles, t0 + G);
-    int mx = 0;
-    for (int t = t0; t < t1; ++t) mx = max(mx, units[t]);
-    gunits[g] = mx * (t1 - t0);
-  }
-}
-
-// Pairs the screen evaluates: wavefronts (of qpw query slots) with at least
-// one real query, times their slots, times the tile's scanned window.
-__global__ void k_executed(const int32_t* __restrict__ tlo, const int32_t* __restrict__ thi, int ntiles, int T,
-                           int64_t m, int qpw, unsigned long long* __restrict__ out) {
+// The tile plan in one single-workgroup launch (the tile count is small
+// next to the work): clamp and align every tile window (symmetric
+// self-queries start a tile at its own first row), count its work units,
+// add the evaluated pairs (stats), reserve G x max units per group of G
+// tiles, and scan the groups into unit offsets (unit_off[ngroups] = total).
+__global__ __launch_bounds__(1024) void k_tile_plan(int32_t* __restrict__ tlo, int32_t* __restrict__ thi, int ntiles,
+                                                   int CH, int align, int sym_T, int32_t* __restrict__ units, int G,
+                                                   int64_t* __restrict__ unit_off, int T, int64_t m, int qpw,
+                                                   unsigned long long* __restrict__ executed) {
+  __shared__ int64_t carry;
+  __shared__ int64_t wsum[1024 / kWave];
   unsigned long long e = 0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x) {
-    const int64_t valid = min((int64_t)T, max((int64_t)0, m - (int64_t)t * T));
-    const int64_t waves = (valid + qpw - 1) / qpw;
-    e += (unsigned long long)(waves * qpw) * (unsigned long long)max(0, thi[t] - tlo[t]);
+  for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
+    int a = tlo[t], b = thi[t];
+    if (sym_T > 0 && a != INT_MAX) a = max(a, t * sym_T);
+    int u = 0;
+    if (a == INT_MAX || b <= a) {
+      a = 0;
+      b = 0;
+    } else {
+      a -= a % align;
+      b = (int)((((int64_t)b + align - 1) / align) * align);
+      u = (int)(((int64_t)b - a + CH - 1) / CH);
+    }
+    tlo[t] = a;
+    thi[t] = b;
+    units[t] = u;
+    if (executed) {
+      const int64_t valid = min((int64_t)T, max((int64_t)0, m - (int64_t)t * T));
+      e += (unsigned long long)(((valid + qpw - 1) / qpw) * qpw) * (unsigned long long)(b - a);
+    }
   }
-  e = wave_sum(e);
-  if (lane_id() == 0 && e) atomicAdd(out, e);
+  if (executed) {
+    e = wave_sum(e);
+    if (lane_id() == 0 && e) atomicAdd(executed, e);
+  }
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int ngroups = (ntiles + G - 1) / G;
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  for (int g0 = 0; g0 < ngroups; g0 += blockDim.x) {
+    const int g = g0 + threadIdx.x;
+    int64_t v = 0;
+    if (g < ngroups) {
+      const int t0 = g * G, t1 = min(ntiles, t0 + G);
+      int mx = 0;
+      for (int t = t0; t < t1; ++t) mx = max(mx, units[t]);
+      v = (int64_t)mx * (t1 - t0);
+    }
+    // exclusive scan of v over the block, offset by the running carry
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t y = __shfl_up(x, o, kWave);
+      if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    int64_t pre = carry, tot = 0;
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) {
+      if (k < w) pre += wsum[k];
+      tot += wsum[k];
+    }
+    if (g < ngroups) unit_off[g] = pre + x - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) unit_off[ngroups] = carry;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -212,27 +254,6 @@ int grid_for(int64_t work, int cap) {
   return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 }  // namespace
-
-void launch_tile_init(int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s) {
-  k_tile_init<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles);
-  SNN_LAUNCH_CHECK();
-}
-
-void launch_tile_units(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int32_t* units, hipStream_t s) {
-  k_tile_units<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles, CH, align, 0, units);
-  SNN_LAUNCH_CHECK();
-}
-
-void launch_executed(const int32_t* tlo, const int32_t* thi, int ntiles, int T, int64_t m, int qpw,
-                     unsigned long long* out, hipStream_t s) {
-  k_executed<<<grid_for(ntiles, 64), kThreads, 0, s>>>(tlo, thi, ntiles, T, m, qpw, out);
-  SNN_LAUNCH_CHECK();
-}
-
-void launch_group_units(const int32_t* units, int ntiles, int G, int32_t* gunits, hipStream_t s) {
-  k_group_units<<<grid_for((ntiles + G - 1) / G, 1024), kThreads, 0, s>>>(units, ntiles, G, gunits);
-  SNN_LAUNCH_CHECK();
-}
 
 int query_buckets(int64_t m) {
   int K = 256;
@@ -266,17 +287,25 @@ void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, 
   SNN_LAUNCH_CHECK();
 }
 
-void launch_windows(const double* key, int n, const double* qalpha, const double* qnorm, int64_t m, double w_base,
-                    double eps_scale, int T, int CH, int align, int ntiles, int sym, int32_t* lo, int32_t* hi,
-                    int32_t* tlo, int32_t* thi, int32_t* units, unsigned long long* pairs_window, hipStream_t s) {
-  k_tile_init<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles);
+void launch_query_init(unsigned long long* ctl, int ctl_words, int32_t* row_cnt, int64_t m, uint32_t* hist, int nb,
+                       int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s) {
+  const int64_t top = std::max(std::max((int64_t)ctl_words, m), (int64_t)std::max(nb, ntiles));
+  k_query_init<<<grid_for(top, 4096), kThreads, 0, s>>>(ctl, ctl_words, row_cnt, m, hist, nb, tlo, thi, ntiles);
   SNN_LAUNCH_CHECK();
-  if (m > 0) {
-    k_window<<<grid_for(m, 2048), kThreads, 0, s>>>(key, n, qalpha, qnorm, m, w_base, eps_scale, T, sym, lo, hi,
-                                                    tlo, thi, pairs_window);
-    SNN_LAUNCH_CHECK();
-  }
-  k_tile_units<<<grid_for(ntiles, 1024), kThreads, 0, s>>>(tlo, thi, ntiles, CH, align, sym ? T : 0, units);
+}
+
+void launch_windows(const double* key, int n, const double* qalpha, const double* qnorm, int64_t m, double w_base,
+                    double eps_scale, int T, int sym, int32_t* lo, int32_t* hi, int32_t* tlo, int32_t* thi,
+                    unsigned long long* pairs_window, hipStream_t s) {
+  if (m <= 0) return;
+  k_window<<<grid_for(m, 2048), kThreads, 0, s>>>(key, n, qalpha, qnorm, m, w_base, eps_scale, T, sym, lo, hi, tlo,
+                                                  thi, pairs_window);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_tile_plan(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int sym, int32_t* units, int G,
+                      int64_t* unit_off, int T, int64_t m, int qpw, unsigned long long* executed, hipStream_t s) {
+  k_tile_plan<<<1, 1024, 0, s>>>(tlo, thi, ntiles, CH, align, sym ? T : 0, units, G, unit_off, T, m, qpw, executed);
   SNN_LAUNCH_CHECK();
 }
 

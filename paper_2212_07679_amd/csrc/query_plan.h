@@ -106,18 +106,19 @@ void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, 
 // sym: symmetric self-query (counts only candidates j >= s, tiles start at
 // their first row; see QueryDev::sym)
 void launch_windows(const double* key, int n, const double* qalpha, const double* qnorm, int64_t m, double w_base,
-                    double eps_scale, int T, int CH, int align, int ntiles, int sym, int32_t* lo, int32_t* hi,
-                    int32_t* tlo, int32_t* thi, int32_t* units, unsigned long long* pairs_window, hipStream_t s);
+                    double eps_scale, int T, int sym, int32_t* lo, int32_t* hi, int32_t* tlo, int32_t* thi,
+                    unsigned long long* pairs_window, hipStream_t s);
+// one launch: zero ctl_words control words, row_cnt (m) and hist (nb, may be
+// NULL), and empty tile windows (tlo = INT_MAX, thi = INT_MIN)
+void launch_query_init(unsigned long long* ctl, int ctl_words, int32_t* row_cnt, int64_t m, uint32_t* hist, int nb,
+                       int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s);
+// one single-workgroup launch after the windows: tile windows clamped and
+// aligned, units per tile, G x max units per group of G tiles scanned into
+// unit_off (ngroups + 1 entries), evaluated pairs added to *executed
+// (nullable; qpw query slots per wavefront)
+void launch_tile_plan(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int sym, int32_t* units, int G,
+                      int64_t* unit_off, int T, int64_t m, int qpw, unsigned long long* executed, hipStream_t s);
 
-void launch_tile_init(int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s);
-void launch_tile_units(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int32_t* units, hipStream_t s);
-// stats only: adds to *out the (query slot, candidate) pairs the screen
-// evaluates, counting qpw slots per wavefront that holds a real query
-void launch_executed(const int32_t* tlo, const int32_t* thi, int ntiles, int T, int64_t m, int qpw,
-                     unsigned long long* out, hipStream_t s);
-
-// units reserved per group of G tiles: Gg x max units of its tiles
-void launch_group_units(const int32_t* units, int ntiles, int G, int32_t* gunits, hipStream_t s);
 
 // k_cand_fp64.hip: plain float64 screen (every window pair, normative rule)
 void launch_cand_fp64(const QueryDev& q, int grid, hipStream_t s);
@@ -268,6 +269,10 @@ void launch_row_sort_move(const RowMove& mv, int64_t m, int64_t max_len, int32_t
                           unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s);
 // cnt_dst[map[r]] = length of source row r
 void launch_perm_counts(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst, hipStream_t s);
+// the same, plus *row_max = max row length (atomic max; zero beforehand) and
+// *total = src_rp[m]
+void launch_perm_counts_stats(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst,
+                              unsigned long long* row_max, unsigned long long* total, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 

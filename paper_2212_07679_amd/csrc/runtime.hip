@@ -17,7 +17,6 @@
 
 namespace snn {
 
-void launch_row_max(const int32_t* row_cnt, int64_t m, unsigned long long* out, hipStream_t s);
 void launch_self_qnorm(const float* ynorm, int64_t n, double* out, hipStream_t s);
 
 namespace {
@@ -135,6 +134,7 @@ struct Ctl {
   unsigned long long row_max;
   unsigned long long executed;
   unsigned long long accepted;  // neighbour entries (clustering mode)
+  unsigned long long nnz;       // neighbour entries (lists mode)
   int bad;
   int pad1;
 };
@@ -275,7 +275,6 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       int32_t* thi;
       int32_t* units;
       int64_t* unit_off;
-      int32_t* gunits;
       char* scan_scratch;
       Ctl* ctl;
       int32_t* row_cnt;  // per query slot
@@ -302,7 +301,6 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     p.thi = c.take<int32_t>(ntiles);
     p.units = c.take<int32_t>(ntiles);
     p.unit_off = c.take<int64_t>(ntiles + 1);
-    p.gunits = c.take<int32_t>(ntiles);
     p.scan_scratch = c.take<char>(std::max({scan_scratch_bytes(ntiles), scan_scratch_bytes(std::max<int64_t>(m, 1)),
                                             scan_scratch_bytes(nbuckets)}));
     p.ctl = c.take<Ctl>(1);
@@ -321,8 +319,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   Carver carve(ix.ws[0].ptr);
   auto P = plan_query(carve);
 
-  launch_fill_u64(reinterpret_cast<unsigned long long*>(P.ctl), sizeof(Ctl) / 8, 0ull, s);
-  launch_fill_i32(P.row_cnt, m, 0, s);
+  const bool sort_queries = !self && m > 0;
+  launch_query_init(reinterpret_cast<unsigned long long*>(P.ctl), (int)(sizeof(Ctl) / 8), P.row_cnt, m,
+                    sort_queries ? P.hist : nullptr, nbuckets, P.tlo, P.thi, ntiles, s);
 
   const double* q64;
   const int32_t* qorig;
@@ -331,7 +330,6 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   if (!self) {
     if (m > 0) {
       // queries into score order by a counting sort on a uniform score grid
-      launch_fill_i32(reinterpret_cast<int32_t*>(P.hist), nbuckets, 0, s);
       launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), ix.key.as<double>(), (int)n,
                         nbuckets, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, &P.ctl->bad, s);
       exclusive_scan_u32(P.hist, nbuckets, P.scan_scratch, s);
@@ -356,21 +354,18 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const double eps_scale = 1.01 * (u32 + gamma64(d + 2)) * (1.0 + u32) * ix.vnorm;
   // self-queries scan each unordered pair once (S is exactly symmetric)
   const int sym = (self && !o.full_self_scan) ? 1 : 0;
-  launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, CH, prec == SNN_PREC_FP64 ? 1 : 32,
-                 ntiles, sym, P.lo, P.hi, P.tlo, P.thi, P.units, &P.ctl->pairs_window, s);
-  if (st) {
-    // query slots per wavefront: the matrix-core screens evaluate whole
-    // 32-query blocks, the float64 screen one query at a time
-    const int qpw = prec == SNN_PREC_MIXED  ? mixed_queries_per_wave(ka_of(terms))
-                    : prec == SNN_PREC_FP32 ? mfma32_queries_per_tile() / 4
-                                            : 1;
-    launch_executed(P.tlo, P.thi, ntiles, T, m, qpw, &P.ctl->executed, s);
-  }
+  launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, sym, P.lo, P.hi, P.tlo, P.thi,
+                 &P.ctl->pairs_window, s);
+  // query slots per wavefront (stats): the matrix-core screens evaluate
+  // whole 32-query blocks, the float64 screen one query at a time
+  const int qpw = prec == SNN_PREC_MIXED  ? mixed_queries_per_wave(ka_of(terms))
+                  : prec == SNN_PREC_FP32 ? mfma32_queries_per_tile() / 4
+                                          : 1;
   // chunk-major work order inside groups of G score-adjacent tiles (L2 reuse)
   const int G = prec == SNN_PREC_FP64 ? 16 : 8;
   const int ngroups = (ntiles + G - 1) / G;
-  launch_group_units(P.units, ntiles, G, P.gunits, s);
-  exclusive_scan_i32_to_i64(P.gunits, P.unit_off, ngroups, P.scan_scratch, s);
+  launch_tile_plan(P.tlo, P.thi, ntiles, CH, prec == SNN_PREC_FP64 ? 1 : 32, sym, P.units, G, P.unit_off, T, m, qpw,
+                   st ? &P.ctl->executed : nullptr, s);
 
   QueryDev qd{};
   qd.G = G;
@@ -495,12 +490,12 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     // row offsets in slot order (where the neighbours are assembled) and in
     // the caller's order (where each row ends up)
     exclusive_scan_i32_to_i64(P.row_cnt, P.rp_s, m, P.scan_scratch, s);
-    launch_perm_counts(P.rp_s, m, qorig, P.cnt_o, s);
+    // counts in the caller's order, the longest row and the total in one pass
+    launch_perm_counts_stats(P.rp_s, m, qorig, P.cnt_o, &P.ctl->row_max, &P.ctl->nnz, s);
     exclusive_scan_i32_to_i64(P.cnt_o, out->row_ptr, m, P.scan_scratch, s);
-    launch_row_max(P.row_cnt, m, &P.ctl->row_max, s);
     SNN_HIP(hipMemcpyAsync(&hc.ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    SNN_HIP(hipMemcpyAsync(&hc.nnz, out->row_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SNN_HIP(hipStreamSynchronize(s));
+    hc.nnz = (int64_t)hc.ctl.nnz;
     if (hc.ctl.bad) fail(SNN_EINVAL, "Q contains NaN or Inf");
     if ((long long)hc.ctl.survivors <= cap) {
       out->nnz = hc.nnz;
@@ -538,9 +533,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       SNN_HIP(hipEventElapsedTime(&b, ev[0], ev[3]));
       st->screen_ms = a;
       st->total_ms = b;
-      unsigned long long executed = 0;
-      SNN_HIP(hipMemcpy(&executed, &P.ctl->executed, sizeof(executed), hipMemcpyDeviceToHost));
-      st->pairs_executed = (int64_t)executed;
+      st->pairs_executed = (int64_t)hc.ctl.executed;
       for (auto& e : ev) (void)hipEventDestroy(e);
     }
     return;
@@ -566,9 +559,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     SNN_HIP(hipEventElapsedTime(&b, ev[0], ev[3]));
     st->screen_ms = a;
     st->total_ms = b;
-    unsigned long long executed = 0;
-    SNN_HIP(hipMemcpy(&executed, &P.ctl->executed, sizeof(executed), hipMemcpyDeviceToHost));
-    st->pairs_executed = (int64_t)executed;
+    st->pairs_executed = (int64_t)hc.ctl.executed;
     for (auto& e : ev) (void)hipEventDestroy(e);
   }
 }
