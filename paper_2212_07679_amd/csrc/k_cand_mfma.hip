@@ -96,15 +96,21 @@ __global__ __launch_bounds__(kThreads) void k_mixed_qprep(const double* __restri
   }
 }
 
-// Self-queries: the query rows are the index rows.
+// Self-queries: the query rows are the index rows; G lanes read a row
+// together and their partial squared norms meet by shuffles (any order stays
+// within the gamma_{d+1} bound the start value allows for).
+template <int G>
 __global__ __launch_bounds__(kThreads) void k_mixed_qprep_self(const float* __restrict__ ys, int64_t n, int d,
                                                               MixedBound b, float* __restrict__ cthr) {
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+  const int sub = threadIdx.x % G;
+  for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; s < n;
+       s += ((int64_t)gridDim.x * blockDim.x) / G) {
     const float* y = ys + s * d;
     double nn = 0.0;
-    for (int k = 0; k < d; ++k) nn += (double)y[k] * (double)y[k];
-    const double nq = sqrt(nn) * (1.0 + 1e-15);
-    cthr[s] = screen_threshold(b, 0.5 * nn, nq);
+    for (int k = sub; k < d; k += G) nn += (double)y[k] * (double)y[k];
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) nn += __shfl_xor(nn, off, G);
+    if (sub == 0) cthr[s] = screen_threshold(b, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
   }
 }
 
@@ -499,7 +505,10 @@ void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const doubl
 }
 
 void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* cthr, hipStream_t s) {
-  k_mixed_qprep_self<<<grid_for(n, 8192), kThreads, 0, s>>>(ys, n, d, b, cthr);
+  if (d <= 8)
+    k_mixed_qprep_self<1><<<grid_for(n, 8192), kThreads, 0, s>>>(ys, n, d, b, cthr);
+  else
+    k_mixed_qprep_self<16><<<grid_for(n * 16, 8192), kThreads, 0, s>>>(ys, n, d, b, cthr);
   SNN_LAUNCH_CHECK();
 }
 

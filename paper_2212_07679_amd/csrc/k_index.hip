@@ -140,61 +140,70 @@ __global__ void k_gram_final(const double* __restrict__ part, int nblocks, int64
   }
 }
 
-__device__ double block_sum_1024(double v, double* red) {
-  const int t = threadIdx.x;
-  v = wave_sum(v);
+// Power iteration v <- C v / ||C v|| in one workgroup of NT threads (one
+// wavefront for d <= 64, reductions by shuffles only; 1024 threads above):
+// thread i owns rows i, i + NT, ...; C is symmetric, so row i of C v is read
+// down column i (C[j][i], j = 0..d-1), one coalesced row of C per j across
+// the threads; v and C v stay in LDS.  Stops when the Rayleigh quotient
+// changes by less than 1e-12 relative (it converges at twice the rate of v)
+// or after max_iter.  The largest-magnitude entry is made positive; C = 0
+// gives e_1.
+template <int NT>
+__device__ __forceinline__ double group_sum(double x, double* red) {
+  x = wave_sum(x);
+  if (NT == kWave) return x;
   __syncthreads();
-  if (t % kWave == 0) red[t / kWave] = v;
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = x;
   __syncthreads();
   double s = 0.0;
-  for (int w = 0; w < (int)(blockDim.x / kWave); ++w) s += red[w];
+  for (int w = 0; w < NT / kWave; ++w) s += red[w];
   return s;
 }
 
-// Power iteration v <- C v / ||C v|| in one workgroup of 1024 threads, with v
-// and C v in LDS and C read from global memory (L2-resident).  Stops when
-// the Rayleigh quotient changes by less than 1e-12 relative (it converges at
-// twice the rate of v) or after max_iter.  The largest-magnitude entry is
-// made positive; C = 0 gives e_1.
-__global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ C, int d, int max_iter,
-                                                     double* __restrict__ v_out, int* __restrict__ iters_out) {
+template <int NT>
+__global__ __launch_bounds__(NT) void k_power_iter(const double* __restrict__ C, int d, int max_iter,
+                                                  double* __restrict__ v_out, int* __restrict__ iters_out) {
   extern __shared__ double lds[];
-  __shared__ double red[16];
-  __shared__ int s_stop;
+  __shared__ double red[NT / kWave];
   const int t = threadIdx.x;
   double* v = lds;      // d
   double* w = lds + d;  // d
   // deterministic start: 1 + small distinct perturbation per coordinate
-  for (int i = t; i < d; i += blockDim.x) v[i] = 1.0 + 0.01 * (double)((i * 2654435761u) % 1000u) / 1000.0;
-  __syncthreads();
   double loc = 0.0;
-  for (int i = t; i < d; i += blockDim.x) loc += v[i] * v[i];
-  double nv = sqrt(block_sum_1024(loc, red));
-  for (int i = t; i < d; i += blockDim.x) v[i] /= nv;
+  for (int i = t; i < d; i += NT) {
+    const double x = 1.0 + 0.01 * (double)((i * 2654435761u) % 1000u) / 1000.0;
+    v[i] = x;
+    loc += x * x;
+  }
+  const double nv = sqrt(group_sum<NT>(loc, red));
+  for (int i = t; i < d; i += NT) v[i] /= nv;
   __syncthreads();
   double lambda_prev = -1.0;
   int it = 0;
   bool zero = false;
   for (it = 1; it <= max_iter; ++it) {
-    double part = 0.0;
-    for (int i = t; i < d; i += blockDim.x) {
-      double s = 0.0;
-      for (int j = 0; j < d; ++j) s += C[(int64_t)i * d + j] * v[j];
-      w[i] = s;
-      part += s * v[i];
+    double part = 0.0, nn = 0.0;
+    for (int i0 = 0; i0 < d; i0 += NT) {
+      const int i = i0 + t;
+      double sacc = 0.0;
+      if (i < d)
+        for (int j = 0; j < d; ++j) sacc += C[(int64_t)j * d + i] * v[j];
+      if (i < d) {
+        w[i] = sacc;
+        part += sacc * v[i];
+        nn += sacc * sacc;
+      }
     }
-    double lambda = block_sum_1024(part, red);  // Rayleigh quotient v^T C v
-    loc = 0.0;
-    for (int i = t; i < d; i += blockDim.x) loc += w[i] * w[i];
-    double nw = sqrt(block_sum_1024(loc, red));
+    const double lambda = group_sum<NT>(part, red);  // Rayleigh quotient v^T C v
+    const double nw = sqrt(group_sum<NT>(nn, red));
     if (!(nw > 0.0)) {
       zero = true;
       break;
     }
-    for (int i = t; i < d; i += blockDim.x) v[i] = w[i] / nw;
-    if (t == 0) s_stop = (fabs(lambda - lambda_prev) <= 1e-12 * fabs(lambda)) ? 1 : 0;
     __syncthreads();
-    if (s_stop) break;
+    for (int i = t; i < d; i += NT) v[i] = w[i] / nw;
+    __syncthreads();
+    if (fabs(lambda - lambda_prev) <= 1e-12 * fabs(lambda)) break;
     lambda_prev = lambda;
   }
   __syncthreads();
@@ -219,23 +228,35 @@ __global__ __launch_bounds__(1024) void k_power_iter(const double* __restrict__ 
 }
 
 // ---- step 5: scores ----------------------------------------------------------
-template <typename T>
+// G lanes per row (coalesced row reads); the partial sums of a row meet by
+// shuffles within its G lanes, in a fixed order (deterministic).  Any order
+// stays within the gamma_{d+2} bound of the key error.
+template <typename T, int G>
 __global__ __launch_bounds__(kThreads) void k_project(const T* __restrict__ X, int64_t n, int d,
                                                      const double* __restrict__ mu, const double* __restrict__ v,
                                                      uint32_t* __restrict__ ukey, uint32_t* __restrict__ val,
                                                      double* __restrict__ max_norm) {
+  const int sub = threadIdx.x % G;
   double nmax = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; i < n;
+       i += ((int64_t)gridDim.x * blockDim.x) / G) {
     const T* p = X + i * d;
     double a = 0.0, nn = 0.0;
-    for (int k = 0; k < d; ++k) {
-      double x = (double)p[k] - mu[k];
+    for (int k = sub; k < d; k += G) {
+      const double x = (double)p[k] - mu[k];
       a += x * v[k];
-      double y = (double)(float)x;
+      const double y = (double)(float)x;
       nn += y * y;
     }
-    ukey[i] = float_to_ordered((float)a);
-    val[i] = (uint32_t)i;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+      a += __shfl_xor(a, off, G);
+      nn += __shfl_xor(nn, off, G);
+    }
+    if (sub == 0) {
+      ukey[i] = float_to_ordered((float)a);
+      val[i] = (uint32_t)i;
+    }
     nmax = fmax(nmax, nn);
   }
   nmax = wave_max(nmax);
@@ -243,7 +264,10 @@ __global__ __launch_bounds__(kThreads) void k_project(const T* __restrict__ X, i
 }
 
 // ---- gather into score order -------------------------------------------------
-template <typename T>
+// G lanes per row: the source row (a random row of X) and every destination
+// row are read and written G consecutive elements at a time; the row's
+// squared norm meets by shuffles within its G lanes.
+template <typename T, int G>
 __global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, int64_t n, int d, int dp,
                                                     const double* __restrict__ mu,
                                                     const uint32_t* __restrict__ ukey,
@@ -253,27 +277,72 @@ __global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, in
                                                     float* __restrict__ h, float* __restrict__ ynorm,
                                                     int64_t id_base) {
   if (blockIdx.x == 0 && threadIdx.x < 64) h[n + threadIdx.x] = INFINITY;  // padding rows
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
+  const int sub = threadIdx.x % G;
+  for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; s < n;
+       s += ((int64_t)gridDim.x * blockDim.x) / G) {
     const uint32_t i = val[s];
-    perm[s] = (int32_t)(id_base + i);
-    key[s] = (double)ordered_to_float(ukey[s]);
     const T* p = X + (int64_t)i * d;
     double nn = 0.0;
-    for (int k = 0; k < d; ++k) {
-      T x = p[k];
-      po[s * d + k] = x;
-      p64[s * dp + k] = (double)x;
-      float y = (float)((double)x - mu[k]);
-      ys[s * d + k] = y;
-      nn += (double)y * (double)y;
+    for (int k = sub; k < dp; k += G) {
+      if (k < d) {
+        const T x = p[k];
+        po[s * d + k] = x;
+        p64[s * dp + k] = (double)x;
+        const float y = (float)((double)x - mu[k]);
+        ys[s * d + k] = y;
+        nn += (double)y * (double)y;
+      } else {
+        p64[s * dp + k] = 0.0;
+      }
     }
-    for (int k = d; k < dp; ++k) p64[s * dp + k] = 0.0;
-    h[s] = (float)(0.5 * nn);
-    // round ||y|| up to float so it bounds the true norm
-    float nr = (float)sqrt(nn);
-    if ((double)nr < sqrt(nn)) nr = nextafterf(nr, INFINITY);
-    ynorm[s] = nr;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) nn += __shfl_xor(nn, off, G);
+    if (sub == 0) {
+      perm[s] = (int32_t)(id_base + i);
+      key[s] = (double)ordered_to_float(ukey[s]);
+      h[s] = (float)(0.5 * nn);
+      // round ||y|| up to float so it bounds the true norm
+      float nr = (float)sqrt(nn);
+      if ((double)nr < sqrt(nn)) nr = nextafterf(nr, INFINITY);
+      ynorm[s] = nr;
+    }
   }
+}
+
+int grid_for(int64_t work, int per_block, int cap);
+
+// lanes per row of the row kernels: enough to read a row in one or two
+// steps, at most 16
+inline int row_lanes(int d) { return d <= 4 ? 4 : (d <= 8 ? 8 : 16); }
+
+template <typename T>
+void launch_project(const T* X, int64_t n, int d, const double* mu, const double* v, uint32_t* ukey, uint32_t* val,
+                    double* max_norm, int cap, hipStream_t s) {
+  const int G = row_lanes(d);
+  const int grid = grid_for(n * G, kThreads, cap);
+  if (G == 4)
+    k_project<T, 4><<<grid, kThreads, 0, s>>>(X, n, d, mu, v, ukey, val, max_norm);
+  else if (G == 8)
+    k_project<T, 8><<<grid, kThreads, 0, s>>>(X, n, d, mu, v, ukey, val, max_norm);
+  else
+    k_project<T, 16><<<grid, kThreads, 0, s>>>(X, n, d, mu, v, ukey, val, max_norm);
+  SNN_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_gather(const T* X, int64_t n, int d, int dp, const double* mu, const uint32_t* ukey, const uint32_t* val,
+                   double* key, int32_t* perm, T* po, double* p64, float* ys, float* h, float* ynorm, int64_t id_base,
+                   int cap, hipStream_t s) {
+  const int G = row_lanes(d);
+  const int grid = grid_for(std::max<int64_t>(n, 1) * G, kThreads, cap);
+  if (G == 4)
+    k_gather<T, 4><<<grid, kThreads, 0, s>>>(X, n, d, dp, mu, ukey, val, key, perm, po, p64, ys, h, ynorm, id_base);
+  else if (G == 8)
+    k_gather<T, 8><<<grid, kThreads, 0, s>>>(X, n, d, dp, mu, ukey, val, key, perm, po, p64, ys, h, ynorm, id_base);
+  else
+    k_gather<T, 16><<<grid, kThreads, 0, s>>>(X, n, d, dp, mu, ukey, val, key, perm, po, p64, ys, h, ynorm,
+                                              id_base);
+  SNN_LAUNCH_CHECK();
 }
 
 // ---- mixed-precision operand rows ---------------------------------------------
@@ -389,19 +458,17 @@ void build_index_t(Index& ix, const T* X) {
   SNN_LAUNCH_CHECK();
   k_gram_final<<<grid_for(dd), kThreads, 0, s>>>(part2, g2, dd, C);
   SNN_LAUNCH_CHECK();
-  k_power_iter<<<1, 1024, 2 * sizeof(double) * d, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
+  if (d <= kWave)
+    k_power_iter<kWave><<<1, kWave, 2 * sizeof(double) * d, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
+  else
+    k_power_iter<1024><<<1, 1024, 2 * sizeof(double) * d, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
   SNN_LAUNCH_CHECK();
-  k_project<T><<<grid_for(n, kThreads, 4 * di.cus * 8), kThreads, 0, s>>>(X, n, d, ix.mu.as<double>(),
-                                                                          ix.v.as<double>(), ukey, val,
-                                                                          &sc->max_norm);
-  SNN_LAUNCH_CHECK();
+  launch_project<T>(X, n, d, ix.mu.as<double>(), ix.v.as<double>(), ukey, val, &sc->max_norm, 4 * di.cus * 8, s);
   radix_sort_pairs(ix.arena, ukey, val, n, 0, 32, s);
   T* po = ix.po.as<T>();
   double* p64 = ix.p64.as<double>();
-  k_gather<T><<<grid_for(n, kThreads, 4 * di.cus * 8), kThreads, 0, s>>>(
-      X, n, d, ix.dp, ix.mu.as<double>(), ukey, val, ix.key.as<double>(), ix.perm.as<int32_t>(), po, p64,
-      ix.ys.as<float>(), ix.h.as<float>(), ix.ynorm.as<float>(), 0);
-  SNN_LAUNCH_CHECK();
+  launch_gather<T>(X, n, d, ix.dp, ix.mu.as<double>(), ukey, val, ix.key.as<double>(), ix.perm.as<int32_t>(), po, p64,
+                   ix.ys.as<float>(), ix.h.as<float>(), ix.ynorm.as<float>(), 0, 4 * di.cus * 8, s);
 
   Scratch hs;
   SNN_HIP(hipMemcpyAsync(&hs, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
@@ -538,14 +605,9 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   const int cap = 4 * di.cus * 8;
   k_check_finite<T><<<grid_for(k * d, kThreads, cap), kThreads, 0, s>>>(Xn, k * d, &sc->bad);
   SNN_LAUNCH_CHECK();
-  k_project<T><<<grid_for(k, kThreads, 4 * di.cus * 8), kThreads, 0, s>>>(Xn, k, d, ix.mu.as<double>(),
-                                                                          ix.v.as<double>(), ukey, val,
-                                                                          &sc->max_norm);
-  SNN_LAUNCH_CHECK();
+  launch_project<T>(Xn, k, d, ix.mu.as<double>(), ix.v.as<double>(), ukey, val, &sc->max_norm, cap, s);
   radix_sort_pairs(ix.arena, ukey, val, k, 0, 32, s);
-  k_gather<T><<<grid_for(k, kThreads, 4 * di.cus * 8), kThreads, 0, s>>>(
-      Xn, k, d, dp, ix.mu.as<double>(), ukey, val, keyb, permb, pob, p64b, ysb, hb, ynb, na);
-  SNN_LAUNCH_CHECK();
+  launch_gather<T>(Xn, k, d, dp, ix.mu.as<double>(), ukey, val, keyb, permb, pob, p64b, ysb, hb, ynb, na, cap, s);
   Scratch hs;
   SNN_HIP(hipMemcpyAsync(&hs, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
   SNN_HIP(hipStreamSynchronize(s));
