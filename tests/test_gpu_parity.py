@@ -312,3 +312,18 @@ def test_dense_self_output(B, prec):
     assert ref.row_ptr[-1] > 20 * w.n
     idx = B.Index(to_dev(w.P))
     check_same(idx.query_self(w.R, precision=prec), ref, f"dense self {prec}")
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32", "fp64"])
+@pytest.mark.parametrize("tile_c", [32, 96, 1024])
+def test_small_work_units(B, precision, tile_c):
+    """Many work units per tile (and chunk ends inside windows) for every screen."""
+    w = W.gmm16(n=30_000, m=900, R=3.0)
+    say(f"small work units: tile_c={tile_c} precision={precision}")
+    ref = oracle.brute_radius(w.P, w.Q, w.R)
+    idx = B.Index(to_dev(w.P))
+    check_same(idx.query(to_dev(w.Q), w.R, precision=precision, tile_c=tile_c), ref, f"tile_c={tile_c}")
+    selfw = w.P[:6000]
+    ref_s = oracle.brute_radius(selfw, selfw, w.R)
+    idx_s = B.Index(to_dev(selfw))
+    check_same(idx_s.query_self(w.R, precision=precision, tile_c=tile_c), ref_s, f"self tile_c={tile_c}")
