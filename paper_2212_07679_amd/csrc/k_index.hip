@@ -68,13 +68,15 @@ __global__ __launch_bounds__(kThreads) void k_colsum_partial(const T* __restrict
   if (badloc) atomicOr(bad, 1);
 }
 
-__global__ void k_colsum_final(const double* __restrict__ part, int nblocks, int d, int64_t n,
-                               double* __restrict__ mu) {
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < d; c += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * d + c];
-    mu[c] = s / (double)n;
-  }
+// One wavefront per column: the lanes take the block partials in a fixed
+// interleaved order and meet by shuffles (deterministic).
+__global__ __launch_bounds__(kWave) void k_colsum_final(const double* __restrict__ part, int nblocks, int d,
+                                                       int64_t n, double* __restrict__ mu) {
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kWave) s += part[(int64_t)b * d + c];
+  s = wave_sum(s);
+  if (threadIdx.x == 0) mu[c] = s / (double)n;
 }
 
 // ---- step 4: centred Gram matrix --------------------------------------------
@@ -132,11 +134,16 @@ __global__ __launch_bounds__(kThreads) void k_gram_partial(const T* __restrict__
   }
 }
 
-__global__ void k_gram_final(const double* __restrict__ part, int nblocks, int64_t dd, double* __restrict__ C) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < dd; e += (int64_t)gridDim.x * blockDim.x) {
+// One wavefront per entry of C, as k_colsum_final (the same order for C[a][b]
+// and C[b][a], whose partials are equal, so C stays exactly symmetric).
+__global__ __launch_bounds__(kThreads) void k_gram_final(const double* __restrict__ part, int nblocks, int64_t dd,
+                                                        double* __restrict__ C) {
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; e < dd; e += waves) {
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * dd + e];
-    C[e] = s;
+    for (int b = lane_id(); b < nblocks; b += kWave) s += part[(int64_t)b * dd + e];
+    s = wave_sum(s);
+    if (lane_id() == 0) C[e] = s;
   }
 }
 
@@ -259,8 +266,15 @@ __global__ __launch_bounds__(kThreads) void k_project(const T* __restrict__ X, i
     }
     nmax = fmax(nmax, nn);
   }
+  // one atomic per workgroup (the address is the same for all of them)
+  __shared__ double red[kThreads / kWave];
   nmax = wave_max(nmax);
-  if (lane_id() == 0) atomic_max_nonneg(max_norm, nmax);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = nmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / kWave; ++w) nmax = fmax(nmax, red[w]);
+    atomic_max_nonneg(max_norm, nmax);
+  }
 }
 
 // ---- gather into score order -------------------------------------------------
@@ -418,7 +432,9 @@ void build_index_t(Index& ix, const T* X) {
   const int tiles_1d = (d + ts - 1) / ts;
   const int gy = (tiles_1d * tiles_1d + kThreads - 1) / kThreads;
   int64_t dd = (int64_t)d * d;
-  int g2 = (int)std::min<int64_t>(std::max<int64_t>(1, (n + 4095) / 4096), 2 * (int64_t)di.cus);
+  // about 512 rows per workgroup and up to 8 workgroups per CU: with fewer,
+  // larger blocks the staging rounds of the rows are latency-bound
+  int g2 = (int)std::min<int64_t>(std::max<int64_t>(1, (n + 511) / 512), 8 * (int64_t)di.cus);
   g2 = (int)std::max<int64_t>(1, std::min<int64_t>(g2, (int64_t)(256ll << 20) / (dd * 8)));
   const int64_t rpb2 = (n + g2 - 1) / g2;
   const int rows_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, 4096 / d));
@@ -444,7 +460,7 @@ void build_index_t(Index& ix, const T* X) {
   SNN_HIP(hipMemsetAsync(sc, 0, sizeof(Scratch), s));
   k_colsum_partial<T><<<g1, kThreads, 0, s>>>(X, n, d, rpb1, part1, &sc->bad);
   SNN_LAUNCH_CHECK();
-  k_colsum_final<<<(d + 255) / 256, 256, 0, s>>>(part1, g1, d, n, ix.mu.as<double>());
+  k_colsum_final<<<d, kWave, 0, s>>>(part1, g1, d, n, ix.mu.as<double>());
   SNN_LAUNCH_CHECK();
 
   const size_t lds2 = sizeof(double) * rows_chunk * d;
@@ -456,7 +472,7 @@ void build_index_t(Index& ix, const T* X) {
     default: k_gram_partial<T, 8><<<grid2, kThreads, lds2, s>>>(X, n, d, ix.mu.as<double>(), rpb2, rows_chunk, part2); break;
   }
   SNN_LAUNCH_CHECK();
-  k_gram_final<<<grid_for(dd), kThreads, 0, s>>>(part2, g2, dd, C);
+  k_gram_final<<<grid_for(dd * kWave), kThreads, 0, s>>>(part2, g2, dd, C);
   SNN_LAUNCH_CHECK();
   if (d <= kWave)
     k_power_iter<kWave><<<1, kWave, 2 * sizeof(double) * d, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
