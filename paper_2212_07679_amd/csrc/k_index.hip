@@ -234,6 +234,114 @@ __global__ __launch_bounds__(NT) void k_power_iter(const double* __restrict__ C,
   }
 }
 
+// Same iteration for 64 < d <= 128 with C resident in LDS (at most 128 KB):
+// read once from HBM instead of from L2 on every step.  512 threads = 4 parts
+// x 128 row slots; part p sums columns j = p, p + 4, ... of row i (C[j][i],
+// conflict-free across a wavefront), the 4 partial sums meet in LDS, and the
+// Rayleigh quotient and ||C v||^2 share one reduction.
+constexpr int kPiSlots = 128, kPiParts = 4, kPiThreads = kPiSlots * kPiParts;
+
+__global__ __launch_bounds__(kPiThreads) void k_power_iter_lds(const double* __restrict__ Cg, int d, int max_iter,
+                                                               double* __restrict__ v_out,
+                                                               int* __restrict__ iters_out) {
+  extern __shared__ double lds[];
+  __shared__ double red[2 * (kPiSlots / kWave)];
+  double* v = lds;                 // kPiSlots
+  double* wp = v + kPiSlots;       // kPiParts x kPiSlots partial sums
+  double* C = wp + kPiThreads;     // d x d
+  const int t = threadIdx.x, i = t % kPiSlots, p = t / kPiSlots;
+  for (int e = t; e < d * d; e += kPiThreads) C[e] = Cg[e];
+  double x = 0.0;
+  if (t < d) x = 1.0 + 0.01 * (double)((t * 2654435761u) % 1000u) / 1000.0;
+  if (t < kPiSlots) v[t] = x;
+  __syncthreads();
+  double loc = 0.0;
+  for (int k = 0; k < d; ++k) loc += v[k] * v[k];
+  __syncthreads();  // every thread has read v before it is overwritten
+  if (t < kPiSlots) v[t] = x / sqrt(loc);
+  __syncthreads();
+  double lambda_prev = -1.0;
+  int it = 0;
+  bool zero = false;
+  for (it = 1; it <= max_iter; ++it) {
+    if (i < d) {
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int j = p;
+      for (; j + 3 * kPiParts < d; j += 4 * kPiParts) {
+        a0 += C[j * d + i] * v[j];
+        a1 += C[(j + kPiParts) * d + i] * v[j + kPiParts];
+        a2 += C[(j + 2 * kPiParts) * d + i] * v[j + 2 * kPiParts];
+        a3 += C[(j + 3 * kPiParts) * d + i] * v[j + 3 * kPiParts];
+      }
+      for (; j < d; j += kPiParts) a0 += C[j * d + i] * v[j];
+      wp[p * kPiSlots + i] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+    double sacc = 0.0, part = 0.0, nn = 0.0;
+    if (t < kPiSlots) {  // waves 0 and 1 own the rows
+      if (t < d) {
+        sacc = (wp[t] + wp[kPiSlots + t]) + (wp[2 * kPiSlots + t] + wp[3 * kPiSlots + t]);
+        part = sacc * v[t];
+        nn = sacc * sacc;
+      }
+      part = wave_sum(part);
+      nn = wave_sum(nn);
+      if (lane_id() == 0) {
+        red[2 * (t / kWave)] = part;
+        red[2 * (t / kWave) + 1] = nn;
+      }
+    }
+    __syncthreads();
+    double lambda = 0.0, n2 = 0.0;
+    for (int w = 0; w < kPiSlots / kWave; ++w) {
+      lambda += red[2 * w];
+      n2 += red[2 * w + 1];
+    }
+    const double nw = sqrt(n2);
+    if (!(nw > 0.0)) {
+      zero = true;
+      break;
+    }
+    if (t < kPiSlots) v[t] = sacc / nw;  // every read of v this step is behind the barrier above
+    __syncthreads();
+    if (fabs(lambda - lambda_prev) <= 1e-12 * fabs(lambda)) break;
+    lambda_prev = lambda;
+  }
+  __syncthreads();
+  if (t == 0) {
+    if (zero)
+      for (int k = 0; k < d; ++k) v[k] = (k == 0) ? 1.0 : 0.0;
+    int im = 0;
+    double am = -1.0;
+    for (int k = 0; k < d; ++k)
+      if (fabs(v[k]) > am) {
+        am = fabs(v[k]);
+        im = k;
+      }
+    const double sgn = v[im] < 0 ? -1.0 : 1.0;
+    double ss = 0.0;
+    for (int k = 0; k < d; ++k) ss += v[k] * v[k];
+    const double inv = 1.0 / sqrt(ss);
+    for (int k = 0; k < d; ++k) v_out[k] = sgn * v[k] * inv;
+    *iters_out = it > max_iter ? max_iter : it;
+  }
+}
+
+size_t power_iter_lds_bytes(int d) { return sizeof(double) * ((size_t)kPiSlots + kPiThreads + (size_t)d * d); }
+
+// The LDS form needs more than the default 64 KB of dynamic LDS: allowed
+// when the device reports enough per workgroup and the limit can be raised.
+bool power_iter_lds_ok(const DeviceInfo& di, int d) {
+  const size_t need = power_iter_lds_bytes(d);
+  if (need + 64 > (size_t)di.lds_bytes) return false;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_power_iter_lds),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)need) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
 // ---- step 5: scores ----------------------------------------------------------
 // G lanes per row (coalesced row reads); the partial sums of a row meet by
 // shuffles within its G lanes, in a fixed order (deterministic).  Any order
@@ -476,6 +584,8 @@ void build_index_t(Index& ix, const T* X) {
   SNN_LAUNCH_CHECK();
   if (d <= kWave)
     k_power_iter<kWave><<<1, kWave, 2 * sizeof(double) * d, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
+  else if (d <= kPiSlots && power_iter_lds_ok(di, d))
+    k_power_iter_lds<<<1, kPiThreads, power_iter_lds_bytes(d), s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
   else
     k_power_iter<1024><<<1, 1024, 2 * sizeof(double) * d, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
   SNN_LAUNCH_CHECK();

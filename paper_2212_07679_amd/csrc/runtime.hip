@@ -85,6 +85,11 @@ const DeviceInfo& device_info(int device) {
     SNN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
     cache[device].cus = cus > 0 ? cus : 1;
     cache[device].xcds = cus >= 64 ? 8 : 1;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+      cache[device].lds_bytes = lds;
+    else
+      (void)hipGetLastError();
     have[device] = true;
   }
   return cache[device];

@@ -105,7 +105,7 @@ struct Buffer {
 struct DeviceInfo {
   int cus = 256;       // compute units
   int xcds = 8;        // accelerator complex dies (separate L2 each)
-  int lds_bytes = 160 * 1024;
+  int lds_bytes = 64 * 1024;  // LDS one workgroup may use (queried)
 };
 const DeviceInfo& device_info(int device);
 

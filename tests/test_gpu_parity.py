@@ -252,6 +252,27 @@ def test_index_internals(B):
     assert np.all(np.abs(key - alpha) <= v["key_eps"])
 
 
+@pytest.mark.parametrize("d", [16, 64, 65, 100, 128, 129, 200])
+def test_power_iteration_widths(B, d):
+    # every form of the power iteration (one wavefront; C in LDS for
+    # 64 < d <= 128; C through the caches above): unit v along the top
+    # eigenvector of a spectrum with a clear gap, Rayleigh quotient at the top
+    say(f"power iteration d={d}")
+    g = np.random.default_rng([2212, 7679, 99, d])
+    scale = np.linspace(1.0, 2.0, d)
+    scale[d // 3] = 3.0
+    P = (g.standard_normal((20_000, d)) * scale).astype(np.float32)
+    v = B.Index(to_dev(P)).view()
+    X = P.astype(np.float64) - P.astype(np.float64).mean(0)
+    C = X.T @ X
+    lam, vec = np.linalg.eigh(C)
+    vv = v["v"].cpu().numpy()
+    assert abs(np.linalg.norm(vv) - 1) < 1e-12
+    assert vv @ C @ vv >= (1 - 1e-9) * lam[-1]
+    assert abs(vv @ vec[:, -1]) >= 1 - 1e-6
+    assert 1 <= v["power_iters"] <= 500
+
+
 @pytest.mark.parametrize("n,bits", [(1, (0, 32)), (1000, (0, 32)), (100_003, (0, 32)), (70_000, (8, 32)),
                                     (5000, (0, 3))])
 def test_radix_sort(B, n, bits):
