@@ -80,58 +80,124 @@ __global__ __launch_bounds__(kWave) void k_colsum_final(const double* __restrict
 }
 
 // ---- step 4: centred Gram matrix --------------------------------------------
-// Each thread owns a TS x TS tile of C.  Rows are staged in LDS, centred in
-// float64.  blockIdx.y selects the group of 256 thread tiles (large d).
-template <typename T, int TS>
+// Narrow data (d < kGramMfmaMinD, so d * d < 64): thread t owns entry
+// (t / d, t % d) of one partial C; rows are staged in LDS, centred in float64.
+template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gram_partial(const T* __restrict__ X, int64_t n, int d,
                                                           const double* __restrict__ mu, int64_t rows_per_block,
                                                           int rows_chunk, double* __restrict__ part) {
   extern __shared__ double stage[];  // rows_chunk x d
   const int t = threadIdx.x;
-  const int tiles_1d = (d + TS - 1) / TS;
-  const int tile = blockIdx.y * kThreads + t;
-  const bool active = tile < tiles_1d * tiles_1d;
-  const int ta = active ? (tile / tiles_1d) * TS : 0;
-  const int tb = active ? (tile % tiles_1d) * TS : 0;
-  double acc[TS][TS];
-#pragma unroll
-  for (int i = 0; i < TS; ++i)
-#pragma unroll
-    for (int j = 0; j < TS; ++j) acc[i][j] = 0.0;
+  const bool active = t < d * d;
+  const int ea = active ? t / d : 0, eb = active ? t % d : 0;
+  double acc = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = min(n, r0 + rows_per_block);
   for (int64_t rc = r0; rc < r1; rc += rows_chunk) {
     const int rows = (int)min((int64_t)rows_chunk, r1 - rc);
     __syncthreads();
-    for (int e = t; e < rows * d; e += kThreads) {
-      int c = e % d;
-      stage[e] = ld(X, rc * d + e) - mu[c];
-    }
+    for (int e = t; e < rows * d; e += kThreads) stage[e] = ld(X, rc * d + e) - mu[e % d];
     __syncthreads();
-    if (active) {
-      for (int r = 0; r < rows; ++r) {
-        const double* row = stage + r * d;
-        double a[TS], b[TS];
+    if (active)
+      for (int r = 0; r < rows; ++r) acc = fma(stage[r * d + ea], stage[r * d + eb], acc);
+  }
+  if (active) part[(int64_t)blockIdx.x * d * d + t] = acc;
+}
+
+// The same partial Gram matrices on the float64 matrix cores
+// (v_mfma_f64_16x16x4f64): C is cut into column blocks of BW = 16 TB and
+// each wavefront owns one pair of blocks (a, b), a <= b, accumulating
+// Y[:, a]^T Y[:, b] over 4 rows per instruction, Y = X - mu in float64.
+// Operands go from memory straight into registers (no LDS): lane l loads
+// column 16 t + l % 16 of row l / 16 of each 4-row step.  Only entries on or
+// above the diagonal are kept and each is written to both halves, so every
+// partial (and C) is exactly symmetric.
+constexpr int kGramWaves = 4;
+// below 8 columns the 16-wide tiles are mostly padding (at d = 3 the
+// one-entry-per-thread form above is measured faster)
+constexpr int kGramMfmaMinD = 8;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int TB>
+__global__ __launch_bounds__(kGramWaves * kWave) void k_gram_mfma(const T* __restrict__ X, int64_t n, int d,
+                                                                const double* __restrict__ mu,
+                                                                int64_t rows_per_block, int npairs,
+                                                                double* __restrict__ part) {
+  constexpr int BW = 16 * TB;
+  const int pair = blockIdx.y * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (pair >= npairs) return;  // no barriers below
+  const int nbk = (d + BW - 1) / BW;
+  int ba = 0, rest = pair;
+  while (rest >= nbk - ba) {
+    rest -= nbk - ba;
+    ++ba;
+  }
+  const int bb = ba + rest;
+  const bool diag = ba == bb;
+  const int l = lane_id(), c16 = l % 16, k4 = l / 16;
+  int ca[TB], cb[TB];
+  double mua[TB], mub[TB];
 #pragma unroll
-        for (int i = 0; i < TS; ++i) {
-          a[i] = (ta + i < d) ? row[ta + i] : 0.0;
-          b[i] = (tb + i < d) ? row[tb + i] : 0.0;
-        }
+  for (int t = 0; t < TB; ++t) {
+    ca[t] = ba * BW + 16 * t + c16;
+    cb[t] = bb * BW + 16 * t + c16;
+    mua[t] = ca[t] < d ? mu[ca[t]] : 0.0;
+    mub[t] = cb[t] < d ? mu[cb[t]] : 0.0;
+  }
+  f64x4 acc[TB][TB];
 #pragma unroll
-        for (int i = 0; i < TS; ++i)
+  for (int i = 0; i < TB; ++i)
 #pragma unroll
-          for (int j = 0; j < TS; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+    for (int j = 0; j < TB; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(n, r0 + rows_per_block);
+  // raw operands of the next PF steps stay in flight in a register ring
+  // (measured: 8 steps for one or two tiles a side, 2 for the 16-tile pairs)
+  constexpr int PF = (TB >= 3 ? 2 : 8) / (sizeof(T) == 8 ? 2 : 1);
+  T ra[PF][TB], rb[PF][TB];
+  auto issue = [&](int64_t step, T* xa, T* xb) {
+    const int64_t row = step + k4;
+    const bool ok = row < r1;
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+      xa[t] = (ok && ca[t] < d) ? X[row * d + ca[t]] : T(0);
+      if (!diag) xb[t] = (ok && cb[t] < d) ? X[row * d + cb[t]] : T(0);
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < PF; ++q) issue(r0 + 4 * q, ra[q], rb[q]);
+  for (int64_t step = r0; step < r1; step += 4 * PF) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int64_t row = step + 4 * q + k4;
+      double a[TB], b[TB];
+#pragma unroll
+      for (int t = 0; t < TB; ++t) {  // padding (rows past r1, columns past d) stays exactly zero
+        a[t] = (row < r1 && ca[t] < d) ? (double)ra[q][t] - mua[t] : 0.0;
+        b[t] = diag ? a[t] : ((row < r1 && cb[t] < d) ? (double)rb[q][t] - mub[t] : 0.0);
       }
+      issue(step + 4 * (q + PF), ra[q], rb[q]);
+#pragma unroll
+      for (int i = 0; i < TB; ++i)
+#pragma unroll
+        for (int j = 0; j < TB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
   }
-  if (active) {
-    double* out = part + (int64_t)blockIdx.x * d * d;
+  // element e of lane l holds D[l / 16 + 4 e][l % 16] of each 16 x 16 tile
+  double* out = part + (int64_t)blockIdx.x * d * d;
 #pragma unroll
-    for (int i = 0; i < TS; ++i)
+  for (int i = 0; i < TB; ++i)
 #pragma unroll
-      for (int j = 0; j < TS; ++j)
-        if (ta + i < d && tb + j < d) out[(int64_t)(ta + i) * d + tb + j] = acc[i][j];
-  }
+    for (int j = 0; j < TB; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int gi = ba * BW + 16 * i + k4 + 4 * e, gj = bb * BW + 16 * j + c16;
+        if (gi < d && gj < d && gi <= gj) {
+          out[(int64_t)gi * d + gj] = acc[i][j][e];
+          out[(int64_t)gj * d + gi] = acc[i][j][e];
+        }
+      }
 }
 
 // One wavefront per entry of C, as k_colsum_final (the same order for C[a][b]
@@ -535,10 +601,6 @@ void build_index_t(Index& ix, const T* X) {
   // scratch: partials, flags, Gram, power-iteration work
   const int g1 = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 2047) / 2048));
   const int64_t rpb1 = (n + g1 - 1) / g1;
-  int ts = 1;
-  while (ts < 8 && (d + ts - 1) / ts > 16) ts *= 2;
-  const int tiles_1d = (d + ts - 1) / ts;
-  const int gy = (tiles_1d * tiles_1d + kThreads - 1) / kThreads;
   int64_t dd = (int64_t)d * d;
   // about 512 rows per workgroup and up to 8 workgroups per CU: with fewer,
   // larger blocks the staging rounds of the rows are latency-bound
@@ -572,12 +634,20 @@ void build_index_t(Index& ix, const T* X) {
   SNN_LAUNCH_CHECK();
 
   const size_t lds2 = sizeof(double) * rows_chunk * d;
-  dim3 grid2(g2, gy);
-  switch (ts) {
-    case 1: k_gram_partial<T, 1><<<grid2, kThreads, lds2, s>>>(X, n, d, ix.mu.as<double>(), rpb2, rows_chunk, part2); break;
-    case 2: k_gram_partial<T, 2><<<grid2, kThreads, lds2, s>>>(X, n, d, ix.mu.as<double>(), rpb2, rows_chunk, part2); break;
-    case 4: k_gram_partial<T, 4><<<grid2, kThreads, lds2, s>>>(X, n, d, ix.mu.as<double>(), rpb2, rows_chunk, part2); break;
-    default: k_gram_partial<T, 8><<<grid2, kThreads, lds2, s>>>(X, n, d, ix.mu.as<double>(), rpb2, rows_chunk, part2); break;
+  if (d >= kGramMfmaMinD) {
+    const int tb = d <= 16 ? 1 : d <= 32 ? 2 : d <= 48 ? 3 : 4;
+    const int nbk = (d + 16 * tb - 1) / (16 * tb), npairs = nbk * (nbk + 1) / 2;
+    const int w = std::min(npairs, kGramWaves);
+    const dim3 grid(g2, (npairs + w - 1) / w);
+    const double* mu = ix.mu.as<double>();
+    switch (tb) {
+      case 1: k_gram_mfma<T, 1><<<grid, w * kWave, 0, s>>>(X, n, d, mu, rpb2, npairs, part2); break;
+      case 2: k_gram_mfma<T, 2><<<grid, w * kWave, 0, s>>>(X, n, d, mu, rpb2, npairs, part2); break;
+      case 3: k_gram_mfma<T, 3><<<grid, w * kWave, 0, s>>>(X, n, d, mu, rpb2, npairs, part2); break;
+      default: k_gram_mfma<T, 4><<<grid, w * kWave, 0, s>>>(X, n, d, mu, rpb2, npairs, part2); break;
+    }
+  } else {
+    k_gram_partial<T><<<g2, kThreads, lds2, s>>>(X, n, d, ix.mu.as<double>(), rpb2, rows_chunk, part2);
   }
   SNN_LAUNCH_CHECK();
   k_gram_final<<<grid_for(dd * kWave), kThreads, 0, s>>>(part2, g2, dd, C);
