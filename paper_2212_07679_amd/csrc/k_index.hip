@@ -34,7 +34,9 @@ __device__ __forceinline__ double ld(const T* p, int64_t i) {
 
 // ---- step 2: column sums ---------------------------------------------------
 // Thread layout: cols_per_pass = min(d, 256) consecutive columns, rows_per_pass
-// rows at once; each thread owns one column of a fixed row subset.
+// rows at once; each thread owns one column of a fixed row subset.  Partials
+// are stored column-major (part[c * nblocks + b]) so that the final pass
+// reads each column's partials contiguously.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_colsum_partial(const T* __restrict__ X, int64_t n, int d,
                                                             int64_t rows_per_block, double* __restrict__ part,
@@ -50,8 +52,20 @@ __global__ __launch_bounds__(kThreads) void k_colsum_partial(const T* __restrict
     const int roff = t / cpp, c = c0 + t % cpp;
     double s = 0.0;
     if (roff < rpp) {
-      for (int64_t r = r0 + roff; r < r1; r += rpp) {
-        double x = ld(X, r * d + c);
+      // eight independent loads in flight, added in row order
+      int64_t r = r0 + roff;
+      for (; r + 7 * rpp < r1; r += 8 * rpp) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = ld(X, (r + u * rpp) * d + c);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (!isfinite(x[u])) badloc = 1;
+          s += x[u];
+        }
+      }
+      for (; r < r1; r += rpp) {
+        const double x = ld(X, r * d + c);
         if (!isfinite(x)) badloc = 1;
         s += x;
       }
@@ -61,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void k_colsum_partial(const T* __restrict
     if (t < cpp) {
       double tot = 0.0;
       for (int k = 0; k < rpp; ++k) tot += red[k * cpp + t];
-      part[(int64_t)blockIdx.x * d + c0 + t] = tot;
+      part[(int64_t)(c0 + t) * gridDim.x + blockIdx.x] = tot;
     }
     __syncthreads();
   }
@@ -73,8 +87,17 @@ __global__ __launch_bounds__(kThreads) void k_colsum_partial(const T* __restrict
 __global__ __launch_bounds__(kWave) void k_colsum_final(const double* __restrict__ part, int nblocks, int d,
                                                        int64_t n, double* __restrict__ mu) {
   const int c = blockIdx.x;
+  const double* pc = part + (int64_t)c * nblocks;
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kWave) s += part[(int64_t)b * d + c];
+  int b = threadIdx.x;
+  for (; b + 7 * kWave < nblocks; b += 8 * kWave) {  // eight loads in flight, added in order
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = pc[b + u * kWave];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += x[u];
+  }
+  for (; b < nblocks; b += kWave) s += pc[b];
   s = wave_sum(s);
   if (threadIdx.x == 0) mu[c] = s / (double)n;
 }
@@ -200,24 +223,44 @@ __global__ __launch_bounds__(kGramWaves * kWave) void k_gram_mfma(const T* __res
       }
 }
 
-// One wavefront per entry of C, as k_colsum_final (the same order for C[a][b]
-// and C[b][a], whose partials are equal, so C stays exactly symmetric).
-__global__ __launch_bounds__(kThreads) void k_gram_final(const double* __restrict__ part, int nblocks, int64_t dd,
-                                                        double* __restrict__ C) {
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-  for (int64_t e = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; e < dd; e += waves) {
-    double s = 0.0;
-    for (int b = lane_id(); b < nblocks; b += kWave) s += part[(int64_t)b * dd + e];
-    s = wave_sum(s);
-    if (lane_id() == 0) C[e] = s;
+// Sum of the partial Gram matrices: a workgroup of kGramFinalWaves
+// wavefronts takes 64 consecutive entries (one per lane, coalesced); wave w
+// adds partials w, w + W, ... in order with eight loads in flight, and the W
+// wave sums meet in LDS in wave order.  C[a][b] and C[b][a] have equal
+// partials and the same order, so C stays exactly symmetric.
+constexpr int kGramFinalWaves = 16;
+
+__global__ __launch_bounds__(kGramFinalWaves * kWave) void k_gram_final(const double* __restrict__ part,
+                                                                       int nblocks, int64_t dd,
+                                                                       double* __restrict__ C) {
+  __shared__ double red[kGramFinalWaves][kWave];
+  const int w = threadIdx.x / kWave, l = lane_id();
+  const int64_t e = (int64_t)blockIdx.x * kWave + l;
+  double s = 0.0;
+  if (e < dd) {
+    int b = w;
+    for (; b + 7 * kGramFinalWaves < nblocks; b += 8 * kGramFinalWaves) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = part[(int64_t)(b + u * kGramFinalWaves) * dd + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += x[u];
+    }
+    for (; b < nblocks; b += kGramFinalWaves) s += part[(int64_t)b * dd + e];
+  }
+  red[w][l] = s;
+  __syncthreads();
+  if (w == 0 && e < dd) {
+    double t = 0.0;
+    for (int k = 0; k < kGramFinalWaves; ++k) t += red[k][l];
+    C[e] = t;
   }
 }
 
-// Power iteration v <- C v / ||C v|| in one workgroup of NT threads (one
-// wavefront for d <= 64, reductions by shuffles only; 1024 threads above):
-// thread i owns rows i, i + NT, ...; C is symmetric, so row i of C v is read
-// down column i (C[j][i], j = 0..d-1), one coalesced row of C per j across
-// the threads; v and C v stay in LDS.  Stops when the Rayleigh quotient
+// Power iteration v <- C v / ||C v|| in one workgroup of NT threads (the
+// general form, used for d > 128): thread i owns rows i, i + NT, ...; C is
+// symmetric, so row i of C v is read down column i (C[j][i], j = 0..d-1),
+// one coalesced row of C per j across the threads; v and C v stay in LDS.  Stops when the Rayleigh quotient
 // changes by less than 1e-12 relative (it converges at twice the rate of v)
 // or after max_iter.  The largest-magnitude entry is made positive; C = 0
 // gives e_1.
@@ -296,6 +339,75 @@ __global__ __launch_bounds__(NT) void k_power_iter(const double* __restrict__ C,
     for (int i = 0; i < d; ++i) ss += v[i] * v[i];
     double inv = 1.0 / sqrt(ss);
     for (int i = 0; i < d; ++i) v_out[i] = sgn * v[i] * inv;
+    *iters_out = it > max_iter ? max_iter : it;
+  }
+}
+
+// The same iteration for d <= DB <= 64 in one wavefront with no LDS traffic
+// or barriers in the loop: lane i holds row i of C (= column i) in registers
+// and v_i; v_j reaches every lane by a lane read, and the two sums of a step
+// are taken over lane reads in lane order, so every lane holds the same
+// value and the stopping test is uniform.
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <int DB>
+__device__ __forceinline__ double lanes_sum(double x) {
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < DB; ++j) s += readlane_f64(x, j);
+  return s;
+}
+
+template <int DB>
+__global__ __launch_bounds__(kWave) void k_power_iter_wave(const double* __restrict__ C, int d, int max_iter,
+                                                          double* __restrict__ v_out, int* __restrict__ iters_out) {
+  __shared__ double vs[kWave];
+  const int i = threadIdx.x;
+  double crow[DB];
+#pragma unroll
+  for (int j = 0; j < DB; ++j) crow[j] = (i < d && j < d) ? C[(int64_t)j * d + i] : 0.0;
+  // deterministic start: 1 + small distinct perturbation per coordinate
+  double vi = i < d ? 1.0 + 0.01 * (double)((i * 2654435761u) % 1000u) / 1000.0 : 0.0;
+  vi /= sqrt(lanes_sum<DB>(vi * vi));
+  double lambda_prev = -1.0;
+  int it = 0;
+  bool zero = false;
+  for (it = 1; it <= max_iter; ++it) {
+    double w = 0.0;
+#pragma unroll
+    for (int j = 0; j < DB; ++j) w += crow[j] * readlane_f64(vi, j);
+    const double lambda = lanes_sum<DB>(w * vi);  // Rayleigh quotient v^T C v
+    const double nw = sqrt(lanes_sum<DB>(w * w));
+    if (!(nw > 0.0)) {
+      zero = true;
+      break;
+    }
+    vi = w / nw;
+    if (fabs(lambda - lambda_prev) <= 1e-12 * fabs(lambda)) break;
+    lambda_prev = lambda;
+  }
+  vs[i] = vi;
+  __syncthreads();
+  if (i == 0) {
+    if (zero)
+      for (int k = 0; k < d; ++k) vs[k] = (k == 0) ? 1.0 : 0.0;
+    int im = 0;
+    double am = -1.0;
+    for (int k = 0; k < d; ++k)
+      if (fabs(vs[k]) > am) {
+        am = fabs(vs[k]);
+        im = k;
+      }
+    const double sgn = vs[im] < 0 ? -1.0 : 1.0;
+    double ss = 0.0;
+    for (int k = 0; k < d; ++k) ss += vs[k] * vs[k];
+    const double inv = 1.0 / sqrt(ss);
+    for (int k = 0; k < d; ++k) v_out[k] = sgn * vs[k] * inv;
     *iters_out = it > max_iter ? max_iter : it;
   }
 }
@@ -409,53 +521,122 @@ bool power_iter_lds_ok(const DeviceInfo& di, int d) {
 }
 
 // ---- step 5: scores ----------------------------------------------------------
-// G lanes per row (coalesced row reads); the partial sums of a row meet by
-// shuffles within its G lanes, in a fixed order (deterministic).  Any order
-// stays within the gamma_{d+2} bound of the key error.
-template <typename T, int G>
+// Row kernels: G lanes per row (coalesced row reads), each lane taking
+// elements sub, sub + G, ... of the row, NE of them per pass; a group of G
+// lanes takes U rows at once (the projection: U = 8 / NE, so about eight
+// loads per lane are in flight; the gather, whose row reads are random and
+// whose occupancy matters more, U = 1).  The 64 / G groups of a wavefront take
+// consecutive rows in each of the U slots, so that one load or store
+// instruction covers one contiguous stretch of memory.  The mu and v entries
+// a lane needs sit in its registers when a row takes one pass (d <= NE G),
+// else in LDS (PM_LDS) or are read from memory.
+// The partial sums of a row meet by shuffles within its G lanes, in a fixed
+// order (deterministic); any order stays within the gamma_{d+2} bound of the
+// key error.
+enum ParamMode { PM_REG, PM_LDS, PM_MEM };
+
+template <typename T, int G, int NE, int U, int PM>
 __global__ __launch_bounds__(kThreads) void k_project(const T* __restrict__ X, int64_t n, int d,
                                                      const double* __restrict__ mu, const double* __restrict__ v,
                                                      uint32_t* __restrict__ ukey, uint32_t* __restrict__ val,
-                                                     double* __restrict__ max_norm) {
-  const int sub = threadIdx.x % G;
+                                                     double* __restrict__ block_max) {
+  extern __shared__ double prm[];  // PM_LDS: mu (d) | v (d)
+  const double* mup = mu;
+  const double* vp = v;
+  if (PM == PM_LDS) {
+    for (int k = threadIdx.x; k < d; k += kThreads) {
+      prm[k] = mu[k];
+      prm[d + k] = v[k];
+    }
+    __syncthreads();
+    mup = prm;
+    vp = prm + d;
+  }
+  constexpr int GW = kWave / G;  // groups per wavefront
+  const int sub = threadIdx.x % G, q = (threadIdx.x % kWave) / G;
+  double mur[NE], vr[NE];  // PM_REG: the lane's entries k = sub + j G
+#pragma unroll
+  for (int j = 0; j < NE; ++j) {
+    const int k = sub + j * G;
+    mur[j] = (PM == PM_REG && k < d) ? mu[k] : 0.0;
+    vr[j] = (PM == PM_REG && k < d) ? v[k] : 0.0;
+  }
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   double nmax = 0.0;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; i < n;
-       i += ((int64_t)gridDim.x * blockDim.x) / G) {
-    const T* p = X + i * d;
-    double a = 0.0, nn = 0.0;
-    for (int k = sub; k < d; k += G) {
-      const double x = (double)p[k] - mu[k];
-      a += x * v[k];
-      const double y = (double)(float)x;
-      nn += y * y;
+  for (int64_t base = wave * U * GW; base < n; base += nwaves * U * GW) {
+    const int64_t i0 = base + q;  // rows i0 + u GW
+    double a[U], nn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] = nn[u] = 0.0;
+    for (int kc = 0; kc < d; kc += NE * G) {
+      T xv[U][NE];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+          const int k = kc + sub + j * G;
+          xv[u][j] = (i0 + u * GW < n && k < d) ? X[(i0 + u * GW) * d + k] : T(0);
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+          const int k = kc + sub + j * G;
+          if (k < d) {
+            const double x = (double)xv[u][j] - (PM == PM_REG ? mur[j] : mup[k]);
+            a[u] += x * (PM == PM_REG ? vr[j] : vp[k]);
+            const double y = (double)(float)x;
+            nn[u] += y * y;
+          }
+        }
     }
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) {
-      a += __shfl_xor(a, off, G);
-      nn += __shfl_xor(nn, off, G);
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) {
+        a[u] += __shfl_xor(a[u], off, G);
+        nn[u] += __shfl_xor(nn[u], off, G);
+      }
+      if (sub == 0 && i0 + u * GW < n) {
+        ukey[i0 + u * GW] = float_to_ordered((float)a[u]);
+        val[i0 + u * GW] = (uint32_t)(i0 + u * GW);
+      }
+      nmax = fmax(nmax, nn[u]);
     }
-    if (sub == 0) {
-      ukey[i] = float_to_ordered((float)a);
-      val[i] = (uint32_t)i;
-    }
-    nmax = fmax(nmax, nn);
   }
-  // one atomic per workgroup (the address is the same for all of them)
+  // one maximum per workgroup, folded by k_max_final (atomics on a single
+  // address serialise: thousands of them cost more than the whole pass)
   __shared__ double red[kThreads / kWave];
   nmax = wave_max(nmax);
   if (lane_id() == 0) red[threadIdx.x / kWave] = nmax;
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < kThreads / kWave; ++w) nmax = fmax(nmax, red[w]);
-    atomic_max_nonneg(max_norm, nmax);
+    block_max[blockIdx.x] = nmax;
+  }
+}
+
+// *max_norm = max(*max_norm, block_max[0 .. nblocks)) in one workgroup
+__global__ __launch_bounds__(kThreads) void k_max_final(const double* __restrict__ block_max, int nblocks,
+                                                       double* __restrict__ max_norm) {
+  __shared__ double red[kThreads / kWave];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kThreads) m = fmax(m, block_max[b]);
+  m = wave_max(m);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kThreads / kWave; ++w) m = fmax(m, red[w]);
+    *max_norm = fmax(*max_norm, m);
   }
 }
 
 // ---- gather into score order -------------------------------------------------
-// G lanes per row: the source row (a random row of X) and every destination
-// row are read and written G consecutive elements at a time; the row's
-// squared norm meets by shuffles within its G lanes.
-template <typename T, int G>
+// Same lane layout: a group gathers U consecutive destination rows (random
+// source rows of X), G consecutive elements at a time; the squared norm of
+// each row meets by shuffles within its G lanes.
+template <typename T, int G, int NE, int U, int PM>
 __global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, int64_t n, int d, int dp,
                                                     const double* __restrict__ mu,
                                                     const uint32_t* __restrict__ ukey,
@@ -464,56 +645,125 @@ __global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, in
                                                     double* __restrict__ p64, float* __restrict__ ys,
                                                     float* __restrict__ h, float* __restrict__ ynorm,
                                                     int64_t id_base) {
+  extern __shared__ double prm[];  // PM_LDS: mu (d)
+  const double* mup = mu;
+  if (PM == PM_LDS) {
+    for (int k = threadIdx.x; k < d; k += kThreads) prm[k] = mu[k];
+    __syncthreads();
+    mup = prm;
+  }
+  double mur[NE];  // PM_REG: the lane's entries k = sub + j G
+#pragma unroll
+  for (int j = 0; j < NE; ++j) {
+    const int k = threadIdx.x % G + j * G;
+    mur[j] = (PM == PM_REG && k < d) ? mu[k] : 0.0;
+  }
   if (blockIdx.x == 0 && threadIdx.x < 64) h[n + threadIdx.x] = INFINITY;  // padding rows
-  const int sub = threadIdx.x % G;
-  for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; s < n;
-       s += ((int64_t)gridDim.x * blockDim.x) / G) {
-    const uint32_t i = val[s];
-    const T* p = X + (int64_t)i * d;
-    double nn = 0.0;
-    for (int k = sub; k < dp; k += G) {
-      if (k < d) {
-        const T x = p[k];
-        po[s * d + k] = x;
-        p64[s * dp + k] = (double)x;
-        const float y = (float)((double)x - mu[k]);
-        ys[s * d + k] = y;
-        nn += (double)y * (double)y;
-      } else {
-        p64[s * dp + k] = 0.0;
-      }
+  constexpr int GW = kWave / G;  // groups per wavefront
+  const int sub = threadIdx.x % G, q = (threadIdx.x % kWave) / G;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t base = wave * U * GW; base < n; base += nwaves * U * GW) {
+    const int64_t s0 = base + q;  // destination rows s0 + u GW
+    uint32_t src[U];
+    double nn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      src[u] = s0 + u * GW < n ? val[s0 + u * GW] : 0u;
+      nn[u] = 0.0;
+    }
+    for (int kc = 0; kc < dp; kc += NE * G) {
+      T xv[U][NE];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+          const int k = kc + sub + j * G;
+          xv[u][j] = (s0 + u * GW < n && k < d) ? X[(int64_t)src[u] * d + k] : T(0);
+        }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+          const int64_t s = s0 + u * GW;
+          const int k = kc + sub + j * G;
+          if (s < n && k < dp) {
+            if (k < d) {
+              const T x = xv[u][j];
+              po[s * d + k] = x;
+              p64[s * dp + k] = (double)x;
+              const float y = (float)((double)x - (PM == PM_REG ? mur[j] : mup[k]));
+              ys[s * d + k] = y;
+              nn[u] += (double)y * (double)y;
+            } else {
+              p64[s * dp + k] = 0.0;
+            }
+          }
+        }
     }
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) nn += __shfl_xor(nn, off, G);
-    if (sub == 0) {
-      perm[s] = (int32_t)(id_base + i);
-      key[s] = (double)ordered_to_float(ukey[s]);
-      h[s] = (float)(0.5 * nn);
-      // round ||y|| up to float so it bounds the true norm
-      float nr = (float)sqrt(nn);
-      if ((double)nr < sqrt(nn)) nr = nextafterf(nr, INFINITY);
-      ynorm[s] = nr;
+    for (int u = 0; u < U; ++u) {
+      const int64_t s = s0 + u * GW;
+#pragma unroll
+      for (int off = G / 2; off > 0; off >>= 1) nn[u] += __shfl_xor(nn[u], off, G);
+      if (sub == 0 && s < n) {
+        perm[s] = (int32_t)(id_base + src[u]);
+        key[s] = (double)ordered_to_float(ukey[s]);
+        h[s] = (float)(0.5 * nn[u]);
+        // round ||y|| up to float so it bounds the true norm
+        float nr = (float)sqrt(nn[u]);
+        if ((double)nr < sqrt(nn[u])) nr = nextafterf(nr, INFINITY);
+        ynorm[s] = nr;
+      }
     }
   }
 }
 
 int grid_for(int64_t work, int per_block, int cap);
 
-// lanes per row of the row kernels: enough to read a row in one or two
-// steps, at most 16
-inline int row_lanes(int d) { return d <= 4 ? 4 : (d <= 8 ? 8 : 16); }
+// Lanes per row G of the row kernels (enough to read a short row in one
+// step, at most 16) and elements per lane per pass NE (a power of two, at
+// most 8; rows wider than 8 G take several passes).  f is called with both as
+// integral constants.
+template <typename F>
+void row_shape(int width, F&& f) {
+  using std::integral_constant;
+  if (width <= 4)
+    f(integral_constant<int, 4>{}, integral_constant<int, 1>{});
+  else if (width <= 8)
+    f(integral_constant<int, 8>{}, integral_constant<int, 1>{});
+  else if (width <= 16)
+    f(integral_constant<int, 16>{}, integral_constant<int, 1>{});
+  else if (width <= 32)
+    f(integral_constant<int, 16>{}, integral_constant<int, 2>{});
+  else if (width <= 64)
+    f(integral_constant<int, 16>{}, integral_constant<int, 4>{});
+  else
+    f(integral_constant<int, 16>{}, integral_constant<int, 8>{});
+}
 
+// mu (and v) are staged in LDS up to this width
+constexpr int kRowParamLds = 2048;
+
+// block_max: cap doubles of scratch; *max_norm is raised to the largest
+// squared norm of fl32(x - mu) over the rows
 template <typename T>
 void launch_project(const T* X, int64_t n, int d, const double* mu, const double* v, uint32_t* ukey, uint32_t* val,
-                    double* max_norm, int cap, hipStream_t s) {
-  const int G = row_lanes(d);
-  const int grid = grid_for(n * G, kThreads, cap);
-  if (G == 4)
-    k_project<T, 4><<<grid, kThreads, 0, s>>>(X, n, d, mu, v, ukey, val, max_norm);
-  else if (G == 8)
-    k_project<T, 8><<<grid, kThreads, 0, s>>>(X, n, d, mu, v, ukey, val, max_norm);
-  else
-    k_project<T, 16><<<grid, kThreads, 0, s>>>(X, n, d, mu, v, ukey, val, max_norm);
+                    double* block_max, double* max_norm, int cap, hipStream_t s) {
+  int grid = 1;
+  row_shape(d, [&](auto g, auto ne) {
+    constexpr int G = decltype(g)::value, NE = decltype(ne)::value, U = NE >= 8 ? 1 : 8 / NE;
+    grid = grid_for((std::max<int64_t>(n, 1) + U - 1) / U * G, kThreads, cap);
+    if (d <= NE * G)
+      k_project<T, G, NE, U, PM_REG><<<grid, kThreads, 0, s>>>(X, n, d, mu, v, ukey, val, block_max);
+    else if (d <= kRowParamLds)
+      k_project<T, G, NE, U, PM_LDS><<<grid, kThreads, 2 * sizeof(double) * d, s>>>(X, n, d, mu, v, ukey, val,
+                                                                                   block_max);
+    else
+      k_project<T, G, NE, U, PM_MEM><<<grid, kThreads, 0, s>>>(X, n, d, mu, v, ukey, val, block_max);
+  });
+  SNN_LAUNCH_CHECK();
+  k_max_final<<<1, kThreads, 0, s>>>(block_max, grid, max_norm);
   SNN_LAUNCH_CHECK();
 }
 
@@ -521,15 +771,19 @@ template <typename T>
 void launch_gather(const T* X, int64_t n, int d, int dp, const double* mu, const uint32_t* ukey, const uint32_t* val,
                    double* key, int32_t* perm, T* po, double* p64, float* ys, float* h, float* ynorm, int64_t id_base,
                    int cap, hipStream_t s) {
-  const int G = row_lanes(d);
-  const int grid = grid_for(std::max<int64_t>(n, 1) * G, kThreads, cap);
-  if (G == 4)
-    k_gather<T, 4><<<grid, kThreads, 0, s>>>(X, n, d, dp, mu, ukey, val, key, perm, po, p64, ys, h, ynorm, id_base);
-  else if (G == 8)
-    k_gather<T, 8><<<grid, kThreads, 0, s>>>(X, n, d, dp, mu, ukey, val, key, perm, po, p64, ys, h, ynorm, id_base);
-  else
-    k_gather<T, 16><<<grid, kThreads, 0, s>>>(X, n, d, dp, mu, ukey, val, key, perm, po, p64, ys, h, ynorm,
-                                              id_base);
+  row_shape(dp, [&](auto g, auto ne) {
+    constexpr int G = decltype(g)::value, NE = decltype(ne)::value;
+    const int grid = grid_for(std::max<int64_t>(n, 1) * G, kThreads, cap);
+    if (dp <= NE * G)
+      k_gather<T, G, NE, 1, PM_REG><<<grid, kThreads, 0, s>>>(X, n, d, dp, mu, ukey, val, key, perm, po, p64, ys, h,
+                                                           ynorm, id_base);
+    else if (d <= kRowParamLds)
+      k_gather<T, G, NE, 1, PM_LDS><<<grid, kThreads, sizeof(double) * d, s>>>(X, n, d, dp, mu, ukey, val, key, perm,
+                                                                          po, p64, ys, h, ynorm, id_base);
+    else
+      k_gather<T, G, NE, 1, PM_MEM><<<grid, kThreads, 0, s>>>(X, n, d, dp, mu, ukey, val, key, perm, po, p64, ys, h,
+                                                           ynorm, id_base);
+  });
   SNN_LAUNCH_CHECK();
 }
 
@@ -599,7 +853,9 @@ void build_index_t(Index& ix, const T* X) {
   ix.ynorm.ensure(ix.arena, sizeof(float) * n);
 
   // scratch: partials, flags, Gram, power-iteration work
-  const int g1 = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 2047) / 2048));
+  // at least 16 elements per thread (4096 per workgroup) keep enough loads
+  // in flight; at most 4096 workgroups
+  const int g1 = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n * d + 4095) / 4096));
   const int64_t rpb1 = (n + g1 - 1) / g1;
   int64_t dd = (int64_t)d * d;
   // about 512 rows per workgroup and up to 8 workgroups per CU: with fewer,
@@ -617,13 +873,16 @@ void build_index_t(Index& ix, const T* X) {
   const size_t off_part1 = 256;
   const size_t off_part2 = off_part1 + ((sizeof(double) * g1 * d + 255) & ~size_t(255));
   const size_t off_C = off_part2 + ((sizeof(double) * g2 * dd + 255) & ~size_t(255));
-  const size_t off_keys = off_C + ((sizeof(double) * dd + 255) & ~size_t(255));
+  const int proj_cap = 4 * di.cus * 8;
+  const size_t off_bmax = off_C + ((sizeof(double) * dd + 255) & ~size_t(255));
+  const size_t off_keys = off_bmax + ((sizeof(double) * proj_cap + 255) & ~size_t(255));
   const size_t total = off_keys + 2 * sizeof(uint32_t) * n + 256;
   char* mem = static_cast<char*>(ix.arena.alloc(total));
   Scratch* sc = reinterpret_cast<Scratch*>(mem);
   double* part1 = reinterpret_cast<double*>(mem + off_part1);
   double* part2 = reinterpret_cast<double*>(mem + off_part2);
   double* C = reinterpret_cast<double*>(mem + off_C);
+  double* bmax = reinterpret_cast<double*>(mem + off_bmax);
   uint32_t* ukey = reinterpret_cast<uint32_t*>(mem + off_keys);
   uint32_t* val = ukey + n;
 
@@ -650,16 +909,22 @@ void build_index_t(Index& ix, const T* X) {
     k_gram_partial<T><<<g2, kThreads, lds2, s>>>(X, n, d, ix.mu.as<double>(), rpb2, rows_chunk, part2);
   }
   SNN_LAUNCH_CHECK();
-  k_gram_final<<<grid_for(dd * kWave), kThreads, 0, s>>>(part2, g2, dd, C);
+  k_gram_final<<<(int)((dd + kWave - 1) / kWave), kGramFinalWaves * kWave, 0, s>>>(part2, g2, dd, C);
   SNN_LAUNCH_CHECK();
-  if (d <= kWave)
-    k_power_iter<kWave><<<1, kWave, 2 * sizeof(double) * d, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
+  if (d <= 8)
+    k_power_iter_wave<8><<<1, kWave, 0, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
+  else if (d <= 16)
+    k_power_iter_wave<16><<<1, kWave, 0, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
+  else if (d <= 32)
+    k_power_iter_wave<32><<<1, kWave, 0, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
+  else if (d <= kWave)
+    k_power_iter_wave<64><<<1, kWave, 0, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
   else if (d <= kPiSlots && power_iter_lds_ok(di, d))
     k_power_iter_lds<<<1, kPiThreads, power_iter_lds_bytes(d), s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
   else
     k_power_iter<1024><<<1, 1024, 2 * sizeof(double) * d, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
   SNN_LAUNCH_CHECK();
-  launch_project<T>(X, n, d, ix.mu.as<double>(), ix.v.as<double>(), ukey, val, &sc->max_norm, 4 * di.cus * 8, s);
+  launch_project<T>(X, n, d, ix.mu.as<double>(), ix.v.as<double>(), ukey, val, bmax, &sc->max_norm, proj_cap, s);
   radix_sort_pairs(ix.arena, ukey, val, n, 0, 32, s);
   T* po = ix.po.as<T>();
   double* p64 = ix.p64.as<double>();
@@ -778,6 +1043,7 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   sz.take<float>(k + 64);             // h
   sz.take<float>(k);                  // ynorm
   sz.take<int64_t>(nt);               // merge sources
+  sz.take<double>(4 * di.cus * 8);    // per-workgroup norm maxima
   void* mem = ix.arena.alloc(sz.off);
   struct Release {
     DeviceArena& a;
@@ -796,12 +1062,13 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   float* hb = c.take<float>(k + 64);
   float* ynb = c.take<float>(k);
   int64_t* src = c.take<int64_t>(nt);
+  double* bmax = c.take<double>(4 * di.cus * 8);
 
   SNN_HIP(hipMemsetAsync(sc, 0, sizeof(Scratch), s));
   const int cap = 4 * di.cus * 8;
   k_check_finite<T><<<grid_for(k * d, kThreads, cap), kThreads, 0, s>>>(Xn, k * d, &sc->bad);
   SNN_LAUNCH_CHECK();
-  launch_project<T>(Xn, k, d, ix.mu.as<double>(), ix.v.as<double>(), ukey, val, &sc->max_norm, cap, s);
+  launch_project<T>(Xn, k, d, ix.mu.as<double>(), ix.v.as<double>(), ukey, val, bmax, &sc->max_norm, cap, s);
   radix_sort_pairs(ix.arena, ukey, val, k, 0, 32, s);
   launch_gather<T>(Xn, k, d, dp, ix.mu.as<double>(), ukey, val, keyb, permb, pob, p64b, ysb, hb, ynb, na, cap, s);
   Scratch hs;
