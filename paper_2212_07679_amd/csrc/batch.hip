@@ -105,6 +105,7 @@ struct BatchPlan {
   float* cthr = nullptr;
   int32_t *tlo = nullptr, *thi = nullptr, *units = nullptr;
   int64_t* group_off = nullptr;
+  int32_t* gbase = nullptr;
   void* scan_ws = nullptr;
   BatchCtl* ctl = nullptr;
   int32_t* row_cnt = nullptr;  // per query slot
@@ -285,6 +286,7 @@ void alloc_query(BatchPlan& p) {
     p.thi = c.take<int32_t>(nt);
     p.units = c.take<int32_t>(nt);
     p.group_off = c.take<int64_t>(nt + 1);
+    p.gbase = c.take<int32_t>(nt);
     p.scan_ws = c.take<char>(std::max(scan_scratch_bytes(nt + 1), scan_scratch_bytes(MS + 1)));
     p.ctl = c.take<BatchCtl>(1);
     p.row_cnt = c.take<int32_t>(MS);
@@ -376,7 +378,7 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
                      p.cthr, s);
   batch_windows(b, p.key, p.qa, p.qn, p.qorig, p.tlo, p.thi, p.ctl, s);
   const int ngroups = (p.ntiles + p.G - 1) / p.G;
-  launch_tile_plan(p.tlo, p.thi, p.ntiles, p.CH, 32, 0, p.units, p.G, p.group_off, p.T, p.MS, 1, nullptr, s);
+  launch_tile_plan(p.tlo, p.thi, p.ntiles, p.CH, 32, 0, p.units, p.G, p.group_off, p.gbase, p.T, p.MS, 1, nullptr, s);
   batch_executed(b, p.tlo, p.thi, p.T / 4, p.ctl, s);
 
   QueryDev qd{};
@@ -390,6 +392,7 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   qd.thi = p.thi;
   qd.units = p.units;
   qd.group_off = p.group_off;
+  qd.gbase = p.gbase;
   qd.counters = p.ctl->counters;
   qd.nxcd = di.xcds;
   qd.sink.out = p.sv.pairs;

@@ -44,12 +44,10 @@ __global__ __launch_bounds__(kThreads) void k_cand_fp64_reg(QueryDev q) {
     const int64_t u = uniform_i64(s_unit);
     if (u < 0) break;
     int tile;
-    int64_t c;
-    if (!decode_unit(q, u, tile, c)) continue;
+    int64_t j0, j1;
+    if (!decode_unit(q, u, tile, j0, j1)) continue;
     const int64_t q0 = (int64_t)tile * q.T;
     const int qn = (int)min((int64_t)q.T, q.m - q0);
-    const int64_t j0 = q.tlo[tile] + c * q.CH;
-    const int64_t j1 = min(j0 + q.CH, (int64_t)q.thi[tile]);
     for (int64_t jb = j0; jb < j1; jb += kThreads) {
       const int64_t jr = jb + threadIdx.x;
       const bool valid = jr < j1;
@@ -90,12 +88,10 @@ __global__ __launch_bounds__(kThreads) void k_cand_fp64_big(QueryDev q, int dp) 
     const int64_t u = uniform_i64(s_unit);
     if (u < 0) break;
     int tile;
-    int64_t c;
-    if (!decode_unit(q, u, tile, c)) continue;
+    int64_t j0, j1;
+    if (!decode_unit(q, u, tile, j0, j1)) continue;
     const int64_t q0 = (int64_t)tile * q.T;
     const int qn = (int)min((int64_t)q.T, q.m - q0);
-    const int64_t j0 = q.tlo[tile] + c * q.CH;
-    const int64_t j1 = min(j0 + q.CH, (int64_t)q.thi[tile]);
     for (int64_t jb = j0; jb < j1; jb += kThreads) {
       const int64_t jr = jb + threadIdx.x;
       const bool valid = jr < j1;

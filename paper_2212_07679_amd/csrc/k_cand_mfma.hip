@@ -234,11 +234,9 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
     const int64_t u = uniform_i64(s_unit);
     if (u < 0) break;
     int tile;
-    int64_t c;
-    if (!decode_unit(q, u, tile, c)) continue;
+    int64_t j0, j1;
+    if (!decode_unit(q, u, tile, j0, j1)) continue;
     const int64_t q0 = (int64_t)tile * q.T + (int64_t)wave * 32 * QB;
-    const int64_t j0 = q.tlo[tile] + c * q.CH;
-    const int64_t j1 = min(j0 + q.CH, (int64_t)q.thi[tile]);
     if (q0 >= q.m) continue;  // this wave has no queries in the (ragged) last tile
     // padding query slots (start value -inf) only occur after the real
     // queries of a tile: a wave whose first slot is padding has no work
@@ -318,11 +316,9 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma32(QueryDev q, Mfma32Dev 
     const int64_t u = uniform_i64(s_unit);
     if (u < 0) break;
     int tile;
-    int64_t c;
-    if (!decode_unit(q, u, tile, c)) continue;
+    int64_t j0, j1;
+    if (!decode_unit(q, u, tile, j0, j1)) continue;
     const int64_t q0 = (int64_t)tile * q.T + (int64_t)wave * 32 * QB;
-    const int64_t j0 = q.tlo[tile] + c * q.CH;
-    const int64_t j1 = min(j0 + q.CH, (int64_t)q.thi[tile]);
     if (q0 >= q.m) continue;  // this wave has no queries in the (ragged) last tile
 
     float A[QB][NK];

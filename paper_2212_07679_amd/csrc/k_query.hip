@@ -181,10 +181,12 @@ __global__ __launch_bounds__(kThreads) void k_query_init(unsigned long long* __r
 // self-queries start a tile at its own first row), count its work units,
 // add the evaluated pairs (stats), reserve G x max units per group of G
 // tiles, and scan the groups into unit offsets (unit_off[ngroups] = total).
+constexpr int kAbsChunks = 8;
+
 __global__ __launch_bounds__(1024) void k_tile_plan(int32_t* __restrict__ tlo, int32_t* __restrict__ thi, int ntiles,
                                                    int CH, int align, int sym_T, int32_t* __restrict__ units, int G,
-                                                   int64_t* __restrict__ unit_off, int T, int64_t m, int qpw,
-                                                   unsigned long long* __restrict__ executed) {
+                                                   int64_t* __restrict__ unit_off, int32_t* __restrict__ gbase, int T,
+                                                   int64_t m, int qpw, unsigned long long* __restrict__ executed) {
   __shared__ int64_t carry;
   __shared__ int64_t wsum[1024 / kWave];
   unsigned long long e = 0;
@@ -221,9 +223,25 @@ __global__ __launch_bounds__(1024) void k_tile_plan(int32_t* __restrict__ tlo, i
     int64_t v = 0;
     if (g < ngroups) {
       const int t0 = g * G, t1 = min(ntiles, t0 + G);
-      int mx = 0;
-      for (int t = t0; t < t1; ++t) mx = max(mx, units[t]);
-      v = (int64_t)mx * (t1 - t0);
+      // absolute chunks when the windows average at least kAbsChunks
+      // chunks (then the chunks cut at window ends cost little)
+      int b0 = INT_MAX, b1 = 0, mx = 0, nt = 0;
+      int64_t len = 0;
+      for (int t = t0; t < t1; ++t)
+        if (units[t] > 0) {
+          b0 = min(b0, tlo[t] / CH);
+          b1 = max(b1, (thi[t] - 1) / CH + 1);
+          mx = max(mx, units[t]);
+          len += thi[t] - tlo[t];
+          ++nt;
+        }
+      if (nt > 0 && len >= (int64_t)kAbsChunks * CH * nt) {
+        gbase[g] = b0;
+        v = (int64_t)(b1 - b0) * (t1 - t0);
+      } else {
+        gbase[g] = -1;
+        v = (int64_t)mx * (t1 - t0);
+      }
     }
     // exclusive scan of v over the block, offset by the running carry
     int64_t x = v;
@@ -304,8 +322,10 @@ void launch_windows(const double* key, int n, const double* qalpha, const double
 }
 
 void launch_tile_plan(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int sym, int32_t* units, int G,
-                      int64_t* unit_off, int T, int64_t m, int qpw, unsigned long long* executed, hipStream_t s) {
-  k_tile_plan<<<1, 1024, 0, s>>>(tlo, thi, ntiles, CH, align, sym ? T : 0, units, G, unit_off, T, m, qpw, executed);
+                      int64_t* unit_off, int32_t* gbase, int T, int64_t m, int qpw, unsigned long long* executed,
+                      hipStream_t s) {
+  k_tile_plan<<<1, 1024, 0, s>>>(tlo, thi, ntiles, CH, align, sym ? T : 0, units, G, unit_off, gbase, T, m, qpw,
+                                 executed);
   SNN_LAUNCH_CHECK();
 }
 

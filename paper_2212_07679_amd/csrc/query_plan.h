@@ -14,16 +14,22 @@ namespace snn {
 constexpr int kMaxXcd = 8;
 
 // Tile t holds score-ordered queries [t*T, min((t+1)*T, m)) and the union
-// window [tlo[t], thi[t]); chunk c of the tile is the candidates
-// [tlo + c*CH, min(tlo + (c+1)*CH, thi)), units[t] chunks in all.
+// window [tlo[t], thi[t]), cut into chunks of at most CH candidates.
 //
 // Work units are ordered chunk-major inside groups of G consecutive tiles:
 // unit u of group g (group_off[g] <= u < group_off[g+1]) is chunk
-// c = l / Gg of tile t = g*G + l % Gg, with l = u - group_off[g] and Gg the
+// k = l / Gg of tile t = g*G + l % Gg, with l = u - group_off[g] and Gg the
 // tiles in the group.  Score-adjacent tiles have nearly the same window, so
 // the units that run at the same time on one XCD read the same candidate
-// rows from its L2.  A group reserves (max units of its tiles) x Gg units;
-// (t, c) with c >= units[t] is empty.
+// rows from its L2.  Two kinds of group:
+//  * long windows (gbase[g] >= 0): chunk k is the absolute range
+//    [B*CH, (B+1)*CH), B = gbase[g] + k, clipped to the tile's window, so
+//    all tiles of the group read it at the same addresses; the group
+//    reserves its chunk span x Gg units;
+//  * short windows (gbase[g] = -1): chunk k is [tlo + k*CH, tlo + (k+1)*CH)
+//    clipped to the window (units[t] chunks), which does not cut a short
+//    window in two; the group reserves (max units[t]) x Gg units.
+// A unit whose chunk misses its tile's window is empty.
 struct QueryDev {
   int64_t m;
   int d;
@@ -44,6 +50,7 @@ struct QueryDev {
   const int32_t* thi;    // ntiles
   const int32_t* units;          // ntiles
   const int64_t* group_off;      // ngroups + 1
+  const int32_t* gbase;          // ngroups: first absolute chunk, or -1
   unsigned long long* counters;  // kMaxXcd work counters (zeroed per call)
   int nxcd;
   // Symmetric self-query: query position s is data position s, tiles scan
@@ -75,9 +82,9 @@ __device__ __forceinline__ int64_t next_unit(const QueryDev& q, int xcd) {
   return -1;
 }
 
-// (tile, chunk) of unit u; false for an empty unit.  Results are
-// wavefront-uniform.
-__device__ __forceinline__ bool decode_unit(const QueryDev& q, int64_t u, int& tile, int64_t& chunk) {
+// Tile and candidate range [j0, j1) of unit u; false for an empty unit.
+// Results are wavefront-uniform.
+__device__ __forceinline__ bool decode_unit(const QueryDev& q, int64_t u, int& tile, int64_t& j0, int64_t& j1) {
   int lo = 0, hi = q.ngroups - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -88,9 +95,19 @@ __device__ __forceinline__ bool decode_unit(const QueryDev& q, int64_t u, int& t
   }
   const int gg = min(q.G, q.ntiles - lo * q.G);
   const int64_t l = u - q.group_off[lo];
-  chunk = uniform_i64(l / gg);
+  const int64_t k = uniform_i64(l / gg);
+  const int gb = uniform_i32(q.gbase[lo]);
   tile = uniform_i32(lo * q.G + (int)(l % gg));
-  return chunk < q.units[tile];
+  if (gb < 0) {
+    if (k >= q.units[tile]) return false;
+    j0 = uniform_i64((int64_t)q.tlo[tile] + k * q.CH);
+    j1 = uniform_i64(min((int64_t)q.thi[tile], j0 + q.CH));
+  } else {
+    const int64_t B = gb + k;
+    j0 = uniform_i64(max((int64_t)q.tlo[tile], B * q.CH));
+    j1 = uniform_i64(min((int64_t)q.thi[tile], (B + 1) * q.CH));
+  }
+  return j0 < j1;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -117,7 +134,8 @@ void launch_query_init(unsigned long long* ctl, int ctl_words, int32_t* row_cnt,
 // unit_off (ngroups + 1 entries), evaluated pairs added to *executed
 // (nullable; qpw query slots per wavefront)
 void launch_tile_plan(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int sym, int32_t* units, int G,
-                      int64_t* unit_off, int T, int64_t m, int qpw, unsigned long long* executed, hipStream_t s);
+                      int64_t* unit_off, int32_t* gbase, int T, int64_t m, int qpw, unsigned long long* executed,
+                      hipStream_t s);
 
 
 // k_cand_fp64.hip: plain float64 screen (every window pair, normative rule)

@@ -282,6 +282,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       int32_t* thi;
       int32_t* units;
       int64_t* unit_off;
+      int32_t* gbase;
       char* scan_scratch;
       Ctl* ctl;
       int32_t* row_cnt;  // per query slot
@@ -308,6 +309,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     p.thi = c.take<int32_t>(ntiles);
     p.units = c.take<int32_t>(ntiles);
     p.unit_off = c.take<int64_t>(ntiles + 1);
+    p.gbase = c.take<int32_t>(ntiles);
     p.scan_scratch = c.take<char>(std::max({scan_scratch_bytes(ntiles), scan_scratch_bytes(std::max<int64_t>(m, 1)),
                                             scan_scratch_bytes(nbuckets)}));
     p.ctl = c.take<Ctl>(1);
@@ -371,8 +373,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   // chunk-major work order inside groups of G score-adjacent tiles (L2 reuse)
   const int G = prec == SNN_PREC_FP64 ? 16 : 8;
   const int ngroups = (ntiles + G - 1) / G;
-  launch_tile_plan(P.tlo, P.thi, ntiles, CH, prec == SNN_PREC_FP64 ? 1 : 32, sym, P.units, G, P.unit_off, T, m, qpw,
-                   st ? &P.ctl->executed : nullptr, s);
+  launch_tile_plan(P.tlo, P.thi, ntiles, CH, prec == SNN_PREC_FP64 ? 1 : 32, sym, P.units, G, P.unit_off, P.gbase,
+                   T, m, qpw, st ? &P.ctl->executed : nullptr, s);
 
   QueryDev qd{};
   qd.G = G;
@@ -394,6 +396,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   qd.tlo = P.tlo;
   qd.thi = P.thi;
   qd.group_off = P.unit_off;
+  qd.gbase = P.gbase;
   qd.counters = P.ctl->counters;
   qd.nxcd = di.xcds;
   qd.sym = sym;
