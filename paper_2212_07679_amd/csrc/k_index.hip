@@ -617,17 +617,28 @@ __global__ __launch_bounds__(kThreads) void k_project(const T* __restrict__ X, i
   }
 }
 
-// *max_norm = max(*max_norm, block_max[0 .. nblocks)) in one workgroup
-__global__ __launch_bounds__(kThreads) void k_max_final(const double* __restrict__ block_max, int nblocks,
-                                                       double* __restrict__ max_norm) {
-  __shared__ double red[kThreads / kWave];
+// *max_norm = max(*max_norm, block_max[0 .. nblocks)) in one workgroup of
+// kMaxFinalThreads, eight loads in flight per thread
+constexpr int kMaxFinalThreads = 1024;
+
+__global__ __launch_bounds__(kMaxFinalThreads) void k_max_final(const double* __restrict__ block_max, int nblocks,
+                                                                double* __restrict__ max_norm) {
+  __shared__ double red[kMaxFinalThreads / kWave];
   double m = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kThreads) m = fmax(m, block_max[b]);
+  int b = threadIdx.x;
+  for (; b + 7 * kMaxFinalThreads < nblocks; b += 8 * kMaxFinalThreads) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = block_max[b + u * kMaxFinalThreads];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m = fmax(m, x[u]);
+  }
+  for (; b < nblocks; b += kMaxFinalThreads) m = fmax(m, block_max[b]);
   m = wave_max(m);
   if (lane_id() == 0) red[threadIdx.x / kWave] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 0; w < kThreads / kWave; ++w) m = fmax(m, red[w]);
+    for (int w = 0; w < kMaxFinalThreads / kWave; ++w) m = fmax(m, red[w]);
     *max_norm = fmax(*max_norm, m);
   }
 }
@@ -763,7 +774,7 @@ void launch_project(const T* X, int64_t n, int d, const double* mu, const double
       k_project<T, G, NE, U, PM_MEM><<<grid, kThreads, 0, s>>>(X, n, d, mu, v, ukey, val, block_max);
   });
   SNN_LAUNCH_CHECK();
-  k_max_final<<<1, kThreads, 0, s>>>(block_max, grid, max_norm);
+  k_max_final<<<1, kMaxFinalThreads, 0, s>>>(block_max, grid, max_norm);
   SNN_LAUNCH_CHECK();
 }
 
