@@ -148,12 +148,31 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_sums(const TI* __restrict
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-// out[i] = offsets[block] + exclusive prefix within the tile; if `write_total`
-// the thread owning element n-1 also writes out[n].
+// out[i] = offset of the block + exclusive prefix within the tile; if
+// `write_total` the thread owning element n-1 also writes out[n].  The
+// block's offset is offsets[block] (scanned block sums), or, with
+// `raw_sums`, the sum of offsets[0 .. block) taken here (the block sums
+// unscanned: saves the launch that would scan them; at most kScanTile
+// blocks).
 template <typename TI, typename TO>
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const TI* in, TO* out, int64_t n,
-                                                            const TO* __restrict__ offsets, int write_total) {
+                                                            const TO* __restrict__ offsets, int write_total,
+                                                            int raw_sums = 0) {
   __shared__ TO lds[kScanThreads / kWave];
+  __shared__ TO block_off;
+  if (raw_sums) {
+    TO part = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanThreads) part += offsets[b];
+    part = wave_sum(part);
+    if (lane_id() == 0) lds[threadIdx.x / kWave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      TO t = 0;
+      for (int w = 0; w < kScanThreads / kWave; ++w) t += lds[w];
+      block_off = t;
+    }
+    __syncthreads();  // lds is reused by the scan below
+  }
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   TI vals[kScanItems];
   TO s = 0;
@@ -164,7 +183,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const TI* in, TO* o
     s += (TO)vals[i];
   }
   TO total;
-  TO run = block_exclusive_scan<TO>(s, lds, total) + (offsets ? offsets[blockIdx.x] : (TO)0);
+  TO run = block_exclusive_scan<TO>(s, lds, total) + (raw_sums ? block_off : offsets ? offsets[blockIdx.x] : (TO)0);
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     int64_t idx = base + i;
@@ -254,6 +273,11 @@ void scan_rec(const TI* in, TO* out, int64_t n, int write_total, TO* scratch, hi
   TO* sums = scratch;
   k_scan_sums<TI, TO><<<(unsigned)nb, kScanThreads, 0, s>>>(in, n, sums);
   SNN_LAUNCH_CHECK();
+  if (nb <= kScanTile) {  // each block adds up the sums before it
+    k_scan_apply<TI, TO><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, sums, write_total, 1);
+    SNN_LAUNCH_CHECK();
+    return;
+  }
   scan_rec<TO, TO>(sums, sums, nb, 0, scratch + nb, s);
   k_scan_apply<TI, TO><<<(unsigned)nb, kScanThreads, 0, s>>>(in, out, n, sums, write_total);
   SNN_LAUNCH_CHECK();
