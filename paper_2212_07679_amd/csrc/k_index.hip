@@ -529,18 +529,18 @@ bool power_iter_lds_ok(const DeviceInfo& di, int d) {
 // consecutive rows in each of the U slots, so that one load or store
 // instruction covers one contiguous stretch of memory.  The mu and v entries
 // a lane needs sit in its registers when a row takes one pass (d <= NE G),
-// else in LDS (PM_LDS) or are read from memory.
+// else in LDS (PM_LDS; d is at most 1024).
 // The partial sums of a row meet by shuffles within its G lanes, in a fixed
 // order (deterministic); any order stays within the gamma_{d+2} bound of the
 // key error.
-enum ParamMode { PM_REG, PM_LDS, PM_MEM };
+enum ParamMode { PM_REG, PM_LDS };
 
 template <typename T, int G, int NE, int U, int PM>
 __global__ __launch_bounds__(kThreads) void k_project(const T* __restrict__ X, int64_t n, int d,
                                                      const double* __restrict__ mu, const double* __restrict__ v,
                                                      uint32_t* __restrict__ ukey, uint32_t* __restrict__ val,
                                                      double* __restrict__ block_max) {
-  extern __shared__ double prm[];  // PM_LDS: mu (d) | v (d)
+  extern __shared__ double prm[];  // PM_LDS: mu (d) | v (d), at most 16 KB
   const double* mup = mu;
   const double* vp = v;
   if (PM == PM_LDS) {
@@ -753,9 +753,6 @@ void row_shape(int width, F&& f) {
     f(integral_constant<int, 16>{}, integral_constant<int, 8>{});
 }
 
-// mu (and v) are staged in LDS up to this width
-constexpr int kRowParamLds = 2048;
-
 // block_max: cap doubles of scratch; *max_norm is raised to the largest
 // squared norm of fl32(x - mu) over the rows
 template <typename T>
@@ -767,11 +764,9 @@ void launch_project(const T* X, int64_t n, int d, const double* mu, const double
     grid = grid_for((std::max<int64_t>(n, 1) + U - 1) / U * G, kThreads, cap);
     if (d <= NE * G)
       k_project<T, G, NE, U, PM_REG><<<grid, kThreads, 0, s>>>(X, n, d, mu, v, ukey, val, block_max);
-    else if (d <= kRowParamLds)
+    else
       k_project<T, G, NE, U, PM_LDS><<<grid, kThreads, 2 * sizeof(double) * d, s>>>(X, n, d, mu, v, ukey, val,
                                                                                    block_max);
-    else
-      k_project<T, G, NE, U, PM_MEM><<<grid, kThreads, 0, s>>>(X, n, d, mu, v, ukey, val, block_max);
   });
   SNN_LAUNCH_CHECK();
   k_max_final<<<1, kMaxFinalThreads, 0, s>>>(block_max, grid, max_norm);
@@ -788,12 +783,9 @@ void launch_gather(const T* X, int64_t n, int d, int dp, const double* mu, const
     if (dp <= NE * G)
       k_gather<T, G, NE, 1, PM_REG><<<grid, kThreads, 0, s>>>(X, n, d, dp, mu, ukey, val, key, perm, po, p64, ys, h,
                                                            ynorm, id_base);
-    else if (d <= kRowParamLds)
+    else
       k_gather<T, G, NE, 1, PM_LDS><<<grid, kThreads, sizeof(double) * d, s>>>(X, n, d, dp, mu, ukey, val, key, perm,
                                                                           po, p64, ys, h, ynorm, id_base);
-    else
-      k_gather<T, G, NE, 1, PM_MEM><<<grid, kThreads, 0, s>>>(X, n, d, dp, mu, ukey, val, key, perm, po, p64, ys, h,
-                                                           ynorm, id_base);
   });
   SNN_LAUNCH_CHECK();
 }

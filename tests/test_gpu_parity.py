@@ -125,7 +125,7 @@ def test_self_query_blobs(B, prec):
     check_same(got, ref, "blobs3d self")
 
 
-@pytest.mark.parametrize("d", [1, 3, 5, 8, 13, 32, 37, 70])
+@pytest.mark.parametrize("d", [1, 3, 5, 8, 13, 32, 37, 70, 129, 300, 1024])
 def test_dims(B, d):
     g = np.random.default_rng(100 + d)
     n, m = 3000, 257
@@ -136,7 +136,7 @@ def test_dims(B, d):
     ref = oracle.brute_radius(P, Q, R)
     idx = B.Index(to_dev(P))
     for prec in PRECS:
-        if prec == "fp32" and d > 16:
+        if (prec == "fp32" and d > 16) or (prec == "mixed" and d > 128):
             with pytest.raises(B.SnnError) as e:
                 idx.query(to_dev(Q), R, precision=prec)
             assert e.value.status == B.SNN_ENOTSUP
@@ -230,12 +230,22 @@ def test_nan_rejected(B):
         idx.query(to_dev(P[:5]), -1.0)
 
 
-def test_index_internals(B):
-    say("index internals")
-    w = W.gmm16(n=50_000, m=10, R=1.5)
-    idx = B.Index(to_dev(w.P))
+@pytest.mark.parametrize("d", [3, 16, 40, 129, 300, 1024])
+def test_index_internals(B, d):
+    # every shape of the row kernels: one to eight elements per lane and
+    # pass, several passes per row (d > 128), the centre and direction held
+    # in registers (d <= 128) or in LDS (up to the largest d, 1024)
+    say(f"index internals d={d}")
+    if d == 16:
+        P = W.gmm16(n=50_000, m=10, R=1.5).P
+    else:
+        g = np.random.default_rng([2212, 7679, 101, d])
+        scale = np.linspace(1.0, 2.0, d)
+        scale[d // 3] = 3.0
+        P = (g.standard_normal((20_000, d)) * scale + 5.0).astype(np.float32)
+    idx = B.Index(to_dev(P))
     v = idx.view()
-    P = w.P.astype(np.float64)
+    P = P.astype(np.float64)
     mu = P.mean(0)
     assert np.allclose(v["mu"].cpu().numpy(), mu, rtol=1e-12, atol=1e-12)
     vv = v["v"].cpu().numpy()
@@ -247,7 +257,7 @@ def test_index_internals(B):
     key = v["key"].cpu().numpy()
     perm = v["perm"].cpu().numpy()
     assert np.all(np.diff(key) >= 0)
-    assert np.array_equal(np.sort(perm), np.arange(w.n))
+    assert np.array_equal(np.sort(perm), np.arange(P.shape[0]))
     alpha = X[perm] @ vv
     assert np.all(np.abs(key - alpha) <= v["key_eps"])
 
