@@ -29,7 +29,10 @@ namespace {
 constexpr int kThreads = 256;
 }
 
-template <typename T>
+// G lanes per query row (coalesced row reads); the row's partial sums meet
+// by shuffles within its G lanes in a fixed order (deterministic; any order
+// stays within the float64 bounds the windows and the screen allow for).
+template <typename T, int G>
 __global__ __launch_bounds__(kThreads) void k_query_keys(const T* __restrict__ Q, int64_t m, int d,
                                                         const double* __restrict__ mu, const double* __restrict__ v,
                                                         const double* __restrict__ key, int n, int K,
@@ -38,29 +41,40 @@ __global__ __launch_bounds__(kThreads) void k_query_keys(const T* __restrict__ Q
                                                         double* __restrict__ qnorm, int* __restrict__ bad) {
   const double amin = key[0], amax = key[n - 1];
   const double scale = amax > amin ? (double)K / (amax - amin) : 0.0;
+  const int sub = threadIdx.x % G;
   int badloc = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; i < m;
+       i += ((int64_t)gridDim.x * blockDim.x) / G) {
     const T* q = Q + i * d;
     double a = 0.0, nn = 0.0;
-    for (int k = 0; k < d; ++k) {
-      double qk = (double)q[k];
+    for (int k = sub; k < d; k += G) {
+      const double qk = (double)q[k];
       if (!isfinite(qk)) badloc = 1;
-      double x = qk - mu[k];
+      const double x = qk - mu[k];
       a += x * v[k];
-      double y = (double)(float)x;
+      const double y = (double)(float)x;
       nn += y * y;
     }
-    const double t = (a - amin) * scale;
-    const int b = (t >= 0.0) ? (t < (double)K ? (int)t : K - 1) : 0;
-    bucket[i] = (uint32_t)b;
-    slot[i] = atomicAdd(&hist[b], 1u);
-    qalpha[i] = a;
-    qnorm[i] = sqrt(nn);
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+      a += __shfl_xor(a, off, G);
+      nn += __shfl_xor(nn, off, G);
+    }
+    if (sub == 0) {
+      const double t = (a - amin) * scale;
+      const int b = (t >= 0.0) ? (t < (double)K ? (int)t : K - 1) : 0;
+      bucket[i] = (uint32_t)b;
+      slot[i] = atomicAdd(&hist[b], 1u);
+      qalpha[i] = a;
+      qnorm[i] = sqrt(nn);
+    }
   }
   if (badloc) atomicOr(bad, 1);
 }
 
-template <typename T>
+// G lanes per query row: the row's destination slot is read once per group,
+// its elements are copied G at a time.
+template <typename T, int G>
 __global__ __launch_bounds__(kThreads) void k_query_gather(const T* __restrict__ Q, int64_t m, int d, int dp,
                                                           const uint32_t* __restrict__ bucket,
                                                           const uint32_t* __restrict__ slot,
@@ -69,12 +83,12 @@ __global__ __launch_bounds__(kThreads) void k_query_gather(const T* __restrict__
                                                           const double* __restrict__ qnorm_in,
                                                           double* __restrict__ q64, int32_t* __restrict__ qorig,
                                                           double* __restrict__ qalpha, double* __restrict__ qnorm) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m * dp; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / dp;
-    const int k = (int)(e % dp);
+  const int sub = threadIdx.x % G;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; i < m;
+       i += ((int64_t)gridDim.x * blockDim.x) / G) {
     const int64_t s = (int64_t)boff[bucket[i]] + slot[i];
-    q64[s * dp + k] = k < d ? (double)Q[i * d + k] : 0.0;
-    if (k == 0) {
+    for (int k = sub; k < dp; k += G) q64[s * dp + k] = k < d ? (double)Q[i * d + k] : 0.0;
+    if (sub == 0) {
       qorig[s] = (int32_t)i;
       qalpha[s] = qalpha_in[i];
       qnorm[s] = qnorm_in[i];
@@ -279,29 +293,70 @@ int query_buckets(int64_t m) {
   return K;
 }
 
+namespace {
+// lanes per query row: enough to read a short row in one step, at most 16
+int query_row_lanes(int width) { return width <= 4 ? 4 : (width <= 8 ? 8 : 16); }
+
+template <typename T, int G>
+void query_keys_t(const T* Q, int64_t m, int d, const double* mu, const double* v, const double* key, int n, int K,
+                  uint32_t* bucket, uint32_t* slot, uint32_t* hist, double* qalpha, double* qnorm, int* bad,
+                  hipStream_t s) {
+  k_query_keys<T, G><<<grid_for(m * G, 8192), kThreads, 0, s>>>(Q, m, d, mu, v, key, n, K, bucket, slot, hist,
+                                                                qalpha, qnorm, bad);
+}
+
+template <typename T>
+void query_keys_d(const T* Q, int64_t m, int d, const double* mu, const double* v, const double* key, int n, int K,
+                  uint32_t* bucket, uint32_t* slot, uint32_t* hist, double* qalpha, double* qnorm, int* bad,
+                  hipStream_t s) {
+  switch (query_row_lanes(d)) {
+    case 4: query_keys_t<T, 4>(Q, m, d, mu, v, key, n, K, bucket, slot, hist, qalpha, qnorm, bad, s); break;
+    case 8: query_keys_t<T, 8>(Q, m, d, mu, v, key, n, K, bucket, slot, hist, qalpha, qnorm, bad, s); break;
+    default: query_keys_t<T, 16>(Q, m, d, mu, v, key, n, K, bucket, slot, hist, qalpha, qnorm, bad, s); break;
+  }
+}
+
+}  // namespace
+
 void launch_query_keys(snn_dtype dt, const void* Q, int64_t m, int d, const double* mu, const double* v,
                        const double* key, int n, int K, uint32_t* bucket, uint32_t* slot, uint32_t* hist,
                        double* qalpha, double* qnorm, int* bad, hipStream_t s) {
-  const int g = grid_for(m, 8192);
   if (dt == SNN_F32)
-    k_query_keys<float><<<g, kThreads, 0, s>>>((const float*)Q, m, d, mu, v, key, n, K, bucket, slot, hist, qalpha,
-                                               qnorm, bad);
+    query_keys_d<float>((const float*)Q, m, d, mu, v, key, n, K, bucket, slot, hist, qalpha, qnorm, bad, s);
   else
-    k_query_keys<double><<<g, kThreads, 0, s>>>((const double*)Q, m, d, mu, v, key, n, K, bucket, slot, hist,
-                                                qalpha, qnorm, bad);
+    query_keys_d<double>((const double*)Q, m, d, mu, v, key, n, K, bucket, slot, hist, qalpha, qnorm, bad, s);
   SNN_LAUNCH_CHECK();
 }
+
+namespace {
+template <typename T>
+void query_gather_d(const T* Q, int64_t m, int d, int dp, const uint32_t* bucket, const uint32_t* slot,
+                    const uint32_t* boff, const double* qalpha_in, const double* qnorm_in, double* q64, int32_t* qorig,
+                    double* qalpha, double* qnorm, hipStream_t s) {
+  const int G = query_row_lanes(dp);
+  const int g = grid_for(m * G, 8192);
+  if (G == 4)
+    k_query_gather<T, 4><<<g, kThreads, 0, s>>>(Q, m, d, dp, bucket, slot, boff, qalpha_in, qnorm_in, q64, qorig,
+                                                qalpha, qnorm);
+  else if (G == 8)
+    k_query_gather<T, 8><<<g, kThreads, 0, s>>>(Q, m, d, dp, bucket, slot, boff, qalpha_in, qnorm_in, q64, qorig,
+                                                qalpha, qnorm);
+  else
+    k_query_gather<T, 16><<<g, kThreads, 0, s>>>(Q, m, d, dp, bucket, slot, boff, qalpha_in, qnorm_in, q64, qorig,
+                                                 qalpha, qnorm);
+}
+
+}  // namespace
 
 void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, const uint32_t* bucket,
                          const uint32_t* slot, const uint32_t* boff, const double* qalpha_in, const double* qnorm_in,
                          double* q64, int32_t* qorig, double* qalpha, double* qnorm, hipStream_t s) {
-  const int g = grid_for(m * dp, 16384);
   if (dt == SNN_F32)
-    k_query_gather<float><<<g, kThreads, 0, s>>>((const float*)Q, m, d, dp, bucket, slot, boff, qalpha_in, qnorm_in,
-                                                 q64, qorig, qalpha, qnorm);
+    query_gather_d<float>((const float*)Q, m, d, dp, bucket, slot, boff, qalpha_in, qnorm_in, q64, qorig, qalpha,
+                          qnorm, s);
   else
-    k_query_gather<double><<<g, kThreads, 0, s>>>((const double*)Q, m, d, dp, bucket, slot, boff, qalpha_in,
-                                                  qnorm_in, q64, qorig, qalpha, qnorm);
+    query_gather_d<double>((const double*)Q, m, d, dp, bucket, slot, boff, qalpha_in, qnorm_in, q64, qorig, qalpha,
+                           qnorm, s);
   SNN_LAUNCH_CHECK();
 }
 
