@@ -443,16 +443,19 @@ __global__ __launch_bounds__(kThreads) void kb_query_pad(BatchDev b, int32_t* __
   }
 }
 
+constexpr int kQG = 16;
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void kb_query_gather(
     BatchDev b, const double* __restrict__ mu, const uint32_t* __restrict__ qval, const uint32_t* __restrict__ qikey,
     const uint32_t* __restrict__ qidx, const double* __restrict__ qa_in, const double* __restrict__ qn_in,
     double* __restrict__ q64, int32_t* __restrict__ qorig, double* __restrict__ qa, double* __restrict__ qn,
     uint16_t* __restrict__ qop, float* __restrict__ cthr) {
-  // one wavefront per query: lanes cover the coordinates and the operand row
-  const int KA = b.KA, lane = lane_id();
-  for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; t < b.M;
-       t += ((int64_t)gridDim.x * blockDim.x) / kWave) {
+  // kQG lanes per query (four queries per wavefront): lanes cover the
+  // coordinates and the operand row
+  const int KA = b.KA, lane = threadIdx.x % kQG;
+  for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kQG; t < b.M;
+       t += ((int64_t)gridDim.x * blockDim.x) / kQG) {
     const uint32_t p = qidx[t];
     const int i = (int)qikey[t];
     const BatchInst& in = b.inst[i];
@@ -464,7 +467,7 @@ __global__ __launch_bounds__(kThreads) void kb_query_gather(
     const double* m = mu + in.vec_off;
     double* qrow = q64 + in.q64_off + r * in.dp;
     double nn = 0.0;
-    for (int k = lane; k < in.dp; k += kWave) {
+    for (int k = lane; k < in.dp; k += kQG) {
       const double qv = k < d ? (double)q[k] : 0.0;
       qrow[k] = qv;
       if (k < d) {
@@ -474,9 +477,10 @@ __global__ __launch_bounds__(kThreads) void kb_query_gather(
     }
     // any summation order of the squares stays within the gamma_{d+1} bound
     // the start value allows for
-    nn = wave_sum(nn);
+#pragma unroll
+    for (int off = kQG / 2; off > 0; off >>= 1) nn += __shfl_xor(nn, off, kQG);
     uint16_t* row = qop + s * KA;
-    for (int k = lane; k < KA; k += kWave) row[k] = operand_value<T>(in.terms, d, k, q, m, true);
+    for (int k = lane; k < KA; k += kQG) row[k] = operand_value<T>(in.terms, d, k, q, m, true);
     if (lane == 0) {
       qorig[s] = (int32_t)g;
       qa[s] = qa_in[g];
@@ -776,7 +780,7 @@ void batch_query_gather(snn_dtype dt, const BatchDev& b, const double* mu, const
                         const uint32_t* qikey, const uint32_t* qidx, const double* qa_in, const double* qn_in,
                         double* q64, int32_t* qorig, double* qa, double* qn, uint16_t* qop, float* cthr,
                         hipStream_t s) {
-  SNN_DT_LAUNCH(kb_query_gather, grid_for(b.M * (int64_t)kWave, 16384), kThreads, b, mu, qval, qikey, qidx, qa_in,
+  SNN_DT_LAUNCH(kb_query_gather, grid_for(b.M * (int64_t)kQG, 16384), kThreads, b, mu, qval, qikey, qidx, qa_in,
                 qn_in, q64, qorig, qa, qn, qop, cthr);
 }
 
