@@ -71,12 +71,17 @@ __device__ __forceinline__ uint16_t operand_value(int terms, int d, int k, const
   return take_lo ? f32_to_bf16_rne(y - bf16_to_f32(hi)) : hi;
 }
 
+// lanes per row in the row kernels (gathers of data and query rows)
+constexpr int kQG = 16;
+
 // KA bf16 values of one row as 16-byte stores: dst[c8] for c8 < KA / 8, where
-// dst(c8) gives the address of the c8-th group of 8 values.
+// dst(c8) gives the address of the c8-th group of 8 values; groups c8_0,
+// c8_0 + c8_step, ... (several lanes may share a row).
 template <typename T, typename Dst>
 __device__ __forceinline__ void write_operand_row(int terms, int d, int KA, const T* __restrict__ x,
-                                                  const double* __restrict__ mu, bool query, Dst dst) {
-  for (int c8 = 0; c8 < KA / 8; ++c8) {
+                                                  const double* __restrict__ mu, bool query, Dst dst, int c8_0 = 0,
+                                                  int c8_step = 1) {
+  for (int c8 = c8_0; c8 < KA / 8; c8 += c8_step) {
     uint32_t w[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -347,8 +352,12 @@ __global__ __launch_bounds__(kThreads) void kb_gather(BatchDev b, const double* 
                                                      const uint32_t* __restrict__ idx, double* __restrict__ key,
                                                      int32_t* __restrict__ perm, double* __restrict__ p64,
                                                      float* __restrict__ h, uint16_t* __restrict__ cop) {
-  const int KA = b.KA;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < b.N; t += (int64_t)gridDim.x * blockDim.x) {
+  // kQG lanes per row: the float64 copy and the squared norm G elements at
+  // a time (partial sums meet by shuffles in a fixed order; any order stays
+  // within the bound the screen allows for), the operand groups shared out
+  const int KA = b.KA, sub = threadIdx.x % kQG;
+  for (int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kQG; t < b.N;
+       t += ((int64_t)gridDim.x * blockDim.x) / kQG) {
     const uint32_t p = idx[t];
     const int i = (int)ikey[t];
     const BatchInst in = b.inst[i];
@@ -356,24 +365,30 @@ __global__ __launch_bounds__(kThreads) void kb_gather(BatchDev b, const double* 
     const int64_t r = t - in.in_off;
     const int64_t R = in.row_base + r;
     const int64_t local = (int64_t)val[p] - in.in_off;
-    key[R] = (double)ordered_to_float(ukey[p]);
-    perm[R] = (int32_t)local;
     const T* x = static_cast<const T*>(in.X) + local * d;
     const double* m = mu + in.vec_off;
     double* prow = p64 + in.p64_off + r * in.dp;
     double nn = 0.0;
-    for (int k = 0; k < d; ++k) {
-      const double xv = (double)x[k];
+    for (int k = sub; k < in.dp; k += kQG) {
+      const double xv = k < d ? (double)x[k] : 0.0;
       prow[k] = xv;
-      const float y = (float)(xv - m[k]);
-      nn += (double)y * (double)y;
+      if (k < d) {
+        const float y = (float)(xv - m[k]);
+        nn += (double)y * (double)y;
+      }
     }
-    for (int k = d; k < in.dp; ++k) prow[k] = 0.0;
-    h[R] = (float)(0.5 * nn);
+#pragma unroll
+    for (int off = kQG / 2; off > 0; off >>= 1) nn += __shfl_xor(nn, off, kQG);
+    if (sub == 0) {
+      key[R] = (double)ordered_to_float(ukey[p]);
+      perm[R] = (int32_t)local;
+      h[R] = (float)(0.5 * nn);
+    }
     // candidate operands in the 32-row block layout of the matrix-core screen
     uint16_t* blk = cop + (R / 32) * (int64_t)KA * 32 + (R % 32) * 8;
-    write_operand_row<T>(in.terms, d, KA, x, m, false,
-                         [&](int c8) { return reinterpret_cast<uint4*>(blk + (int64_t)c8 * 256); });
+    write_operand_row<T>(
+        in.terms, d, KA, x, m, false, [&](int c8) { return reinterpret_cast<uint4*>(blk + (int64_t)c8 * 256); },
+        sub, kQG);
   }
 }
 
@@ -442,8 +457,6 @@ __global__ __launch_bounds__(kThreads) void kb_query_pad(BatchDev b, int32_t* __
     for (int c8 = 0; c8 < KA / 8; ++c8) row[c8] = make_uint4(0, 0, 0, 0);
   }
 }
-
-constexpr int kQG = 16;
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void kb_query_gather(
@@ -757,7 +770,8 @@ void batch_finalize(const BatchDev& b, hipStream_t s) {
 void batch_gather(snn_dtype dt, const BatchDev& b, const double* mu, const uint32_t* ukey, const uint32_t* val,
                   const uint32_t* ikey, const uint32_t* idx, double* key, int32_t* perm, double* p64, float* h,
                   uint16_t* cop, hipStream_t s) {
-  SNN_DT_LAUNCH(kb_gather, grid_for(b.N, 16384), kThreads, b, mu, ukey, val, ikey, idx, key, perm, p64, h, cop);
+  SNN_DT_LAUNCH(kb_gather, grid_for(b.N * (int64_t)kQG, 65536), kThreads, b, mu, ukey, val, ikey, idx, key, perm, p64,
+                h, cop);
 }
 
 void batch_pad_rows(const BatchDev& b, float* h, int32_t* perm, uint16_t* cop, hipStream_t s) {
