@@ -138,7 +138,59 @@ __global__ __launch_bounds__(kBatchMaxD) void kb_colsum_final(BatchDev b, const 
 
 // ---- Gram matrix ---------------------------------------------------------------
 constexpr int kGramStage = 4096;  // doubles of centred rows in LDS
-constexpr int kGramPerThread = 16;
+
+// Thread t owns the TS x TS tile of C at rows ta.., columns tb.. (at most
+// 256 tiles: TS = 1, 2, 4, 8 for d up to 16, 32, 64, 128), so each pair of
+// staged values read from LDS feeds TS^2 / 2 fused multiply-adds.  Entries
+// (a, b) and (b, a) see the same products in the same order, so C stays
+// exactly symmetric.
+template <int TS>
+__device__ __forceinline__ void gram_tiles(int d, int rows, const double* __restrict__ stage, double (&acc)[TS][TS]) {
+  const int tiles_1d = (d + TS - 1) / TS;
+  const int t = threadIdx.x;
+  if (t >= tiles_1d * tiles_1d) return;
+  const int ta = (t / tiles_1d) * TS, tb = (t % tiles_1d) * TS;
+  for (int r = 0; r < rows; ++r) {
+    const double* row = stage + r * d;
+    double a[TS], b[TS];
+#pragma unroll
+    for (int k = 0; k < TS; ++k) {
+      a[k] = ta + k < d ? row[ta + k] : 0.0;
+      b[k] = tb + k < d ? row[tb + k] : 0.0;
+    }
+#pragma unroll
+    for (int x = 0; x < TS; ++x)
+#pragma unroll
+      for (int y = 0; y < TS; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+  }
+}
+
+template <typename T, int TS>
+__device__ __forceinline__ void gram_chunk(const T* __restrict__ X, int d, const double* __restrict__ m, int64_t r0,
+                                           int64_t r1, double* __restrict__ stage, double* __restrict__ out) {
+  double acc[TS][TS];
+#pragma unroll
+  for (int x = 0; x < TS; ++x)
+#pragma unroll
+    for (int y = 0; y < TS; ++y) acc[x][y] = 0.0;
+  const int rc = kGramStage / d;
+  for (int64_t ra = r0; ra < r1; ra += rc) {
+    const int rows = (int)min((int64_t)rc, r1 - ra);
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * d; e += kThreads) stage[e] = (double)X[ra * d + e] - m[e % d];
+    __syncthreads();
+    gram_tiles<TS>(d, rows, stage, acc);
+  }
+  const int tiles_1d = (d + TS - 1) / TS;
+  const int t = threadIdx.x;
+  if (t >= tiles_1d * tiles_1d) return;
+  const int ta = (t / tiles_1d) * TS, tb = (t % tiles_1d) * TS;
+#pragma unroll
+  for (int x = 0; x < TS; ++x)
+#pragma unroll
+    for (int y = 0; y < TS; ++y)
+      if (ta + x < d && tb + y < d) out[(ta + x) * d + tb + y] = acc[x][y];
+}
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void kb_gram(BatchDev b, int ddmax, const int32_t* __restrict__ chunk_inst,
@@ -146,40 +198,21 @@ __global__ __launch_bounds__(kThreads) void kb_gram(BatchDev b, int ddmax, const
                                                    const int64_t* __restrict__ chunk_r1,
                                                    const double* __restrict__ mu, double* __restrict__ part) {
   __shared__ double stage[kGramStage];
-  const int c = blockIdx.x, t = threadIdx.x;
+  const int c = blockIdx.x;
   const int i = chunk_inst[c];
   const BatchInst in = b.inst[i];
-  const int d = in.d, dd = d * d;
-  const int rc = kGramStage / d;
+  const int d = in.d;
   const T* X = static_cast<const T*>(in.X);
   const double* m = mu + in.vec_off;
-  const int64_t r0 = chunk_r0[c], r1 = chunk_r1[c];
-  for (int e0 = 0; e0 < dd; e0 += kGramPerThread * kThreads) {
-    double acc[kGramPerThread];
-#pragma unroll
-    for (int k = 0; k < kGramPerThread; ++k) acc[k] = 0.0;
-    for (int64_t ra = r0; ra < r1; ra += rc) {
-      const int rows = (int)min((int64_t)rc, r1 - ra);
-      __syncthreads();
-      for (int e = t; e < rows * d; e += kThreads) stage[e] = (double)X[ra * d + e] - m[e % d];
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < kGramPerThread; ++k) {
-        const int e = e0 + k * kThreads + t;
-        if (e < dd) {
-          const int a = e / d, bb = e % d;
-          double s = acc[k];
-          for (int r = 0; r < rows; ++r) s += stage[r * d + a] * stage[r * d + bb];
-          acc[k] = s;
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kGramPerThread; ++k) {
-      const int e = e0 + k * kThreads + t;
-      if (e < dd) part[(int64_t)c * ddmax + e] = acc[k];
-    }
-  }
+  double* out = part + (int64_t)c * ddmax;
+  if (d <= 16)
+    gram_chunk<T, 1>(X, d, m, chunk_r0[c], chunk_r1[c], stage, out);
+  else if (d <= 32)
+    gram_chunk<T, 2>(X, d, m, chunk_r0[c], chunk_r1[c], stage, out);
+  else if (d <= 64)
+    gram_chunk<T, 4>(X, d, m, chunk_r0[c], chunk_r1[c], stage, out);
+  else
+    gram_chunk<T, 8>(X, d, m, chunk_r0[c], chunk_r1[c], stage, out);
 }
 
 __global__ __launch_bounds__(kThreads) void kb_gram_final(BatchDev b, int ddmax, const double* __restrict__ part,
