@@ -66,15 +66,21 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
   __syncthreads();
   const uint64_t lt = (1ull << lane) - 1ull;
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  // every item of the thread is loaded up front (all loads in flight at
+  // once), then ranked round by round
+  uint32_t ks[kSortItems], vs[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    const int64_t idx = base + (int64_t)i * kSortThreads + t;
+    ks[i] = idx < n ? kin[idx] : 0u;
+    vs[i] = idx < n ? vin[idx] : 0u;
+  }
+#pragma unroll
   for (int i = 0; i < kSortItems; ++i) {
     const int64_t idx = base + (int64_t)i * kSortThreads + t;
     const bool valid = idx < n;
-    uint32_t k = 0, v = 0, dg = 0;
-    if (valid) {
-      k = kin[idx];
-      v = vin[idx];
-      dg = (k >> shift) & mask;
-    }
+    const uint32_t k = ks[i], v = vs[i];
+    const uint32_t dg = valid ? (k >> shift) & mask : 0u;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < bits; ++b) {
       uint64_t mb = __ballot((dg >> b) & 1u);
