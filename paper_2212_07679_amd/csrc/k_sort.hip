@@ -18,11 +18,11 @@ namespace snn {
 namespace {
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per block
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
+// ITEMS keys per thread, kSortThreads * ITEMS per block
+template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
                                                             int shift, uint32_t mask, uint32_t* __restrict__ hist,
                                                             int nblocks) {
@@ -30,9 +30,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
   const int t = threadIdx.x, w = t / kWave;
   for (int i = t; i < (kSortThreads / kWave) * kRadix; i += kSortThreads) (&h[0][0])[i] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = (int64_t)blockIdx.x * kSortThreads * ITEMS;
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     int64_t idx = base + (int64_t)i * kSortThreads + t;
     if (idx < n) atomicAdd(&h[w][(keys[idx] >> shift) & mask], 1u);
   }
@@ -45,6 +45,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __r
   }
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
                                                                const uint32_t* __restrict__ vin,
                                                                uint32_t* __restrict__ kout,
@@ -65,18 +66,18 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
   }
   __syncthreads();
   const uint64_t lt = (1ull << lane) - 1ull;
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = (int64_t)blockIdx.x * kSortThreads * ITEMS;
   // every item of the thread is loaded up front (all loads in flight at
   // once), then ranked round by round
-  uint32_t ks[kSortItems], vs[kSortItems];
+  uint32_t ks[ITEMS], vs[ITEMS];
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const int64_t idx = base + (int64_t)i * kSortThreads + t;
     ks[i] = idx < n ? kin[idx] : 0u;
     vs[i] = idx < n ? vin[idx] : 0u;
   }
 #pragma unroll
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < ITEMS; ++i) {
     const int64_t idx = base + (int64_t)i * kSortThreads + t;
     const bool valid = idx < n;
     const uint32_t k = ks[i], v = vs[i];
@@ -309,11 +310,35 @@ void exclusive_scan_u32(uint32_t* data, int64_t n, void* scratch, hipStream_t s)
   scan_rec<uint32_t, uint32_t>(data, data, n, 0, reinterpret_cast<uint32_t*>(scratch), s);
 }
 
+namespace {
+// keys per thread of the radix kernels: 8 up to 2^21 keys (more workgroups
+// for mid-size sorts), 16 above (measured: 1e6 keys 6% faster with 8,
+// 5e6 keys 1% faster with 16)
+int sort_items(int64_t n) { return n <= (int64_t(1) << 21) ? 8 : 16; }
+int64_t sort_tile(int64_t n) { return (int64_t)kSortThreads * sort_items(n); }
+
+// one 8-bit pass: histograms, their scan, the stable scatter
+void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n, int shift,
+                int bits, uint32_t mask, uint32_t* hist, size_t nhist, int nblocks, void* scratch, hipStream_t s) {
+  if (sort_items(n) == 8)
+    k_radix_hist<8><<<nblocks, kSortThreads, 0, s>>>(kin, n, shift, mask, hist, nblocks);
+  else
+    k_radix_hist<16><<<nblocks, kSortThreads, 0, s>>>(kin, n, shift, mask, hist, nblocks);
+  SNN_LAUNCH_CHECK();
+  exclusive_scan_u32(hist, (int64_t)nhist, scratch, s);
+  if (sort_items(n) == 8)
+    k_radix_scatter<8><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, bits, hist, nblocks);
+  else
+    k_radix_scatter<16><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, bits, hist, nblocks);
+  SNN_LAUNCH_CHECK();
+}
+}  // namespace
+
 void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n, int begin_bit, int end_bit,
                       hipStream_t s) {
   if (n <= 1 || begin_bit >= end_bit) return;
   if (n > (int64_t)UINT32_MAX / 2) fail(SNN_EINVAL, "radix sort: too many keys");
-  const int nblocks = (int)ceil_div(n, kSortTile);
+  const int nblocks = (int)ceil_div(n, sort_tile(n));
   const size_t nhist = (size_t)nblocks * kRadix;
   const size_t bytes = 2 * (size_t)n * sizeof(uint32_t) + nhist * sizeof(uint32_t) + scan_scratch_bytes(nhist) + 1024;
   char* mem = static_cast<char*>(a.alloc(bytes));
@@ -325,11 +350,7 @@ void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n,
   for (int shift = begin_bit; shift < end_bit; shift += kRadixBits) {
     const int bits = std::min(kRadixBits, end_bit - shift);
     const uint32_t mask = (1u << bits) - 1u;
-    k_radix_hist<<<nblocks, kSortThreads, 0, s>>>(kin, n, shift, mask, hist, nblocks);
-    SNN_LAUNCH_CHECK();
-    exclusive_scan_u32(hist, (int64_t)nhist, scratch, s);
-    k_radix_scatter<<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, bits, hist, nblocks);
-    SNN_LAUNCH_CHECK();
+    radix_pass(kin, vin, kout, vout, n, shift, bits, mask, hist, nhist, nblocks, scratch, s);
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
@@ -341,7 +362,7 @@ void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n,
 }
 
 size_t radix_sort_ws_bytes(int64_t n) {
-  const int64_t nblocks = ceil_div(std::max<int64_t>(n, 1), kSortTile);
+  const int64_t nblocks = ceil_div(std::max<int64_t>(n, 1), sort_tile(n));
   const size_t nhist = (size_t)nblocks * kRadix;
   return 2 * (size_t)n * sizeof(uint32_t) + nhist * sizeof(uint32_t) + scan_scratch_bytes((int64_t)nhist) + 1024;
 }
@@ -363,7 +384,7 @@ void radix_sort_pairs_ws(uint32_t* keys, uint32_t* vals, int64_t n, int begin_bi
                          hipStream_t s) {
   if (n <= 1 || begin_bit >= end_bit) return;
   if (n > (int64_t)UINT32_MAX / 2) fail(SNN_EINVAL, "radix sort: too many keys");
-  const int nblocks = (int)ceil_div(n, kSortTile);
+  const int nblocks = (int)ceil_div(n, sort_tile(n));
   const size_t nhist = (size_t)nblocks * kRadix;
   uint32_t* k2 = static_cast<uint32_t*>(ws);
   uint32_t* v2 = k2 + n;
@@ -373,11 +394,7 @@ void radix_sort_pairs_ws(uint32_t* keys, uint32_t* vals, int64_t n, int begin_bi
   for (int shift = begin_bit; shift < end_bit; shift += kRadixBits) {
     const int bits = std::min(kRadixBits, end_bit - shift);
     const uint32_t mask = (1u << bits) - 1u;
-    k_radix_hist<<<nblocks, kSortThreads, 0, s>>>(kin, n, shift, mask, hist, nblocks);
-    SNN_LAUNCH_CHECK();
-    exclusive_scan_u32(hist, (int64_t)nhist, scratch, s);
-    k_radix_scatter<<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, bits, hist, nblocks);
-    SNN_LAUNCH_CHECK();
+    radix_pass(kin, vin, kout, vout, n, shift, bits, mask, hist, nhist, nblocks, scratch, s);
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
