@@ -412,6 +412,84 @@ __global__ __launch_bounds__(kWave) void k_power_iter_wave(const double* __restr
   }
 }
 
+// d <= kJacobiMaxD: the top eigenvector of C by cyclic Jacobi rotations
+// (symmetric Schur rotations, rows and columns of a rotation updated by the
+// lanes k < d), which converges in a few sweeps however close the two
+// largest eigenvalues are, where the power iteration would need hundreds of
+// steps.  A and the accumulated rotations V sit in LDS; the rotation of each
+// pair (p, q) is computed by every lane from the same values (uniform).
+// Stops when the off-diagonal entries are below 1e-30 of the squared
+// Frobenius norm, or after 30 sweeps; v is the column of V of the largest
+// diagonal entry, with the same sign convention as the power iteration (C = 0
+// gives e_1).  iters_out counts sweeps.
+constexpr int kJacobiMaxD = 4;
+
+__global__ __launch_bounds__(kWave) void k_eig_jacobi(const double* __restrict__ C, int d, double* __restrict__ v_out,
+                                                     int* __restrict__ iters_out) {
+  __shared__ double A[kJacobiMaxD][kJacobiMaxD], V[kJacobiMaxD][kJacobiMaxD];
+  const int k = threadIdx.x;
+  if (k < d)
+    for (int j = 0; j < d; ++j) {
+      A[k][j] = C[(int64_t)k * d + j];
+      V[k][j] = k == j ? 1.0 : 0.0;
+    }
+  __syncthreads();
+  double fro = 0.0;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) fro += A[i][j] * A[i][j];
+  int sweep = 0;
+  for (; sweep < 30; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < d; ++i)
+      for (int j = i + 1; j < d; ++j) off += A[i][j] * A[i][j];
+    if (!(off > 1e-30 * fro)) break;
+    for (int p = 0; p < d; ++p)
+      for (int q = p + 1; q < d; ++q) {
+        const double apq = A[p][q];
+        if (apq == 0.0) continue;
+        const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+        __syncthreads();  // every lane has read A[p][q], A[p][p], A[q][q]
+        if (k < d) {      // columns p, q of A and V
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - sn * akq;
+          A[k][q] = sn * akp + c * akq;
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - sn * vkq;
+          V[k][q] = sn * vkp + c * vkq;
+        }
+        __syncthreads();
+        if (k < d) {  // rows p, q of A
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - sn * aqk;
+          A[q][k] = sn * apk + c * aqk;
+        }
+        __syncthreads();
+      }
+  }
+  if (k == 0) {
+    int best = 0;
+    for (int i = 1; i < d; ++i)
+      if (A[i][i] > A[best][best]) best = i;
+    double col[kJacobiMaxD];
+    for (int i = 0; i < d; ++i) col[i] = fro > 0.0 ? V[i][best] : (i == 0 ? 1.0 : 0.0);
+    int im = 0;
+    double am = -1.0;
+    for (int i = 0; i < d; ++i)
+      if (fabs(col[i]) > am) {
+        am = fabs(col[i]);
+        im = i;
+      }
+    const double sgn = col[im] < 0 ? -1.0 : 1.0;
+    double ss = 0.0;
+    for (int i = 0; i < d; ++i) ss += col[i] * col[i];
+    const double inv = 1.0 / sqrt(ss);
+    for (int i = 0; i < d; ++i) v_out[i] = sgn * col[i] * inv;
+    *iters_out = sweep > 0 ? sweep : 1;
+  }
+}
+
 // Same iteration for 64 < d <= 128 with C resident in LDS (at most 128 KB):
 // read once from HBM instead of from L2 on every step.  512 threads = 4 parts
 // x 128 row slots; part p sums columns j = p, p + 4, ... of row i (C[j][i],
@@ -914,7 +992,9 @@ void build_index_t(Index& ix, const T* X) {
   SNN_LAUNCH_CHECK();
   k_gram_final<<<(int)((dd + kWave - 1) / kWave), kGramFinalWaves * kWave, 0, s>>>(part2, g2, dd, C);
   SNN_LAUNCH_CHECK();
-  if (d <= 8)
+  if (d <= kJacobiMaxD)
+    k_eig_jacobi<<<1, kWave, 0, s>>>(C, d, ix.v.as<double>(), &sc->iters);
+  else if (d <= 8)
     k_power_iter_wave<8><<<1, kWave, 0, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
   else if (d <= 16)
     k_power_iter_wave<16><<<1, kWave, 0, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);

@@ -262,11 +262,12 @@ def test_index_internals(B, d):
     assert np.all(np.abs(key - alpha) <= v["key_eps"])
 
 
-@pytest.mark.parametrize("d", [16, 64, 65, 100, 128, 129, 200])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 16, 64, 65, 100, 128, 129, 200])
 def test_power_iteration_widths(B, d):
-    # every form of the power iteration (one wavefront; C in LDS for
-    # 64 < d <= 128; C through the caches above): unit v along the top
-    # eigenvector of a spectrum with a clear gap, Rayleigh quotient at the top
+    # every form of the direction solve (Jacobi rotations for d <= 4; the
+    # power iteration in one wavefront, with C in LDS for 64 < d <= 128, or
+    # C through the caches above): unit v along the top eigenvector of a
+    # spectrum with a clear gap, Rayleigh quotient at the top
     say(f"power iteration d={d}")
     g = np.random.default_rng([2212, 7679, 99, d])
     scale = np.linspace(1.0, 2.0, d)
@@ -281,6 +282,22 @@ def test_power_iteration_widths(B, d):
     assert vv @ C @ vv >= (1 - 1e-9) * lam[-1]
     assert abs(vv @ vec[:, -1]) >= 1 - 1e-6
     assert 1 <= v["power_iters"] <= 500
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_direction_near_degenerate(B, d):
+    # two nearly equal top eigenvalues (the uniform square and cube): the
+    # Jacobi solve still returns a top eigenvector, in a few sweeps
+    say(f"direction near-degenerate d={d}")
+    g = np.random.default_rng([2212, 7679, 102, d])
+    P = g.random((50_000, d)).astype(np.float32)
+    v = B.Index(to_dev(P)).view()
+    X = P.astype(np.float64) - P.astype(np.float64).mean(0)
+    C = X.T @ X
+    lam = np.linalg.eigvalsh(C)
+    vv = v["v"].cpu().numpy()
+    assert vv @ C @ vv >= (1 - 1e-12) * lam[-1]
+    assert v["power_iters"] <= 10
 
 
 @pytest.mark.parametrize("n,bits", [(1, (0, 32)), (1000, (0, 32)), (100_003, (0, 32)), (70_000, (8, 32)),
