@@ -128,7 +128,8 @@ __global__ __launch_bounds__(kThreads) void k_recheck_edges(QueryDev q, Survivor
 
 __global__ __launch_bounds__(kThreads) void k_scatter(Survivors sv, const int64_t* __restrict__ row_ptr,
                                                      uint64_t* __restrict__ keys) {
-  const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count) * sv.per;
+  if (*sv.count > (unsigned long long)sv.cap) return;  // overflowed: the host runs the query again
+  const long long cnt = (long long)*sv.count * sv.per;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
        i += (long long)gridDim.x * blockDim.x) {
     const int qo = sv.res_q[i];
@@ -136,6 +137,10 @@ __global__ __launch_bounds__(kThreads) void k_scatter(Survivors sv, const int64_
     keys[row_ptr[qo] + sv.res_slot[i]] = sv.res_key[i];
   }
 }
+
+// false when the move was enqueued before the host checked the sizes and
+// the rows do not fit the destination (then nothing is written)
+__device__ __forceinline__ bool rows_fit(const RowMove& mv) { return !mv.total || *mv.total <= mv.cap; }
 
 // Row length classes: 2..16, 17..32, 33..64, 65..128, 129..256, 257..512 and
 // longer (kRowClasses lists).
@@ -191,6 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_row_classify(const int64_t* __rest
 template <int SEG>
 __global__ __launch_bounds__(kThreads) void k_row_sort_seg(RowMove mv, const int32_t* __restrict__ list,
                                                           const unsigned long long* __restrict__ count) {
+  if (!rows_fit(mv)) return;
   constexpr int kRows = kWave / SEG;
   const long long nrows = (long long)*count;
   const int lane = lane_id(), sub = lane % SEG, grp = lane / SEG;
@@ -231,6 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_seg(RowMove mv, const int
 template <int E>
 __global__ __launch_bounds__(kThreads) void k_row_sort_reg(RowMove mv, const int32_t* __restrict__ list,
                                                           const unsigned long long* __restrict__ count) {
+  if (!rows_fit(mv)) return;
   constexpr int N = kWave * E;
   const long long nrows = (long long)*count;
   const int lane = lane_id();
@@ -316,6 +323,7 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_block(RowMove mv, const i
                                                             int32_t* __restrict__ tmp_col,
                                                             float* __restrict__ tmp_dist) {
   __shared__ uint64_t a[kBlockSort];
+  if (!rows_fit(mv)) return;  // uniform: before any barrier
   const long long nrows = (long long)*count;
   for (long long w = blockIdx.x; w < nrows; w += gridDim.x) {
     const int r = list[w];
@@ -477,20 +485,23 @@ void launch_scatter(const Survivors& sv, const int64_t* row_ptr, uint64_t* keys,
 // class); list_counts: 8 counters; tmp_col / tmp_dist: destination nnz
 // entries, needed only when a row exceeds 4096.  Fixed grids (the counts stay
 // on the device), so the sequence can be captured.
-void launch_row_sort_move(const RowMove& mv, int64_t m, int64_t max_len, int32_t* lists,
-                          unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s) {
+void launch_row_sort_head(const RowMove& mv, int64_t m, int32_t* lists, unsigned long long* list_counts,
+                          hipStream_t s) {
   k_fill_u64<<<1, 64, 0, s>>>(list_counts, 8, 0ull);
   SNN_LAUNCH_CHECK();
-  if (m <= 0 || max_len <= 0) return;
+  if (m <= 0) return;
   k_row_classify<<<grid_for(m, 1024), kThreads, 0, s>>>(mv.src_rp, m, lists, list_counts);
   SNN_LAUNCH_CHECK();
-  // classes whose shortest row exceeds max_len are empty
   k_row_sort_seg<16><<<2048, kThreads, 0, s>>>(mv, lists, list_counts);
   SNN_LAUNCH_CHECK();
-  if (max_len > 16) {
-    k_row_sort_seg<32><<<2048, kThreads, 0, s>>>(mv, lists + m, list_counts + 1);
-    SNN_LAUNCH_CHECK();
-  }
+}
+
+// classes whose shortest row exceeds max_len are empty and not launched
+void launch_row_sort_tail(const RowMove& mv, int64_t m, int64_t max_len, int32_t* lists,
+                          unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s) {
+  if (m <= 0 || max_len <= 16) return;
+  k_row_sort_seg<32><<<2048, kThreads, 0, s>>>(mv, lists + m, list_counts + 1);
+  SNN_LAUNCH_CHECK();
   if (max_len > 32) {
     k_row_sort_seg<64><<<2048, kThreads, 0, s>>>(mv, lists + 2 * m, list_counts + 2);
     SNN_LAUNCH_CHECK();
@@ -511,6 +522,18 @@ void launch_row_sort_move(const RowMove& mv, int64_t m, int64_t max_len, int32_t
     k_row_sort_block<<<512, kThreads, 0, s>>>(mv, lists + 6 * m, list_counts + 6, tmp_col, tmp_dist);
     SNN_LAUNCH_CHECK();
   }
+}
+
+void launch_row_sort_move(const RowMove& mv, int64_t m, int64_t max_len, int32_t* lists,
+                          unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s) {
+  k_fill_u64<<<1, 64, 0, s>>>(list_counts, 8, 0ull);
+  SNN_LAUNCH_CHECK();
+  if (m <= 0 || max_len <= 0) return;
+  k_row_classify<<<grid_for(m, 1024), kThreads, 0, s>>>(mv.src_rp, m, lists, list_counts);
+  SNN_LAUNCH_CHECK();
+  k_row_sort_seg<16><<<2048, kThreads, 0, s>>>(mv, lists, list_counts);
+  SNN_LAUNCH_CHECK();
+  launch_row_sort_tail(mv, m, max_len, lists, list_counts, tmp_col, tmp_dist, s);
 }
 
 void launch_perm_counts(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst, hipStream_t s) {

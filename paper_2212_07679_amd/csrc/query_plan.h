@@ -254,6 +254,7 @@ __host__ __device__ __forceinline__ uint64_t neighbour_key(int32_t id, float dis
 void launch_recheck(const QueryDev& q, const Survivors& sv, snn_dtype dt, const void* po, bool self,
                     int32_t* row_cnt, int grid, hipStream_t s);
 // keys into slot-order rows at row_ptr[row] + slot
+// (does nothing when the survivor list overflowed: *sv.count > sv.cap)
 void launch_scatter(const Survivors& sv, const int64_t* row_ptr, uint64_t* keys, int grid, hipStream_t s);
 // self-queries for clustering: row counts of both points of every accepted
 // pair, res_q[i] = query slot of survivor i if accepted else -1 (one entry
@@ -277,6 +278,10 @@ struct RowMove {
   const int64_t* dst_rp;
   int32_t* dst_col;
   float* dst_dist;
+  // optional guard for moves enqueued before the host has checked the
+  // sizes: nothing is written unless *total <= cap (total NULL: no guard)
+  const unsigned long long* total;
+  unsigned long long cap;
 };
 // lists: row_sort_lists() x m int32, list_counts: 8 counters, tmp_col /
 // tmp_dist: destination nnz entries (may be NULL when no row exceeds 4096)
@@ -284,6 +289,13 @@ int row_sort_lists();
 // max_len: an upper bound on the row lengths when the host knows one (the
 // kernels of longer length classes are not launched), else INT64_MAX
 void launch_row_sort_move(const RowMove& mv, int64_t m, int64_t max_len, int32_t* lists,
+                          unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s);
+// The same in two parts: the head (class lists and rows of up to 16 entries)
+// needs no host-side size, so it can be enqueued before the sizes are read
+// back; the tail launches the longer classes up to max_len.
+void launch_row_sort_head(const RowMove& mv, int64_t m, int32_t* lists, unsigned long long* list_counts,
+                          hipStream_t s);
+void launch_row_sort_tail(const RowMove& mv, int64_t m, int64_t max_len, int32_t* lists,
                           unsigned long long* list_counts, int32_t* tmp_col, float* tmp_dist, hipStream_t s);
 // cnt_dst[map[r]] = length of source row r
 void launch_perm_counts(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst, hipStream_t s);

@@ -435,6 +435,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   long long cap = std::max<long long>(1 << 16, (long long)(ix.ws[1].bytes / per_bytes));
   HostCtl hc{};
   uint64_t* stage_key = nullptr;  // neighbour keys in slot-order rows
+  RowMove mv{};                   // their move to the caller's rows
   for (int attempt = 0;; ++attempt) {
     // five arrays, each padded to 256 bytes by the carver
     const size_t need = (size_t)cap * per_bytes + 2048;
@@ -503,6 +504,22 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     // counts in the caller's order, the longest row and the total in one pass
     launch_perm_counts_stats(P.rp_s, m, qorig, P.cnt_o, &P.ctl->row_max, &P.ctl->nnz, s);
     exclusive_scan_i32_to_i64(P.cnt_o, out->row_ptr, m, P.scan_scratch, s);
+    // The assembly of rows of up to 16 neighbours is enqueued before the
+    // sizes are read back, so the device does not wait for the host in
+    // between: the staging rows hold every neighbour this attempt can
+    // produce (cap x per), the scatter does nothing when the survivor list
+    // overflowed, and the moves write nothing when the rows exceed the
+    // caller's capacity (the host then retries or reports it, as below).
+    {
+      const size_t stage_n = (size_t)cap * per;
+      ix.ws[3].ensure(ix.arena, stage_n * 8 + 512);
+      Carver gc(ix.ws[3].ptr);
+      stage_key = gc.take<uint64_t>(stage_n);
+    }
+    launch_scatter(sv, P.rp_s, stage_key, di.cus * 16, s);
+    mv = RowMove{P.rp_s, stage_key, qorig, out->row_ptr, out->col, out->dist, &P.ctl->nnz,
+                 (unsigned long long)out->nnz_cap};
+    launch_row_sort_head(mv, m, P.lists, P.ctl->list_counts, s);
     SNN_HIP(hipMemcpyAsync(&hc.ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     SNN_HIP(hipStreamSynchronize(s));
     hc.nnz = (int64_t)hc.ctl.nnz;
@@ -523,11 +540,6 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
                       (long long)hc.nnz);
         throw Error(SNN_EOVERFLOW, buf);
       }
-      // neighbours into slot-order staging rows
-      ix.ws[3].ensure(ix.arena, (size_t)hc.nnz * 8 + 512);
-      Carver gc(ix.ws[3].ptr);
-      stage_key = gc.take<uint64_t>(hc.nnz);
-      launch_scatter(sv, P.rp_s, stage_key, di.cus * 16, s);
       break;
     }
     cap = (long long)(hc.ctl.survivors * 5 / 4) + 1024;
@@ -558,8 +570,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     tmp_col = tc.take<int32_t>(hc.nnz);
     tmp_dist = tc.take<float>(hc.nnz);
   }
-  const RowMove mv{P.rp_s, stage_key, qorig, out->row_ptr, out->col, out->dist};
-  launch_row_sort_move(mv, m, (int64_t)hc.ctl.row_max, P.lists, P.ctl->list_counts, tmp_col, tmp_dist, s);
+  launch_row_sort_tail(mv, m, (int64_t)hc.ctl.row_max, P.lists, P.ctl->list_counts, tmp_col, tmp_dist, s);
 
   if (st) {
     SNN_HIP(hipEventRecord(ev[3], s));
