@@ -378,7 +378,8 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
                      p.cthr, s);
   batch_windows(b, p.key, p.qa, p.qn, p.qorig, p.tlo, p.thi, p.ctl, s);
   const int ngroups = (p.ntiles + p.G - 1) / p.G;
-  launch_tile_plan(p.tlo, p.thi, p.ntiles, p.CH, 32, 0, p.units, p.G, p.group_off, p.gbase, p.T, p.MS, 1, nullptr, s);
+  launch_tile_plan(p.tlo, p.thi, p.ntiles, p.CH, 32, 0, p.units, p.G, p.group_off, p.gbase, p.T, p.MS, 1, nullptr,
+                   nullptr, 0, nullptr, s);
   batch_executed(b, p.tlo, p.thi, p.T / 4, p.ctl, s);
 
   QueryDev qd{};

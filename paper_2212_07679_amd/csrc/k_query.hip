@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_window(const double* __restrict__ 
                                                     double eps_scale, int T, int sym, int32_t* __restrict__ lo_out,
                                                     int32_t* __restrict__ hi_out, int32_t* __restrict__ tlo,
                                                     int32_t* __restrict__ thi,
-                                                    unsigned long long* __restrict__ pairs_window) {
+                                                    unsigned long long* __restrict__ wpart) {
   const double u = 1.1102230246251565e-16;
   __shared__ unsigned long long red[kThreads / kWave];
   unsigned long long acc = 0;  // this lane's window sizes over the grid-stride loop
@@ -159,14 +159,15 @@ __global__ __launch_bounds__(kThreads) void k_window(const double* __restrict__ 
       atomicMax(&thi[tile], whi);
     }
   }
-  // one counter atomic per block (same-address atomics serialise)
+  // one partial count per workgroup, summed by k_tile_plan (atomics on a
+  // single address serialise)
   const unsigned long long wc = wave_sum(acc);
   if (lane_id() == 0) red[threadIdx.x / kWave] = wc;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long c = 0;
     for (int w = 0; w < kThreads / kWave; ++w) c += red[w];
-    if (c) atomicAdd(pairs_window, c);
+    wpart[blockIdx.x] = c;
   }
 }
 
@@ -200,9 +201,24 @@ constexpr int kAbsChunks = 8;
 __global__ __launch_bounds__(1024) void k_tile_plan(int32_t* __restrict__ tlo, int32_t* __restrict__ thi, int ntiles,
                                                    int CH, int align, int sym_T, int32_t* __restrict__ units, int G,
                                                    int64_t* __restrict__ unit_off, int32_t* __restrict__ gbase, int T,
-                                                   int64_t m, int qpw, unsigned long long* __restrict__ executed) {
+                                                   int64_t m, int qpw, unsigned long long* __restrict__ executed,
+                                                   const unsigned long long* __restrict__ wpart, int nwpart,
+                                                   unsigned long long* __restrict__ pairs_window) {
   __shared__ int64_t carry;
   __shared__ int64_t wsum[1024 / kWave];
+  if (pairs_window) {  // the window-pair total from the per-workgroup partials
+    __shared__ unsigned long long pw_s[1024 / kWave];
+    unsigned long long pw = 0;
+    for (int b = threadIdx.x; b < nwpart; b += blockDim.x) pw += wpart[b];
+    pw = wave_sum(pw);
+    if (lane_id() == 0) pw_s[threadIdx.x / kWave] = pw;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long t = 0;
+      for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += pw_s[w];
+      *pairs_window = t;
+    }
+  }
   unsigned long long e = 0;
   for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
     int a = tlo[t], b = thi[t];
@@ -367,20 +383,23 @@ void launch_query_init(unsigned long long* ctl, int ctl_words, int32_t* row_cnt,
   SNN_LAUNCH_CHECK();
 }
 
+int window_blocks(int64_t m) { return m > 0 ? grid_for(m, kWindowMaxBlocks) : 0; }
+
 void launch_windows(const double* key, int n, const double* qalpha, const double* qnorm, int64_t m, double w_base,
                     double eps_scale, int T, int sym, int32_t* lo, int32_t* hi, int32_t* tlo, int32_t* thi,
-                    unsigned long long* pairs_window, hipStream_t s) {
+                    unsigned long long* wpart, hipStream_t s) {
   if (m <= 0) return;
-  k_window<<<grid_for(m, 2048), kThreads, 0, s>>>(key, n, qalpha, qnorm, m, w_base, eps_scale, T, sym, lo, hi, tlo,
-                                                  thi, pairs_window);
+  k_window<<<window_blocks(m), kThreads, 0, s>>>(key, n, qalpha, qnorm, m, w_base, eps_scale, T, sym, lo, hi, tlo,
+                                                 thi, wpart);
   SNN_LAUNCH_CHECK();
 }
 
 void launch_tile_plan(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int sym, int32_t* units, int G,
                       int64_t* unit_off, int32_t* gbase, int T, int64_t m, int qpw, unsigned long long* executed,
+                      const unsigned long long* wpart, int nwpart, unsigned long long* pairs_window,
                       hipStream_t s) {
   k_tile_plan<<<1, 1024, 0, s>>>(tlo, thi, ntiles, CH, align, sym ? T : 0, units, G, unit_off, gbase, T, m, qpw,
-                                 executed);
+                                 executed, wpart, nwpart, pairs_window);
   SNN_LAUNCH_CHECK();
 }
 

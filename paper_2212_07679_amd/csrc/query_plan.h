@@ -122,9 +122,13 @@ void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, 
 // mixed screen reads 32-row blocks); extra candidates never change results.
 // sym: symmetric self-query (counts only candidates j >= s, tiles start at
 // their first row; see QueryDev::sym)
+// k_window writes one partial window-pair count per workgroup (wpart, at
+// most kWindowMaxBlocks of them: window_blocks(m)); k_tile_plan sums them
+constexpr int kWindowMaxBlocks = 2048;
+int window_blocks(int64_t m);
 void launch_windows(const double* key, int n, const double* qalpha, const double* qnorm, int64_t m, double w_base,
                     double eps_scale, int T, int sym, int32_t* lo, int32_t* hi, int32_t* tlo, int32_t* thi,
-                    unsigned long long* pairs_window, hipStream_t s);
+                    unsigned long long* wpart, hipStream_t s);
 // one launch: zero ctl_words control words, row_cnt (m) and hist (nb, may be
 // NULL), and empty tile windows (tlo = INT_MAX, thi = INT_MIN)
 void launch_query_init(unsigned long long* ctl, int ctl_words, int32_t* row_cnt, int64_t m, uint32_t* hist, int nb,
@@ -133,8 +137,11 @@ void launch_query_init(unsigned long long* ctl, int ctl_words, int32_t* row_cnt,
 // aligned, units per tile, G x max units per group of G tiles scanned into
 // unit_off (ngroups + 1 entries), evaluated pairs added to *executed
 // (nullable; qpw query slots per wavefront)
+// wpart / nwpart / pairs_window: the window-pair partials of k_window and
+// their total (NULL / 0 / NULL when there are none)
 void launch_tile_plan(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int sym, int32_t* units, int G,
                       int64_t* unit_off, int32_t* gbase, int T, int64_t m, int qpw, unsigned long long* executed,
+                      const unsigned long long* wpart, int nwpart, unsigned long long* pairs_window,
                       hipStream_t s);
 
 

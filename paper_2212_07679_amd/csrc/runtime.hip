@@ -283,6 +283,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       int32_t* units;
       int64_t* unit_off;
       int32_t* gbase;
+      unsigned long long* wpart;
       char* scan_scratch;
       Ctl* ctl;
       int32_t* row_cnt;  // per query slot
@@ -310,6 +311,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     p.units = c.take<int32_t>(ntiles);
     p.unit_off = c.take<int64_t>(ntiles + 1);
     p.gbase = c.take<int32_t>(ntiles);
+    p.wpart = c.take<unsigned long long>(kWindowMaxBlocks);
     p.scan_scratch = c.take<char>(std::max({scan_scratch_bytes(ntiles), scan_scratch_bytes(std::max<int64_t>(m, 1)),
                                             scan_scratch_bytes(nbuckets)}));
     p.ctl = c.take<Ctl>(1);
@@ -364,7 +366,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   // self-queries scan each unordered pair once (S is exactly symmetric)
   const int sym = (self && !o.full_self_scan) ? 1 : 0;
   launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, sym, P.lo, P.hi, P.tlo, P.thi,
-                 &P.ctl->pairs_window, s);
+                 P.wpart, s);
   // query slots per wavefront (stats): the matrix-core screens evaluate
   // whole 32-query blocks, the float64 screen one query at a time
   const int qpw = prec == SNN_PREC_MIXED  ? mixed_queries_per_wave(ka_of(terms))
@@ -374,7 +376,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const int G = prec == SNN_PREC_FP64 ? 16 : 8;
   const int ngroups = (ntiles + G - 1) / G;
   launch_tile_plan(P.tlo, P.thi, ntiles, CH, prec == SNN_PREC_FP64 ? 1 : 32, sym, P.units, G, P.unit_off, P.gbase,
-                   T, m, qpw, st ? &P.ctl->executed : nullptr, s);
+                   T, m, qpw, st ? &P.ctl->executed : nullptr, P.wpart, window_blocks(m), &P.ctl->pairs_window, s);
 
   QueryDev qd{};
   qd.G = G;
