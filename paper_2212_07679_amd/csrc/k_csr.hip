@@ -158,6 +158,10 @@ __device__ __forceinline__ int row_class(const int64_t* __restrict__ row_ptr, in
   return 6;
 }
 
+// about 4096 rows per workgroup (at most 1024 workgroups): each reserves
+// list space with one atomic per class, and atomics on one address serialise
+inline int classify_blocks(int64_t m) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, m / 4096)); }
+
 // Rows by length class, each class appended to its own list.  A block owns a
 // contiguous range of rows: it counts its rows per class in LDS, reserves
 // each class's space with one global atomic, then writes (so the global
@@ -420,7 +424,11 @@ __global__ __launch_bounds__(kThreads) void k_perm_counts_stats(const int64_t* _
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < kThreads / kWave; ++w) v = max(v, red[w]);
-    if (v > 0) atomicMax(row_max, (unsigned long long)v);
+    // the maximum only grows, so a workgroup that cannot raise it skips the
+    // atomic (atomics on one address serialise); a stale read only costs an
+    // unneeded atomic
+    if (v > 0 && (unsigned long long)v > __hip_atomic_load(row_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(row_max, (unsigned long long)v);
     if (blockIdx.x == 0) *total = (unsigned long long)src_rp[m];
   }
 }
@@ -490,7 +498,7 @@ void launch_row_sort_head(const RowMove& mv, int64_t m, int32_t* lists, unsigned
   k_fill_u64<<<1, 64, 0, s>>>(list_counts, 8, 0ull);
   SNN_LAUNCH_CHECK();
   if (m <= 0) return;
-  k_row_classify<<<grid_for(m, 1024), kThreads, 0, s>>>(mv.src_rp, m, lists, list_counts);
+  k_row_classify<<<classify_blocks(m), kThreads, 0, s>>>(mv.src_rp, m, lists, list_counts);
   SNN_LAUNCH_CHECK();
   k_row_sort_seg<16><<<2048, kThreads, 0, s>>>(mv, lists, list_counts);
   SNN_LAUNCH_CHECK();
@@ -529,7 +537,7 @@ void launch_row_sort_move(const RowMove& mv, int64_t m, int64_t max_len, int32_t
   k_fill_u64<<<1, 64, 0, s>>>(list_counts, 8, 0ull);
   SNN_LAUNCH_CHECK();
   if (m <= 0 || max_len <= 0) return;
-  k_row_classify<<<grid_for(m, 1024), kThreads, 0, s>>>(mv.src_rp, m, lists, list_counts);
+  k_row_classify<<<classify_blocks(m), kThreads, 0, s>>>(mv.src_rp, m, lists, list_counts);
   SNN_LAUNCH_CHECK();
   k_row_sort_seg<16><<<2048, kThreads, 0, s>>>(mv, lists, list_counts);
   SNN_LAUNCH_CHECK();
