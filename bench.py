@@ -137,54 +137,94 @@ def make_workload(name, n, m):
 
 
 def run_query(idx, w, Qdev, prec):
+    if w.alpha is not None:  # angular neighbours of unit rows: the library takes the angle
+        return idx.query(Qdev, w.alpha, precision=prec, stats=True, metric="angular")
     if w.Q is None:
         return idx.query_self(w.R, precision=prec, stats=True)
     return idx.query(Qdev, w.R, precision=prec, stats=True)
 
 
 def time_precision(idx, w, Qdev, prec, steps, warmup, torch):
+    """W warm-ups, then K steps bracketed by synchronisations; each step is
+    also bracketed by its own events on the library's stream, for the median."""
     for _ in range(warmup):
         out = run_query(idx, w, Qdev, prec)
     torch.cuda.synchronize()
     screen = []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record(idx.stream)
-    for _ in range(steps):
+    ev[0].record(idx.stream)
+    for k in range(steps):
         out = run_query(idx, w, Qdev, prec)
+        ev[k + 1].record(idx.stream)
         screen.append(out[3]["screen_ms"])
-    stop.record(idx.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ev_ms = start.elapsed_time(stop)
-    return out, wall, ev_ms, sum(screen) / len(screen)
+    per = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))
+    ev_ms = ev[0].elapsed_time(ev[steps])
+    med = per[steps // 2] if steps % 2 else 0.5 * (per[steps // 2 - 1] + per[steps // 2])
+    return out, wall, ev_ms, med, sum(screen) / len(screen)  # the screen kernel's average duration
+
+
+def host_cpu():
+    """Model name and logical core count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
 
 
 def cpu_baseline(w, sample):
+    """The oracle's CPU SNN (Algorithms 1-2 with float64 BLAS) on a seeded
+    sample of the queries, with the BLAS threads the host offers and again on
+    one thread (the paper's own timings are single-threaded)."""
     import numpy as np
 
     import oracle
 
-    try:
-        from threadpoolctl import threadpool_info
-
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    cores = oracle_cores()
     g = np.random.default_rng(0)
     sel = np.sort(g.choice(w.m, size=min(sample, w.m), replace=False))
     t0 = time.perf_counter()
     idx = oracle.build_index(w.P)
     t1 = time.perf_counter()
-    nb, st = oracle.snn_query(idx, w.queries[sel], w.R)
+
+    def run(rows):
+        if w.alpha is not None:
+            from oracle.metrics import snn_angular
+
+            return snn_angular(idx, w.queries[rows], w.alpha)
+        return oracle.snn_query(idx, w.queries[rows], w.R)
+
+    nb, st = run(sel)
     t2 = time.perf_counter()
+    one = None
+    try:
+        from threadpoolctl import threadpool_limits
+
+        sel1 = sel[: max(1, len(sel) // 4)]
+        with threadpool_limits(limits=1):
+            t3 = time.perf_counter()
+            run(sel1)
+            one = {"value": len(sel1) / (time.perf_counter() - t3), "sample": f"first {len(sel1)} of the sample"}
+    except Exception as e:  # threadpoolctl unavailable: report only the multi-thread figure
+        one = {"value": None, "error": str(e)}
+    model, ncpu = host_cpu()
     return {
         "value": len(sel) / (t2 - t1),
         "unit": "queries/s",
         "cores": int(cores),
         "kind": "oracle",
         "sample": f"{len(sel)} of the {w.m} queries (seeded), index built separately in {t1 - t0:.1f} s",
+        "single_thread": one,
+        "host_cpu": model,
+        "host_logical_cpus": ncpu,
     }, (sel, nb)
 
 
@@ -317,7 +357,7 @@ def main_batch(a):
             for k in range(min(take, 8)):
                 assert np.array_equal(col[rp[k]:rp[k + 1]], nb.col[nb.row_ptr[k]:nb.row_ptr[k + 1]]), \
                     f"instance {i} query {k} differs from the oracle"
-        cpu = {"value": done / tq, "unit": "queries/s", "cores": oracle_cores(), "kind": "oracle",
+        cpu = {"value": done / tq, "unit": "queries/s", "cores": oracle_cores(), "kind": "oracle", "host_cpu": host_cpu()[0],
                "sample": f"first {done} queries (up to 64 each) of {used} seeded-random instances; "
                          "index builds not timed"}
 
@@ -423,7 +463,7 @@ def main_dbscan(a):
         t0 = time.perf_counter()
         oracle.dbscan(ws.P, eps, min_samples)
         tc = time.perf_counter() - t0
-        cpu = {"value": ns / tc, "unit": "points/s", "cores": oracle_cores(), "kind": "oracle",
+        cpu = {"value": ns / tc, "unit": "points/s", "cores": oracle_cores(), "kind": "oracle", "host_cpu": host_cpu()[0],
                "sample": f"the blobs3d recipe at n={ns} with {kb} blobs (same points per blob), eps={eps}, "
                          f"min_samples={min_samples}; brute-force lists + DBSCAN, {tc:.1f} s"}
     line = {
@@ -513,7 +553,7 @@ def main_stream(a):
         t0 = time.perf_counter()
         oracle.build_index(w.P[:ns])
         tc = time.perf_counter() - t0
-        cpu = {"value": ns / tc, "unit": "points/s", "cores": oracle_cores(), "kind": "oracle",
+        cpu = {"value": ns / tc, "unit": "points/s", "cores": oracle_cores(), "kind": "oracle", "host_cpu": host_cpu()[0],
                "sample": f"the oracle's index build (Algorithm 1) of {ns} rows of the same mixture, {tc:.2f} s"}
     line = {
         "metric": "streaming insert points/s into an exact SNN index",
@@ -577,11 +617,8 @@ def main():
     Qdev = torch.from_numpy(w.Q).to(dev) if w.Q is not None else None
     normalize_ms = None
     if w.alpha is not None:
-        # angular neighbours: a Euclidean search of the rows normalised on the
-        # device, with R = sqrt(2 - 2 cos alpha)
-        import dataclasses
-
-        w = dataclasses.replace(w, R=binding.angular_radius(w.alpha))
+        # angular neighbours: rows normalised on the device, then a search by
+        # angle (the library compares S with the squared chord 2 - 2 cos alpha)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         binding.normalize_rows(X, out=X)
@@ -599,11 +636,12 @@ def main():
 
     results = {}
     for prec in precisions:
-        out, wall, ev_ms, screen_ms = time_precision(idx, w, Qdev, prec, a.steps, a.warmup, torch)
+        out, wall, ev_ms, med_ms, screen_ms = time_precision(idx, w, Qdev, prec, a.steps, a.warmup, torch)
         st = out[3]
         results[prec] = {
-            "qps": w.m * a.steps / (ev_ms / 1e3),
-            "ms_per_step": ev_ms / a.steps,
+            "qps": w.m / (med_ms / 1e3),
+            "ms_per_step": med_ms,
+            "mean_ms_per_step": ev_ms / a.steps,
             "wall_ms_per_step": wall * 1e3 / a.steps,
             "screen_ms": screen_ms,
             "stats": st,
@@ -648,12 +686,15 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": r["ms_per_step"],
+        "timing": "value and ms_per_step: median of the K steps, each bracketed by HIP events on the library's "
+                  "stream; mean_ms_per_step: the K steps between one pair of events",
+        "mean_ms_per_step": r["mean_ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"mixed": "bf16+f64", "fp32": "f32+f64", "fp64": "f64"}[used],
         "data": "synthetic",
-        "config": {"workload": spec["desc"], "n": w.n, "d": w.d, "m": w.m, "R": w.R, "self_query": w.Q is None,
+        "config": {"workload": spec["desc"], "n": w.n, "d": w.d, "m": w.m, "R": (None if w.alpha is not None else w.R), "self_query": w.Q is None,
                    "precision": used, "terms": st["terms_used"],
                    **({"alpha_deg": math.degrees(w.alpha), "normalize_ms": normalize_ms} if w.alpha is not None
                       else {})},

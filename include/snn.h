@@ -73,11 +73,17 @@ typedef enum { SNN_PREC_FP64 = 0, SNN_PREC_MIXED = 1, SNN_PREC_AUTO = 2, SNN_PRE
  *     the Euclidean ball of radius R (the 2-norm never exceeds the 1-norm),
  *     so the Euclidean window and screen, run with R widened by the rounding
  *     of M, find a superset that the float64 recheck decides by M.
- * Angular and cosine neighbours are Euclidean neighbours of normalised rows
- * (snn_normalize_rows): angle <= a iff ||u - v||^2 <= 2 - 2 cos(a), cosine
- * distance <= c iff ||u - v||^2 <= 2c, so they are L2 queries with
- * R = sqrt(2 - 2 cos a) or sqrt(2c). */
-typedef enum { SNN_METRIC_L2 = 0, SNN_METRIC_L1 = 1 } snn_metric;
+ * ANGULAR and COSINE: on unit vectors the angle is at most a iff
+ *     ||u - v||^2 <= 2 - 2 cos(a), and the cosine distance is ||u - v||^2 / 2,
+ *     so both are Euclidean searches of normalised rows (snn_normalize_rows;
+ *     the rows are used as given) with the squared threshold
+ *       ANGULAR: R = a in radians, 0 <= a <= pi:  T = fl(2 - 2 cos(a)),
+ *                cos the host C library's double cosine;
+ *       COSINE:  R = c >= 0:                       T = fl(2 c);
+ *     N(q) = { i : S(p_i, q) <= T } with S the normative sum above, and
+ *     dist = fl32(2 asin(min(1, sqrt(S) / 2))) (the angle, radians) or
+ *     fl32(S / 2) (the cosine distance), evaluated in float64. */
+typedef enum { SNN_METRIC_L2 = 0, SNN_METRIC_L1 = 1, SNN_METRIC_ANGULAR = 2, SNN_METRIC_COSINE = 3 } snn_metric;
 
 typedef struct {
   /* Device allocator; both NULL selects hipMalloc/hipFree.  alloc returns

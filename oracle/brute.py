@@ -69,14 +69,22 @@ def brute_radius(P, Q, R: float, max_block_elems: int = 1 << 22) -> Neighbors:
     P: (n, d), Q: (m, d), R >= 0 finite.  Returns CSR with ascending ids per
     row and dist = fl32(sqrt(S)) computed in float64.
     """
+    R = float(R)
+    if not np.isfinite(R) or R < 0:
+        raise ValueError("R must be finite and >= 0")
+    return brute_sq_threshold(P, Q, R * R, max_block_elems)  # Python float multiply: one rounding
+
+
+def brute_sq_threshold(P, Q, T2: float, max_block_elems: int = 1 << 22) -> Neighbors:
+    """All i with S(P[i], Q[r]) <= T2 (a squared threshold given directly,
+    e.g. the squared chord of an angle on unit vectors), dist = fl32(sqrt(S))."""
     P = _f64(P)
     Q = _f64(Q)
     if P.ndim != 2 or Q.ndim != 2 or P.shape[1] != Q.shape[1]:
         raise ValueError("P and Q must be 2-D with the same number of columns")
-    R = float(R)
-    if not np.isfinite(R) or R < 0:
-        raise ValueError("R must be finite and >= 0")
-    R2 = R * R  # Python float multiply: one float64 rounding
+    R2 = float(T2)
+    if not np.isfinite(R2) or R2 < 0:
+        raise ValueError("the threshold must be finite and >= 0")
     n, m = P.shape[0], Q.shape[0]
     counts = np.zeros(m, dtype=np.int64)
     cols, dists = [], []

@@ -34,6 +34,7 @@ hold (each one is listed in the design notes):
 from __future__ import annotations
 
 from dataclasses import dataclass
+from fractions import Fraction
 
 import numpy as np
 
@@ -122,7 +123,7 @@ def _window(index: SnnIndex, aq: np.ndarray, qnorm: np.ndarray, R: float, d: int
     return lo, hi
 
 
-def query(index: SnnIndex, Q, R: float, block: int = 64, literal: bool = False):
+def query(index: SnnIndex, Q, R: float, block: int = 64, literal: bool = False, R2=None):
     """Algorithm 2 for every row of Q.  Returns (Neighbors, stats).
 
     block == 1 runs one gemv per query as printed; block > 1 sorts the
@@ -133,6 +134,9 @@ def query(index: SnnIndex, Q, R: float, block: int = 64, literal: bool = False):
     stats: pairs_window = sum_q |J_q|, band = pairs re-decided with the
     normative S, literal_diff = pairs where the printed test (no band)
     would decide differently.
+
+    R2: the squared threshold S is compared with (default fl(R*R)); when
+    given, R must satisfy R^2 >= R2 exactly, since the window is cut with R.
     """
     Q = np.ascontiguousarray(np.asarray(Q), dtype=np.float64)
     m, d = Q.shape
@@ -141,7 +145,11 @@ def query(index: SnnIndex, Q, R: float, block: int = 64, literal: bool = False):
     R = float(R)
     if not np.isfinite(R) or R < 0:
         raise ValueError("R must be finite and >= 0")
-    R2 = R * R
+    if R2 is None:
+        R2 = R * R
+    elif not (0.0 <= float(R2) and Fraction(R) ** 2 >= Fraction(float(R2))):
+        raise ValueError("R2 must be >= 0 and at most R^2")
+    R2 = float(R2)
     xq = Q - index.mu  # step 2
     aq = xq @ index.v  # step 3
     qn2 = np.einsum("ij,ij->i", xq, xq)

@@ -10,7 +10,6 @@ no fallback path.
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 from typing import Optional, Tuple
 
@@ -23,7 +22,7 @@ SNN_OK, SNN_EINVAL, SNN_ENOMEM, SNN_EDEVICE, SNN_EOVERFLOW, SNN_ENOTSUP = 0, -1,
 SNN_F32, SNN_F64 = 0, 1
 PRECISION = {"fp64": 0, "mixed": 1, "auto": 2, "fp32": 3}
 PRECISION_NAMES = {v: k for k, v in PRECISION.items()}
-METRIC = {"l2": 0, "l1": 1}
+METRIC = {"l2": 0, "l1": 1, "angular": 2, "cosine": 3}
 
 STATUS_NAMES = {
     SNN_OK: "SNN_OK",
@@ -328,8 +327,10 @@ class Index:
 
     def query(self, Q: torch.Tensor, R: float, precision: str = "auto", terms: int = 0, tile_q: int = 0,
               tile_c: int = 0, nnz_cap: Optional[int] = None, stats: bool = False, metric: str = "l2"):
-        """Algorithm 2 for the rows of Q (m x d, same dtype and device);
-        ``metric="l1"`` for Manhattan neighbours."""
+        """Algorithm 2 for the rows of Q (m x d, same dtype and device).
+        ``metric``: "l2" (radius R), "l1" (Manhattan radius R), "angular"
+        (R = angle in radians) or "cosine" (R = cosine distance); the last
+        two expect unit rows (``normalize_rows``)."""
         if not isinstance(Q, torch.Tensor) or not Q.is_cuda or Q.dim() != 2 or Q.shape[1] != self.d:
             raise SnnError(SNN_EINVAL, "Q must be a CUDA tensor of shape (m, d)")
         if Q.dtype != self.dtype:
@@ -426,17 +427,6 @@ def normalize_rows(X: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch
     _check(lib().snn_normalize_rows(ctypes.byref(alloc.dev), ctypes.c_void_p(X.data_ptr()), X.shape[0], X.shape[1],
                                     _dtype_code(X), ctypes.c_void_p(out.data_ptr())))
     return out
-
-
-def angular_radius(alpha: float) -> float:
-    """Euclidean radius on unit vectors for angles at most ``alpha`` (radians):
-    sqrt(2 - 2 cos(alpha))."""
-    return math.sqrt(max(0.0, 2.0 - 2.0 * math.cos(alpha)))
-
-
-def cosine_radius(c: float) -> float:
-    """Euclidean radius on unit vectors for cosine distance at most ``c``: sqrt(2c)."""
-    return math.sqrt(2.0 * c)
 
 
 def dbscan_csr(row_ptr: torch.Tensor, col: torch.Tensor, min_samples: int = 5,

@@ -336,13 +336,8 @@ snn_status snn_dbscan(const snn_device* dev, int64_t n, const int64_t* row_ptr, 
     sz.take<uint8_t>(core ? 1 : n);            // core flags when the caller passes none
     sz.take<char>(scan_scratch_bytes(n));
     sz.take<int>(1);                           // bad flag
-    void* mem = a.alloc(sz.off);
-    struct Release {
-      DeviceArena& a;
-      void* p;
-      ~Release() { a.release(p); }
-    } rel{a, mem};
-    Carver c(mem);
+    ScopedAlloc scratch_mem(a, sz.off);
+    Carver c(scratch_mem.get());
     int32_t* parent = c.take<int32_t>(n);
     int32_t* is_root = c.take<int32_t>(n);
     int64_t* rank = c.take<int64_t>(n + 1);

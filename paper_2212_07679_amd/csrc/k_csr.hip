@@ -45,6 +45,16 @@ __device__ __forceinline__ double pair_measure(int metric, const A* __restrict__
   return s;
 }
 
+// Reported distance of an accepted pair from its measure s: the 1-norm (L1),
+// the angle 2 asin(sqrt(S) / 2) or the cosine distance S / 2 of unit rows
+// (Section 2), else the Euclidean distance sqrt(S); float64, rounded once.
+__device__ __forceinline__ float pair_distance(int metric, double s) {
+  if (metric == SNN_METRIC_L1) return (float)s;
+  if (metric == SNN_METRIC_ANGULAR) return (float)(2.0 * asin(fmin(1.0, 0.5 * sqrt(s))));
+  if (metric == SNN_METRIC_COSINE) return (float)(0.5 * s);
+  return (float)sqrt(s);
+}
+
 // Data rows are read in the input dtype (their promotion to float64 is
 // exact), the query rows of a self-query likewise; out-of-sample query rows
 // are the float64 copies.
@@ -72,7 +82,7 @@ __global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, 
     if (keep) {
       // rows are query slots (score order): a tile's rows are neighbours in
       // memory, so the counters and the later writes stay cache-local
-      const float dist = (float)(q.metric == SNN_METRIC_L1 ? s : sqrt(s));
+      const float dist = pair_distance(q.metric, s);
       sv.res_q[r0] = pr.x;
       sv.res_key[r0] = neighbour_key(q.perm[pr.y], dist);
       sv.res_slot[r0] = atomicAdd(&row_cnt[pr.x], 1);

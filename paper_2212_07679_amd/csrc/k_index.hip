@@ -958,7 +958,8 @@ void build_index_t(Index& ix, const T* X) {
   const size_t off_bmax = off_C + ((sizeof(double) * dd + 255) & ~size_t(255));
   const size_t off_keys = off_bmax + ((sizeof(double) * proj_cap + 255) & ~size_t(255));
   const size_t total = off_keys + 2 * sizeof(uint32_t) * n + 256;
-  char* mem = static_cast<char*>(ix.arena.alloc(total));
+  ScopedAlloc scratch(ix.arena, total);
+  char* mem = static_cast<char*>(scratch.get());
   Scratch* sc = reinterpret_cast<Scratch*>(mem);
   double* part1 = reinterpret_cast<double*>(mem + off_part1);
   double* part2 = reinterpret_cast<double*>(mem + off_part2);
@@ -1017,7 +1018,6 @@ void build_index_t(Index& ix, const T* X) {
   Scratch hs;
   SNN_HIP(hipMemcpyAsync(&hs, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
   SNN_HIP(hipStreamSynchronize(s));
-  ix.arena.release(mem);
   if (hs.bad) fail(SNN_EINVAL, "snn_index: X contains NaN or Inf");
   std::vector<double> vh(d);
   SNN_HIP(hipMemcpy(vh.data(), ix.v.ptr, sizeof(double) * d, hipMemcpyDeviceToHost));
@@ -1127,13 +1127,8 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   sz.take<float>(k);                  // ynorm
   sz.take<int64_t>(nt);               // merge sources
   sz.take<double>(4 * di.cus * 8);    // per-workgroup norm maxima
-  void* mem = ix.arena.alloc(sz.off);
-  struct Release {
-    DeviceArena& a;
-    void* p;
-    ~Release() { a.release(p); }
-  } rel{ix.arena, mem};
-  Carver c(mem);
+  ScopedAlloc scratch(ix.arena, sz.off);
+  Carver c(scratch.get());
   Scratch* sc = c.take<Scratch>(1);
   uint32_t* ukey = c.take<uint32_t>(k);
   uint32_t* val = c.take<uint32_t>(k);
@@ -1163,6 +1158,15 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   k_merge_path<<<grid_for(nt, kThreads, 4 * di.cus * 8), kThreads, 0, s>>>(ix.key.as<double>(), na, keyb, k, src);
   SNN_LAUNCH_CHECK();
   Buffer key, perm, po, p64, ys, h, ynorm;
+  // released at scope end: after the swaps below these hold the old arrays,
+  // and on an error part way the new ones
+  struct ReleaseAll {
+    DeviceArena& a;
+    std::initializer_list<Buffer*> bufs;
+    ~ReleaseAll() {
+      for (Buffer* b : bufs) b->reset(a);
+    }
+  } release_all{ix.arena, {&key, &perm, &po, &p64, &ys, &h, &ynorm}};
   key.ensure(ix.arena, sizeof(double) * nt);
   perm.ensure(ix.arena, sizeof(int32_t) * nt);
   po.ensure(ix.arena, sizeof(T) * nt * d);
@@ -1187,7 +1191,6 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   std::swap(ix.ys, ys);
   std::swap(ix.h, h);
   std::swap(ix.ynorm, ynorm);
-  for (Buffer* b : {&key, &perm, &po, &p64, &ys, &h, &ynorm}) b->reset(ix.arena);
 
   // bounds over all points; screen operands are rebuilt on the next query
   const double u64 = std::ldexp(1.0, -53), u32 = std::ldexp(1.0, -24);

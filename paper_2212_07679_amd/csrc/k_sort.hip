@@ -341,8 +341,8 @@ void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n,
   const int nblocks = (int)ceil_div(n, sort_tile(n));
   const size_t nhist = (size_t)nblocks * kRadix;
   const size_t bytes = 2 * (size_t)n * sizeof(uint32_t) + nhist * sizeof(uint32_t) + scan_scratch_bytes(nhist) + 1024;
-  char* mem = static_cast<char*>(a.alloc(bytes));
-  uint32_t* k2 = reinterpret_cast<uint32_t*>(mem);
+  ScopedAlloc mem(a, bytes);
+  uint32_t* k2 = static_cast<uint32_t*>(mem.get());
   uint32_t* v2 = k2 + n;
   uint32_t* hist = v2 + n;
   void* scratch = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(hist + nhist) + 255) & ~uintptr_t(255));
@@ -358,7 +358,6 @@ void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n,
     SNN_HIP(hipMemcpyAsync(keys, kin, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     SNN_HIP(hipMemcpyAsync(vals, vin, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   }
-  a.release(mem);
 }
 
 size_t radix_sort_ws_bytes(int64_t n) {

@@ -72,12 +72,8 @@ snn_status snn_normalize_rows(const snn_device* dev, const void* X, int64_t n, i
     DeviceArena a(*dev);
     hipStream_t s = a.stream();
     const DeviceInfo& di = device_info(dev->device);
-    int* bad = static_cast<int*>(a.alloc(256));
-    struct Release {
-      DeviceArena& a;
-      void* p;
-      ~Release() { a.release(p); }
-    } rel{a, bad};
+    ScopedAlloc flag(a, 256);
+    int* bad = static_cast<int*>(flag.get());
     launch_fill_i32(bad, 1, 0, s);
     const int grid = grid_for(n, di.cus * 16);
     if (dtype == SNN_F32)

@@ -192,7 +192,10 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   if (o.tile_q < 0 || o.tile_c < 0) fail(SNN_EINVAL, "tile sizes must be >= 0");
   if (o.tile_q % 64 != 0) fail(SNN_EINVAL, "tile_q must be a multiple of 64");
   if (o.full_self_scan != 0 && o.full_self_scan != 1) fail(SNN_EINVAL, "full_self_scan must be 0 or 1");
-  if (o.metric != SNN_METRIC_L2 && o.metric != SNN_METRIC_L1) fail(SNN_EINVAL, "unknown metric");
+  if (o.metric != SNN_METRIC_L2 && o.metric != SNN_METRIC_L1 && o.metric != SNN_METRIC_ANGULAR &&
+      o.metric != SNN_METRIC_COSINE)
+    fail(SNN_EINVAL, "unknown metric");
+  if (o.metric == SNN_METRIC_ANGULAR && R > M_PI) fail(SNN_EINVAL, "angular radius must be at most pi");
 
   DeviceScope scope(ix.arena.dev().device);
   hipStream_t s = ix.arena.stream();
@@ -204,8 +207,19 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   // M (1 + 2 gamma_{d+1}), the 2-norm at most the 1-norm, and S at most the
   // exact squared 2-norm times (1 + gamma_{d+2}).  The window and the screen
   // use Rs, the recheck decides by M <= R.
-  const double Rs = o.metric == SNN_METRIC_L1 ? R * (1.0 + 8.0 * gamma64(d + 2)) : R;
-  const double R2 = Rs * Rs;
+  //
+  // Angular and cosine searches of unit rows compare S with the squared
+  // chord T = fl(2 - 2 cos a) or fl(2 c) (Section 2) instead of fl(R*R); the
+  // window and the screen take Rs = sqrt(T) rounded up, so Rs^2 >= T.
+  double Rs = R, R2 = R * R;
+  if (o.metric == SNN_METRIC_L1) {
+    Rs = R * (1.0 + 8.0 * gamma64(d + 2));
+    R2 = Rs * Rs;
+  } else if (o.metric == SNN_METRIC_ANGULAR || o.metric == SNN_METRIC_COSINE) {
+    R2 = o.metric == SNN_METRIC_ANGULAR ? 2.0 - 2.0 * std::cos(R) : 2.0 * R;
+    if (!std::isfinite(R2)) fail(SNN_EINVAL, "cosine radius too large");
+    Rs = std::nextafter(std::sqrt(R2), INFINITY);
+  }
 
   // ---- precision plan
   // A screen passes every pair whose decomposed distance is within about

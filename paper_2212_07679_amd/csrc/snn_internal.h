@@ -89,6 +89,23 @@ class DeviceArena {
   snn_device dev_;
 };
 
+// A device allocation for the duration of one call: released when the scope
+// ends, also when an error is thrown part way (the release is stream-ordered
+// for the caller's allocator and synchronous for hipFree, so work already
+// enqueued on the buffer is not cut short).
+class ScopedAlloc {
+ public:
+  ScopedAlloc(DeviceArena& a, size_t bytes) : a_(a), p_(a.alloc(bytes)) {}
+  ~ScopedAlloc() { a_.release(p_); }
+  ScopedAlloc(const ScopedAlloc&) = delete;
+  ScopedAlloc& operator=(const ScopedAlloc&) = delete;
+  void* get() const { return p_; }
+
+ private:
+  DeviceArena& a_;
+  void* p_;
+};
+
 // A grow-only device buffer owned by an arena.
 struct Buffer {
   void* ptr = nullptr;

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.metrics import brute_l1, normalize_rows
+from oracle.metrics import brute_angular, brute_cosine, brute_l1, normalize_rows
 from paper_2212_07679_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -70,19 +70,49 @@ def test_normalize_rejects_zero_and_nan_rows(B):
 
 @pytest.mark.parametrize("precision", ["auto", "mixed", "fp64"])
 def test_angular_and_cosine_search(B, precision):
+    """The library takes the angle (or cosine distance) itself; the oracle
+    decides by its own squared chord 2 - 2 cos(alpha) (or 2c)."""
     w = W.angular100(n=30000, m=700, k=3)
     say(f"angular100 small n={w.n} m={w.m} alpha={w.alpha} precision={precision}")
     Yp, Yq = normalize_rows(w.P), normalize_rows(w.Q)
     Xd = B.normalize_rows(to_dev(w.P))
     Qd = B.normalize_rows(to_dev(w.Q))
     idx = B.Index(Xd)
-    R = B.angular_radius(w.alpha)
-    ref = oracle.brute_radius(Yp, Yq, R)
+    ref = brute_angular(Yp, Yq, w.alpha)
     assert ref.row_ptr[-1] > w.m  # neighbours beyond a handful
-    check_same(idx.query(Qd, R, precision=precision), ref, "angular")
+    check_same(idx.query(Qd, w.alpha, precision=precision, metric="angular"), ref, "angular")
     c = 1.0 - math.cos(w.alpha) * 1.01
-    Rc = B.cosine_radius(c)
-    check_same(idx.query(Qd, Rc, precision=precision), oracle.brute_radius(Yp, Yq, Rc), "cosine")
+    check_same(idx.query(Qd, c, precision=precision, metric="cosine"), brute_cosine(Yp, Yq, c), "cosine")
+    # self-queries (symmetric and full scans) and clustering with the angular neighbourhood
+    Ys = Yp[:6000]
+    idx2 = B.Index(to_dev(Ys))
+    refs = brute_angular(Ys, Ys, w.alpha)
+    check_same(idx2.query_self(w.alpha, precision=precision, metric="angular"), refs, "angular self")
+    check_same(idx2.query_self(w.alpha, precision=precision, metric="angular", full_self_scan=True), refs,
+               "angular self full")
+    refd = oracle.dbscan_from_neighbors(refs.row_ptr, refs.col, 5)
+    labels, core, k = idx2.dbscan(w.alpha, 5, precision=precision, metric="angular")
+    assert np.array_equal(labels.cpu().numpy(), refd.labels) and np.array_equal(core.cpu().numpy(), refd.core)
+
+
+def test_angular_boundary_and_errors(B):
+    """Unit vectors 7 degrees apart on a circle: an angle of exactly 14
+    degrees between the radii of two points decides by the squared chord."""
+    say("angular on a circle, errors")
+    ang = np.arange(60) * math.radians(7.0)
+    Y = normalize_rows(np.stack([np.cos(ang), np.sin(ang)], axis=1))
+    idx = B.Index(to_dev(Y))
+    for a_deg in (0.0, 6.9, 14.0, 20.0, 180.0):
+        a = math.radians(a_deg)
+        for precision in ("auto", "mixed", "fp64", "fp32"):
+            check_same(idx.query(to_dev(Y), a, precision=precision, metric="angular"), brute_angular(Y, Y, a),
+                       f"angle {a_deg} {precision}")
+    with pytest.raises(B.SnnError) as e:
+        idx.query(to_dev(Y), math.pi * 1.01, metric="angular")
+    assert e.value.status == B.SNN_EINVAL
+    with pytest.raises(B.SnnError) as e:
+        idx.query(to_dev(Y), -0.1, metric="cosine")
+    assert e.value.status == B.SNN_EINVAL
 
 
 @pytest.mark.parametrize("precision", ["auto", "mixed", "fp32", "fp64"])

@@ -18,7 +18,8 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.metrics import brute_l1, manhattan, normalize_rows
+from oracle.metrics import (angular_threshold, brute_angular, brute_cosine, brute_l1, cosine_threshold, manhattan,
+                            normalize_rows, snn_angular)
 from paper_2212_07679_amd import workloads as W
 
 U64 = 2.0**-53
@@ -109,11 +110,34 @@ def test_angular_on_a_circle():
     ang = np.arange(40) * step
     X = np.stack([np.cos(ang), np.sin(ang)], axis=1) * 3.0  # not unit length before normalising
     Y = normalize_rows(X)
-    R = math.sqrt(2.0 - 2.0 * math.cos(math.radians(20.0)))
-    nb = oracle.brute_radius(Y, Y, R)
+    nb = brute_angular(Y, Y, math.radians(20.0))
     for k in range(40):
         want = [j for j in range(40) if abs(j - k) <= 2]  # 14 degrees in, 21 out
-        assert nb.col[nb.row_ptr[k]:nb.row_ptr[k + 1]].tolist() == want
+        got = nb.col[nb.row_ptr[k]:nb.row_ptr[k + 1]]
+        assert got.tolist() == want
+        # reported distances are the angles themselves
+        ref = np.radians(7.0 * np.abs(np.array(want) - k))
+        assert np.allclose(nb.dist[nb.row_ptr[k]:nb.row_ptr[k + 1]], ref, rtol=1e-5, atol=1e-6)
+    # cosine distance 1 - cos(14 deg) lies between the 2- and 3-step neighbours
+    c = 1.0 - math.cos(math.radians(17.0))
+    nbc = brute_cosine(Y, Y, c)
+    for k in range(40):
+        want = [j for j in range(40) if abs(j - k) <= 2]
+        assert nbc.col[nbc.row_ptr[k]:nbc.row_ptr[k + 1]].tolist() == want
+        ref = 1.0 - np.cos(np.radians(7.0 * np.abs(np.array(want) - k)))
+        assert np.allclose(nbc.dist[nbc.row_ptr[k]:nbc.row_ptr[k + 1]], ref, rtol=1e-5, atol=1e-7)
+
+
+def test_angular_thresholds():
+    # the squared chord of an angle: 60 degrees on unit vectors is a chord of 1
+    assert abs(angular_threshold(math.pi / 3) - 1.0) <= 4 * U64
+    assert angular_threshold(0.0) == 0.0 and angular_threshold(math.pi) == 4.0
+    assert cosine_threshold(0.25) == 0.5
+    for bad in (-0.1, math.pi + 1e-9, float("nan")):
+        with pytest.raises(ValueError):
+            angular_threshold(bad)
+    with pytest.raises(ValueError):
+        cosine_threshold(-1.0)
 
 
 def test_angular_and_cosine_random_directions():
@@ -121,8 +145,7 @@ def test_angular_and_cosine_random_directions():
     X = g.standard_normal((600, 8))
     Y = normalize_rows(X)
     alpha = 1.0
-    R = math.sqrt(2.0 - 2.0 * math.cos(alpha))
-    nb = oracle.brute_radius(Y, Y[:40], R)
+    nb = brute_angular(Y, Y[:40], alpha)
     cosines = np.clip(Y[:40] @ Y.T, -1.0, 1.0)
     theta = np.arccos(cosines)
     for j in range(40):
@@ -130,13 +153,21 @@ def test_angular_and_cosine_random_directions():
         want = np.flatnonzero((theta[j] <= alpha) & far)
         got = nb.col[nb.row_ptr[j]:nb.row_ptr[j + 1]]
         assert set(want.tolist()) == set(got.tolist()) & set(np.flatnonzero(far).tolist())
+        assert np.allclose(nb.dist[nb.row_ptr[j]:nb.row_ptr[j + 1]], theta[j][got], rtol=1e-5, atol=1e-6)
     c = 0.3
-    nbc = oracle.brute_radius(Y, Y[:40], math.sqrt(2.0 * c))
+    nbc = brute_cosine(Y, Y[:40], c)
     for j in range(40):
         far = np.abs((1.0 - cosines[j]) - c) > 1e-9
         want = np.flatnonzero((1.0 - cosines[j] <= c) & far)
         got = nbc.col[nbc.row_ptr[j]:nbc.row_ptr[j + 1]]
         assert set(want.tolist()) == set(got.tolist()) & set(np.flatnonzero(far).tolist())
+        assert np.allclose(nbc.dist[nbc.row_ptr[j]:nbc.row_ptr[j + 1]], 1.0 - cosines[j][got], rtol=1e-5,
+                           atol=1e-7)
+    # the CPU SNN with the squared chord gives the same sets (eq. (lower) on unit rows)
+    idx = oracle.build_index(Y)
+    nbs, _ = snn_angular(idx, Y[:40], alpha)
+    assert np.array_equal(nbs.row_ptr, nb.row_ptr) and np.array_equal(nbs.col, nb.col)
+    assert np.allclose(nbs.dist, nb.dist, rtol=1e-5)
 
 
 def _lattice_pins_hold():
