@@ -2,15 +2,16 @@
 
 Default (the headline): the gmm16 workload -- n = 1e6 points, d = 16,
 float32, 20-cluster Gaussian mixture, 1e5 out-of-sample queries, R = 1.5 --
-with the mixed-precision screen (bf16 matrix cores + float64 recheck) timed
-against the plain float64 GPU kernel.  ``--workload`` selects another
-configuration (uniform2d, gmm128z, blobs3d); those print the same kind of
-line for that workload.
+with the precision form (the matrix-core screen AUTO picks -- fp16 operands
+on this set -- plus the float64 recheck) timed against the bf16 three-term
+screen and the plain float64 GPU kernel.  ``--workload`` selects another
+configuration (uniform2d, gmm128z, blobs3d, ...); those print the same kind
+of line for that workload.
 
 One step = one snn_query (or snn_query_self) call over all queries with the
 index and the queries resident in HBM.  W untimed warm-up steps, then K timed
-steps bracketed by torch.cuda.synchronize(); value = m * K / elapsed, timed
-with events on the library's stream.
+steps bracketed by torch.cuda.synchronize(), each step also bracketed by HIP
+events on the library's stream; value = m / (median step time).
 
 Prints one JSON line.  ``roofline`` describes the dominant kernel (the
 candidate screen): algorithmic work per launch (the sum over queries of the
@@ -42,7 +43,7 @@ HEADLINE_METRIC = "exact radius queries/s at n=1e6,d=16: MFMA+FP64 recheck vs pl
 
 WORKLOADS = {
     "gmm16": dict(desc="gmm16: n=1e6 d=16 float32, 20-cluster Gaussian mixture, 1e5 out-of-sample queries, R=1.5",
-                  precisions="mixed,fp64", cpu_sample=2000),
+                  precisions="auto,mixed,fp64", cpu_sample=2000),
     "uniform2d": dict(desc="uniform2d: n=1e4 d=2 float64 uniform in [0,1]^2, 1e3 queries sampled from the data, "
                            "R=0.05", precisions="auto,fp64", cpu_sample=1000),
     "gmm128z": dict(desc="gmm128z: n=2e6 d=128 float32, 50-cluster mixture z-scored per feature, all-points "
@@ -68,6 +69,7 @@ WORKLOADS = {
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {
     "mixed": "paper_2212_07679_amd/csrc/k_cand_mfma.hip",
+    "fp16": "paper_2212_07679_amd/csrc/k_cand_mfma.hip",
     "fp32": "paper_2212_07679_amd/csrc/k_cand_mfma.hip",
     "fp64": "paper_2212_07679_amd/csrc/k_cand_fp64.hip",
 }
@@ -114,6 +116,7 @@ def parse():
     ap.add_argument("--workload", default="gmm16", choices=sorted(WORKLOADS) + ["copyprobe"])
     ap.add_argument("--n", type=int, default=0, help="override the number of points (0: the workload's)")
     ap.add_argument("--m", type=int, default=0, help="override the number of queries (gmm16, uniform2d)")
+    ap.add_argument("--R", type=float, default=0.0, help="override the radius (0: the workload's)")
     ap.add_argument("--precisions", default="", help="comma list; the first is the reported value")
     ap.add_argument("--cpu-sample", type=int, default=-1, help="queries the CPU oracle times (0: skip)")
     ap.add_argument("--check", type=int, default=200, help="queries checked against the oracle (0: skip)")
@@ -229,7 +232,7 @@ def cpu_baseline(w, sample):
 
 
 def roofline(prec_used, terms, st, screen_ms, d):
-    if prec_used == "mixed":
+    if prec_used in ("mixed", "fp16"):  # bf16 and fp16 share the dense matrix peak
         achieved = st["pairs_window"] * 2 * d / (screen_ms / 1e3)
         return {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_BF16_FLOPS / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_BF16_FLOPS, "traffic": None}
@@ -610,6 +613,10 @@ def main():
     cpu_sample = spec["cpu_sample"] if a.cpu_sample < 0 else a.cpu_sample
     t_gen = time.perf_counter()
     w = make_workload(a.workload, a.n, a.m)
+    if a.R > 0:
+        import dataclasses
+
+        w = dataclasses.replace(w, R=a.R)
     print(f"[bench] {a.workload}: n={w.n} d={w.d} m={w.m} R={w.R} generated in {time.perf_counter() - t_gen:.1f} s",
           file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
@@ -692,7 +699,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "bf16+f64", "fp32": "f32+f64", "fp64": "f64"}[used],
+        "dtype": {"mixed": "bf16+f64", "fp16": "f16+f64", "fp32": "f32+f64", "fp64": "f64"}[used],
         "data": "synthetic",
         "config": {"workload": spec["desc"], "n": w.n, "d": w.d, "m": w.m, "R": (None if w.alpha is not None else w.R), "self_query": w.Q is None,
                    "precision": used, "terms": st["terms_used"],

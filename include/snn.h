@@ -59,12 +59,24 @@ typedef enum { SNN_F32 = 0, SNN_F64 = 1 } snn_dtype;
  *        fp32 accumulation) against a rigorous rounding bound; only pairs
  *        the screen cannot reject are re-decided by the normative rule in
  *        float64 (the "precision form").
+ * FP16:  the same screen with one fp16 operand per coordinate of the rows
+ *        scaled by a power of two (d <= 128): a rounding band 8x narrower
+ *        than one bf16 term at the same matrix-core rate.
  * FP32:  the same screen with fp32 operands on the matrix cores (d <= 16):
  *        a much narrower rounding band, for low dimensions with a radius
  *        that is small against the data's extent.
  * AUTO:  the library picks from the width of each screen's rounding band
- *        relative to R^2 and from d. */
-typedef enum { SNN_PREC_FP64 = 0, SNN_PREC_MIXED = 1, SNN_PREC_AUTO = 2, SNN_PREC_FP32 = 3 } snn_precision;
+ *        relative to R^2 and from d.
+ * The 16-bit and fp32 screens need the centred rows within fp32 range (norms
+ * below 2^60; fp16: below 2^75); beyond it they return SNN_ENOTSUP and AUTO
+ * takes FP64. */
+typedef enum {
+  SNN_PREC_FP64 = 0,
+  SNN_PREC_MIXED = 1,
+  SNN_PREC_AUTO = 2,
+  SNN_PREC_FP32 = 3,
+  SNN_PREC_FP16 = 4
+} snn_precision;
 
 /* Distance of a query (Section 2).
  * L2: the Euclidean rule above.
@@ -127,7 +139,7 @@ typedef struct {
   int64_t pairs_recheck;  /* pairs re-decided in float64 by the normative rule */
   int64_t nnz;
   int32_t precision_used; /* snn_precision actually run */
-  int32_t terms_used;     /* MIXED: bf16 terms per coordinate */
+  int32_t terms_used;     /* MIXED: bf16 terms per coordinate; FP16: 1 */
   double screen_ms;       /* device time of the candidate-screen kernel */
   double total_ms;        /* device time of the whole call */
   double flops_window;    /* algorithmic work of the window: sum over queries of

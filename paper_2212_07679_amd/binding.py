@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsnn.so")
 
 SNN_OK, SNN_EINVAL, SNN_ENOMEM, SNN_EDEVICE, SNN_EOVERFLOW, SNN_ENOTSUP = 0, -1, -2, -3, -4, -5
 SNN_F32, SNN_F64 = 0, 1
-PRECISION = {"fp64": 0, "mixed": 1, "auto": 2, "fp32": 3}
+PRECISION = {"fp64": 0, "mixed": 1, "auto": 2, "fp32": 3, "fp16": 4}
 PRECISION_NAMES = {v: k for k, v in PRECISION.items()}
 METRIC = {"l2": 0, "l1": 1, "angular": 2, "cosine": 3}
 
@@ -145,7 +145,22 @@ class snn_batch_info_t(ctypes.Structure):
 
 SNN_BATCH_INDEX, SNN_BATCH_QUERY = 1, 2
 
-# symbol -> (restype, argtypes): every entry point declared in include/snn.h
+
+class snn_screen_layout(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("terms", ctypes.c_int32),
+        ("ka", ctypes.c_int32),
+        ("kb", ctypes.c_int32),
+        ("chain", ctypes.c_int32),
+        ("scale_exp", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+# symbol -> (restype, argtypes): every entry point declared in include/snn.h and
+# include/snn_testing.h
 SIGNATURES = {
     "snn_batch_create": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_int, ctypes.POINTER(snn_instance),
                                         ctypes.c_int32, ctypes.POINTER(snn_batch_options),
@@ -175,6 +190,11 @@ SIGNATURES = {
                                         ctypes.POINTER(snn_stats)]),
     "snn_normalize_rows": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                           ctypes.c_int, ctypes.c_void_p]),
+    "snn_debug_screen_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(snn_options),
+                                               ctypes.POINTER(snn_screen_layout)]),
+    "snn_debug_screen": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                        ctypes.POINTER(snn_options), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(snn_screen_layout)]),
     "snn_last_error": (ctypes.c_char_p, []),
     "snn_version": (ctypes.c_char_p, []),
 }
@@ -379,6 +399,33 @@ class Index:
             core = core[:self.n].bool()
         res = (labels[:self.n], core, int(k.value))
         return (res + (st.as_dict(),)) if stats else res
+
+    def screen_values(self, Q: torch.Tensor, R: float, precision: str = "auto", terms: int = 0) -> dict:
+        """Test support (include/snn_testing.h): every (query, candidate)
+        pair's screen value D, the candidates' H, the queries' start values
+        C and both operand row sets of the screen a query would run."""
+        if not isinstance(Q, torch.Tensor) or not Q.is_cuda or Q.dim() != 2 or Q.shape[1] != self.d:
+            raise SnnError(SNN_EINVAL, "Q must be a CUDA tensor of shape (m, d)")
+        if Q.dtype != self.dtype:
+            raise SnnError(SNN_EINVAL, "Q must have the index dtype")
+        Q = Q.contiguous()
+        opts = self._opts(precision, terms, 0, 0)
+        lay = snn_screen_layout()
+        _check(lib().snn_debug_screen_layout(self._h, float(R), ctypes.byref(opts), ctypes.byref(lay)))
+        m, n = Q.shape[0], self.n
+        dev = f"cuda:{self.device}"
+        vt = torch.float32 if lay.precision == PRECISION["fp32"] else torch.int16
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+            D = torch.empty((m, n), dtype=torch.float32, device=dev)
+            H = torch.empty(n, dtype=torch.float32, device=dev)
+            C = torch.empty(m, dtype=torch.float32, device=dev)
+            A = torch.empty((m, lay.ka), dtype=vt, device=dev)
+            Bm = torch.empty((n, lay.kb), dtype=vt, device=dev)
+            _check(lib().snn_debug_screen(self._h, ctypes.c_void_p(Q.data_ptr()), m, float(R), ctypes.byref(opts),
+                                          ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(H.data_ptr()),
+                                          ctypes.c_void_p(C.data_ptr()), ctypes.c_void_p(A.data_ptr()),
+                                          ctypes.c_void_p(Bm.data_ptr()), ctypes.byref(lay)))
+        return {"layout": lay.as_dict(), "D": D, "H": H, "C": C, "A": A, "B": Bm}
 
     def view(self) -> dict:
         """Index internals copied into new tensors (for checks)."""

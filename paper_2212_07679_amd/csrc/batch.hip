@@ -752,7 +752,7 @@ BatchPlan* create_batch(const snn_device& devc, snn_dtype dtype, const snn_insta
     alloc_survivors(p, std::max<int64_t>(1 << 20, 2 * p.M + caps));
     alloc_stage(p, std::max<int64_t>(1 << 16, caps));
     const DeviceInfo& di = device_info(devc.device);
-    const int per_cu = mixed_blocks_per_cu(p.KA, p.KA);
+    const int per_cu = mixed_blocks_per_cu(p.KA, p.KA, false);
     p.screen_grid = std::max(di.xcds, (di.cus * per_cu / di.xcds) * di.xcds);
     build_graphs(p);
     // first run: builds the index and sizes the survivor / staging arrays

@@ -15,16 +15,24 @@
 // constant C_q, the screen passes (q, j) iff
 //     D = fl_mfma( sum_k a_qk b_jk + C_q )  >=  fl32(h_j),
 // where the packed operands satisfy sum_k a_qk b_jk ~ y_q . y_j:
-//   terms = 1:  a = bf16(y_q),              b = bf16(y_j)
-//   terms = 3:  a = [hi_q, hi_q, lo_q],     b = [hi_j, lo_j, hi_j]
-//               hi = bf16(y), lo = bf16(y - hi)   (hi*hi + hi*lo + lo*hi)
+//   bf16, one term:  a = bf16(y_q),              b = bf16(y_j)
+//   bf16, 3 terms:   a = [hi_q, hi_q, lo_q],     b = [hi_j, lo_j, hi_j]
+//                    hi = bf16(y), lo = bf16(y - hi)   (hi*hi + hi*lo + lo*hi)
+//   fp16:            a = fp16(s y_q),            b = fp16(s y_j),  s = 2^e
+//                    (v_mfma_f32_32x32x16_f16; the accumulator, C_q and h_j
+//                    are then in units scaled by s^2, which is exact)
 // C_q is chosen (k_mixed_qprep) so that every pair with S(p_j, q) <= fl(R*R)
 // passes:
 //   C_q >= R2'/2 - h_q + eta sqrt(R2') + eta^2/2 + e_rep + e_acc + e_h
 //   R2'   = fl(R*R) (1 + 2 gamma64_{d+2})   bounds the exact ||p - q||^2
 //   eta   = 1.01 u32 (Y + ||y_q||)          centring rounding, Y = max_j ||y_j||
-//   e_rep = c_rep Y ||y_q||                 bf16 representation error
-//           c_rep = u_b (2 + u_b) (terms 1), u_b^2 (3 + 3 u_b) (terms 3), u_b = 2^-8
+//   e_rep = c_rep Y ||y_q|| + e_sub         operand representation error
+//           c_rep = u_b (2 + u_b) (bf16), u_b^2 (3 + 3 u_b) (bf16 x3), u_b = 2^-8,
+//                   u_h (2 + u_h) (fp16), u_h = 2^-11
+//           e_sub = (1 + u) t sqrt(K) delta (||y_q|| + Y) + t K delta^2: an operand
+//                   below the normal range is off by at most delta (its format's
+//                   smallest normal, fp16: 2^-14 / s) whether it is kept subnormal
+//                   or read as zero (t operand values per coordinate)
 //   e_acc = 2 gamma32_{K+1} (1.02 Y ||y_q|| + |C_q|)  fp32 accumulation of the
 //           K exact bf16 products and C (factor 2: the accumulation order and
 //           rounding inside the matrix core are not specified)
@@ -51,7 +59,31 @@
 namespace snn {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// The 16-bit operand format of a screen: its vector type and its 32x32x16
+// matrix instruction (same operand layout for both).
+template <bool F16>
+struct Op16;
+template <>
+struct Op16<false> {
+  typedef bf16x8 V;
+  static __device__ __forceinline__ f32x16 mfma(V a, V b, const f32x16& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Op16<true> {
+  typedef f16x8 V;
+  static __device__ __forceinline__ f32x16 mfma(V a, V b, const f32x16& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// fp16 bits of x (round to nearest even, subnormals kept: the kernels run
+// with fp16 denormals enabled)
+__device__ __forceinline__ uint16_t f32_to_f16_bits(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
 
 namespace {
 
@@ -63,9 +95,10 @@ constexpr int kWaveStage = 1536;
 
 // Out-of-sample queries: operands and thresholds from the float64 rows.
 __global__ __launch_bounds__(kThreads) void k_mixed_qprep(const double* __restrict__ q64, int64_t m, int d, int dp,
-                                                         const double* __restrict__ mu, int terms, int KA,
+                                                         const double* __restrict__ mu, int kind, int e, int KA,
                                                          MixedBound b, uint16_t* __restrict__ qop,
                                                          float* __restrict__ cthr) {
+  const int terms = kind == kOpBf16x3 ? 3 : 1;
   // kQLanes lanes per query: they share the coordinates and the operand row
   constexpr int kQLanes = 16;
   const int sub = threadIdx.x % kQLanes;
@@ -80,15 +113,19 @@ __global__ __launch_bounds__(kThreads) void k_mixed_qprep(const double* __restri
     // any summation order stays within the gamma_{d+1} bound the start value allows for
 #pragma unroll
     for (int off = kQLanes / 2; off > 0; off >>= 1) nn += __shfl_xor(nn, off, kQLanes);
-    // row [bf16(y)] or [hi | hi | lo]
+    // row [bf16(y)], [hi | hi | lo] or [fp16(2^e y)]
     uint16_t* o = qop + s * KA;
     for (int k = sub; k < KA; k += kQLanes) {
       uint16_t v = 0;
       if (k < terms * d) {
         const int seg = k / d, cc = k % d;
         const float y = (float)(q[cc] - mu[cc]);
-        const uint16_t hi = f32_to_bf16_rne(y);
-        v = (seg == 2) ? f32_to_bf16_rne(y - bf16_to_f32(hi)) : hi;
+        if (kind == kOpF16) {
+          v = f32_to_f16_bits(ldexpf(y, e));
+        } else {
+          const uint16_t hi = f32_to_bf16_rne(y);
+          v = (seg == 2) ? f32_to_bf16_rne(y - bf16_to_f32(hi)) : hi;
+        }
       }
       o[k] = v;
     }
@@ -133,12 +170,12 @@ constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format
 // scalar, so no per-step vector address arithmetic exists.  Reads past the
 // unit (the look-ahead of the last step) are outside num_records and return
 // zeros without touching memory.
-template <int NL>
-__device__ __forceinline__ void load_step(bf16x8 (&B)[NL], float& h, __amdgpu_buffer_rsrc_t rc,
+template <int NL, typename V>
+__device__ __forceinline__ void load_step(V (&B)[NL], float& h, __amdgpu_buffer_rsrc_t rc,
                                           __amdgpu_buffer_rsrc_t rh, int voff_c, int voff_h, int it) {
 #pragma unroll
   for (int s = 0; s < NL; ++s)  // slices are 1 KB apart in a 32-row block
-    B[s] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rc, voff_c, it * (NL * 1024) + s * 1024, 0));
+    B[s] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rc, voff_c, it * (NL * 1024) + s * 1024, 0));
   h = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rh, voff_h, it * 128, 0));
 }
 
@@ -194,37 +231,62 @@ __device__ __forceinline__ void screen_epilogue(const f32x16 (&acc)[QB], float h
 // The products of one 32-candidate step for QB blocks of 32 queries.
 // Operand slice s of the candidate is B[s] for s < NL and B[s - NL] beyond
 // (the split layout repeats hi as the third segment).
-template <int NS, int QB, int NL>
-__device__ __forceinline__ void step_products(const bf16x8 (&A)[QB][NS], const f32x16 (&Cin)[QB],
-                                              const bf16x8 (&B)[NL], f32x16 (&acc)[QB]) {
+template <bool F16, int NS, int QB, int NL>
+__device__ __forceinline__ void step_products(const typename Op16<F16>::V (&A)[QB][NS], const f32x16 (&Cin)[QB],
+                                              const typename Op16<F16>::V (&B)[NL], f32x16 (&acc)[QB]) {
 #pragma unroll
-  for (int b = 0; b < QB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][0], B[0], Cin[b], 0, 0, 0);
+  for (int b = 0; b < QB; ++b) acc[b] = Op16<F16>::mfma(A[b][0], B[0], Cin[b]);
 #pragma unroll
   for (int s = 1; s < NS; ++s)
 #pragma unroll
-    for (int b = 0; b < QB; ++b)
-      acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[b][s], B[s < NL ? s : s - NL], acc[b], 0, 0, 0);
+    for (int b = 0; b < QB; ++b) acc[b] = Op16<F16>::mfma(A[b][s], B[s < NL ? s : s - NL], acc[b]);
 }
 
-// One 32-candidate step of the bf16 screen: products, then compares.
-template <int NS, int QB, int NL>
-__device__ __forceinline__ void screen_step(const bf16x8 (&A)[QB][NS], const f32x16 (&Cin)[QB],
-                                            const bf16x8 (&B)[NL], float hv, int jr, int span, int j0,
+// One 32-candidate step of the 16-bit screen: products, then compares.
+template <bool F16, int NS, int QB, int NL>
+__device__ __forceinline__ void screen_step(const typename Op16<F16>::V (&A)[QB][NS], const f32x16 (&Cin)[QB],
+                                            const typename Op16<F16>::V (&B)[NL], float hv, int jr, int span, int j0,
                                             int64_t q0, int half, int2* wbuf, int& wcnt, const PairSink& sink) {
   const float hj = jr < span ? hv : INFINITY;
   f32x16 acc[QB];
-  step_products<NS, QB, NL>(A, Cin, B, acc);
+  step_products<F16, NS, QB, NL>(A, Cin, B, acc);
   screen_epilogue<QB, false>(acc, hj, j0 + jr, q0, half, wbuf, wcnt, sink);
 }
 
-template <int NS, int QB, int NL>
+// Query operands of one wavefront: QB blocks of 32 rows of NS slices (lane
+// l: row l % 32, 8 values at 8 (l / 32) of each 16-value slice) and the
+// blocks' start values in accumulator order; rows past m are zero / -inf.
+template <bool F16, int NS, int QB>
+__device__ __forceinline__ void load_queries(const MixedDev& x, int64_t m, int64_t q0, int l32, int half,
+                                             typename Op16<F16>::V (&A)[QB][NS], f32x16 (&Cin)[QB]) {
+  typedef typename Op16<F16>::V V;
+#pragma unroll
+  for (int b = 0; b < QB; ++b) {
+    const int64_t qr = q0 + b * 32 + l32;
+    const bool vq = qr < m;
+    const V* src = reinterpret_cast<const V*>(x.qop + (vq ? qr : 0) * x.KA + 8 * half);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      V v = src[2 * s];
+      if (!vq) v = V{};
+      A[b][s] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t qi = q0 + b * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+      Cin[b][r] = qi < m ? x.cthr[qi] : -INFINITY;
+    }
+  }
+}
+
+template <bool F16, int NS, int QB, int NL>
 __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) {
+  typedef typename Op16<F16>::V V;
   __shared__ int2 wstage[kWaves][kWaveStage];
   __shared__ long long s_unit;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int l32 = lane & 31, half = lane >> 5;
   const int xcd = blockIdx.x % q.nxcd;
-  const int KA = x.KA;
   int2* wbuf = wstage[wave];
   int wcnt = 0;  // wave-uniform fill of wbuf
   for (;;) {
@@ -242,25 +304,9 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
     // queries of a tile: a wave whose first slot is padding has no work
     if (x.cthr[q0] == -INFINITY) continue;
 
-    bf16x8 A[QB][NS];
+    V A[QB][NS];
     f32x16 Cin[QB];
-#pragma unroll
-    for (int b = 0; b < QB; ++b) {
-      const int64_t qr = q0 + b * 32 + l32;
-      const bool vq = qr < q.m;
-      const bf16x8* src = reinterpret_cast<const bf16x8*>(x.qop + (vq ? qr : 0) * KA + 8 * half);
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        bf16x8 v = src[2 * s];
-        if (!vq) v = bf16x8{};
-        A[b][s] = v;
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t qi = q0 + b * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-        Cin[b][r] = qi < q.m ? x.cthr[qi] : -INFINITY;
-      }
-    }
+    load_queries<F16, NS, QB>(x, q.m, q0, l32, half, A, Cin);
 
     // Candidate rows j0 + 32*it + l32 (for the split layout a row is
     // [hi | lo] and the third operand slice reuses hi).  j0 is a multiple of
@@ -276,15 +322,16 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
     const __amdgpu_buffer_rsrc_t rh =
         __builtin_amdgcn_make_buffer_rsrc((void*)(x.h + j0), (short)0, nsteps * 128, kRsrcWord3);
     const int voff_c = lane * 16, voff_h = l32 * 4;
-    bf16x8 B0[NL], B1[NL];
+    V B0[NL], B1[NL];
     float h0, h1;
     load_step<NL>(B0, h0, rc, rh, voff_c, voff_h, 0);
     for (int it = 0; it < nsteps; it += 2) {
       load_step<NL>(B1, h1, rc, rh, voff_c, voff_h, it + 1);
-      screen_step<NS, QB, NL>(A, Cin, B0, h0, it * 32 + l32, span, (int)j0, q0, half, wbuf, wcnt, q.sink);
+      screen_step<F16, NS, QB, NL>(A, Cin, B0, h0, it * 32 + l32, span, (int)j0, q0, half, wbuf, wcnt, q.sink);
       if (it + 1 >= nsteps) break;
       load_step<NL>(B0, h0, rc, rh, voff_c, voff_h, it + 2);
-      screen_step<NS, QB, NL>(A, Cin, B1, h1, (it + 1) * 32 + l32, span, (int)j0, q0, half, wbuf, wcnt, q.sink);
+      screen_step<F16, NS, QB, NL>(A, Cin, B1, h1, (it + 1) * 32 + l32, span, (int)j0, q0, half, wbuf, wcnt,
+                                   q.sink);
     }
   }
   wave_flush(wbuf, wcnt, q.sink);
@@ -300,6 +347,42 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
 // Candidate operands: blocks of 32 rows, NK slices of two coordinates, a
 // slice being 64 floats [k][row], so lane l = 32 k + row reads float l.  The
 // query rows are [y, C_q, 0 ...] of stride DV (k_mfma32_qprep).
+// Query operands of one wavefront for the fp32 screen: QB blocks of 32 rows,
+// lane l holding coordinate 2 s + l / 32 of row l % 32 in slice s, and the
+// start values C_q in accumulator order; rows past m are zero / -inf.
+template <int NK, int QB>
+__device__ __forceinline__ void load_queries32(const Mfma32Dev& x, int64_t m, int64_t q0, int l32, int half,
+                                               float (&A)[QB][NK], f32x16 (&Cin)[QB]) {
+#pragma unroll
+  for (int b = 0; b < QB; ++b) {
+    const int64_t qr = q0 + b * 32 + l32;
+    const bool vq = qr < m;
+    const float* row = x.vq + (vq ? qr : 0) * x.DV;
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      const int k = 2 * s + half;
+      A[b][s] = (vq && k < x.d) ? row[k] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t qi = q0 + b * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+      Cin[b][r] = qi < m ? x.vq[qi * x.DV + x.d] : -INFINITY;
+    }
+  }
+}
+
+// The fp32 product chain of one 32-candidate step for QB query blocks.
+template <int NK, int QB>
+__device__ __forceinline__ void step_products32(const float (&A)[QB][NK], const f32x16 (&Cin)[QB],
+                                                const float (&B)[NK], f32x16 (&acc)[QB]) {
+#pragma unroll
+  for (int b = 0; b < QB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b][0], B[0], Cin[b], 0, 0, 0);
+#pragma unroll
+  for (int s = 1; s < NK; ++s)
+#pragma unroll
+    for (int b = 0; b < QB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b][s], B[s], acc[b], 0, 0, 0);
+}
+
 template <int NK, int QB>
 __global__ __launch_bounds__(kThreads) void k_cand_mfma32(QueryDev q, Mfma32Dev x) {
   __shared__ int2 wstage[kWaves][kWaveStage];
@@ -323,22 +406,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma32(QueryDev q, Mfma32Dev 
 
     float A[QB][NK];
     f32x16 Cin[QB];
-#pragma unroll
-    for (int b = 0; b < QB; ++b) {
-      const int64_t qr = q0 + b * 32 + l32;
-      const bool vq = qr < q.m;
-      const float* row = x.vq + (vq ? qr : 0) * x.DV;
-#pragma unroll
-      for (int s = 0; s < NK; ++s) {
-        const int k = 2 * s + half;
-        A[b][s] = (vq && k < x.d) ? row[k] : 0.f;
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t qi = q0 + b * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-        Cin[b][r] = qi < q.m ? x.vq[qi * x.DV + x.d] : -INFINITY;
-      }
-    }
+    load_queries32<NK, QB>(x, q.m, q0, l32, half, A, Cin);
 
     // Step `it` covers candidates j0 + 32 it + l32 (j0 is a multiple of 32):
     // NK slices of 256 bytes through a buffer resource whose reads past the
@@ -363,12 +431,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma32(QueryDev q, Mfma32Dev 
       const int jr = it * 32 + l32;
       const float hj = jr < span ? hv : INFINITY;
       f32x16 acc[QB];
-#pragma unroll
-      for (int b = 0; b < QB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b][0], B[0], Cin[b], 0, 0, 0);
-#pragma unroll
-      for (int s = 1; s < NK; ++s)
-#pragma unroll
-        for (int b = 0; b < QB; ++b) acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[b][s], B[s], acc[b], 0, 0, 0);
+      step_products32<NK, QB>(A, Cin, B, acc);
       screen_epilogue<QB, true>(acc, hj, (int)j0 + jr, q0, half, wbuf, wcnt, q.sink);
     };
     load(B0, h0, 0);
@@ -428,6 +491,74 @@ __global__ __launch_bounds__(kThreads) void k_mfma32_qprep_self(const float* __r
   }
 }
 
+// ---- screen values of every pair (test support) ------------------------------
+// One wavefront per (32-query block, 32-candidate block) of a small query:
+// the operand loads and the product chain of the screens above, with the
+// accumulators written out instead of compared.  D[qorig[q] n + j] for
+// score-order queries q < m and candidates j < n.
+template <bool F16, int NS, int NL>
+__global__ __launch_bounds__(kWave) void k_dump_mixed(MixedDev x, int64_t m, int64_t n,
+                                                     const int32_t* __restrict__ qorig, float* __restrict__ D) {
+  typedef typename Op16<F16>::V V;
+  const int lane = threadIdx.x, l32 = lane & 31, half = lane >> 5;
+  const int64_t q0 = (int64_t)blockIdx.x * 32, jb = blockIdx.y;
+  V A[1][NS];
+  f32x16 Cin[1];
+  load_queries<F16, NS, 1>(x, m, q0, l32, half, A, Cin);
+  V B[NL];
+  const char* blk = reinterpret_cast<const char*>(x.cop) + jb * (NL * 1024);
+#pragma unroll
+  for (int s = 0; s < NL; ++s) B[s] = *reinterpret_cast<const V*>(blk + s * 1024 + lane * 16);
+  f32x16 acc[1];
+  step_products<F16, NS, 1, NL>(A, Cin, B, acc);
+  const int64_t j = jb * 32 + l32;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t qi = q0 + 8 * (r / 4) + 4 * half + (r % 4);
+    if (qi < m && j < n) D[(int64_t)qorig[qi] * n + j] = acc[0][r];
+  }
+}
+
+template <int NK>
+__global__ __launch_bounds__(kWave) void k_dump_mfma32(Mfma32Dev x, int64_t m, int64_t n,
+                                                      const int32_t* __restrict__ qorig, float* __restrict__ D) {
+  const int lane = threadIdx.x, l32 = lane & 31, half = lane >> 5;
+  const int64_t q0 = (int64_t)blockIdx.x * 32, jb = blockIdx.y;
+  float A[1][NK];
+  f32x16 Cin[1];
+  load_queries32<NK, 1>(x, m, q0, l32, half, A, Cin);
+  float B[NK];
+#pragma unroll
+  for (int s = 0; s < NK; ++s) B[s] = x.cop[(jb * NK + s) * 64 + lane];
+  f32x16 acc[1];
+  step_products32<NK, 1>(A, Cin, B, acc);
+  const int64_t j = jb * 32 + l32;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t qi = q0 + 8 * (r / 4) + 4 * half + (r % 4);
+    if (qi < m && j < n) D[(int64_t)qorig[qi] * n + j] = acc[0][r];
+  }
+}
+
+// Candidate operand rows out of the 32-row block layout: out[j KB + k], j < n.
+__global__ __launch_bounds__(kThreads) void k_dump_cand16(const uint16_t* __restrict__ cop, int64_t n, int KB,
+                                                         uint16_t* __restrict__ out) {
+  const int nl = KB / 16;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * KB; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / KB;
+    const int k = (int)(e % KB);
+    out[e] = cop[((j / 32 * nl + k / 16) * 2 + (k % 16) / 8) * 256 + (j % 32) * 8 + k % 8];
+  }
+}
+
+// Score-order rows of W values into the caller's order: out[qorig[s] W + k].
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dump_rows(const T* __restrict__ in, int64_t m, int W,
+                                                       const int32_t* __restrict__ qorig, T* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m * W; e += (int64_t)gridDim.x * blockDim.x)
+    out[(int64_t)qorig[e / W] * W + e % W] = in[e];
+}
+
 // Query blocks of 32 per wavefront in the fp32 screen: with two product
 // slices per chain (d <= 4) four blocks keep the matrix pipe busiest
 // (measured on the 5e6-point d = 3 self-query: 30.5 ms per query pass with
@@ -462,13 +593,18 @@ typedef void (*MixedKernel)(QueryDev, MixedDev);
 // lost a wave per SIMD at four.
 constexpr int qb_for(int) { return 2; }
 
-// (slices per product chain, slices loaded per candidate row)
-MixedKernel pick_kernel(int KA, int KB) {
+// (slices per product chain, slices loaded per candidate row); fp16
+// operands come one per coordinate only (ns = nl)
+MixedKernel pick_kernel(int KA, int KB, bool f16) {
   const int ns = KA / 16, nl = KB / 16;
 #define SNN_CASE(NS_, NL_) \
-  if (ns == NS_ && nl == NL_) return k_cand_mfma<NS_, qb_for(NS_), NL_>;
-  SNN_CASE(1, 1) SNN_CASE(2, 2) SNN_CASE(3, 3) SNN_CASE(3, 2) SNN_CASE(4, 4) SNN_CASE(5, 5)
-  SNN_CASE(6, 6) SNN_CASE(6, 4) SNN_CASE(7, 7) SNN_CASE(8, 8)
+  if (ns == NS_ && nl == NL_) return f16 ? k_cand_mfma<true, NS_, qb_for(NS_), NL_> : k_cand_mfma<false, NS_, qb_for(NS_), NL_>;
+  SNN_CASE(1, 1) SNN_CASE(2, 2) SNN_CASE(3, 3) SNN_CASE(4, 4) SNN_CASE(5, 5) SNN_CASE(6, 6) SNN_CASE(7, 7)
+  SNN_CASE(8, 8)
+#undef SNN_CASE
+#define SNN_CASE(NS_, NL_) \
+  if (!f16 && ns == NS_ && nl == NL_) return k_cand_mfma<false, NS_, qb_for(NS_), NL_>;
+  SNN_CASE(3, 2) SNN_CASE(6, 4)
 #undef SNN_CASE
   return nullptr;
 }
@@ -483,8 +619,8 @@ int grid_for(int64_t work, int cap) {
 int mixed_max_slices() { return 8; }
 int mixed_queries_per_wave(int KA) { return 32 * qb_for(KA / 16); }
 
-int mixed_blocks_per_cu(int KA, int KB) {
-  MixedKernel k = pick_kernel(KA, KB);
+int mixed_blocks_per_cu(int KA, int KB, bool f16) {
+  MixedKernel k = pick_kernel(KA, KB, f16);
   int nb = 0;
   if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kThreads, 0) != hipSuccess || nb < 1) {
     (void)hipGetLastError();
@@ -493,10 +629,10 @@ int mixed_blocks_per_cu(int KA, int KB) {
   return nb;
 }
 
-void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, int terms, int KA,
+void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, int kind, int e, int KA,
                         const MixedBound& b, uint16_t* qop, float* cthr, hipStream_t s) {
   if (m <= 0) return;
-  k_mixed_qprep<<<grid_for(m * 16, 8192), kThreads, 0, s>>>(q64, m, d, dp, mu, terms, KA, b, qop, cthr);
+  k_mixed_qprep<<<grid_for(m * 16, 8192), kThreads, 0, s>>>(q64, m, d, dp, mu, kind, e, KA, b, qop, cthr);
   SNN_LAUNCH_CHECK();
 }
 
@@ -550,10 +686,60 @@ void launch_cand_mfma32(const QueryDev& q, const Mfma32Dev& x, int grid, hipStre
   SNN_LAUNCH_CHECK();
 }
 
+void launch_dump_mixed(const MixedDev& x, int64_t m, int64_t n, const int32_t* qorig, float* D, hipStream_t s) {
+  const dim3 grid((unsigned)((m + 31) / 32), (unsigned)((n + 31) / 32));
+  const int ns = x.KA / 16, nl = x.KB / 16;
+  if (m <= 0 || n <= 0) return;
+#define SNN_CASE(NS_, NL_)                                                                          \
+  if (ns == NS_ && nl == NL_) {                                                                     \
+    if (x.f16)                                                                                      \
+      k_dump_mixed<true, NS_, NL_><<<grid, kWave, 0, s>>>(x, m, n, qorig, D);                        \
+    else                                                                                            \
+      k_dump_mixed<false, NS_, NL_><<<grid, kWave, 0, s>>>(x, m, n, qorig, D);                       \
+    SNN_LAUNCH_CHECK();                                                                             \
+    return;                                                                                         \
+  }
+  SNN_CASE(1, 1) SNN_CASE(2, 2) SNN_CASE(3, 3) SNN_CASE(4, 4) SNN_CASE(5, 5) SNN_CASE(6, 6) SNN_CASE(7, 7)
+  SNN_CASE(8, 8) SNN_CASE(3, 2) SNN_CASE(6, 4)
+#undef SNN_CASE
+  fail(SNN_ENOTSUP, "no screen for this operand layout");
+}
+
+void launch_dump_mfma32(const Mfma32Dev& x, int64_t m, int64_t n, const int32_t* qorig, float* D, hipStream_t s) {
+  if (m <= 0 || n <= 0) return;
+  const dim3 grid((unsigned)((m + 31) / 32), (unsigned)((n + 31) / 32));
+  switch ((x.d + 1) / 2) {
+#define SNN_CASE(NK_) \
+  case NK_: k_dump_mfma32<NK_><<<grid, kWave, 0, s>>>(x, m, n, qorig, D); break;
+    SNN_CASE(1) SNN_CASE(2) SNN_CASE(3) SNN_CASE(4) SNN_CASE(5) SNN_CASE(6) SNN_CASE(7) SNN_CASE(8)
+#undef SNN_CASE
+    default: fail(SNN_ENOTSUP, "fp32 matrix-core screen supports d <= 16");
+  }
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_dump_cand16(const uint16_t* cop, int64_t n, int KB, uint16_t* out, hipStream_t s) {
+  if (n <= 0) return;
+  k_dump_cand16<<<grid_for(n * KB, 8192), kThreads, 0, s>>>(cop, n, KB, out);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_dump_rows_u16(const uint16_t* in, int64_t m, int W, const int32_t* qorig, uint16_t* out, hipStream_t s) {
+  if (m <= 0) return;
+  k_dump_rows<uint16_t><<<grid_for(m * W, 8192), kThreads, 0, s>>>(in, m, W, qorig, out);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_dump_rows_f32(const float* in, int64_t m, int W, const int32_t* qorig, float* out, hipStream_t s) {
+  if (m <= 0) return;
+  k_dump_rows<float><<<grid_for(m * W, 8192), kThreads, 0, s>>>(in, m, W, qorig, out);
+  SNN_LAUNCH_CHECK();
+}
+
 // T must equal 4 waves x 32 x QB (QB = 2).
 void launch_cand_mfma(const QueryDev& q, const MixedDev& x, int grid, hipStream_t s) {
-  MixedKernel k = pick_kernel(x.KA, x.KB);
-  if (!k) fail(SNN_ENOTSUP, "mixed screen supports packed operand rows of at most 128 bf16");
+  MixedKernel k = pick_kernel(x.KA, x.KB, x.f16 != 0);
+  if (!k) fail(SNN_ENOTSUP, "16-bit screens support operand rows of at most 128 values");
   k<<<grid, kThreads, 0, s>>>(q, x);
   SNN_LAUNCH_CHECK();
 }

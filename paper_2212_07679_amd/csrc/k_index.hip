@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "device_common.h"
+#include "query_plan.h"
 #include "snn_internal.h"
 
 namespace snn {
@@ -881,17 +882,27 @@ void launch_gather(const T* X, int64_t n, int d, int dp, const double* mu, const
 // of contiguous memory.  npad (a multiple of 32, at least n + 32) rows are
 // stored; rows n .. npad-1 are zero.  Query rows for self-queries stay
 // row-major (ka per row).
-__global__ __launch_bounds__(kThreads) void k_operands(const float* __restrict__ ys, int64_t n, int64_t npad, int d,
-                                                      int terms, int ka, int kb, uint16_t* __restrict__ cand,
-                                                      uint16_t* __restrict__ qself) {
+// Screen operand rows of the sorted centred rows y (see k_cand_mfma.hip):
+// kind bf16: bf16(y); bf16 hi/lo: candidates [hi | lo], queries [hi | hi |
+// lo] (hi = bf16(y), lo = bf16(y - hi)); fp16: fp16(2^e y).  Candidate rows
+// go to 32-row blocks of 16-value slices (half-slice h of row r at
+// ((block * nl + slice) * 2 + h) * 256 + r * 8), query rows stay row-major.
+// For fp16 the candidates' h is scaled by 2^(2e) and rounded down into hs.
+__global__ __launch_bounds__(kThreads) void k_operands(const float* __restrict__ ys, const float* __restrict__ h,
+                                                      int64_t n, int64_t npad, int d, int kind, int e, int ka, int kb,
+                                                      uint16_t* __restrict__ cand, uint16_t* __restrict__ qself,
+                                                      float* __restrict__ hs) {
   const int64_t total = npad * (int64_t)ka;
   const int nl = kb / 16;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = e / ka;
-    const int k = (int)(e % ka);
+  for (int64_t el = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; el < total;
+       el += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = el / ka;
+    const int k = (int)(el % ka);
     uint16_t cv = 0, qv = 0;
     if (s < n) {
-      if (terms == 1) {
+      if (kind == kOpF16) {
+        if (k < d) cv = qv = __builtin_bit_cast(uint16_t, (_Float16)ldexpf(ys[s * d + k], e));
+      } else if (kind == kOpBf16) {
         if (k < d) cv = qv = f32_to_bf16_rne(ys[s * d + k]);
       } else if (k < 3 * d) {
         const int seg = k / d, c = k % d;
@@ -904,10 +915,20 @@ __global__ __launch_bounds__(kThreads) void k_operands(const float* __restrict__
     }
     if (k < kb) {
       const int64_t blk = s / 32;
-      const int r = (int)(s % 32), sl = k / 16, hh = (k % 16) / 8, el = k % 8;
-      cand[((blk * nl + sl) * 2 + hh) * 256 + r * 8 + el] = cv;
+      const int r = (int)(s % 32), sl = k / 16, hh = (k % 16) / 8, c8 = k % 8;
+      cand[((blk * nl + sl) * 2 + hh) * 256 + r * 8 + c8] = cv;
     }
-    if (qself && s < n) qself[e] = qv;
+    if (qself && s < n) qself[el] = qv;
+    if (hs && k == 0) {
+      float v = INFINITY;
+      if (s < n) {
+        // the scaling is exact unless it lands below fp32's normal range
+        const double x = ldexp((double)h[s], 2 * e);
+        v = (float)x;
+        if ((double)v > x) v = nextafterf(v, -INFINITY);
+      }
+      hs[s] = v;
+    }
   }
 }
 
@@ -1198,8 +1219,7 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   ix.max_norm = std::max(ix.max_norm, std::sqrt(hs.max_norm) * (1.0 + 4.0 * (d + 2) * u64));
   const double g64 = (d + 2) * u64 / (1.0 - (d + 2) * u64);
   ix.key_eps = 1.01 * (u32 + g64) * (1.0 + u32) * ix.max_norm * ix.vnorm;
-  ix.mixed[0].terms = 0;
-  ix.mixed[1].terms = 0;
+  for (auto& mo : ix.mixed) mo.built = false;
   ix.vcand_built = false;
 }
 
@@ -1211,22 +1231,26 @@ void insert_points(Index& ix, const void* X, int64_t k) {
     insert_points_t<double>(ix, static_cast<const double*>(X), k);
 }
 
-void build_mixed_operands(Index& ix, int terms) {
-  MixedOperands& mo = ix.mixed[terms == 1 ? 0 : 1];
-  if (mo.terms == terms) return;
+void build_mixed_operands(Index& ix, int kind) {
+  MixedOperands& mo = ix.mixed[mixed_slot(kind)];
+  if (mo.built) return;
   const int d = ix.d;
-  const int ka = terms == 1 ? ((d + 15) / 16) * 16 : ((3 * d + 15) / 16) * 16;
-  const int kb = (terms == 3 && d % 16 == 0) ? 2 * d : ka;
+  const int ka = kind == kOpBf16x3 ? ((3 * d + 15) / 16) * 16 : ((d + 15) / 16) * 16;
+  const int kb = (kind == kOpBf16x3 && d % 16 == 0) ? 2 * d : ka;
+  const int e = kind == kOpF16 ? f16_scale_exp(ix.max_norm) : 0;
   const int64_t npad = ((ix.n + 32 + 31) / 32) * 32;
   mo.cand.ensure(ix.arena, sizeof(uint16_t) * npad * kb + 256);
   mo.qself.ensure(ix.arena, sizeof(uint16_t) * ix.n * ka + 256);
+  if (kind == kOpF16) mo.hs.ensure(ix.arena, sizeof(float) * npad + 256);
   const DeviceInfo& di = device_info(ix.arena.dev().device);
   k_operands<<<grid_for(npad * ka, kThreads, 4 * di.cus * 8), kThreads, 0, ix.arena.stream()>>>(
-      ix.ys.as<float>(), ix.n, npad, d, terms, ka, kb, mo.cand.as<uint16_t>(), mo.qself.as<uint16_t>());
+      ix.ys.as<float>(), ix.h.as<float>(), ix.n, npad, d, kind, e, ka, kb, mo.cand.as<uint16_t>(),
+      mo.qself.as<uint16_t>(), kind == kOpF16 ? mo.hs.as<float>() : nullptr);
   SNN_LAUNCH_CHECK();
-  mo.terms = terms;
+  mo.built = true;
   mo.ka = ka;
   mo.kb = kb;
+  mo.e = e;
 }
 
 }  // namespace snn

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "device_common.h"
 #include "snn.h"
 
@@ -151,39 +153,76 @@ int fp64_blocks_per_cu(int dp);
 
 // k_cand_mfma.hip: mixed-precision screen on the matrix cores
 struct MixedDev {
-  const uint16_t* qop;  // m x KA bf16: query operand rows (score order)
-  const float* cthr;    // m: per-query accumulator start C_q
-  const uint16_t* cop;  // (n + 32) x KB bf16: candidate operand rows (score order)
-  const float* h;       // n + 32: fl32(||y_j||^2 / 2), padding +inf
+  const uint16_t* qop;  // m x KA 16-bit operands: query operand rows (score order)
+  const float* cthr;    // m: per-query accumulator start C_q (scaled units)
+  const uint16_t* cop;  // (n + 32) x KB 16-bit operands: candidate operand rows (score order)
+  const float* h;       // n + 32: the candidates' half squared norms in the accumulator's units, padding +inf
   int KA;               // query operand row length = product chain length
   int KB;               // candidate row length: KA, or 2 KA / 3 for the split layout
+  int f16;              // 1: fp16 operands (v_mfma_f32_32x32x16_f16), 0: bf16
 };
+
+// Operand encodings of the matrix-core screens.
+enum OperandKind {
+  kOpF32 = 0,     // the fp32 centred rows themselves
+  kOpBf16 = 1,    // one bf16 value per coordinate
+  kOpBf16x3 = 3,  // bf16 hi/lo split, three products hi*hi + hi*lo + lo*hi
+  kOpF16 = 4      // one fp16 value per coordinate of the rows scaled by 2^e
+};
+
 struct MixedBound {
   double r2p_half;  // R2' / 2
   double sqrt_r2p;  // sqrt(R2'), rounded up
   double u32p;      // 1.01 u32
   double Y;         // max_j ||y_j||
-  double c_rep;     // bf16 representation error coefficient
+  double c_rep;     // representation error coefficient of the operands
+  double sub;       // (1 + u) sqrt(K) delta: operands below the normal range, times (||y_q|| + Y)
+  double sub2;      // K delta^2
   double g_acc;     // 2 gamma32_{K+1}
   double e_h;       // rounding of h_j to fp32
   double g64;       // gamma64_{d+1}: relative error of h_q in float64
+  double scale2;    // s^2 = 2^(2e): accumulator units (fp16 operands), else 1
 };
-// Representation error coefficient of the screen operands, u_b = 2^-8:
-// terms = 1: bf16(y) carries |y - bf16(y)| <= u_b |y|, so the product of two
-// rounded operands differs from y_q . y_j by at most u_b (2 + u_b) |y_q||y_j|;
-// terms = 3: hi + lo leaves u_b^2 |y| and the dropped lo*lo product adds
-// u_b^2, giving u_b^2 (3 + 3 u_b); terms = 0: exact fp32 operands.
-__host__ __device__ inline double mixed_c_rep(int terms) {
-  const double ub = 0.00390625;
-  if (terms == 0) return 0.0;
-  return 1.01 * (terms == 1 ? ub * (2.0 + ub) : ub * ub * (3.0 + 3.0 * ub));
+
+// Representation error coefficient of the screen operands:
+// bf16 (u_b = 2^-8): |y - bf16(y)| <= u_b |y|, so the product of two rounded
+//   operands differs from y_q . y_j by at most u_b (2 + u_b) |y_q||y_j|;
+// bf16 hi/lo: hi + lo leaves u_b^2 |y| and the dropped lo*lo product adds
+//   u_b^2, giving u_b^2 (3 + 3 u_b);
+// fp16 (u_h = 2^-11) of the rows scaled by a power of two: u_h (2 + u_h);
+// fp32: the operands are the rows themselves.
+__host__ __device__ inline double mixed_c_rep(int kind) {
+  const double ub = 0.00390625, uh = 0.00048828125;
+  switch (kind) {
+    case kOpF32: return 0.0;
+    case kOpBf16: return 1.01 * ub * (2.0 + ub);
+    case kOpF16: return 1.01 * uh * (2.0 + uh);
+    default: return 1.01 * ub * ub * (3.0 + 3.0 * ub);
+  }
+}
+
+// fp16 operands hold s y with s = 2^e chosen so that every |s y_k| <= s Y <=
+// 2^15 (fp16's largest finite value is 65504); 0 when Y = 0.
+__host__ __device__ inline int f16_scale_exp(double Y) {
+  if (!(Y > 0)) return 0;
+  int ex = 0;
+  frexp(Y, &ex);  // Y < 2^ex
+  int e = 15 - ex;
+  return e < -60 ? -60 : (e > 60 ? 60 : e);
+}
+// Whether a screen's fp32 arithmetic holds every value it forms for rows of
+// norm at most Y: squared norms below 2^120 (bf16 / fp32 operands), scaled
+// fp16 rows below 2^15.
+__host__ __device__ inline bool screen_in_range(int kind, double Y) {
+  if (kind == kOpF16) return ldexp(Y, f16_scale_exp(Y)) <= 32768.0;
+  return Y <= ldexp(1.0, 60);
 }
 
 // Constants of the screen start value for one index and radius (the terms
-// of C_q derived in k_cand_mfma.hip).
-__host__ __device__ inline MixedBound mixed_bound(int terms, int KA, int d, double R2, double Y) {
+// of C_q derived in k_cand_mfma.hip).  K: the product chain length.
+__host__ __device__ inline MixedBound mixed_bound(int kind, int K, int d, double R2, double Y) {
   const double u32 = 5.9604644775390625e-08, u64 = 1.1102230246251565e-16;
-  const double ga = (KA + 1) * u32 / (1.0 - (KA + 1) * u32);
+  const double ga = (K + 1) * u32 / (1.0 - (K + 1) * u32);
   const double gr = (d + 2) * u64 / (1.0 - (d + 2) * u64);
   const double gh = (d + 1) * u64 / (1.0 - (d + 1) * u64);
   MixedBound b;
@@ -192,10 +231,20 @@ __host__ __device__ inline MixedBound mixed_bound(int terms, int KA, int d, doub
   b.sqrt_r2p = sqrt(r2p) * (1.0 + 1e-15);
   b.u32p = 1.01 * u32;
   b.Y = Y;
-  b.c_rep = mixed_c_rep(terms);
+  b.c_rep = mixed_c_rep(kind);
+  // delta: the largest error of an operand below the normal range, whether
+  // the conversion keeps it subnormal or the matrix core reads it as zero:
+  // fp16's smallest normal 2^-14 in the scaled units (2^-14 / s unscaled),
+  // else bf16's / fp32's 2^-126.
+  const int e = kind == kOpF16 ? f16_scale_exp(Y) : 0;
+  const double delta = kind == kOpF16 ? ldexp(1.0, -14 - e) : ldexp(1.0, -126);
+  const double terms = kind == kOpBf16x3 ? 3.0 : 1.0;  // operand values per coordinate
+  b.sub = 1.01 * (1.0 + 0.00390625) * terms * sqrt((double)K) * delta;
+  b.sub2 = 1.01 * terms * K * delta * delta;
   b.g_acc = 2.0 * ga;
   b.e_h = 1.01 * u32 * Y * Y * 0.5;
   b.g64 = gh;
+  b.scale2 = ldexp(1.0, 2 * e);
   return b;
 }
 
@@ -206,20 +255,23 @@ __device__ __forceinline__ float round_up_f32(double c) {
 }
 
 // Accumulator start C_q of a screen (see k_cand_mfma.hip): every pair with
-// S(p_j, q) <= fl(R*R) satisfies (screen value) >= fl32(h_j).  hq = ||y_q||^2/2
-// and nq >= ||y_q|| in float64.
+// S(p_j, q) <= fl(R*R) satisfies (screen value) >= (the candidate's h in
+// accumulator units).  hq = ||y_q||^2/2 and nq >= ||y_q|| in float64.
 __device__ __forceinline__ float screen_threshold(const MixedBound& b, double hq, double nq) {
   const double eta = b.u32p * (b.Y + nq);
   const double hlo = hq * (1.0 - b.g64);
-  double c0 = b.r2p_half - hlo + eta * b.sqrt_r2p + 0.5 * eta * eta + b.c_rep * b.Y * nq + b.e_h;
+  const double e_sub = b.sub * (nq + b.Y) + b.sub2;
+  double c0 = b.r2p_half - hlo + eta * b.sqrt_r2p + 0.5 * eta * eta + b.c_rep * b.Y * nq + e_sub + b.e_h;
   c0 += 8.0 * 1.1102230246251565e-16 * (b.r2p_half + hq + b.Y * nq) + 1e-30;
-  const double e_acc = b.g_acc * (1.02 * b.Y * nq + fabs(c0)) * 1.01;
-  return round_up_f32(c0 + e_acc);
+  const double e_acc = b.g_acc * (1.02 * b.Y * nq + e_sub + fabs(c0)) * 1.01;
+  return round_up_f32((c0 + e_acc) * b.scale2);
 }
 int mixed_max_slices();
 int mixed_queries_per_wave(int KA);  // 32 x query blocks per wavefront
-int mixed_blocks_per_cu(int KA, int KB);
-void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, int terms, int KA,
+int mixed_blocks_per_cu(int KA, int KB, bool f16);
+// operand row length (16-bit values) of an OperandKind at dimension d
+int operand_ka(int kind, int d);
+void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, int kind, int e, int KA,
                         const MixedBound& b, uint16_t* qop, float* cthr, hipStream_t s);
 void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* cthr, hipStream_t s);
 void launch_cand_mfma(const QueryDev& q, const MixedDev& x, int grid, hipStream_t s);
@@ -242,6 +294,16 @@ void launch_mfma32_qprep(const double* q64, int64_t m, int d, int dp, const doub
                          hipStream_t s);
 void launch_mfma32_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* vq, hipStream_t s);
 void launch_cand_mfma32(const QueryDev& q, const Mfma32Dev& x, int grid, hipStream_t s);
+
+// Test support (k_cand_mfma.hip): every pair's screen value of a small query,
+// D[qorig[q] n + j] (q < m score-order queries, j < n score-order
+// candidates), with the operand loads and product chains of the screens; and
+// the operands in plain row-major form.
+void launch_dump_mixed(const MixedDev& x, int64_t m, int64_t n, const int32_t* qorig, float* D, hipStream_t s);
+void launch_dump_mfma32(const Mfma32Dev& x, int64_t m, int64_t n, const int32_t* qorig, float* D, hipStream_t s);
+void launch_dump_cand16(const uint16_t* cop, int64_t n, int KB, uint16_t* out, hipStream_t s);
+void launch_dump_rows_u16(const uint16_t* in, int64_t m, int W, const int32_t* qorig, uint16_t* out, hipStream_t s);
+void launch_dump_rows_f32(const float* in, int64_t m, int W, const int32_t* qorig, float* out, hipStream_t s);
 
 // k_csr.hip
 struct Survivors {

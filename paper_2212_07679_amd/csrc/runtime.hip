@@ -14,6 +14,7 @@
 
 #include "query_plan.h"
 #include "snn_internal.h"
+#include "snn_testing.h"
 
 namespace snn {
 
@@ -160,6 +161,98 @@ static void build_fp32_operands(Index& ix) {
   ix.vcand_built = true;
 }
 
+// The screen a query runs.  Each matrix-core screen passes every pair whose
+// decomposed distance is within about band = 2 c_rep Y^2 of R^2 (Y = max
+// ||y||), so the pairs re-decided in float64 grow with band / R^2.  One
+// 16-bit product per coordinate is cheapest on the matrix cores, and fp16
+// (scaled rows) has a band 8x narrower than bf16 at the same rate; the bf16
+// hi/lo split costs three products and narrows the band by ~2^8 more; the fp32
+// screen (d <= 16) has an essentially empty band at a quarter of the rate.
+struct ScreenPlan {
+  snn_precision prec;  // FP64, MIXED (bf16), FP16 or FP32
+  int kind;            // OperandKind of a matrix-core screen
+  int terms() const { return kind == kOpBf16x3 ? 3 : ((prec == SNN_PREC_MIXED || prec == SNN_PREC_FP16) ? 1 : 0); }
+};
+
+// AUTO takes fp16 while its band is at most this fraction of R^2 (measured
+// on the n = 1e6, d = 16 mixture against the bf16 hi/lo screen; see the
+// design notes)
+constexpr double kF16AutoBand = 1.0;
+
+int operand_ka(int kind, int d) { return (((kind == kOpBf16x3 ? 3 : 1) * d + 15) / 16) * 16; }
+
+static ScreenPlan plan_screen(const Index& ix, const snn_options& o, double R2) {
+  const int d = ix.d;
+  const double Y = ix.max_norm;
+  auto fits = [&](int kind) { return operand_ka(kind, d) <= 16 * mixed_max_slices() && screen_in_range(kind, Y); };
+  auto band = [&](int kind) { return R2 > 0 ? 2.0 * mixed_c_rep(kind) * Y * Y / R2 : INFINITY; };
+  const bool fp32_ok = d <= mfma32_max_d() && screen_in_range(kOpF32, Y);
+  ScreenPlan p{o.precision, kOpBf16};
+  snn_precision want = o.precision;
+  if (want == SNN_PREC_AUTO && o.mixed_terms != 0) want = SNN_PREC_MIXED;  // bf16 terms asked for
+  switch (want) {
+    case SNN_PREC_FP64:
+      return p;
+    case SNN_PREC_MIXED: {
+      int t = o.mixed_terms;
+      if (t == 0) t = ((fits(kOpBf16) && band(kOpBf16) <= 0.1) || !fits(kOpBf16x3)) ? 1 : 3;
+      p.prec = SNN_PREC_MIXED;
+      p.kind = t == 3 ? kOpBf16x3 : kOpBf16;
+      if (!fits(p.kind))
+        fail(SNN_ENOTSUP, "bf16 screen: packed operand rows longer than 128 values or data too large for fp32 "
+                          "(lower d, use terms = 1, or FP64)");
+      return p;
+    }
+    case SNN_PREC_FP16:
+      p.kind = kOpF16;
+      if (!fits(kOpF16)) fail(SNN_ENOTSUP, "fp16 screen: d > 128 or data too large to scale into fp16 (use FP64)");
+      return p;
+    case SNN_PREC_FP32:
+      p.kind = kOpF32;
+      if (!fp32_ok) fail(SNN_ENOTSUP, "fp32 screen supports d <= 16 and data within fp32 range");
+      return p;
+    default:
+      break;
+  }
+  if (fits(kOpF16) && band(kOpF16) <= kF16AutoBand) return ScreenPlan{SNN_PREC_FP16, kOpF16};
+  if (fits(kOpBf16x3) && band(kOpBf16x3) <= 0.5) return ScreenPlan{SNN_PREC_MIXED, kOpBf16x3};
+  if (fp32_ok) return ScreenPlan{SNN_PREC_FP32, kOpF32};
+  if (fits(kOpF16) && band(kOpF16) <= 2.0) return ScreenPlan{SNN_PREC_FP16, kOpF16};
+  return ScreenPlan{SNN_PREC_FP64, kOpBf16};
+}
+
+// Operands and start values of a 16-bit screen for one query call.
+static MixedDev prepare_mixed(Index& ix, int kind, double R2, bool self, const double* q64, int64_t m,
+                              uint16_t* qop, float* cthr, hipStream_t s) {
+  MixedOperands& mo = ix.mixed[mixed_slot(kind)];
+  const MixedBound mb = mixed_bound(kind, mo.ka, ix.d, R2, ix.max_norm);
+  MixedDev mx{};
+  mx.KA = mo.ka;
+  mx.KB = mo.kb;
+  mx.f16 = kind == kOpF16;
+  mx.cop = mo.cand.as<uint16_t>();
+  mx.h = kind == kOpF16 ? mo.hs.as<float>() : ix.h.as<float>();
+  mx.cthr = cthr;
+  if (self) {
+    mx.qop = mo.qself.as<uint16_t>();
+    launch_mixed_qprep_self(ix.ys.as<float>(), ix.n, ix.d, mb, cthr, s);
+  } else {
+    mx.qop = qop;
+    launch_mixed_qprep(q64, m, ix.d, ix.dp, ix.mu.as<double>(), kind, mo.e, mo.ka, mb, qop, cthr, s);
+  }
+  return mx;
+}
+
+// Query rows and start values of the fp32 screen for one query call.
+static void prepare_fp32(Index& ix, double R2, bool self, const double* q64, int64_t m, float* vq, hipStream_t s) {
+  // K = d rounded up to the two coordinates of one fp32 matrix instruction
+  const MixedBound vb = mixed_bound(kOpF32, 2 * ((ix.d + 1) / 2), ix.d, R2, ix.max_norm);
+  if (self)
+    launch_mfma32_qprep_self(ix.ys.as<float>(), ix.n, ix.d, vb, vq, s);
+  else
+    launch_mfma32_qprep(q64, m, ix.d, ix.dp, ix.mu.as<double>(), vb, vq, s);
+}
+
 // Clustering request: the self-query's accepted pairs go to DBSCAN instead
 // of being assembled into neighbour lists.
 struct DbscanReq {
@@ -186,7 +279,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   o.precision = SNN_PREC_AUTO;
   if (opts) o = *opts;
   if (o.precision != SNN_PREC_FP64 && o.precision != SNN_PREC_MIXED && o.precision != SNN_PREC_AUTO &&
-      o.precision != SNN_PREC_FP32)
+      o.precision != SNN_PREC_FP32 && o.precision != SNN_PREC_FP16)
     fail(SNN_EINVAL, "unknown precision");
   if (o.mixed_terms != 0 && o.mixed_terms != 1 && o.mixed_terms != 3) fail(SNN_EINVAL, "mixed_terms must be 0, 1 or 3");
   if (o.tile_q < 0 || o.tile_c < 0) fail(SNN_EINVAL, "tile sizes must be >= 0");
@@ -222,42 +315,12 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   }
 
   // ---- precision plan
-  // A screen passes every pair whose decomposed distance is within about
-  // band(t) = 2 c_rep(t) Y^2 of R^2 (Y = max ||y||), so the pairs re-decided in
-  // float64 grow with band(t) / R^2.  bf16 with one term is cheapest on the
-  // matrix cores; three terms cost three times the products but narrow the
-  // band by ~2^8; the fp32 vector screen has an essentially empty band but
-  // costs d + 1 vector operations per pair.
+  const ScreenPlan sp = plan_screen(ix, o, R2);
+  const snn_precision prec = sp.prec;
+  const bool mix16 = prec == SNN_PREC_MIXED || prec == SNN_PREC_FP16;  // 16-bit operand screens
   const double Y = ix.max_norm;
-  auto ka_of = [&](int t) { return ((t * d + 15) / 16) * 16; };
-  auto rel_band = [&](int t) { return R2 > 0 ? 2.0 * mixed_c_rep(t) * Y * Y / R2 : INFINITY; };
-  auto fits = [&](int t) { return ka_of(t) <= 16 * mixed_max_slices(); };
-  int terms = o.mixed_terms;
-  if (terms == 0) {
-    if (fits(1) && rel_band(1) <= 0.1)
-      terms = 1;
-    else if (fits(3))
-      terms = 3;
-    else
-      terms = 1;
-  }
-  snn_precision prec = o.precision;
-  if (prec == SNN_PREC_AUTO) {
-    if (fits(terms) && rel_band(terms) <= 0.5)
-      prec = SNN_PREC_MIXED;
-    else if (d <= mfma32_max_d())
-      prec = SNN_PREC_FP32;
-    else if (fits(1) && rel_band(1) <= 2.0) {
-      prec = SNN_PREC_MIXED;
-      terms = 1;
-    } else
-      prec = SNN_PREC_FP64;
-  }
-  if (prec == SNN_PREC_MIXED && !fits(terms))
-    fail(SNN_ENOTSUP, "mixed screen: packed operand rows longer than 128 bf16 (lower d or use terms=1)");
-  if (prec == SNN_PREC_FP32 && d > mfma32_max_d()) fail(SNN_ENOTSUP, "fp32 screen supports d <= 16");
   int T_fixed = 0;
-  if (prec == SNN_PREC_MIXED) T_fixed = 4 * mixed_queries_per_wave(ka_of(terms));
+  if (mix16) T_fixed = 4 * mixed_queries_per_wave(operand_ka(sp.kind, d));
   if (prec == SNN_PREC_FP32) T_fixed = mfma32_queries_per_tile();
   if (T_fixed && o.tile_q && o.tile_q != T_fixed)
     fail(SNN_EINVAL, "tile_q must be " + std::to_string(T_fixed) + " for this screen and dimension");
@@ -266,7 +329,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   // against 2048-16384 with 256-query tiles), 1024 for the float64 screen
   const int CH = o.tile_c ? o.tile_c : (prec == SNN_PREC_FP64 ? 1024 : 8192);
   if (prec != SNN_PREC_FP64 && CH % 32 != 0) fail(SNN_EINVAL, "matrix-core screens: tile_c must be a multiple of 32");
-  if (prec == SNN_PREC_MIXED) build_mixed_operands(ix, terms);
+  if (mix16) build_mixed_operands(ix, sp.kind);
   if (prec == SNN_PREC_FP32) build_fp32_operands(ix);
   const int ntiles = (int)std::max<int64_t>(1, (m + T - 1) / T);
 
@@ -333,9 +396,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     p.rp_s = c.take<int64_t>(m + 1);
     p.cnt_o = c.take<int32_t>(std::max<int64_t>(m, 1));
     p.lists =c.take<int32_t>((size_t)row_sort_lists() * std::max<int64_t>(m, 1));
-    const bool mix = prec == SNN_PREC_MIXED;
-    p.qop = c.take<uint16_t>(mix && !self ? (size_t)m * ka_of(terms) : 1);
-    p.cthr = c.take<float>(mix ? std::max<int64_t>(m, 1) : 1);
+    p.qop = c.take<uint16_t>(mix16 && !self ? (size_t)m * operand_ka(sp.kind, d) : 1);
+    p.cthr = c.take<float>(mix16 ? std::max<int64_t>(m, 1) : 1);
     p.vq = c.take<float>(prec == SNN_PREC_FP32 ? (size_t)std::max<int64_t>(m, 1) * mfma32_query_floats(d) : 1);
     return p;
   };
@@ -383,7 +445,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
                  P.wpart, s);
   // query slots per wavefront (stats): the matrix-core screens evaluate
   // whole 32-query blocks, the float64 screen one query at a time
-  const int qpw = prec == SNN_PREC_MIXED  ? mixed_queries_per_wave(ka_of(terms))
+  const int qpw = mix16                   ? mixed_queries_per_wave(operand_ka(sp.kind, d))
                   : prec == SNN_PREC_FP32 ? mfma32_queries_per_tile() / 4
                                           : 1;
   // chunk-major work order inside groups of G score-adjacent tiles (L2 reuse)
@@ -418,30 +480,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   qd.sym = sym;
 
   MixedDev mx{};
-  if (prec == SNN_PREC_MIXED) {
-    MixedOperands& mo = ix.mixed[terms == 1 ? 0 : 1];
-    const MixedBound mb = mixed_bound(terms, mo.ka, d, R2, Y);
-    mx.KA = mo.ka;
-    mx.KB = mo.kb;
-    mx.cop = mo.cand.as<uint16_t>();
-    mx.h = ix.h.as<float>();
-    mx.cthr = P.cthr;
-    if (self) {
-      mx.qop = mo.qself.as<uint16_t>();
-      launch_mixed_qprep_self(ix.ys.as<float>(), n, d, mb, P.cthr, s);
-    } else {
-      mx.qop = P.qop;
-      launch_mixed_qprep(q64, m, d, ix.dp, ix.mu.as<double>(), terms, mo.ka, mb, P.qop, P.cthr, s);
-    }
-  }
-  if (prec == SNN_PREC_FP32) {
-    // K = d rounded up to the two coordinates of one fp32 matrix instruction
-    const MixedBound vb = mixed_bound(0, 2 * ((d + 1) / 2), d, R2, Y);
-    if (self)
-      launch_mfma32_qprep_self(ix.ys.as<float>(), n, d, vb, P.vq, s);
-    else
-      launch_mfma32_qprep(q64, m, d, ix.dp, ix.mu.as<double>(), vb, P.vq, s);
-  }
+  if (mix16) mx = prepare_mixed(ix, sp.kind, R2, self, q64, m, P.qop, P.cthr, s);
+  if (prec == SNN_PREC_FP32) prepare_fp32(ix, R2, self, q64, m, P.vq, s);
 
   // survivors: capacity remembered on the index, grown on overflow
   // bytes per survivor: the pair, and per result row, column, distance, slot
@@ -476,13 +516,13 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       launch_fill_u64(&P.ctl->accepted, 1, 0ull, s);
       launch_fill_i32(P.row_cnt, m, 0, s);
     }
-    const int per_cu = prec == SNN_PREC_MIXED  ? mixed_blocks_per_cu(mx.KA, mx.KB)
+    const int per_cu = mix16                   ? mixed_blocks_per_cu(mx.KA, mx.KB, mx.f16 != 0)
                        : prec == SNN_PREC_FP32 ? mfma32_blocks_per_cu(d)
                                                : fp64_blocks_per_cu(ix.dp);
     const int grid = std::max(di.xcds, (di.cus * per_cu / di.xcds) * di.xcds);
     if (st) SNN_HIP(hipEventRecord(ev[1], s));
     if (m > 0) {
-      if (prec == SNN_PREC_MIXED)
+      if (mix16)
         launch_cand_mfma(qd, mx, grid, s);
       else if (prec == SNN_PREC_FP32)
         launch_cand_mfma32(qd, Mfma32Dev{P.vq, mfma32_query_floats(d), d, ix.vcand.as<float>(), ix.h.as<float>()}, grid,
@@ -505,7 +545,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
           st->pairs_recheck = (int64_t)hc.ctl.survivors;
           st->nnz = (int64_t)hc.ctl.accepted;
           st->precision_used = prec;
-          st->terms_used = prec == SNN_PREC_MIXED ? terms : 0;
+          st->terms_used = sp.terms();
         }
         break;
       }
@@ -548,7 +588,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
         st->pairs_recheck = (int64_t)hc.ctl.survivors;
         st->nnz = hc.nnz;
         st->precision_used = prec;
-        st->terms_used = prec == SNN_PREC_MIXED ? terms : 0;
+        st->terms_used = sp.terms();
       }
       if (hc.nnz > out->nnz_cap) {
         char buf[160];
@@ -601,6 +641,112 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   }
 }
 
+// ------------------------------------------------------------------------ test support
+// The screen a query would run, and the sizes of its operand rows.
+static ScreenPlan debug_plan(const Index& ix, double R, const snn_options* opts, snn_screen_layout* lay) {
+  if (!std::isfinite(R) || R < 0) fail(SNN_EINVAL, "R must be finite and >= 0");
+  snn_options o{};
+  o.precision = SNN_PREC_AUTO;
+  if (opts) o = *opts;
+  if (o.metric != SNN_METRIC_L2) fail(SNN_EINVAL, "screen values are dumped for the Euclidean metric");
+  if (o.mixed_terms != 0 && o.mixed_terms != 1 && o.mixed_terms != 3) fail(SNN_EINVAL, "mixed_terms must be 0, 1 or 3");
+  const ScreenPlan sp = plan_screen(ix, o, R * R);
+  if (sp.prec == SNN_PREC_FP64) fail(SNN_EINVAL, "the float64 path has no screen values");
+  const int d = ix.d;
+  lay->precision = sp.prec;
+  lay->terms = sp.terms();
+  if (sp.prec == SNN_PREC_FP32) {
+    lay->ka = mfma32_query_floats(d);
+    lay->kb = d;
+    lay->chain = 2 * ((d + 1) / 2);
+    lay->scale_exp = 0;
+  } else {
+    lay->ka = operand_ka(sp.kind, d);
+    lay->kb = (sp.kind == kOpBf16x3 && d % 16 == 0) ? 2 * d : lay->ka;
+    lay->chain = lay->ka;
+    lay->scale_exp = sp.kind == kOpF16 ? f16_scale_exp(ix.max_norm) : 0;
+  }
+  return sp;
+}
+
+static void debug_screen(Index& ix, const void* Q, int64_t m, double R, const snn_options* opts, float* D, float* H,
+                         float* C, void* A, void* B, snn_screen_layout* lay) {
+  const ScreenPlan sp = debug_plan(ix, R, opts, lay);
+  if (m < 1 || m >= (int64_t)INT32_MAX) fail(SNN_EINVAL, "m must be in [1, 2^31 - 1)");
+  if (!Q || !D || !H || !C || !A || !B) fail(SNN_EINVAL, "NULL buffer");
+  DeviceScope scope(ix.arena.dev().device);
+  hipStream_t s = ix.arena.stream();
+  const int d = ix.d;
+  const int64_t n = ix.n;
+  const double R2 = R * R;
+  const bool mix16 = sp.prec != SNN_PREC_FP32;
+  if (mix16)
+    build_mixed_operands(ix, sp.kind);
+  else
+    build_fp32_operands(ix);
+  // the queries in score order, as a query call sorts them
+  const int nb = query_buckets(m);
+  auto plan = [&](Carver& c) {
+    struct P {
+      unsigned long long* ctl;
+      uint32_t *ukey, *val, *hist;
+      double *qa_in, *qn_in, *q64, *qa, *qn;
+      int32_t *qorig, *row_cnt;
+      char* scan;
+      uint16_t* qop;
+      float *cthr, *vq;
+    } p;
+    p.ctl = c.take<unsigned long long>(1);
+    p.ukey = c.take<uint32_t>(m);
+    p.val = c.take<uint32_t>(m);
+    p.hist = c.take<uint32_t>(nb);
+    p.qa_in = c.take<double>(m);
+    p.qn_in = c.take<double>(m);
+    p.q64 = c.take<double>((size_t)m * ix.dp);
+    p.qa = c.take<double>(m);
+    p.qn = c.take<double>(m);
+    p.qorig = c.take<int32_t>(m);
+    p.row_cnt = c.take<int32_t>(m);
+    p.scan = c.take<char>(scan_scratch_bytes(nb));
+    p.qop = c.take<uint16_t>(mix16 ? (size_t)m * lay->ka : 1);
+    p.cthr = c.take<float>(m);
+    p.vq = c.take<float>(mix16 ? 1 : (size_t)m * lay->ka);
+    return p;
+  };
+  Carver probe(nullptr);
+  plan(probe);
+  ScopedAlloc mem(ix.arena, probe.off + 256);
+  Carver carve(mem.get());
+  auto P = plan(carve);
+  launch_query_init(P.ctl, 1, P.row_cnt, m, P.hist, nb, nullptr, nullptr, 0, s);
+  launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), ix.key.as<double>(), (int)n, nb, P.ukey,
+                    P.val, P.hist, P.qa_in, P.qn_in, reinterpret_cast<int*>(P.ctl), s);
+  exclusive_scan_u32(P.hist, nb, P.scan, s);
+  launch_query_gather(ix.dtype, Q, m, d, ix.dp, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, P.q64, P.qorig, P.qa, P.qn,
+                      s);
+  if (mix16) {
+    const MixedDev mx = prepare_mixed(ix, sp.kind, R2, false, P.q64, m, P.qop, P.cthr, s);
+    launch_dump_mixed(mx, m, n, P.qorig, D, s);
+    SNN_HIP(hipMemcpyAsync(H, mx.h, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    launch_dump_rows_f32(P.cthr, m, 1, P.qorig, C, s);
+    launch_dump_rows_u16(P.qop, m, lay->ka, P.qorig, static_cast<uint16_t*>(A), s);
+    launch_dump_cand16(mx.cop, n, lay->kb, static_cast<uint16_t*>(B), s);
+  } else {
+    prepare_fp32(ix, R2, false, P.q64, m, P.vq, s);
+    const Mfma32Dev x{P.vq, lay->ka, d, ix.vcand.as<float>(), ix.h.as<float>()};
+    launch_dump_mfma32(x, m, n, P.qorig, D, s);
+    SNN_HIP(hipMemcpyAsync(H, ix.h.ptr, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    launch_dump_rows_f32(P.vq, m, lay->ka, P.qorig, static_cast<float*>(A), s);
+    SNN_HIP(hipMemcpy2DAsync(C, sizeof(float), static_cast<float*>(A) + d, sizeof(float) * lay->ka, sizeof(float), m,
+                             hipMemcpyDeviceToDevice, s));
+    SNN_HIP(hipMemcpyAsync(B, ix.ys.ptr, sizeof(float) * n * d, hipMemcpyDeviceToDevice, s));
+  }
+  unsigned long long bad = 0;
+  SNN_HIP(hipMemcpyAsync(&bad, P.ctl, sizeof(bad), hipMemcpyDeviceToHost, s));
+  SNN_HIP(hipStreamSynchronize(s));
+  if (bad) fail(SNN_EINVAL, "Q contains NaN or Inf");
+}
+
 }  // namespace snn
 
 using namespace snn;
@@ -618,6 +764,7 @@ static void free_index(snn_index_s* ix) {
   for (auto& mo : ix->mixed) {
     mo.cand.reset(a);
     mo.qself.reset(a);
+    mo.hs.reset(a);
   }
   {
     ix->vcand.reset(a);
@@ -730,6 +877,21 @@ snn_status snn_sort_pairs_u32(const snn_device* dev, uint32_t* keys, uint32_t* v
     DeviceScope scope(dev->device);
     DeviceArena a(*dev);
     radix_sort_pairs(a, keys, vals, n, begin_bit, end_bit, a.stream());
+  });
+}
+
+snn_status snn_debug_screen_layout(snn_index_t idx, double R, const snn_options* opts, snn_screen_layout* layout) {
+  return guard([&] {
+    if (!idx || !layout) fail(SNN_EINVAL, "NULL argument");
+    debug_plan(*idx, R, opts, layout);
+  });
+}
+
+snn_status snn_debug_screen(snn_index_t idx, const void* Q, int64_t m, double R, const snn_options* opts, float* D,
+                            float* H, float* C, void* A, void* B, snn_screen_layout* layout) {
+  return guard([&] {
+    if (!idx || !layout) fail(SNN_EINVAL, "NULL argument");
+    debug_screen(*idx, Q, m, R, opts, D, H, C, A, B, layout);
   });
 }
 

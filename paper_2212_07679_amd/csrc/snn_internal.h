@@ -129,12 +129,16 @@ const DeviceInfo& device_info(int device);
 // ---------------------------------------------------------------- index
 // Everything lives in sorted (score) order unless noted.
 struct MixedOperands {
-  int terms = 0;     // 1 or 3
-  int ka = 0;        // query operand row length in bf16 (multiple of 16)
-  int kb = 0;        // candidate row length: ka, or 2 ka / 3 when the rows are [hi | lo]
-  Buffer cand;       // (n + 32) x kb bf16: candidate operand rows, zero padding rows
-  Buffer qself;      // n x ka bf16: query operand rows for self-queries
+  bool built = false;  // operands of the current rows
+  int ka = 0;          // query operand row length in 16-bit values (multiple of 16)
+  int kb = 0;          // candidate row length: ka, or 2 ka / 3 when the rows are [hi | lo]
+  int e = 0;           // fp16: operands are fp16(2^e y)
+  Buffer cand;         // (n + 32) x kb: candidate operand rows, zero padding rows
+  Buffer qself;        // n x ka: query operand rows for self-queries
+  Buffer hs;           // fp16: n + 32 floats, h scaled by 2^(2e) (rounded down), padding +inf
 };
+// Slot of an operand kind (OperandKind of query_plan.h: bf16, bf16 hi/lo, fp16) in Index::mixed.
+inline int mixed_slot(int kind) { return kind == 3 ? 1 : (kind == 4 ? 2 : 0); }
 
 struct Index {
   explicit Index(const snn_device& d) : arena(d) {}
@@ -153,7 +157,7 @@ struct Index {
   Buffer ys;    // n x d floats: fl32(p - mu), sorted
   Buffer h;     // n + 32 floats: ||ys||^2 / 2 rounded to nearest, sorted; padding +inf
   Buffer ynorm; // n floats: ||ys|| rounded up, sorted
-  MixedOperands mixed[2];  // [0]: terms = 1, [1]: terms = 3
+  MixedOperands mixed[3];  // bf16 one term, bf16 hi/lo, fp16 (mixed_slot)
   Buffer vcand;            // fp32 screen candidate operand blocks (k_cand_mfma32)
   bool vcand_built = false;
 
@@ -184,7 +188,8 @@ void exclusive_scan_u32(uint32_t* data, int64_t n, void* scratch, hipStream_t s)
 
 // k_index.hip
 void build_index(Index& ix, const void* X);
-void build_mixed_operands(Index& ix, int terms);
+// screen operands of one OperandKind (bf16, bf16 hi/lo or fp16) for the current rows
+void build_mixed_operands(Index& ix, int kind);
 // appends k rows (ids n .. n+k-1) with the index's mu and v: merged into the
 // key order, bounds updated, screen operands marked for rebuilding
 void insert_points(Index& ix, const void* X, int64_t k);

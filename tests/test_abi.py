@@ -10,18 +10,20 @@ import pytest
 from paper_2212_07679_amd import binding as B
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "snn.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("snn.h", "snn_testing.h")]
 
 
 def declared_symbols():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(snn_[a-z0-9_]+)\s*\(", src)))
+    syms = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        syms.update(re.findall(r"\b(snn_[a-z0-9_]+)\s*\(", src))
+    return sorted(syms)
 
 
 def test_header_declares_the_boundary():
     syms = declared_symbols()
-    for s in ("snn_index", "snn_query", "snn_query_self", "snn_index_free", "snn_last_error"):
+    for s in ("snn_index", "snn_query", "snn_query_self", "snn_index_free", "snn_last_error", "snn_debug_screen"):
         assert s in syms
 
 
@@ -148,3 +150,10 @@ def test_no_device_is_a_clean_error():
     fake = ctypes.c_void_p(0x1000)
     assert L.snn_index(ctypes.byref(dev), fake, 10, 2, 0, ctypes.byref(out)) == B.SNN_EDEVICE
     assert b"device" in L.snn_last_error()
+
+
+def test_debug_screen_argument_errors():
+    L = B.lib()
+    lay = B.snn_screen_layout()
+    assert L.snn_debug_screen_layout(None, 1.0, None, ctypes.byref(lay)) == B.SNN_EINVAL
+    assert L.snn_debug_screen(None, None, 1, 1.0, None, None, None, None, None, None, ctypes.byref(lay)) == B.SNN_EINVAL

@@ -49,7 +49,7 @@ def check_same(got, ref, what=""):
     assert np.all(rel <= 1e-5), f"{what}: max rel dist err {rel.max()}"
 
 
-PRECS = ["fp64", "mixed", "fp32", "auto"]
+PRECS = ["fp64", "mixed", "fp16", "fp32", "auto"]
 
 
 @pytest.mark.parametrize("terms", [1, 3])
@@ -136,7 +136,7 @@ def test_dims(B, d):
     ref = oracle.brute_radius(P, Q, R)
     idx = B.Index(to_dev(P))
     for prec in PRECS:
-        if (prec == "fp32" and d > 16) or (prec == "mixed" and d > 128):
+        if (prec == "fp32" and d > 16) or (prec in ("mixed", "fp16") and d > 128):
             with pytest.raises(B.SnnError) as e:
                 idx.query(to_dev(Q), R, precision=prec)
             assert e.value.status == B.SNN_ENOTSUP
@@ -328,14 +328,16 @@ def test_auto_policy(B):
     w2 = W.gmm16(n=30_000, m=500, R=1.5)
     idx2 = B.Index(to_dev(w2.P))
     st2 = idx2.query(to_dev(w2.Q), w2.R, stats=True)[3]
-    assert B.PRECISION_NAMES[st2["precision_used"]] == "mixed" and st2["terms_used"] == 3
+    assert B.PRECISION_NAMES[st2["precision_used"]] == "fp16" and st2["terms_used"] == 1  # fp16 band < R^2
+    st2b = idx2.query(to_dev(w2.Q), 0.9, stats=True)[3]
+    assert B.PRECISION_NAMES[st2b["precision_used"]] == "mixed" and st2b["terms_used"] == 3  # fp16 band > R^2
     w3 = W.gmm128z(n=5_000, R=4.0)
     idx3 = B.Index(to_dev(w3.P))
     st3 = idx3.query_self(w3.R, stats=True)[3]
-    assert B.PRECISION_NAMES[st3["precision_used"]] == "mixed" and st3["terms_used"] == 1
+    assert B.PRECISION_NAMES[st3["precision_used"]] == "fp16" and st3["terms_used"] == 1
 
 
-@pytest.mark.parametrize("prec", ["fp32", "mixed", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "mixed", "fp16", "fp64"])
 def test_symmetric_self_scan(B, prec):
     # each unordered pair scanned once and reported in both rows: identical
     # output to the full scan, with about half the window pairs
@@ -351,7 +353,7 @@ def test_symmetric_self_scan(B, prec):
     assert 0.45 * fw < hw < 0.6 * fw, (hw, fw)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "mixed", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "mixed", "fp16", "fp64"])
 def test_dense_self_output(B, prec):
     # many neighbours per row: survivor staging drains, wave/block row sorts
     say(f"dense self {prec}")
@@ -362,7 +364,7 @@ def test_dense_self_output(B, prec):
     check_same(idx.query_self(w.R, precision=prec), ref, f"dense self {prec}")
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["mixed", "fp16", "fp32", "fp64"])
 @pytest.mark.parametrize("tile_c", [32, 96, 1024])
 def test_small_work_units(B, precision, tile_c):
     """Many work units per tile (and chunk ends inside windows) for every screen."""
