@@ -89,9 +89,24 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
-// per-wavefront pair stage: flushed when fewer than one query block's worth
-// of pushes (16 x 64) would fit
-constexpr int kWaveStage = 1536;
+// Per-wavefront pair stages (entries): flushed when fewer than one query
+// block's worth of pushes (16 x 64) would fit.  The 16-bit screens keep theirs
+// small enough for four workgroups (four waves per SIMD) per CU; the fp32
+// screen, whose dense outputs push much more, keeps a larger one (measured on
+// the n = 1e6, d = 16 set: 0.420 ms with 1264 entries against 0.422 ms with
+// 1536 at two steps of prefetch, 0.442 against 0.480 ms at one).
+#ifndef SNN_WAVE_STAGE
+#define SNN_WAVE_STAGE 1264
+#endif
+constexpr int kWaveStage16 = SNN_WAVE_STAGE;
+constexpr int kWaveStage32 = 1536;
+// candidate steps whose operands are in flight ahead of the one being
+// screened in the 16-bit screens (same set: 0.422 ms with two or three,
+// 0.480 ms with one)
+#ifndef SNN_SCREEN_PREFETCH
+#define SNN_SCREEN_PREFETCH 2
+#endif
+constexpr int kPrefetch = SNN_SCREEN_PREFETCH;
 
 // Out-of-sample queries: operands and thresholds from the float64 rows.
 __global__ __launch_bounds__(kThreads) void k_mixed_qprep(const double* __restrict__ q64, int64_t m, int d, int dp,
@@ -162,6 +177,27 @@ __device__ __forceinline__ float max16(const f32x16& a) {
   return fmaxf(m0, m3);
 }
 
+// max of m and the 16 values of a (eight 3-input maxima)
+__device__ __forceinline__ float max16_into(float m, const f32x16& a) {
+  float m0 = fmaxf(fmaxf(m, a[0]), a[1]);
+  float m1 = fmaxf(fmaxf(a[2], a[3]), a[4]);
+  float m2 = fmaxf(fmaxf(a[5], a[6]), a[7]);
+  float m3 = fmaxf(fmaxf(a[8], a[9]), a[10]);
+  float m4 = fmaxf(fmaxf(a[11], a[12]), a[13]);
+  m0 = fmaxf(fmaxf(m0, m1), m2);
+  m3 = fmaxf(fmaxf(m3, m4), a[14]);
+  return fmaxf(fmaxf(m0, m3), a[15]);
+}
+
+// max over the QB blocks of a lane's accumulators
+template <int QB>
+__device__ __forceinline__ float max_blocks(const f32x16 (&acc)[QB]) {
+  float m = max16(acc[0]);
+#pragma unroll
+  for (int b = 1; b < QB; ++b) m = max16_into(m, acc[b]);
+  return m;
+}
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format
 
@@ -171,12 +207,19 @@ constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format
 // unit (the look-ahead of the last step) are outside num_records and return
 // zeros without touching memory.
 template <int NL, typename V>
-__device__ __forceinline__ void load_step(V (&B)[NL], float& h, __amdgpu_buffer_rsrc_t rc,
-                                          __amdgpu_buffer_rsrc_t rh, int voff_c, int voff_h, int it) {
+__device__ __forceinline__ void load_cand(V (&B)[NL], __amdgpu_buffer_rsrc_t rc, int voff_c, int it) {
 #pragma unroll
   for (int s = 0; s < NL; ++s)  // slices are 1 KB apart in a 32-row block
     B[s] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rc, voff_c, it * (NL * 1024) + s * 1024, 0));
-  h = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rh, voff_h, it * 128, 0));
+}
+__device__ __forceinline__ float load_h(__amdgpu_buffer_rsrc_t rh, int voff_h, int it) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rh, voff_h, it * 128, 0));
+}
+template <int NL, typename V>
+__device__ __forceinline__ void load_step(V (&B)[NL], float& h, __amdgpu_buffer_rsrc_t rc,
+                                          __amdgpu_buffer_rsrc_t rh, int voff_c, int voff_h, int it) {
+  load_cand<NL>(B, rc, voff_c, it);
+  h = load_h(rh, voff_h, it);
 }
 
 // The max/compare epilogue of one step: acc[b] is the 32x32 block of query
@@ -190,17 +233,14 @@ __device__ __forceinline__ void load_step(V (&B)[NL], float& h, __amdgpu_buffer_
 //       wave pushes one pair per lane per round (cheaper when passes are
 //       many, as in dense bf16 outputs: measured on one box, 1.25 vs 1.51 ms
 //       for the 256-instance batch, 21 vs 17 ms for the d = 3 particles).
-template <int QB, bool ROWS>
-__device__ __forceinline__ void screen_epilogue(const f32x16 (&acc)[QB], float hj, int jj, int64_t q0, int half,
-                                                int2* wbuf, int& wcnt, const PairSink& sink) {
+// The common case is one max over all the lane's accumulators and one
+// compare; blocks are told apart only when some lane passes.
+template <int QB, bool ROWS, int STAGE>
+__device__ __forceinline__ void screen_pushes(const f32x16 (&acc)[QB], float hj, int jj, int64_t q0, int half,
+                                              int2* wbuf, int& wcnt, const PairSink& sink) {
   uint64_t pm[QB];  // wave masks: lanes with a passing accumulator in block b
-  uint64_t any = 0;
 #pragma unroll
-  for (int b = 0; b < QB; ++b) {
-    pm[b] = __ballot(max16(acc[b]) >= hj);
-    any |= pm[b];
-  }
-  if (!any) return;
+  for (int b = 0; b < QB; ++b) pm[b] = QB == 1 ? ~0ull : __ballot(max16(acc[b]) >= hj);
   // uncommon: push the passing pairs of each block with a passing lane into
   // the wavefront's LDS stage (at most 16 x 64 per block).  The row base is
   // made opaque per step so that the 16 QB row offsets are not hoisted out of
@@ -224,8 +264,15 @@ __device__ __forceinline__ void screen_epilogue(const f32x16 (&acc)[QB], float h
         wave_push(wbuf, wcnt, p, qb + b * 32 + 8 * (r >> 2) + (r & 3), jj);
       }
     }
-    if (wcnt > kWaveStage - 16 * kWave) wave_flush(wbuf, wcnt, sink);
+    if (wcnt > STAGE - 16 * kWave) wave_flush(wbuf, wcnt, sink);
   }
+}
+
+template <int QB, bool ROWS, int STAGE>
+__device__ __forceinline__ void screen_epilogue(const f32x16 (&acc)[QB], float hj, int jj, int64_t q0, int half,
+                                                int2* wbuf, int& wcnt, const PairSink& sink) {
+  if (!__ballot(max_blocks<QB>(acc) >= hj)) return;
+  screen_pushes<QB, ROWS, STAGE>(acc, hj, jj, q0, half, wbuf, wcnt, sink);
 }
 
 // The products of one 32-candidate step for QB blocks of 32 queries.
@@ -242,15 +289,29 @@ __device__ __forceinline__ void step_products(const typename Op16<F16>::V (&A)[Q
     for (int b = 0; b < QB; ++b) acc[b] = Op16<F16>::mfma(A[b][s], B[s < NL ? s : s - NL], acc[b]);
 }
 
-// One 32-candidate step of the 16-bit screen: products, then compares.
-template <bool F16, int NS, int QB, int NL>
-__device__ __forceinline__ void screen_step(const typename Op16<F16>::V (&A)[QB][NS], const f32x16 (&Cin)[QB],
-                                            const typename Op16<F16>::V (&B)[NL], float hv, int jr, int span, int j0,
-                                            int64_t q0, int half, int2* wbuf, int& wcnt, const PairSink& sink) {
-  const float hj = jr < span ? hv : INFINITY;
+// One 32-candidate step of a 16-bit screen on operand set (B, h): products,
+// the next load into the set (PF steps ahead; reads past the unit return
+// zeros), one max over the lane's accumulators and one compare.  Only the
+// last step of a unit can have lanes past its span (units are cut at
+// multiples of 32 rows except at the end of the index), so only it masks.
+template <bool F16, int NS, int QB, int NL, int PF, bool LAST>
+__device__ __forceinline__ void mixed_step(const typename Op16<F16>::V (&A)[QB][NS], const f32x16 (&Cin)[QB],
+                                           typename Op16<F16>::V (&B)[NL], float& h, __amdgpu_buffer_rsrc_t rc,
+                                           __amdgpu_buffer_rsrc_t rh, int voff_c, int voff_h, int it, int span,
+                                           int l32, int j0, int64_t q0, int half, int2* wbuf, int& wcnt,
+                                           const PairSink& sink) {
   f32x16 acc[QB];
   step_products<F16, NS, QB, NL>(A, Cin, B, acc);
-  screen_epilogue<QB, false>(acc, hj, j0 + jr, q0, half, wbuf, wcnt, sink);
+  if (!LAST) load_cand<NL>(B, rc, voff_c, it + PF);
+  float hj = h;
+  if (LAST && it * 32 + l32 >= span) hj = INFINITY;
+  if (__ballot(max_blocks<QB>(acc) >= hj))
+    screen_pushes<QB, false, kWaveStage16>(acc, hj, j0 + it * 32 + l32, q0, half, wbuf, wcnt, sink);
+  // the set's next h goes into the register the compare just read: the load
+  // stays after every use of hj (hoisted above one, it would need a second
+  // register and a copy that waits for the load at the end of every step)
+  __builtin_amdgcn_sched_barrier(0);
+  if (!LAST) h = load_h(rh, voff_h, it + PF);
 }
 
 // Query operands of one wavefront: QB blocks of 32 rows of NS slices (lane
@@ -282,7 +343,7 @@ __device__ __forceinline__ void load_queries(const MixedDev& x, int64_t m, int64
 template <bool F16, int NS, int QB, int NL>
 __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) {
   typedef typename Op16<F16>::V V;
-  __shared__ int2 wstage[kWaves][kWaveStage];
+  __shared__ int2 wstage[kWaves][kWaveStage16];
   __shared__ long long s_unit;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int l32 = lane & 31, half = lane >> 5;
@@ -322,17 +383,30 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
     const __amdgpu_buffer_rsrc_t rh =
         __builtin_amdgcn_make_buffer_rsrc((void*)(x.h + j0), (short)0, nsteps * 128, kRsrcWord3);
     const int voff_c = lane * 16, voff_h = l32 * 4;
-    V B0[NL], B1[NL];
-    float h0, h1;
-    load_step<NL>(B0, h0, rc, rh, voff_c, voff_h, 0);
-    for (int it = 0; it < nsteps; it += 2) {
-      load_step<NL>(B1, h1, rc, rh, voff_c, voff_h, it + 1);
-      screen_step<F16, NS, QB, NL>(A, Cin, B0, h0, it * 32 + l32, span, (int)j0, q0, half, wbuf, wcnt, q.sink);
-      if (it + 1 >= nsteps) break;
-      load_step<NL>(B0, h0, rc, rh, voff_c, voff_h, it + 2);
-      screen_step<F16, NS, QB, NL>(A, Cin, B1, h1, (it + 1) * 32 + l32, span, (int)j0, q0, half, wbuf, wcnt,
-                                   q.sink);
+    // kPrefetch register sets of operands rotate: step it uses set it % PF,
+    // whose next load (step it + PF) is issued as soon as the step's matrix
+    // instructions have read it; the candidate's h is read once the step's
+    // compare has used it.
+    constexpr int PF = kPrefetch;
+    V Bs[PF][NL];
+    float hs[PF];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) load_step<NL>(Bs[p], hs[p], rc, rh, voff_c, voff_h, p);
+    const int last = nsteps - 1;
+    for (int it0 = 0; it0 < last; it0 += PF) {
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const int it = it0 + p;
+        if (it >= last) break;
+        mixed_step<F16, NS, QB, NL, PF, false>(A, Cin, Bs[p], hs[p], rc, rh, voff_c, voff_h, it, span, l32, (int)j0,
+                                               q0, half, wbuf, wcnt, q.sink);
+      }
     }
+#pragma unroll
+    for (int p = 0; p < PF; ++p)
+      if (last % PF == p)
+        mixed_step<F16, NS, QB, NL, PF, true>(A, Cin, Bs[p], hs[p], rc, rh, voff_c, voff_h, last, span, l32, (int)j0,
+                                              q0, half, wbuf, wcnt, q.sink);
   }
   wave_flush(wbuf, wcnt, q.sink);
 }
@@ -385,7 +459,7 @@ __device__ __forceinline__ void step_products32(const float (&A)[QB][NK], const 
 
 template <int NK, int QB>
 __global__ __launch_bounds__(kThreads) void k_cand_mfma32(QueryDev q, Mfma32Dev x) {
-  __shared__ int2 wstage[kWaves][kWaveStage];
+  __shared__ int2 wstage[kWaves][kWaveStage32];
   __shared__ long long s_unit;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int l32 = lane & 31, half = lane >> 5;
@@ -432,7 +506,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma32(QueryDev q, Mfma32Dev 
       const float hj = jr < span ? hv : INFINITY;
       f32x16 acc[QB];
       step_products32<NK, QB>(A, Cin, B, acc);
-      screen_epilogue<QB, true>(acc, hj, (int)j0 + jr, q0, half, wbuf, wcnt, q.sink);
+      screen_epilogue<QB, true, kWaveStage32>(acc, hj, (int)j0 + jr, q0, half, wbuf, wcnt, q.sink);
     };
     load(B0, h0, 0);
     for (int it = 0; it < nsteps; it += 2) {
