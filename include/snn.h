@@ -327,6 +327,19 @@ snn_status snn_dbscan_index(snn_index_t index, double eps, int32_t min_samples, 
 snn_status snn_sort_pairs_u32(const snn_device* dev, uint32_t* keys, uint32_t* vals, int64_t n,
                               int begin_bit, int end_bit);
 
+/* The same sort without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the workspace is a static device array of the library
+ * (18 MiB on every GPU it runs on, held until the process ends), so at most
+ * 2^21 pairs.  dev->alloc / dev->free are not used; the work is enqueued on
+ * dev->stream (kernel launches only: no allocation, copy, memset or
+ * synchronisation) and the call returns without waiting for it.  All calls on
+ * one GPU share that array: calls whose work overlaps on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * Errors: SNN_EINVAL (as snn_sort_pairs_u32, and n > 2^21), SNN_EDEVICE. */
+snn_status snn_sort_pairs_u32_noalloc(const snn_device* dev, uint32_t* keys, uint32_t* vals, int64_t n,
+                                      int begin_bit, int end_bit);
+
 /* Message for the last failed call on this thread ("" if none). */
 const char* snn_last_error(void);
 

@@ -182,6 +182,8 @@ SIGNATURES = {
     "snn_index_insert": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
     "snn_sort_pairs_u32": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_void_p, ctypes.c_void_p,
                                           ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
+    "snn_sort_pairs_u32_noalloc": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_void_p, ctypes.c_void_p,
+                                                  ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
     "snn_dbscan": (ctypes.c_int, [ctypes.POINTER(snn_device), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.POINTER(ctypes.c_int64)]),
@@ -457,6 +459,24 @@ def sort_pairs_u32(keys: torch.Tensor, vals: torch.Tensor, begin_bit: int = 0, e
     alloc = _TorchAllocator(device)
     _check(lib().snn_sort_pairs_u32(ctypes.byref(alloc.dev), ctypes.c_void_p(keys.data_ptr()),
                                     ctypes.c_void_p(vals.data_ptr()), keys.numel(), begin_bit, end_bit))
+
+
+def sort_pairs_u32_noalloc(keys: torch.Tensor, vals: torch.Tensor, begin_bit: int = 0, end_bit: int = 32,
+                           stream: Optional[torch.cuda.Stream] = None) -> None:
+    """The same sort through the allocation-free entry point (static device
+    workspace, at most 2^21 pairs); enqueued on ``stream`` (default: the
+    current stream) without waiting."""
+    if keys.shape != vals.shape or keys.dim() != 1 or not keys.is_cuda or not vals.is_cuda:
+        raise SnnError(SNN_EINVAL, "keys and vals must be 1-D CUDA tensors of equal length")
+    if keys.dtype not in (torch.int32, torch.uint32) or vals.dtype not in (torch.int32, torch.uint32):
+        raise SnnError(SNN_EINVAL, "keys and vals must be 32-bit")
+    if not keys.is_contiguous() or not vals.is_contiguous():
+        raise SnnError(SNN_EINVAL, "keys and vals must be contiguous")
+    device = keys.device.index
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    dev = snn_device(ALLOC_FN(), FREE_FN(), None, ctypes.c_void_p(st.cuda_stream), device)
+    _check(lib().snn_sort_pairs_u32_noalloc(ctypes.byref(dev), ctypes.c_void_p(keys.data_ptr()),
+                                            ctypes.c_void_p(vals.data_ptr()), keys.numel(), begin_bit, end_bit))
 
 
 def normalize_rows(X: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
