@@ -291,6 +291,7 @@ class Index:
         self.dtype = X.dtype
         self.n, self.d = X.shape
         self._alloc = _TorchAllocator(self.device, stream)
+        self._devobj = torch.device("cuda", self.device)
         self._h = ctypes.c_void_p()
         self._nnz_hint = 0
         _check(lib().snn_index(ctypes.byref(self._alloc.dev), ctypes.c_void_p(X.data_ptr()), self.n, self.d,
@@ -322,8 +323,10 @@ class Index:
 
     def _run(self, Q: Optional[torch.Tensor], m: int, R: float, opts: snn_options, nnz_cap: Optional[int],
              want_stats: bool):
-        dev = f"cuda:{self.device}"
-        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
+        dev = self._devobj
+        # the stream context also selects the stream's device; allocations
+        # made under it are tied to that stream by the caching allocator
+        with torch.cuda.stream(self.stream):
             row_ptr = torch.empty(m + 1, dtype=torch.int64, device=dev)
             cap = int(nnz_cap) if nnz_cap is not None else max(self._nnz_hint, 4 * m, 1024)
             for _ in range(3):

@@ -21,7 +21,7 @@
 //   fp16:            a = fp16(s y_q),            b = fp16(s y_j),  s = 2^e
 //                    (v_mfma_f32_32x32x16_f16; the accumulator, C_q and h_j
 //                    are then in units scaled by s^2, which is exact)
-// C_q is chosen (k_mixed_qprep) so that every pair with S(p_j, q) <= fl(R*R)
+// C_q is chosen (k_query_gather, k_mixed_qprep_self) so that every pair with S(p_j, q) <= fl(R*R)
 // passes:
 //   C_q >= R2'/2 - h_q + eta sqrt(R2') + eta^2/2 + e_rep + e_acc + e_h
 //   R2'   = fl(R*R) (1 + 2 gamma64_{d+2})   bounds the exact ||p - q||^2
@@ -107,46 +107,6 @@ constexpr int kWaveStage32 = 1536;
 #define SNN_SCREEN_PREFETCH 2
 #endif
 constexpr int kPrefetch = SNN_SCREEN_PREFETCH;
-
-// Out-of-sample queries: operands and thresholds from the float64 rows.
-__global__ __launch_bounds__(kThreads) void k_mixed_qprep(const double* __restrict__ q64, int64_t m, int d, int dp,
-                                                         const double* __restrict__ mu, int kind, int e, int KA,
-                                                         MixedBound b, uint16_t* __restrict__ qop,
-                                                         float* __restrict__ cthr) {
-  const int terms = kind == kOpBf16x3 ? 3 : 1;
-  // kQLanes lanes per query: they share the coordinates and the operand row
-  constexpr int kQLanes = 16;
-  const int sub = threadIdx.x % kQLanes;
-  for (int64_t s = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kQLanes; s < m;
-       s += ((int64_t)gridDim.x * blockDim.x) / kQLanes) {
-    const double* q = q64 + s * dp;
-    double nn = 0.0;
-    for (int k = sub; k < d; k += kQLanes) {
-      const float y = (float)(q[k] - mu[k]);
-      nn += (double)y * (double)y;
-    }
-    // any summation order stays within the gamma_{d+1} bound the start value allows for
-#pragma unroll
-    for (int off = kQLanes / 2; off > 0; off >>= 1) nn += __shfl_xor(nn, off, kQLanes);
-    // row [bf16(y)], [hi | hi | lo] or [fp16(2^e y)]
-    uint16_t* o = qop + s * KA;
-    for (int k = sub; k < KA; k += kQLanes) {
-      uint16_t v = 0;
-      if (k < terms * d) {
-        const int seg = k / d, cc = k % d;
-        const float y = (float)(q[cc] - mu[cc]);
-        if (kind == kOpF16) {
-          v = f32_to_f16_bits(ldexpf(y, e));
-        } else {
-          const uint16_t hi = f32_to_bf16_rne(y);
-          v = (seg == 2) ? f32_to_bf16_rne(y - bf16_to_f32(hi)) : hi;
-        }
-      }
-      o[k] = v;
-    }
-    if (sub == 0) cthr[s] = screen_threshold(b, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
-  }
-}
 
 // Self-queries: the query rows are the index rows; G lanes read a row
 // together and their partial squared norms meet by shuffles (any order stays
@@ -393,15 +353,21 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
 #pragma unroll
     for (int p = 0; p < PF; ++p) load_step<NL>(Bs[p], hs[p], rc, rh, voff_c, voff_h, p);
     const int last = nsteps - 1;
-    for (int it0 = 0; it0 < last; it0 += PF) {
+    // whole rounds of PF steps (no exit inside a round, which keeps the
+    // compiler's load-count waits at the depth the ring gives), the rest of
+    // the steps before the last, then the last step
+    int it0 = 0;
+    for (; it0 + PF <= last; it0 += PF) {
 #pragma unroll
-      for (int p = 0; p < PF; ++p) {
-        const int it = it0 + p;
-        if (it >= last) break;
-        mixed_step<F16, NS, QB, NL, PF, false>(A, Cin, Bs[p], hs[p], rc, rh, voff_c, voff_h, it, span, l32, (int)j0,
-                                               q0, half, wbuf, wcnt, q.sink);
-      }
+      for (int p = 0; p < PF; ++p)
+        mixed_step<F16, NS, QB, NL, PF, false>(A, Cin, Bs[p], hs[p], rc, rh, voff_c, voff_h, it0 + p, span, l32,
+                                               (int)j0, q0, half, wbuf, wcnt, q.sink);
     }
+#pragma unroll
+    for (int p = 0; p < PF - 1; ++p)
+      if (it0 + p < last)
+        mixed_step<F16, NS, QB, NL, PF, false>(A, Cin, Bs[p], hs[p], rc, rh, voff_c, voff_h, it0 + p, span, l32,
+                                               (int)j0, q0, half, wbuf, wcnt, q.sink);
 #pragma unroll
     for (int p = 0; p < PF; ++p)
       if (last % PF == p)
@@ -420,7 +386,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
 // epilogue is amortised over 32 x 32 blocks.  K = 2 NK coordinates (zero padded).
 // Candidate operands: blocks of 32 rows, NK slices of two coordinates, a
 // slice being 64 floats [k][row], so lane l = 32 k + row reads float l.  The
-// query rows are [y, C_q, 0 ...] of stride DV (k_mfma32_qprep).
+// query rows are [y, C_q, 0 ...] of stride DV (k_query_gather, k_mfma32_qprep_self).
 // Query operands of one wavefront for the fp32 screen: QB blocks of 32 rows,
 // lane l holding coordinate 2 s + l / 32 of row l % 32 in slice s, and the
 // start values C_q in accumulator order; rows past m are zero / -inf.
@@ -532,24 +498,9 @@ __global__ __launch_bounds__(kThreads) void k_mfma32_operands(const float* __res
   }
 }
 
-// Query rows of the fp32 screen: [y_0 .. y_{d-1}, C_q, 0 ...] with stride
-// pad4(d + 1); C_q is the rigorous start value for the fp32 product chain.
-__global__ __launch_bounds__(kThreads) void k_mfma32_qprep(const double* __restrict__ q64, int64_t m, int d, int dp,
-                                                          const double* __restrict__ mu, int DV, MixedBound b,
-                                                          float* __restrict__ vq) {
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x) {
-    float* o = vq + s * DV;
-    double nn = 0.0;
-    for (int k = 0; k < d; ++k) {
-      const float y = (float)(q64[s * dp + k] - mu[k]);
-      nn += (double)y * (double)y;
-      o[k] = y;
-    }
-    for (int k = d + 1; k < DV; ++k) o[k] = 0.f;
-    o[d] = screen_threshold(b, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
-  }
-}
-
+// Query rows of the fp32 screen for a self-query: [y_0 .. y_{d-1}, C_q, 0 ...]
+// with stride pad4(d + 1); C_q is the rigorous start value for the fp32
+// product chain (out-of-sample queries get theirs in k_query_gather).
 __global__ __launch_bounds__(kThreads) void k_mfma32_qprep_self(const float* __restrict__ ys, int64_t n, int d, int DV,
                                                                MixedBound b, float* __restrict__ vq) {
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (int64_t)gridDim.x * blockDim.x) {
@@ -703,13 +654,6 @@ int mixed_blocks_per_cu(int KA, int KB, bool f16) {
   return nb;
 }
 
-void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, int kind, int e, int KA,
-                        const MixedBound& b, uint16_t* qop, float* cthr, hipStream_t s) {
-  if (m <= 0) return;
-  k_mixed_qprep<<<grid_for(m * 16, 8192), kThreads, 0, s>>>(q64, m, d, dp, mu, kind, e, KA, b, qop, cthr);
-  SNN_LAUNCH_CHECK();
-}
-
 void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* cthr, hipStream_t s) {
   if (d <= 8)
     k_mixed_qprep_self<1><<<grid_for(n, 8192), kThreads, 0, s>>>(ys, n, d, b, cthr);
@@ -736,13 +680,6 @@ int mfma32_blocks_per_cu(int d) {
 void launch_mfma32_operands(const float* ys, int64_t n, int d, float* cop, hipStream_t s) {
   const int64_t npad = ((n + 32 + 31) / 32) * 32;
   k_mfma32_operands<<<grid_for(npad * 2 * ((d + 1) / 2), 16384), kThreads, 0, s>>>(ys, n, npad, d, (d + 1) / 2, cop);
-  SNN_LAUNCH_CHECK();
-}
-
-void launch_mfma32_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, const MixedBound& b, float* vq,
-                         hipStream_t s) {
-  if (m <= 0) return;
-  k_mfma32_qprep<<<grid_for(m, 8192), kThreads, 0, s>>>(q64, m, d, dp, mu, mfma32_query_floats(d), b, vq);
   SNN_LAUNCH_CHECK();
 }
 

@@ -415,6 +415,52 @@ __global__ __launch_bounds__(kThreads) void k_perm_counts(const int64_t* __restr
   }
 }
 
+// k_perm_counts_stats and k_row_classify in one pass: a block owns a
+// contiguous range of rows (about 1024), counts its rows per class in LDS and
+// reserves each class's list space with one global atomic.
+__global__ __launch_bounds__(kThreads) void k_rows_stats(const int64_t* __restrict__ src_rp, int64_t m,
+                                                        const int32_t* __restrict__ map, int32_t* __restrict__ cnt_dst,
+                                                        unsigned long long* __restrict__ row_max,
+                                                        unsigned long long* __restrict__ total,
+                                                        int32_t* __restrict__ lists,
+                                                        unsigned long long* __restrict__ counts) {
+  __shared__ int cnt[kRowClasses];
+  __shared__ unsigned long long base[kRowClasses];
+  __shared__ int red[kThreads / kWave];
+  const int t = threadIdx.x;
+  const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(m, r0 + per);
+  if (t < kRowClasses) cnt[t] = 0;
+  __syncthreads();
+  int v = 0;
+  for (int64_t r = r0 + t; r < r1; r += kThreads) {
+    const int len = (int)(src_rp[r + 1] - src_rp[r]);
+    const int d = map[r];
+    if (d >= 0) cnt_dst[d] = len;
+    v = max(v, len);
+    const int c = row_class(src_rp, r);
+    if (c >= 0) atomicAdd(&cnt[c], 1);
+  }
+  v = wave_max(v);
+  if (lane_id() == 0) red[t / kWave] = v;
+  __syncthreads();
+  if (t < kRowClasses) {
+    base[t] = cnt[t] ? atomicAdd(&counts[t], (unsigned long long)cnt[t]) : 0ull;
+    cnt[t] = 0;
+  }
+  if (t == 0) {
+    for (int w = 1; w < kThreads / kWave; ++w) v = max(v, red[w]);
+    if (v > 0 && (unsigned long long)v > __hip_atomic_load(row_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(row_max, (unsigned long long)v);
+    if (blockIdx.x == 0) *total = (unsigned long long)src_rp[m];
+  }
+  __syncthreads();
+  for (int64_t r = r0 + t; r < r1; r += kThreads) {
+    const int c = row_class(src_rp, r);
+    if (c >= 0) lists[(int64_t)c * m + (int64_t)base[c] + atomicAdd(&cnt[c], 1)] = (int32_t)r;
+  }
+}
+
 // k_perm_counts plus the longest row and (block 0, thread 0) the total.
 __global__ __launch_bounds__(kThreads) void k_perm_counts_stats(const int64_t* __restrict__ src_rp, int64_t m,
                                                                const int32_t* __restrict__ map,
@@ -557,6 +603,19 @@ void launch_row_sort_move(const RowMove& mv, int64_t m, int64_t max_len, int32_t
 void launch_perm_counts(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst, hipStream_t s) {
   if (m <= 0) return;
   k_perm_counts<<<grid_for(m, 4096), kThreads, 0, s>>>(src_rp, m, map, cnt_dst);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_rows_stats(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst,
+                       unsigned long long* row_max, unsigned long long* total, int32_t* lists,
+                       unsigned long long* list_counts, hipStream_t s) {
+  const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (m + 1023) / 1024));
+  k_rows_stats<<<blocks, kThreads, 0, s>>>(src_rp, m, map, cnt_dst, row_max, total, lists, list_counts);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_row_sort_short(const RowMove& mv, int32_t* lists, unsigned long long* list_counts, hipStream_t s) {
+  k_row_sort_seg<16><<<2048, kThreads, 0, s>>>(mv, lists, list_counts);
   SNN_LAUNCH_CHECK();
 }
 

@@ -1221,6 +1221,7 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   ix.key_eps = 1.01 * (u32 + g64) * (1.0 + u32) * ix.max_norm * ix.vnorm;
   for (auto& mo : ix.mixed) mo.built = false;
   ix.vcand_built = false;
+  ix.wcells_built = false;
 }
 
 void insert_points(Index& ix, const void* X, int64_t k) {

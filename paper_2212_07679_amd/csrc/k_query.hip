@@ -3,16 +3,19 @@
 //  k_query_keys    x_q = q - mu, alpha_q = x_q . v (float64), ||fl32(x_q)||,
 //                  and a bucket of alpha_q on a uniform grid over the range of
 //                  the index scores; each query takes a slot in its bucket
-//  (scan)          bucket offsets
+//  k_scan_buckets  bucket offsets (one workgroup)
 //  k_query_gather  query rows in float64, in bucket (score) order, so that a
 //                  tile of consecutive queries shares one union window (the
-//                  gemm over the union of candidate sets, Section 4).  Any
-//                  query order gives the same result; score order only keeps
-//                  the union windows tight.
+//                  gemm over the union of candidate sets, Section 4), and the
+//                  screen's query operands and start values.  Any query
+//                  order gives the same result; score order only keeps the
+//                  union windows tight.
 //  k_window        J_q = [lo_q, hi_q) by binary search on the sorted keys,
 //                  with the half-width widened outward by a rigorous bound on
 //                  the score rounding (eq. (lower) is exact only for exact
-//                  scores); per-tile union windows
+//                  scores), each search confined to one cell of a uniform
+//                  grid over the score range (k_window_table); per-tile
+//                  union windows
 //  k_tile_plan     work units per tile and their offsets (one workgroup)
 #include <hip/hip_runtime.h>
 
@@ -27,6 +30,39 @@ namespace snn {
 
 namespace {
 constexpr int kThreads = 256;
+}
+
+// Exclusive scan of nb <= kBucketsMax bucket counts by one workgroup of
+// kThreads threads: staged in LDS with coalesced loads, each thread scans a
+// run of consecutive entries, the run totals are scanned across the
+// workgroup and the offsets written back.
+constexpr int kBucketsMax = 4096;
+constexpr int kBucketRun = kBucketsMax / kThreads;
+__device__ void scan_buckets_block(uint32_t* __restrict__ hist, int nb, uint32_t* buf, uint32_t* part) {
+  const int t = threadIdx.x;
+  for (int i = t; i < kBucketsMax; i += kThreads)
+    buf[i] = i < nb ? hist[i] : 0u;
+  __syncthreads();
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kBucketRun; ++k) sum += buf[t * kBucketRun + k];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {  // inclusive scan of the run totals
+    const uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+#pragma unroll
+  for (int k = 0; k < kBucketRun; ++k) {
+    const uint32_t x = buf[t * kBucketRun + k];
+    buf[t * kBucketRun + k] = run;
+    run += x;
+  }
+  __syncthreads();
+  for (int i = t; i < nb; i += kThreads) hist[i] = buf[i];
 }
 
 // G lanes per query row (coalesced row reads); the row's partial sums meet
@@ -72,8 +108,20 @@ __global__ __launch_bounds__(kThreads) void k_query_keys(const T* __restrict__ Q
   if (badloc) atomicOr(bad, 1);
 }
 
+// The bucket counts into bucket offsets, one workgroup (a ticket per
+// workgroup of the key pass instead, for the last one to scan, serialises
+// thousands of atomics on one address: measured 150 us against 11 us).
+__global__ __launch_bounds__(kThreads) void k_scan_buckets(uint32_t* __restrict__ hist, int nb) {
+  __shared__ uint32_t buf[kBucketsMax];
+  __shared__ uint32_t part[kThreads];
+  scan_buckets_block(hist, nb, buf, part);
+}
+
 // G lanes per query row: the row's destination slot is read once per group,
-// its elements are copied G at a time.
+// its elements are copied G at a time, and the lanes build the screen's
+// operand row and start value from the centred row y = fl32(q - mu)
+// (k_cand_mfma.hip): 16-bit rows [bf16(y)], [hi | hi | lo] or [fp16(2^e y)]
+// with C_q, or the fp32 row [y, C_q, 0 ...].
 template <typename T, int G>
 __global__ __launch_bounds__(kThreads) void k_query_gather(const T* __restrict__ Q, int64_t m, int d, int dp,
                                                           const uint32_t* __restrict__ bucket,
@@ -82,17 +130,75 @@ __global__ __launch_bounds__(kThreads) void k_query_gather(const T* __restrict__
                                                           const double* __restrict__ qalpha_in,
                                                           const double* __restrict__ qnorm_in,
                                                           double* __restrict__ q64, int32_t* __restrict__ qorig,
-                                                          double* __restrict__ qalpha, double* __restrict__ qnorm) {
+                                                          double* __restrict__ qalpha, double* __restrict__ qnorm,
+                                                          const double* __restrict__ mu, QueryOperands op) {
   const int sub = threadIdx.x % G;
+  const int terms = op.kind == kOpBf16x3 ? 3 : 1;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; i < m;
        i += ((int64_t)gridDim.x * blockDim.x) / G) {
     const int64_t s = (int64_t)boff[bucket[i]] + slot[i];
-    for (int k = sub; k < dp; k += G) q64[s * dp + k] = k < d ? (double)Q[i * d + k] : 0.0;
+    const T* q = Q + i * d;
+    for (int k = sub; k < dp; k += G) q64[s * dp + k] = k < d ? (double)q[k] : 0.0;
     if (sub == 0) {
       qorig[s] = (int32_t)i;
       qalpha[s] = qalpha_in[i];
       qnorm[s] = qnorm_in[i];
     }
+    if (op.mode == kQOpNone) continue;
+    double nn = 0.0;
+    for (int k = sub; k < d; k += G) {
+      const float y = (float)((double)q[k] - mu[k]);
+      nn += (double)y * (double)y;
+    }
+    // any summation order stays within the gamma_{d+1} bound the start value allows for
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) nn += __shfl_xor(nn, off, G);
+    const float c = screen_threshold(op.b, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
+    if (op.mode == kQOp16) {
+      uint16_t* o = op.qop + s * op.KA;
+      for (int k = sub; k < op.KA; k += G) {
+        uint16_t v = 0;
+        if (k < terms * d) {
+          const int seg = k / d, cc = k % d;
+          const float y = (float)((double)q[cc] - mu[cc]);
+          if (op.kind == kOpF16) {
+            v = __builtin_bit_cast(uint16_t, (_Float16)ldexpf(y, op.e));
+          } else {
+            const uint16_t hi = f32_to_bf16_rne(y);
+            v = (seg == 2) ? f32_to_bf16_rne(y - bf16_to_f32(hi)) : hi;
+          }
+        }
+        o[k] = v;
+      }
+      if (sub == 0) op.cthr[s] = c;
+    } else {
+      float* o = op.vq + s * op.DV;
+      for (int k = sub; k < op.DV; k += G) o[k] = k < d ? (float)((double)q[k] - mu[k]) : (k == d ? c : 0.f);
+    }
+  }
+}
+
+// Start of every cell of a uniform grid over the score range: start[c] is
+// the first sorted position whose key lies in cell c or beyond (start[C] =
+// n).  The cell of a score x is floor((x - key[0]) * C / (key[n-1] -
+// key[0])) clamped to [0, C - 1], monotone in x, so every key below a score
+// x's cell is below x and every key beyond it above: a search for x stays
+// within [start[cell(x)], start[cell(x) + 1]].
+__device__ __forceinline__ int score_cell(double x, double amin, double scale, int C) {
+  const double t = (x - amin) * scale;
+  return t >= 0.0 ? (t < (double)C ? (int)t : C - 1) : 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_window_table(const double* __restrict__ key, int n, int C,
+                                                          int32_t* __restrict__ start) {
+  const double amin = key[0], amax = key[n - 1];
+  const double scale = amax > amin ? (double)C / (amax - amin) : 0.0;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const int cj = score_cell(key[j], amin, scale, C);
+    const int cp = j > 0 ? score_cell(key[j - 1], amin, scale, C) : -1;
+    for (int c = cp + 1; c <= cj; ++c) start[c] = j;
+    if (j == n - 1)
+      for (int c = cj + 1; c <= C; ++c) start[c] = n;
   }
 }
 
@@ -101,6 +207,7 @@ __global__ __launch_bounds__(kThreads) void k_query_gather(const T* __restrict__
 // lower and upper binary searches run interleaved (independent loads).
 // Requires T % 64 == 0 so that a wavefront never straddles two tiles.
 __global__ __launch_bounds__(kThreads) void k_window(const double* __restrict__ key, int n,
+                                                    const int32_t* __restrict__ cells, int C,
                                                     const double* __restrict__ qalpha,
                                                     const double* __restrict__ qnorm, int64_t m, double w_base,
                                                     double eps_scale, int T, int sym, int32_t* __restrict__ lo_out,
@@ -108,6 +215,8 @@ __global__ __launch_bounds__(kThreads) void k_window(const double* __restrict__ 
                                                     int32_t* __restrict__ thi,
                                                     unsigned long long* __restrict__ wpart) {
   const double u = 1.1102230246251565e-16;
+  const double amin = key[0], amax = key[n - 1];
+  const double scale = amax > amin ? (double)C / (amax - amin) : 0.0;
   __shared__ unsigned long long red[kThreads / kWave];
   unsigned long long acc = 0;  // this lane's window sizes over the grid-stride loop
   for (int64_t s0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x / kWave) * kWave; s0 < m;
@@ -119,8 +228,10 @@ __global__ __launch_bounds__(kThreads) void k_window(const double* __restrict__ 
       const double a = qalpha[s];
       const double lv = nextafter(a - W, -INFINITY);
       const double hv = nextafter(a + W, INFINITY);
-      // lo: first index with key >= lv;  hi: first index with key > hv
-      int l0 = 0, l1 = n, h0 = 0, h1 = n;
+      // lo: first index with key >= lv;  hi: first index with key > hv,
+      // each within the grid cell of its bound
+      const int cl = score_cell(lv, amin, scale, C), ch = score_cell(hv, amin, scale, C);
+      int l0 = cells[cl], l1 = cells[cl + 1], h0 = cells[ch], h1 = cells[ch + 1];
       while (l0 < l1 || h0 < h1) {
         const int lm = (l0 + l1) >> 1, hm = (h0 + h1) >> 1;
         const double kl = key[min(lm, n - 1)], kh = key[min(hm, n - 1)];
@@ -303,9 +414,12 @@ int grid_for(int64_t work, int cap) {
 }
 }  // namespace
 
+// about one bucket per 8 queries, at most 4096 (one workgroup scans them);
+// queries sharing a bucket lie within 1/4096 of the score range, far inside
+// one tile's union window
 int query_buckets(int64_t m) {
   int K = 256;
-  while (K < 65536 && K < m) K <<= 1;
+  while (K < kBucketsMax && 8 * (int64_t)K < m) K <<= 1;
   return K;
 }
 
@@ -342,37 +456,48 @@ void launch_query_keys(snn_dtype dt, const void* Q, int64_t m, int d, const doub
   else
     query_keys_d<double>((const double*)Q, m, d, mu, v, key, n, K, bucket, slot, hist, qalpha, qnorm, bad, s);
   SNN_LAUNCH_CHECK();
+  k_scan_buckets<<<1, kThreads, 0, s>>>(hist, K);
+  SNN_LAUNCH_CHECK();
 }
 
 namespace {
 template <typename T>
 void query_gather_d(const T* Q, int64_t m, int d, int dp, const uint32_t* bucket, const uint32_t* slot,
                     const uint32_t* boff, const double* qalpha_in, const double* qnorm_in, double* q64, int32_t* qorig,
-                    double* qalpha, double* qnorm, hipStream_t s) {
-  const int G = query_row_lanes(dp);
+                    double* qalpha, double* qnorm, const double* mu, const QueryOperands& op, hipStream_t s) {
+  const int width = std::max(dp, op.mode == kQOp16 ? op.KA : (op.mode == kQOp32 ? op.DV : 0));
+  const int G = query_row_lanes(width);
   const int g = grid_for(m * G, 8192);
   if (G == 4)
     k_query_gather<T, 4><<<g, kThreads, 0, s>>>(Q, m, d, dp, bucket, slot, boff, qalpha_in, qnorm_in, q64, qorig,
-                                                qalpha, qnorm);
+                                                qalpha, qnorm, mu, op);
   else if (G == 8)
     k_query_gather<T, 8><<<g, kThreads, 0, s>>>(Q, m, d, dp, bucket, slot, boff, qalpha_in, qnorm_in, q64, qorig,
-                                                qalpha, qnorm);
+                                                qalpha, qnorm, mu, op);
   else
     k_query_gather<T, 16><<<g, kThreads, 0, s>>>(Q, m, d, dp, bucket, slot, boff, qalpha_in, qnorm_in, q64, qorig,
-                                                 qalpha, qnorm);
+                                                 qalpha, qnorm, mu, op);
 }
 
 }  // namespace
 
 void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, const uint32_t* bucket,
                          const uint32_t* slot, const uint32_t* boff, const double* qalpha_in, const double* qnorm_in,
-                         double* q64, int32_t* qorig, double* qalpha, double* qnorm, hipStream_t s) {
+                         double* q64, int32_t* qorig, double* qalpha, double* qnorm, const double* mu,
+                         const QueryOperands& op, hipStream_t s) {
   if (dt == SNN_F32)
     query_gather_d<float>((const float*)Q, m, d, dp, bucket, slot, boff, qalpha_in, qnorm_in, q64, qorig, qalpha,
-                          qnorm, s);
+                          qnorm, mu, op, s);
   else
     query_gather_d<double>((const double*)Q, m, d, dp, bucket, slot, boff, qalpha_in, qnorm_in, q64, qorig, qalpha,
-                           qnorm, s);
+                           qnorm, mu, op, s);
+  SNN_LAUNCH_CHECK();
+}
+
+int window_table_cells(int64_t n) { return (int)std::max<int64_t>(1, n / 8); }
+
+void launch_window_table(const double* key, int n, int C, int32_t* start, hipStream_t s) {
+  k_window_table<<<grid_for(n, 8192), kThreads, 0, s>>>(key, n, C, start);
   SNN_LAUNCH_CHECK();
 }
 
@@ -385,12 +510,12 @@ void launch_query_init(unsigned long long* ctl, int ctl_words, int32_t* row_cnt,
 
 int window_blocks(int64_t m) { return m > 0 ? grid_for(m, kWindowMaxBlocks) : 0; }
 
-void launch_windows(const double* key, int n, const double* qalpha, const double* qnorm, int64_t m, double w_base,
-                    double eps_scale, int T, int sym, int32_t* lo, int32_t* hi, int32_t* tlo, int32_t* thi,
-                    unsigned long long* wpart, hipStream_t s) {
+void launch_windows(const double* key, int n, const int32_t* cells, int C, const double* qalpha,
+                    const double* qnorm, int64_t m, double w_base, double eps_scale, int T, int sym, int32_t* lo,
+                    int32_t* hi, int32_t* tlo, int32_t* thi, unsigned long long* wpart, hipStream_t s) {
   if (m <= 0) return;
-  k_window<<<window_blocks(m), kThreads, 0, s>>>(key, n, qalpha, qnorm, m, w_base, eps_scale, T, sym, lo, hi, tlo,
-                                                 thi, wpart);
+  k_window<<<window_blocks(m), kThreads, 0, s>>>(key, n, cells, C, qalpha, qnorm, m, w_base, eps_scale, T, sym, lo,
+                                                 hi, tlo, thi, wpart);
   SNN_LAUNCH_CHECK();
 }
 

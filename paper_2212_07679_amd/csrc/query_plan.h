@@ -114,12 +114,21 @@ __device__ __forceinline__ bool decode_unit(const QueryDev& q, int64_t u, int& t
 
 // ---------------------------------------------------------------- launchers
 int query_buckets(int64_t m);
+// keys, buckets and slots of the queries, then hist (K <= 4096 counts, zero
+// beforehand) turned into bucket offsets
 void launch_query_keys(snn_dtype dt, const void* Q, int64_t m, int d, const double* mu, const double* v,
                        const double* key, int n, int K, uint32_t* bucket, uint32_t* slot, uint32_t* hist,
                        double* qalpha, double* qnorm, int* bad, hipStream_t s);
+struct QueryOperands;
+// queries into score order (bucket offsets boff), with the screen's query
+// operands and start values (op.mode: none, 16-bit rows + C_q, fp32 rows)
 void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, const uint32_t* bucket,
                          const uint32_t* slot, const uint32_t* boff, const double* qalpha_in, const double* qnorm_in,
-                         double* q64, int32_t* qorig, double* qalpha, double* qnorm, hipStream_t s);
+                         double* q64, int32_t* qorig, double* qalpha, double* qnorm, const double* mu,
+                         const QueryOperands& op, hipStream_t s);
+// start of every cell of a uniform grid over the sorted scores (cells + 1 entries)
+int window_table_cells(int64_t n);
+void launch_window_table(const double* key, int n, int C, int32_t* start, hipStream_t s);
 // align: tile windows are widened outward to multiples of `align` rows (the
 // mixed screen reads 32-row blocks); extra candidates never change results.
 // sym: symmetric self-query (counts only candidates j >= s, tiles start at
@@ -128,9 +137,9 @@ void launch_query_gather(snn_dtype dt, const void* Q, int64_t m, int d, int dp, 
 // most kWindowMaxBlocks of them: window_blocks(m)); k_tile_plan sums them
 constexpr int kWindowMaxBlocks = 2048;
 int window_blocks(int64_t m);
-void launch_windows(const double* key, int n, const double* qalpha, const double* qnorm, int64_t m, double w_base,
-                    double eps_scale, int T, int sym, int32_t* lo, int32_t* hi, int32_t* tlo, int32_t* thi,
-                    unsigned long long* wpart, hipStream_t s);
+void launch_windows(const double* key, int n, const int32_t* cells, int C, const double* qalpha,
+                    const double* qnorm, int64_t m, double w_base, double eps_scale, int T, int sym, int32_t* lo,
+                    int32_t* hi, int32_t* tlo, int32_t* thi, unsigned long long* wpart, hipStream_t s);
 // one launch: zero ctl_words control words, row_cnt (m) and hist (nb, may be
 // NULL), and empty tile windows (tlo = INT_MAX, thi = INT_MIN)
 void launch_query_init(unsigned long long* ctl, int ctl_words, int32_t* row_cnt, int64_t m, uint32_t* hist, int nb,
@@ -266,13 +275,25 @@ __device__ __forceinline__ float screen_threshold(const MixedBound& b, double hq
   const double e_acc = b.g_acc * (1.02 * b.Y * nq + e_sub + fabs(c0)) * 1.01;
   return round_up_f32((c0 + e_acc) * b.scale2);
 }
+// Query operands built while the queries are gathered into score order.
+enum { kQOpNone = 0, kQOp16 = 1, kQOp32 = 2 };
+struct QueryOperands {
+  int mode = kQOpNone;
+  int kind = kOpBf16;  // 16-bit rows: OperandKind
+  int e = 0;           // fp16 scale exponent
+  int KA = 0;          // 16-bit row length
+  int DV = 0;          // fp32 row stride
+  MixedBound b{};
+  uint16_t* qop = nullptr;
+  float* cthr = nullptr;
+  float* vq = nullptr;
+};
+
 int mixed_max_slices();
 int mixed_queries_per_wave(int KA);  // 32 x query blocks per wavefront
 int mixed_blocks_per_cu(int KA, int KB, bool f16);
 // operand row length (16-bit values) of an OperandKind at dimension d
 int operand_ka(int kind, int d);
-void launch_mixed_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, int kind, int e, int KA,
-                        const MixedBound& b, uint16_t* qop, float* cthr, hipStream_t s);
 void launch_mixed_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* cthr, hipStream_t s);
 void launch_cand_mfma(const QueryDev& q, const MixedDev& x, int grid, hipStream_t s);
 
@@ -290,8 +311,6 @@ int mfma32_queries_per_tile();
 int64_t mfma32_operand_floats(int64_t n, int d);
 int mfma32_blocks_per_cu(int d);
 void launch_mfma32_operands(const float* ys, int64_t n, int d, float* cop, hipStream_t s);
-void launch_mfma32_qprep(const double* q64, int64_t m, int d, int dp, const double* mu, const MixedBound& b, float* vq,
-                         hipStream_t s);
 void launch_mfma32_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* vq, hipStream_t s);
 void launch_cand_mfma32(const QueryDev& q, const Mfma32Dev& x, int grid, hipStream_t s);
 
@@ -372,6 +391,13 @@ void launch_perm_counts(const int64_t* src_rp, int64_t m, const int32_t* map, in
 // *total = src_rp[m]
 void launch_perm_counts_stats(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst,
                               unsigned long long* row_max, unsigned long long* total, hipStream_t s);
+// the same pass also appending every row to the list of its length class
+// (lists / list_counts as for launch_row_sort_head, counts zero beforehand)
+void launch_rows_stats(const int64_t* src_rp, int64_t m, const int32_t* map, int32_t* cnt_dst,
+                       unsigned long long* row_max, unsigned long long* total, int32_t* lists,
+                       unsigned long long* list_counts, hipStream_t s);
+// rows of at most 16 entries of classified lists, moved sorted
+void launch_row_sort_short(const RowMove& mv, int32_t* lists, unsigned long long* list_counts, hipStream_t s);
 void launch_fill_u64(unsigned long long* p, int64_t n, unsigned long long v, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 

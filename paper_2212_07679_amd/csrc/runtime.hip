@@ -221,9 +221,23 @@ static ScreenPlan plan_screen(const Index& ix, const snn_options& o, double R2) 
   return ScreenPlan{SNN_PREC_FP64, kOpBf16};
 }
 
-// Operands and start values of a 16-bit screen for one query call.
-static MixedDev prepare_mixed(Index& ix, int kind, double R2, bool self, const double* q64, int64_t m,
-                              uint16_t* qop, float* cthr, hipStream_t s) {
+// The grid over the sorted scores that confines the window searches,
+// built once per set of rows.
+static const int32_t* window_cells(Index& ix) {
+  if (!ix.wcells_built) {
+    ix.wcells_n = window_table_cells(ix.n);
+    ix.wcells.ensure(ix.arena, sizeof(int32_t) * (ix.wcells_n + 1) + 256);
+    launch_window_table(ix.key.as<double>(), (int)ix.n, ix.wcells_n, ix.wcells.as<int32_t>(), ix.arena.stream());
+    ix.wcells_built = true;
+  }
+  return ix.wcells.as<int32_t>();
+}
+
+// Operands and start values of a 16-bit screen for one query call: for a
+// self-query the start values now, for out-of-sample queries the request in
+// *op that the gather into score order carries out.
+static MixedDev prepare_mixed(Index& ix, int kind, double R2, bool self, int64_t m, uint16_t* qop, float* cthr,
+                              QueryOperands* op, hipStream_t s) {
   MixedOperands& mo = ix.mixed[mixed_slot(kind)];
   const MixedBound mb = mixed_bound(kind, mo.ka, ix.d, R2, ix.max_norm);
   MixedDev mx{};
@@ -238,19 +252,32 @@ static MixedDev prepare_mixed(Index& ix, int kind, double R2, bool self, const d
     launch_mixed_qprep_self(ix.ys.as<float>(), ix.n, ix.d, mb, cthr, s);
   } else {
     mx.qop = qop;
-    launch_mixed_qprep(q64, m, ix.d, ix.dp, ix.mu.as<double>(), kind, mo.e, mo.ka, mb, qop, cthr, s);
+    op->mode = kQOp16;
+    op->kind = kind;
+    op->e = mo.e;
+    op->KA = mo.ka;
+    op->b = mb;
+    op->qop = qop;
+    op->cthr = cthr;
   }
+  (void)m;
   return mx;
 }
 
-// Query rows and start values of the fp32 screen for one query call.
-static void prepare_fp32(Index& ix, double R2, bool self, const double* q64, int64_t m, float* vq, hipStream_t s) {
+// Query rows and start values of the fp32 screen for one query call (as
+// prepare_mixed: now for a self-query, through *op otherwise).
+static void prepare_fp32(Index& ix, double R2, bool self, int64_t m, float* vq, QueryOperands* op, hipStream_t s) {
   // K = d rounded up to the two coordinates of one fp32 matrix instruction
   const MixedBound vb = mixed_bound(kOpF32, 2 * ((ix.d + 1) / 2), ix.d, R2, ix.max_norm);
-  if (self)
+  if (self) {
     launch_mfma32_qprep_self(ix.ys.as<float>(), ix.n, ix.d, vb, vq, s);
-  else
-    launch_mfma32_qprep(q64, m, ix.d, ix.dp, ix.mu.as<double>(), vb, vq, s);
+  } else {
+    op->mode = kQOp32;
+    op->DV = mfma32_query_floats(ix.d);
+    op->b = vb;
+    op->vq = vq;
+  }
+  (void)m;
 }
 
 // Clustering request: the self-query's accepted pairs go to DBSCAN instead
@@ -333,9 +360,11 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   if (prec == SNN_PREC_FP32) build_fp32_operands(ix);
   const int ntiles = (int)std::max<int64_t>(1, (m + T - 1) / T);
 
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // stats: call start, screen start / end, call end (events kept on the index)
+  hipEvent_t* ev = ix.ev;
   if (st) {
-    for (auto& e : ev) SNN_HIP(hipEventCreate(&e));
+    for (int i = 0; i < 4; ++i)
+      if (!ev[i]) SNN_HIP(hipEventCreate(&ev[i]));
     SNN_HIP(hipEventRecord(ev[0], s));
   }
 
@@ -410,6 +439,13 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   launch_query_init(reinterpret_cast<unsigned long long*>(P.ctl), (int)(sizeof(Ctl) / 8), P.row_cnt, m,
                     sort_queries ? P.hist : nullptr, nbuckets, P.tlo, P.thi, ntiles, s);
 
+  // screen operands and start values: built by the gather for out-of-sample
+  // queries, by their own pass for self-queries
+  QueryOperands qop{};
+  MixedDev mx{};
+  if (mix16) mx = prepare_mixed(ix, sp.kind, R2, self, m, P.qop, P.cthr, &qop, s);
+  if (prec == SNN_PREC_FP32) prepare_fp32(ix, R2, self, m, P.vq, &qop, s);
+
   const double* q64;
   const int32_t* qorig;
   const double* qa;
@@ -419,9 +455,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       // queries into score order by a counting sort on a uniform score grid
       launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), ix.key.as<double>(), (int)n,
                         nbuckets, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, &P.ctl->bad, s);
-      exclusive_scan_u32(P.hist, nbuckets, P.scan_scratch, s);
       launch_query_gather(ix.dtype, Q, m, d, ix.dp, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, P.q64, P.qorig, P.qa,
-                          P.qn, s);
+                          P.qn, ix.mu.as<double>(), qop, s);
     }
     q64 = P.q64;
     qorig = P.qorig;
@@ -441,8 +476,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const double eps_scale = 1.01 * (u32 + gamma64(d + 2)) * (1.0 + u32) * ix.vnorm;
   // self-queries scan each unordered pair once (S is exactly symmetric)
   const int sym = (self && !o.full_self_scan) ? 1 : 0;
-  launch_windows(ix.key.as<double>(), (int)n, qa, qn, m, w_base, eps_scale, T, sym, P.lo, P.hi, P.tlo, P.thi,
-                 P.wpart, s);
+  const int32_t* cells = window_cells(ix);
+  launch_windows(ix.key.as<double>(), (int)n, cells, ix.wcells_n, qa, qn, m, w_base, eps_scale, T, sym, P.lo, P.hi,
+                 P.tlo, P.thi, P.wpart, s);
   // query slots per wavefront (stats): the matrix-core screens evaluate
   // whole 32-query blocks, the float64 screen one query at a time
   const int qpw = mix16                   ? mixed_queries_per_wave(operand_ka(sp.kind, d))
@@ -479,9 +515,6 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   qd.nxcd = di.xcds;
   qd.sym = sym;
 
-  MixedDev mx{};
-  if (mix16) mx = prepare_mixed(ix, sp.kind, R2, self, q64, m, P.qop, P.cthr, s);
-  if (prec == SNN_PREC_FP32) prepare_fp32(ix, R2, self, q64, m, P.vq, s);
 
   // survivors: capacity remembered on the index, grown on overflow
   // bytes per survivor: the pair, and per result row, column, distance, slot
@@ -514,6 +547,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       launch_fill_u64(P.ctl->counters, kMaxXcd, 0ull, s);
       launch_fill_u64(&P.ctl->survivors, 1, 0ull, s);
       launch_fill_u64(&P.ctl->accepted, 1, 0ull, s);
+      launch_fill_u64(P.ctl->list_counts, 8, 0ull, s);
       launch_fill_i32(P.row_cnt, m, 0, s);
     }
     const int per_cu = mix16                   ? mixed_blocks_per_cu(mx.KA, mx.KB, mx.f16 != 0)
@@ -553,12 +587,17 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       ix.ws[1].reset(ix.arena);
       continue;
     }
-    launch_recheck(qd, sv, ix.dtype, ix.po.ptr, self, P.row_cnt, di.cus * 16, s);
+    // grid of the survivor passes from the list's capacity (a grid-stride
+    // loop: few workgroups for the short lists of sparse outputs, where the
+    // dispatch of thousands of idle ones would dominate)
+    const int sgrid = (int)std::min<long long>(16LL * di.cus, std::max<long long>(2LL * di.cus, cap / 2048));
+    launch_recheck(qd, sv, ix.dtype, ix.po.ptr, self, P.row_cnt, sgrid, s);
     // row offsets in slot order (where the neighbours are assembled) and in
     // the caller's order (where each row ends up)
     exclusive_scan_i32_to_i64(P.row_cnt, P.rp_s, m, P.scan_scratch, s);
-    // counts in the caller's order, the longest row and the total in one pass
-    launch_perm_counts_stats(P.rp_s, m, qorig, P.cnt_o, &P.ctl->row_max, &P.ctl->nnz, s);
+    // counts in the caller's order, the longest row, the total and the rows
+    // by length class in one pass
+    launch_rows_stats(P.rp_s, m, qorig, P.cnt_o, &P.ctl->row_max, &P.ctl->nnz, P.lists, P.ctl->list_counts, s);
     exclusive_scan_i32_to_i64(P.cnt_o, out->row_ptr, m, P.scan_scratch, s);
     // The assembly of rows of up to 16 neighbours is enqueued before the
     // sizes are read back, so the device does not wait for the host in
@@ -572,11 +611,13 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       Carver gc(ix.ws[3].ptr);
       stage_key = gc.take<uint64_t>(stage_n);
     }
-    launch_scatter(sv, P.rp_s, stage_key, di.cus * 16, s);
+    launch_scatter(sv, P.rp_s, stage_key, sgrid, s);
     mv = RowMove{P.rp_s, stage_key, qorig, out->row_ptr, out->col, out->dist, &P.ctl->nnz,
                  (unsigned long long)out->nnz_cap};
-    launch_row_sort_head(mv, m, P.lists, P.ctl->list_counts, s);
+    launch_row_sort_short(mv, P.lists, P.ctl->list_counts, s);
     SNN_HIP(hipMemcpyAsync(&hc.ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    // the call's end unless longer rows follow the read-back
+    if (st) SNN_HIP(hipEventRecord(ev[3], s));
     SNN_HIP(hipStreamSynchronize(s));
     hc.nnz = (int64_t)hc.ctl.nnz;
     if (hc.ctl.bad) fail(SNN_EINVAL, "Q contains NaN or Inf");
@@ -612,7 +653,6 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       st->screen_ms = a;
       st->total_ms = b;
       st->pairs_executed = (int64_t)hc.ctl.executed;
-      for (auto& e : ev) (void)hipEventDestroy(e);
     }
     return;
   }
@@ -629,15 +669,16 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   launch_row_sort_tail(mv, m, (int64_t)hc.ctl.row_max, P.lists, P.ctl->list_counts, tmp_col, tmp_dist, s);
 
   if (st) {
-    SNN_HIP(hipEventRecord(ev[3], s));
-    SNN_HIP(hipEventSynchronize(ev[3]));
+    if (hc.ctl.row_max > 16) {  // longer rows were sorted after the read-back
+      SNN_HIP(hipEventRecord(ev[3], s));
+      SNN_HIP(hipEventSynchronize(ev[3]));
+    }
     float a = 0, b = 0;
     SNN_HIP(hipEventElapsedTime(&a, ev[1], ev[2]));
     SNN_HIP(hipEventElapsedTime(&b, ev[0], ev[3]));
     st->screen_ms = a;
     st->total_ms = b;
     st->pairs_executed = (int64_t)hc.ctl.executed;
-    for (auto& e : ev) (void)hipEventDestroy(e);
   }
 }
 
@@ -719,20 +760,23 @@ static void debug_screen(Index& ix, const void* Q, int64_t m, double R, const sn
   Carver carve(mem.get());
   auto P = plan(carve);
   launch_query_init(P.ctl, 1, P.row_cnt, m, P.hist, nb, nullptr, nullptr, 0, s);
+  QueryOperands qop{};
+  MixedDev mx{};
+  if (mix16)
+    mx = prepare_mixed(ix, sp.kind, R2, false, m, P.qop, P.cthr, &qop, s);
+  else
+    prepare_fp32(ix, R2, false, m, P.vq, &qop, s);
   launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), ix.key.as<double>(), (int)n, nb, P.ukey,
                     P.val, P.hist, P.qa_in, P.qn_in, reinterpret_cast<int*>(P.ctl), s);
-  exclusive_scan_u32(P.hist, nb, P.scan, s);
   launch_query_gather(ix.dtype, Q, m, d, ix.dp, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, P.q64, P.qorig, P.qa, P.qn,
-                      s);
+                      ix.mu.as<double>(), qop, s);
   if (mix16) {
-    const MixedDev mx = prepare_mixed(ix, sp.kind, R2, false, P.q64, m, P.qop, P.cthr, s);
     launch_dump_mixed(mx, m, n, P.qorig, D, s);
     SNN_HIP(hipMemcpyAsync(H, mx.h, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
     launch_dump_rows_f32(P.cthr, m, 1, P.qorig, C, s);
     launch_dump_rows_u16(P.qop, m, lay->ka, P.qorig, static_cast<uint16_t*>(A), s);
     launch_dump_cand16(mx.cop, n, lay->kb, static_cast<uint16_t*>(B), s);
   } else {
-    prepare_fp32(ix, R2, false, P.q64, m, P.vq, s);
     const Mfma32Dev x{P.vq, lay->ka, d, ix.vcand.as<float>(), ix.h.as<float>()};
     launch_dump_mfma32(x, m, n, P.qorig, D, s);
     SNN_HIP(hipMemcpyAsync(H, ix.h.ptr, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
@@ -741,10 +785,10 @@ static void debug_screen(Index& ix, const void* Q, int64_t m, double R, const sn
                              hipMemcpyDeviceToDevice, s));
     SNN_HIP(hipMemcpyAsync(B, ix.ys.ptr, sizeof(float) * n * d, hipMemcpyDeviceToDevice, s));
   }
-  unsigned long long bad = 0;
-  SNN_HIP(hipMemcpyAsync(&bad, P.ctl, sizeof(bad), hipMemcpyDeviceToHost, s));
+  int flags[2] = {0, 0};  // NaN/Inf flag, padding
+  SNN_HIP(hipMemcpyAsync(flags, P.ctl, sizeof(flags), hipMemcpyDeviceToHost, s));
   SNN_HIP(hipStreamSynchronize(s));
-  if (bad) fail(SNN_EINVAL, "Q contains NaN or Inf");
+  if (flags[0]) fail(SNN_EINVAL, "Q contains NaN or Inf");
 }
 
 }  // namespace snn
@@ -766,9 +810,10 @@ static void free_index(snn_index_s* ix) {
     mo.qself.reset(a);
     mo.hs.reset(a);
   }
-  {
-    ix->vcand.reset(a);
-  }
+  ix->vcand.reset(a);
+  ix->wcells.reset(a);
+  for (hipEvent_t& e : ix->ev)
+    if (e) (void)hipEventDestroy(e);
   for (auto& w : ix->ws) w.reset(a);
   delete ix;
 }

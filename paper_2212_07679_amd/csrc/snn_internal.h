@@ -160,6 +160,9 @@ struct Index {
   MixedOperands mixed[3];  // bf16 one term, bf16 hi/lo, fp16 (mixed_slot)
   Buffer vcand;            // fp32 screen candidate operand blocks (k_cand_mfma32)
   bool vcand_built = false;
+  Buffer wcells;           // window_table_cells(n) + 1 int32: grid cells of the sorted scores
+  int wcells_n = 0;
+  bool wcells_built = false;
 
   double max_norm = 0;  // max ||ys_i|| (float64, rounded up)
   double vnorm = 1;     // ||v|| (float64, rounded up)
@@ -168,6 +171,7 @@ struct Index {
 
   // per-call workspace (grow-only)
   Buffer ws[16];
+  hipEvent_t ev[4] = {};  // stats timing (created on first use)
   Buffer stats_host_dev;  // small device block read back at the end of a query
 };
 
