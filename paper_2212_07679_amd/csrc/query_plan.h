@@ -114,11 +114,11 @@ __device__ __forceinline__ bool decode_unit(const QueryDev& q, int64_t u, int& t
 
 // ---------------------------------------------------------------- launchers
 int query_buckets(int64_t m);
-// keys, buckets and slots of the queries, then hist (K <= 4096 counts, zero
-// beforehand) turned into bucket offsets
+// keys, buckets and slots of the queries, then hist (K counts, zero
+// beforehand) turned into bucket offsets (scan_scratch: scan_scratch_bytes(K))
 void launch_query_keys(snn_dtype dt, const void* Q, int64_t m, int d, const double* mu, const double* v,
                        const double* key, int n, int K, uint32_t* bucket, uint32_t* slot, uint32_t* hist,
-                       double* qalpha, double* qnorm, int* bad, hipStream_t s);
+                       double* qalpha, double* qnorm, int* bad, void* scan_scratch, hipStream_t s);
 struct QueryOperands;
 // queries into score order (bucket offsets boff), with the screen's query
 // operands and start values (op.mode: none, 16-bit rows + C_q, fp32 rows)

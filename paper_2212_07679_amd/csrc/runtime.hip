@@ -454,7 +454,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     if (m > 0) {
       // queries into score order by a counting sort on a uniform score grid
       launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), ix.key.as<double>(), (int)n,
-                        nbuckets, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, &P.ctl->bad, s);
+                        nbuckets, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, &P.ctl->bad, P.scan_scratch, s);
       launch_query_gather(ix.dtype, Q, m, d, ix.dp, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, P.q64, P.qorig, P.qa,
                           P.qn, ix.mu.as<double>(), qop, s);
     }
@@ -767,7 +767,7 @@ static void debug_screen(Index& ix, const void* Q, int64_t m, double R, const sn
   else
     prepare_fp32(ix, R2, false, m, P.vq, &qop, s);
   launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), ix.key.as<double>(), (int)n, nb, P.ukey,
-                    P.val, P.hist, P.qa_in, P.qn_in, reinterpret_cast<int*>(P.ctl), s);
+                    P.val, P.hist, P.qa_in, P.qn_in, reinterpret_cast<int*>(P.ctl), P.scan, s);
   launch_query_gather(ix.dtype, Q, m, d, ix.dp, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, P.q64, P.qorig, P.qa, P.qn,
                       ix.mu.as<double>(), qop, s);
   if (mix16) {
