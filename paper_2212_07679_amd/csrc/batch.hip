@@ -738,7 +738,7 @@ BatchPlan* create_batch(const snn_device& devc, snn_dtype dtype, const snn_insta
       KA = std::max(KA, pad16(t * b.d));
     }
     p.KA = KA;
-    p.T = 4 * mixed_queries_per_wave(KA);
+    p.T = 4 * mixed_queries_per_wave(KA, false);  // bf16 operands
     p.CH = o.tile_c ? o.tile_c : 4096;
     p.G = o.tile_g ? o.tile_g : 8;
     plan_layout(p);

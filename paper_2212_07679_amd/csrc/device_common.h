@@ -165,6 +165,9 @@ __device__ __forceinline__ void wave_flush(int2* buf, int& wcnt, const PairSink&
   base = __shfl(base, 0, kWave);
   for (int i = lane_id(); i < wcnt; i += kWave) sink_store(sink, (long long)base + i, buf[i]);
   __builtin_amdgcn_wave_barrier();  // and these reads before the next pushes
+  // this (rare) path drains the wave's memory counters, so that the callers'
+  // load waits after it are counted as on the path without a flush
+  __builtin_amdgcn_s_waitcnt(0);
   wcnt = 0;
 }
 

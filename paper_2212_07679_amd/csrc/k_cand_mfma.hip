@@ -254,6 +254,9 @@ __device__ __forceinline__ void step_products(const typename Op16<F16>::V (&A)[Q
 // zeros), one max over the lane's accumulators and one compare.  Only the
 // last step of a unit can have lanes past its span (units are cut at
 // multiples of 32 rows except at the end of the index), so only it masks.
+// (Loading the block together with h after the compare keeps the compiler's
+// load-count waits exact but starts the block's load a compare later: 0.385
+// against 0.378 ms on the n = 1e6, d = 16 set.)
 template <bool F16, int NS, int QB, int NL, int PF, bool LAST>
 __device__ __forceinline__ void mixed_step(const typename Op16<F16>::V (&A)[QB][NS], const f32x16 (&Cin)[QB],
                                            typename Op16<F16>::V (&B)[NL], float& h, __amdgpu_buffer_rsrc_t rc,
@@ -611,24 +614,28 @@ typedef void (*MixedKernel)(QueryDev, MixedDev);
 // Query blocks of 32 per wavefront.  More blocks share each candidate load
 // among more product chains, but also make the tiles (4 wavefronts x QB x
 // 32 queries) longer, and with them the union windows of small instances.
-// Measured on one box: two blocks against four, 1.03-1.05 vs 1.25-1.31 ms
-// for the 256-instance batch screen and equal within noise for the n = 1e6,
-// d = 16 set; issuing the next step's products before the previous step's
-// compare epilogue (two accumulator sets) gained nothing at two blocks and
-// lost a wave per SIMD at four.
-constexpr int qb_for(int) { return 2; }
+// The one-slice fp16 screen has one product per block and step, so its
+// candidate loads are the larger share of the work: three blocks there
+// (n = 1e6, d = 16 set: 0.379 ms against 0.415 ms with two, 0.374 ms with
+// four at 5% more executed pairs and two wavefronts per SIMD).  Two blocks
+// elsewhere: two against four measured 1.03-1.05 vs 1.25-1.31 ms for the
+// 256-instance batch screen and equal within noise for the d = 16 set in
+// three-term bf16; issuing the next step's products before the previous
+// step's compare epilogue (two accumulator sets) gained nothing at two
+// blocks and lost a wave per SIMD at four.
+constexpr int qb_for(bool f16, int ns) { return f16 && ns == 1 ? 3 : 2; }
 
 // (slices per product chain, slices loaded per candidate row); fp16
 // operands come one per coordinate only (ns = nl)
 MixedKernel pick_kernel(int KA, int KB, bool f16) {
   const int ns = KA / 16, nl = KB / 16;
 #define SNN_CASE(NS_, NL_) \
-  if (ns == NS_ && nl == NL_) return f16 ? k_cand_mfma<true, NS_, qb_for(NS_), NL_> : k_cand_mfma<false, NS_, qb_for(NS_), NL_>;
+  if (ns == NS_ && nl == NL_) return f16 ? k_cand_mfma<true, NS_, qb_for(true, NS_), NL_> : k_cand_mfma<false, NS_, qb_for(false, NS_), NL_>;
   SNN_CASE(1, 1) SNN_CASE(2, 2) SNN_CASE(3, 3) SNN_CASE(4, 4) SNN_CASE(5, 5) SNN_CASE(6, 6) SNN_CASE(7, 7)
   SNN_CASE(8, 8)
 #undef SNN_CASE
 #define SNN_CASE(NS_, NL_) \
-  if (!f16 && ns == NS_ && nl == NL_) return k_cand_mfma<false, NS_, qb_for(NS_), NL_>;
+  if (!f16 && ns == NS_ && nl == NL_) return k_cand_mfma<false, NS_, qb_for(false, NS_), NL_>;
   SNN_CASE(3, 2) SNN_CASE(6, 4)
 #undef SNN_CASE
   return nullptr;
@@ -642,7 +649,7 @@ int grid_for(int64_t work, int cap) {
 }  // namespace
 
 int mixed_max_slices() { return 8; }
-int mixed_queries_per_wave(int KA) { return 32 * qb_for(KA / 16); }
+int mixed_queries_per_wave(int KA, bool f16) { return 32 * qb_for(f16, KA / 16); }
 
 int mixed_blocks_per_cu(int KA, int KB, bool f16) {
   MixedKernel k = pick_kernel(KA, KB, f16);

@@ -290,7 +290,7 @@ struct QueryOperands {
 };
 
 int mixed_max_slices();
-int mixed_queries_per_wave(int KA);  // 32 x query blocks per wavefront
+int mixed_queries_per_wave(int KA, bool f16);  // 32 x query blocks per wavefront
 int mixed_blocks_per_cu(int KA, int KB, bool f16);
 // operand row length (16-bit values) of an OperandKind at dimension d
 int operand_ka(int kind, int d);

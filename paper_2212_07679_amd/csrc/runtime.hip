@@ -347,7 +347,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const bool mix16 = prec == SNN_PREC_MIXED || prec == SNN_PREC_FP16;  // 16-bit operand screens
   const double Y = ix.max_norm;
   int T_fixed = 0;
-  if (mix16) T_fixed = 4 * mixed_queries_per_wave(operand_ka(sp.kind, d));
+  if (mix16) T_fixed = 4 * mixed_queries_per_wave(operand_ka(sp.kind, d), sp.kind == kOpF16);
   if (prec == SNN_PREC_FP32) T_fixed = mfma32_queries_per_tile();
   if (T_fixed && o.tile_q && o.tile_q != T_fixed)
     fail(SNN_EINVAL, "tile_q must be " + std::to_string(T_fixed) + " for this screen and dimension");
@@ -481,7 +481,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
                  P.tlo, P.thi, P.wpart, s);
   // query slots per wavefront (stats): the matrix-core screens evaluate
   // whole 32-query blocks, the float64 screen one query at a time
-  const int qpw = mix16                   ? mixed_queries_per_wave(operand_ka(sp.kind, d))
+  const int qpw = mix16                   ? mixed_queries_per_wave(operand_ka(sp.kind, d), sp.kind == kOpF16)
                   : prec == SNN_PREC_FP32 ? mfma32_queries_per_tile() / 4
                                           : 1;
   // chunk-major work order inside groups of G score-adjacent tiles (L2 reuse)
