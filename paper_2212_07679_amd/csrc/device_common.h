@@ -199,4 +199,57 @@ __device__ __forceinline__ void stage_flush(PairStage<kStage>& st, const PairSin
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) sink_store(sink, base + i, st.buf[i]);
 }
 
+
+// ---- single-pass scans (decoupled look-back)
+// A workgroup takes its tile of kLookbackTile elements by a ticket, so every
+// tile before it belongs to a workgroup that has already started; it
+// publishes its tile total, then adds the totals of the tiles before it,
+// one wavefront reading 64 of them at a time, back to the nearest tile that
+// has published its inclusive prefix, and publishes its own.  state[0] is
+// the ticket, state[1 + t] tile t's word: (flag << 62) | value with flag 0
+// (nothing yet), 1 (tile total) or 2 (inclusive prefix); the whole state is
+// zero before the launch.  A wait that does not end within kLookbackSpins
+// polls sets *err and takes 0, so the kernel still ends (the host then
+// reports the error); it cannot happen while every started workgroup
+// progresses.
+constexpr int kLookbackThreads = 256;
+constexpr int kLookbackItems = 8;
+constexpr int kLookbackTile = kLookbackThreads * kLookbackItems;
+constexpr int kLookbackSpins = 1 << 22;
+constexpr unsigned long long kLookbackValue = (1ull << 62) - 1;
+
+__device__ __forceinline__ void lookback_publish(unsigned long long* state, long long t, unsigned long long flag,
+                                                 unsigned long long v) {
+  __hip_atomic_store(&state[1 + t], (flag << 62) | (v & kLookbackValue), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of tile t (t > 0), called by one whole wavefront.
+__device__ __forceinline__ unsigned long long lookback_exclusive(unsigned long long* state, long long t, int* err) {
+  const int lane = lane_id();
+  unsigned long long excl = 0;
+  long long base = t - 1;
+  int spins = 0;
+  for (;;) {
+    const long long j = base - lane;
+    unsigned long long w = 2ull << 62;  // before tile 0: an inclusive prefix of 0
+    if (j >= 0) w = __hip_atomic_load(&state[1 + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long flag = w >> 62;
+    const uint64_t pre = __ballot(flag == 2);
+    const int p = pre ? __ffsll((long long)pre) - 1 : kWave;  // nearest prefix within the window
+    const uint64_t need = p == kWave ? ~0ull : (p == 63 ? ~0ull : ((2ull << p) - 1ull));
+    if (__ballot(flag == 0) & need) {  // a tile this window needs has not published yet
+      if (++spins > kLookbackSpins) {
+        if (lane == 0) *err = 1;
+        return 0;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += wave_sum(lane <= p ? (w & kLookbackValue) : 0ull);
+    if (p < kWave) return excl;
+    base -= kWave;
+  }
+}
+
 }  // namespace snn

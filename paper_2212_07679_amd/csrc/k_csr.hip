@@ -1,17 +1,20 @@
 // From surviving (query, candidate) pairs to CSR neighbour lists.
 //
-//  k_recheck  every survivor is decided by the normative rule on the
-//             original coordinates in float64 (direct form of eq. (ip1),
-//             left to right, no fused multiply-add; inclusive compare of
-//             Section 3.2).  Neighbours take a slot in their row; rows are
-//             query slots (score order).
-//  (scan)     row counts -> slot-order row offsets
-//  k_scatter  neighbours into their slot-order rows
-//  row sort   each row sorted by id on its way to the caller's row order:
-//             rows of <= 16 / 32 / 64 entries by lane groups of that size
-//             (bitonic across lanes), up to 512 by one wavefront with 2 / 4 / 8
-//             entries per lane, longer rows by one workgroup (bitonic in LDS,
-//             then merge passes).
+//  k_recheck    every survivor is decided by the normative rule on the
+//               original coordinates in float64 (direct form of eq. (ip1),
+//               left to right, no fused multiply-add; inclusive compare of
+//               Section 3.2).  Neighbours take a slot in their row; rows are
+//               query slots (score order).
+//  k_rows_scan  row counts -> row offsets in one launch (look-back scan);
+//               for the slot-order rows also the counts in the caller's
+//               order, the longest row, the total and the rows by length
+//               class; again for the caller's row offsets
+//  k_scatter    neighbours into their slot-order rows
+//  row sort     each row sorted by id on its way to the caller's row order:
+//               rows of <= 16 / 32 / 64 entries by lane groups of that size
+//               (bitonic across lanes), up to 512 by one wavefront with 2 / 4
+//               / 8 entries per lane, longer rows by one workgroup (bitonic in
+//               LDS, then merge passes).
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -156,8 +159,7 @@ __device__ __forceinline__ bool rows_fit(const RowMove& mv) { return !mv.total |
 // longer (kRowClasses lists).
 constexpr int kRowClasses = 7;
 
-__device__ __forceinline__ int row_class(const int64_t* __restrict__ row_ptr, int64_t r) {
-  const int64_t len = row_ptr[r + 1] - row_ptr[r];
+__device__ __forceinline__ int len_class(int64_t len) {
   if (len <= 0) return -1;
   if (len <= 16) return 0;
   if (len <= 32) return 1;
@@ -166,6 +168,10 @@ __device__ __forceinline__ int row_class(const int64_t* __restrict__ row_ptr, in
   if (len <= 256) return 4;
   if (len <= 512) return 5;
   return 6;
+}
+
+__device__ __forceinline__ int row_class(const int64_t* __restrict__ row_ptr, int64_t r) {
+  return len_class(row_ptr[r + 1] - row_ptr[r]);
 }
 
 // about 4096 rows per workgroup (at most 1024 workgroups): each reserves
@@ -224,7 +230,7 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_seg(RowMove mv, const int
       const int r = list[k];
       b = mv.src_rp[r];
       len = (int)(mv.src_rp[r + 1] - b);
-      o = mv.dst_rp[mv.map[r]];
+      o = mv.dst_rp[mv.map ? mv.map[r] : r];
     }
     uint64_t key = sub < len ? mv.src_key[b + sub] : ~0ull;
 #pragma unroll
@@ -261,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_reg(RowMove mv, const int
     const int r = list[w];
     const int64_t b = mv.src_rp[r];
     const int len = (int)(mv.src_rp[r + 1] - b);
-    const int64_t o = mv.dst_rp[mv.map[r]];
+    const int64_t o = mv.dst_rp[mv.map ? mv.map[r] : r];
     uint64_t key[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -343,7 +349,7 @@ __global__ __launch_bounds__(kThreads) void k_row_sort_block(RowMove mv, const i
     const int r = list[w];
     const int64_t b = mv.src_rp[r];
     const int64_t len = mv.src_rp[r + 1] - b;
-    const int64_t o = mv.dst_rp[mv.map[r]];
+    const int64_t o = mv.dst_rp[mv.map ? mv.map[r] : r];
     for (int64_t c0 = 0; c0 < len; c0 += kBlockSort) {
       const int cl = (int)min((int64_t)kBlockSort, len - c0);
       int np2 = 1;
@@ -458,6 +464,105 @@ __global__ __launch_bounds__(kThreads) void k_rows_stats(const int64_t* __restri
   for (int64_t r = r0 + t; r < r1; r += kThreads) {
     const int c = row_class(src_rp, r);
     if (c >= 0) lists[(int64_t)c * m + (int64_t)base[c] + atomicAdd(&cnt[c], 1)] = (int32_t)r;
+  }
+}
+
+// Row offsets from row counts in one launch (look-back scan: row_ptr[r] =
+// sum of cnt before r, row_ptr[m] = total) and, when given (RowsExtra), the
+// counts in the destination order (cnt_dst[map[r]] = cnt[r]), the longest
+// row, the total and the rows by length class (each workgroup reserves its
+// class list space with one atomic per class).
+__global__ __launch_bounds__(kLookbackThreads) void k_rows_scan(const int32_t* __restrict__ cnt, int64_t m,
+                                                               int64_t* __restrict__ row_ptr,
+                                                               unsigned long long* __restrict__ state,
+                                                               int* __restrict__ err, RowsExtra ex) {
+  const int32_t* __restrict__ map = ex.map;
+  int32_t* __restrict__ cnt_dst = ex.cnt_dst;
+  unsigned long long* __restrict__ row_max = ex.row_max;
+  unsigned long long* __restrict__ total = ex.total;
+  int32_t* __restrict__ lists = ex.lists;
+  unsigned long long* __restrict__ list_counts = ex.list_counts;
+  __shared__ unsigned long long s_tile;
+  __shared__ long long s_wave[kLookbackThreads / kWave];
+  __shared__ int s_max[kLookbackThreads / kWave];
+  __shared__ long long s_excl;
+  __shared__ int s_cls[kRowClasses];
+  __shared__ unsigned long long s_base[kRowClasses];
+  const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+  if (t == 0) s_tile = atomicAdd(&state[0], 1ull);
+  if (t < kRowClasses) s_cls[t] = 0;
+  __syncthreads();
+  const long long tile = (long long)s_tile;
+  const int64_t i0 = tile * kLookbackTile + (int64_t)t * kLookbackItems;
+  int v[kLookbackItems];
+  long long sum = 0;
+  int vmax = 0;
+#pragma unroll
+  for (int k = 0; k < kLookbackItems; ++k) {
+    v[k] = i0 + k < m ? cnt[i0 + k] : 0;
+    sum += v[k];
+    vmax = max(vmax, v[k]);
+    if (lists) {
+      const int c = len_class(v[k]);
+      if (c >= 0) atomicAdd(&s_cls[c], 1);
+    }
+    if (map && i0 + k < m) {
+      const int r = map[i0 + k];
+      if (r >= 0) cnt_dst[r] = v[k];
+    }
+  }
+  long long x = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const long long y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  vmax = wave_max(vmax);
+  if (lane == kWave - 1) s_wave[w] = x;
+  if (lane == 0) s_max[w] = vmax;
+  __syncthreads();
+  long long before = 0, tot = 0;
+  int bmax = 0;
+#pragma unroll
+  for (int k = 0; k < kLookbackThreads / kWave; ++k) {
+    if (k < w) before += s_wave[k];
+    tot += s_wave[k];
+    bmax = max(bmax, s_max[k]);
+  }
+  if (w == 0) {
+    unsigned long long excl = 0;
+    if (tile == 0) {
+      if (lane == 0) lookback_publish(state, 0, 2, (unsigned long long)tot);
+    } else {
+      if (lane == 0) lookback_publish(state, tile, 1, (unsigned long long)tot);
+      excl = lookback_exclusive(state, tile, err);
+      if (lane == 0) lookback_publish(state, tile, 2, excl + (unsigned long long)tot);
+    }
+    if (lane == 0) {
+      s_excl = (long long)excl;
+      // the maximum only grows: a workgroup that cannot raise it skips the atomic
+      if (row_max && bmax > 0 &&
+          (unsigned long long)bmax > __hip_atomic_load(row_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(row_max, (unsigned long long)bmax);
+      if ((tile + 1) * kLookbackTile >= m) {  // the last tile: the total
+        row_ptr[m] = (int64_t)(excl + (unsigned long long)tot);
+        if (total) *total = excl + (unsigned long long)tot;
+      }
+    }
+  } else if (lists && w == 1 && lane < kRowClasses) {
+    s_base[lane] = s_cls[lane] ? atomicAdd(&list_counts[lane], (unsigned long long)s_cls[lane]) : 0ull;
+    s_cls[lane] = 0;
+  }
+  __syncthreads();
+  long long run = s_excl + before + x - sum;
+#pragma unroll
+  for (int k = 0; k < kLookbackItems; ++k) {
+    if (i0 + k < m) {
+      row_ptr[i0 + k] = run;
+      const int c = lists ? len_class(v[k]) : -1;
+      if (c >= 0) lists[(int64_t)c * m + (int64_t)s_base[c] + atomicAdd(&s_cls[c], 1)] = (int32_t)(i0 + k);
+    }
+    run += v[k];
   }
 }
 
@@ -611,6 +716,13 @@ void launch_rows_stats(const int64_t* src_rp, int64_t m, const int32_t* map, int
                        unsigned long long* list_counts, hipStream_t s) {
   const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (m + 1023) / 1024));
   k_rows_stats<<<blocks, kThreads, 0, s>>>(src_rp, m, map, cnt_dst, row_max, total, lists, list_counts);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_rows_scan(const int32_t* cnt, int64_t m, int64_t* row_ptr, unsigned long long* state, int* err,
+                      const RowsExtra& ex, hipStream_t s) {
+  const int blocks = (int)std::max<int64_t>(1, (m + kLookbackTile - 1) / kLookbackTile);
+  k_rows_scan<<<blocks, kLookbackThreads, 0, s>>>(cnt, m, row_ptr, state, err, ex);
   SNN_LAUNCH_CHECK();
 }
 

@@ -1222,6 +1222,7 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   for (auto& mo : ix.mixed) mo.built = false;
   ix.vcand_built = false;
   ix.wcells_built = false;
+  ++ix.epoch;
 }
 
 void insert_points(Index& ix, const void* X, int64_t k) {

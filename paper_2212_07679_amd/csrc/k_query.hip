@@ -3,7 +3,7 @@
 //  k_query_keys    x_q = q - mu, alpha_q = x_q . v (float64), ||fl32(x_q)||,
 //                  and a bucket of alpha_q on a uniform grid over the range of
 //                  the index scores; each query takes a slot in its bucket
-//  k_scan_buckets  bucket offsets (one workgroup)
+//  (scan)          bucket offsets (one launch, look-back)
 //  k_query_gather  query rows in float64, in bucket (score) order, so that a
 //                  tile of consecutive queries shares one union window (the
 //                  gemm over the union of candidate sets, Section 4), and the
@@ -30,39 +30,6 @@ namespace snn {
 
 namespace {
 constexpr int kThreads = 256;
-}
-
-// Exclusive scan of nb <= kBucketsMax bucket counts by one workgroup of
-// kThreads threads: staged in LDS with coalesced loads, each thread scans a
-// run of consecutive entries, the run totals are scanned across the
-// workgroup and the offsets written back.
-constexpr int kBucketsMax = 4096;
-constexpr int kBucketRun = kBucketsMax / kThreads;
-__device__ void scan_buckets_block(uint32_t* __restrict__ hist, int nb, uint32_t* buf, uint32_t* part) {
-  const int t = threadIdx.x;
-  for (int i = t; i < kBucketsMax; i += kThreads)
-    buf[i] = i < nb ? hist[i] : 0u;
-  __syncthreads();
-  uint32_t sum = 0;
-#pragma unroll
-  for (int k = 0; k < kBucketRun; ++k) sum += buf[t * kBucketRun + k];
-  part[t] = sum;
-  __syncthreads();
-  for (int off = 1; off < kThreads; off <<= 1) {  // inclusive scan of the run totals
-    const uint32_t v = t >= off ? part[t - off] : 0u;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  uint32_t run = part[t] - sum;
-#pragma unroll
-  for (int k = 0; k < kBucketRun; ++k) {
-    const uint32_t x = buf[t * kBucketRun + k];
-    buf[t * kBucketRun + k] = run;
-    run += x;
-  }
-  __syncthreads();
-  for (int i = t; i < nb; i += kThreads) hist[i] = buf[i];
 }
 
 // G lanes per query row (coalesced row reads); the row's partial sums meet
@@ -106,16 +73,6 @@ __global__ __launch_bounds__(kThreads) void k_query_keys(const T* __restrict__ Q
     }
   }
   if (badloc) atomicOr(bad, 1);
-}
-
-// The bucket counts into bucket offsets for up to kBucketsMax buckets, one
-// workgroup (a ticket per workgroup of the key pass instead, for the last one
-// to scan, serialises thousands of atomics on one address: measured 150 us
-// against 11 us).
-__global__ __launch_bounds__(kThreads) void k_scan_buckets(uint32_t* __restrict__ hist, int nb) {
-  __shared__ uint32_t buf[kBucketsMax];
-  __shared__ uint32_t part[kThreads];
-  scan_buckets_block(hist, nb, buf, part);
 }
 
 // G lanes per query row: the row's destination slot is read once per group,
@@ -452,18 +409,14 @@ void query_keys_d(const T* Q, int64_t m, int d, const double* mu, const double* 
 
 void launch_query_keys(snn_dtype dt, const void* Q, int64_t m, int d, const double* mu, const double* v,
                        const double* key, int n, int K, uint32_t* bucket, uint32_t* slot, uint32_t* hist,
-                       double* qalpha, double* qnorm, int* bad, void* scan_scratch, hipStream_t s) {
+                       double* qalpha, double* qnorm, int* bad, unsigned long long* scan_state, int* scan_err,
+                       hipStream_t s) {
   if (dt == SNN_F32)
     query_keys_d<float>((const float*)Q, m, d, mu, v, key, n, K, bucket, slot, hist, qalpha, qnorm, bad, s);
   else
     query_keys_d<double>((const double*)Q, m, d, mu, v, key, n, K, bucket, slot, hist, qalpha, qnorm, bad, s);
   SNN_LAUNCH_CHECK();
-  if (K <= kBucketsMax) {
-    k_scan_buckets<<<1, kThreads, 0, s>>>(hist, K);
-    SNN_LAUNCH_CHECK();
-  } else {
-    exclusive_scan_u32(hist, K, scan_scratch, s);
-  }
+  lookback_scan_u32(hist, K, scan_state, scan_err, s);
 }
 
 namespace {

@@ -290,7 +290,68 @@ void scan_rec(const TI* in, TO* out, int64_t n, int write_total, TO* scratch, hi
   SNN_LAUNCH_CHECK();
 }
 
+// In-place exclusive scan of n u32 values in one launch (look-back; state:
+// lookback_words(n) zeroed words).
+__global__ __launch_bounds__(kLookbackThreads) void k_scan_u32_lookback(uint32_t* __restrict__ data, int64_t n,
+                                                                       unsigned long long* __restrict__ state,
+                                                                       int* __restrict__ err) {
+  __shared__ unsigned long long s_tile;
+  __shared__ uint32_t s_wave[kLookbackThreads / kWave];
+  __shared__ uint32_t s_excl;
+  const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+  if (t == 0) s_tile = atomicAdd(&state[0], 1ull);
+  __syncthreads();
+  const long long tile = (long long)s_tile;
+  const int64_t i0 = tile * kLookbackTile + (int64_t)t * kLookbackItems;
+  uint32_t v[kLookbackItems], sum = 0;
+#pragma unroll
+  for (int k = 0; k < kLookbackItems; ++k) {
+    v[k] = i0 + k < n ? data[i0 + k] : 0u;
+    sum += v[k];
+  }
+  uint32_t x = sum;  // inclusive scan of the thread sums within the wavefront
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, kWave);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) s_wave[w] = x;
+  __syncthreads();
+  uint32_t before = 0, total = 0;
+#pragma unroll
+  for (int k = 0; k < kLookbackThreads / kWave; ++k) {
+    if (k < w) before += s_wave[k];
+    total += s_wave[k];
+  }
+  if (w == 0) {
+    unsigned long long excl = 0;
+    if (tile == 0) {
+      if (lane == 0) lookback_publish(state, 0, 2, total);
+    } else {
+      if (lane == 0) lookback_publish(state, tile, 1, total);
+      excl = lookback_exclusive(state, tile, err);
+      if (lane == 0) lookback_publish(state, tile, 2, excl + total);
+    }
+    if (lane == 0) s_excl = (uint32_t)excl;
+  }
+  __syncthreads();
+  uint32_t run = s_excl + before + x - sum;
+#pragma unroll
+  for (int k = 0; k < kLookbackItems; ++k) {
+    if (i0 + k < n) data[i0 + k] = run;
+    run += v[k];
+  }
+}
+
 }  // namespace
+
+size_t lookback_words(int64_t n) { return 1 + (size_t)std::max<int64_t>(1, ceil_div(n, kLookbackTile)); }
+
+void lookback_scan_u32(uint32_t* data, int64_t n, unsigned long long* state, int* err, hipStream_t s) {
+  if (n <= 0) return;
+  k_scan_u32_lookback<<<(unsigned)ceil_div(n, kLookbackTile), kLookbackThreads, 0, s>>>(data, n, state, err);
+  SNN_LAUNCH_CHECK();
+}
 
 size_t scan_scratch_bytes(int64_t n) {
   size_t total = 0;

@@ -115,10 +115,12 @@ __device__ __forceinline__ bool decode_unit(const QueryDev& q, int64_t u, int& t
 // ---------------------------------------------------------------- launchers
 int query_buckets(int64_t m);
 // keys, buckets and slots of the queries, then hist (K counts, zero
-// beforehand) turned into bucket offsets (scan_scratch: scan_scratch_bytes(K))
+// beforehand) turned into bucket offsets (scan_state: lookback_words(K)
+// zero words)
 void launch_query_keys(snn_dtype dt, const void* Q, int64_t m, int d, const double* mu, const double* v,
                        const double* key, int n, int K, uint32_t* bucket, uint32_t* slot, uint32_t* hist,
-                       double* qalpha, double* qnorm, int* bad, void* scan_scratch, hipStream_t s);
+                       double* qalpha, double* qnorm, int* bad, unsigned long long* scan_state, int* scan_err,
+                       hipStream_t s);
 struct QueryOperands;
 // queries into score order (bucket offsets boff), with the screen's query
 // operands and start values (op.mode: none, 16-bit rows + C_q, fp32 rows)
@@ -338,9 +340,26 @@ struct Survivors {
 __host__ __device__ __forceinline__ uint64_t neighbour_key(int32_t id, float dist) {
   return ((uint64_t)(uint32_t)id << 32) | (uint64_t)__builtin_bit_cast(uint32_t, dist);
 }
-// po: the index's data rows in the input dtype, score order (n x d)
+// po: the index's data rows in the input dtype, score order (n x d);
+// row_cnt: counts of the slot-order rows (m, zero beforehand)
 void launch_recheck(const QueryDev& q, const Survivors& sv, snn_dtype dt, const void* po, bool self,
                     int32_t* row_cnt, int grid, hipStream_t s);
+// Optional outputs of launch_rows_scan (each may be NULL): counts in the
+// destination order cnt_dst[map[r]] = cnt[r], the longest row (atomic max),
+// the total, and the rows by length class (lists: row_sort_lists() x m,
+// list_counts zero beforehand; lists NULL: none).
+struct RowsExtra {
+  const int32_t* map;
+  int32_t* cnt_dst;
+  unsigned long long* row_max;
+  unsigned long long* total;
+  int32_t* lists;
+  unsigned long long* list_counts;
+};
+// row_ptr (m + 1) from the counts in one launch; state: lookback_words(m)
+// zero words
+void launch_rows_scan(const int32_t* cnt, int64_t m, int64_t* row_ptr, unsigned long long* state, int* err,
+                      const RowsExtra& ex, hipStream_t s);
 // keys into slot-order rows at row_ptr[row] + slot
 // (does nothing when the survivor list overflowed: *sv.count > sv.cap)
 void launch_scatter(const Survivors& sv, const int64_t* row_ptr, uint64_t* keys, int grid, hipStream_t s);
@@ -357,12 +376,12 @@ size_t dbscan_work_bytes(int64_t n);
 // (synchronises the stream)
 int64_t dbscan_from_survivors(const Survivors& sv, int64_t n, const int32_t* row_cnt, const int32_t* perm,
                               int min_samples, void* work, int32_t* labels, uint8_t* core, int grid, hipStream_t s);
-// Source row r of a CSR in slot order (neighbour keys) goes, sorted by id,
-// to destination row map[r] of the caller's CSR.
+// Source row r of a CSR of neighbour keys goes, sorted by id, to
+// destination row map[r] (row r when map is NULL) of the caller's CSR.
 struct RowMove {
   const int64_t* src_rp;
   const uint64_t* src_key;
-  const int32_t* map;  // source row -> destination row (< 0: empty padding row)
+  const int32_t* map;  // source row -> destination row (< 0: empty padding row), or NULL
   const int64_t* dst_rp;
   int32_t* dst_col;
   float* dst_dist;

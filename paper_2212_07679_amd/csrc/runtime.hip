@@ -142,7 +142,7 @@ struct Ctl {
   unsigned long long accepted;  // neighbour entries (clustering mode)
   unsigned long long nnz;       // neighbour entries (lists mode)
   int bad;
-  int pad1;
+  int scan_err;  // a look-back scan's wait did not end (not expected)
 };
 
 struct HostCtl {
@@ -233,11 +233,12 @@ static const int32_t* window_cells(Index& ix) {
   return ix.wcells.as<int32_t>();
 }
 
-// Operands and start values of a 16-bit screen for one query call: for a
-// self-query the start values now, for out-of-sample queries the request in
-// *op that the gather into score order carries out.
-static MixedDev prepare_mixed(Index& ix, int kind, double R2, bool self, int64_t m, uint16_t* qop, float* cthr,
-                              QueryOperands* op, hipStream_t s) {
+// Operands and start values of a 16-bit screen for one query call: for
+// out-of-sample queries the request in *op that the gather into score order
+// carries out; for a self-query the bound its own start-value pass takes
+// (*self_bound).
+static MixedDev prepare_mixed(Index& ix, int kind, double R2, bool self, uint16_t* qop, float* cthr,
+                              QueryOperands* op, MixedBound* self_bound) {
   MixedOperands& mo = ix.mixed[mixed_slot(kind)];
   const MixedBound mb = mixed_bound(kind, mo.ka, ix.d, R2, ix.max_norm);
   MixedDev mx{};
@@ -249,7 +250,7 @@ static MixedDev prepare_mixed(Index& ix, int kind, double R2, bool self, int64_t
   mx.cthr = cthr;
   if (self) {
     mx.qop = mo.qself.as<uint16_t>();
-    launch_mixed_qprep_self(ix.ys.as<float>(), ix.n, ix.d, mb, cthr, s);
+    *self_bound = mb;
   } else {
     mx.qop = qop;
     op->mode = kQOp16;
@@ -260,24 +261,85 @@ static MixedDev prepare_mixed(Index& ix, int kind, double R2, bool self, int64_t
     op->qop = qop;
     op->cthr = cthr;
   }
-  (void)m;
   return mx;
 }
 
 // Query rows and start values of the fp32 screen for one query call (as
-// prepare_mixed: now for a self-query, through *op otherwise).
-static void prepare_fp32(Index& ix, double R2, bool self, int64_t m, float* vq, QueryOperands* op, hipStream_t s) {
+// prepare_mixed).
+static void prepare_fp32(Index& ix, double R2, bool self, float* vq, QueryOperands* op, MixedBound* self_bound) {
   // K = d rounded up to the two coordinates of one fp32 matrix instruction
   const MixedBound vb = mixed_bound(kOpF32, 2 * ((ix.d + 1) / 2), ix.d, R2, ix.max_norm);
   if (self) {
-    launch_mfma32_qprep_self(ix.ys.as<float>(), ix.n, ix.d, vb, vq, s);
+    *self_bound = vb;
   } else {
     op->mode = kQOp32;
     op->DV = mfma32_query_floats(ix.d);
     op->b = vb;
     op->vq = vq;
   }
-  (void)m;
+}
+
+static uint64_t bits_of(double x) {
+  uint64_t u;
+  std::memcpy(&u, &x, sizeof u);
+  return u;
+}
+
+// The graph slot of a call with key k: the slot that saw k before (its use
+// count raised), else the least recently used slot, emptied and given k.
+static QueryGraph* query_graph(Index& ix, const GraphKey& k) {
+  const uint64_t now = ++ix.qgraph_clock;
+  for (QueryGraph& g : ix.qgraphs)
+    if (g.uses > 0 && std::memcmp(g.key.v, k.v, sizeof k.v) == 0) {
+      ++g.uses;
+      g.stamp = now;
+      return &g;
+    }
+  QueryGraph* v = &ix.qgraphs[0];
+  for (QueryGraph& g : ix.qgraphs)
+    if (g.stamp < v->stamp) v = &g;
+  destroy_query_graph(*v);
+  v->key = k;
+  v->uses = 1;
+  v->stamp = now;
+  return v;
+}
+
+// Runs body's launches on the index's stream: by replaying *g when it holds
+// a graph, else by capturing them into *g and replaying that when capture
+// is set, else directly.  An instantiation the runtime refuses falls back to
+// the direct launches.
+template <typename F>
+static void run_captured(Index& ix, hipGraphExec_t* g, bool capture, F&& body) {
+  hipStream_t s = ix.arena.stream();
+  if (g && *g) {
+    SNN_HIP(hipGraphLaunch(*g, s));
+    return;
+  }
+  if (!g || !capture) {
+    body();
+    return;
+  }
+  SNN_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipGraph_t graph = nullptr;
+  try {
+    body();
+  } catch (...) {
+    (void)hipStreamEndCapture(s, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  SNN_HIP(hipStreamEndCapture(s, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    body();
+    return;
+  }
+  *g = exec;
+  SNN_HIP(hipGraphLaunch(exec, s));
 }
 
 // Clustering request: the self-query's accepted pairs go to DBSCAN instead
@@ -392,9 +454,12 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       unsigned long long* wpart;
       char* scan_scratch;
       Ctl* ctl;
-      int32_t* row_cnt;  // per query slot
-      int64_t* rp_s;     // slot-order row offsets
-      int32_t* cnt_o;    // per caller row
+      unsigned long long* lb_buckets;  // look-back scan states (zeroed with ctl)
+      unsigned long long* lb_rows;     // (two: slot-order and caller-order rows)
+      int ctl_words;                   // words zeroed at the call's start
+      int32_t* row_cnt;                // per query slot
+      int64_t* rp_s;                   // slot-order row offsets
+      int32_t* cnt_o;                  // per caller row
       int32_t* lists;
       uint16_t* qop;
       float* cthr;
@@ -420,7 +485,14 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     p.wpart = c.take<unsigned long long>(kWindowMaxBlocks);
     p.scan_scratch = c.take<char>(std::max({scan_scratch_bytes(ntiles), scan_scratch_bytes(std::max<int64_t>(m, 1)),
                                             scan_scratch_bytes(nbuckets)}));
-    p.ctl = c.take<Ctl>(1);
+    {
+      const size_t wc = sizeof(Ctl) / 8, wb = lookback_words(nbuckets), wr = lookback_words(m);
+      unsigned long long* region = c.take<unsigned long long>(wc + wb + 2 * wr);
+      p.ctl = reinterpret_cast<Ctl*>(region);
+      p.lb_buckets = region + wc;
+      p.lb_rows = region + wc + wb;
+      p.ctl_words = (int)(wc + wb + 2 * wr);
+    }
     p.row_cnt = c.take<int32_t>(std::max<int64_t>(m, 1));
     p.rp_s = c.take<int64_t>(m + 1);
     p.cnt_o = c.take<int32_t>(std::max<int64_t>(m, 1));
@@ -435,40 +507,18 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   Carver carve(ix.ws[0].ptr);
   auto P = plan_query(carve);
 
-  const bool sort_queries = !self && m > 0;
-  launch_query_init(reinterpret_cast<unsigned long long*>(P.ctl), (int)(sizeof(Ctl) / 8), P.row_cnt, m,
-                    sort_queries ? P.hist : nullptr, nbuckets, P.tlo, P.thi, ntiles, s);
-
+  // ---- host values of every launch of the call
   // screen operands and start values: built by the gather for out-of-sample
   // queries, by their own pass for self-queries
   QueryOperands qop{};
   MixedDev mx{};
-  if (mix16) mx = prepare_mixed(ix, sp.kind, R2, self, m, P.qop, P.cthr, &qop, s);
-  if (prec == SNN_PREC_FP32) prepare_fp32(ix, R2, self, m, P.vq, &qop, s);
-
-  const double* q64;
-  const int32_t* qorig;
-  const double* qa;
-  const double* qn;
-  if (!self) {
-    if (m > 0) {
-      // queries into score order by a counting sort on a uniform score grid
-      launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), ix.key.as<double>(), (int)n,
-                        nbuckets, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, &P.ctl->bad, P.scan_scratch, s);
-      launch_query_gather(ix.dtype, Q, m, d, ix.dp, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, P.q64, P.qorig, P.qa,
-                          P.qn, ix.mu.as<double>(), qop, s);
-    }
-    q64 = P.q64;
-    qorig = P.qorig;
-    qa = P.qa;
-    qn = P.qn;
-  } else {
-    q64 = ix.p64.as<double>();
-    qorig = ix.perm.as<int32_t>();
-    qa = ix.key.as<double>();
-    launch_self_qnorm(ix.ynorm.as<float>(), n, P.qn, s);
-    qn = P.qn;
-  }
+  MixedBound self_bound{};
+  if (mix16) mx = prepare_mixed(ix, sp.kind, R2, self, P.qop, P.cthr, &qop, &self_bound);
+  if (prec == SNN_PREC_FP32) prepare_fp32(ix, R2, self, P.vq, &qop, &self_bound);
+  const double* q64 = self ? ix.p64.as<double>() : P.q64;
+  const int32_t* qorig = self ? ix.perm.as<int32_t>() : P.qorig;
+  const double* qa = self ? ix.key.as<double>() : P.qa;
+  const double* qn = P.qn;
 
   // W_q = R ||v|| (1 + 4 gamma_{d+3}) + key_eps + eps_q, eps_q = c ||y_q||
   const double u32 = std::ldexp(1.0, -24);
@@ -476,9 +526,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const double eps_scale = 1.01 * (u32 + gamma64(d + 2)) * (1.0 + u32) * ix.vnorm;
   // self-queries scan each unordered pair once (S is exactly symmetric)
   const int sym = (self && !o.full_self_scan) ? 1 : 0;
-  const int32_t* cells = window_cells(ix);
-  launch_windows(ix.key.as<double>(), (int)n, cells, ix.wcells_n, qa, qn, m, w_base, eps_scale, T, sym, P.lo, P.hi,
-                 P.tlo, P.thi, P.wpart, s);
+  const int32_t* cells = window_cells(ix);  // built on the index's first query
   // query slots per wavefront (stats): the matrix-core screens evaluate
   // whole 32-query blocks, the float64 screen one query at a time
   const int qpw = mix16                   ? mixed_queries_per_wave(operand_ka(sp.kind, d), sp.kind == kOpF16)
@@ -487,8 +535,6 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   // chunk-major work order inside groups of G score-adjacent tiles (L2 reuse)
   const int G = prec == SNN_PREC_FP64 ? 16 : 8;
   const int ngroups = (ntiles + G - 1) / G;
-  launch_tile_plan(P.tlo, P.thi, ntiles, CH, prec == SNN_PREC_FP64 ? 1 : 32, sym, P.units, G, P.unit_off, P.gbase,
-                   T, m, qpw, st ? &P.ctl->executed : nullptr, P.wpart, window_blocks(m), &P.ctl->pairs_window, s);
 
   QueryDev qd{};
   qd.G = G;
@@ -515,7 +561,6 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   qd.nxcd = di.xcds;
   qd.sym = sym;
 
-
   // survivors: capacity remembered on the index, grown on overflow
   // bytes per survivor: the pair, and per result row, column, distance, slot
   // (clustering: the pair and one accepted mark)
@@ -523,47 +568,137 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const size_t per_bytes = db ? 12 : 8 + 16 * (size_t)per;
   long long cap = std::max<long long>(1 << 16, (long long)(ix.ws[1].bytes / per_bytes));
   HostCtl hc{};
+  Survivors sv{};
   uint64_t* stage_key = nullptr;  // neighbour keys in slot-order rows
   RowMove mv{};                   // their move to the caller's rows
-  for (int attempt = 0;; ++attempt) {
+  // The survivor list and the staging rows are carved before any launch, so
+  // that every launch of the call is fixed by the values above.  The rows of
+  // up to 16 neighbours are assembled before the sizes are read back, so the
+  // device does not wait for the host in between: the staging rows hold
+  // every neighbour this attempt can produce (cap x per), the scatter does
+  // nothing when the survivor list overflowed, and the moves write nothing
+  // when the rows exceed the caller's capacity (the host then retries or
+  // reports it).
+  auto carve_survivors = [&]() {
     // five arrays, each padded to 256 bytes by the carver
     const size_t need = (size_t)cap * per_bytes + 2048;
     ix.ws[1].ensure(ix.arena, need);
     cap = (long long)((ix.ws[1].bytes - 2048) / per_bytes);
     Carver sc(ix.ws[1].ptr);
-    Survivors sv{};
+    sv = Survivors{};
     sv.per = per;
     sv.pairs = sc.take<int2>(cap);
     sv.res_q = sc.take<int32_t>(cap * per);
     sv.res_key = db ? nullptr : sc.take<uint64_t>(cap * per);
     sv.res_slot = db ? nullptr : sc.take<int32_t>(cap * per);
-    // recompute cap to fit the carve exactly
     sv.cap = cap;
     sv.count = &P.ctl->survivors;
     qd.sink.out = sv.pairs;
     qd.sink.counter = sv.count;
     qd.sink.cap = cap;
+    if (!db) {
+      const size_t stage_n = (size_t)cap * per;
+      ix.ws[3].ensure(ix.arena, stage_n * 8 + 512);
+      Carver gc(ix.ws[3].ptr);
+      stage_key = gc.take<uint64_t>(stage_n);
+      mv = RowMove{P.rp_s, stage_key, qorig, out->row_ptr, out->col, out->dist, &P.ctl->nnz,
+                   (unsigned long long)out->nnz_cap};
+    }
+  };
+  carve_survivors();
+  const int per_cu = mix16                   ? mixed_blocks_per_cu(mx.KA, mx.KB, mx.f16 != 0)
+                     : prec == SNN_PREC_FP32 ? mfma32_blocks_per_cu(d)
+                                             : fp64_blocks_per_cu(ix.dp);
+  const int grid = std::max(di.xcds, (di.cus * per_cu / di.xcds) * di.xcds);
+
+  // ---- the launches before the screen: queries into score order, their
+  // operands, windows and the tile plan
+  const bool sort_queries = !self && m > 0;
+  auto enqueue_pre = [&]() {
+    launch_query_init(reinterpret_cast<unsigned long long*>(P.ctl), P.ctl_words, P.row_cnt, m,
+                      sort_queries ? P.hist : nullptr, nbuckets, P.tlo, P.thi, ntiles, s);
+    if (self && mix16) launch_mixed_qprep_self(ix.ys.as<float>(), ix.n, ix.d, self_bound, P.cthr, s);
+    if (self && prec == SNN_PREC_FP32) launch_mfma32_qprep_self(ix.ys.as<float>(), ix.n, ix.d, self_bound, P.vq, s);
+    if (sort_queries) {
+      // queries into score order by a counting sort on a uniform score grid
+      launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), ix.key.as<double>(), (int)n,
+                        nbuckets, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, &P.ctl->bad, P.lb_buckets,
+                        &P.ctl->scan_err, s);
+      launch_query_gather(ix.dtype, Q, m, d, ix.dp, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, P.q64, P.qorig, P.qa,
+                          P.qn, ix.mu.as<double>(), qop, s);
+    }
+    if (self) launch_self_qnorm(ix.ynorm.as<float>(), n, P.qn, s);
+    launch_windows(ix.key.as<double>(), (int)n, cells, ix.wcells_n, qa, qn, m, w_base, eps_scale, T, sym, P.lo,
+                   P.hi, P.tlo, P.thi, P.wpart, s);
+    launch_tile_plan(P.tlo, P.thi, ntiles, CH, prec == SNN_PREC_FP64 ? 1 : 32, sym, P.units, G, P.unit_off,
+                     P.gbase, T, m, qpw, st ? &P.ctl->executed : nullptr, P.wpart, window_blocks(m),
+                     &P.ctl->pairs_window, s);
+  };
+  // ---- the screen
+  auto enqueue_screen = [&]() {
+    if (m <= 0) return;
+    if (mix16)
+      launch_cand_mfma(qd, mx, grid, s);
+    else if (prec == SNN_PREC_FP32)
+      launch_cand_mfma32(qd, Mfma32Dev{P.vq, mfma32_query_floats(d), d, ix.vcand.as<float>(), ix.h.as<float>()}, grid,
+                         s);
+    else
+      launch_cand_fp64(qd, grid, s);
+  };
+  // ---- the launches after the screen: recheck, row offsets, the
+  // neighbours into their rows and the rows of up to 16 neighbours sorted
+  // into the caller's rows (longer rows follow the read-back)
+  auto enqueue_post = [&]() {
+    // grid of the survivor passes from the list's capacity (a grid-stride
+    // loop: few workgroups for the short lists of sparse outputs, where the
+    // dispatch of thousands of idle ones would dominate)
+    const int sgrid = (int)std::min<long long>(16LL * di.cus, std::max<long long>(2LL * di.cus, cap / 2048));
+    launch_recheck(qd, sv, ix.dtype, ix.po.ptr, self, P.row_cnt, sgrid, s);
+    // slot-order row offsets (where the neighbours are assembled) with the
+    // counts in the caller's order, the longest row, the total and the rows
+    // by length class; then the caller's row offsets
+    launch_rows_scan(P.row_cnt, m, P.rp_s, P.lb_rows, &P.ctl->scan_err,
+                     RowsExtra{qorig, P.cnt_o, &P.ctl->row_max, &P.ctl->nnz, P.lists, P.ctl->list_counts}, s);
+    launch_rows_scan(P.cnt_o, m, out->row_ptr, P.lb_rows + lookback_words(m), &P.ctl->scan_err, RowsExtra{}, s);
+    launch_scatter(sv, P.rp_s, stage_key, sgrid, s);
+    launch_row_sort_short(mv, P.lists, P.ctl->list_counts, s);
+  };
+
+  // A call repeated with the same inputs, outputs and workspace (a serving
+  // loop) replays the launch sequences before and after the screen from
+  // graphs captured on its second occurrence: one launch each instead of
+  // about fifteen.
+  QueryGraph* qg = nullptr;
+  if (!db && s) {  // (the null stream cannot be captured)
+    GraphKey gk{};
+    const uint64_t fields[] = {reinterpret_cast<uint64_t>(Q), (uint64_t)m, bits_of(R), (uint64_t)self,
+                               (uint64_t)o.precision, (uint64_t)o.mixed_terms, (uint64_t)o.tile_q,
+                               (uint64_t)o.tile_c, (uint64_t)o.full_self_scan, (uint64_t)o.metric,
+                               reinterpret_cast<uint64_t>(out->row_ptr), reinterpret_cast<uint64_t>(out->col),
+                               reinterpret_cast<uint64_t>(out->dist), (uint64_t)out->nnz_cap, st ? 1ull : 0ull,
+                               ix.epoch, reinterpret_cast<uint64_t>(ix.ws[0].ptr), (uint64_t)ix.ws[0].bytes,
+                               reinterpret_cast<uint64_t>(ix.ws[1].ptr), (uint64_t)ix.ws[1].bytes,
+                               reinterpret_cast<uint64_t>(ix.ws[3].ptr), (uint64_t)ix.ws[3].bytes, (uint64_t)cap,
+                               reinterpret_cast<uint64_t>(s)};
+    static_assert(sizeof(fields) <= sizeof(gk.v), "graph key too long");
+    std::memcpy(gk.v, fields, sizeof(fields));
+    qg = query_graph(ix, gk);
+  }
+  run_captured(ix, qg ? &qg->pre : nullptr, qg && qg->uses > 1, enqueue_pre);
+
+  for (int attempt = 0;; ++attempt) {
     if (attempt > 0) {
+      carve_survivors();
       launch_fill_u64(P.ctl->counters, kMaxXcd, 0ull, s);
       launch_fill_u64(&P.ctl->survivors, 1, 0ull, s);
       launch_fill_u64(&P.ctl->accepted, 1, 0ull, s);
       launch_fill_u64(P.ctl->list_counts, 8, 0ull, s);
+      launch_fill_u64(&P.ctl->row_max, 1, 0ull, s);
+      launch_fill_u64(P.lb_rows, 2 * (int64_t)lookback_words(m), 0ull, s);
       launch_fill_i32(P.row_cnt, m, 0, s);
     }
-    const int per_cu = mix16                   ? mixed_blocks_per_cu(mx.KA, mx.KB, mx.f16 != 0)
-                       : prec == SNN_PREC_FP32 ? mfma32_blocks_per_cu(d)
-                                               : fp64_blocks_per_cu(ix.dp);
-    const int grid = std::max(di.xcds, (di.cus * per_cu / di.xcds) * di.xcds);
     if (st) SNN_HIP(hipEventRecord(ev[1], s));
-    if (m > 0) {
-      if (mix16)
-        launch_cand_mfma(qd, mx, grid, s);
-      else if (prec == SNN_PREC_FP32)
-        launch_cand_mfma32(qd, Mfma32Dev{P.vq, mfma32_query_floats(d), d, ix.vcand.as<float>(), ix.h.as<float>()}, grid,
-                           s);
-      else
-        launch_cand_fp64(qd, grid, s);
-    }
+    enqueue_screen();
     if (st) SNN_HIP(hipEventRecord(ev[2], s));
     if (db) {
       launch_recheck_edges(qd, sv, ix.dtype, ix.po.ptr, P.row_cnt, &P.ctl->accepted, di.cus * 16, s);
@@ -587,40 +722,15 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       ix.ws[1].reset(ix.arena);
       continue;
     }
-    // grid of the survivor passes from the list's capacity (a grid-stride
-    // loop: few workgroups for the short lists of sparse outputs, where the
-    // dispatch of thousands of idle ones would dominate)
-    const int sgrid = (int)std::min<long long>(16LL * di.cus, std::max<long long>(2LL * di.cus, cap / 2048));
-    launch_recheck(qd, sv, ix.dtype, ix.po.ptr, self, P.row_cnt, sgrid, s);
-    // row offsets in slot order (where the neighbours are assembled) and in
-    // the caller's order (where each row ends up)
-    exclusive_scan_i32_to_i64(P.row_cnt, P.rp_s, m, P.scan_scratch, s);
-    // counts in the caller's order, the longest row, the total and the rows
-    // by length class in one pass
-    launch_rows_stats(P.rp_s, m, qorig, P.cnt_o, &P.ctl->row_max, &P.ctl->nnz, P.lists, P.ctl->list_counts, s);
-    exclusive_scan_i32_to_i64(P.cnt_o, out->row_ptr, m, P.scan_scratch, s);
-    // The assembly of rows of up to 16 neighbours is enqueued before the
-    // sizes are read back, so the device does not wait for the host in
-    // between: the staging rows hold every neighbour this attempt can
-    // produce (cap x per), the scatter does nothing when the survivor list
-    // overflowed, and the moves write nothing when the rows exceed the
-    // caller's capacity (the host then retries or reports it, as below).
-    {
-      const size_t stage_n = (size_t)cap * per;
-      ix.ws[3].ensure(ix.arena, stage_n * 8 + 512);
-      Carver gc(ix.ws[3].ptr);
-      stage_key = gc.take<uint64_t>(stage_n);
-    }
-    launch_scatter(sv, P.rp_s, stage_key, sgrid, s);
-    mv = RowMove{P.rp_s, stage_key, qorig, out->row_ptr, out->col, out->dist, &P.ctl->nnz,
-                 (unsigned long long)out->nnz_cap};
-    launch_row_sort_short(mv, P.lists, P.ctl->list_counts, s);
+    // (a retry's larger survivor list is not the captured call's)
+    run_captured(ix, qg && attempt == 0 ? &qg->post : nullptr, qg && qg->uses > 1, enqueue_post);
     SNN_HIP(hipMemcpyAsync(&hc.ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     // the call's end unless longer rows follow the read-back
     if (st) SNN_HIP(hipEventRecord(ev[3], s));
     SNN_HIP(hipStreamSynchronize(s));
     hc.nnz = (int64_t)hc.ctl.nnz;
     if (hc.ctl.bad) fail(SNN_EINVAL, "Q contains NaN or Inf");
+    if (hc.ctl.scan_err) fail(SNN_EDEVICE, "a single-pass scan did not complete");
     if ((long long)hc.ctl.survivors <= cap) {
       out->nnz = hc.nnz;
       if (st) {
@@ -733,11 +843,11 @@ static void debug_screen(Index& ix, const void* Q, int64_t m, double R, const sn
       uint32_t *ukey, *val, *hist;
       double *qa_in, *qn_in, *q64, *qa, *qn;
       int32_t *qorig, *row_cnt;
-      char* scan;
       uint16_t* qop;
       float *cthr, *vq;
     } p;
-    p.ctl = c.take<unsigned long long>(1);
+    // ints: bad, scan error; then the bucket scan's look-back state
+    p.ctl = c.take<unsigned long long>(1 + lookback_words(nb));
     p.ukey = c.take<uint32_t>(m);
     p.val = c.take<uint32_t>(m);
     p.hist = c.take<uint32_t>(nb);
@@ -748,7 +858,6 @@ static void debug_screen(Index& ix, const void* Q, int64_t m, double R, const sn
     p.qn = c.take<double>(m);
     p.qorig = c.take<int32_t>(m);
     p.row_cnt = c.take<int32_t>(m);
-    p.scan = c.take<char>(scan_scratch_bytes(nb));
     p.qop = c.take<uint16_t>(mix16 ? (size_t)m * lay->ka : 1);
     p.cthr = c.take<float>(m);
     p.vq = c.take<float>(mix16 ? 1 : (size_t)m * lay->ka);
@@ -759,15 +868,17 @@ static void debug_screen(Index& ix, const void* Q, int64_t m, double R, const sn
   ScopedAlloc mem(ix.arena, probe.off + 256);
   Carver carve(mem.get());
   auto P = plan(carve);
-  launch_query_init(P.ctl, 1, P.row_cnt, m, P.hist, nb, nullptr, nullptr, 0, s);
+  launch_query_init(P.ctl, (int)(1 + lookback_words(nb)), P.row_cnt, m, P.hist, nb, nullptr, nullptr, 0, s);
   QueryOperands qop{};
   MixedDev mx{};
+  MixedBound unused{};
   if (mix16)
-    mx = prepare_mixed(ix, sp.kind, R2, false, m, P.qop, P.cthr, &qop, s);
+    mx = prepare_mixed(ix, sp.kind, R2, false, P.qop, P.cthr, &qop, &unused);
   else
-    prepare_fp32(ix, R2, false, m, P.vq, &qop, s);
+    prepare_fp32(ix, R2, false, P.vq, &qop, &unused);
   launch_query_keys(ix.dtype, Q, m, d, ix.mu.as<double>(), ix.v.as<double>(), ix.key.as<double>(), (int)n, nb, P.ukey,
-                    P.val, P.hist, P.qa_in, P.qn_in, reinterpret_cast<int*>(P.ctl), P.scan, s);
+                    P.val, P.hist, P.qa_in, P.qn_in, reinterpret_cast<int*>(P.ctl), P.ctl + 1,
+                    reinterpret_cast<int*>(P.ctl) + 1, s);
   launch_query_gather(ix.dtype, Q, m, d, ix.dp, P.ukey, P.val, P.hist, P.qa_in, P.qn_in, P.q64, P.qorig, P.qa, P.qn,
                       ix.mu.as<double>(), qop, s);
   if (mix16) {
@@ -785,10 +896,11 @@ static void debug_screen(Index& ix, const void* Q, int64_t m, double R, const sn
                              hipMemcpyDeviceToDevice, s));
     SNN_HIP(hipMemcpyAsync(B, ix.ys.ptr, sizeof(float) * n * d, hipMemcpyDeviceToDevice, s));
   }
-  int flags[2] = {0, 0};  // NaN/Inf flag, padding
+  int flags[2] = {0, 0};  // NaN/Inf flag, scan error
   SNN_HIP(hipMemcpyAsync(flags, P.ctl, sizeof(flags), hipMemcpyDeviceToHost, s));
   SNN_HIP(hipStreamSynchronize(s));
   if (flags[0]) fail(SNN_EINVAL, "Q contains NaN or Inf");
+  if (flags[1]) fail(SNN_EDEVICE, "a single-pass scan did not complete");
 }
 
 }  // namespace snn
@@ -814,6 +926,7 @@ static void free_index(snn_index_s* ix) {
   ix->wcells.reset(a);
   for (hipEvent_t& e : ix->ev)
     if (e) (void)hipEventDestroy(e);
+  for (QueryGraph& g : ix->qgraphs) destroy_query_graph(g);
   for (auto& w : ix->ws) w.reset(a);
   delete ix;
 }

@@ -140,6 +140,24 @@ struct MixedOperands {
 // Slot of an operand kind (OperandKind of query_plan.h: bf16, bf16 hi/lo, fp16) in Index::mixed.
 inline int mixed_slot(int kind) { return kind == 3 ? 1 : (kind == 4 ? 2 : 0); }
 
+// Launch sequences of a repeated query call captured as graphs (runtime.hip):
+// the key holds every value the launches depend on.
+struct GraphKey {
+  uint64_t v[32];
+};
+struct QueryGraph {
+  GraphKey key{};
+  hipGraphExec_t pre = nullptr;   // query order, operands, windows, tile plan
+  hipGraphExec_t post = nullptr;  // recheck to the rows of up to 16 neighbours
+  int uses = 0;                   // calls with this key since the slot was taken
+  uint64_t stamp = 0;             // last use (least recently used slot is reused)
+};
+inline void destroy_query_graph(QueryGraph& g) {
+  if (g.pre) (void)hipGraphExecDestroy(g.pre);
+  if (g.post) (void)hipGraphExecDestroy(g.post);
+  g = QueryGraph{};
+}
+
 struct Index {
   explicit Index(const snn_device& d) : arena(d) {}
   DeviceArena arena;
@@ -169,8 +187,12 @@ struct Index {
   double key_eps = 0;   // bound on |key_i - v.(p_i - mu)|
   int power_iters = 0;
 
+  uint64_t epoch = 0;   // raised by every change of the indexed rows
+
   // per-call workspace (grow-only)
   Buffer ws[16];
+  QueryGraph qgraphs[4];
+  uint64_t qgraph_clock = 0;
   hipEvent_t ev[4] = {};  // stats timing (created on first use)
   Buffer stats_host_dev;  // small device block read back at the end of a query
 };
@@ -189,6 +211,11 @@ size_t scan_scratch_bytes(int64_t n);
 // out[n] = total).  scratch: scan_scratch_bytes(n).
 void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* scratch, hipStream_t s);
 void exclusive_scan_u32(uint32_t* data, int64_t n, void* scratch, hipStream_t s);
+// Single-pass exclusive scans (decoupled look-back, one launch): state holds
+// lookback_words(n) 64-bit words that must be zero before the launch; *err
+// is set if a wait for an earlier tile did not end (not expected).
+size_t lookback_words(int64_t n);
+void lookback_scan_u32(uint32_t* data, int64_t n, unsigned long long* state, int* err, hipStream_t s);
 
 // k_index.hip
 void build_index(Index& ix, const void* X);
