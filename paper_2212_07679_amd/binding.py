@@ -327,11 +327,16 @@ class Index:
         # the stream context also selects the stream's device; allocations
         # made under it are tied to that stream by the caching allocator
         with torch.cuda.stream(self.stream):
-            row_ptr = torch.empty(m + 1, dtype=torch.int64, device=dev)
             cap = int(nnz_cap) if nnz_cap is not None else max(self._nnz_hint, 4 * m, 1024)
             for _ in range(3):
-                col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
-                dist = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+                # one allocation for the three outputs (row_ptr, col, dist)
+                c1 = max(cap, 1)
+                o1 = (8 * (m + 1) + 255) // 256 * 256
+                o2 = o1 + (4 * c1 + 255) // 256 * 256
+                buf = torch.empty(o2 + 4 * c1, dtype=torch.uint8, device=dev)
+                row_ptr = buf[:8 * (m + 1)].view(torch.int64)
+                col = buf[o1:o1 + 4 * c1].view(torch.int32)
+                dist = buf[o2:o2 + 4 * c1].view(torch.float32)
                 csr = snn_csr(row_ptr.data_ptr(), col.data_ptr(), dist.data_ptr(), cap, 0)
                 st = snn_stats()
                 if Q is None:

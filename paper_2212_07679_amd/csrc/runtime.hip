@@ -279,6 +279,15 @@ static void prepare_fp32(Index& ix, double R2, bool self, float* vq, QueryOperan
   }
 }
 
+// The control block read back through the index's pinned host copy: a
+// copy into pageable memory holds the host until the stream drains and then
+// needs a further staging copy, one into pinned memory is an ordinary
+// asynchronous copy that the call's synchronisation completes.
+static Ctl* pinned_ctl(Index& ix) {
+  if (!ix.host_ctl) SNN_HIP(hipHostMalloc(&ix.host_ctl, sizeof(Ctl), hipHostMallocDefault));
+  return static_cast<Ctl*>(ix.host_ctl);
+}
+
 static uint64_t bits_of(double x) {
   uint64_t u;
   std::memcpy(&u, &x, sizeof u);
@@ -568,6 +577,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const size_t per_bytes = db ? 12 : 8 + 16 * (size_t)per;
   long long cap = std::max<long long>(1 << 16, (long long)(ix.ws[1].bytes / per_bytes));
   HostCtl hc{};
+  Ctl* hctl = pinned_ctl(ix);
   Survivors sv{};
   uint64_t* stage_key = nullptr;  // neighbour keys in slot-order rows
   RowMove mv{};                   // their move to the caller's rows
@@ -702,8 +712,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     if (st) SNN_HIP(hipEventRecord(ev[2], s));
     if (db) {
       launch_recheck_edges(qd, sv, ix.dtype, ix.po.ptr, P.row_cnt, &P.ctl->accepted, di.cus * 16, s);
-      SNN_HIP(hipMemcpyAsync(&hc.ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+      SNN_HIP(hipMemcpyAsync(hctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
       SNN_HIP(hipStreamSynchronize(s));
+      hc.ctl = *hctl;
       if ((long long)hc.ctl.survivors <= cap) {
         ix.ws[3].ensure(ix.arena, dbscan_work_bytes(n));
         db->nclusters = dbscan_from_survivors(sv, n, P.row_cnt, ix.perm.as<int32_t>(), db->min_samples,
@@ -724,10 +735,11 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     }
     // (a retry's larger survivor list is not the captured call's)
     run_captured(ix, qg && attempt == 0 ? &qg->post : nullptr, qg && qg->uses > 1, enqueue_post);
-    SNN_HIP(hipMemcpyAsync(&hc.ctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    SNN_HIP(hipMemcpyAsync(hctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     // the call's end unless longer rows follow the read-back
     if (st) SNN_HIP(hipEventRecord(ev[3], s));
     SNN_HIP(hipStreamSynchronize(s));
+    hc.ctl = *hctl;
     hc.nnz = (int64_t)hc.ctl.nnz;
     if (hc.ctl.bad) fail(SNN_EINVAL, "Q contains NaN or Inf");
     if (hc.ctl.scan_err) fail(SNN_EDEVICE, "a single-pass scan did not complete");
@@ -927,6 +939,7 @@ static void free_index(snn_index_s* ix) {
   for (hipEvent_t& e : ix->ev)
     if (e) (void)hipEventDestroy(e);
   for (QueryGraph& g : ix->qgraphs) destroy_query_graph(g);
+  if (ix->host_ctl) (void)hipHostFree(ix->host_ctl);
   for (auto& w : ix->ws) w.reset(a);
   delete ix;
 }

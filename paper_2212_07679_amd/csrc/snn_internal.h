@@ -195,6 +195,7 @@ struct Index {
   uint64_t qgraph_clock = 0;
   hipEvent_t ev[4] = {};  // stats timing (created on first use)
   Buffer stats_host_dev;  // small device block read back at the end of a query
+  void* host_ctl = nullptr;  // pinned host copy of a query's control block (hipHostMalloc)
 };
 
 // ---------------------------------------------------------------- launchers
