@@ -42,7 +42,17 @@
 extern "C" {
 #endif
 
-typedef enum {
+/* Enumerations are int-sized.  Compiled as C++ they get int as their fixed
+ * underlying type, so any int a C caller passes is a value of the type and
+ * the library can reject it (without it, reading an out-of-range value of an
+ * enumeration is undefined in C++). */
+#ifdef __cplusplus
+#define SNN_ENUM(tag) enum tag : int
+#else
+#define SNN_ENUM(tag) enum tag
+#endif
+
+typedef SNN_ENUM(snn_status_e) {
   SNN_OK = 0,
   SNN_EINVAL = -1,    /* bad argument, or NaN/Inf in the data or queries */
   SNN_ENOMEM = -2,    /* the allocator returned NULL */
@@ -51,7 +61,7 @@ typedef enum {
   SNN_ENOTSUP = -5    /* valid but unsupported request */
 } snn_status;
 
-typedef enum { SNN_F32 = 0, SNN_F64 = 1 } snn_dtype;
+typedef SNN_ENUM(snn_dtype_e) { SNN_F32 = 0, SNN_F64 = 1 } snn_dtype;
 
 /* How candidate distances are screened (all give the same exact result).
  * FP64:  every window pair is decided by the normative rule in float64.
@@ -70,7 +80,7 @@ typedef enum { SNN_F32 = 0, SNN_F64 = 1 } snn_dtype;
  * The 16-bit and fp32 screens need the centred rows within fp32 range (norms
  * below 2^60; fp16: below 2^75); beyond it they return SNN_ENOTSUP and AUTO
  * takes FP64. */
-typedef enum {
+typedef SNN_ENUM(snn_precision_e) {
   SNN_PREC_FP64 = 0,
   SNN_PREC_MIXED = 1,
   SNN_PREC_AUTO = 2,
@@ -95,7 +105,7 @@ typedef enum {
  *     N(q) = { i : S(p_i, q) <= T } with S the normative sum above, and
  *     dist = fl32(2 asin(min(1, sqrt(S) / 2))) (the angle, radians) or
  *     fl32(S / 2) (the cosine distance), evaluated in float64. */
-typedef enum { SNN_METRIC_L2 = 0, SNN_METRIC_L1 = 1, SNN_METRIC_ANGULAR = 2, SNN_METRIC_COSINE = 3 } snn_metric;
+typedef SNN_ENUM(snn_metric_e) { SNN_METRIC_L2 = 0, SNN_METRIC_L1 = 1, SNN_METRIC_ANGULAR = 2, SNN_METRIC_COSINE = 3 } snn_metric;
 
 typedef struct {
   /* Device allocator; both NULL selects hipMalloc/hipFree.  alloc returns

@@ -16,7 +16,9 @@ from typing import Optional, Tuple
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsnn.so")
+# SNN_LIBRARY selects another build of the library (e.g. the sanitizer build
+# the CPU ABI tests load); default: the in-tree libsnn.so
+LIB_PATH = os.environ.get("SNN_LIBRARY") or os.path.join(_HERE, "libsnn.so")
 
 SNN_OK, SNN_EINVAL, SNN_ENOMEM, SNN_EDEVICE, SNN_EOVERFLOW, SNN_ENOTSUP = 0, -1, -2, -3, -4, -5
 SNN_F32, SNN_F64 = 0, 1
