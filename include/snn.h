@@ -251,6 +251,9 @@ typedef struct {
   int32_t operand_k;          /* bf16 operand row length of the screen */
   int32_t graph_timed_screen; /* 1 if the query graph times its screen kernel */
   float tuned_query_ms;       /* best query-pass time the autotuner measured (0: not tuned) */
+  int32_t fp32_instances;     /* instances on the fp32 matrix-core screen (d <= 16, chosen
+                                 when three bf16 terms would pass too many pairs) */
+  int32_t fp32_k;             /* their padded operand length (0: none) */
 } snn_batch_info_t;
 
 typedef struct snn_batch_s* snn_batch_t;

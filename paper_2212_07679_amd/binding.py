@@ -139,6 +139,8 @@ class snn_batch_info_t(ctypes.Structure):
         ("operand_k", ctypes.c_int32),
         ("graph_timed_screen", ctypes.c_int32),
         ("tuned_query_ms", ctypes.c_float),
+        ("fp32_instances", ctypes.c_int32),
+        ("fp32_k", ctypes.c_int32),
     ]
 
     def as_dict(self):

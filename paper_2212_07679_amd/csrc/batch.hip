@@ -74,7 +74,9 @@ struct BatchPlan {
   int64_t N = 0, M = 0, NR = 0, MS = 0, P64 = 0, Q64 = 0, GRAM = 0;
   int ntiles = 0, nchunks = 0, dmax = 1, vec_total = 0, ibits = 1;
   int KA = 16, T = 512, CH = 4096, G = 8, max_terms = 1;
-  int screen_grid = 0;
+  int NK32 = 0, D32 = 0, DV32 = 0;  // fp32 screen row shape (NK32 = 0: no fp32 instance)
+  int n16 = 0;                      // instances on the 16-bit screen
+  int screen_grid = 0, screen_grid32 = 0;
   int64_t sv_cap = 0, stage_cap = 0;
 
   // device memory
@@ -98,14 +100,20 @@ struct BatchPlan {
   int32_t* perm = nullptr;
   float* h = nullptr;
   uint16_t* cop = nullptr;
+  float* cop32 = nullptr;
   uint32_t *qkey = nullptr, *qval = nullptr, *qikey = nullptr, *qidx = nullptr;
   double *qa_in = nullptr, *qn_in = nullptr, *q64 = nullptr, *qa = nullptr, *qn = nullptr;
   int32_t* qorig = nullptr;
   uint16_t* qop = nullptr;
   float* cthr = nullptr;
+  float* vq32 = nullptr;
   int32_t *tlo = nullptr, *thi = nullptr, *units = nullptr;
   int64_t* group_off = nullptr;
   int32_t* gbase = nullptr;
+  // the fp32 screen's tile windows and work units (its own tile plan)
+  int32_t *tlo32 = nullptr, *thi32 = nullptr, *units32 = nullptr;
+  int64_t* group_off32 = nullptr;
+  int32_t* gbase32 = nullptr;
   void* scan_ws = nullptr;
   BatchCtl* ctl = nullptr;
   int32_t* row_cnt = nullptr;  // per query slot
@@ -137,6 +145,11 @@ struct BatchPlan {
     b.T = T;
     b.KA = KA;
     b.ntiles = ntiles;
+    b.NK32 = NK32;
+    b.D32 = D32;
+    b.DV32 = DV32;
+    b.cop32 = cop32;
+    b.vq32 = vq32;
     b.N = N;
     b.M = M;
     b.NR = NR;
@@ -258,6 +271,7 @@ void alloc_index(BatchPlan& p, bool with_operands) {
     p.p64 = c.take<double>(p.P64);
     p.h = c.take<float>(p.NR);
     p.cop = c.take<uint16_t>(with_operands ? (size_t)p.NR * p.KA : 1);
+    p.cop32 = c.take<float>(with_operands && p.NK32 ? (size_t)p.NR * p.D32 : 1);
   };
   Carver probe(nullptr);
   carve(probe);
@@ -282,11 +296,18 @@ void alloc_query(BatchPlan& p) {
     p.qorig = c.take<int32_t>(MS);
     p.qop = c.take<uint16_t>((size_t)MS * p.KA);
     p.cthr = c.take<float>(MS);
+    p.vq32 = c.take<float>(p.NK32 ? (size_t)MS * p.DV32 : 1);
     p.tlo = c.take<int32_t>(nt);
     p.thi = c.take<int32_t>(nt);
     p.units = c.take<int32_t>(nt);
     p.group_off = c.take<int64_t>(nt + 1);
     p.gbase = c.take<int32_t>(nt);
+    const int nt32 = p.NK32 ? nt : 1;
+    p.tlo32 = c.take<int32_t>(nt32);
+    p.thi32 = c.take<int32_t>(nt32);
+    p.units32 = c.take<int32_t>(nt32);
+    p.group_off32 = c.take<int64_t>(nt32 + 1);
+    p.gbase32 = c.take<int32_t>(nt32);
     p.scan_ws = c.take<char>(std::max(scan_scratch_bytes(nt + 1), scan_scratch_bytes(MS + 1)));
     p.ctl = c.take<BatchCtl>(1);
     p.row_cnt = c.take<int32_t>(MS);
@@ -378,9 +399,18 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
                      p.cthr, s);
   batch_windows(b, p.key, p.qa, p.qn, p.qorig, p.tlo, p.thi, p.ctl, s);
   const int ngroups = (p.ntiles + p.G - 1) / p.G;
+  // instances on the fp32 screen get a tile plan of their own (the tiles of
+  // the other screen empty in each plan), so each screen's persistent launch
+  // takes only its own work units
+  if (p.NK32) batch_split_tiles(b, p.tlo, p.thi, p.tlo32, p.thi32, s);
   launch_tile_plan(p.tlo, p.thi, p.ntiles, p.CH, 32, 0, p.units, p.G, p.group_off, p.gbase, p.T, p.MS, 1, nullptr,
                    nullptr, 0, nullptr, s);
   batch_executed(b, p.tlo, p.thi, p.T / 4, p.ctl, s);
+  if (p.NK32) {
+    launch_tile_plan(p.tlo32, p.thi32, p.ntiles, p.CH, 32, 0, p.units32, p.G, p.group_off32, p.gbase32, p.T, p.MS, 1,
+                     nullptr, nullptr, 0, nullptr, s);
+    batch_executed(b, p.tlo32, p.thi32, p.T / 4, p.ctl, s);
+  }
 
   QueryDev qd{};
   qd.m = p.MS;
@@ -407,7 +437,17 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   mx.KA = p.KA;
   mx.KB = p.KA;
   if (timed) batch_stamp(&p.ctl->stamp[0], s);
-  launch_cand_mfma(qd, mx, p.screen_grid, s);
+  if (p.n16) launch_cand_mfma(qd, mx, p.screen_grid, s);
+  if (p.NK32) {
+    QueryDev q32 = qd;
+    q32.tlo = p.tlo32;
+    q32.thi = p.thi32;
+    q32.units = p.units32;
+    q32.group_off = p.group_off32;
+    q32.gbase = p.gbase32;
+    q32.counters = p.ctl->counters32;
+    launch_cand_mfma32_batch(q32, Mfma32Dev{p.vq32, p.DV32, p.D32, p.cop32, p.h}, p.screen_grid32, s);
+  }
   if (timed) batch_stamp(&p.ctl->stamp[1], s);
 
   // neighbours are assembled in slot order (a tile's rows are contiguous),
@@ -722,23 +762,41 @@ BatchPlan* create_batch(const snn_device& devc, snn_dtype dtype, const snn_insta
     SNN_HIP(hipStreamSynchronize(s));
     int KA = 16;
     p.max_terms = 1;
+    p.NK32 = 0;
+    p.n16 = 0;
     for (int i = 0; i < count; ++i) {
       if (dyn[i].bad) fail(SNN_EINVAL, "instance " + std::to_string(i) + ": X contains NaN or Inf");
       BatchInst& b = p.inst[i];
       int t = o.mixed_terms;
       if (t == 0) {
-        // relative band of one bf16 term: 2 c_rep Y^2 / R^2 (see the single-instance policy)
+        // relative bands 2 c_rep Y^2 / R^2 of one and three bf16 terms (the
+        // single-instance policy): one term while its band is <= 0.1 R^2,
+        // three while theirs is <= 0.5 R^2, else the fp32 screen for d <= 16
         const double Y = std::sqrt(dyn[i].maxnorm2);
-        const double rel1 = b.R2 > 0 ? 2.0 * mixed_c_rep(1) * Y * Y / b.R2 : INFINITY;
-        t = (rel1 <= 0.1 || 3 * b.d > kBatchMaxD) ? 1 : 3;
+        auto band = [&](int kind) { return b.R2 > 0 ? 2.0 * mixed_c_rep(kind) * Y * Y / b.R2 : INFINITY; };
+        if (band(kOpBf16) <= 0.1 || 3 * b.d > kBatchMaxD)
+          t = 1;
+        else if (band(kOpBf16x3) <= 0.5 || b.d > mfma32_max_d() || !screen_in_range(kOpF32, Y))
+          t = 3;
+        else
+          t = 0;
       }
       if (t == 3 && 3 * b.d > kBatchMaxD) fail(SNN_ENOTSUP, "instance " + std::to_string(i) + ": 3 terms need d <= 42");
       b.terms = t;
-      p.max_terms = std::max(p.max_terms, t);
-      KA = std::max(KA, pad16(t * b.d));
+      if (t == 0) {
+        p.NK32 = std::max(p.NK32, (b.d + 1) / 2);
+      } else {
+        ++p.n16;
+        p.max_terms = std::max(p.max_terms, t);
+        KA = std::max(KA, pad16(t * b.d));
+      }
     }
+    p.D32 = 2 * p.NK32;
+    p.DV32 = p.NK32 ? mfma32_query_floats(p.D32) : 0;
     p.KA = KA;
     p.T = 4 * mixed_queries_per_wave(KA, false);  // bf16 operands
+    if (p.NK32 && p.T != mfma32_batch_queries_per_tile())
+      fail(SNN_EDEVICE, "internal: the fp32 and 16-bit screens need one tile size");
     p.CH = o.tile_c ? o.tile_c : 4096;
     p.G = o.tile_g ? o.tile_g : 8;
     plan_layout(p);
@@ -754,6 +812,10 @@ BatchPlan* create_batch(const snn_device& devc, snn_dtype dtype, const snn_insta
     const DeviceInfo& di = device_info(devc.device);
     const int per_cu = mixed_blocks_per_cu(p.KA, p.KA, false);
     p.screen_grid = std::max(di.xcds, (di.cus * per_cu / di.xcds) * di.xcds);
+    if (p.NK32) {
+      const int per_cu32 = mfma32_batch_blocks_per_cu(p.D32);
+      p.screen_grid32 = std::max(di.xcds, (di.cus * per_cu32 / di.xcds) * di.xcds);
+    }
     build_graphs(p);
     // first run: builds the index and sizes the survivor / staging arrays
     run_graphs(p, true, true);
@@ -811,6 +873,8 @@ snn_status snn_batch_info(snn_batch_t b, snn_batch_info_t* info) {
     info->operand_k = p.KA;
     info->graph_timed_screen = p.screen_timed ? 1 : 0;
     info->tuned_query_ms = p.last_tune_ms;
+    info->fp32_instances = p.count - p.n16;
+    info->fp32_k = p.D32;
   });
 }
 

@@ -30,7 +30,7 @@ struct BatchInst {
   int64_t n, m;
   int d;
   int dp;     // float64 row stride of the p64 / q64 rows (even, zero padded)
-  int terms;  // bf16 terms per coordinate of the screen operands (1 or 3)
+  int terms;  // screen operands: bf16 terms per coordinate (1 or 3), or 0 for the fp32 screen
   int ntiles;
   double R, R2;  // radius and fl(R*R)
   int64_t in_off;     // first data row in input order (prefix sum of n)
@@ -76,8 +76,8 @@ struct BatchCtl {
   unsigned long long executed;  // pairs the screen evaluated
   unsigned long long list_counts[8];
   unsigned long long qbad;  // NaN or Inf in some Q
-  unsigned long long stamp[2];  // device clock around the screen kernel
-  unsigned long long pad;
+  unsigned long long stamp[2];  // device clock around the screen kernels
+  unsigned long long counters32[kMaxXcd];  // work counters of the fp32 screen
 };
 
 struct BatchDev {
@@ -88,8 +88,15 @@ struct BatchDev {
   const int32_t* tile_inst;  // ntiles: owning instance of each tile
   int count;
   int T;   // query slots per tile
-  int KA;  // bf16 operand row length (multiple of 16), the same for all instances
+  int KA;  // bf16 operand row length (multiple of 16), the same for all bf16 instances
   int ntiles;
+  // fp32 screen (instances with terms == 0): D32 = 2 NK32 coordinates per
+  // row (zero padded), candidate blocks of 32 rows x NK32 slices of 64
+  // floats (slice s: coordinates 2s and 2s + 1 of the block's rows), query
+  // rows [y, 0 .., C_q at D32, 0 ..] of DV32 floats; NK32 = 0 without any
+  int NK32, D32, DV32;
+  float* cop32;
+  float* vq32;
   int64_t N;   // sum of n
   int64_t M;   // sum of m
   int64_t NR;  // sorted rows (sum of ceil32(n))
@@ -122,6 +129,9 @@ void batch_query_gather(snn_dtype dt, const BatchDev& b, const double* mu, const
                         hipStream_t s);
 void batch_windows(const BatchDev& b, const double* key, const double* qa, const double* qn, const int32_t* qorig,
                    int32_t* tlo, int32_t* thi, BatchCtl* ctl, hipStream_t s);
+// the tile windows of fp32-screen instances moved to (tlo32, thi32), the
+// others left in (tlo, thi); the tile of the other screen is empty in each
+void batch_split_tiles(const BatchDev& b, int32_t* tlo, int32_t* thi, int32_t* tlo32, int32_t* thi32, hipStream_t s);
 void batch_executed(const BatchDev& b, const int32_t* tlo, const int32_t* thi, int queries_per_wave, BatchCtl* ctl,
                     hipStream_t s);
 // row_cnt per query slot (rows are assembled in slot order)

@@ -373,7 +373,8 @@ __global__ void kb_finalize(BatchDev b) {
   dy.key_eps = 1.01 * (kU32 + gamma64d(d + 2)) * (1.0 + kU32) * Y * dy.vnorm;
   dy.w_base = in.R * dy.vnorm * (1.0 + 4.0 * gamma64d(d + 3)) + dy.key_eps;
   dy.eps_scale = 1.01 * (kU32 + gamma64d(d + 2)) * (1.0 + kU32) * dy.vnorm;
-  dy.mb = mixed_bound(in.terms, b.KA, d, in.R2, Y);
+  // terms 0: the fp32 screen (kOpF32) over D32 coordinates
+  dy.mb = mixed_bound(in.terms, in.terms == 0 ? b.D32 : b.KA, d, in.R2, Y);
 }
 
 // ---- rows into score order ---------------------------------------------------------
@@ -417,6 +418,13 @@ __global__ __launch_bounds__(kThreads) void kb_gather(BatchDev b, const double* 
       perm[R] = (int32_t)local;
       h[R] = (float)(0.5 * nn);
     }
+    if (in.terms == 0) {
+      // fp32 screen: coordinate k of row R at slice k / 2, lane R % 32 + 32 (k % 2)
+      float* blk32 = b.cop32 + (R / 32) * (int64_t)b.NK32 * 64 + (R % 32);
+      for (int k = sub; k < b.D32; k += kQG)
+        blk32[(k / 2) * 64 + 32 * (k % 2)] = k < d ? (float)((double)x[k] - m[k]) : 0.f;
+      continue;
+    }
     // candidate operands in the 32-row block layout of the matrix-core screen
     uint16_t* blk = cop + (R / 32) * (int64_t)KA * 32 + (R % 32) * 8;
     write_operand_row<T>(
@@ -435,6 +443,11 @@ __global__ void kb_pad_rows(BatchDev b, float* __restrict__ h, int32_t* __restri
     const int64_t R = in.row_base + r;
     h[R] = INFINITY;
     perm[R] = -1;
+    if (in.terms == 0) {
+      float* blk32 = b.cop32 + (R / 32) * (int64_t)b.NK32 * 64 + (R % 32);
+      for (int k = 0; k < b.D32; ++k) blk32[(k / 2) * 64 + 32 * (k % 2)] = 0.f;
+      continue;
+    }
     uint16_t* blk = cop + (R / 32) * (int64_t)KA * 32 + (R % 32) * 8;
     for (int c8 = 0; c8 < KA / 8; ++c8) *reinterpret_cast<uint4*>(blk + (int64_t)c8 * 256) = make_uint4(0, 0, 0, 0);
   }
@@ -486,6 +499,11 @@ __global__ __launch_bounds__(kThreads) void kb_query_pad(BatchDev b, int32_t* __
     qa[s] = 0.0;
     qn[s] = 0.0;
     cthr[s] = -INFINITY;
+    if (in.terms == 0) {  // fp32 query row: zeros, start value -inf
+      float* row32 = b.vq32 + s * b.DV32;
+      for (int k = 0; k < b.DV32; ++k) row32[k] = k == b.D32 ? -INFINITY : 0.f;
+      continue;
+    }
     uint4* row = reinterpret_cast<uint4*>(qop + s * KA);
     for (int c8 = 0; c8 < KA / 8; ++c8) row[c8] = make_uint4(0, 0, 0, 0);
   }
@@ -525,13 +543,20 @@ __global__ __launch_bounds__(kThreads) void kb_query_gather(
     // the start value allows for
 #pragma unroll
     for (int off = kQG / 2; off > 0; off >>= 1) nn += __shfl_xor(nn, off, kQG);
-    uint16_t* row = qop + s * KA;
-    for (int k = lane; k < KA; k += kQG) row[k] = operand_value<T>(in.terms, d, k, q, m, true);
+    const float c = screen_threshold(b.dyn[i].mb, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
+    if (in.terms == 0) {  // fp32 query row [y, 0 .., C_q at D32, 0 ..]
+      float* row32 = b.vq32 + s * b.DV32;
+      for (int k = lane; k < b.DV32; k += kQG)
+        row32[k] = k < d ? (float)((double)q[k] - m[k]) : (k == b.D32 ? c : 0.f);
+    } else {
+      uint16_t* row = qop + s * KA;
+      for (int k = lane; k < KA; k += kQG) row[k] = operand_value<T>(in.terms, d, k, q, m, true);
+    }
     if (lane == 0) {
       qorig[s] = (int32_t)g;
       qa[s] = qa_in[g];
       qn[s] = qn_in[g];
-      cthr[s] = screen_threshold(b.dyn[i].mb, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
+      cthr[s] = c;
     }
   }
 }
@@ -616,6 +641,22 @@ __global__ __launch_bounds__(kThreads) void kb_window(BatchDev b, const double* 
       atomicAdd(&ctl->pairs_window, c);
       atomicAdd(&ctl->flops, f);
     }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void kb_split_tiles(BatchDev b, int32_t* __restrict__ tlo,
+                                                          int32_t* __restrict__ thi, int32_t* __restrict__ tlo32,
+                                                          int32_t* __restrict__ thi32) {
+  const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tile >= b.ntiles) return;
+  if (b.inst[b.tile_inst[tile]].terms == 0) {
+    tlo32[tile] = tlo[tile];
+    thi32[tile] = thi[tile];
+    tlo[tile] = INT_MAX;
+    thi[tile] = INT_MIN;
+  } else {
+    tlo32[tile] = INT_MAX;
+    thi32[tile] = INT_MIN;
   }
 }
 
@@ -834,6 +875,12 @@ void batch_query_gather(snn_dtype dt, const BatchDev& b, const double* mu, const
 void batch_windows(const BatchDev& b, const double* key, const double* qa, const double* qn, const int32_t* qorig,
                    int32_t* tlo, int32_t* thi, BatchCtl* ctl, hipStream_t s) {
   kb_window<<<grid_for(b.MS, 1024), kThreads, 0, s>>>(b, key, qa, qn, qorig, tlo, thi, ctl);
+  SNN_LAUNCH_CHECK();
+}
+
+void batch_split_tiles(const BatchDev& b, int32_t* tlo, int32_t* thi, int32_t* tlo32, int32_t* thi32, hipStream_t s) {
+  if (b.ntiles <= 0) return;
+  kb_split_tiles<<<(b.ntiles + kThreads - 1) / kThreads, kThreads, 0, s>>>(b, tlo, thi, tlo32, thi32);
   SNN_LAUNCH_CHECK();
 }
 

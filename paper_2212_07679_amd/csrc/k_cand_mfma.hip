@@ -595,19 +595,24 @@ constexpr int kQB32 = 4;
 
 typedef void (*Mfma32Kernel)(QueryDev, Mfma32Dev);
 
-Mfma32Kernel pick_kernel32(int d) {
+// query blocks per wavefront: kQB32 for single queries, 2 in the batch
+// (whose tiles of 256 slots are shared with the 16-bit screen)
+template <int QB>
+Mfma32Kernel pick_kernel32_qb(int d) {
   switch ((d + 1) / 2) {
-    case 1: return k_cand_mfma32<1, kQB32>;
-    case 2: return k_cand_mfma32<2, kQB32>;
-    case 3: return k_cand_mfma32<3, kQB32>;
-    case 4: return k_cand_mfma32<4, kQB32>;
-    case 5: return k_cand_mfma32<5, kQB32>;
-    case 6: return k_cand_mfma32<6, kQB32>;
-    case 7: return k_cand_mfma32<7, kQB32>;
-    case 8: return k_cand_mfma32<8, kQB32>;
+    case 1: return k_cand_mfma32<1, QB>;
+    case 2: return k_cand_mfma32<2, QB>;
+    case 3: return k_cand_mfma32<3, QB>;
+    case 4: return k_cand_mfma32<4, QB>;
+    case 5: return k_cand_mfma32<5, QB>;
+    case 6: return k_cand_mfma32<6, QB>;
+    case 7: return k_cand_mfma32<7, QB>;
+    case 8: return k_cand_mfma32<8, QB>;
     default: return nullptr;
   }
 }
+Mfma32Kernel pick_kernel32(int d) { return pick_kernel32_qb<kQB32>(d); }
+constexpr int kQB32Batch = 2;
 
 typedef void (*MixedKernel)(QueryDev, MixedDev);
 
@@ -699,6 +704,23 @@ void launch_mfma32_qprep_self(const float* ys, int64_t n, int d, const MixedBoun
 // T must equal mfma32_queries_per_tile(); tile windows aligned to 32 rows.
 void launch_cand_mfma32(const QueryDev& q, const Mfma32Dev& x, int grid, hipStream_t s) {
   Mfma32Kernel k = pick_kernel32(x.d);
+  if (!k) fail(SNN_ENOTSUP, "fp32 matrix-core screen supports d <= 16");
+  k<<<grid, kThreads, 0, s>>>(q, x);
+  SNN_LAUNCH_CHECK();
+}
+
+int mfma32_batch_queries_per_tile() { return 4 * 32 * kQB32Batch; }
+int mfma32_batch_blocks_per_cu(int d) {
+  Mfma32Kernel k = pick_kernel32_qb<kQB32Batch>(d);
+  int nb = 0;
+  if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kThreads, 0) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  return nb;
+}
+void launch_cand_mfma32_batch(const QueryDev& q, const Mfma32Dev& x, int grid, hipStream_t s) {
+  Mfma32Kernel k = pick_kernel32_qb<kQB32Batch>(x.d);
   if (!k) fail(SNN_ENOTSUP, "fp32 matrix-core screen supports d <= 16");
   k<<<grid, kThreads, 0, s>>>(q, x);
   SNN_LAUNCH_CHECK();

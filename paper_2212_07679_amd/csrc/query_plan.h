@@ -315,6 +315,11 @@ int mfma32_blocks_per_cu(int d);
 void launch_mfma32_operands(const float* ys, int64_t n, int d, float* cop, hipStream_t s);
 void launch_mfma32_qprep_self(const float* ys, int64_t n, int d, const MixedBound& b, float* vq, hipStream_t s);
 void launch_cand_mfma32(const QueryDev& q, const Mfma32Dev& x, int grid, hipStream_t s);
+// the same screen with two query blocks per wavefront (tiles of
+// mfma32_batch_queries_per_tile() = 256 slots), for the batch
+int mfma32_batch_queries_per_tile();
+int mfma32_batch_blocks_per_cu(int d);
+void launch_cand_mfma32_batch(const QueryDev& q, const Mfma32Dev& x, int grid, hipStream_t s);
 
 // Test support (k_cand_mfma.hip): every pair's screen value of a small query,
 // D[qorig[q] n + j] (q < m score-order queries, j < n score-order

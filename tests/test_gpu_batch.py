@@ -140,6 +140,52 @@ def test_batch_replay_new_data(B):
     bt.close()
 
 
+def fp32_instances(seed=0):
+    """Low-dimensional instances whose radius is small against their extent
+    (three bf16 terms would pass too many pairs: the fp32 screen), next to
+    instances the 16-bit screen takes."""
+    g = np.random.default_rng([2212, 7679, 78, seed])
+    blobs = W.blobs3d(n=20_000, R=0.005, k=200, seed=7).P
+    cent = g.random((20, 16))
+    b16 = (cent[g.integers(0, 20, 4000)] + g.normal(0, 0.004, (4000, 16))).astype(np.float32)
+    q16 = (cent[g.integers(0, 20, 500)] + g.normal(0, 0.004, (500, 16))).astype(np.float32)
+    return [
+        (blobs, None, 0.005),                                               # fp32, self
+        (g.random((5000, 8)).astype(np.float32), g.random((400, 8)).astype(np.float32), 0.012),  # fp32
+        (b16, q16, 0.012),                                                  # fp32, d = 16
+        (g.random((3000, 32)).astype(np.float32), g.random((300, 32)).astype(np.float32), 1.1),  # 16-bit
+        (g.random((2000, 3)).astype(np.float32), g.random((250, 3)).astype(np.float32), 0.08),   # 16-bit
+        (g.random((700, 5)).astype(np.float32), np.zeros((0, 5), np.float32), 0.01),           # fp32, no queries
+        (g.random((1, 3)).astype(np.float32), g.random((7, 3)).astype(np.float32), 0.001),      # fp32, one point
+    ]
+
+
+def test_batch_fp32_screen_instances(B):
+    insts = fp32_instances()
+    refs = [oracle_of(P, Q, R) for P, Q, R in insts]
+    say(f"batch with fp32-screen instances: nnz {[int(r.row_ptr[-1]) for r in refs]}")
+    dev, bt = make_batch(B, insts)
+    info = bt.info()
+    say(f"  info {info}")
+    assert info["fp32_instances"] >= 4 and info["fp32_k"] >= 16
+    for rep in range(2):  # the first run at creation, then graph replays
+        res, st = bt.run(stats=True)
+        for i, (P, Q, R) in enumerate(insts):
+            check_same(res[i], refs[i], f"run {rep} instance {i} (n={P.shape[0]}, d={P.shape[1]}, R={R})")
+    # new data in the same buffers, index and query passes replayed
+    g = np.random.default_rng(9)
+    new = []
+    for (Pd, Qd, R), (P, Q, _) in zip(dev, insts):
+        P2 = (P + g.normal(0, 1e-3, P.shape)).astype(np.float32)
+        Pd.copy_(torch.from_numpy(P2))
+        new.append((P2, Q, R))
+    torch.cuda.synchronize()
+    res = bt.run()
+    for i, (P, Q, R) in enumerate(new):
+        check_same(res[i], oracle_of(P, Q, R), f"new data instance {i}")
+    bt.close()
+
+
 def test_batch_overflow_growth(B):
     # dense output: capacities of 1 force EOVERFLOW and the binding's regrowth
     insts = [(W.blobs3d(n=3000, R=0.2, seed=3).P, None, 0.2),
