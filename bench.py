@@ -746,6 +746,18 @@ def main():
               f"screen {screen_ms:.3f} ms, nnz {st['nnz']}, window pairs {st['pairs_window']}, "
               f"rechecked {st['pairs_recheck']}", file=sys.stderr, flush=True)
 
+    # one more call of the first precision with per-stage device times
+    # (SNN_PROFILE: launched kernel by kernel, outside the timed steps)
+    os.environ["SNN_PROFILE"] = "1"
+    try:
+        prof = run_query(idx, w, Qdev, precisions[0])[3]
+    finally:
+        del os.environ["SNN_PROFILE"]
+    stage_ms = dict(zip(("order", "window", "screen", "recheck", "assemble"), prof["stage_ms"]))
+    stage_ms["call"] = prof["total_ms"]
+    print(f"[bench] stages (profiled call): {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}",
+          file=sys.stderr, flush=True)
+
     # identical results across precisions
     for p in precisions[1:]:
         for x, y in zip(results[precisions[0]]["out"][:3], results[p]["out"][:3]):
@@ -802,6 +814,7 @@ def main():
         "recheck_fraction": st["pairs_recheck"] / max(st["pairs_window"], 1),
         "nnz": st["nnz"],
         "screen_ms": r["screen_ms"],
+        "stage_ms": stage_ms,
         "index_ms": index_ms,
         "index_hbm": index_hbm(w.n, w.d, w.P.dtype.itemsize, index_ms),
         "roofline": roofline(used, st["terms_used"], st, r["screen_ms"], w.d),

@@ -31,6 +31,21 @@
  * snn_last_error() describes it (thread-local, valid until the next call on
  * the thread).  No C++ exception crosses this interface.  Calls on one
  * index from several host threads must be serialised by the caller.
+ *
+ * Environment (read at every call).
+ *   SNN_LOG=0..3      lines on stderr: 0 none (default), 1 every failing
+ *                     call (status and message), 2 also one line per query
+ *                     and per batch run (sizes, screen chosen, pairs, nnz,
+ *                     device times when stats are asked for), 3 also
+ *                     workspace growth, survivor-list retries and graph
+ *                     capture.
+ *   SNN_PROFILE=1     snn_stats.stage_ms holds the device time of each
+ *                     stage of the query (SNN_STAGE_*); otherwise every
+ *                     entry is -1.  Profiled single-instance calls launch
+ *                     kernel by kernel (no replay of captured graphs, so
+ *                     that events can sit between the stages); a batch
+ *                     created with SNN_PROFILE=1 has clock stamps between
+ *                     the stages inside its query graph.
  */
 #ifndef SNN_H_
 #define SNN_H_
@@ -143,6 +158,18 @@ typedef struct {
   int64_t nnz;      /* out: number of neighbours (also on SNN_EOVERFLOW) */
 } snn_csr;
 
+/* Stages of a query (Algorithm 2) as timed under SNN_PROFILE=1. */
+enum {
+  SNN_STAGE_ORDER = 0,    /* steps 2-3: queries centred and projected, put
+                             into score order; their screen operands */
+  SNN_STAGE_WINDOW = 1,   /* step 4: candidate windows by eq. (lower), the
+                             tile plan */
+  SNN_STAGE_SCREEN = 2,   /* step 5: the candidate screen */
+  SNN_STAGE_RECHECK = 3,  /* step 6: survivors re-decided by the normative rule */
+  SNN_STAGE_ASSEMBLE = 4, /* row offsets, neighbours into rows, rows sorted by id */
+  SNN_STAGES = 5
+};
+
 typedef struct {
   int64_t pairs_window;   /* sum over queries of |J_q| (Algorithm 2, step 4) */
   int64_t pairs_executed; /* (query, candidate) pairs the screen evaluated */
@@ -154,6 +181,9 @@ typedef struct {
   double total_ms;        /* device time of the whole call */
   double flops_window;    /* algorithmic work of the window: sum over queries of
                              2 d |J_q| (the flop count of eq. (ip2) per candidate) */
+  double stage_ms[SNN_STAGES]; /* with SNN_PROFILE=1: device time of each stage
+                                  (SNN_STAGE_*), boundary to boundary on the
+                                  stream; -1 when not profiled */
 } snn_stats;
 
 typedef struct snn_index_s* snn_index_t;

@@ -88,10 +88,13 @@ class snn_stats(ctypes.Structure):
         ("screen_ms", ctypes.c_double),
         ("total_ms", ctypes.c_double),
         ("flops_window", ctypes.c_double),
+        ("stage_ms", ctypes.c_double * 5),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["stage_ms"] = list(self.stage_ms)
+        return d
 
 
 class snn_index_view(ctypes.Structure):

@@ -58,6 +58,7 @@ struct RunResult {
   std::vector<int64_t> nnz;
   int64_t total = 0;
   float graph_ms = 0, screen_ms = -1;
+  float stage_ms[SNN_STAGES] = {-1, -1, -1, -1, -1};
 };
 
 struct BatchPlan {
@@ -130,6 +131,7 @@ struct BatchPlan {
   // graphs: index pass, query pass, both
   hipGraphExec_t g_index = nullptr, g_query = nullptr, g_all = nullptr;
   bool screen_timed = false;  // device clock stamps bracket the screen in the query graph
+  bool profiled = false;      // ... and every stage of the query pass (SNN_PROFILE at creation)
   double clock_khz = 0;       // frequency of that clock
   float last_tune_ms = 0;
   RunResult last;  // read-back of the latest query pass
@@ -390,6 +392,8 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
     batch_outputs(b, p.d_outs, p.row_ptr, p.col_o, p.dist_o, p.stage_cap, p.nnz_base, p.nnz, s);
     return;
   }
+  const bool prof = timed && p.profiled;
+  if (prof) batch_stamp(&p.ctl->stamp[0], s);
   batch_query_keys(p.dtype, b, p.mu, p.v, p.qkey, p.qval, p.qa_in, p.qn_in, p.ctl, s);
   radix_sort_pairs_ws(p.qkey, p.qval, p.M, 0, 32, p.sort_ws, s);
   batch_inst_keys(p.d_qin_off, p.count, p.qval, p.M, p.qikey, p.qidx, s);
@@ -397,6 +401,7 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   batch_query_pad(b, p.qorig, p.qa, p.qn, p.qop, p.cthr, s);
   batch_query_gather(p.dtype, b, p.mu, p.qval, p.qikey, p.qidx, p.qa_in, p.qn_in, p.q64, p.qorig, p.qa, p.qn, p.qop,
                      p.cthr, s);
+  if (prof) batch_stamp(&p.ctl->stamp[1], s);
   batch_windows(b, p.key, p.qa, p.qn, p.qorig, p.tlo, p.thi, p.ctl, s);
   const int ngroups = (p.ntiles + p.G - 1) / p.G;
   // instances on the fp32 screen get a tile plan of their own (the tiles of
@@ -436,7 +441,7 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   mx.h = p.h;
   mx.KA = p.KA;
   mx.KB = p.KA;
-  if (timed) batch_stamp(&p.ctl->stamp[0], s);
+  if (timed) batch_stamp(&p.ctl->stamp[2], s);
   if (p.n16) launch_cand_mfma(qd, mx, p.screen_grid, s);
   if (p.NK32) {
     QueryDev q32 = qd;
@@ -448,11 +453,12 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
     q32.counters = p.ctl->counters32;
     launch_cand_mfma32_batch(q32, Mfma32Dev{p.vq32, p.DV32, p.D32, p.cop32, p.h}, p.screen_grid32, s);
   }
-  if (timed) batch_stamp(&p.ctl->stamp[1], s);
+  if (timed) batch_stamp(&p.ctl->stamp[3], s);
 
   // neighbours are assembled in slot order (a tile's rows are contiguous),
   // then each row is sorted on its way to its output row
   batch_recheck(b, p.sv, p.q64, p.p64, p.perm, p.row_cnt, di.cus * 16, s);
+  if (prof) batch_stamp(&p.ctl->stamp[4], s);
   exclusive_scan_i32_to_i64(p.row_cnt, p.rp_s, p.MS, p.scan_ws, s);
   launch_perm_counts(p.rp_s, p.MS, p.qorig, p.cnt_o, s);
   exclusive_scan_i32_to_i64(p.cnt_o, p.row_ptr, p.M, p.scan_ws, s);
@@ -461,6 +467,7 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   const RowMove mv{p.rp_sg, p.key_s, p.qorig, p.row_ptr, p.col_o, p.dist_o};
   launch_row_sort_move(mv, p.MS, INT64_MAX, p.lists, p.ctl->list_counts, p.tmp_col, p.tmp_dist, s);
   batch_outputs(b, p.d_outs, p.row_ptr, p.col_o, p.dist_o, p.stage_cap, p.nnz_base, p.nnz, s);
+  if (prof) batch_stamp(&p.ctl->stamp[5], s);
 }
 
 template <class F>
@@ -553,11 +560,17 @@ RunResult run_graphs(BatchPlan& p, bool do_index, bool do_query) {
     const bool st_over = !sv_over && rr.total > p.stage_cap;
     if (!sv_over && !st_over) {
       rr.screen_ms = -1;
-      if (!do_index && p.M > 0 && p.clock_khz > 0 && rr.ctl.stamp[1] > rr.ctl.stamp[0])
-        rr.screen_ms = (float)((double)(rr.ctl.stamp[1] - rr.ctl.stamp[0]) / p.clock_khz);
+      const unsigned long long* t = rr.ctl.stamp;
+      if (!do_index && p.M > 0 && p.clock_khz > 0 && t[3] > t[2])
+        rr.screen_ms = (float)((double)(t[3] - t[2]) / p.clock_khz);
+      if (!do_index && p.M > 0 && p.profiled)
+        for (int k = 0; k < SNN_STAGES; ++k)
+          rr.stage_ms[k] = t[k + 1] >= t[k] ? (float)((double)(t[k + 1] - t[k]) / p.clock_khz) : -1.0f;
       p.last = rr;
       return rr;
     }
+    log_line(3, "batch: %s overflowed (%llu survivors, %lld neighbours): growing and running the query pass again",
+             sv_over ? "survivor list" : "staging arrays", rr.ctl.survivors, (long long)rr.total);
     if (sv_over) alloc_survivors(p, (int64_t)rr.ctl.survivors * 5 / 4 + 4096);
     if (st_over) alloc_stage(p, rr.total * 5 / 4 + 4096);
     build_graphs(p);
@@ -679,6 +692,7 @@ void fill_stats(const BatchPlan& p, const RunResult& rr, snn_stats* st) {
   st->screen_ms = rr.screen_ms;
   st->total_ms = rr.graph_ms;
   st->flops_window = (double)rr.ctl.flops;
+  for (int k = 0; k < SNN_STAGES; ++k) st->stage_ms[k] = rr.stage_ms[k];
 }
 
 void finish_outputs(BatchPlan& p, const RunResult& rr) {
@@ -749,6 +763,7 @@ BatchPlan* create_batch(const snn_device& devc, snn_dtype dtype, const snn_insta
     }
     p.clock_khz = khz;
     p.screen_timed = khz > 0;
+    p.profiled = p.screen_timed && profile_on();
 
     // pre-pass: centring, direction and norms decide the operand terms
     p.T = 512;
@@ -855,10 +870,15 @@ snn_status snn_batch_run(snn_batch_t b, int32_t what, snn_stats* st) {
     RunResult rr = run_graphs(p, (what & SNN_BATCH_INDEX) != 0, q);
     if (q) {
       fill_stats(p, rr, st);
+      log_line(2, "batch run: %d instances, %lld queries, window pairs=%llu survivors=%llu nnz=%lld, graph %.3f ms "
+                  "(screen %.3f)", p.count, (long long)p.M, rr.ctl.pairs_window, rr.ctl.survivors,
+               (long long)rr.total, rr.graph_ms, rr.screen_ms);
       finish_outputs(p, rr);
     } else if (st) {
       std::memset(st, 0, sizeof(*st));
       st->total_ms = rr.graph_ms;
+      st->screen_ms = -1;
+      for (double& t : st->stage_ms) t = -1;
     }
   });
 }

@@ -76,7 +76,10 @@ struct BatchCtl {
   unsigned long long executed;  // pairs the screen evaluated
   unsigned long long list_counts[8];
   unsigned long long qbad;  // NaN or Inf in some Q
-  unsigned long long stamp[2];  // device clock around the screen kernels
+  // device clock: query pass start, queries ordered, screen start, screen
+  // end, recheck done, pass end (the screen pair always, the others when
+  // profiled)
+  unsigned long long stamp[6];
   unsigned long long counters32[kMaxXcd];  // work counters of the fp32 screen
 };
 

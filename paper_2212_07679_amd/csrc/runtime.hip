@@ -5,7 +5,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -64,6 +66,7 @@ void Buffer::ensure(DeviceArena& a, size_t need) {
   reset(a);
   ptr = a.alloc(need);
   bytes = need;
+  log_line(3, "workspace buffer of %zu bytes", need);
 }
 
 void Buffer::reset(DeviceArena& a) {
@@ -124,6 +127,32 @@ DeviceScope::~DeviceScope() {
 }
 
 void set_last_error(const std::string& msg) { g_err = msg; }
+
+static int env_int(const char* name) {
+  const char* v = std::getenv(name);
+  return v && *v ? std::atoi(v) : 0;
+}
+
+int log_level() { return std::min(3, std::max(0, env_int("SNN_LOG"))); }
+
+bool profile_on() { return env_int("SNN_PROFILE") != 0; }
+
+void log_line(int level, const char* fmt, ...) {
+  if (level > log_level()) return;
+  char buf[640];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[snn] %s\n", buf);
+}
+
+void report_failure(snn_status code, const std::string& msg) {
+  set_last_error(msg);
+  static const char* const names[] = {"OK", "EINVAL", "ENOMEM", "EDEVICE", "EOVERFLOW", "ENOTSUP"};
+  const int k = -(int)code;
+  log_line(1, "failed: SNN_%s: %s", k >= 0 && k <= 5 ? names[k] : "?", msg.c_str());
+}
 
 namespace {
 
@@ -344,9 +373,11 @@ static void run_captured(Index& ix, hipGraphExec_t* g, bool capture, F&& body) {
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
     (void)hipGetLastError();
+    log_line(3, "graph instantiation refused (%d): launching directly", (int)e);
     body();
     return;
   }
+  log_line(3, "captured a repeated call's launches into a graph");
   *g = exec;
   SNN_HIP(hipGraphLaunch(exec, s));
 }
@@ -359,6 +390,50 @@ struct DbscanReq {
   uint8_t* core;       // device, n or nullptr
   int64_t nclusters;   // out
 };
+
+// Stage times of a profiled call from its events: ev[0] call start,
+// ev[4] queries in score order, ev[5] windows and tile plan done, ev[1] /
+// ev[2] screen start / end (of the last attempt), ev[6] recheck done,
+// ev[end] call end.
+static void stage_times(hipEvent_t* ev, int end, snn_stats* st) {
+  const int from[SNN_STAGES] = {0, 4, 1, 2, 6};
+  const int to[SNN_STAGES] = {4, 5, 2, 6, end};
+  for (int k = 0; k < SNN_STAGES; ++k) {
+    float t = 0;
+    SNN_HIP(hipEventElapsedTime(&t, ev[from[k]], ev[to[k]]));
+    st->stage_ms[k] = t;
+  }
+}
+
+static const char* screen_name(snn_precision p, int terms) {
+  switch (p) {
+    case SNN_PREC_FP16:
+      return "fp16";
+    case SNN_PREC_FP32:
+      return "fp32";
+    case SNN_PREC_MIXED:
+      return terms == 1 ? "bf16" : "bf16x3";
+    default:
+      return "fp64";
+  }
+}
+
+// One SNN_LOG=2 line per query.
+static void log_query(const Index& ix, int64_t m, double R, bool self, snn_precision prec, int terms,
+                      unsigned long long window, unsigned long long survivors, int64_t result, const snn_stats* st,
+                      const QueryGraph* qg, const char* result_name) {
+  if (log_level() < 2) return;
+  char times[200] = "";
+  if (st) {
+    int k = std::snprintf(times, sizeof(times), ", device %.3f ms (screen %.3f)", st->total_ms, st->screen_ms);
+    if (st->stage_ms[0] >= 0)
+      std::snprintf(times + k, sizeof(times) - k, ", stages %.3f / %.3f / %.3f / %.3f / %.3f ms", st->stage_ms[0],
+                    st->stage_ms[1], st->stage_ms[2], st->stage_ms[3], st->stage_ms[4]);
+  }
+  log_line(2, "%s n=%lld d=%d m=%lld R=%.17g screen=%s window pairs=%llu survivors=%llu %s=%lld%s%s",
+           self ? "self-query" : "query", (long long)ix.n, ix.d, (long long)m, R, screen_name(prec, terms), window,
+           survivors, result_name, (long long)result, qg && qg->uses > 2 ? " (graph replay)" : "", times);
+}
 
 static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, const snn_options* opts,
                       snn_csr* out, snn_stats* st, DbscanReq* db = nullptr) {
@@ -431,13 +506,20 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   if (prec == SNN_PREC_FP32) build_fp32_operands(ix);
   const int ntiles = (int)std::max<int64_t>(1, (m + T - 1) / T);
 
-  // stats: call start, screen start / end, call end (events kept on the index)
+  // stats: call start, screen start / end, call end (events kept on the
+  // index); a profiled call also marks the ends of query ordering, of the
+  // window pass and of the recheck
   hipEvent_t* ev = ix.ev;
+  const bool prof = st && profile_on();
   if (st) {
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < (prof ? 7 : 4); ++i)
       if (!ev[i]) SNN_HIP(hipEventCreate(&ev[i]));
+    for (double& t : st->stage_ms) t = -1;
     SNN_HIP(hipEventRecord(ev[0], s));
   }
+  auto mark = [&](int i) {
+    if (prof) SNN_HIP(hipEventRecord(ev[i], s));
+  };
 
   // ---- workspace
   const int nbuckets = query_buckets(m);
@@ -638,11 +720,13 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
                           P.qn, ix.mu.as<double>(), qop, s);
     }
     if (self) launch_self_qnorm(ix.ynorm.as<float>(), n, P.qn, s);
+    mark(4);
     launch_windows(ix.key.as<double>(), (int)n, cells, ix.wcells_n, qa, qn, m, w_base, eps_scale, T, sym, P.lo,
                    P.hi, P.tlo, P.thi, P.wpart, s);
     launch_tile_plan(P.tlo, P.thi, ntiles, CH, prec == SNN_PREC_FP64 ? 1 : 32, sym, P.units, G, P.unit_off,
                      P.gbase, T, m, qpw, st ? &P.ctl->executed : nullptr, P.wpart, window_blocks(m),
                      &P.ctl->pairs_window, s);
+    mark(5);
   };
   // ---- the screen
   auto enqueue_screen = [&]() {
@@ -664,6 +748,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     // dispatch of thousands of idle ones would dominate)
     const int sgrid = (int)std::min<long long>(16LL * di.cus, std::max<long long>(2LL * di.cus, cap / 2048));
     launch_recheck(qd, sv, ix.dtype, ix.po.ptr, self, P.row_cnt, sgrid, s);
+    mark(6);
     // slot-order row offsets (where the neighbours are assembled) with the
     // counts in the caller's order, the longest row, the total and the rows
     // by length class; then the caller's row offsets
@@ -679,7 +764,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   // graphs captured on its second occurrence: one launch each instead of
   // about fifteen.
   QueryGraph* qg = nullptr;
-  if (!db && s) {  // (the null stream cannot be captured)
+  if (!db && s && !prof) {  // (the null stream cannot be captured)
     GraphKey gk{};
     const uint64_t fields[] = {reinterpret_cast<uint64_t>(Q), (uint64_t)m, bits_of(R), (uint64_t)self,
                                (uint64_t)o.precision, (uint64_t)o.mixed_terms, (uint64_t)o.tile_q,
@@ -712,6 +797,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     if (st) SNN_HIP(hipEventRecord(ev[2], s));
     if (db) {
       launch_recheck_edges(qd, sv, ix.dtype, ix.po.ptr, P.row_cnt, &P.ctl->accepted, di.cus * 16, s);
+      mark(6);
       SNN_HIP(hipMemcpyAsync(hctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
       SNN_HIP(hipStreamSynchronize(s));
       hc.ctl = *hctl;
@@ -729,6 +815,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
         }
         break;
       }
+      log_line(3, "survivor list of %lld overflowed (%llu survivors): screening again", cap, hc.ctl.survivors);
       cap = (long long)(hc.ctl.survivors * 5 / 4) + 1024;
       ix.ws[1].reset(ix.arena);
       continue;
@@ -761,6 +848,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       }
       break;
     }
+    log_line(3, "survivor list of %lld overflowed (%llu survivors): screening again", cap, hc.ctl.survivors);
     cap = (long long)(hc.ctl.survivors * 5 / 4) + 1024;
     ix.ws[1].reset(ix.arena);
   }
@@ -775,7 +863,11 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       st->screen_ms = a;
       st->total_ms = b;
       st->pairs_executed = (int64_t)hc.ctl.executed;
+      // (the clustering after the read-back is the assembly stage)
+      if (prof) stage_times(ev, 3, st);
     }
+    log_query(ix, m, R, self, prec, sp.terms(), hc.ctl.pairs_window, hc.ctl.survivors, (int64_t)hc.ctl.accepted, st,
+              qg, "clusters");
     return;
   }
 
@@ -801,7 +893,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     st->screen_ms = a;
     st->total_ms = b;
     st->pairs_executed = (int64_t)hc.ctl.executed;
+    if (prof) stage_times(ev, 3, st);
   }
+  log_query(ix, m, R, self, prec, sp.terms(), hc.ctl.pairs_window, hc.ctl.survivors, hc.nnz, st, qg, "nnz");
 }
 
 // ------------------------------------------------------------------------ test support

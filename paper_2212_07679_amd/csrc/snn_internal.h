@@ -27,6 +27,15 @@ void check_hip(hipError_t e, const char* what, const char* file, int line);
 
 // thread-local message returned by snn_last_error()
 void set_last_error(const std::string& msg);
+// set_last_error plus, with SNN_LOG >= 1, a line on stderr
+void report_failure(snn_status code, const std::string& msg);
+
+// SNN_LOG level, 0..3 (read from the environment at every call)
+int log_level();
+// "[snn] <text>" on stderr when level <= log_level()
+void log_line(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+// SNN_PROFILE set to a non-zero integer: per-stage device times in snn_stats
+bool profile_on();
 
 // Runs f, turning every exception into a status code (nothing crosses the C ABI).
 template <class F>
@@ -36,16 +45,16 @@ snn_status guard(F&& f) {
     set_last_error("");
     return SNN_OK;
   } catch (const Error& e) {
-    set_last_error(e.what());
+    report_failure(e.code, e.what());
     return e.code;
   } catch (const std::bad_alloc&) {
-    set_last_error("host allocation failed");
+    report_failure(SNN_ENOMEM, "host allocation failed");
     return SNN_ENOMEM;
   } catch (const std::exception& e) {
-    set_last_error(e.what());
+    report_failure(SNN_EDEVICE, e.what());
     return SNN_EDEVICE;
   } catch (...) {
-    set_last_error("unknown error");
+    report_failure(SNN_EDEVICE, "unknown error");
     return SNN_EDEVICE;
   }
 }
@@ -193,7 +202,9 @@ struct Index {
   Buffer ws[16];
   QueryGraph qgraphs[4];
   uint64_t qgraph_clock = 0;
-  hipEvent_t ev[4] = {};  // stats timing (created on first use)
+  // stats timing (created on first use): call start, screen start and end,
+  // call end, then the stage boundaries of a profiled call
+  hipEvent_t ev[8] = {};
   Buffer stats_host_dev;  // small device block read back at the end of a query
   void* host_ctl = nullptr;  // pinned host copy of a query's control block (hipHostMalloc)
 };
