@@ -9,6 +9,7 @@ no fallback path.
 
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 from typing import Optional, Tuple
@@ -331,34 +332,37 @@ class Index:
     def _run(self, Q: Optional[torch.Tensor], m: int, R: float, opts: snn_options, nnz_cap: Optional[int],
              want_stats: bool):
         dev = self._devobj
-        # the stream context also selects the stream's device; allocations
-        # made under it are tied to that stream by the caching allocator
-        with torch.cuda.stream(self.stream):
+        # outputs are allocated for the index's stream (the caching allocator
+        # ties a block to the stream current at allocation; the library may
+        # still write them when the call returns)
+        if torch.cuda.current_stream(self.device) == self.stream:
+            ctx = contextlib.nullcontext()
+        else:
+            ctx = torch.cuda.stream(self.stream)
+        with ctx:
             cap = int(nnz_cap) if nnz_cap is not None else max(self._nnz_hint, 4 * m, 1024)
+            st = snn_stats() if want_stats else None
+            stp = ctypes.byref(st) if want_stats else None
+            L = lib()
             for _ in range(3):
-                # one allocation for the three outputs (row_ptr, col, dist)
                 c1 = max(cap, 1)
-                o1 = (8 * (m + 1) + 255) // 256 * 256
-                o2 = o1 + (4 * c1 + 255) // 256 * 256
-                buf = torch.empty(o2 + 4 * c1, dtype=torch.uint8, device=dev)
-                row_ptr = buf[:8 * (m + 1)].view(torch.int64)
-                col = buf[o1:o1 + 4 * c1].view(torch.int32)
-                dist = buf[o2:o2 + 4 * c1].view(torch.float32)
+                row_ptr = torch.empty(m + 1, dtype=torch.int64, device=dev)
+                col = torch.empty(c1, dtype=torch.int32, device=dev)
+                dist = torch.empty(c1, dtype=torch.float32, device=dev)
                 csr = snn_csr(row_ptr.data_ptr(), col.data_ptr(), dist.data_ptr(), cap, 0)
-                st = snn_stats()
                 if Q is None:
-                    status = lib().snn_query_self(self._h, float(R), ctypes.byref(opts), ctypes.byref(csr),
-                                                  ctypes.byref(st))
+                    status = L.snn_query_self(self._h, float(R), ctypes.byref(opts), ctypes.byref(csr), stp)
                 else:
-                    status = lib().snn_query(self._h, ctypes.c_void_p(Q.data_ptr()), m, float(R),
-                                             ctypes.byref(opts), ctypes.byref(csr), ctypes.byref(st))
+                    status = L.snn_query(self._h, Q.data_ptr(), m, float(R), ctypes.byref(opts), ctypes.byref(csr),
+                                         stp)
                 if status == SNN_EOVERFLOW and nnz_cap is None:
                     cap = int(csr.nnz)
                     continue
                 _check(status)
                 break
             nnz = int(csr.nnz)
-            self._nnz_hint = max(self._nnz_hint, nnz + nnz // 4)
+            if nnz + (nnz >> 2) > self._nnz_hint:
+                self._nnz_hint = nnz + (nnz >> 2)
             res = (row_ptr, col[:nnz], dist[:nnz])
             return (res + (st.as_dict(),)) if want_stats else res
 

@@ -35,6 +35,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_fp64_reg(QueryDev q) {
   __shared__ PairStage<kStage> st;
   __shared__ long long s_unit;
   stage_init(st);
+  mark_begin(q);
   const int xcd = blockIdx.x % q.nxcd;
   for (;;) {
     __syncthreads();
@@ -69,6 +70,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_fp64_reg(QueryDev q) {
     }
   }
   stage_flush(st, q.sink);
+  mark_end(q);
 }
 
 // Large d: the candidate is streamed in chunks of 16 coordinates while the
@@ -79,6 +81,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_fp64_big(QueryDev q, int dp) 
   __shared__ PairStage<kStage> st;
   __shared__ long long s_unit;
   stage_init(st);
+  mark_begin(q);
   const int xcd = blockIdx.x % q.nxcd;
   for (;;) {
     __syncthreads();
@@ -127,6 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_fp64_big(QueryDev q, int dp) 
     }
   }
   stage_flush(st, q.sink);
+  mark_end(q);
 }
 
 }  // namespace

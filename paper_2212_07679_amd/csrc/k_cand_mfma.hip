@@ -313,6 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
   const int xcd = blockIdx.x % q.nxcd;
   int2* wbuf = wstage[wave];
   int wcnt = 0;  // wave-uniform fill of wbuf
+  mark_begin(q);
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_unit = next_unit(q, xcd);
@@ -378,6 +379,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma(QueryDev q, MixedDev x) 
                                               q0, half, wbuf, wcnt, q.sink);
   }
   wave_flush(wbuf, wcnt, q.sink);
+  mark_end(q);
 }
 
 // ---- fp32 operands ------------------------------------------------------------
@@ -435,6 +437,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma32(QueryDev q, Mfma32Dev 
   const int xcd = blockIdx.x % q.nxcd;
   int2* wbuf = wstage[wave];
   int wcnt = 0;  // wave-uniform fill of wbuf
+  mark_begin(q);
   for (;;) {
     __syncthreads();
     if (threadIdx.x == 0) s_unit = next_unit(q, xcd);
@@ -487,6 +490,7 @@ __global__ __launch_bounds__(kThreads) void k_cand_mfma32(QueryDev q, Mfma32Dev 
     }
   }
   wave_flush(wbuf, wcnt, q.sink);
+  mark_end(q);
 }
 
 __global__ __launch_bounds__(kThreads) void k_mfma32_operands(const float* __restrict__ ys, int64_t n, int64_t npad,

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 
 #include "device_common.h"
 #include "query_plan.h"
@@ -133,6 +134,68 @@ __global__ __launch_bounds__(kThreads) void k_query_gather(const T* __restrict__
       float* o = op.vq + s * op.DV;
       for (int k = sub; k < op.DV; k += G) o[k] = k < d ? (float)((double)q[k] - mu[k]) : (k == d ? c : 0.f);
     }
+  }
+}
+
+// The same for float rows of at most 16 values per output row (d <= 16 and
+// one operand value per coordinate): four lanes per row, each a run of four
+// coordinates read once and written with wide stores (float64 row: 32
+// bytes, operand row: 8 bytes per lane).  Results are identical to
+// k_query_gather's.
+__global__ __launch_bounds__(kThreads) void k_query_gather4(const float* __restrict__ Q, int64_t m, int d, int dp,
+                                                           const uint32_t* __restrict__ bucket,
+                                                           const uint32_t* __restrict__ slot,
+                                                           const uint32_t* __restrict__ boff,
+                                                           const double* __restrict__ qalpha_in,
+                                                           const double* __restrict__ qnorm_in,
+                                                           double* __restrict__ q64, int32_t* __restrict__ qorig,
+                                                           double* __restrict__ qalpha, double* __restrict__ qnorm,
+                                                           const double* __restrict__ mu, QueryOperands op,
+                                                           int vec) {
+  const int sub = threadIdx.x & 3, k0 = 4 * sub;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 4; i < m;
+       i += ((int64_t)gridDim.x * blockDim.x) / 4) {
+    const int64_t s = (int64_t)boff[bucket[i]] + slot[i];
+    const float* q = Q + i * d;
+    float qv[4];
+    if (vec && k0 < d) {  // rows 16-byte aligned
+      const float4 t = *reinterpret_cast<const float4*>(q + k0);
+      qv[0] = t.x, qv[1] = t.y, qv[2] = t.z, qv[3] = t.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) qv[j] = k0 + j < d ? q[k0 + j] : 0.f;
+    }
+    if (k0 < dp) {  // dp is a multiple of 4
+      double2* o = reinterpret_cast<double2*>(q64 + s * dp + k0);
+      o[0] = make_double2((double)qv[0], (double)qv[1]);
+      o[1] = make_double2((double)qv[2], (double)qv[3]);
+    }
+    if (sub == 0) {
+      qorig[s] = (int32_t)i;
+      qalpha[s] = qalpha_in[i];
+      qnorm[s] = qnorm_in[i];
+    }
+    if (op.mode == kQOpNone) continue;
+    float y[4];
+    double nn = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      y[j] = k0 + j < d ? (float)((double)qv[j] - mu[k0 + j]) : 0.f;
+      nn += (double)y[j] * (double)y[j];
+    }
+    // any summation order stays within the gamma_{d+1} bound the start value allows for
+    nn += __shfl_xor(nn, 1, 4);
+    nn += __shfl_xor(nn, 2, 4);
+    const float c = screen_threshold(op.b, 0.5 * nn, sqrt(nn) * (1.0 + 1e-15));
+    if (k0 < op.KA) {  // KA is a multiple of 16
+      uint16_t v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        v[j] = op.kind == kOpF16 ? __builtin_bit_cast(uint16_t, (_Float16)ldexpf(y[j], op.e)) : f32_to_bf16_rne(y[j]);
+      *reinterpret_cast<uint2*>(op.qop + s * op.KA + k0) =
+          make_uint2((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16));
+    }
+    if (sub == 0) op.cthr[s] = c;
   }
 }
 
@@ -425,6 +488,14 @@ void query_gather_d(const T* Q, int64_t m, int d, int dp, const uint32_t* bucket
                     const uint32_t* boff, const double* qalpha_in, const double* qnorm_in, double* q64, int32_t* qorig,
                     double* qalpha, double* qnorm, const double* mu, const QueryOperands& op, hipStream_t s) {
   const int width = std::max(dp, op.mode == kQOp16 ? op.KA : (op.mode == kQOp32 ? op.DV : 0));
+  if (std::is_same<T, float>::value && width <= 16 &&
+      (op.mode == kQOpNone || (op.mode == kQOp16 && op.kind != kOpBf16x3))) {
+    const int vec = d % 4 == 0 && reinterpret_cast<uintptr_t>(Q) % 16 == 0;
+    k_query_gather4<<<grid_for(m * 4, 8192), kThreads, 0, s>>>(reinterpret_cast<const float*>(Q), m, d, dp, bucket,
+                                                              slot, boff, qalpha_in, qnorm_in, q64, qorig, qalpha,
+                                                              qnorm, mu, op, vec);
+    return;
+  }
   const int G = query_row_lanes(width);
   const int g = grid_for(m * G, 8192);
   if (G == 4)

@@ -60,6 +60,10 @@ struct QueryDev {
   // decided once and reported in both rows (S is exactly symmetric).
   int sym;
   PairSink sink;
+  // device clock marks of the launch, or NULL: [0] the complement of the
+  // earliest workgroup start (zero is then the neutral value of atomicMax),
+  // [1] the latest workgroup end
+  unsigned long long* stamps;
 };
 
 __device__ __forceinline__ int uniform_i32(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -67,6 +71,15 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t x) {
   uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(x & 0xffffffffu));
   uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Clock marks of a screen launch (thread 0 of each workgroup, at its start
+// and after its last work unit).
+__device__ __forceinline__ void mark_begin(const QueryDev& q) {
+  if (q.stamps && threadIdx.x == 0) atomicMax(&q.stamps[0], ~(unsigned long long)wall_clock64());
+}
+__device__ __forceinline__ void mark_end(const QueryDev& q) {
+  if (q.stamps && threadIdx.x == 0) atomicMax(&q.stamps[1], (unsigned long long)wall_clock64());
 }
 
 // Next work unit for a block on XCD `xcd`: each XCD owns a contiguous range

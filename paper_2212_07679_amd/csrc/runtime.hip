@@ -94,6 +94,11 @@ const DeviceInfo& device_info(int device) {
       cache[device].lds_bytes = lds;
     else
       (void)hipGetLastError();
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+      cache[device].clock_khz = khz;
+    else
+      (void)hipGetLastError();
     have[device] = true;
   }
   return cache[device];
@@ -170,6 +175,7 @@ struct Ctl {
   unsigned long long executed;
   unsigned long long accepted;  // neighbour entries (clustering mode)
   unsigned long long nnz;       // neighbour entries (lists mode)
+  unsigned long long screen_mark[2];  // device clock marks of the screen launch (QueryDev::stamps)
   int bad;
   int scan_err;  // a look-back scan's wait did not end (not expected)
 };
@@ -178,6 +184,13 @@ struct HostCtl {
   Ctl ctl;
   int64_t nnz;
 };
+
+// Duration of the screen launch from its clock marks (0 without a launch).
+double screen_ms_of(const Ctl& c, const DeviceInfo& di) {
+  const unsigned long long t0 = ~c.screen_mark[0], t1 = c.screen_mark[1];
+  if (c.screen_mark[1] == 0 || t1 < t0 || di.clock_khz <= 0) return 0.0;
+  return (double)(t1 - t0) / di.clock_khz;
+}
 
 
 }  // namespace
@@ -506,9 +519,10 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   if (prec == SNN_PREC_FP32) build_fp32_operands(ix);
   const int ntiles = (int)std::max<int64_t>(1, (m + T - 1) / T);
 
-  // stats: call start, screen start / end, call end (events kept on the
-  // index); a profiled call also marks the ends of query ordering, of the
-  // window pass and of the recheck
+  // stats: events at the call's start and end (kept on the index); the
+  // screen is timed by its own clock marks.  A profiled call also records
+  // events at the screen's start and end and after query ordering, the
+  // window pass and the recheck.
   hipEvent_t* ev = ix.ev;
   const bool prof = st && profile_on();
   if (st) {
@@ -651,6 +665,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   qd.counters = P.ctl->counters;
   qd.nxcd = di.xcds;
   qd.sym = sym;
+  // the screen's duration from clock marks its workgroups leave (no events
+  // around the launch, which would cost the host a few microseconds each)
+  qd.stamps = st && di.clock_khz > 0 ? P.ctl->screen_mark : nullptr;
 
   // survivors: capacity remembered on the index, grown on overflow
   // bytes per survivor: the pair, and per result row, column, distance, slot
@@ -789,12 +806,13 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       launch_fill_u64(&P.ctl->accepted, 1, 0ull, s);
       launch_fill_u64(P.ctl->list_counts, 8, 0ull, s);
       launch_fill_u64(&P.ctl->row_max, 1, 0ull, s);
+      launch_fill_u64(P.ctl->screen_mark, 2, 0ull, s);
       launch_fill_u64(P.lb_rows, 2 * (int64_t)lookback_words(m), 0ull, s);
       launch_fill_i32(P.row_cnt, m, 0, s);
     }
-    if (st) SNN_HIP(hipEventRecord(ev[1], s));
+    mark(1);
     enqueue_screen();
-    if (st) SNN_HIP(hipEventRecord(ev[2], s));
+    mark(2);
     if (db) {
       launch_recheck_edges(qd, sv, ix.dtype, ix.po.ptr, P.row_cnt, &P.ctl->accepted, di.cus * 16, s);
       mark(6);
@@ -857,10 +875,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     if (st) {
       SNN_HIP(hipEventRecord(ev[3], s));
       SNN_HIP(hipEventSynchronize(ev[3]));
-      float a = 0, b = 0;
-      SNN_HIP(hipEventElapsedTime(&a, ev[1], ev[2]));
+      float b = 0;
       SNN_HIP(hipEventElapsedTime(&b, ev[0], ev[3]));
-      st->screen_ms = a;
+      st->screen_ms = screen_ms_of(hc.ctl, di);
       st->total_ms = b;
       st->pairs_executed = (int64_t)hc.ctl.executed;
       // (the clustering after the read-back is the assembly stage)
@@ -887,10 +904,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
       SNN_HIP(hipEventRecord(ev[3], s));
       SNN_HIP(hipEventSynchronize(ev[3]));
     }
-    float a = 0, b = 0;
-    SNN_HIP(hipEventElapsedTime(&a, ev[1], ev[2]));
+    float b = 0;
     SNN_HIP(hipEventElapsedTime(&b, ev[0], ev[3]));
-    st->screen_ms = a;
+    st->screen_ms = screen_ms_of(hc.ctl, di);
     st->total_ms = b;
     st->pairs_executed = (int64_t)hc.ctl.executed;
     if (prof) stage_times(ev, 3, st);

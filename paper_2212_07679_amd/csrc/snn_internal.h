@@ -132,6 +132,7 @@ struct DeviceInfo {
   int cus = 256;       // compute units
   int xcds = 8;        // accelerator complex dies (separate L2 each)
   int lds_bytes = 64 * 1024;  // LDS one workgroup may use (queried)
+  double clock_khz = 0;       // rate of the device's constant clock (wall_clock64), 0 if unknown
 };
 const DeviceInfo& device_info(int device);
 

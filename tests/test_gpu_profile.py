@@ -2,7 +2,7 @@
 
 A profiled call reports one non-negative time per stage of Algorithm 2
 (ordering, windows, screen, recheck, assembly) whose sum stays within the
-call's device time, the screen stage equal to screen_ms; the results are
+call's device time, the screen stage close to screen_ms; the results are
 the same as without profiling (checked against the oracle).  Without
 SNN_PROFILE every stage time is -1.
 """
@@ -55,7 +55,10 @@ def check(got, ref, what):
 def check_stages(st, what):
     t = st["stage_ms"]
     assert len(t) == 5 and all(x >= 0 for x in t), f"{what}: {t}"
-    assert abs(t[2] - st["screen_ms"]) <= 1e-3 + 1e-3 * st["screen_ms"], f"{what}: screen stage {t[2]} vs {st['screen_ms']}"
+    # the screen stage runs event to event, screen_ms from the first
+    # workgroup's start to the last one's end: a little shorter
+    assert st["screen_ms"] <= t[2] + 2e-3, f"{what}: screen stage {t[2]} vs {st['screen_ms']}"
+    assert t[2] <= st["screen_ms"] * 1.05 + 0.05, f"{what}: screen stage {t[2]} vs {st['screen_ms']}"
     assert sum(t) <= st["total_ms"] * 1.001 + 1e-3, f"{what}: stages {t} exceed the call {st['total_ms']}"
 
 
@@ -75,6 +78,7 @@ def test_profiled_query_stages(B, gmm, env, precision):
     got = idx.query(Q, w.R, precision=precision, stats=True)
     check(got, ref, "unprofiled")
     assert got[3]["stage_ms"] == [-1.0] * 5
+    assert 0 < got[3]["screen_ms"] < got[3]["total_ms"], got[3]
     env.setenv("SNN_PROFILE", "1")
     for k in range(3):  # the same call again: never replayed from a graph while profiled
         got = idx.query(Q, w.R, precision=precision, stats=True)
