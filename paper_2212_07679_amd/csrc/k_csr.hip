@@ -60,7 +60,8 @@ __device__ __forceinline__ float pair_distance(int metric, double s) {
 
 // Data rows are read in the input dtype (their promotion to float64 is
 // exact), the query rows of a self-query likewise; out-of-sample query rows
-// are the float64 copies.
+// are the float64 copies in score order, or the caller's rows (input dtype,
+// through qorig) when the screen made no such copies.
 template <typename T, bool SELF>
 __global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, const T* __restrict__ po,
                                                      int32_t* __restrict__ row_cnt) {
@@ -78,8 +79,10 @@ __global__ __launch_bounds__(kThreads) void k_recheck(QueryDev q, Survivors sv, 
       const T* pp = po + (int64_t)pr.y * d;
       if (SELF)
         s = pair_measure(q.metric, pp, po + (int64_t)pr.x * d, d);
-      else
+      else if (q.q64)
         s = pair_measure(q.metric, pp, q.q64 + (int64_t)pr.x * q.dp, d);
+      else
+        s = pair_measure(q.metric, pp, static_cast<const T*>(q.qsrc) + (int64_t)q.qorig[pr.x] * d, d);
       keep = q.metric == SNN_METRIC_L1 ? s <= q.R1 : s <= q.R2;
     }
     if (keep) {
@@ -139,16 +142,20 @@ __global__ __launch_bounds__(kThreads) void k_recheck_edges(QueryDev q, Survivor
   if (lane_id() == 0 && acc) atomicAdd(accepted, acc);
 }
 
-__global__ __launch_bounds__(kThreads) void k_scatter(Survivors sv, const int64_t* __restrict__ row_ptr,
-                                                     uint64_t* __restrict__ keys) {
+__device__ __forceinline__ void scatter_body(const Survivors& sv, const int64_t* __restrict__ row_ptr,
+                                             uint64_t* __restrict__ keys, int block, int nblocks) {
   if (*sv.count > (unsigned long long)sv.cap) return;  // overflowed: the host runs the query again
   const long long cnt = (long long)*sv.count * sv.per;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
-       i += (long long)gridDim.x * blockDim.x) {
+  for (long long i = (long long)block * blockDim.x + threadIdx.x; i < cnt; i += (long long)nblocks * blockDim.x) {
     const int qo = sv.res_q[i];
     if (qo < 0) continue;
     keys[row_ptr[qo] + sv.res_slot[i]] = sv.res_key[i];
   }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(Survivors sv, const int64_t* __restrict__ row_ptr,
+                                                     uint64_t* __restrict__ keys) {
+  scatter_body(sv, row_ptr, keys, blockIdx.x, gridDim.x);
 }
 
 // false when the move was enqueued before the host checked the sizes and
@@ -472,10 +479,8 @@ __global__ __launch_bounds__(kThreads) void k_rows_stats(const int64_t* __restri
 // counts in the destination order (cnt_dst[map[r]] = cnt[r]), the longest
 // row, the total and the rows by length class (each workgroup reserves its
 // class list space with one atomic per class).
-__global__ __launch_bounds__(kLookbackThreads) void k_rows_scan(const int32_t* __restrict__ cnt, int64_t m,
-                                                               int64_t* __restrict__ row_ptr,
-                                                               unsigned long long* __restrict__ state,
-                                                               int* __restrict__ err, RowsExtra ex) {
+__device__ void rows_scan_body(const int32_t* __restrict__ cnt, int64_t m, int64_t* __restrict__ row_ptr,
+                               unsigned long long* __restrict__ state, int* __restrict__ err, const RowsExtra& ex) {
   const int32_t* __restrict__ map = ex.map;
   int32_t* __restrict__ cnt_dst = ex.cnt_dst;
   unsigned long long* __restrict__ row_max = ex.row_max;
@@ -564,6 +569,30 @@ __global__ __launch_bounds__(kLookbackThreads) void k_rows_scan(const int32_t* _
     }
     run += v[k];
   }
+}
+
+__global__ __launch_bounds__(kLookbackThreads) void k_rows_scan(const int32_t* __restrict__ cnt, int64_t m,
+                                                               int64_t* __restrict__ row_ptr,
+                                                               unsigned long long* __restrict__ state,
+                                                               int* __restrict__ err, RowsExtra ex) {
+  rows_scan_body(cnt, m, row_ptr, state, err, ex);
+}
+
+// k_rows_scan (no extras) and k_scatter in one launch: the first nscan
+// workgroups scan, the others scatter (the two are independent; the scan's
+// tiles are taken in ticket order, so its look-back only ever waits for
+// workgroups that are already running).
+__global__ __launch_bounds__(kLookbackThreads) void k_rows_scan_scatter(const int32_t* __restrict__ cnt, int64_t m,
+                                                                       int64_t* __restrict__ row_ptr,
+                                                                       unsigned long long* __restrict__ state,
+                                                                       int* __restrict__ err, int nscan,
+                                                                       Survivors sv,
+                                                                       const int64_t* __restrict__ rp_s,
+                                                                       uint64_t* __restrict__ keys) {
+  if ((int)blockIdx.x < nscan)
+    rows_scan_body(cnt, m, row_ptr, state, err, RowsExtra{});
+  else
+    scatter_body(sv, rp_s, keys, blockIdx.x - nscan, gridDim.x - nscan);
 }
 
 // k_perm_counts plus the longest row and (block 0, thread 0) the total.
@@ -723,6 +752,15 @@ void launch_rows_scan(const int32_t* cnt, int64_t m, int64_t* row_ptr, unsigned 
                       const RowsExtra& ex, hipStream_t s) {
   const int blocks = (int)std::max<int64_t>(1, (m + kLookbackTile - 1) / kLookbackTile);
   k_rows_scan<<<blocks, kLookbackThreads, 0, s>>>(cnt, m, row_ptr, state, err, ex);
+  SNN_LAUNCH_CHECK();
+}
+
+void launch_rows_scan_scatter(const int32_t* cnt, int64_t m, int64_t* row_ptr, unsigned long long* state, int* err,
+                              const Survivors& sv, const int64_t* rp_s, uint64_t* keys, int scatter_grid,
+                              hipStream_t s) {
+  const int nscan = (int)std::max<int64_t>(1, (m + kLookbackTile - 1) / kLookbackTile);
+  k_rows_scan_scatter<<<nscan + scatter_grid, kLookbackThreads, 0, s>>>(cnt, m, row_ptr, state, err, nscan, sv, rp_s,
+                                                                        keys);
   SNN_LAUNCH_CHECK();
 }
 

@@ -76,6 +76,57 @@ __global__ __launch_bounds__(kThreads) void k_query_keys(const T* __restrict__ Q
   if (badloc) atomicOr(bad, 1);
 }
 
+// The same for float rows of d <= 16: four lanes per row, each a run of
+// four coordinates (one 16-byte load where the rows are 16-byte aligned).
+__global__ __launch_bounds__(kThreads) void k_query_keys4(const float* __restrict__ Q, int64_t m, int d,
+                                                         const double* __restrict__ mu,
+                                                         const double* __restrict__ v,
+                                                         const double* __restrict__ key, int n, int K,
+                                                         uint32_t* __restrict__ bucket, uint32_t* __restrict__ slot,
+                                                         uint32_t* __restrict__ hist, double* __restrict__ qalpha,
+                                                         double* __restrict__ qnorm, int* __restrict__ bad, int vec) {
+  const double amin = key[0], amax = key[n - 1];
+  const double scale = amax > amin ? (double)K / (amax - amin) : 0.0;
+  const int sub = threadIdx.x & 3, k0 = 4 * sub;
+  int badloc = 0;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 4; i < m;
+       i += ((int64_t)gridDim.x * blockDim.x) / 4) {
+    const float* q = Q + i * d;
+    float qv[4];
+    if (vec && k0 < d) {
+      const float4 t = *reinterpret_cast<const float4*>(q + k0);
+      qv[0] = t.x, qv[1] = t.y, qv[2] = t.z, qv[3] = t.w;
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) qv[j] = k0 + j < d ? q[k0 + j] : 0.f;
+    }
+    double a = 0.0, nn = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (k0 + j < d) {
+        const double qk = (double)qv[j];
+        if (!isfinite(qk)) badloc = 1;
+        const double x = qk - mu[k0 + j];
+        a += x * v[k0 + j];
+        const double y = (double)(float)x;
+        nn += y * y;
+      }
+    a += __shfl_xor(a, 1, 4);
+    nn += __shfl_xor(nn, 1, 4);
+    a += __shfl_xor(a, 2, 4);
+    nn += __shfl_xor(nn, 2, 4);
+    if (sub == 0) {
+      const double t = (a - amin) * scale;
+      const int b = (t >= 0.0) ? (t < (double)K ? (int)t : K - 1) : 0;
+      bucket[i] = (uint32_t)b;
+      slot[i] = atomicAdd(&hist[b], 1u);
+      qalpha[i] = a;
+      qnorm[i] = sqrt(nn);
+    }
+  }
+  if (badloc) atomicOr(bad, 1);
+}
+
 // G lanes per query row: the row's destination slot is read once per group,
 // its elements are copied G at a time, and the lanes build the screen's
 // operand row and start value from the centred row y = fl32(q - mu)
@@ -97,7 +148,8 @@ __global__ __launch_bounds__(kThreads) void k_query_gather(const T* __restrict__
        i += ((int64_t)gridDim.x * blockDim.x) / G) {
     const int64_t s = (int64_t)boff[bucket[i]] + slot[i];
     const T* q = Q + i * d;
-    for (int k = sub; k < dp; k += G) q64[s * dp + k] = k < d ? (double)q[k] : 0.0;
+    if (q64)
+      for (int k = sub; k < dp; k += G) q64[s * dp + k] = k < d ? (double)q[k] : 0.0;
     if (sub == 0) {
       qorig[s] = (int32_t)i;
       qalpha[s] = qalpha_in[i];
@@ -165,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_query_gather4(const float* __restr
 #pragma unroll
       for (int j = 0; j < 4; ++j) qv[j] = k0 + j < d ? q[k0 + j] : 0.f;
     }
-    if (k0 < dp) {  // dp is a multiple of 4
+    if (q64 && k0 < dp) {  // dp is a multiple of 4
       double2* o = reinterpret_cast<double2*>(q64 + s * dp + k0);
       o[0] = make_double2((double)qv[0], (double)qv[1]);
       o[1] = make_double2((double)qv[2], (double)qv[3]);
@@ -330,14 +382,20 @@ __global__ __launch_bounds__(kThreads) void k_query_init(unsigned long long* __r
 // tiles, and scan the groups into unit offsets (unit_off[ngroups] = total).
 constexpr int kAbsChunks = 8;
 
-__global__ __launch_bounds__(1024) void k_tile_plan(int32_t* __restrict__ tlo, int32_t* __restrict__ thi, int ntiles,
-                                                   int CH, int align, int sym_T, int32_t* __restrict__ units, int G,
-                                                   int64_t* __restrict__ unit_off, int32_t* __restrict__ gbase, int T,
-                                                   int64_t m, int qpw, unsigned long long* __restrict__ executed,
-                                                   const unsigned long long* __restrict__ wpart, int nwpart,
-                                                   unsigned long long* __restrict__ pairs_window) {
+__device__ void tile_plan_body(const TilePlanArgs& pa) {
+  int32_t* __restrict__ tlo = pa.tlo;
+  int32_t* __restrict__ thi = pa.thi;
+  int32_t* __restrict__ units = pa.units;
+  int64_t* __restrict__ unit_off = pa.unit_off;
+  int32_t* __restrict__ gbase = pa.gbase;
+  unsigned long long* __restrict__ executed = pa.executed;
+  const unsigned long long* __restrict__ wpart = pa.wpart;
+  unsigned long long* __restrict__ pairs_window = pa.pairs_window;
+  const int ntiles = pa.ntiles, CH = pa.CH, align = pa.align, sym_T = pa.sym_T, G = pa.G, T = pa.T, qpw = pa.qpw;
+  const int nwpart = pa.nwpart;
+  const int64_t m = pa.m;
   __shared__ int64_t carry;
-  __shared__ int64_t wsum[1024 / kWave];
+  __shared__ int64_t wsum[1024 / kWave];  // (any workgroup of up to 1024 threads)
   if (pairs_window) {  // the window-pair total from the per-workgroup partials
     __shared__ unsigned long long pw_s[1024 / kWave];
     unsigned long long pw = 0;
@@ -427,6 +485,8 @@ __global__ __launch_bounds__(1024) void k_tile_plan(int32_t* __restrict__ tlo, i
   if (threadIdx.x == 0) unit_off[ngroups] = carry;
 }
 
+__global__ __launch_bounds__(1024) void k_tile_plan(TilePlanArgs pa) { tile_plan_body(pa); }
+
 // ---------------------------------------------------------------- launchers
 namespace {
 int grid_for(int64_t work, int cap) {
@@ -461,6 +521,12 @@ template <typename T>
 void query_keys_d(const T* Q, int64_t m, int d, const double* mu, const double* v, const double* key, int n, int K,
                   uint32_t* bucket, uint32_t* slot, uint32_t* hist, double* qalpha, double* qnorm, int* bad,
                   hipStream_t s) {
+  if (std::is_same<T, float>::value && d <= 16) {
+    const int vec = d % 4 == 0 && reinterpret_cast<uintptr_t>(Q) % 16 == 0;
+    k_query_keys4<<<grid_for(m * 4, 8192), kThreads, 0, s>>>(reinterpret_cast<const float*>(Q), m, d, mu, v, key, n,
+                                                            K, bucket, slot, hist, qalpha, qnorm, bad, vec);
+    return;
+  }
   switch (query_row_lanes(d)) {
     case 4: query_keys_t<T, 4>(Q, m, d, mu, v, key, n, K, bucket, slot, hist, qalpha, qnorm, bad, s); break;
     case 8: query_keys_t<T, 8>(Q, m, d, mu, v, key, n, K, bucket, slot, hist, qalpha, qnorm, bad, s); break;
@@ -549,12 +615,30 @@ void launch_windows(const double* key, int n, const int32_t* cells, int C, const
   SNN_LAUNCH_CHECK();
 }
 
+void launch_windows_plan(const double* key, int n, const int32_t* cells, int C, const double* qalpha,
+                         const double* qnorm, int64_t m, double w_base, double eps_scale, int T, int sym, int32_t* lo,
+                         int32_t* hi, const TilePlanArgs& plan, hipStream_t s) {
+  // (A k_window whose last workgroup ran the plan, after a fence and a
+  // ticket, took 20 us longer on a 1e5-query call: an agent-scope fence
+  // writes back the XCD's whole L2.)
+  TilePlanArgs pa = plan;
+  pa.nwpart = window_blocks(m);
+  if (m > 0) {
+    k_window<<<pa.nwpart, kThreads, 0, s>>>(key, n, cells, C, qalpha, qnorm, m, w_base, eps_scale, T, sym, lo, hi,
+                                            plan.tlo, plan.thi, const_cast<unsigned long long*>(plan.wpart));
+    SNN_LAUNCH_CHECK();
+  }
+  k_tile_plan<<<1, 1024, 0, s>>>(pa);
+  SNN_LAUNCH_CHECK();
+}
+
 void launch_tile_plan(int32_t* tlo, int32_t* thi, int ntiles, int CH, int align, int sym, int32_t* units, int G,
                       int64_t* unit_off, int32_t* gbase, int T, int64_t m, int qpw, unsigned long long* executed,
                       const unsigned long long* wpart, int nwpart, unsigned long long* pairs_window,
                       hipStream_t s) {
-  k_tile_plan<<<1, 1024, 0, s>>>(tlo, thi, ntiles, CH, align, sym ? T : 0, units, G, unit_off, gbase, T, m, qpw,
-                                 executed, wpart, nwpart, pairs_window);
+  const TilePlanArgs pa{tlo, thi, ntiles, CH, align, sym ? T : 0, units, G, unit_off, gbase, T, m, qpw, executed,
+                        wpart, nwpart, pairs_window};
+  k_tile_plan<<<1, 1024, 0, s>>>(pa);
   SNN_LAUNCH_CHECK();
 }
 

@@ -44,7 +44,8 @@ struct QueryDev {
   double R2;  // fl64(R*R) of the screen radius
   int metric; // snn_metric of the recheck
   double R1;  // the L1 radius (metric L1; R2 then belongs to the widened L2 radius)
-  const double* q64;     // m x dp: query rows in float64, score order
+  const double* q64;     // m x dp: query rows in float64, score order (the float64 screen and self-queries)
+  const void* qsrc;      // the caller's query rows (input dtype), read by the recheck when q64 is NULL
   const int32_t* qorig;  // m: score-order position -> caller's query row
   const double* p64;     // n x dp: data rows in float64, score order
   const int32_t* perm;   // n: score-order position -> original data row
@@ -152,6 +153,33 @@ void launch_window_table(const double* key, int n, int C, int32_t* start, hipStr
 // most kWindowMaxBlocks of them: window_blocks(m)); k_tile_plan sums them
 constexpr int kWindowMaxBlocks = 2048;
 int window_blocks(int64_t m);
+// Arguments of the tile plan (k_tile_plan, or the last workgroup of
+// k_window): per-tile windows widened to `align`, work units of CH
+// candidates, groups of G tiles with their unit offsets and absolute chunk
+// bases, the executed-pair count and the window-pair total.
+struct TilePlanArgs {
+  int32_t* tlo;
+  int32_t* thi;
+  int ntiles;
+  int CH;
+  int align;
+  int sym_T;  // T for a symmetric self-query, else 0
+  int32_t* units;
+  int G;
+  int64_t* unit_off;
+  int32_t* gbase;
+  int T;
+  int64_t m;
+  int qpw;
+  unsigned long long* executed;
+  const unsigned long long* wpart;
+  int nwpart;
+  unsigned long long* pairs_window;
+};
+// k_window (m > 0) followed by the tile plan
+void launch_windows_plan(const double* key, int n, const int32_t* cells, int C, const double* qalpha,
+                         const double* qnorm, int64_t m, double w_base, double eps_scale, int T, int sym, int32_t* lo,
+                         int32_t* hi, const TilePlanArgs& plan, hipStream_t s);
 void launch_windows(const double* key, int n, const int32_t* cells, int C, const double* qalpha,
                     const double* qnorm, int64_t m, double w_base, double eps_scale, int T, int sym, int32_t* lo,
                     int32_t* hi, int32_t* tlo, int32_t* thi, unsigned long long* wpart, hipStream_t s);
@@ -376,6 +404,10 @@ struct RowsExtra {
 };
 // row_ptr (m + 1) from the counts in one launch; state: lookback_words(m)
 // zero words
+// launch_rows_scan without extras and launch_scatter as one launch
+void launch_rows_scan_scatter(const int32_t* cnt, int64_t m, int64_t* row_ptr, unsigned long long* state, int* err,
+                              const Survivors& sv, const int64_t* rp_s, uint64_t* keys, int scatter_grid,
+                              hipStream_t s);
 void launch_rows_scan(const int32_t* cnt, int64_t m, int64_t* row_ptr, unsigned long long* state, int* err,
                       const RowsExtra& ex, hipStream_t s);
 // keys into slot-order rows at row_ptr[row] + slot

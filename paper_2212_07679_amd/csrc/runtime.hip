@@ -576,7 +576,10 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     p.hist = c.take<uint32_t>(self ? 1 : nbuckets);
     p.qa_in = c.take<double>(mq);
     p.qn_in = c.take<double>(mq);
-    p.q64 = c.take<double>(mq * ix.dp);
+    // float64 copies of out-of-sample queries in score order: only the
+    // float64 screen reads them (the recheck of the others reads the
+    // caller's rows through qorig)
+    p.q64 = prec == SNN_PREC_FP64 ? c.take<double>(mq * ix.dp) : nullptr;
     p.qorig = c.take<int32_t>(mq);
     p.qa = c.take<double>(mq);
     p.qn = c.take<double>(std::max<size_t>(m, 1));
@@ -620,7 +623,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   MixedBound self_bound{};
   if (mix16) mx = prepare_mixed(ix, sp.kind, R2, self, P.qop, P.cthr, &qop, &self_bound);
   if (prec == SNN_PREC_FP32) prepare_fp32(ix, R2, self, P.vq, &qop, &self_bound);
-  const double* q64 = self ? ix.p64.as<double>() : P.q64;
+  const double* q64 = self ? ix.p64.as<double>() : P.q64;  // NULL: the recheck reads Q
   const int32_t* qorig = self ? ix.perm.as<int32_t>() : P.qorig;
   const double* qa = self ? ix.key.as<double>() : P.qa;
   const double* qn = P.qn;
@@ -655,6 +658,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   qd.metric = o.metric;
   qd.R1 = R;
   qd.q64 = q64;
+  qd.qsrc = Q;
   qd.qorig = qorig;
   qd.p64 = ix.p64.as<double>();
   qd.perm = ix.perm.as<int32_t>();
@@ -738,11 +742,26 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     }
     if (self) launch_self_qnorm(ix.ynorm.as<float>(), n, P.qn, s);
     mark(4);
-    launch_windows(ix.key.as<double>(), (int)n, cells, ix.wcells_n, qa, qn, m, w_base, eps_scale, T, sym, P.lo,
-                   P.hi, P.tlo, P.thi, P.wpart, s);
-    launch_tile_plan(P.tlo, P.thi, ntiles, CH, prec == SNN_PREC_FP64 ? 1 : 32, sym, P.units, G, P.unit_off,
-                     P.gbase, T, m, qpw, st ? &P.ctl->executed : nullptr, P.wpart, window_blocks(m),
-                     &P.ctl->pairs_window, s);
+    TilePlanArgs plan{};
+    plan.tlo = P.tlo;
+    plan.thi = P.thi;
+    plan.ntiles = ntiles;
+    plan.CH = CH;
+    plan.align = prec == SNN_PREC_FP64 ? 1 : 32;
+    plan.sym_T = sym ? T : 0;
+    plan.units = P.units;
+    plan.G = G;
+    plan.unit_off = P.unit_off;
+    plan.gbase = P.gbase;
+    plan.T = T;
+    plan.m = m;
+    plan.qpw = qpw;
+    plan.executed = st ? &P.ctl->executed : nullptr;
+    plan.wpart = P.wpart;
+    plan.nwpart = window_blocks(m);
+    plan.pairs_window = &P.ctl->pairs_window;
+    launch_windows_plan(ix.key.as<double>(), (int)n, cells, ix.wcells_n, qa, qn, m, w_base, eps_scale, T, sym, P.lo,
+                        P.hi, plan, s);
     mark(5);
   };
   // ---- the screen
@@ -771,8 +790,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     // by length class; then the caller's row offsets
     launch_rows_scan(P.row_cnt, m, P.rp_s, P.lb_rows, &P.ctl->scan_err,
                      RowsExtra{qorig, P.cnt_o, &P.ctl->row_max, &P.ctl->nnz, P.lists, P.ctl->list_counts}, s);
-    launch_rows_scan(P.cnt_o, m, out->row_ptr, P.lb_rows + lookback_words(m), &P.ctl->scan_err, RowsExtra{}, s);
-    launch_scatter(sv, P.rp_s, stage_key, sgrid, s);
+    launch_rows_scan_scatter(P.cnt_o, m, out->row_ptr, P.lb_rows + lookback_words(m), &P.ctl->scan_err, sv, P.rp_s,
+                             stage_key, sgrid, s);
     launch_row_sort_short(mv, P.lists, P.ctl->list_counts, s);
   };
 
