@@ -12,6 +12,7 @@ from __future__ import annotations
 import contextlib
 import ctypes
 import os
+import struct
 from typing import Optional, Tuple
 
 import torch
@@ -93,9 +94,17 @@ class snn_stats(ctypes.Structure):
     ]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_}
-        d["stage_ms"] = list(self.stage_ms)
+        # one unpack of the whole block (field-by-field ctypes reads cost
+        # microseconds per call)
+        v = struct.unpack_from(_STATS_FMT, self)
+        d = dict(zip(_STATS_NAMES, v[:9]))
+        d["stage_ms"] = list(v[9:])
         return d
+
+
+_STATS_FMT = "<4q2i3d5d"
+_STATS_NAMES = tuple(k for k, _ in snn_stats._fields_[:9])
+assert struct.calcsize(_STATS_FMT) == ctypes.sizeof(snn_stats)
 
 
 class snn_index_view(ctypes.Structure):
@@ -302,6 +311,8 @@ class Index:
         self._devobj = torch.device("cuda", self.device)
         self._h = ctypes.c_void_p()
         self._nnz_hint = 0
+        self._opt_cache = {}
+        self._csr_cache = {}
         _check(lib().snn_index(ctypes.byref(self._alloc.dev), ctypes.c_void_p(X.data_ptr()), self.n, self.d,
                                _dtype_code(X), ctypes.byref(self._h)))
 
@@ -322,6 +333,16 @@ class Index:
 
     def _opts(self, precision: str, terms: int, tile_q: int, tile_c: int, full_self_scan: bool = False,
               metric: str = "l2") -> snn_options:
+        # the library only reads the options: one object per distinct set
+        key = (precision, terms, tile_q, tile_c, full_self_scan, metric)
+        o = self._opt_cache.get(key)
+        if o is None:
+            o = self._opt_cache[key] = self._make_opts(*key)
+        return o
+
+    @staticmethod
+    def _make_opts(precision: str, terms: int, tile_q: int, tile_c: int, full_self_scan: bool,
+                   metric: str) -> snn_options:
         if precision not in PRECISION:
             raise SnnError(SNN_EINVAL, f"precision must be one of {sorted(PRECISION)}")
         if metric not in METRIC:
@@ -378,6 +399,45 @@ class Index:
             raise SnnError(SNN_EINVAL, "Q must have the index dtype")
         Q = Q.contiguous()
         return self._run(Q, Q.shape[0], R, self._opts(precision, terms, tile_q, tile_c, metric=metric), nnz_cap, stats)
+
+    def query_into(self, Q: Optional[torch.Tensor], R: float, row_ptr: torch.Tensor, col: torch.Tensor,
+                   dist: torch.Tensor, precision: str = "auto", terms: int = 0, tile_q: int = 0, tile_c: int = 0,
+                   stats: bool = False, metric: str = "l2", full_self_scan: bool = False):
+        """Algorithm 2 into caller-owned output tensors (a serving loop's form:
+        no allocation per call).  Q (m x d) or None for the all-points
+        self-query; row_ptr: int64 with at least m + 1 entries; col / dist:
+        int32 / float32 of one capacity.  Returns nnz (plus the stats dict);
+        raises SnnError(SNN_EOVERFLOW) when the neighbours exceed the
+        capacity (the message holds the count needed).  The tensors must be
+        on the index's device; the library writes them on the index's stream
+        (work on another stream that reads them must wait for it)."""
+        m = self.n if Q is None else Q.shape[0]
+        key = (row_ptr.data_ptr(), col.data_ptr(), dist.data_ptr(), col.numel(), dist.numel(), row_ptr.dtype,
+               col.dtype, dist.dtype)
+        csr = self._csr_cache.get(key)
+        if csr is None:
+            if (row_ptr.dtype != torch.int64 or col.dtype != torch.int32 or dist.dtype != torch.float32
+                    or dist.numel() != col.numel() or not (row_ptr.is_contiguous() and col.is_contiguous()
+                                                            and dist.is_contiguous())):
+                raise SnnError(SNN_EINVAL, "row_ptr / col / dist: contiguous int64 / int32 / float32, one capacity")
+            if len(self._csr_cache) > 16:
+                self._csr_cache.clear()
+            csr = self._csr_cache[key] = snn_csr(key[0], key[1], key[2], key[3], 0)
+        if row_ptr.numel() < m + 1:
+            raise SnnError(SNN_EINVAL, "row_ptr needs m + 1 entries")
+        opts = self._opts(precision, terms, tile_q, tile_c, full_self_scan, metric)
+        st = snn_stats() if stats else None
+        if Q is None:
+            status = lib().snn_query_self(self._h, float(R), ctypes.byref(opts), ctypes.byref(csr),
+                                          ctypes.byref(st) if stats else None)
+        else:
+            if not Q.is_cuda or Q.dim() != 2 or Q.shape[1] != self.d or Q.dtype != self.dtype or not Q.is_contiguous():
+                raise SnnError(SNN_EINVAL, "Q must be a contiguous CUDA tensor of shape (m, d) and the index dtype")
+            status = lib().snn_query(self._h, Q.data_ptr(), m, float(R), ctypes.byref(opts), ctypes.byref(csr),
+                                     ctypes.byref(st) if stats else None)
+        _check(status)
+        nnz = csr.nnz
+        return (nnz, st.as_dict()) if stats else nnz
 
     def query_self(self, R: float, precision: str = "auto", terms: int = 0, tile_q: int = 0, tile_c: int = 0,
                    nnz_cap: Optional[int] = None, stats: bool = False, full_self_scan: bool = False,

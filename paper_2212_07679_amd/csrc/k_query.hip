@@ -362,10 +362,12 @@ __global__ __launch_bounds__(kThreads) void k_query_init(unsigned long long* __r
                                                         int32_t* __restrict__ row_cnt, int64_t m,
                                                         uint32_t* __restrict__ hist, int nb,
                                                         int32_t* __restrict__ tlo, int32_t* __restrict__ thi,
-                                                        int ntiles) {
+                                                        int ntiles, int mark_word) {
   const int64_t top = max(max((int64_t)ctl_words, m), (int64_t)max(nb, ntiles));
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < top; i += (int64_t)gridDim.x * blockDim.x) {
-    if (i < ctl_words) ctl[i] = 0ull;
+    // (the word mark_word of the control block takes the device clock: the
+    // start of the call)
+    if (i < ctl_words) ctl[i] = i == mark_word ? (unsigned long long)wall_clock64() : 0ull;
     if (i < m) row_cnt[i] = 0;
     if (hist && i < nb) hist[i] = 0u;
     if (i < ntiles) {
@@ -598,9 +600,19 @@ void launch_window_table(const double* key, int n, int C, int32_t* start, hipStr
 }
 
 void launch_query_init(unsigned long long* ctl, int ctl_words, int32_t* row_cnt, int64_t m, uint32_t* hist, int nb,
-                       int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s) {
+                       int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s, int mark_word) {
   const int64_t top = std::max(std::max((int64_t)ctl_words, m), (int64_t)std::max(nb, ntiles));
-  k_query_init<<<grid_for(top, 4096), kThreads, 0, s>>>(ctl, ctl_words, row_cnt, m, hist, nb, tlo, thi, ntiles);
+  k_query_init<<<grid_for(top, 4096), kThreads, 0, s>>>(ctl, ctl_words, row_cnt, m, hist, nb, tlo, thi, ntiles,
+                                                        mark_word);
+  SNN_LAUNCH_CHECK();
+}
+
+__global__ void k_clock_mark(unsigned long long* out) {
+  if (threadIdx.x == 0) *out = (unsigned long long)wall_clock64();
+}
+
+void launch_clock_mark(unsigned long long* out, hipStream_t s) {
+  k_clock_mark<<<1, 64, 0, s>>>(out);
   SNN_LAUNCH_CHECK();
 }
 
@@ -618,9 +630,9 @@ void launch_windows(const double* key, int n, const int32_t* cells, int C, const
 void launch_windows_plan(const double* key, int n, const int32_t* cells, int C, const double* qalpha,
                          const double* qnorm, int64_t m, double w_base, double eps_scale, int T, int sym, int32_t* lo,
                          int32_t* hi, const TilePlanArgs& plan, hipStream_t s) {
-  // (A k_window whose last workgroup ran the plan, after a fence and a
-  // ticket, took 20 us longer on a 1e5-query call: an agent-scope fence
-  // writes back the XCD's whole L2.)
+  // (The plan run by the last k_window workgroup to finish, found with a
+  // ticket, gave no shorter call: with device-scope fences it took 20 us
+  // longer, as such a fence writes back the XCD's whole L2.)
   TilePlanArgs pa = plan;
   pa.nwpart = window_blocks(m);
   if (m > 0) {

@@ -185,8 +185,12 @@ void launch_windows(const double* key, int n, const int32_t* cells, int C, const
                     int32_t* hi, int32_t* tlo, int32_t* thi, unsigned long long* wpart, hipStream_t s);
 // one launch: zero ctl_words control words, row_cnt (m) and hist (nb, may be
 // NULL), and empty tile windows (tlo = INT_MAX, thi = INT_MIN)
+// mark_word >= 0: that word of ctl takes the device clock (wall_clock64)
+// instead of zero
 void launch_query_init(unsigned long long* ctl, int ctl_words, int32_t* row_cnt, int64_t m, uint32_t* hist, int nb,
-                       int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s);
+                       int32_t* tlo, int32_t* thi, int ntiles, hipStream_t s, int mark_word = -1);
+// *out = the device clock (wall_clock64) when the stream reaches it
+void launch_clock_mark(unsigned long long* out, hipStream_t s);
 // one single-workgroup launch after the windows: tile windows clamped and
 // aligned, units per tile, G x max units per group of G tiles scanned into
 // unit_off (ngroups + 1 entries), evaluated pairs added to *executed

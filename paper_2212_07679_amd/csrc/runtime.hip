@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -106,25 +107,36 @@ const DeviceInfo& device_info(int device) {
 
 // Select the device of `dev` for the duration of a call, check it is gfx950.
 DeviceScope::DeviceScope(int device) {
-  int count = 0;
-  hipError_t e = hipGetDeviceCount(&count);
-  if (e != hipSuccess || count <= 0) {
-    (void)hipGetLastError();
-    fail(SNN_EDEVICE, "no HIP device available");
+  // device count and architecture are checked once per process and device
+  // (every call passes through here; each HIP query costs the host time on
+  // the call's critical path)
+  static std::atomic<int> count{-1};
+  static std::atomic<int> ok[64];
+  int c = count.load(std::memory_order_acquire);
+  if (c < 0) {
+    hipError_t e = hipGetDeviceCount(&c);
+    if (e != hipSuccess || c <= 0) {
+      (void)hipGetLastError();
+      fail(SNN_EDEVICE, "no HIP device available");
+    }
+    count.store(c, std::memory_order_release);
   }
-  if (device < 0 || device >= count) fail(SNN_EINVAL, "device ordinal out of range");
-  SNN_HIP(hipGetDevice(&prev));
-  SNN_HIP(hipSetDevice(device));
-  static std::mutex mu;
-  static std::vector<int> ok;
-  std::lock_guard<std::mutex> lk(mu);
-  if ((int)ok.size() <= device) ok.resize(device + 1, -1);
-  if (ok[device] < 0) {
+  if (device < 0 || device >= c) fail(SNN_EINVAL, "device ordinal out of range");
+  if (device >= 64) fail(SNN_ENOTSUP, "device ordinals above 63 are not supported");
+  int v = ok[device].load(std::memory_order_acquire);  // 0 unknown, 1 gfx950, 2 other
+  if (v == 0) {
     hipDeviceProp_t p;
     SNN_HIP(hipGetDeviceProperties(&p, device));
-    ok[device] = std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+    v = std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+    ok[device].store(v, std::memory_order_release);
   }
-  if (!ok[device]) fail(SNN_EDEVICE, "device is not gfx950 (this library is built for MI355X only)");
+  if (v != 1) fail(SNN_EDEVICE, "device is not gfx950 (this library is built for MI355X only)");
+  int cur = -1;
+  SNN_HIP(hipGetDevice(&cur));
+  if (cur != device) {
+    SNN_HIP(hipSetDevice(device));
+    prev = cur;
+  }
 }
 
 DeviceScope::~DeviceScope() {
@@ -176,6 +188,7 @@ struct Ctl {
   unsigned long long accepted;  // neighbour entries (clustering mode)
   unsigned long long nnz;       // neighbour entries (lists mode)
   unsigned long long screen_mark[2];  // device clock marks of the screen launch (QueryDev::stamps)
+  unsigned long long call_mark[2];    // device clock at the call's first kernel and after its last
   int bad;
   int scan_err;  // a look-back scan's wait did not end (not expected)
 };
@@ -184,6 +197,12 @@ struct HostCtl {
   Ctl ctl;
   int64_t nnz;
 };
+
+// Device time of the call from its clock marks.
+double call_ms_of(const Ctl& c, const DeviceInfo& di) {
+  if (di.clock_khz <= 0 || c.call_mark[1] < c.call_mark[0]) return 0.0;
+  return (double)(c.call_mark[1] - c.call_mark[0]) / di.clock_khz;
+}
 
 // Duration of the screen launch from its clock marks (0 without a launch).
 double screen_ms_of(const Ctl& c, const DeviceInfo& di) {
@@ -519,17 +538,20 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   if (prec == SNN_PREC_FP32) build_fp32_operands(ix);
   const int ntiles = (int)std::max<int64_t>(1, (m + T - 1) / T);
 
-  // stats: events at the call's start and end (kept on the index); the
-  // screen is timed by its own clock marks.  A profiled call also records
-  // events at the screen's start and end and after query ordering, the
-  // window pass and the recheck.
+  // stats: the device clock marks the call's start (its first kernel) and
+  // end (a mark kernel after the last one), and the screen's workgroups
+  // mark the screen's; events (each costs the host microseconds on the
+  // critical path) only for a profiled call, at the call's start and end
+  // and between its stages (kept on the index)
   hipEvent_t* ev = ix.ev;
   const bool prof = st && profile_on();
+  const bool marks = st && di.clock_khz > 0;
   if (st) {
-    for (int i = 0; i < (prof ? 7 : 4); ++i)
-      if (!ev[i]) SNN_HIP(hipEventCreate(&ev[i]));
+    if (prof || !marks)
+      for (int i = 0; i < (prof ? 7 : 4); ++i)
+        if (!ev[i]) SNN_HIP(hipEventCreate(&ev[i]));
     for (double& t : st->stage_ms) t = -1;
-    SNN_HIP(hipEventRecord(ev[0], s));
+    if (prof || !marks) SNN_HIP(hipEventRecord(ev[0], s));
   }
   auto mark = [&](int i) {
     if (prof) SNN_HIP(hipEventRecord(ev[i], s));
@@ -681,6 +703,29 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   long long cap = std::max<long long>(1 << 16, (long long)(ix.ws[1].bytes / per_bytes));
   HostCtl hc{};
   Ctl* hctl = pinned_ctl(ix);
+  // the mark kernel after the call's last kernel (the end of the post
+  // sequence, or after the work that follows the read-back), read back
+  auto end_mark = [&](bool read_back) {
+    if (!marks) return;
+    launch_clock_mark(&P.ctl->call_mark[1], s);
+    if (read_back) {
+      SNN_HIP(hipMemcpyAsync(&hctl->call_mark[1], &P.ctl->call_mark[1], 8, hipMemcpyDeviceToHost, s));
+      SNN_HIP(hipStreamSynchronize(s));
+      hc.ctl.call_mark[1] = hctl->call_mark[1];
+    }
+  };
+  // device time of the call; later: work was enqueued after the read-back
+  auto call_end_ms = [&](bool later) -> double {
+    if (marks && !prof) {
+      if (later) end_mark(true);
+      return call_ms_of(hc.ctl, di);
+    }
+    if (later) SNN_HIP(hipEventRecord(ev[3], s));
+    SNN_HIP(hipEventSynchronize(ev[3]));
+    float b = 0;
+    SNN_HIP(hipEventElapsedTime(&b, ev[0], ev[3]));
+    return b;
+  };
   Survivors sv{};
   uint64_t* stage_key = nullptr;  // neighbour keys in slot-order rows
   RowMove mv{};                   // their move to the caller's rows
@@ -729,7 +774,8 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const bool sort_queries = !self && m > 0;
   auto enqueue_pre = [&]() {
     launch_query_init(reinterpret_cast<unsigned long long*>(P.ctl), P.ctl_words, P.row_cnt, m,
-                      sort_queries ? P.hist : nullptr, nbuckets, P.tlo, P.thi, ntiles, s);
+                      sort_queries ? P.hist : nullptr, nbuckets, P.tlo, P.thi, ntiles, s,
+                      marks ? (int)(offsetof(Ctl, call_mark) / 8) : -1);
     if (self && mix16) launch_mixed_qprep_self(ix.ys.as<float>(), ix.n, ix.d, self_bound, P.cthr, s);
     if (self && prec == SNN_PREC_FP32) launch_mfma32_qprep_self(ix.ys.as<float>(), ix.n, ix.d, self_bound, P.vq, s);
     if (sort_queries) {
@@ -793,6 +839,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     launch_rows_scan_scatter(P.cnt_o, m, out->row_ptr, P.lb_rows + lookback_words(m), &P.ctl->scan_err, sv, P.rp_s,
                              stage_key, sgrid, s);
     launch_row_sort_short(mv, P.lists, P.ctl->list_counts, s);
+    end_mark(false);
   };
 
   // A call repeated with the same inputs, outputs and workspace (a serving
@@ -861,7 +908,7 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     run_captured(ix, qg && attempt == 0 ? &qg->post : nullptr, qg && qg->uses > 1, enqueue_post);
     SNN_HIP(hipMemcpyAsync(hctl, P.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     // the call's end unless longer rows follow the read-back
-    if (st) SNN_HIP(hipEventRecord(ev[3], s));
+    if (prof || (st && !marks)) SNN_HIP(hipEventRecord(ev[3], s));
     SNN_HIP(hipStreamSynchronize(s));
     hc.ctl = *hctl;
     hc.nnz = (int64_t)hc.ctl.nnz;
@@ -892,12 +939,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
 
   if (db) {
     if (st) {
-      SNN_HIP(hipEventRecord(ev[3], s));
-      SNN_HIP(hipEventSynchronize(ev[3]));
-      float b = 0;
-      SNN_HIP(hipEventElapsedTime(&b, ev[0], ev[3]));
+      // (the clustering ran after the read-back)
+      st->total_ms = call_end_ms(true);
       st->screen_ms = screen_ms_of(hc.ctl, di);
-      st->total_ms = b;
       st->pairs_executed = (int64_t)hc.ctl.executed;
       // (the clustering after the read-back is the assembly stage)
       if (prof) stage_times(ev, 3, st);
@@ -919,14 +963,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   launch_row_sort_tail(mv, m, (int64_t)hc.ctl.row_max, P.lists, P.ctl->list_counts, tmp_col, tmp_dist, s);
 
   if (st) {
-    if (hc.ctl.row_max > 16) {  // longer rows were sorted after the read-back
-      SNN_HIP(hipEventRecord(ev[3], s));
-      SNN_HIP(hipEventSynchronize(ev[3]));
-    }
-    float b = 0;
-    SNN_HIP(hipEventElapsedTime(&b, ev[0], ev[3]));
+    // longer rows were sorted after the read-back
+    st->total_ms = call_end_ms(hc.ctl.row_max > 16);
     st->screen_ms = screen_ms_of(hc.ctl, di);
-    st->total_ms = b;
     st->pairs_executed = (int64_t)hc.ctl.executed;
     if (prof) stage_times(ev, 3, st);
   }
