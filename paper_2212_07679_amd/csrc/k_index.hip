@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <vector>
 
@@ -696,6 +697,72 @@ __global__ __launch_bounds__(kThreads) void k_project(const T* __restrict__ X, i
   }
 }
 
+// The same for float rows of d <= 16: four lanes per row, each a run of
+// four coordinates (one 16-byte load where the rows are 16-byte aligned, vec),
+// U rows per group of lanes in flight.
+template <int U>
+__global__ __launch_bounds__(kThreads) void k_project4(const float* __restrict__ X, int64_t n, int d,
+                                                      const double* __restrict__ mu, const double* __restrict__ v,
+                                                      uint32_t* __restrict__ ukey, uint32_t* __restrict__ val,
+                                                      double* __restrict__ block_max, int vec) {
+  const int sub = threadIdx.x & 3, k0 = 4 * sub, grp = (threadIdx.x % kWave) >> 2;
+  double mur[4], vr[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    mur[j] = k0 + j < d ? mu[k0 + j] : 0.0;
+    vr[j] = k0 + j < d ? v[k0 + j] : 0.0;
+  }
+  constexpr int GW = kWave / 4;  // rows per wavefront and unroll step
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  double nmax = 0.0;
+  for (int64_t base = wave * U * GW; base < n; base += nwaves * U * GW) {
+    float xv[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + grp + u * GW;
+      const float* x = X + i * d;
+      if (vec && i < n && k0 < d) {
+        const float4 t = *reinterpret_cast<const float4*>(x + k0);
+        xv[u][0] = t.x, xv[u][1] = t.y, xv[u][2] = t.z, xv[u][3] = t.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[u][j] = (i < n && k0 + j < d) ? x[k0 + j] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + grp + u * GW;
+      double a = 0.0, nn = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (k0 + j < d) {
+          const double x = (double)xv[u][j] - mur[j];
+          a += x * vr[j];
+          const double y = (double)(float)x;
+          nn += y * y;
+        }
+      a += __shfl_xor(a, 1, 4);
+      nn += __shfl_xor(nn, 1, 4);
+      a += __shfl_xor(a, 2, 4);
+      nn += __shfl_xor(nn, 2, 4);
+      if (sub == 0 && i < n) {
+        ukey[i] = float_to_ordered((float)a);
+        val[i] = (uint32_t)i;
+      }
+      if (i < n) nmax = fmax(nmax, nn);
+    }
+  }
+  __shared__ double red[kThreads / kWave];
+  nmax = wave_max(nmax);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = nmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / kWave; ++w) nmax = fmax(nmax, red[w]);
+    block_max[blockIdx.x] = nmax;
+  }
+}
+
 // *max_norm = max(*max_norm, block_max[0 .. nblocks)) in one workgroup of
 // kMaxFinalThreads, eight loads in flight per thread
 constexpr int kMaxFinalThreads = 1024;
@@ -809,6 +876,91 @@ __global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, in
   }
 }
 
+// The same for float rows of d <= 16 (dp <= 16): four lanes per row, each a
+// run of four coordinates, U destination rows per group of lanes in flight;
+// 16-byte loads and stores where the rows are 16-byte aligned (vec).
+template <int U>
+__global__ __launch_bounds__(kThreads) void k_gather4(const float* __restrict__ X, int64_t n, int d, int dp,
+                                                     const double* __restrict__ mu,
+                                                     const uint32_t* __restrict__ ukey,
+                                                     const uint32_t* __restrict__ val, double* __restrict__ key,
+                                                     int32_t* __restrict__ perm, float* __restrict__ po,
+                                                     double* __restrict__ p64, float* __restrict__ ys,
+                                                     float* __restrict__ h, float* __restrict__ ynorm,
+                                                     int64_t id_base, int vec) {
+  const int sub = threadIdx.x & 3, k0 = 4 * sub, grp = (threadIdx.x % kWave) >> 2;
+  double mur[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) mur[j] = k0 + j < d ? mu[k0 + j] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x < 64) h[n + threadIdx.x] = INFINITY;  // padding rows
+  constexpr int GW = kWave / 4;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t base = wave * U * GW; base < n; base += nwaves * U * GW) {
+    uint32_t src[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t s = base + grp + u * GW;
+      src[u] = s < n ? val[s] : 0u;
+    }
+    float xv[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t s = base + grp + u * GW;
+      const float* x = X + (int64_t)src[u] * d;
+      if (vec && s < n && k0 < d) {
+        const float4 t = *reinterpret_cast<const float4*>(x + k0);
+        xv[u][0] = t.x, xv[u][1] = t.y, xv[u][2] = t.z, xv[u][3] = t.w;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[u][j] = (s < n && k0 + j < d) ? x[k0 + j] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t s = base + grp + u * GW;
+      float y[4];
+      double nn = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        y[j] = k0 + j < d ? (float)((double)xv[u][j] - mur[j]) : 0.f;
+        nn += (double)y[j] * (double)y[j];
+      }
+      if (s < n) {
+        if (vec) {
+          if (k0 < d) {
+            *reinterpret_cast<float4*>(po + s * d + k0) = make_float4(xv[u][0], xv[u][1], xv[u][2], xv[u][3]);
+            *reinterpret_cast<float4*>(ys + s * d + k0) = make_float4(y[0], y[1], y[2], y[3]);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (k0 + j < d) {
+              po[s * d + k0 + j] = xv[u][j];
+              ys[s * d + k0 + j] = y[j];
+            }
+        }
+        if (k0 < dp) {  // dp is a multiple of 4; the padding columns are zero
+          double2* o = reinterpret_cast<double2*>(p64 + s * dp + k0);
+          o[0] = make_double2((double)xv[u][0], (double)xv[u][1]);
+          o[1] = make_double2((double)xv[u][2], (double)xv[u][3]);
+        }
+      }
+      nn += __shfl_xor(nn, 1, 4);
+      nn += __shfl_xor(nn, 2, 4);
+      if (sub == 0 && s < n) {
+        perm[s] = (int32_t)(id_base + src[u]);
+        key[s] = (double)ordered_to_float(ukey[s]);
+        h[s] = (float)(0.5 * nn);
+        // round ||y|| up to float so it bounds the true norm
+        float nr = (float)sqrt(nn);
+        if ((double)nr < sqrt(nn)) nr = nextafterf(nr, INFINITY);
+        ynorm[s] = nr;
+      }
+    }
+  }
+}
+
 int grid_for(int64_t work, int per_block, int cap);
 
 // Lanes per row G of the row kernels (enough to read a short row in one
@@ -838,6 +990,17 @@ template <typename T>
 void launch_project(const T* X, int64_t n, int d, const double* mu, const double* v, uint32_t* ukey, uint32_t* val,
                     double* block_max, double* max_norm, int cap, hipStream_t s) {
   int grid = 1;
+  if (std::is_same<T, float>::value && d <= 16) {
+    constexpr int U = 4;
+    const int vec = d % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
+    grid = grid_for((std::max<int64_t>(n, 1) + U - 1) / U * 4, kThreads, cap);
+    k_project4<U><<<grid, kThreads, 0, s>>>(reinterpret_cast<const float*>(X), n, d, mu, v, ukey, val, block_max,
+                                            vec);
+    SNN_LAUNCH_CHECK();
+    k_max_final<<<1, kMaxFinalThreads, 0, s>>>(block_max, grid, max_norm);
+    SNN_LAUNCH_CHECK();
+    return;
+  }
   row_shape(d, [&](auto g, auto ne) {
     constexpr int G = decltype(g)::value, NE = decltype(ne)::value, U = NE >= 8 ? 1 : 8 / NE;
     grid = grid_for((std::max<int64_t>(n, 1) + U - 1) / U * G, kThreads, cap);
@@ -856,6 +1019,15 @@ template <typename T>
 void launch_gather(const T* X, int64_t n, int d, int dp, const double* mu, const uint32_t* ukey, const uint32_t* val,
                    double* key, int32_t* perm, T* po, double* p64, float* ys, float* h, float* ynorm, int64_t id_base,
                    int cap, hipStream_t s) {
+  if (std::is_same<T, float>::value && dp <= 16) {
+    constexpr int U = 2;
+    const int vec = d % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
+    const int grid = grid_for((std::max<int64_t>(n, 1) + U - 1) / U * 4, kThreads, cap);
+    k_gather4<U><<<grid, kThreads, 0, s>>>(reinterpret_cast<const float*>(X), n, d, dp, mu, ukey, val, key, perm,
+                                           reinterpret_cast<float*>(po), p64, ys, h, ynorm, id_base, vec);
+    SNN_LAUNCH_CHECK();
+    return;
+  }
   row_shape(dp, [&](auto g, auto ne) {
     constexpr int G = decltype(g)::value, NE = decltype(ne)::value;
     const int grid = grid_for(std::max<int64_t>(n, 1) * G, kThreads, cap);
