@@ -270,7 +270,7 @@ void alloc_index(BatchPlan& p, bool with_operands) {
     p.sort_ws = c.take<char>(radix_sort_ws_bytes(std::max(p.N, p.M)));
     p.key = c.take<double>(p.NR);
     p.perm = c.take<int32_t>(p.NR);
-    p.p64 = c.take<double>(p.P64);
+    p.p64 = nullptr;  // (the recheck reads the caller's rows)
     p.h = c.take<float>(p.NR);
     p.cop = c.take<uint16_t>(with_operands ? (size_t)p.NR * p.KA : 1);
     p.cop32 = c.take<float>(with_operands && p.NK32 ? (size_t)p.NR * p.D32 : 1);
@@ -292,7 +292,7 @@ void alloc_query(BatchPlan& p) {
     p.qidx = c.take<uint32_t>(M);
     p.qa_in = c.take<double>(M);
     p.qn_in = c.take<double>(M);
-    p.q64 = c.take<double>(std::max<int64_t>(p.Q64, 1));
+    p.q64 = nullptr;
     p.qa = c.take<double>(MS);
     p.qn = c.take<double>(MS);
     p.qorig = c.take<int32_t>(MS);
@@ -457,7 +457,7 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
 
   // neighbours are assembled in slot order (a tile's rows are contiguous),
   // then each row is sorted on its way to its output row
-  batch_recheck(b, p.sv, p.q64, p.p64, p.perm, p.row_cnt, di.cus * 16, s);
+  batch_recheck(p.dtype, b, p.sv, p.qorig, p.perm, p.row_cnt, di.cus * 16, s);
   if (prof) batch_stamp(&p.ctl->stamp[4], s);
   exclusive_scan_i32_to_i64(p.row_cnt, p.rp_s, p.MS, p.scan_ws, s);
   launch_perm_counts(p.rp_s, p.MS, p.qorig, p.cnt_o, s);

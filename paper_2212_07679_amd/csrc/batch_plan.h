@@ -138,7 +138,8 @@ void batch_split_tiles(const BatchDev& b, int32_t* tlo, int32_t* thi, int32_t* t
 void batch_executed(const BatchDev& b, const int32_t* tlo, const int32_t* thi, int queries_per_wave, BatchCtl* ctl,
                     hipStream_t s);
 // row_cnt per query slot (rows are assembled in slot order)
-void batch_recheck(const BatchDev& b, const Survivors& sv, const double* q64, const double* p64,
+// (rows read from the caller's X and Q through perm and qorig)
+void batch_recheck(snn_dtype dt, const BatchDev& b, const Survivors& sv, const int32_t* qorig,
                    const int32_t* perm, int32_t* row_cnt, int grid, hipStream_t s);
 // neighbour keys into slot-order rows (nothing when row_ptr[M] > cap)
 void batch_scatter(const Survivors& sv, const int64_t* row_ptr, int64_t M, uint64_t* keys, int64_t cap, int grid,

@@ -401,11 +401,10 @@ __global__ __launch_bounds__(kThreads) void kb_gather(BatchDev b, const double* 
     const int64_t local = (int64_t)val[p] - in.in_off;
     const T* x = static_cast<const T*>(in.X) + local * d;
     const double* m = mu + in.vec_off;
-    double* prow = p64 + in.p64_off + r * in.dp;
     double nn = 0.0;
     for (int k = sub; k < in.dp; k += kQG) {
       const double xv = k < d ? (double)x[k] : 0.0;
-      prow[k] = xv;
+      if (p64) p64[in.p64_off + r * in.dp + k] = xv;
       if (k < d) {
         const float y = (float)(xv - m[k]);
         nn += (double)y * (double)y;
@@ -529,11 +528,10 @@ __global__ __launch_bounds__(kThreads) void kb_query_gather(
     const int64_t s = in.slot_base + r;
     const T* q = static_cast<const T*>(in.Q) + (g - in.qin_off) * d;
     const double* m = mu + in.vec_off;
-    double* qrow = q64 + in.q64_off + r * in.dp;
     double nn = 0.0;
     for (int k = lane; k < in.dp; k += kQG) {
       const double qv = k < d ? (double)q[k] : 0.0;
-      qrow[k] = qv;
+      if (q64) q64[in.q64_off + r * in.dp + k] = qv;
       if (k < d) {
         const float y = (float)(qv - m[k]);
         nn += (double)y * (double)y;
@@ -678,8 +676,10 @@ __global__ __launch_bounds__(kThreads) void kb_executed(BatchDev b, const int32_
 }
 
 // ---- survivors -> CSR ------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void kb_recheck(BatchDev b, Survivors sv, const double* __restrict__ q64,
-                                                      const double* __restrict__ p64,
+// The caller's rows in their dtype (promotion to float64 is exact): the
+// data row through perm, the query row through qorig.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void kb_recheck(BatchDev b, Survivors sv, const int32_t* __restrict__ qorig,
                                                       const int32_t* __restrict__ perm,
                                                       int32_t* __restrict__ row_cnt) {
   const long long cnt = (long long)min((unsigned long long)sv.cap, *sv.count);
@@ -687,18 +687,20 @@ __global__ __launch_bounds__(kThreads) void kb_recheck(BatchDev b, Survivors sv,
        k += (long long)gridDim.x * blockDim.x) {
     const int2 pr = sv.pairs[k];
     const int i = b.tile_inst[pr.x / b.T];
-    const BatchInst in = b.inst[i];
-    const double* qp = q64 + in.q64_off + ((int64_t)pr.x - in.slot_base) * in.dp;
-    const double* pp = p64 + in.p64_off + ((int64_t)pr.y - in.row_base) * in.dp;
+    const BatchInst& in = b.inst[i];
+    const int d = in.d;
+    const int pj = perm[pr.y];
+    const T* pp = static_cast<const T*>(in.X) + (int64_t)pj * d;
+    const T* qp = static_cast<const T*>(in.Q) + ((int64_t)qorig[pr.x] - in.qin_off) * d;
     double s = 0.0;
-    for (int c = 0; c < in.d; ++c) {
-      const double t = pp[c] - qp[c];
+    for (int c = 0; c < d; ++c) {
+      const double t = (double)pp[c] - (double)qp[c];
       s = s + t * t;
     }
     if (s <= in.R2) {
       // rows are query slots: a tile's rows are neighbours in memory
       sv.res_q[k] = pr.x;
-      sv.res_key[k] = neighbour_key(perm[pr.y], (float)sqrt(s));
+      sv.res_key[k] = neighbour_key(pj, (float)sqrt(s));
       sv.res_slot[k] = atomicAdd(&row_cnt[pr.x], 1);
     } else {
       sv.res_q[k] = -1;
@@ -891,9 +893,9 @@ void batch_executed(const BatchDev& b, const int32_t* tlo, const int32_t* thi, i
   SNN_LAUNCH_CHECK();
 }
 
-void batch_recheck(const BatchDev& b, const Survivors& sv, const double* q64, const double* p64,
+void batch_recheck(snn_dtype dt, const BatchDev& b, const Survivors& sv, const int32_t* qorig,
                    const int32_t* perm, int32_t* row_cnt, int grid, hipStream_t s) {
-  kb_recheck<<<grid, kThreads, 0, s>>>(b, sv, q64, p64, perm, row_cnt);
+  SNN_DT_LAUNCH(kb_recheck, grid, kThreads, b, sv, qorig, perm, row_cnt);
   SNN_LAUNCH_CHECK();
 }
 
