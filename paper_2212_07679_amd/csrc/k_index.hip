@@ -1118,13 +1118,23 @@ void build_index_t(Index& ix, const T* X) {
 
   ix.mu.ensure(ix.arena, sizeof(double) * d);
   ix.v.ensure(ix.arena, sizeof(double) * d);
-  ix.key.ensure(ix.arena, sizeof(double) * n);
-  ix.perm.ensure(ix.arena, sizeof(int32_t) * n);
-  ix.po.ensure(ix.arena, sizeof(T) * n * d);
-  ix.p64.ensure(ix.arena, sizeof(double) * n * ix.dp);
-  ix.ys.ensure(ix.arena, sizeof(float) * n * d);
-  ix.h.ensure(ix.arena, sizeof(float) * (n + 64));
-  ix.ynorm.ensure(ix.arena, sizeof(float) * n);
+  {
+    Buffer* views[] = {&ix.key, &ix.perm, &ix.po, &ix.p64, &ix.ys, &ix.h, &ix.ynorm};
+    const size_t sizes[] = {sizeof(double) * n,         sizeof(int32_t) * n,      sizeof(T) * n * d,
+                            sizeof(double) * n * ix.dp, sizeof(float) * n * d,    sizeof(float) * (n + 64),
+                            sizeof(float) * n};
+    size_t total = 0;
+    for (size_t b : sizes) total += align256(b);
+    for (Buffer* b : views) b->reset(ix.arena);
+    ix.rows.ensure(ix.arena, total);
+    char* base = static_cast<char*>(ix.rows.ptr);
+    for (int k = 0; k < 7; ++k) {
+      views[k]->ptr = base;
+      views[k]->bytes = sizes[k];
+      views[k]->view = true;
+      base += align256(sizes[k]);
+    }
+  }
 
   // scratch: partials, flags, Gram, power-iteration work
   // at least 16 elements per thread (4096 per workgroup) keep enough loads
@@ -1150,7 +1160,8 @@ void build_index_t(Index& ix, const T* X) {
   const int proj_cap = 4 * di.cus * 8;
   const size_t off_bmax = off_C + ((sizeof(double) * dd + 255) & ~size_t(255));
   const size_t off_keys = off_bmax + ((sizeof(double) * proj_cap + 255) & ~size_t(255));
-  const size_t total = off_keys + 2 * sizeof(uint32_t) * n + 256;
+  const size_t off_sort = off_keys + align256(2 * sizeof(uint32_t) * n);
+  const size_t total = off_sort + radix_sort_ws_bytes(n) + 256;
   ScopedAlloc scratch(ix.arena, total);
   char* mem = static_cast<char*>(scratch.get());
   Scratch* sc = reinterpret_cast<Scratch*>(mem);
@@ -1202,7 +1213,7 @@ void build_index_t(Index& ix, const T* X) {
     k_power_iter<1024><<<1, 1024, 2 * sizeof(double) * d, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
   SNN_LAUNCH_CHECK();
   launch_project<T>(X, n, d, ix.mu.as<double>(), ix.v.as<double>(), ukey, val, bmax, &sc->max_norm, proj_cap, s);
-  radix_sort_pairs(ix.arena, ukey, val, n, 0, 32, s);
+  radix_sort_pairs_ws(ukey, val, n, 0, 32, mem + off_sort, s);
   T* po = ix.po.as<T>();
   double* p64 = ix.p64.as<double>();
   launch_gather<T>(X, n, d, ix.dp, ix.mu.as<double>(), ukey, val, ix.key.as<double>(), ix.perm.as<int32_t>(), po, p64,
@@ -1384,6 +1395,11 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   std::swap(ix.ys, ys);
   std::swap(ix.h, h);
   std::swap(ix.ynorm, ynorm);
+  // the arrays of the build (views into one allocation) are all replaced
+  if (key.view) {
+    for (Buffer* b : {&key, &perm, &po, &p64, &ys, &h, &ynorm}) b->reset(ix.arena);
+    ix.rows.reset(ix.arena);
+  }
 
   // bounds over all points; screen operands are rebuilt on the next query
   const double u64 = std::ldexp(1.0, -53), u32 = std::ldexp(1.0, -24);

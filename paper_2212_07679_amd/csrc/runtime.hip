@@ -71,9 +71,10 @@ void Buffer::ensure(DeviceArena& a, size_t need) {
 }
 
 void Buffer::reset(DeviceArena& a) {
-  if (ptr) a.release(ptr);
+  if (ptr && !view) a.release(ptr);
   ptr = nullptr;
   bytes = 0;
+  view = false;
 }
 
 const DeviceInfo& device_info(int device) {
@@ -1094,8 +1095,8 @@ struct snn_index_s : Index {
 static void free_index(snn_index_s* ix) {
   if (!ix) return;
   DeviceArena& a = ix->arena;
-  Buffer* bufs[] = {&ix->mu, &ix->v, &ix->key, &ix->perm, &ix->po, &ix->p64, &ix->ys, &ix->h, &ix->ynorm,
-                    &ix->stats_host_dev};
+  Buffer* bufs[] = {&ix->mu,    &ix->v,  &ix->key,   &ix->perm,           &ix->po,   &ix->p64,
+                    &ix->ys,    &ix->h,  &ix->ynorm, &ix->stats_host_dev, &ix->rows};
   for (Buffer* b : bufs) b->reset(a);
   for (auto& mo : ix->mixed) {
     mo.cand.reset(a);

@@ -119,6 +119,7 @@ class ScopedAlloc {
 struct Buffer {
   void* ptr = nullptr;
   size_t bytes = 0;
+  bool view = false;  // a range of another buffer: reset forgets it, frees nothing
   template <typename T>
   T* as() const {
     return reinterpret_cast<T*>(ptr);
@@ -198,6 +199,10 @@ struct Index {
   int power_iters = 0;
 
   uint64_t epoch = 0;   // raised by every change of the indexed rows
+
+  // one allocation holding key, perm, po, p64, ys, h and ynorm as views
+  // (each allocation may cross into the caller's allocator)
+  Buffer rows;
 
   // per-call workspace (grow-only)
   Buffer ws[16];
