@@ -241,6 +241,20 @@ def _check(status: int):
         raise SnnError(status, lib().snn_last_error().decode())
 
 
+_ALLOCATORS = {}
+
+
+def _allocator(device: int, stream: Optional[torch.cuda.Stream] = None) -> "_TorchAllocator":
+    """One allocator per (device, stream), shared by the indexes and plans on
+    it (creating the ctypes callbacks costs tens of microseconds)."""
+    st = stream if stream is not None else torch.cuda.current_stream(device)
+    key = (device, st.cuda_stream)
+    a = _ALLOCATORS.get(key)
+    if a is None:
+        a = _ALLOCATORS[key] = _TorchAllocator(device, st)
+    return a
+
+
 class _TorchAllocator:
     """snn_device backed by torch's caching allocator on one device/stream."""
 
@@ -307,7 +321,7 @@ class Index:
         self.device = X.device.index if X.device.index is not None else torch.cuda.current_device()
         self.dtype = X.dtype
         self.n, self.d = X.shape
-        self._alloc = _TorchAllocator(self.device, stream)
+        self._alloc = _allocator(self.device, stream)
         self._devobj = torch.device("cuda", self.device)
         self._h = ctypes.c_void_p()
         self._nnz_hint = 0
@@ -535,7 +549,7 @@ def sort_pairs_u32(keys: torch.Tensor, vals: torch.Tensor, begin_bit: int = 0, e
     if not keys.is_contiguous() or not vals.is_contiguous():
         raise SnnError(SNN_EINVAL, "keys and vals must be contiguous")
     device = keys.device.index
-    alloc = _TorchAllocator(device)
+    alloc = _allocator(device)
     _check(lib().snn_sort_pairs_u32(ctypes.byref(alloc.dev), ctypes.c_void_p(keys.data_ptr()),
                                     ctypes.c_void_p(vals.data_ptr()), keys.numel(), begin_bit, end_bit))
 
@@ -569,7 +583,7 @@ def normalize_rows(X: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch
     if out.shape != X.shape or out.dtype != X.dtype or not out.is_contiguous() or out.device != X.device:
         raise SnnError(SNN_EINVAL, "out must be a contiguous tensor like X")
     device = X.device.index if X.device.index is not None else torch.cuda.current_device()
-    alloc = _TorchAllocator(device)
+    alloc = _allocator(device)
     _check(lib().snn_normalize_rows(ctypes.byref(alloc.dev), ctypes.c_void_p(X.data_ptr()), X.shape[0], X.shape[1],
                                     _dtype_code(X), ctypes.c_void_p(out.data_ptr())))
     return out
@@ -593,7 +607,7 @@ def dbscan_csr(row_ptr: torch.Tensor, col: torch.Tensor, min_samples: int = 5,
     col = col.contiguous()
     n = row_ptr.numel() - 1
     device = row_ptr.device.index if row_ptr.device.index is not None else torch.cuda.current_device()
-    alloc = _TorchAllocator(device, stream)
+    alloc = _allocator(device, stream)
     with torch.cuda.device(device), torch.cuda.stream(alloc.stream):
         labels = torch.empty(max(n, 1), dtype=torch.int32, device=f"cuda:{device}")
         core = torch.empty(max(n, 1), dtype=torch.uint8, device=f"cuda:{device}")
@@ -636,7 +650,7 @@ class Batch:
             raise SnnError(SNN_EINVAL, "X must be CUDA tensors")
         self.dtype = X0.dtype
         self.device = X0.device.index if X0.device.index is not None else torch.cuda.current_device()
-        self._alloc = _TorchAllocator(self.device, stream)
+        self._alloc = _allocator(self.device, stream)
         self._keep = []
         self.count = len(instances)
         self._csr = (snn_csr * self.count)()

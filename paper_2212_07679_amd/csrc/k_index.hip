@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <type_traits>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "device_common.h"
@@ -1219,14 +1220,17 @@ void build_index_t(Index& ix, const T* X) {
   launch_gather<T>(X, n, d, ix.dp, ix.mu.as<double>(), ukey, val, ix.key.as<double>(), ix.perm.as<int32_t>(), po, p64,
                    ix.ys.as<float>(), ix.h.as<float>(), ix.ynorm.as<float>(), 0, 4 * di.cus * 8, s);
 
-  Scratch hs;
-  SNN_HIP(hipMemcpyAsync(&hs, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+  // one read-back into page-locked memory: the flags and the direction
+  char* hb = static_cast<char*>(pinned_host(256 + sizeof(double) * d));
+  SNN_HIP(hipMemcpyAsync(hb, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+  SNN_HIP(hipMemcpyAsync(hb + 256, ix.v.ptr, sizeof(double) * d, hipMemcpyDeviceToHost, s));
   SNN_HIP(hipStreamSynchronize(s));
+  Scratch hs;
+  std::memcpy(&hs, hb, sizeof(Scratch));
   if (hs.bad) fail(SNN_EINVAL, "snn_index: X contains NaN or Inf");
-  std::vector<double> vh(d);
-  SNN_HIP(hipMemcpy(vh.data(), ix.v.ptr, sizeof(double) * d, hipMemcpyDeviceToHost));
+  const double* vh = reinterpret_cast<const double*>(hb + 256);
   double vn = 0.0;
-  for (double x : vh) vn += x * x;
+  for (int k = 0; k < d; ++k) vn += vh[k] * vh[k];
   const double u64 = std::ldexp(1.0, -53), u32 = std::ldexp(1.0, -24);
   ix.vnorm = std::sqrt(vn) * (1.0 + 4.0 * (d + 2) * u64);
   ix.max_norm = std::sqrt(hs.max_norm) * (1.0 + 4.0 * (d + 2) * u64);

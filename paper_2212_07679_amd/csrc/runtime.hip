@@ -146,6 +146,20 @@ DeviceScope::~DeviceScope() {
 
 void set_last_error(const std::string& msg) { g_err = msg; }
 
+void* pinned_host(size_t bytes) {
+  thread_local void* p = nullptr;
+  thread_local size_t cap = 0;
+  if (bytes > cap) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+    const size_t want = std::max<size_t>(bytes, 64 * 1024);
+    SNN_HIP(hipHostMalloc(&p, want, hipHostMallocDefault));
+    cap = want;
+  }
+  return p;
+}
+
 static int env_int(const char* name) {
   const char* v = std::getenv(name);
   return v && *v ? std::atoi(v) : 0;

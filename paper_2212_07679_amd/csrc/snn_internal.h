@@ -25,6 +25,11 @@ void check_hip(hipError_t e, const char* what, const char* file, int line);
 #define SNN_HIP(call) ::snn::check_hip((call), #call, __FILE__, __LINE__)
 #define SNN_LAUNCH_CHECK() ::snn::check_hip(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
 
+// Page-locked host memory of at least `bytes` for small read-backs, one
+// block per host thread, kept until the process ends (a copy into pageable
+// memory is staged by the runtime and costs the call microseconds).
+void* pinned_host(size_t bytes);
+
 // thread-local message returned by snn_last_error()
 void set_last_error(const std::string& msg);
 // set_last_error plus, with SNN_LOG >= 1, a line on stderr
