@@ -696,7 +696,11 @@ class Batch:
         _check(lib().snn_batch_info(self._h, ctypes.byref(inf)))
         return inf.as_dict()
 
-    def run(self, index: bool = True, query: bool = True, stats: bool = False):
+    def run(self, index: bool = True, query: bool = True, stats: bool = False, views: bool = True):
+        """Launches the pass(es) and waits.  Returns one (row_ptr, col, dist)
+        per instance (views of the output buffers cut at nnz), or with
+        ``views=False`` only the nnz of each instance (the lists are the first
+        nnz entries of ``buffers()[i]``; no tensor is made per call)."""
         what = (SNN_BATCH_INDEX if index else 0) | (SNN_BATCH_QUERY if query else 0)
         dev = f"cuda:{self.device}"
         st = snn_stats()
@@ -720,8 +724,15 @@ class Batch:
                 _check(status)
         if not query:
             return st.as_dict() if stats else None
-        res = [(o[0], o[1][: int(self._csr[i].nnz)], o[2][: int(self._csr[i].nnz)]) for i, o in enumerate(self._out)]
+        if views:
+            res = [(o[0], o[1][: int(self._csr[i].nnz)], o[2][: int(self._csr[i].nnz)]) for i, o in enumerate(self._out)]
+        else:
+            res = [int(c.nnz) for c in self._csr]
         return (res, st.as_dict()) if stats else res
+
+    def buffers(self):
+        """The output buffers (row_ptr, col, dist) of every instance."""
+        return [tuple(o) for o in self._out]
 
     def close(self):
         if getattr(self, "_h", None):

@@ -545,12 +545,20 @@ RunResult run_graphs(BatchPlan& p, bool do_index, bool do_query) {
       SNN_HIP(hipGraphLaunch(p.g_query, s));
     SNN_HIP(hipEventRecord(e1, s));
     index_pending = false;
-    std::vector<BatchDyn> dyn(p.count);
-    SNN_HIP(hipMemcpyAsync(dyn.data(), p.d_dyn, sizeof(BatchDyn) * p.count, hipMemcpyDeviceToHost, s));
-    SNN_HIP(hipMemcpyAsync(&rr.ctl, p.ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
-    SNN_HIP(hipMemcpyAsync(rr.nnz.data(), p.nnz, sizeof(int64_t) * p.count, hipMemcpyDeviceToHost, s));
-    SNN_HIP(hipMemcpyAsync(&rr.total, p.nnz_base + p.count, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    // one read-back into page-locked memory (pageable copies are staged)
+    const size_t o_ctl = align256(sizeof(BatchDyn) * p.count), o_nnz = o_ctl + align256(sizeof(BatchCtl)),
+                 o_tot = o_nnz + align256(sizeof(int64_t) * p.count);
+    char* hb = static_cast<char*>(pinned_host(o_tot + sizeof(int64_t)));
+    SNN_HIP(hipMemcpyAsync(hb, p.d_dyn, sizeof(BatchDyn) * p.count, hipMemcpyDeviceToHost, s));
+    SNN_HIP(hipMemcpyAsync(hb + o_ctl, p.ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, s));
+    SNN_HIP(hipMemcpyAsync(hb + o_nnz, p.nnz, sizeof(int64_t) * p.count, hipMemcpyDeviceToHost, s));
+    SNN_HIP(hipMemcpyAsync(hb + o_tot, p.nnz_base + p.count, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SNN_HIP(hipStreamSynchronize(s));
+    std::vector<BatchDyn> dyn(p.count);
+    std::memcpy(dyn.data(), hb, sizeof(BatchDyn) * p.count);
+    std::memcpy(&rr.ctl, hb + o_ctl, sizeof(BatchCtl));
+    std::memcpy(rr.nnz.data(), hb + o_nnz, sizeof(int64_t) * p.count);
+    std::memcpy(&rr.total, hb + o_tot, sizeof(int64_t));
     SNN_HIP(hipEventElapsedTime(&rr.graph_ms, e0, e1));
     for (int i = 0; i < p.count; ++i)
       if (dyn[i].bad) fail(SNN_EINVAL, "instance " + std::to_string(i) + ": X contains NaN or Inf");

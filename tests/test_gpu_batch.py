@@ -100,6 +100,13 @@ def test_batch_mixed_instances(B, dtype):
     assert st["nnz"] == sum(int(r[0][-1]) for r in res)
     assert st["pairs_window"] > 0 and st["pairs_executed"] >= st["pairs_window"] // 2
     say(f"  info {bt.info()}, stats {st}")
+    # the query pass again without per-instance views: the counts, and the
+    # lists at the head of the output buffers
+    nnz = bt.run(index=False, views=False)
+    bufs = bt.buffers()
+    for i, (P, Q, R) in enumerate(insts):
+        assert nnz[i] == int(res[i][0][-1]), f"instance {i}"
+        check_same((bufs[i][0], bufs[i][1][: nnz[i]], bufs[i][2][: nnz[i]]), oracle_of(P, Q, R), f"instance {i} (buffers)")
     bt.close()
 
 
