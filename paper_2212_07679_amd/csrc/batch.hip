@@ -130,6 +130,7 @@ struct BatchPlan {
 
   // graphs: index pass, query pass, both
   hipGraphExec_t g_index = nullptr, g_query = nullptr, g_all = nullptr;
+  bool f16 = false;           // the 16-bit screen on fp16 operands (every instance), else bf16
   bool screen_timed = false;  // device clock stamps bracket the screen in the query graph
   bool profiled = false;      // ... and every stage of the query pass (SNN_PROFILE at creation)
   double clock_khz = 0;       // frequency of that clock
@@ -441,6 +442,7 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
   mx.h = p.h;
   mx.KA = p.KA;
   mx.KB = p.KA;
+  mx.f16 = p.f16 ? 1 : 0;
   if (timed) batch_stamp(&p.ctl->stamp[2], s);
   if (p.n16) launch_cand_mfma(qd, mx, p.screen_grid, s);
   if (p.NK32) {
@@ -592,7 +594,7 @@ std::string tune_key(const BatchPlan& p) {
   std::map<std::pair<int, int>, int> mix;
   for (const BatchInst& b : p.inst) mix[{b.d, b.terms}]++;
   std::ostringstream k;
-  k << "gfx950 KA=" << p.KA << " T=" << p.T << " I=" << p.count << " logN=" << (int)std::log2((double)p.N + 1)
+  k << "gfx950 KA=" << p.KA << (p.f16 ? " f16" : "") << " T=" << p.T << " I=" << p.count << " logN=" << (int)std::log2((double)p.N + 1)
     << " logM=" << (int)std::log2((double)p.M + 1);
   for (auto& e : mix) k << " d" << e.first.first << "t" << e.first.second << "x" << e.second;
   return k.str();
@@ -695,7 +697,7 @@ void fill_stats(const BatchPlan& p, const RunResult& rr, snn_stats* st) {
   st->pairs_executed = (int64_t)rr.ctl.executed;
   st->pairs_recheck = (int64_t)rr.ctl.survivors;
   st->nnz = rr.total;
-  st->precision_used = SNN_PREC_MIXED;
+  st->precision_used = p.f16 ? SNN_PREC_FP16 : SNN_PREC_MIXED;
   st->terms_used = p.max_terms;
   st->screen_ms = rr.screen_ms;
   st->total_ms = rr.graph_ms;
@@ -787,6 +789,7 @@ BatchPlan* create_batch(const snn_device& devc, snn_dtype dtype, const snn_insta
     p.max_terms = 1;
     p.NK32 = 0;
     p.n16 = 0;
+    bool all_f16 = o.mixed_terms == 0;
     for (int i = 0; i < count; ++i) {
       if (dyn[i].bad) fail(SNN_EINVAL, "instance " + std::to_string(i) + ": X contains NaN or Inf");
       BatchInst& b = p.inst[i];
@@ -797,6 +800,9 @@ BatchPlan* create_batch(const snn_device& devc, snn_dtype dtype, const snn_insta
         // three while theirs is <= 0.5 R^2, else the fp32 screen for d <= 16
         const double Y = std::sqrt(dyn[i].maxnorm2);
         auto band = [&](int kind) { return b.R2 > 0 ? 2.0 * mixed_c_rep(kind) * Y * Y / b.R2 : INFINITY; };
+        // (the bound's Y, rounded up as the index pass rounds it)
+        const double Yup = Y * (1.0 + 4.0 * (b.d + 2) * 1.1102230246251565e-16);
+        if (!(screen_in_range(kOpF16, Yup) && b.d <= kBatchMaxD && band(kOpF16) <= 1.0)) all_f16 = false;
         if (band(kOpBf16) <= 0.1 || 3 * b.d > kBatchMaxD)
           t = 1;
         else if (band(kOpBf16x3) <= 0.5 || b.d > mfma32_max_d() || !screen_in_range(kOpF32, Y))
@@ -814,10 +820,27 @@ BatchPlan* create_batch(const snn_device& devc, snn_dtype dtype, const snn_insta
         KA = std::max(KA, pad16(t * b.d));
       }
     }
+    // fp16 operands for every instance when each one's fp16 band is at most
+    // R^2 (the single-instance policy), its rows scale into fp16, and the
+    // shared operand row gets shorter: one product per coordinate where bf16
+    // needs three.  The 16-bit screen of a launch has one operand type and
+    // one row length for all instances, so the choice is made for the whole
+    // batch; with the same row length the three bf16 terms keep a narrower
+    // band (batch256: 10.7e6 against 8.3e6 survivors at the same screen time).
+    int KA16 = 16;
+    for (const BatchInst& b : p.inst) KA16 = std::max(KA16, pad16(b.d));
+    p.f16 = all_f16 && count > 0 && KA16 < KA;
+    if (p.f16) {
+      p.NK32 = 0;
+      p.n16 = count;
+      p.max_terms = 1;
+      KA = KA16;
+      for (BatchInst& b : p.inst) b.terms = kOpF16;
+    }
     p.D32 = 2 * p.NK32;
     p.DV32 = p.NK32 ? mfma32_query_floats(p.D32) : 0;
     p.KA = KA;
-    p.T = 4 * mixed_queries_per_wave(KA, false);  // bf16 operands
+    p.T = 4 * mixed_queries_per_wave(KA, p.f16);
     if (p.NK32 && p.T != mfma32_batch_queries_per_tile())
       fail(SNN_EDEVICE, "internal: the fp32 and 16-bit screens need one tile size");
     p.CH = o.tile_c ? o.tile_c : 4096;
@@ -833,7 +856,7 @@ BatchPlan* create_batch(const snn_device& devc, snn_dtype dtype, const snn_insta
     alloc_survivors(p, std::max<int64_t>(1 << 20, 2 * p.M + caps));
     alloc_stage(p, std::max<int64_t>(1 << 16, caps));
     const DeviceInfo& di = device_info(devc.device);
-    const int per_cu = mixed_blocks_per_cu(p.KA, p.KA, false);
+    const int per_cu = mixed_blocks_per_cu(p.KA, p.KA, p.f16);
     p.screen_grid = std::max(di.xcds, (di.cus * per_cu / di.xcds) * di.xcds);
     if (p.NK32) {
       const int per_cu32 = mfma32_batch_blocks_per_cu(p.D32);

@@ -30,7 +30,7 @@ struct BatchInst {
   int64_t n, m;
   int d;
   int dp;     // float64 row stride of the p64 / q64 rows (even, zero padded)
-  int terms;  // screen operands: bf16 terms per coordinate (1 or 3), or 0 for the fp32 screen
+  int terms;  // screen operands (OperandKind): bf16 with 1 or 3 terms, 4 = fp16 (one term of 2^e y), 0 = fp32
   int ntiles;
   double R, R2;  // radius and fl(R*R)
   int64_t in_off;     // first data row in input order (prefix sum of n)
@@ -57,6 +57,8 @@ struct BatchDyn {
   MixedBound mb;    // screen start-value constants
   int bad;          // NaN or Inf in X or Q
   int iters;        // power iterations run
+  int e16;           // fp16 screen: the operands are fp16(2^e16 y), h in units of 2^(2 e16)
+  int pad1;
 };
 
 // Caller's output arrays of instance i (rewritten before every run).

@@ -58,7 +58,11 @@ __device__ __forceinline__ int find_seg(const int64_t* __restrict__ off, int cou
 // queries [hi | hi | lo], hi = bf16(y), lo = bf16(y - hi).
 template <typename T>
 __device__ __forceinline__ uint16_t operand_value(int terms, int d, int k, const T* __restrict__ x,
-                                                  const double* __restrict__ mu, bool query) {
+                                                  const double* __restrict__ mu, bool query, int e16) {
+  if (terms == kOpF16) {  // fp16 of the row scaled by 2^e16 (exact scaling, one rounding)
+    if (k >= d) return 0;
+    return __builtin_bit_cast(uint16_t, (_Float16)ldexpf((float)((double)x[k] - mu[k]), e16));
+  }
   if (terms == 1) {
     if (k >= d) return 0;
     return f32_to_bf16_rne((float)((double)x[k] - mu[k]));
@@ -79,14 +83,14 @@ constexpr int kQG = 16;
 // c8_0 + c8_step, ... (several lanes may share a row).
 template <typename T, typename Dst>
 __device__ __forceinline__ void write_operand_row(int terms, int d, int KA, const T* __restrict__ x,
-                                                  const double* __restrict__ mu, bool query, Dst dst, int c8_0 = 0,
-                                                  int c8_step = 1) {
+                                                  const double* __restrict__ mu, bool query, int e16, Dst dst,
+                                                  int c8_0 = 0, int c8_step = 1) {
   for (int c8 = c8_0; c8 < KA / 8; c8 += c8_step) {
     uint32_t w[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const uint32_t a = operand_value<T>(terms, d, 8 * c8 + 2 * e, x, mu, query);
-      const uint32_t b = operand_value<T>(terms, d, 8 * c8 + 2 * e + 1, x, mu, query);
+      const uint32_t a = operand_value<T>(terms, d, 8 * c8 + 2 * e, x, mu, query, e16);
+      const uint32_t b = operand_value<T>(terms, d, 8 * c8 + 2 * e + 1, x, mu, query, e16);
       w[e] = a | (b << 16);
     }
     *dst(c8) = make_uint4(w[0], w[1], w[2], w[3]);
@@ -375,6 +379,7 @@ __global__ void kb_finalize(BatchDev b) {
   dy.eps_scale = 1.01 * (kU32 + gamma64d(d + 2)) * (1.0 + kU32) * dy.vnorm;
   // terms 0: the fp32 screen (kOpF32) over D32 coordinates
   dy.mb = mixed_bound(in.terms, in.terms == 0 ? b.D32 : b.KA, d, in.R2, Y);
+  dy.e16 = in.terms == kOpF16 ? f16_scale_exp(Y) : 0;
 }
 
 // ---- rows into score order ---------------------------------------------------------
@@ -415,7 +420,15 @@ __global__ __launch_bounds__(kThreads) void kb_gather(BatchDev b, const double* 
     if (sub == 0) {
       key[R] = (double)ordered_to_float(ukey[p]);
       perm[R] = (int32_t)local;
-      h[R] = (float)(0.5 * nn);
+      float hv = (float)(0.5 * nn);
+      if (in.terms == kOpF16) {
+        // h in the accumulator's units 2^(2 e16): exact unless it lands below
+        // fp32's normal range, then rounded down (the screen passes more)
+        const double x2 = ldexp((double)hv, 2 * b.dyn[i].e16);
+        hv = (float)x2;
+        if ((double)hv > x2) hv = nextafterf(hv, -INFINITY);
+      }
+      h[R] = hv;
     }
     if (in.terms == 0) {
       // fp32 screen: coordinate k of row R at slice k / 2, lane R % 32 + 32 (k % 2)
@@ -427,8 +440,8 @@ __global__ __launch_bounds__(kThreads) void kb_gather(BatchDev b, const double* 
     // candidate operands in the 32-row block layout of the matrix-core screen
     uint16_t* blk = cop + (R / 32) * (int64_t)KA * 32 + (R % 32) * 8;
     write_operand_row<T>(
-        in.terms, d, KA, x, m, false, [&](int c8) { return reinterpret_cast<uint4*>(blk + (int64_t)c8 * 256); },
-        sub, kQG);
+        in.terms, d, KA, x, m, false, b.dyn[i].e16,
+        [&](int c8) { return reinterpret_cast<uint4*>(blk + (int64_t)c8 * 256); }, sub, kQG);
   }
 }
 
@@ -548,7 +561,8 @@ __global__ __launch_bounds__(kThreads) void kb_query_gather(
         row32[k] = k < d ? (float)((double)q[k] - m[k]) : (k == b.D32 ? c : 0.f);
     } else {
       uint16_t* row = qop + s * KA;
-      for (int k = lane; k < KA; k += kQG) row[k] = operand_value<T>(in.terms, d, k, q, m, true);
+      const int e16 = b.dyn[i].e16;
+      for (int k = lane; k < KA; k += kQG) row[k] = operand_value<T>(in.terms, d, k, q, m, true, e16);
     }
     if (lane == 0) {
       qorig[s] = (int32_t)g;

@@ -206,6 +206,49 @@ def test_batch_overflow_growth(B):
     bt.close()
 
 
+def fp16_instances(seed=0):
+    """Instances whose bf16 one-term band is too wide (three bf16 terms would
+    run) but whose fp16 band is at most R^2: the whole batch takes the fp16
+    screen.  Uneven sizes and dimensions, a self-query, a ragged tile."""
+    g = np.random.default_rng([2212, 7679, 79, seed])
+
+    def blobs(cent, n, sd):
+        return (cent[g.integers(0, len(cent), n)] + g.normal(0, sd, (n, cent.shape[1]))).astype(np.float32)
+
+    c16, c32 = g.random((25, 16)), g.random((25, 32))
+    return [
+        (g.random((3000, 8)).astype(np.float32), g.random((301, 8)).astype(np.float32), 0.25),
+        (blobs(c16, 2500, 0.06), None, 0.45),
+        (g.random((1200, 3)).astype(np.float32), g.random((97, 3)).astype(np.float32), 0.09),
+        (blobs(c32, 4000, 0.08), blobs(c32, 450, 0.08), 0.9),
+    ]
+
+
+def test_batch_fp16_screen(B):
+    insts = fp16_instances()
+    refs = [oracle_of(P, Q, R) for P, Q, R in insts]
+    say(f"batch on the fp16 screen: nnz {[int(r.row_ptr[-1]) for r in refs]}")
+    dev, bt = make_batch(B, insts)
+    say(f"  info {bt.info()}")
+    for rep in range(2):
+        res, st = bt.run(stats=True)
+        assert B.PRECISION_NAMES[st["precision_used"]] == "fp16", st
+        for i, (P, Q, R) in enumerate(insts):
+            check_same(res[i], refs[i], f"run {rep} instance {i} (n={P.shape[0]}, d={P.shape[1]}, R={R})")
+    # new data in the same buffers: index and query passes replayed
+    g = np.random.default_rng(10)
+    new = []
+    for (Pd, Qd, R), (P, Q, _) in zip(dev, insts):
+        P2 = (P + g.normal(0, 1e-3, P.shape)).astype(np.float32)
+        Pd.copy_(torch.from_numpy(P2))
+        new.append((P2, Q, R))
+    torch.cuda.synchronize()
+    res = bt.run()
+    for i, (P, Q, R) in enumerate(new):
+        check_same(res[i], oracle_of(P, Q, R), f"new data instance {i}")
+    bt.close()
+
+
 def test_batch_terms_choice_and_forced(B):
     insts = mixed_instances(np.float32, seed=2)[:5]
     for terms in (1, 3):
