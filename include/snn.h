@@ -46,6 +46,10 @@
  *                     that events can sit between the stages); a batch
  *                     created with SNN_PROFILE=1 has clock stamps between
  *                     the stages inside its query graph.
+ *   SNN_FAULT_INJECT=n  (tests) the n-th checked HIP result of each call
+ *                     reads as a failure: the call returns SNN_EDEVICE after
+ *                     freeing what it allocated, every kernel it launched
+ *                     still runs to its end, and an index stays usable.
  */
 #ifndef SNN_H_
 #define SNN_H_

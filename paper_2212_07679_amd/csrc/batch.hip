@@ -475,7 +475,10 @@ void enqueue_query(BatchPlan& p, hipStream_t s, bool timed) {
 template <class F>
 hipGraphExec_t capture(BatchPlan& p, F&& body) {
   hipStream_t s = p.cap_stream;
-  SNN_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  // (begin and end of a capture are checked only when they fail: an injected
+  // failure would leave the stream capturing or the graph unowned)
+  const hipError_t eb = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (eb != hipSuccess) check_hip(eb, "hipStreamBeginCapture", __FILE__, __LINE__);
   hipGraph_t graph = nullptr;
   try {
     body(s);
@@ -485,7 +488,10 @@ hipGraphExec_t capture(BatchPlan& p, F&& body) {
     (void)hipGetLastError();
     throw;
   }
-  SNN_HIP(hipStreamEndCapture(s, &graph));
+  {
+    const hipError_t ee = hipStreamEndCapture(s, &graph);
+    if (ee != hipSuccess) check_hip(ee, "hipStreamEndCapture", __FILE__, __LINE__);
+  }
   hipGraphExec_t exec = nullptr;
   hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);

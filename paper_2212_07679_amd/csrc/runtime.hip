@@ -29,9 +29,18 @@ thread_local std::string g_err;
 
 void fail(snn_status code, const std::string& msg) { throw Error(code, msg); }
 
+// SNN_FAULT_INJECT=n (tests): the n-th checked HIP result of an entry
+// point's call reads as a failure (the call itself was made), so that every
+// error path can be driven from the host; set per call by DeviceScope.
+thread_local long t_fault_countdown = 0;
+
 void check_hip(hipError_t e, const char* what, const char* file, int line) {
-  if (e == hipSuccess) return;
   char buf[512];
+  if (t_fault_countdown > 0 && --t_fault_countdown == 0) {
+    std::snprintf(buf, sizeof(buf), "injected HIP failure (SNN_FAULT_INJECT) in %s at %s:%d", what, file, line);
+    throw Error(SNN_EDEVICE, buf);
+  }
+  if (e == hipSuccess) return;
   std::snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), what, file,
                 line);
   throw Error(e == hipErrorOutOfMemory ? SNN_ENOMEM : SNN_EDEVICE, buf);
@@ -108,6 +117,10 @@ const DeviceInfo& device_info(int device) {
 
 // Select the device of `dev` for the duration of a call, check it is gfx950.
 DeviceScope::DeviceScope(int device) {
+  {
+    const char* f = std::getenv("SNN_FAULT_INJECT");
+    t_fault_countdown = f && *f ? std::atol(f) : 0;
+  }
   // device count and architecture are checked once per process and device
   // (every call passes through here; each HIP query costs the host time on
   // the call's critical path)
@@ -405,7 +418,10 @@ static void run_captured(Index& ix, hipGraphExec_t* g, bool capture, F&& body) {
     body();
     return;
   }
-  SNN_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  // (checked only when it fails: an injected failure after a begun capture
+  // would leave the stream capturing)
+  const hipError_t eb = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (eb != hipSuccess) check_hip(eb, "hipStreamBeginCapture", __FILE__, __LINE__);
   hipGraph_t graph = nullptr;
   try {
     body();
@@ -414,7 +430,10 @@ static void run_captured(Index& ix, hipGraphExec_t* g, bool capture, F&& body) {
     if (graph) (void)hipGraphDestroy(graph);
     throw;
   }
-  SNN_HIP(hipStreamEndCapture(s, &graph));
+  {
+    const hipError_t ee = hipStreamEndCapture(s, &graph);
+    if (ee != hipSuccess) check_hip(ee, "hipStreamEndCapture", __FILE__, __LINE__);
+  }
   hipGraphExec_t exec = nullptr;
   const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
