@@ -46,6 +46,8 @@
  *                     that events can sit between the stages); a batch
  *                     created with SNN_PROFILE=1 has clock stamps between
  *                     the stages inside its query graph.
+ *   SNN_TUNE_CACHE=path  the batch autotuner's cache file when the batch
+ *                     options name none.
  *   SNN_FAULT_INJECT=n  (tests) the n-th checked HIP result of each call
  *                     reads as a failure: the call returns SNN_EDEVICE after
  *                     freeing what it allocated, every kernel it launched
@@ -275,7 +277,8 @@ typedef struct {
   int32_t tile_c;         /* candidates per work unit (multiple of 32); 0: tuned / 4096 */
   int32_t tile_g;         /* tiles per work group; 0: tuned / 8 */
   int32_t autotune;       /* 1: time candidate (tile_c, tile_g) on this batch at creation */
-  const char* tune_cache; /* host path of a tuning cache file (read and appended), or NULL */
+  const char* tune_cache; /* host path of a tuning cache file (read and appended), or NULL:
+                             then SNN_TUNE_CACHE from the environment, if set */
 } snn_batch_options;
 
 typedef struct {

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -872,7 +873,8 @@ BatchPlan* create_batch(const snn_device& devc, snn_dtype dtype, const snn_insta
     // first run: builds the index and sizes the survivor / staging arrays
     run_graphs(p, true, true);
     if (o.autotune && p.M > 0 && !o.tile_c && !o.tile_g) {
-      autotune(p, o.tune_cache);
+      // the options' cache file, else the environment's SNN_TUNE_CACHE
+      autotune(p, o.tune_cache ? o.tune_cache : std::getenv("SNN_TUNE_CACHE"));
       build_graphs(p);
     }
     return pp;
