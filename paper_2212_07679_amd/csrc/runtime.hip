@@ -870,8 +870,17 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
     // by length class; then the caller's row offsets
     launch_rows_scan(P.row_cnt, m, P.rp_s, P.lb_rows, &P.ctl->scan_err,
                      RowsExtra{qorig, P.cnt_o, &P.ctl->row_max, &P.ctl->nnz, P.lists, P.ctl->list_counts}, s);
-    launch_rows_scan_scatter(P.cnt_o, m, out->row_ptr, P.lb_rows + lookback_words(m), &P.ctl->scan_err, sv, P.rp_s,
-                             stage_key, sgrid, s);
+    // the caller-order scan and the scatter in one launch for short survivor
+    // lists (one launch fewer); for long ones (dense outputs) apart, as the
+    // scan's registers and LDS would hold down the scatter's occupancy
+    // (blobs3d: 4.7 ms fused against 3.9 + 0.1 ms)
+    if (cap <= (1LL << 20)) {
+      launch_rows_scan_scatter(P.cnt_o, m, out->row_ptr, P.lb_rows + lookback_words(m), &P.ctl->scan_err, sv,
+                               P.rp_s, stage_key, sgrid, s);
+    } else {
+      launch_rows_scan(P.cnt_o, m, out->row_ptr, P.lb_rows + lookback_words(m), &P.ctl->scan_err, RowsExtra{}, s);
+      launch_scatter(sv, P.rp_s, stage_key, sgrid, s);
+    }
     launch_row_sort_short(mv, P.lists, P.ctl->list_counts, s);
     end_mark(false);
   };
