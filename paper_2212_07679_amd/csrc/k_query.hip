@@ -618,21 +618,13 @@ void launch_clock_mark(unsigned long long* out, hipStream_t s) {
 
 int window_blocks(int64_t m) { return m > 0 ? grid_for(m, kWindowMaxBlocks) : 0; }
 
-void launch_windows(const double* key, int n, const int32_t* cells, int C, const double* qalpha,
-                    const double* qnorm, int64_t m, double w_base, double eps_scale, int T, int sym, int32_t* lo,
-                    int32_t* hi, int32_t* tlo, int32_t* thi, unsigned long long* wpart, hipStream_t s) {
-  if (m <= 0) return;
-  k_window<<<window_blocks(m), kThreads, 0, s>>>(key, n, cells, C, qalpha, qnorm, m, w_base, eps_scale, T, sym, lo,
-                                                 hi, tlo, thi, wpart);
-  SNN_LAUNCH_CHECK();
-}
-
 void launch_windows_plan(const double* key, int n, const int32_t* cells, int C, const double* qalpha,
                          const double* qnorm, int64_t m, double w_base, double eps_scale, int T, int sym, int32_t* lo,
                          int32_t* hi, const TilePlanArgs& plan, hipStream_t s) {
   // (The plan run by the last k_window workgroup to finish, found with a
   // ticket, gave no shorter call: with device-scope fences it took 20 us
-  // longer, as such a fence writes back the XCD's whole L2.)
+  // longer, as such a fence writes back the XCD's whole L2, and with
+  // device-scope loads and workgroup fences it was no faster.)
   TilePlanArgs pa = plan;
   pa.nwpart = window_blocks(m);
   if (m > 0) {

@@ -153,8 +153,8 @@ void launch_window_table(const double* key, int n, int C, int32_t* start, hipStr
 // most kWindowMaxBlocks of them: window_blocks(m)); k_tile_plan sums them
 constexpr int kWindowMaxBlocks = 2048;
 int window_blocks(int64_t m);
-// Arguments of the tile plan (k_tile_plan, or the last workgroup of
-// k_window): per-tile windows widened to `align`, work units of CH
+// Arguments of the tile plan (k_tile_plan): per-tile windows widened to
+// `align`, work units of CH
 // candidates, groups of G tiles with their unit offsets and absolute chunk
 // bases, the executed-pair count and the window-pair total.
 struct TilePlanArgs {
@@ -180,9 +180,6 @@ struct TilePlanArgs {
 void launch_windows_plan(const double* key, int n, const int32_t* cells, int C, const double* qalpha,
                          const double* qnorm, int64_t m, double w_base, double eps_scale, int T, int sym, int32_t* lo,
                          int32_t* hi, const TilePlanArgs& plan, hipStream_t s);
-void launch_windows(const double* key, int n, const int32_t* cells, int C, const double* qalpha,
-                    const double* qnorm, int64_t m, double w_base, double eps_scale, int T, int sym, int32_t* lo,
-                    int32_t* hi, int32_t* tlo, int32_t* thi, unsigned long long* wpart, hipStream_t s);
 // one launch: zero ctl_words control words, row_cnt (m) and hist (nb, may be
 // NULL), and empty tile windows (tlo = INT_MAX, thi = INT_MIN)
 // mark_word >= 0: that word of ctl takes the device clock (wall_clock64)
