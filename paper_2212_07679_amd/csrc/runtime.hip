@@ -566,11 +566,19 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const int T = T_fixed ? T_fixed : (o.tile_q ? o.tile_q : 64);
   // candidates per work unit: 8192 for the matrix-core screens (measured best
   // against 2048-16384 with 256-query tiles), 1024 for the float64 screen
-  const int CH = o.tile_c ? o.tile_c : (prec == SNN_PREC_FP64 ? 1024 : 8192);
+  const int ntiles = (int)std::max<int64_t>(1, (m + T - 1) / T);
+  int CH = o.tile_c ? o.tile_c : (prec == SNN_PREC_FP64 ? 1024 : 8192);
+  if (!o.tile_c) {
+    // a small call: shorter units until every CU can get a few (uniform2d,
+    // 1e3 queries over 1e4 points: 6 units of 8192 candidates kept 6
+    // workgroups busy for the whole screen)
+    const int64_t want = 4LL * di.cus;
+    const int floor_ch = prec == SNN_PREC_FP64 ? 128 : 256;
+    while (CH > floor_ch && (int64_t)ntiles * ((n + CH - 1) / CH) < want) CH /= 2;
+  }
   if (prec != SNN_PREC_FP64 && CH % 32 != 0) fail(SNN_EINVAL, "matrix-core screens: tile_c must be a multiple of 32");
   if (mix16) build_mixed_operands(ix, sp.kind);
   if (prec == SNN_PREC_FP32) build_fp32_operands(ix);
-  const int ntiles = (int)std::max<int64_t>(1, (m + T - 1) / T);
 
   // stats: the device clock marks the call's start (its first kernel) and
   // end (a mark kernel after the last one), and the screen's workgroups
@@ -801,7 +809,12 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   const int per_cu = mix16                   ? mixed_blocks_per_cu(mx.KA, mx.KB, mx.f16 != 0)
                      : prec == SNN_PREC_FP32 ? mfma32_blocks_per_cu(d)
                                              : fp64_blocks_per_cu(ix.dp);
-  const int grid = std::max(di.xcds, (di.cus * per_cu / di.xcds) * di.xcds);
+  // persistent workgroups: enough to fill the chip, but no more than the
+  // work units the tile plan can make (each tile has at most ceil(n / CH) + 1
+  // chunks); a small query then does not dispatch thousands of idle ones
+  const int64_t units_max = (int64_t)ntiles * ((n + CH - 1) / CH + 1);
+  const int grid = (int)std::max<int64_t>(
+      di.xcds, std::min<int64_t>((di.cus * per_cu / di.xcds) * di.xcds, (units_max + di.xcds - 1) / di.xcds * di.xcds));
 
   // ---- the launches before the screen: queries into score order, their
   // operands, windows and the tile plan
