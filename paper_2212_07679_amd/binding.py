@@ -434,6 +434,8 @@ class Index:
                     or dist.numel() != col.numel() or not (row_ptr.is_contiguous() and col.is_contiguous()
                                                             and dist.is_contiguous())):
                 raise SnnError(SNN_EINVAL, "row_ptr / col / dist: contiguous int64 / int32 / float32, one capacity")
+            if any(not t.is_cuda or t.device.index != self.device for t in (row_ptr, col, dist)):
+                raise SnnError(SNN_EINVAL, "row_ptr / col / dist must be on the index's device")
             if len(self._csr_cache) > 16:
                 self._csr_cache.clear()
             csr = self._csr_cache[key] = snn_csr(key[0], key[1], key[2], key[3], 0)

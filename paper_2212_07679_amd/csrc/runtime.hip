@@ -163,7 +163,12 @@ void* pinned_host(size_t bytes) {
   thread_local void* p = nullptr;
   thread_local size_t cap = 0;
   if (bytes > cap) {
-    if (p) (void)hipHostFree(p);
+    // (a call that failed between its copies and their wait can leave one
+    // in flight into the old block)
+    if (p) {
+      (void)hipDeviceSynchronize();
+      (void)hipHostFree(p);
+    }
     p = nullptr;
     cap = 0;
     const size_t want = std::max<size_t>(bytes, 64 * 1024);
