@@ -1154,6 +1154,7 @@ void build_index_t(Index& ix, const T* X) {
     int bad;
     int iters;
     double max_norm;
+    int sort_err;
   };
   const size_t off_part1 = 256;
   const size_t off_part2 = off_part1 + ((sizeof(double) * g1 * d + 255) & ~size_t(255));
@@ -1214,10 +1215,11 @@ void build_index_t(Index& ix, const T* X) {
     k_power_iter<1024><<<1, 1024, 2 * sizeof(double) * d, s>>>(C, d, 500, ix.v.as<double>(), &sc->iters);
   SNN_LAUNCH_CHECK();
   launch_project<T>(X, n, d, ix.mu.as<double>(), ix.v.as<double>(), ukey, val, bmax, &sc->max_norm, proj_cap, s);
-  radix_sort_pairs_ws(ukey, val, n, 0, 32, mem + off_sort, s);
+  uint32_t *skey, *sval;  // the sorted pairs, where the last pass left them
+  radix_sort_pairs_ws(ukey, val, n, 0, 32, mem + off_sort, s, &skey, &sval, &sc->sort_err);
   T* po = ix.po.as<T>();
   double* p64 = ix.p64.as<double>();
-  launch_gather<T>(X, n, d, ix.dp, ix.mu.as<double>(), ukey, val, ix.key.as<double>(), ix.perm.as<int32_t>(), po, p64,
+  launch_gather<T>(X, n, d, ix.dp, ix.mu.as<double>(), skey, sval, ix.key.as<double>(), ix.perm.as<int32_t>(), po, p64,
                    ix.ys.as<float>(), ix.h.as<float>(), ix.ynorm.as<float>(), 0, 4 * di.cus * 8, s);
 
   // one read-back into page-locked memory: the flags and the direction
@@ -1228,6 +1230,7 @@ void build_index_t(Index& ix, const T* X) {
   Scratch hs;
   std::memcpy(&hs, hb, sizeof(Scratch));
   if (hs.bad) fail(SNN_EINVAL, "snn_index: X contains NaN or Inf");
+  if (hs.sort_err) fail(SNN_EDEVICE, "snn_index: a scan of the radix sort did not complete");
   const double* vh = reinterpret_cast<const double*>(hb + 256);
   double vn = 0.0;
   for (int k = 0; k < d; ++k) vn += vh[k] * vh[k];

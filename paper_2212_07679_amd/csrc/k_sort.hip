@@ -5,7 +5,10 @@
 // 8-bit digits.  Each pass: per-block digit histograms (digit-major layout),
 // one exclusive scan over them, and a stable scatter in which every block
 // ranks its keys with wavefront ballots (64-lane match of equal digits) and
-// LDS counters, so equal keys keep their input order.
+// LDS counters, so equal keys keep their input order.  (11-bit digits, three
+// passes for 32 bits, were slower on 1e6 keys: with 2 keys per digit and
+// workgroup the scatter's writes hardly coalesce, and the larger LDS
+// histograms halve the workgroups.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,13 +24,18 @@ constexpr int kSortThreads = 256;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
-// ITEMS keys per thread, kSortThreads * ITEMS per block
+// ITEMS keys per thread, kSortThreads * ITEMS per block.  With lb set the
+// kernel also clears the lb_words state words of the look-back scan that
+// follows it.
 template <int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
                                                             int shift, uint32_t mask, uint32_t* __restrict__ hist,
-                                                            int nblocks) {
+                                                            int nblocks, unsigned long long* __restrict__ lb,
+                                                            int lb_words) {
   __shared__ uint32_t h[kSortThreads / kWave][kRadix];
   const int t = threadIdx.x, w = t / kWave;
+  if (lb)
+    for (int i = blockIdx.x * kSortThreads + t; i < lb_words; i += gridDim.x * kSortThreads) lb[i] = 0ull;
   for (int i = t; i < (kSortThreads / kWave) * kRadix; i += kSortThreads) (&h[0][0])[i] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortThreads * ITEMS;
@@ -53,9 +61,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
                                                                int bits, const uint32_t* __restrict__ hist,
                                                                int nblocks) {
   constexpr int kW = kSortThreads / kWave;
-  __shared__ uint32_t s_off[kRadix];
-  __shared__ uint32_t s_run[kRadix];
-  __shared__ uint32_t s_wcnt[kW][kRadix];
+  __shared__ uint32_t s_off[kRadix];       // the block's first output position per digit
+  __shared__ uint32_t s_run[kRadix];       // keys of each digit placed in earlier rounds
+  __shared__ uint32_t s_wcnt[kW][kRadix];  // this round's count per wavefront and digit (0 where absent)
   const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
   const uint32_t mask = (1u << bits) - 1u;
   if (t < kRadix) {
@@ -68,7 +76,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
   const uint64_t lt = (1ull << lane) - 1ull;
   const int64_t base = (int64_t)blockIdx.x * kSortThreads * ITEMS;
   // every item of the thread is loaded up front (all loads in flight at
-  // once), then ranked round by round
+  // once), then ranked round by round; round i holds block positions
+  // i * kSortThreads + t, so wavefront order within a round and round order
+  // are the input order
   uint32_t ks[ITEMS], vs[ITEMS];
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
@@ -87,8 +97,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
       uint64_t mb = __ballot((dg >> b) & 1u);
       peers &= ((dg >> b) & 1u) ? mb : ~mb;
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && (peers & lt) == 0) s_wcnt[w][dg] = (uint32_t)__popcll(peers);
+    const uint64_t below = peers & lt;
+    const uint32_t rank = (uint32_t)__popcll(below);
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    // the lowest lane of each group of equal digits speaks for the group
+    const bool leader = valid && below == 0;
+    if (leader) s_wcnt[w][dg] = cnt;
     __syncthreads();
     if (valid) {
       uint32_t pos = s_run[dg] + rank;
@@ -98,16 +112,14 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint32_t* 
       vout[g] = v;
     }
     __syncthreads();
-    if (t < kRadix) {
-      uint32_t s = 0;
-#pragma unroll
-      for (int ww = 0; ww < kW; ++ww) {
-        s += s_wcnt[ww][t];
-        s_wcnt[ww][t] = 0;
-      }
-      s_run[t] += s;
+    // after every read of this round: the group's count moves into the
+    // running total and its slot is cleared for the next round (only this
+    // wavefront writes that slot, and the next round reads it after the
+    // next barrier)
+    if (leader) {
+      s_wcnt[w][dg] = 0;
+      atomicAdd(&s_run[dg], cnt);
     }
-    __syncthreads();
   }
 }
 
@@ -378,20 +390,56 @@ namespace {
 int sort_items(int64_t n) { return n <= (int64_t(1) << 21) ? 8 : 16; }
 int64_t sort_tile(int64_t n) { return (int64_t)kSortThreads * sort_items(n); }
 
-// one 8-bit pass: histograms, their scan, the stable scatter
+// one 8-bit pass: histograms, their scan, the stable scatter.  With err the
+// histograms are scanned in one look-back launch (state words in scratch,
+// cleared by the histogram kernel; a wait that runs out sets *err), else
+// by the two-launch scan, which needs no error word.
 void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n, int shift,
-                int bits, uint32_t mask, uint32_t* hist, size_t nhist, int nblocks, void* scratch, hipStream_t s) {
+                int bits, uint32_t mask, uint32_t* hist, size_t nhist, int nblocks, void* scratch, int* err,
+                hipStream_t s) {
+  unsigned long long* lb = err ? static_cast<unsigned long long*>(scratch) : nullptr;
+  const int lbw = err ? (int)lookback_words((int64_t)nhist) : 0;
   if (sort_items(n) == 8)
-    k_radix_hist<8><<<nblocks, kSortThreads, 0, s>>>(kin, n, shift, mask, hist, nblocks);
+    k_radix_hist<8><<<nblocks, kSortThreads, 0, s>>>(kin, n, shift, mask, hist, nblocks, lb, lbw);
   else
-    k_radix_hist<16><<<nblocks, kSortThreads, 0, s>>>(kin, n, shift, mask, hist, nblocks);
+    k_radix_hist<16><<<nblocks, kSortThreads, 0, s>>>(kin, n, shift, mask, hist, nblocks, lb, lbw);
   SNN_LAUNCH_CHECK();
-  exclusive_scan_u32(hist, (int64_t)nhist, scratch, s);
+  if (err)
+    lookback_scan_u32(hist, (int64_t)nhist, lb, err, s);
+  else
+    exclusive_scan_u32(hist, (int64_t)nhist, scratch, s);
   if (sort_items(n) == 8)
     k_radix_scatter<8><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, bits, hist, nblocks);
   else
     k_radix_scatter<16><<<nblocks, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, shift, bits, hist, nblocks);
   SNN_LAUNCH_CHECK();
+}
+
+// Workspace: the ping-pong copies, one pass's histograms, and the scan's
+// block sums or look-back state, whichever is larger.
+size_t ws_bytes(int64_t n, size_t nhist) {
+  const size_t aux = std::max(scan_scratch_bytes((int64_t)nhist), sizeof(unsigned long long) * lookback_words((int64_t)nhist));
+  return 2 * (size_t)n * sizeof(uint32_t) + nhist * sizeof(uint32_t) + aux + 1024;
+}
+
+// All passes from keys/vals through the workspace; kin/vin end up naming
+// the buffers that hold the result.
+void radix_passes(uint32_t*& kin, uint32_t*& vin, int64_t n, int begin_bit, int end_bit, void* ws, int* err,
+                  hipStream_t s) {
+  const int nblocks = (int)ceil_div(n, sort_tile(n));
+  const size_t nhist = (size_t)nblocks * kRadix;
+  uint32_t* k2 = static_cast<uint32_t*>(ws);
+  uint32_t* v2 = k2 + n;
+  uint32_t* hist = v2 + n;
+  void* scratch = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(hist + nhist) + 255) & ~uintptr_t(255));
+  uint32_t *kout = k2, *vout = v2;
+  for (int shift = begin_bit; shift < end_bit; shift += kRadixBits) {
+    const int bits = std::min(kRadixBits, end_bit - shift);
+    const uint32_t mask = (1u << bits) - 1u;
+    radix_pass(kin, vin, kout, vout, n, shift, bits, mask, hist, nhist, nblocks, scratch, err, s);
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
 }
 }  // namespace
 
@@ -399,22 +447,9 @@ void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n,
                       hipStream_t s) {
   if (n <= 1 || begin_bit >= end_bit) return;
   if (n > (int64_t)UINT32_MAX / 2) fail(SNN_EINVAL, "radix sort: too many keys");
-  const int nblocks = (int)ceil_div(n, sort_tile(n));
-  const size_t nhist = (size_t)nblocks * kRadix;
-  const size_t bytes = 2 * (size_t)n * sizeof(uint32_t) + nhist * sizeof(uint32_t) + scan_scratch_bytes(nhist) + 1024;
-  ScopedAlloc mem(a, bytes);
-  uint32_t* k2 = static_cast<uint32_t*>(mem.get());
-  uint32_t* v2 = k2 + n;
-  uint32_t* hist = v2 + n;
-  void* scratch = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(hist + nhist) + 255) & ~uintptr_t(255));
-  uint32_t *kin = keys, *vin = vals, *kout = k2, *vout = v2;
-  for (int shift = begin_bit; shift < end_bit; shift += kRadixBits) {
-    const int bits = std::min(kRadixBits, end_bit - shift);
-    const uint32_t mask = (1u << bits) - 1u;
-    radix_pass(kin, vin, kout, vout, n, shift, bits, mask, hist, nhist, nblocks, scratch, s);
-    std::swap(kin, kout);
-    std::swap(vin, vout);
-  }
+  ScopedAlloc mem(a, radix_sort_ws_bytes(n));
+  uint32_t *kin = keys, *vin = vals;
+  radix_passes(kin, vin, n, begin_bit, end_bit, mem.get(), nullptr, s);
   if (kin != keys) {
     SNN_HIP(hipMemcpyAsync(keys, kin, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     SNN_HIP(hipMemcpyAsync(vals, vin, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
@@ -423,8 +458,7 @@ void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n,
 
 size_t radix_sort_ws_bytes(int64_t n) {
   const int64_t nblocks = ceil_div(std::max<int64_t>(n, 1), sort_tile(n));
-  const size_t nhist = (size_t)nblocks * kRadix;
-  return 2 * (size_t)n * sizeof(uint32_t) + nhist * sizeof(uint32_t) + scan_scratch_bytes((int64_t)nhist) + 1024;
+  return ws_bytes(n, (size_t)nblocks * kRadix);
 }
 
 namespace {
@@ -439,24 +473,19 @@ __global__ void k_copy_pairs(const uint32_t* __restrict__ ks, const uint32_t* __
 
 // Same sort with caller-provided workspace (radix_sort_ws_bytes(n) bytes) and
 // kernels only (no allocation, no copy or memset calls): usable under
-// stream capture.
+// stream capture.  With err (a device word the caller reads back and
+// checks) the histogram scans take the one-launch look-back scan.  With kres/vres the sorted pairs are left where the last
+// pass wrote them (keys/vals or the start of the workspace) and those
+// pointers returned; without, they are copied back into keys/vals.
 void radix_sort_pairs_ws(uint32_t* keys, uint32_t* vals, int64_t n, int begin_bit, int end_bit, void* ws,
-                         hipStream_t s) {
-  if (n <= 1 || begin_bit >= end_bit) return;
+                         hipStream_t s, uint32_t** kres, uint32_t** vres, int* err) {
+  uint32_t *kin = keys, *vin = vals;
   if (n > (int64_t)UINT32_MAX / 2) fail(SNN_EINVAL, "radix sort: too many keys");
-  const int nblocks = (int)ceil_div(n, sort_tile(n));
-  const size_t nhist = (size_t)nblocks * kRadix;
-  uint32_t* k2 = static_cast<uint32_t*>(ws);
-  uint32_t* v2 = k2 + n;
-  uint32_t* hist = v2 + n;
-  void* scratch = reinterpret_cast<void*>((reinterpret_cast<uintptr_t>(hist + nhist) + 255) & ~uintptr_t(255));
-  uint32_t *kin = keys, *vin = vals, *kout = k2, *vout = v2;
-  for (int shift = begin_bit; shift < end_bit; shift += kRadixBits) {
-    const int bits = std::min(kRadixBits, end_bit - shift);
-    const uint32_t mask = (1u << bits) - 1u;
-    radix_pass(kin, vin, kout, vout, n, shift, bits, mask, hist, nhist, nblocks, scratch, s);
-    std::swap(kin, kout);
-    std::swap(vin, vout);
+  if (n > 1 && begin_bit < end_bit) radix_passes(kin, vin, n, begin_bit, end_bit, ws, err, s);
+  if (kres) {
+    *kres = kin;
+    *vres = vin;
+    return;
   }
   if (kin != keys) {
     k_copy_pairs<<<(unsigned)std::min<int64_t>(ceil_div(n, 256), 4096), 256, 0, s>>>(kin, vin, keys, vals, n);

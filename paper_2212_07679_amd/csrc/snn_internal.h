@@ -227,8 +227,12 @@ struct Index {
 void radix_sort_pairs(DeviceArena& a, uint32_t* keys, uint32_t* vals, int64_t n, int begin_bit, int end_bit,
                       hipStream_t s);
 size_t radix_sort_ws_bytes(int64_t n);
+// kres/vres: leave the result where the last pass wrote it and return those
+// pointers (no copy back into keys/vals).  err: a device int, nonzero after
+// the work if a look-back wait ran out (then the order is wrong); the caller
+// must read it back; without it the sort uses the scan that needs no check.
 void radix_sort_pairs_ws(uint32_t* keys, uint32_t* vals, int64_t n, int begin_bit, int end_bit, void* ws,
-                         hipStream_t s);
+                         hipStream_t s, uint32_t** kres = nullptr, uint32_t** vres = nullptr, int* err = nullptr);
 size_t scan_scratch_bytes(int64_t n);
 // Exclusive scan of int32 counts into int64 offsets (out has n+1 entries,
 // out[n] = total).  scratch: scan_scratch_bytes(n).

@@ -301,7 +301,8 @@ def test_direction_near_degenerate(B, d):
 
 
 @pytest.mark.parametrize("n,bits", [(1, (0, 32)), (1000, (0, 32)), (100_003, (0, 32)), (70_000, (8, 32)),
-                                    (5000, (0, 3))])
+                                    (5000, (0, 3)), (30_001, (0, 9)), (30_001, (4, 24)), (4097, (5, 16)),
+                                    (2_500_003, (0, 32))])
 def test_radix_sort(B, n, bits):
     say(f"radix sort n={n} bits={bits}")
     g = np.random.default_rng(n)
