@@ -150,8 +150,12 @@ __global__ __launch_bounds__(kGramWaves * kWave) void k_gram_mfma(const T* __res
                                                                 int64_t rows_per_block, int npairs,
                                                                 double* __restrict__ part) {
   constexpr int BW = 16 * TB;
-  const int pair = blockIdx.y * (blockDim.x / kWave) + threadIdx.x / kWave;
-  if (pair >= npairs) return;  // no barriers below
+  const int wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  // one pair (d <= 64): every wavefront of the workgroup takes that pair over
+  // its own share of the workgroup's rows, and the sums meet in LDS below
+  const bool split = npairs == 1;
+  const int pair = split ? 0 : blockIdx.y * nw + wv;
+  if (pair >= npairs) return;  // never in split mode, the only one with barriers
   const int nbk = (d + BW - 1) / BW;
   int ba = 0, rest = pair;
   while (rest >= nbk - ba) {
@@ -175,8 +179,13 @@ __global__ __launch_bounds__(kGramWaves * kWave) void k_gram_mfma(const T* __res
   for (int i = 0; i < TB; ++i)
 #pragma unroll
     for (int j = 0; j < TB; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-  const int64_t r1 = min(n, r0 + rows_per_block);
+  int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  int64_t r1 = min(n, r0 + rows_per_block);
+  if (split) {  // contiguous shares of a multiple of 4 rows (the last ones may be empty)
+    const int64_t per = ((rows_per_block + nw - 1) / nw + 3) & ~int64_t(3);
+    r0 += wv * per;
+    r1 = min(r1, r0 + per);
+  }
   // raw operands of the next PF steps stay in flight in a register ring
   // (measured: 8 steps for one or two tiles a side, 2 for the 16-tile pairs)
   constexpr int PF = (TB >= 3 ? 2 : 8) / (sizeof(T) == 8 ? 2 : 1);
@@ -209,6 +218,25 @@ __global__ __launch_bounds__(kGramWaves * kWave) void k_gram_mfma(const T* __res
         for (int j = 0; j < TB; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+  }
+  if (split) {  // wavefronts 1.. add into wavefront 0, one at a time (a fixed order)
+    __shared__ f64x4 red[TB * TB][kWave];
+    const int l2 = lane_id();
+    for (int src = 1; src < nw; ++src) {
+      if (wv == src)
+#pragma unroll
+        for (int i = 0; i < TB; ++i)
+#pragma unroll
+          for (int j = 0; j < TB; ++j) red[i * TB + j][l2] = acc[i][j];
+      __syncthreads();
+      if (wv == 0)
+#pragma unroll
+        for (int i = 0; i < TB; ++i)
+#pragma unroll
+          for (int j = 0; j < TB; ++j) acc[i][j] += red[i * TB + j][l2];
+      __syncthreads();
+    }
+    if (wv != 0) return;
   }
   // element e of lane l holds D[l / 16 + 4 e][l % 16] of each 16 x 16 tile
   double* out = part + (int64_t)blockIdx.x * d * d;
@@ -1143,9 +1171,19 @@ void build_index_t(Index& ix, const T* X) {
   const int g1 = (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n * d + 4095) / 4096));
   const int64_t rpb1 = (n + g1 - 1) / g1;
   int64_t dd = (int64_t)d * d;
-  // about 512 rows per workgroup and up to 8 workgroups per CU: with fewer,
-  // larger blocks the staging rounds of the rows are latency-bound
-  int g2 = (int)std::min<int64_t>(std::max<int64_t>(1, (n + 511) / 512), 8 * (int64_t)di.cus);
+  // Gram tiles on the matrix cores: 16 * tb columns a side, npairs tile
+  // pairs on or above the diagonal (one pair up to d = 64)
+  const int tb = d <= 16 ? 1 : d <= 32 ? 2 : d <= 48 ? 3 : 4;
+  const int nbk = (d + 16 * tb - 1) / (16 * tb), npairs = nbk * (nbk + 1) / 2;
+  const bool gram_mfma = d >= kGramMfmaMinD;
+  const bool gram_split = gram_mfma && npairs == 1;
+  // about 512 rows per wavefront and up to 8 wavefronts per CU: with fewer,
+  // larger blocks the staging rounds of the rows are latency-bound.  With
+  // one pair, kGramWaves wavefronts share a workgroup's rows (one partial
+  // Gram matrix per kGramWaves wavefronts for the final sum to read).
+  const int64_t rows_wg = gram_split ? 512 * kGramWaves : 512;
+  const int64_t max_wg = gram_split ? 8 * (int64_t)di.cus / kGramWaves : 8 * (int64_t)di.cus;
+  int g2 = (int)std::min<int64_t>(std::max<int64_t>(1, (n + rows_wg - 1) / rows_wg), max_wg);
   g2 = (int)std::max<int64_t>(1, std::min<int64_t>(g2, (int64_t)(256ll << 20) / (dd * 8)));
   const int64_t rpb2 = (n + g2 - 1) / g2;
   const int rows_chunk = (int)std::max<int64_t>(1, std::min<int64_t>(64, 4096 / d));
@@ -1181,11 +1219,9 @@ void build_index_t(Index& ix, const T* X) {
   SNN_LAUNCH_CHECK();
 
   const size_t lds2 = sizeof(double) * rows_chunk * d;
-  if (d >= kGramMfmaMinD) {
-    const int tb = d <= 16 ? 1 : d <= 32 ? 2 : d <= 48 ? 3 : 4;
-    const int nbk = (d + 16 * tb - 1) / (16 * tb), npairs = nbk * (nbk + 1) / 2;
-    const int w = std::min(npairs, kGramWaves);
-    const dim3 grid(g2, (npairs + w - 1) / w);
+  if (gram_mfma) {
+    const int w = gram_split ? kGramWaves : std::min(npairs, kGramWaves);
+    const dim3 grid(g2, gram_split ? 1 : (npairs + w - 1) / w);
     const double* mu = ix.mu.as<double>();
     switch (tb) {
       case 1: k_gram_mfma<T, 1><<<grid, w * kWave, 0, s>>>(X, n, d, mu, rpb2, npairs, part2); break;
