@@ -394,6 +394,8 @@ __device__ __forceinline__ double lanes_sum(double x) {
   return s;
 }
 
+constexpr int kPowerSquarings = 10;
+
 template <int DB>
 __global__ __launch_bounds__(kWave) void k_power_iter_wave(const double* __restrict__ C, int d, int max_iter,
                                                           double* __restrict__ v_out, int* __restrict__ iters_out) {
@@ -404,6 +406,57 @@ __global__ __launch_bounds__(kWave) void k_power_iter_wave(const double* __restr
   for (int j = 0; j < DB; ++j) crow[j] = (i < d && j < d) ? C[(int64_t)j * d + i] : 0.0;
   // deterministic start: 1 + small distinct perturbation per coordinate
   double vi = i < d ? 1.0 + 0.01 * (double)((i * 2654435761u) % 1000u) / 1000.0 : 0.0;
+  if constexpr (DB <= 16) {
+    // d <= 16: the start is first taken through C^(2^kPowerSquarings), built
+    // by repeated squaring on the matrix cores (four 16x16x4 fp64 products per
+    // square, each square scaled to unit Frobenius norm), so a slow ratio of
+    // the two largest eigenvalues costs a few squarings instead of hundreds
+    // of iterations; the iteration below still decides convergence on C.
+    // Lane l holds M[l % 16][4 kb + l / 16] for kb = 0..3, every entry once,
+    // which is both operands of M M since M is symmetric.
+    __shared__ double ms[16][17];
+    const int c16 = i % 16, k4 = i / 16;
+    double op[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+      const int col = 4 * kb + k4;
+      op[kb] = (c16 < d && col < d) ? C[(int64_t)c16 * d + col] : 0.0;
+    }
+    int done = 0;  // squares written to ms (uniform across lanes)
+    // sums of squares by butterfly, lane 0's value taken by all (uniform)
+    auto frob2 = [](double x) { return readlane_f64(wave_sum(x), 0); };
+    double ss = frob2(op[0] * op[0] + op[1] * op[1] + op[2] * op[2] + op[3] * op[3]);
+    if (ss > 0.0 && ss < INFINITY) {
+      const double inv0 = 1.0 / sqrt(ss);
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) op[kb] *= inv0;
+      for (; done < kPowerSquarings; ++done) {
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(op[kb], op[kb], acc, 0, 0, 0);
+        ss = frob2(acc[0] * acc[0] + acc[1] * acc[1] + acc[2] * acc[2] + acc[3] * acc[3]);
+        if (!(ss > 0.0 && ss < INFINITY)) break;
+        const double inv = 1.0 / sqrt(ss);
+        __syncthreads();  // the previous square has been read
+        // element e of lane l holds the square's entry [l / 16 + 4 e][l % 16]
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ms[k4 + 4 * e][c16] = acc[e] * inv;
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) op[kb] = ms[c16][4 * kb + k4];
+      }
+    }
+    if (done > 0) {  // start from M x0
+      double w = 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double xj = readlane_f64(vi, j);
+        if (i < d) w += ms[i][j] * xj;
+      }
+      const double nw = lanes_sum<DB>(w * w);
+      if (nw > 0.0 && nw < INFINITY) vi = w;
+    }
+  }
   vi /= sqrt(lanes_sum<DB>(vi * vi));
   double lambda_prev = -1.0;
   int it = 0;
