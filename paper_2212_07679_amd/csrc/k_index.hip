@@ -1146,34 +1146,45 @@ __global__ __launch_bounds__(kThreads) void k_operands(const float* __restrict__
                                                       int64_t n, int64_t npad, int d, int kind, int e, int ka, int kb,
                                                       uint16_t* __restrict__ cand, uint16_t* __restrict__ qself,
                                                       float* __restrict__ hs) {
-  const int64_t total = npad * (int64_t)ka;
+  // four consecutive columns per thread (ka and kb are multiples of 16, so
+  // the four lie in one 8-column group of the candidate layout and both
+  // stores are 8-byte aligned)
+  const int ka4 = ka / 4;
+  const int64_t total = npad * (int64_t)ka4;
   const int nl = kb / 16;
-  for (int64_t el = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; el < total;
-       el += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t s = el / ka;
-    const int k = (int)(el % ka);
-    uint16_t cv = 0, qv = 0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = g / ka4;
+    const int k0 = 4 * (int)(g - s * ka4);
+    uint16_t cv[4] = {0, 0, 0, 0}, qv[4] = {0, 0, 0, 0};
     if (s < n) {
-      if (kind == kOpF16) {
-        if (k < d) cv = qv = __builtin_bit_cast(uint16_t, (_Float16)ldexpf(ys[s * d + k], e));
-      } else if (kind == kOpBf16) {
-        if (k < d) cv = qv = f32_to_bf16_rne(ys[s * d + k]);
-      } else if (k < 3 * d) {
-        const int seg = k / d, c = k % d;
-        const float y = ys[s * d + c];
-        const uint16_t hi = f32_to_bf16_rne(y);
-        const uint16_t lo = f32_to_bf16_rne(y - bf16_to_f32(hi));
-        cv = (seg == 1) ? lo : hi;
-        qv = (seg == 2) ? lo : hi;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = k0 + u;
+        if (kind == kOpF16) {
+          if (k < d) cv[u] = qv[u] = __builtin_bit_cast(uint16_t, (_Float16)ldexpf(ys[s * d + k], e));
+        } else if (kind == kOpBf16) {
+          if (k < d) cv[u] = qv[u] = f32_to_bf16_rne(ys[s * d + k]);
+        } else if (k < 3 * d) {
+          const int seg = k / d, c = k % d;
+          const float y = ys[s * d + c];
+          const uint16_t hi = f32_to_bf16_rne(y);
+          const uint16_t lo = f32_to_bf16_rne(y - bf16_to_f32(hi));
+          cv[u] = (seg == 1) ? lo : hi;
+          qv[u] = (seg == 2) ? lo : hi;
+        }
       }
     }
-    if (k < kb) {
+    if (k0 < kb) {
       const int64_t blk = s / 32;
-      const int r = (int)(s % 32), sl = k / 16, hh = (k % 16) / 8, c8 = k % 8;
-      cand[((blk * nl + sl) * 2 + hh) * 256 + r * 8 + c8] = cv;
+      const int r = (int)(s % 32), sl = k0 / 16, hh = (k0 % 16) / 8, c8 = k0 % 8;
+      *reinterpret_cast<uint2*>(cand + ((blk * nl + sl) * 2 + hh) * 256 + r * 8 + c8) =
+          make_uint2(cv[0] | (uint32_t)cv[1] << 16, cv[2] | (uint32_t)cv[3] << 16);
     }
-    if (qself && s < n) qself[el] = qv;
-    if (hs && k == 0) {
+    if (qself && s < n)
+      *reinterpret_cast<uint2*>(qself + s * ka + k0) =
+          make_uint2(qv[0] | (uint32_t)qv[1] << 16, qv[2] | (uint32_t)qv[3] << 16);
+    if (hs && k0 == 0) {
       float v = INFINITY;
       if (s < n) {
         // the scaling is exact unless it lands below fp32's normal range
@@ -1529,7 +1540,7 @@ void build_mixed_operands(Index& ix, int kind) {
   mo.qself.ensure(ix.arena, sizeof(uint16_t) * ix.n * ka + 256);
   if (kind == kOpF16) mo.hs.ensure(ix.arena, sizeof(float) * npad + 256);
   const DeviceInfo& di = device_info(ix.arena.dev().device);
-  k_operands<<<grid_for(npad * ka, kThreads, 4 * di.cus * 8), kThreads, 0, ix.arena.stream()>>>(
+  k_operands<<<grid_for(npad * (ka / 4), kThreads, 4 * di.cus * 8), kThreads, 0, ix.arena.stream()>>>(
       ix.ys.as<float>(), ix.h.as<float>(), ix.n, npad, d, kind, e, ka, kb, mo.cand.as<uint16_t>(),
       mo.qself.as<uint16_t>(), kind == kOpF16 ? mo.hs.as<float>() : nullptr);
   SNN_LAUNCH_CHECK();
