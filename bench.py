@@ -280,12 +280,12 @@ def roofline(prec_used, terms, st, screen_ms, d):
 def index_hbm(n, d, b, index_ms):
     """Algorithmic HBM bytes of the index build (Algorithm 1 on the device)
     over its wall time: the rows are read four times (centring, Gram matrix,
-    scores, gather) and written once in key order in the input dtype, in
-    float64 (padded to a multiple of 4 columns) and centred in fp32, plus key,
-    id, h and norm per row (20 bytes) and four radix passes over 8-byte
-    (key, id) pairs read and written (64 bytes per row)."""
-    dp = ((d + 3) // 4) * 4
-    nbytes = 4 * n * d * b + n * (d * b + 8 * dp + 4 * d + 20) + 64 * n
+    scores, gather) and written once in key order in the input dtype and
+    centred in fp32, plus key, id, h and norm per row (20 bytes) and four
+    radix passes over 8-byte (key, id) pairs read and written (64 bytes per
+    row).  The float64 copy of the rows is not part of the build: the first
+    float64 screen or self-query makes it."""
+    nbytes = 4 * n * d * b + n * (d * b + 4 * d + 20) + 64 * n
     achieved = nbytes / (index_ms / 1e3)
     return {"bytes": nbytes, "achieved_GBps": achieved / 1e9, "peak_GBps": PEAK_HBM / 1e9,
             "frac": achieved / PEAK_HBM}

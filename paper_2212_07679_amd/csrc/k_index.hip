@@ -930,11 +930,11 @@ __global__ __launch_bounds__(kThreads) void k_gather(const T* __restrict__ X, in
             if (k < d) {
               const T x = xv[u][j];
               po[s * d + k] = x;
-              p64[s * dp + k] = (double)x;
+              if (p64) p64[s * dp + k] = (double)x;
               const float y = (float)((double)x - (PM == PM_REG ? mur[j] : mup[k]));
               ys[s * d + k] = y;
               nn[u] += (double)y * (double)y;
-            } else {
+            } else if (p64) {
               p64[s * dp + k] = 0.0;
             }
           }
@@ -1022,7 +1022,7 @@ __global__ __launch_bounds__(kThreads) void k_gather4(const float* __restrict__ 
               ys[s * d + k0 + j] = y[j];
             }
         }
-        if (k0 < dp) {  // dp is a multiple of 4; the padding columns are zero
+        if (p64 && k0 < dp) {  // dp is a multiple of 4; the padding columns are zero
           double2* o = reinterpret_cast<double2*>(p64 + s * dp + k0);
           o[0] = make_double2((double)xv[u][0], (double)xv[u][1]);
           o[1] = make_double2((double)xv[u][2], (double)xv[u][3]);
@@ -1318,7 +1318,9 @@ void build_index_t(Index& ix, const T* X) {
   uint32_t *skey, *sval;  // the sorted pairs, where the last pass left them
   radix_sort_pairs_ws(ukey, val, n, 0, 32, mem + off_sort, s, &skey, &sval, &sc->sort_err);
   T* po = ix.po.as<T>();
-  double* p64 = ix.p64.as<double>();
+  // the float64 rows wait for the first fp64 screen (build_rows64)
+  double* p64 = nullptr;
+  ix.p64_ready = false;
   launch_gather<T>(X, n, d, ix.dp, ix.mu.as<double>(), skey, sval, ix.key.as<double>(), ix.perm.as<int32_t>(), po, p64,
                    ix.ys.as<float>(), ix.h.as<float>(), ix.ynorm.as<float>(), 0, 4 * di.cus * 8, s);
 
@@ -1351,6 +1353,33 @@ void build_index(Index& ix, const void* X) {
     build_index_t<float>(ix, static_cast<const float*>(X));
   else
     build_index_t<double>(ix, static_cast<const double*>(X));
+}
+
+namespace {
+// float64 copy of the sorted rows, zero-padded to dp columns
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_rows64(const T* __restrict__ po, int64_t n, int d, int dp,
+                                                    double* __restrict__ p64) {
+  const int64_t total = n * (int64_t)dp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = e / dp;
+    const int k = (int)(e - s * dp);
+    p64[e] = k < d ? (double)po[s * d + k] : 0.0;
+  }
+}
+}  // namespace
+
+void build_rows64(Index& ix) {
+  if (ix.p64_ready || ix.n == 0) return;
+  const int grid = grid_for(ix.n * (int64_t)ix.dp, kThreads, 4 * device_info(ix.arena.dev().device).cus * 8);
+  if (ix.dtype == SNN_F32)
+    k_rows64<float><<<grid, kThreads, 0, ix.arena.stream()>>>(ix.po.as<float>(), ix.n, ix.d, ix.dp,
+                                                              ix.p64.as<double>());
+  else
+    k_rows64<double><<<grid, kThreads, 0, ix.arena.stream()>>>(ix.po.as<double>(), ix.n, ix.d, ix.dp,
+                                                               ix.p64.as<double>());
+  SNN_LAUNCH_CHECK();
+  ix.p64_ready = true;
 }
 
 // ---- streaming inserts ---------------------------------------------------------
@@ -1432,7 +1461,6 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   sz.take<double>(k);                 // key
   sz.take<int32_t>(k);                // perm
   sz.take<T>((size_t)k * d);          // po
-  sz.take<double>((size_t)k * dp);    // p64
   sz.take<float>((size_t)k * d);      // ys
   sz.take<float>(k + 64);             // h
   sz.take<float>(k);                  // ynorm
@@ -1446,7 +1474,6 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   double* keyb = c.take<double>(k);
   int32_t* permb = c.take<int32_t>(k);
   T* pob = c.take<T>((size_t)k * d);
-  double* p64b = c.take<double>((size_t)k * dp);
   float* ysb = c.take<float>((size_t)k * d);
   float* hb = c.take<float>(k + 64);
   float* ynb = c.take<float>(k);
@@ -1459,7 +1486,7 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   SNN_LAUNCH_CHECK();
   launch_project<T>(Xn, k, d, ix.mu.as<double>(), ix.v.as<double>(), ukey, val, bmax, &sc->max_norm, cap, s);
   radix_sort_pairs(ix.arena, ukey, val, k, 0, 32, s);
-  launch_gather<T>(Xn, k, d, dp, ix.mu.as<double>(), ukey, val, keyb, permb, pob, p64b, ysb, hb, ynb, na, cap, s);
+  launch_gather<T>(Xn, k, d, dp, ix.mu.as<double>(), ukey, val, keyb, permb, pob, nullptr, ysb, hb, ynb, na, cap, s);
   Scratch hs;
   SNN_HIP(hipMemcpyAsync(&hs, sc, sizeof(Scratch), hipMemcpyDeviceToHost, s));
   SNN_HIP(hipStreamSynchronize(s));
@@ -1488,7 +1515,7 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   merge_rows<double>(ix.key.as<double>(), keyb, src, nt, 1, key.as<double>(), cap, s);
   merge_rows<int32_t>(ix.perm.as<int32_t>(), permb, src, nt, 1, perm.as<int32_t>(), cap, s);
   merge_rows<T>(ix.po.as<T>(), pob, src, nt, d, po.as<T>(), cap, s);
-  merge_rows<double>(ix.p64.as<double>(), p64b, src, nt, dp, p64.as<double>(), cap, s);
+  // p64 of the grown index is filled by the next fp64 screen (p64_ready)
   merge_rows<float>(ix.ys.as<float>(), ysb, src, nt, d, ys.as<float>(), cap, s);
   merge_rows<float>(ix.h.as<float>(), hb, src, nt, 1, h.as<float>(), cap, s);
   merge_rows<float>(ix.ynorm.as<float>(), ynb, src, nt, 1, ynorm.as<float>(), cap, s);
@@ -1516,6 +1543,7 @@ static void insert_points_t(Index& ix, const T* Xn, int64_t k) {
   ix.key_eps = 1.01 * (u32 + g64) * (1.0 + u32) * ix.max_norm * ix.vnorm;
   for (auto& mo : ix.mixed) mo.built = false;
   ix.vcand_built = false;
+  ix.p64_ready = false;
   ix.wcells_built = false;
   ++ix.epoch;
 }

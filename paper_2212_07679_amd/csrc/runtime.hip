@@ -584,6 +584,9 @@ static void run_query(Index& ix, const void* Q, int64_t m, double R, bool self, 
   if (prec != SNN_PREC_FP64 && CH % 32 != 0) fail(SNN_EINVAL, "matrix-core screens: tile_c must be a multiple of 32");
   if (mix16) build_mixed_operands(ix, sp.kind);
   if (prec == SNN_PREC_FP32) build_fp32_operands(ix);
+  // the float64 rows: read by the fp64 screen, and as the query rows of a
+  // self-query's recheck; filled before any capture (a replay never needs it)
+  if (prec == SNN_PREC_FP64 || self) build_rows64(ix);
 
   // stats: the device clock marks the call's start (its first kernel) and
   // end (a mark kernel after the last one), and the screen's workgroups

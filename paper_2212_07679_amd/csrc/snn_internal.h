@@ -187,13 +187,14 @@ struct Index {
   Buffer key;   // n doubles: fl32(score) in ascending order
   Buffer perm;  // n int32: sorted position -> original id
   Buffer po;    // n x d input dtype: original rows, sorted
-  Buffer p64;   // n x dp doubles: original rows, sorted, zero-padded
+  Buffer p64;   // n x dp doubles: original rows, sorted, zero-padded (filled on the first fp64 screen: p64_ready)
   Buffer ys;    // n x d floats: fl32(p - mu), sorted
   Buffer h;     // n + 32 floats: ||ys||^2 / 2 rounded to nearest, sorted; padding +inf
   Buffer ynorm; // n floats: ||ys|| rounded up, sorted
   MixedOperands mixed[3];  // bf16 one term, bf16 hi/lo, fp16 (mixed_slot)
   Buffer vcand;            // fp32 screen candidate operand blocks (k_cand_mfma32)
   bool vcand_built = false;
+  bool p64_ready = false;  // p64 holds the rows (only the fp64 screen reads them)
   Buffer wcells;           // window_table_cells(n) + 1 int32: grid cells of the sorted scores
   int wcells_n = 0;
   bool wcells_built = false;
@@ -248,6 +249,8 @@ void lookback_scan_u32(uint32_t* data, int64_t n, unsigned long long* state, int
 void build_index(Index& ix, const void* X);
 // screen operands of one OperandKind (bf16, bf16 hi/lo or fp16) for the current rows
 void build_mixed_operands(Index& ix, int kind);
+// fills ix.p64 from the sorted rows ix.po on the index's stream, once per index version
+void build_rows64(Index& ix);
 // appends k rows (ids n .. n+k-1) with the index's mu and v: merged into the
 // key order, bounds updated, screen operands marked for rebuilding
 void insert_points(Index& ix, const void* X, int64_t k);
